@@ -1,0 +1,154 @@
+/*
+ * mpik.h -- C ABI of the MI355X (gfx950) library for the model operator of
+ * trajectory-independent, model-based Magnetic Particle Imaging.
+ *
+ * Operator (Gapyak, Maerz, Weinmann, arXiv 2505.22797, Section "Methods"):
+ *   the MPI kernel K (eq. kernel:matrix), rescaled K_h(y) = K(y/h)/h, is
+ *   convolved with the particle concentration (eq. coreoperator), the
+ *   matrix-valued result is sampled along the field-free-point trajectory
+ *   r(t) and contracted with its velocity v(t) (eq. core:formula):
+ *       s_k = A_h[c](r_k) v_k.
+ *   A maps the concentration c to the signal s; A^T is its exact transpose.
+ *
+ * Discretisation (the readings the library and its tests share):
+ *   - N x N cell-centred grid over the field of view [-1, 1]^2, pitch
+ *     delta = 2/N, centre x_i = -1 + (i + 1/2) delta; c is row-major
+ *     c[j][i] with j the y index;
+ *   - the convolution is the Riemann sum delta^2 * sum_d K_h(delta d) c[. - d]
+ *     over integer offsets |d_x|, |d_y| <= R (square window, zero outside the
+ *     grid); R >= N-1 is the untruncated kernel;
+ *   - the field is interpolated bilinearly between cell centres; a sample
+ *     needs g = (r + 1)/delta - 1/2 in [0, N-1] on both axes;
+ *   - s is [T][2] interleaved (x, y), matching a contiguous (T, 2) tensor.
+ *
+ * Memory ownership: the caller owns every device buffer -- inputs, outputs,
+ * the plan memory and the work memory.  The library never allocates device
+ * memory.  An mpi_plan is a small host object owned by the library
+ * (mpi_plan_destroy frees it); it refers into the caller's plan memory, which
+ * must outlive it.  A plan is immutable after the build.  Calls on different
+ * streams may run concurrently if each passes its own work buffer.
+ *
+ * Errors: every call returns an mpi_status; nothing throws or aborts across
+ * the ABI.  Argument errors are found on the host before anything is
+ * enqueued.  Every apply call only enqueues work on the given stream and
+ * never synchronises; a fault of an earlier kernel surfaces as MPI_ERR_HIP
+ * on a later call.  mpi_kernel_build synchronises its stream once, to report
+ * samples outside the grid (MPI_ERR_DOMAIN).
+ */
+#ifndef MPIK_H
+#define MPIK_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPIK_ABI_VERSION 1
+
+typedef enum {
+    MPI_OK = 0,
+    MPI_ERR_ARG = -1,          /* NULL pointer, bad size, misaligned pointer  */
+    MPI_ERR_DOMAIN = -2,       /* a trajectory sample lies outside the grid   */
+    MPI_ERR_WORKSPACE = -3,    /* plan or work buffer smaller than required   */
+    MPI_ERR_DTYPE = -4,        /* unknown dtype                               */
+    MPI_ERR_HIP = -5,          /* HIP runtime error (incl. earlier faults)    */
+    MPI_ERR_UNSUPPORTED = -6   /* valid but not implemented option            */
+} mpi_status;
+
+enum { MPI_F32 = 0, MPI_F64 = 1 };
+enum { MPI_CONV_AUTO = 0, MPI_CONV_DIRECT = 1, MPI_CONV_FFT = 2 };
+enum { MPI_INTERP_BILINEAR = 0 };
+enum { MPI_CH_XY = 0 };
+
+/* One reconstruction problem.  r and v are device pointers to [T][2] arrays
+ * of the given dtype, read only during mpi_kernel_build. */
+typedef struct {
+    int32_t n;             /* grid side N, 2 <= N <= 1024                      */
+    int32_t dtype;         /* MPI_F32 or MPI_F64: every array of the problem   */
+    double h;              /* kernel resolution in field-of-view units, > 0    */
+    int32_t radius;        /* window half-width R >= 0 in pixels; capped N-1   */
+    int32_t conv_mode;     /* MPI_CONV_*: selects speed only, never the result */
+    int32_t interp;        /* MPI_INTERP_BILINEAR                              */
+    int32_t channels;      /* MPI_CH_XY: both signal channels                  */
+    int64_t n_samples;     /* T >= 1, T < 2^26                                 */
+    const void* r;         /* device [T][2] sample positions r_k               */
+    const void* v;         /* device [T][2] velocities v_k = dr/dt(t_k)        */
+} mpi_problem;
+
+/* Parameters of mpi_iterate: c <- D(c - tau A^T (A c - s)), n_iter times.
+ * D is the identity when denoise_sigma_px <= 0, else a separable Gaussian of
+ * standard deviation denoise_sigma_px pixels and half-width denoise_radius
+ * (weights normalised to sum 1, zero padding) -- a stand-in for the learned
+ * denoiser of the half-quadratic-splitting loop (eqs. dec:sub:tik and
+ * dec:sub:den). */
+typedef struct {
+    int32_t n_iter;            /* >= 0                                         */
+    double tau;                /* step size (the caller's 1/lambda_max(A^T A)) */
+    double denoise_sigma_px;   /* <= 0: no denoiser                            */
+    int32_t denoise_radius;    /* 0..8                                         */
+    int32_t use_graph;         /* 1: capture one iteration as a HIP graph and  */
+                               /*    replay it (needs a non-null stream)       */
+} mpi_iter_params;
+
+typedef struct mpi_plan mpi_plan;
+
+/* Bytes of plan memory (kept for the plan's lifetime) and of work memory
+ * (scratch for each apply call) the problem needs.  Host-only; validates the
+ * descriptor (except the sample positions, checked by the build). */
+int mpi_plan_bytes(const mpi_problem* prob, size_t* plan_bytes, size_t* work_bytes);
+
+/* Build the plan in caller-owned device memory plan_mem (256-byte aligned,
+ * >= plan_bytes): the kernel table K_h(delta d) for |d_x|,|d_y| <= R
+ * (eq. kernel:matrix, computed in float64 on the device), its spectra for
+ * the FFT path, and the sample-to-cell binning (base cell, bilinear fractions
+ * in float64, a stable sort by cell).  Enqueued on `stream`, then the stream
+ * is synchronised once; returns MPI_ERR_DOMAIN if a sample is outside the
+ * grid.  On success *out receives a new host plan object. */
+int mpi_kernel_build(const mpi_problem* prob, void* plan_mem, size_t plan_bytes,
+                     hipStream_t stream, mpi_plan** out);
+
+/* s = A c (eq. core:formula).  c: device [N][N], s: device [T][2], both of
+ * the plan's dtype; s is overwritten.  work: >= work_bytes, 256-byte aligned. */
+int mpi_forward(const mpi_plan* plan, const void* c, void* s,
+                void* work, size_t work_bytes, hipStream_t stream);
+
+/* c = A^T s, the exact transpose of mpi_forward.  The sampling transpose is
+ * deterministic: contributions are summed per cell in a fixed order, without
+ * floating-point atomics, so repeated calls give bitwise identical results. */
+int mpi_adjoint(const mpi_plan* plan, const void* s, void* c,
+                void* work, size_t work_bytes, hipStream_t stream);
+
+/* c <- D(c - tau A^T(A c - s)) repeated params->n_iter times, in place on c
+ * (device [N][N], holding c_0 on entry).  s: device [T][2]. */
+int mpi_iterate(const mpi_plan* plan, const void* s, void* c, const mpi_iter_params* params,
+                void* work, size_t work_bytes, hipStream_t stream);
+
+/* Query a built plan: effective radius, FFT size (0 on the direct path) and
+ * the convolution path taken (MPI_CONV_DIRECT or MPI_CONV_FFT). */
+int mpi_plan_info(const mpi_plan* plan, int32_t* radius, int32_t* fft_size, int32_t* conv_mode);
+
+/* Diagnostics for timing one kernel at a time.  The forward operator and its
+ * transpose each run as a short sequence of kernels (stages); stages
+ * 0 .. count/2-1 are those of mpi_forward, the rest those of mpi_adjoint.
+ * mpi_stage_launch enqueues `reps` launches of one stage exactly as the full
+ * call would launch it (same grid, same buffers: c is read by the forward
+ * stages and written by the last transpose stage, s the other way round,
+ * intermediates live in `work`).  A stage reads what the previous stage of its
+ * sequence left in `work`, so run the full call once first for meaningful
+ * data.  Names are static strings. */
+int mpi_stage_count(const mpi_plan* plan);
+const char* mpi_stage_name(const mpi_plan* plan, int stage);
+int mpi_stage_launch(const mpi_plan* plan, int stage, int reps, void* c, void* s,
+                     void* work, size_t work_bytes, hipStream_t stream);
+
+int mpi_plan_destroy(mpi_plan* plan);
+const char* mpi_status_str(int status);
+int mpi_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPIK_H */

@@ -1,0 +1,316 @@
+// Plan-build kernels: the float64 kernel table K_h(delta d) (eq. kernel:matrix
+// with K_h(y) = K(y/h)/h), its spectra for the FFT path, the FFT twiddles and
+// the sample-to-cell binning (base cell, bilinear fractions, stable sort by
+// cell, and the cell-grouped list of (sample, corner) contributions used by
+// the deterministic transpose).
+#pragma once
+#include "common.hpp"
+
+namespace mpik {
+
+// Taylor coefficients of L(z) = coth z - 1/z = sum_{n>=1} b_n z^(2n-1).
+// f(z) = z coth z = 1 + sum b_n z^(2n) solves z f' = f - f^2 + z^2, which gives
+// (2n+1) b_n = [n == 1] - sum_{k=1}^{n-1} b_k b_{n-k}.  Filled once per build.
+constexpr int kSeriesTerms = 24;
+constexpr double kSeriesCut = 1.0;   // |z| below: series (radius of convergence pi)
+
+__device__ __forceinline__ void langevin_all(double z, const double* __restrict__ b,
+                                             double& L, double& L1, double& L2) {
+    // z >= 0 in every use here (a distance over h)
+    if (z < kSeriesCut) {
+        const double z2 = z * z;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        // Horner in z^2 from the highest term
+        for (int n = kSeriesTerms; n >= 1; --n) {
+            const double p = 2.0 * n - 1.0;
+            s0 = s0 * z2 + b[n - 1];
+            s1 = s1 * z2 + b[n - 1] * p;
+            if (n >= 2) s2 = s2 * z2 + b[n - 1] * p * (p - 1.0);
+        }
+        L = s0 * z;         // sum_{n>=1} b_n z^(2n-1)
+        L1 = s1;            // sum_{n>=1} b_n (2n-1) z^(2n-2)
+        L2 = s2 * z;        // sum_{n>=2} b_n (2n-1)(2n-2) z^(2n-3)
+    } else {
+        const double u = exp(-2.0 * z);           // e^{-2z}
+        const double om = -expm1(-2.0 * z);       // 1 - e^{-2z}
+        const double iz = 1.0 / z;
+        L = (1.0 + u) / om - iz;                  // coth z - 1/z
+        L1 = iz * iz - 4.0 * u / (om * om);       // 1/z^2 - 1/sinh^2 z
+        L2 = 8.0 * u * (1.0 + u) / (om * om * om) - 2.0 * iz * iz * iz;   // 2 cosh/sinh^3 - 2/z^3
+    }
+}
+
+__global__ void k_series(double* __restrict__ b) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        for (int n = 1; n <= kSeriesTerms; ++n) {
+            double acc = (n == 1) ? 1.0 : 0.0;
+            for (int k = 1; k < n; ++k) acc -= b[k - 1] * b[n - k - 1];
+            b[n - 1] = acc / (2.0 * n + 1.0);
+        }
+    }
+}
+
+// Kernel table in float64, [3][2R+1][2R+1] indexed [ch][dy+R][dx+R], and the
+// delta^2-scaled copy for the direct path in the compute type, reversed in x
+// (taps[ch][dy+R][t] = delta^2 K_ch(R - t, dy)) with rows zero-padded to taps_w.
+// With q = dx^2 + dy^2 and r = delta sqrt(q) / h:
+//   K_xx = (L'(r) dx^2 + L(r)/r dy^2) / (q h),  K_xy = (L'(r) - L(r)/r) dx dy / (q h),
+//   K_yy = (L'(r) dy^2 + L(r)/r dx^2) / (q h),  K(0) = I / (3h).
+// With `deriv` the table holds dK_h/dh instead:
+//   -h^-2 [(L' + r L'') P + L' (I - P)],  -I/(3h^2) at 0.
+template <typename T>
+__global__ void k_table(const Prob* __restrict__ P, char* __restrict__ plan, const double* __restrict__ series,
+                        double* __restrict__ tab64, T* __restrict__ taps, int deriv) {
+    const Prob& p = *P;
+    const int R = p.radius, W = 2 * R + 1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= W * W) return;
+    const int dy = idx / W - R, dx = idx % W - R;
+    const double h = p.h, delta = 2.0 / p.n;
+    const double q = double(dx * dx + dy * dy);
+    double kxx, kxy, kyy;
+    if (q == 0.0) {
+        kxx = kyy = deriv ? -1.0 / (3.0 * h * h) : 1.0 / (3.0 * h);
+        kxy = 0.0;
+    } else {
+        const double r = delta * sqrt(q) / h;
+        double L, L1, L2;
+        langevin_all(r, series, L, L1, L2);
+        double a, b, s;
+        if (!deriv) { a = L1; b = L / r; s = 1.0 / (q * h); }
+        else { a = L1 + r * L2; b = L1; s = -1.0 / (q * h * h); }
+        kxx = (a * dx * dx + b * dy * dy) * s;
+        kxy = (a - b) * dx * dy * s;
+        kyy = (a * dy * dy + b * dx * dx) * s;
+    }
+    const int plane = W * W;
+    if (tab64) {
+        tab64[idx] = kxx;
+        tab64[plane + idx] = kxy;
+        tab64[2 * plane + idx] = kyy;
+    }
+    if (taps) {
+        const double d2 = delta * delta;
+        const int tw = p.taps_w;
+        const int o = (dy + R) * tw + (R - dx);
+        taps[o] = T(d2 * kxx);
+        taps[W * tw + o] = T(d2 * kxy);
+        taps[2 * W * tw + o] = T(d2 * kyy);
+    }
+}
+
+// Zero the padding columns of the direct-path tap rows.
+template <typename T>
+__global__ void k_taps_pad(const Prob* __restrict__ P, T* __restrict__ taps) {
+    const Prob& p = *P;
+    const int W = 2 * p.radius + 1, tw = p.taps_w;
+    const int pad = tw - W;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 3 * W * pad) return;
+    const int row = idx / pad, col = W + idx % pad;
+    taps[row * tw + col] = T(0);
+}
+
+// cos / sin of 2 pi m / M in float64 and the twiddles e^{-2 pi i m/M}.
+template <typename T>
+__global__ void k_trig(const Prob* __restrict__ P, double* __restrict__ cs, cx<T>* __restrict__ tw) {
+    const int M = P->m;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    double s, c;
+    sincospi(2.0 * m / M, &s, &c);
+    cs[2 * m] = c;
+    cs[2 * m + 1] = s;
+    tw[m] = cx<T>{T(c), T(-s)};
+}
+
+// Spectra of the circularly embedded table on the M x M grid.  Every channel
+// has a real spectrum: K_xx, K_yy are even in each axis, K_xy odd in each:
+//   xx, yy:  S(kx, ky) =  sum_{dx,dy} K cos(2 pi kx dx/M) cos(2 pi ky dy/M)
+//   xy:      S(kx, ky) = -sum_{dx,dy} K sin(2 pi kx dx/M) sin(2 pi ky dy/M)
+// computed separably in float64 over the half ranges; stored for
+// kx, ky in [0, M/2] as [ch][kx][ky], scaled by delta^2 / M^2 (the Riemann
+// weight and the inverse-FFT normalisation).
+// Pass 1: U[ch][dy][kx] for dy in [0, R].
+__global__ void k_spec_rows(const Prob* __restrict__ P, const double* __restrict__ tab64,
+                            const double* __restrict__ cs, double* __restrict__ U) {
+    const Prob& p = *P;
+    const int R = p.radius, W = 2 * R + 1, M = p.m, H = M / 2 + 1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 3 * (R + 1) * H) return;
+    const int ch = idx / ((R + 1) * H);
+    const int rem = idx % ((R + 1) * H);
+    const int dy = rem / H, kx = rem % H;
+    const double* row = tab64 + ch * W * W + (dy + R) * W + R;   // row[dx], dx in [-R, R]
+    double acc;
+    if (ch != 1) {
+        acc = row[0];
+        for (int dx = 1; dx <= R; ++dx) acc += 2.0 * row[dx] * cs[2 * ((kx * dx) & (M - 1))];
+    } else {
+        acc = 0.0;
+        for (int dx = 1; dx <= R; ++dx) acc += 2.0 * row[dx] * cs[2 * ((kx * dx) & (M - 1)) + 1];
+    }
+    U[idx] = acc;
+}
+
+template <typename T>
+__global__ void k_spec_cols(const Prob* __restrict__ P, const double* __restrict__ U,
+                            const double* __restrict__ cs, T* __restrict__ spec) {
+    const Prob& p = *P;
+    const int R = p.radius, M = p.m, H = M / 2 + 1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 3 * H * H) return;
+    const int ch = idx / (H * H);
+    const int rem = idx % (H * H);
+    const int kx = rem / H, ky = rem % H;
+    const double* u = U + ch * (R + 1) * H + kx;   // u[dy * H]
+    double acc;
+    if (ch != 1) {
+        acc = u[0];
+        for (int dy = 1; dy <= R; ++dy) acc += 2.0 * u[dy * H] * cs[2 * ((ky * dy) & (M - 1))];
+    } else {
+        acc = 0.0;
+        for (int dy = 1; dy <= R; ++dy) acc -= 2.0 * u[dy * H] * cs[2 * ((ky * dy) & (M - 1)) + 1];
+    }
+    const double delta = 2.0 / p.n;
+    spec[idx] = T(acc * delta * delta / (double(M) * double(M)));
+}
+
+// ---------------------------------------------------------------------------
+// Binning.  g = (x + 1)/delta - 1/2 in float64; a sample needs 0 <= g <= N-1
+// on both axes (else the error flag is raised); i0 = min(floor g, N-2),
+// fraction g - i0 in [0, 1].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_bin_prep(const Prob* __restrict__ P, const T* __restrict__ r, int* __restrict__ cell,
+                           double* __restrict__ frac, int* __restrict__ bincount, int* __restrict__ err) {
+    const Prob& p = *P;
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= p.t) return;
+    const int n = p.n;
+    const double delta = 2.0 / n;
+    const double gx = (double(r[2 * k]) + 1.0) / delta - 0.5;
+    const double gy = (double(r[2 * k + 1]) + 1.0) / delta - 0.5;
+    const bool ok = (gx >= 0.0) && (gx <= double(n - 1)) && (gy >= 0.0) && (gy <= double(n - 1));
+    if (!ok) {
+        err[0] = 1;
+        cell[k] = -1;
+        return;
+    }
+    const int i0 = min(int(floor(gx)), n - 2);
+    const int j0 = min(int(floor(gy)), n - 2);
+    cell[k] = j0 * (n - 1) + i0;
+    frac[2 * k] = gx - i0;
+    frac[2 * k + 1] = gy - j0;
+    atomicAdd(&bincount[j0 * (n - 1) + i0], 1);
+}
+
+// Exclusive scan of `count` ints by one work-group of 1024 threads; out has
+// count + 1 entries.  Also resets `cursor` (if given) to the scanned offsets.
+__global__ void k_scan(const int* __restrict__ in, int* __restrict__ out, int count, int* __restrict__ cursor) {
+    __shared__ int part[1024];
+    const int tid = threadIdx.x;
+    const int per = (count + 1023) / 1024;
+    const int a = min(tid * per, count), b = min(a + per, count);
+    int s = 0;
+    for (int i = a; i < b; ++i) s += in[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = (tid >= off) ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = part[tid] - s;   // exclusive prefix of this thread's chunk
+    for (int i = a; i < b; ++i) {
+        out[i] = run;
+        if (cursor) cursor[i] = run;
+        run += in[i];
+    }
+    if (tid == 1023) out[count] = part[1023];
+}
+
+// Stable placement of the samples in cell order by one work-group: samples
+// are taken in time order in chunks of blockDim; a sample's rank inside its
+// chunk is the number of earlier chunk members with the same cell, its slot
+// cursor[cell] + rank; after each chunk cursor[cell] advances past the chunk.
+template <typename T>
+__global__ void k_place(const Prob* __restrict__ P, const int* __restrict__ cell, const double* __restrict__ frac,
+                        const T* __restrict__ v, int* __restrict__ cursor, char* __restrict__ plan) {
+    extern __shared__ int s_cell[];
+    const Prob& p = *P;
+    vec4<T>* samp = at<vec4<T>>(plan, p.o_samp);
+    int* perm = at<int>(plan, p.o_perm);
+    int* bcell = at<int>(plan, p.o_bcell);
+    const int nb = p.nb;
+    const int tid = threadIdx.x, bs = blockDim.x;
+    for (int64_t c0 = 0; c0 < p.t; c0 += bs) {
+        const int64_t k = c0 + tid;
+        const int q = (k < p.t) ? cell[k] : -1;
+        s_cell[tid] = q;
+        __syncthreads();
+        int rank = 0;
+        for (int u = 0; u < tid; ++u) rank += (s_cell[u] == q);
+        int pos = -1;
+        if (q >= 0) pos = cursor[q] + rank;
+        __syncthreads();
+        if (q >= 0) {
+            atomicMax(&cursor[q], pos + 1);
+            perm[pos] = int(k);
+            bcell[pos] = (q % nb) | ((q / nb) << 16);
+            vec4<T> e;
+            e.x = T(frac[2 * k]);
+            e.y = T(frac[2 * k + 1]);
+            e.z = v[2 * k];
+            e.w = v[2 * k + 1];
+            samp[pos] = e;
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
+// Contributions grouped by target cell.  Cell (j, i) receives corner 0 of
+// base cell (j, i), corner 1 (x-fraction side) of (j, i-1), corner 2 of
+// (j-1, i) and corner 3 of (j-1, i-1), in that order and in cell order within
+// each base cell.
+__device__ __forceinline__ void cell_sources(int j, int i, int n, const int* __restrict__ binstart,
+                                             int lo[4], int hi[4]) {
+    const int nb = n - 1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int bj = j - (c >> 1), bi = i - (c & 1);
+        if (bj >= 0 && bj < nb && bi >= 0 && bi < nb) {
+            lo[c] = binstart[bj * nb + bi];
+            hi[c] = binstart[bj * nb + bi + 1];
+        } else {
+            lo[c] = hi[c] = 0;
+        }
+    }
+}
+
+__global__ void k_cell_count(const Prob* __restrict__ P, const char* __restrict__ plan, int* __restrict__ cnt) {
+    const Prob& p = *P;
+    const int n = p.n;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * n) return;
+    int lo[4], hi[4];
+    cell_sources(idx / n, idx % n, n, at<int>(plan, p.o_binstart), lo, hi);
+    cnt[idx] = (hi[0] - lo[0]) + (hi[1] - lo[1]) + (hi[2] - lo[2]) + (hi[3] - lo[3]);
+}
+
+__global__ void k_cell_items(const Prob* __restrict__ P, char* __restrict__ plan) {
+    const Prob& p = *P;
+    const int n = p.n;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * n) return;
+    int lo[4], hi[4];
+    cell_sources(idx / n, idx % n, n, at<int>(plan, p.o_binstart), lo, hi);
+    int* items = at<int>(plan, p.o_items);
+    int o = at<int>(plan, p.o_cellstart)[idx];
+    for (int c = 0; c < 4; ++c)
+        for (int s = lo[c]; s < hi[c]; ++s) items[o++] = s | (c << 30);
+}
+
+}  // namespace mpik

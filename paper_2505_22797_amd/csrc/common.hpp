@@ -1,0 +1,191 @@
+// Device-side types shared by every kernel of the library: complex numbers,
+// the per-problem descriptor, the in-LDS Stockham FFT and small helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpik {
+
+constexpr int kWave = 64;
+
+template <typename T> struct cx { T x, y; };
+
+template <typename T> __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.x, -a.y}; }
+template <typename T> __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV> __device__ __forceinline__ cx<T> mul_mi(cx<T> a) {
+    return INV ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x};
+}
+
+template <typename T> struct v4;
+template <> struct v4<float> { using type = float4; };
+template <> struct v4<double> { using type = double4; };
+template <typename T> struct v2;
+template <> struct v2<float> { using type = float2; };
+template <> struct v2<double> { using type = double2; };
+template <typename T> using vec4 = typename v4<T>::type;
+template <typename T> using vec2 = typename v2<T>::type;
+
+// ---------------------------------------------------------------------------
+// Problem descriptor, resident in plan memory.  Offsets are in bytes from the
+// plan base (o_*) or from the work base (w_*); every buffer is 256-byte aligned.
+// ---------------------------------------------------------------------------
+struct Prob {
+    int32_t n;         // grid side N
+    int32_t nb;        // bins per side, N - 1
+    int32_t radius;    // effective window half-width R <= N - 1
+    int32_t m;         // FFT size M (0 on the direct path)
+    int32_t log2m;
+    int32_t mode;      // 0 direct, 1 FFT
+    int32_t taps_w;    // padded row length of the direct-path tap table
+    int32_t pad0;
+    int64_t t;         // samples
+    double h;
+    int64_t o_c;       // element offset of this problem's concentration in the caller's buffer
+    int64_t o_s;       // element offset of this problem's signal in the caller's buffer
+    // plan memory
+    int64_t o_taps;      // T [3][2R+1][taps_w]   delta^2 K_h (direct path)
+    int64_t o_spec;      // T [3][M/2+1][M/2+1]   delta^2/M^2 * DFT of K_h, [ch][kx][ky]
+    int64_t o_tw;        // cx<T> [M]             e^{-2 pi i k / M}
+    int64_t o_samp;      // vec4<T> [T]           (fx, fy, vx, vy) in cell order
+    int64_t o_perm;      // int32 [T]             cell order -> time index
+    int64_t o_bcell;     // int32 [T]             base cell i0 | j0 << 16, cell order
+    int64_t o_binstart;  // int32 [nb*nb + 1]     first sample of every base cell
+    int64_t o_items;     // int32 [4T]            (sample | corner << 30), grouped by cell
+    int64_t o_cellstart; // int32 [N*N + 1]       first item of every cell
+    int64_t o_err;       // int32 [4]             build error flags
+    int64_t o_scratch;   // build-time scratch
+    // work memory
+    int64_t w_g;       // T [3][N][N]       sampled field G or its transpose image
+    int64_t w_t1;      // cx<T> [3][M/2+1][N]
+    int64_t w_t2;      // cx<T> [3][N][M/2+1]
+    int64_t w_ysort;   // vec2<T> [T]       measured signal in cell order
+    int64_t w_res;     // vec2<T> [T]       residual in cell order
+    int64_t w_u;       // T [N][N]          pre-denoise iterate
+    int64_t w_grad;    // T [N][N]
+};
+
+template <typename P> __device__ __forceinline__ P* at(char* base, int64_t off) {
+    return reinterpret_cast<P*>(base + off);
+}
+template <typename P> __device__ __forceinline__ const P* at(const char* base, int64_t off) {
+    return reinterpret_cast<const P*>(base + off);
+}
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// ---------------------------------------------------------------------------
+// Stockham autosort FFT of one line of M points held in LDS, executed by a
+// 64-lane wavefront.  Mixed radix 8/4/2: a pass of radix R with span Ns takes
+// butterfly j (j < M/R) from in[j + r M/R], applies the twiddle
+// w^(r (j mod Ns) M/(Ns R)), does a length-R DFT and writes to
+// out[(j / Ns) Ns R + (j mod Ns) + r Ns]; the result comes out in natural
+// order.  Forward uses e^{-2 pi i/M}, inverse the conjugate; no scaling.
+// All waves of the work-group must call it together (it uses __syncthreads);
+// `active` selects the waves that do arithmetic.
+// ---------------------------------------------------------------------------
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cx<T>* v) {
+    cx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cx<T>* v) {
+    cx<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    cx<T> s13 = cadd(v[1], v[3]), d13 = mul_mi<T, INV>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+    const T h = T(0.70710678118654752440084436210484903928);
+    // even half: DFT4 of v0, v2, v4, v6
+    cx<T> a0 = cadd(v[0], v[4]), a1 = csub(v[0], v[4]);
+    cx<T> a2 = cadd(v[2], v[6]), a3 = mul_mi<T, INV>(csub(v[2], v[6]));
+    cx<T> e0 = cadd(a0, a2), e2 = csub(a0, a2), e1 = cadd(a1, a3), e3 = csub(a1, a3);
+    // odd half: DFT4 of v1, v3, v5, v7
+    cx<T> b0 = cadd(v[1], v[5]), b1 = csub(v[1], v[5]);
+    cx<T> b2 = cadd(v[3], v[7]), b3 = mul_mi<T, INV>(csub(v[3], v[7]));
+    cx<T> o0 = cadd(b0, b2), o2 = csub(b0, b2), o1 = cadd(b1, b3), o3 = csub(b1, b3);
+    // twiddles w^1 = (1 -+ i)/sqrt2, w^2 = -+i, w^3 = (-1 -+ i)/sqrt2
+    cx<T> t1 = INV ? cx<T>{h * (o1.x - o1.y), h * (o1.x + o1.y)} : cx<T>{h * (o1.x + o1.y), h * (o1.y - o1.x)};
+    cx<T> t2 = mul_mi<T, INV>(o2);
+    cx<T> t3 = INV ? cx<T>{-h * (o3.x + o3.y), h * (o3.x - o3.y)} : cx<T>{h * (o3.y - o3.x), -h * (o3.x + o3.y)};
+    v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+    v[1] = cadd(e1, t1); v[5] = csub(e1, t1);
+    v[2] = cadd(e2, t2); v[6] = csub(e2, t2);
+    v[3] = cadd(e3, t3); v[7] = csub(e3, t3);
+}
+
+template <typename T, bool INV, int R>
+__device__ __forceinline__ void stockham_pass(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                              const cx<T>* __restrict__ tw, int M, int Ns, int lane) {
+    const int nb = M / R;
+    const int step = M / (Ns * R);
+    for (int j = lane; j < nb; j += kWave) {
+        const int k = j % Ns;
+        cx<T> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = in[j + r * nb];
+        if (Ns > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cx<T> w = tw[(r * k * step) & (M - 1)];
+                if (INV) w.y = -w.y;
+                v[r] = cmul(v[r], w);
+            }
+        }
+        if (R == 8) dft8<T, INV>(v);
+        else if (R == 4) dft4<T, INV>(v);
+        else dft2<T, INV>(v);
+        const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[base + r * Ns] = v[r];
+    }
+}
+
+// Returns the buffer that holds the result (a or b).
+template <typename T, bool INV, int M>
+__device__ __forceinline__ cx<T>* fft_line(cx<T>* a, cx<T>* b, const cx<T>* tw, int lane, bool active) {
+    static_assert(M >= 64 && (M & (M - 1)) == 0, "M must be a power of two >= 64");
+    constexpr int L = __builtin_ctz(M);
+    constexpr int n8 = L / 3;
+    constexpr int rem = L % 3;   // 0, 1 (radix 2) or 2 (radix 4)
+    cx<T>* in = a;
+    cx<T>* out = b;
+    int Ns = 1;
+#pragma unroll
+    for (int p = 0; p < n8; ++p) {
+        if (active) stockham_pass<T, INV, 8>(in, out, tw, M, Ns, lane);
+        __syncthreads();
+        cx<T>* t = in; in = out; out = t;
+        Ns *= 8;
+    }
+    if (rem == 2) {
+        if (active) stockham_pass<T, INV, 4>(in, out, tw, M, Ns, lane);
+        __syncthreads();
+        cx<T>* t = in; in = out; out = t;
+    } else if (rem == 1) {
+        if (active) stockham_pass<T, INV, 2>(in, out, tw, M, Ns, lane);
+        __syncthreads();
+        cx<T>* t = in; in = out; out = t;
+    }
+    return in;
+}
+
+template <int M> struct FftPasses {
+    static constexpr int L = __builtin_ctz(M);
+    static constexpr int count = L / 3 + (L % 3 != 0);
+};
+
+}  // namespace mpik

@@ -1,0 +1,241 @@
+// Direct path of the operator for truncated kernels, plus the element-wise
+// kernels shared by both paths (sampling bands from global memory, the
+// denoiser step, permutations).
+//
+// conv_direct: out_ch[j][i] = sum_{|dx|,|dy|<=R} delta^2 K_ch(dx,dy) in[j-dy][i-dx]
+// (eq. coreoperator as a Riemann sum, zero outside the grid).  A work-group
+// computes a 16 x 16 output tile; its input tile with an R-halo sits in LDS.
+// Lane l of every wave owns a 1 x 4 strip of outputs (row l/4, columns
+// 4(l%4)..+3); the waves split the dy range (wave w takes dy = -R + w,
+// -R + w + S, ...), so the tap address is uniform per wave and the taps come
+// through scalar loads.  Along dx a sliding window of input values in
+// registers gives 4 x COUT multiply-adds per LDS read.  The S wave partials
+// are summed in wave order in LDS (deterministic).
+//   CIN = 1, COUT = 3: the forward field (one input, three kernel channels)
+//   CIN = 3, COUT = 1: the transpose (sum over channels; each K_ch is even)
+#pragma once
+#include "common.hpp"
+#include "sampling.hpp"
+
+namespace mpik {
+
+constexpr int kTile = 16;
+constexpr int kStrip = 4;
+
+__host__ __device__ constexpr int direct_row_len(int R) {
+    // columns read: up to 12 + taps_w + 7 with taps_w <= 2R + 4
+    return ((kTile + 2 * R + 12) + 3) / 4 * 4;
+}
+
+template <typename T, int CIN>
+__device__ __forceinline__ void load_tile(T* tile, const T* __restrict__ in, int N, int R, int y0, int x0,
+                                          int row_len, int tid, int nt) {
+    const int rows = kTile + 2 * R;
+    const int total = CIN * rows * row_len;
+    for (int idx = tid; idx < total; idx += nt) {
+        const int ch = idx / (rows * row_len);
+        const int rem = idx % (rows * row_len);
+        const int ly = rem / row_len, lx = rem % row_len;
+        const int gy = y0 - R + ly, gx = x0 - R + lx;
+        T v = T(0);
+        if (lx < kTile + 2 * R && gy >= 0 && gy < N && gx >= 0 && gx < N) v = in[int64_t(ch) * N * N + int64_t(gy) * N + gx];
+        tile[idx] = v;
+    }
+}
+
+// EPI 0: out = conv;  1: out = c_in - tau * conv  (COUT == 1 only)
+template <typename T, int CIN, int COUT, int S, int EPI>
+__global__ void __launch_bounds__(64 * S) k_conv_direct(const Prob* __restrict__ P, const T* in, T* out,
+                                                        const T* c_in, double tau, const char* __restrict__ plan,
+                                                        int in_is_caller, int out_is_caller) {
+    extern __shared__ __align__(16) char smem[];
+    const Prob& p = P[blockIdx.z];
+    const int N = p.n, R = p.radius, tw = p.taps_w;
+    const int tiles = (N + kTile - 1) / kTile;
+    const int ty0 = blockIdx.y * kTile, tx0 = blockIdx.x * kTile;
+    if (blockIdx.x >= tiles || blockIdx.y >= tiles) return;
+    if (in_is_caller) in += p.o_c;
+    if (out_is_caller) out += p.o_c;
+    if (c_in) c_in += p.o_c;
+    const int row_len = direct_row_len(R);
+    const int rows = kTile + 2 * R;
+    T* tile = reinterpret_cast<T*>(smem);
+    const int tid = threadIdx.x;
+    load_tile<T, CIN>(tile, in, N, R, ty0, tx0, row_len, tid, 64 * S);
+    __syncthreads();
+    const int wave = uniform(tid / kWave), lane = tid % kWave;
+    const int ly = lane / 4, sx = (lane % 4) * kStrip;
+    const T* taps = at<T>(plan, p.o_taps);
+    const int W = 2 * R + 1;
+    T acc[COUT][kStrip];
+#pragma unroll
+    for (int o = 0; o < COUT; ++o)
+#pragma unroll
+        for (int w = 0; w < kStrip; ++w) acc[o][w] = T(0);
+    for (int dy = -R + wave; dy <= R; dy += S) {
+        const int trow = (dy + R) * tw;
+#pragma unroll
+        for (int ci = 0; ci < CIN; ++ci) {
+            const T* row = tile + (ci * rows + ly - dy + R) * row_len + sx;
+            T x[8];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = row[u];
+            for (int t0 = 0; t0 < tw; t0 += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x[4 + u] = row[t0 + 4 + u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (COUT == 3) {
+                        const T k0 = taps[trow + t0 + u];
+                        const T k1 = taps[W * tw + trow + t0 + u];
+                        const T k2 = taps[2 * W * tw + trow + t0 + u];
+#pragma unroll
+                        for (int w = 0; w < kStrip; ++w) {
+                            acc[0][w] += k0 * x[u + w];
+                            acc[COUT > 1 ? 1 : 0][w] += k1 * x[u + w];
+                            acc[COUT > 2 ? 2 : 0][w] += k2 * x[u + w];
+                        }
+                    } else {
+                        const T k = taps[ci * W * tw + trow + t0 + u];
+#pragma unroll
+                        for (int w = 0; w < kStrip; ++w) acc[0][w] += k * x[u + w];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x[u] = x[4 + u];
+            }
+        }
+    }
+    // fixed-order reduction over the S waves
+    __syncthreads();
+    T* red = tile;   // [S][64][COUT * 4]
+#pragma unroll
+    for (int o = 0; o < COUT; ++o)
+#pragma unroll
+        for (int w = 0; w < kStrip; ++w) red[(wave * kWave + lane) * COUT * kStrip + o * kStrip + w] = acc[o][w];
+    __syncthreads();
+    if (wave == 0) {
+        const int gy = ty0 + ly;
+#pragma unroll
+        for (int o = 0; o < COUT; ++o) {
+#pragma unroll
+            for (int w = 0; w < kStrip; ++w) {
+                T s = red[lane * COUT * kStrip + o * kStrip + w];
+                for (int q = 1; q < S; ++q) s += red[(q * kWave + lane) * COUT * kStrip + o * kStrip + w];
+                const int gx = tx0 + sx + w;
+                if (gy < N && gx < N) {
+                    const int64_t off = int64_t(o) * N * N + int64_t(gy) * N + gx;
+                    if (EPI == 0) out[off] = s;
+                    else out[off] = c_in[off] - T(tau) * s;
+                }
+            }
+        }
+    }
+}
+
+// Bilinear gather + contraction for base-cell row b from a field in global
+// memory ([3][N][N]): rows b and b+1 are staged in LDS first.
+template <typename T, bool RESID>
+__global__ void __launch_bounds__(256) k_gather_rows(const Prob* __restrict__ P, const T* __restrict__ G,
+                                                     T* __restrict__ s, const char* __restrict__ plan,
+                                                     char* __restrict__ work) {
+    extern __shared__ __align__(16) char smem[];
+    const Prob& p = P[blockIdx.y];
+    const int N = p.n, nb = p.nb, b = blockIdx.x;
+    if (b >= nb) return;
+    const int* binstart = at<int>(plan, p.o_binstart);
+    const int p0 = binstart[b * nb], p1 = binstart[(b + 1) * nb];
+    if (p0 == p1) return;
+    T* g0 = reinterpret_cast<T*>(smem);
+    T* g1 = g0 + 3 * N;
+    for (int i = threadIdx.x; i < 6 * N; i += blockDim.x) {
+        const int half = i / (3 * N), rem = i % (3 * N), ch = rem / N, x = rem % N;
+        g0[i] = G[int64_t(ch) * N * N + int64_t(b + half) * N + x];
+    }
+    __syncthreads();
+    gather_band<T, RESID>(g0, g1, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int>(plan, p.o_bcell),
+                          at<int>(plan, p.o_perm), at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res),
+                          s + p.o_s, threadIdx.x, blockDim.x);
+}
+
+// Deterministic transpose sampling for a pair of rows into a field in global
+// memory ([3][N][N]).
+template <typename T, bool SORTED>
+__global__ void __launch_bounds__(192) k_scatter_rows(const Prob* __restrict__ P, const T* __restrict__ s,
+                                                      T* __restrict__ G, const char* __restrict__ plan,
+                                                      char* __restrict__ work) {
+    extern __shared__ __align__(16) char smem[];
+    const Prob& p = P[blockIdx.y];
+    const int N = p.n, q = blockIdx.x;
+    const int r0 = 2 * q;
+    if (r0 >= N) return;
+    const int rows = (r0 + 1 < N) ? 2 : 1;
+    auto& sc = *reinterpret_cast<ScatterSmem<T>*>(smem);
+    T* g = reinterpret_cast<T*>(smem + ((sizeof(ScatterSmem<T>) + 15) / 16) * 16);
+    scatter_band<T, SORTED>(g, sc, N, r0, rows, at<int>(plan, p.o_cellstart), at<int>(plan, p.o_items),
+                            at<vec4<T>>(plan, p.o_samp), at<int>(plan, p.o_perm), at<vec2<T>>(work, p.w_res),
+                            s + p.o_s, threadIdx.x);
+    const int nc = rows * N;
+    for (int i = threadIdx.x; i < 3 * nc; i += blockDim.x) {
+        const int ch = i / nc, lc = i % nc;
+        G[int64_t(ch) * N * N + int64_t(r0) * N + lc] = g[i];
+    }
+}
+
+// ysort[p] = s[perm[p]]: the measured signal in cell order.
+template <typename T>
+__global__ void k_permute_signal(const Prob* __restrict__ P, const T* __restrict__ s, const char* __restrict__ plan,
+                                 char* __restrict__ work) {
+    const Prob& p = P[blockIdx.y];
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= p.t) return;
+    const int k = at<int>(plan, p.o_perm)[i];
+    const T* sp = s + p.o_s;
+    vec2<T> y;
+    y.x = sp[2 * k];
+    y.y = sp[2 * k + 1];
+    at<vec2<T>>(work, p.w_ysort)[i] = y;
+}
+
+// c = D(u): separable Gaussian (weights w[0..2r], zero padding), rows then
+// columns, on a 32 x 32 output tile with an r-halo in LDS.
+constexpr int kDnTile = 32;
+constexpr int kDnMaxR = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_denoise(const Prob* __restrict__ P, const T* __restrict__ u,
+                                                 T* __restrict__ c, const double* __restrict__ wts, int rad) {
+    __shared__ T a[(kDnTile + 2 * kDnMaxR) * (kDnTile + 2 * kDnMaxR)];
+    __shared__ T b[(kDnTile + 2 * kDnMaxR) * kDnTile];
+    const Prob& p = P[blockIdx.z];
+    const int N = p.n;
+    const int y0 = blockIdx.y * kDnTile, x0 = blockIdx.x * kDnTile;
+    if (y0 >= N || x0 >= N) return;
+    const T* up = u + p.o_c;
+    T* cp = c + p.o_c;
+    const int L = kDnTile + 2 * rad;
+    for (int i = threadIdx.x; i < L * L; i += blockDim.x) {
+        const int ly = i / L, lx = i % L;
+        const int gy = y0 - rad + ly, gx = x0 - rad + lx;
+        a[i] = (gy >= 0 && gy < N && gx >= 0 && gx < N) ? up[int64_t(gy) * N + gx] : T(0);
+    }
+    __syncthreads();
+    // vertical pass (over y) first: b[ly][x] for ly in [0, 32), then horizontal
+    for (int i = threadIdx.x; i < kDnTile * L; i += blockDim.x) {
+        const int ly = i / L, lx = i % L;
+        T s = T(0);
+        for (int k = 0; k <= 2 * rad; ++k) s += T(wts[k]) * a[(ly + k) * L + lx];
+        b[ly * L + lx] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kDnTile * kDnTile; i += blockDim.x) {
+        const int ly = i / kDnTile, lx = i % kDnTile;
+        const int gy = y0 + ly, gx = x0 + lx;
+        if (gy >= N || gx >= N) continue;
+        T s = T(0);
+        for (int k = 0; k <= 2 * rad; ++k) s += T(wts[k]) * b[ly * L + lx + k];
+        cp[int64_t(gy) * N + gx] = s;
+    }
+}
+
+}  // namespace mpik

@@ -1,0 +1,201 @@
+"""ctypes binding of the C ABI in include/mpik.h.
+
+Argument marshalling only: every step of the operator runs in the HIP kernels
+of libmpik.so.  torch provides device memory (plan and work buffers, inputs,
+outputs) and the stream; the library itself never allocates.  The binding
+raises if the shared library is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmpik.so")
+
+MPI_OK, MPI_ERR_ARG, MPI_ERR_DOMAIN, MPI_ERR_WORKSPACE = 0, -1, -2, -3
+MPI_ERR_DTYPE, MPI_ERR_HIP, MPI_ERR_UNSUPPORTED = -4, -5, -6
+MPI_F32, MPI_F64 = 0, 1
+CONV_MODES = {"auto": 0, "direct": 1, "fft": 2}
+
+EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
+           "mpi_plan_info", "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
+           "mpi_plan_destroy", "mpi_status_str", "mpi_abi_version")
+
+
+class MpiError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("dtype", ctypes.c_int32), ("h", ctypes.c_double),
+                ("radius", ctypes.c_int32), ("conv_mode", ctypes.c_int32), ("interp", ctypes.c_int32),
+                ("channels", ctypes.c_int32), ("n_samples", ctypes.c_int64),
+                ("r", ctypes.c_void_p), ("v", ctypes.c_void_p)]
+
+
+class IterParams(ctypes.Structure):
+    _fields_ = [("n_iter", ctypes.c_int32), ("tau", ctypes.c_double), ("denoise_sigma_px", ctypes.c_double),
+                ("denoise_radius", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with `python -m paper_2505_22797_amd.build`")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        L.mpi_plan_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.mpi_kernel_build.argtypes = [ctypes.POINTER(Problem), vp, sz, vp, ctypes.POINTER(vp)]
+        L.mpi_forward.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.mpi_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.mpi_iterate.argtypes = [vp, vp, vp, ctypes.POINTER(IterParams), vp, sz, vp]
+        L.mpi_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32)]
+        L.mpi_stage_count.argtypes = [vp]
+        L.mpi_stage_name.argtypes = [vp, ctypes.c_int]
+        L.mpi_stage_name.restype = ctypes.c_char_p
+        L.mpi_stage_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, sz, vp]
+        L.mpi_plan_destroy.argtypes = [vp]
+        L.mpi_status_str.argtypes = [ctypes.c_int]
+        L.mpi_status_str.restype = ctypes.c_char_p
+        L.mpi_abi_version.argtypes = []
+        for name in ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
+                     "mpi_plan_info", "mpi_stage_count", "mpi_stage_launch", "mpi_plan_destroy", "mpi_abi_version"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_str(status: int) -> str:
+    return lib().mpi_status_str(int(status)).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != MPI_OK:
+        raise MpiError(rc, what)
+
+
+def _stream(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dtype_code(dt: torch.dtype) -> int:
+    if dt == torch.float32:
+        return MPI_F32
+    if dt == torch.float64:
+        return MPI_F64
+    raise MpiError(MPI_ERR_DTYPE, f"dtype {dt}")
+
+
+def problem(n: int, h: float, radius: int, r: torch.Tensor | None, v: torch.Tensor | None,
+            n_samples: int | None = None, dtype: torch.dtype = torch.float32,
+            conv_mode: str = "auto") -> Problem:
+    p = Problem()
+    p.n, p.h, p.radius = int(n), float(h), int(radius)
+    p.dtype = _dtype_code(r.dtype if r is not None else dtype)
+    p.conv_mode = CONV_MODES[conv_mode]
+    p.interp = 0
+    p.channels = 0
+    p.n_samples = int(r.shape[0] if r is not None else n_samples)
+    p.r = r.data_ptr() if r is not None else None
+    p.v = v.data_ptr() if v is not None else None
+    return p
+
+
+def plan_bytes(prob: Problem) -> tuple[int, int]:
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().mpi_plan_bytes(ctypes.byref(prob), ctypes.byref(pb), ctypes.byref(wb)), "mpi_plan_bytes")
+    return pb.value, wb.value
+
+
+class Plan:
+    """A built plan for one problem: kernel table/spectra and sample binning in
+    device memory owned by this object, plus a reusable work buffer."""
+
+    def __init__(self, n: int, h: float, radius: int, r: torch.Tensor, v: torch.Tensor,
+                 conv_mode: str = "auto", stream=None):
+        if not (r.is_cuda and v.is_cuda):
+            raise ValueError("r and v must be device tensors")
+        if r.dtype != v.dtype or r.shape != v.shape or r.ndim != 2 or r.shape[1] != 2:
+            raise ValueError("r and v must be matching (T, 2) tensors")
+        r = r.contiguous()
+        v = v.contiguous()
+        self.n, self.h, self.dtype, self.device = int(n), float(h), r.dtype, r.device
+        self.n_samples = int(r.shape[0])
+        prob = problem(n, h, radius, r, v, conv_mode=conv_mode)
+        pb, wb = plan_bytes(prob)
+        self.plan_mem = torch.empty(pb, dtype=torch.uint8, device=r.device)
+        self.work = torch.empty(wb, dtype=torch.uint8, device=r.device)
+        handle = ctypes.c_void_p()
+        _check(lib().mpi_kernel_build(ctypes.byref(prob), self.plan_mem.data_ptr(), pb, _stream(stream),
+                                      ctypes.byref(handle)), "mpi_kernel_build")
+        self._h = handle
+        rad, m, mode = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().mpi_plan_info(self._h, ctypes.byref(rad), ctypes.byref(m), ctypes.byref(mode)), "mpi_plan_info")
+        self.radius, self.fft_size = rad.value, m.value
+        self.conv_mode = "fft" if mode.value == 2 else "direct"
+
+    def _vec(self, t: torch.Tensor, shape, name):
+        if t.dtype != self.dtype or t.device != self.device or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of shape {tuple(shape)} on {self.device}")
+        return t
+
+    def forward(self, c: torch.Tensor, s: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        self._vec(c, (self.n, self.n), "c")
+        if s is None:
+            s = torch.empty((self.n_samples, 2), dtype=self.dtype, device=self.device)
+        self._vec(s, (self.n_samples, 2), "s")
+        _check(lib().mpi_forward(self._h, c.data_ptr(), s.data_ptr(), self.work.data_ptr(), self.work.numel(),
+                                 _stream(stream)), "mpi_forward")
+        return s
+
+    def adjoint(self, s: torch.Tensor, c: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        self._vec(s, (self.n_samples, 2), "s")
+        if c is None:
+            c = torch.empty((self.n, self.n), dtype=self.dtype, device=self.device)
+        self._vec(c, (self.n, self.n), "c")
+        _check(lib().mpi_adjoint(self._h, s.data_ptr(), c.data_ptr(), self.work.data_ptr(), self.work.numel(),
+                                 _stream(stream)), "mpi_adjoint")
+        return c
+
+    def iterate(self, s: torch.Tensor, c: torch.Tensor, n_iter: int, tau: float,
+                denoise_sigma_px: float = 0.0, denoise_radius: int = 2, use_graph: bool = True,
+                stream=None) -> torch.Tensor:
+        """In place on c: c <- D(c - tau A^T (A c - s)), n_iter times."""
+        self._vec(s, (self.n_samples, 2), "s")
+        self._vec(c, (self.n, self.n), "c")
+        ip = IterParams(int(n_iter), float(tau), float(denoise_sigma_px), int(denoise_radius), int(bool(use_graph)))
+        _check(lib().mpi_iterate(self._h, s.data_ptr(), c.data_ptr(), ctypes.byref(ip), self.work.data_ptr(),
+                                 self.work.numel(), _stream(stream)), "mpi_iterate")
+        return c
+
+    def stages(self) -> list[str]:
+        n = lib().mpi_stage_count(self._h)
+        return [lib().mpi_stage_name(self._h, k).decode() for k in range(n)]
+
+    def launch_stage(self, stage: int, reps: int, c: torch.Tensor, s: torch.Tensor, stream=None):
+        """Enqueue `reps` launches of one kernel of the forward/transpose sequence."""
+        self._vec(c, (self.n, self.n), "c")
+        self._vec(s, (self.n_samples, 2), "s")
+        _check(lib().mpi_stage_launch(self._h, int(stage), int(reps), c.data_ptr(), s.data_ptr(),
+                                      self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_stage_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mpi_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

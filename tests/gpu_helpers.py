@@ -1,0 +1,49 @@
+"""Shared helpers of the GPU parity tests: seeded inputs rounded once to the
+compute precision, device transfers and the relative L2 metric."""
+import numpy as np
+import torch
+
+import oracle as O
+from paper_2505_22797_amd import mpik
+from paper_2505_22797_amd import synth as S
+
+
+def rel_l2(got, ref) -> float:
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def rounded(a, dtype):
+    """Round once to the compute dtype; return the rounded values in float64."""
+    return np.asarray(a, dtype=np.float32 if dtype == torch.float32 else np.float64).astype(np.float64)
+
+
+def dev(a, dtype):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda").contiguous()
+
+
+class Case:
+    """One problem prepared for both sides: inputs rounded once, the oracle
+    model on the rounded values, and the GPU plan on the same values."""
+
+    def __init__(self, n, h, radius, r, v, c, dtype=torch.float32, conv_mode="auto", method="auto"):
+        self.n, self.h, self.radius, self.dtype = n, h, radius, dtype
+        self.r = rounded(r, dtype)
+        self.v = rounded(v, dtype)
+        self.c = rounded(c, dtype)
+        self.model = O.Model(n, h, radius, self.r, self.v, method=method)
+        self.plan = mpik.Plan(n, h, radius, dev(self.r, dtype), dev(self.v, dtype), conv_mode=conv_mode)
+
+    def t(self, a):
+        return dev(a, self.dtype)
+
+    @staticmethod
+    def host(x):
+        torch.cuda.synchronize()
+        return x.double().cpu().numpy()
+
+
+def case_from(problem: S.Problem, dtype=torch.float32, conv_mode="auto", radius=None):
+    return Case(problem.n, problem.h, problem.radius if radius is None else radius,
+                problem.traj.r, problem.traj.v, problem.c, dtype=dtype, conv_mode=conv_mode)

@@ -1,0 +1,105 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function the
+header declares, and rejects bad descriptors on the host before any device
+work is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpik.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpi_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def mpik():
+    from paper_2505_22797_amd import mpik as m
+    m.lib()
+    return m
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate", "mpi_plan_bytes"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(mpik):
+    lib = mpik.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(mpik.EXPORTS) == set(declared_functions())
+
+
+def test_abi_version_and_status_strings(mpik):
+    assert mpik.lib().mpi_abi_version() == 1
+    seen = set()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        s = mpik.status_str(code)
+        assert s and s != "unknown status"
+        seen.add(s)
+    assert len(seen) == 7
+    assert mpik.status_str(-99) == "unknown status"
+
+
+def _prob(mpik, **kw):
+    base = dict(n=64, h=0.01, radius=31, r=None, v=None, n_samples=1000)
+    base.update(kw)
+    return mpik.problem(base["n"], base["h"], base["radius"], None, None, n_samples=base["n_samples"],
+                        conv_mode=base.get("conv_mode", "auto"))
+
+
+def test_plan_bytes_valid(mpik):
+    pb, wb = mpik.plan_bytes(_prob(mpik))
+    assert pb > 0 and wb > 0 and pb % 256 == 0 and wb % 256 == 0
+    # the FFT path needs its column buffers, the direct path does not
+    pf, wf = mpik.plan_bytes(_prob(mpik, conv_mode="fft"))
+    pd, wd = mpik.plan_bytes(_prob(mpik, conv_mode="direct"))
+    assert wf > wd
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("n", 1, -1), ("n", 2000, -1), ("h", 0.0, -1), ("h", float("nan"), -1), ("radius", -1, -1),
+    ("n_samples", 0, -1), ("dtype", 7, -4), ("conv_mode", 9, -1), ("interp", 1, -6), ("channels", 1, -6),
+])
+def test_plan_bytes_rejects(mpik, field, value, code):
+    p = _prob(mpik)
+    setattr(p, field, value)
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert mpik.lib().mpi_plan_bytes(ctypes.byref(p), ctypes.byref(pb), ctypes.byref(wb)) == code
+
+
+def test_unsupported_sizes(mpik):
+    # an FFT larger than the LDS line buffers
+    p = _prob(mpik, n=1024, radius=1023, conv_mode="fft")
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert mpik.lib().mpi_plan_bytes(ctypes.byref(p), ctypes.byref(pb), ctypes.byref(wb)) == -6
+
+
+def test_build_argument_errors_need_no_gpu(mpik):
+    L = mpik.lib()
+    p = _prob(mpik)
+    out = ctypes.c_void_p()
+    # null r / v / plan memory and a too-small plan are rejected on the host
+    assert L.mpi_kernel_build(ctypes.byref(p), None, 1 << 20, None, ctypes.byref(out)) == -1
+    p.r = 256
+    p.v = 512
+    assert L.mpi_kernel_build(ctypes.byref(p), 4096, 16, None, ctypes.byref(out)) == -3
+    assert L.mpi_kernel_build(ctypes.byref(p), 4097, 1 << 30, None, ctypes.byref(out)) == -1   # misaligned
+    assert out.value is None
+    assert L.mpi_kernel_build(ctypes.byref(p), 4096, 1 << 30, None, None) == -1
+
+
+def test_apply_argument_errors_need_no_gpu(mpik):
+    L = mpik.lib()
+    assert L.mpi_forward(None, 256, 256, 256, 1 << 20, None) == -1
+    assert L.mpi_adjoint(None, 256, 256, 256, 1 << 20, None) == -1
+    assert L.mpi_iterate(None, 256, 256, None, 256, 1 << 20, None) == -1
+    assert L.mpi_plan_destroy(None) == -1
+    assert L.mpi_plan_info(None, None, None, None) == -1
