@@ -126,13 +126,52 @@ int mpi_adjoint(const mpi_plan* plan, const void* s, void* c,
 int mpi_iterate(const mpi_plan* plan, const void* s, void* c, const mpi_iter_params* params,
                 void* work, size_t work_bytes, hipStream_t stream);
 
-/* Query a built plan: effective radius, FFT size (0 on the direct path) and
- * the convolution path taken (MPI_CONV_DIRECT or MPI_CONV_FFT). */
+/* Query a built plan (its first problem): effective radius, FFT size (0 on
+ * the direct path) and the convolution path taken (MPI_CONV_DIRECT or
+ * MPI_CONV_FFT). */
 int mpi_plan_info(const mpi_plan* plan, int32_t* radius, int32_t* fft_size, int32_t* conv_mode);
+
+/* ---------------------------------------------------------------- batches --
+ * Many independent problems (different N, T, h, R, trajectories) in one plan:
+ * every stage of the forward operator, its transpose and the iteration is one
+ * launch over the whole batch.  The concentrations of all problems are
+ * concatenated in one buffer (problem b at element offset c_off[b], N_b^2
+ * elements each) and so are the signals (s_off[b], 2 T_b elements each);
+ * mpi_batch_offsets reports both (count + 1 entries each, the last one the
+ * total).  All problems share one dtype.
+ *
+ * With MPI_BUILD_TUNE and a work buffer of at least work_bytes, problems whose
+ * conv_mode is MPI_CONV_AUTO (and that fit both paths) are built for both
+ * convolution paths and the faster one -- FFT, or the direct path with 4, 8 or
+ * 16 waves splitting a tile's window rows -- is kept, timed with HIP events on
+ * `stream`.  Choices are cached per (dtype, N, R, log2 T) in the process and
+ * appended to the file named by the environment variable MPIK_TUNE_CACHE. */
+enum { MPI_BUILD_TUNE = 1 };
+
+int mpi_batch_bytes(const mpi_problem* probs, int count, size_t* plan_bytes, size_t* work_bytes);
+int mpi_batch_build(const mpi_problem* probs, int count, void* plan_mem, size_t plan_bytes,
+                    void* work, size_t work_bytes, int flags, hipStream_t stream, mpi_plan** out);
+int mpi_batch_count(const mpi_plan* plan);
+int mpi_batch_offsets(const mpi_plan* plan, int64_t* c_offsets, int64_t* s_offsets);
+/* per problem: effective radius, FFT size (0: direct), path, direct-path wave slices */
+int mpi_batch_info(const mpi_plan* plan, int index, int32_t* radius, int32_t* fft_size,
+                   int32_t* conv_mode, int32_t* slices);
+/* s_all = A_b c_b for every problem b, one launch per stage */
+int mpi_batch_forward(const mpi_plan* plan, const void* c_all, void* s_all,
+                      void* work, size_t work_bytes, hipStream_t stream);
+/* c_all = A_b^T s_b for every problem b */
+int mpi_batch_adjoint(const mpi_plan* plan, const void* s_all, void* c_all,
+                      void* work, size_t work_bytes, hipStream_t stream);
+/* c_b <- D(c_b - taus[b] A_b^T (A_b c_b - s_b)), params->n_iter times for all
+ * problems at once (params->tau is ignored; taus is a host array of count). */
+int mpi_batch_iterate(const mpi_plan* plan, const void* s_all, void* c_all,
+                      const mpi_iter_params* params, const double* taus,
+                      void* work, size_t work_bytes, hipStream_t stream);
 
 /* Diagnostics for timing one kernel at a time.  The forward operator and its
  * transpose each run as a short sequence of kernels (stages); stages
- * 0 .. count/2-1 are those of mpi_forward, the rest those of mpi_adjoint.
+ * 0 .. count/2-1 are those of mpi_forward, the rest those of mpi_adjoint;
+ * stages of the path a plan does not use launch nothing.
  * mpi_stage_launch enqueues `reps` launches of one stage exactly as the full
  * call would launch it (same grid, same buffers: c is read by the forward
  * stages and written by the last transpose stage, s the other way round,

@@ -1,8 +1,7 @@
 // Plan-build kernels: the float64 kernel table K_h(delta d) (eq. kernel:matrix
 // with K_h(y) = K(y/h)/h), its spectra for the FFT path, the FFT twiddles and
 // the sample-to-cell binning (base cell, bilinear fractions, stable sort by
-// cell, and the cell-grouped list of (sample, corner) contributions used by
-// the deterministic transpose).
+// base cell).
 #pragma once
 #include "common.hpp"
 
@@ -241,8 +240,7 @@ __global__ void k_place(const Prob* __restrict__ P, const int* __restrict__ cell
     extern __shared__ int s_cell[];
     const Prob& p = *P;
     vec4<T>* samp = at<vec4<T>>(plan, p.o_samp);
-    int* perm = at<int>(plan, p.o_perm);
-    int* bcell = at<int>(plan, p.o_bcell);
+    int2* sidx = at<int2>(plan, p.o_sidx);
     const int nb = p.nb;
     const int tid = threadIdx.x, bs = blockDim.x;
     for (int64_t c0 = 0; c0 < p.t; c0 += bs) {
@@ -257,8 +255,7 @@ __global__ void k_place(const Prob* __restrict__ P, const int* __restrict__ cell
         __syncthreads();
         if (q >= 0) {
             atomicMax(&cursor[q], pos + 1);
-            perm[pos] = int(k);
-            bcell[pos] = (q % nb) | ((q / nb) << 16);
+            sidx[pos] = make_int2((q % nb) | ((q / nb) << 16), int(k));
             vec4<T> e;
             e.x = T(frac[2 * k]);
             e.y = T(frac[2 * k + 1]);
@@ -269,48 +266,6 @@ __global__ void k_place(const Prob* __restrict__ P, const int* __restrict__ cell
         __threadfence_block();
         __syncthreads();
     }
-}
-
-// Contributions grouped by target cell.  Cell (j, i) receives corner 0 of
-// base cell (j, i), corner 1 (x-fraction side) of (j, i-1), corner 2 of
-// (j-1, i) and corner 3 of (j-1, i-1), in that order and in cell order within
-// each base cell.
-__device__ __forceinline__ void cell_sources(int j, int i, int n, const int* __restrict__ binstart,
-                                             int lo[4], int hi[4]) {
-    const int nb = n - 1;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const int bj = j - (c >> 1), bi = i - (c & 1);
-        if (bj >= 0 && bj < nb && bi >= 0 && bi < nb) {
-            lo[c] = binstart[bj * nb + bi];
-            hi[c] = binstart[bj * nb + bi + 1];
-        } else {
-            lo[c] = hi[c] = 0;
-        }
-    }
-}
-
-__global__ void k_cell_count(const Prob* __restrict__ P, const char* __restrict__ plan, int* __restrict__ cnt) {
-    const Prob& p = *P;
-    const int n = p.n;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * n) return;
-    int lo[4], hi[4];
-    cell_sources(idx / n, idx % n, n, at<int>(plan, p.o_binstart), lo, hi);
-    cnt[idx] = (hi[0] - lo[0]) + (hi[1] - lo[1]) + (hi[2] - lo[2]) + (hi[3] - lo[3]);
-}
-
-__global__ void k_cell_items(const Prob* __restrict__ P, char* __restrict__ plan) {
-    const Prob& p = *P;
-    const int n = p.n;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * n) return;
-    int lo[4], hi[4];
-    cell_sources(idx / n, idx % n, n, at<int>(plan, p.o_binstart), lo, hi);
-    int* items = at<int>(plan, p.o_items);
-    int o = at<int>(plan, p.o_cellstart)[idx];
-    for (int c = 0; c < 4; ++c)
-        for (int s = lo[c]; s < hi[c]; ++s) items[o++] = s | (c << 30);
 }
 
 }  // namespace mpik

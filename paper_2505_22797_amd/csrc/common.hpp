@@ -43,7 +43,7 @@ struct Prob {
     int32_t log2m;
     int32_t mode;      // 0 direct, 1 FFT
     int32_t taps_w;    // padded row length of the direct-path tap table
-    int32_t pad0;
+    int32_t slices;    // direct path: waves splitting the dy range of a tile
     int64_t t;         // samples
     double h;
     int64_t o_c;       // element offset of this problem's concentration in the caller's buffer
@@ -53,11 +53,8 @@ struct Prob {
     int64_t o_spec;      // T [3][M/2+1][M/2+1]   delta^2/M^2 * DFT of K_h, [ch][kx][ky]
     int64_t o_tw;        // cx<T> [M]             e^{-2 pi i k / M}
     int64_t o_samp;      // vec4<T> [T]           (fx, fy, vx, vy) in cell order
-    int64_t o_perm;      // int32 [T]             cell order -> time index
-    int64_t o_bcell;     // int32 [T]             base cell i0 | j0 << 16, cell order
+    int64_t o_sidx;      // int2 [T]              (base cell i0 | j0 << 16, time index), cell order
     int64_t o_binstart;  // int32 [nb*nb + 1]     first sample of every base cell
-    int64_t o_items;     // int32 [4T]            (sample | corner << 30), grouped by cell
-    int64_t o_cellstart; // int32 [N*N + 1]       first item of every cell
     int64_t o_err;       // int32 [4]             build error flags
     int64_t o_scratch;   // build-time scratch
     // work memory

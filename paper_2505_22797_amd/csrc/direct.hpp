@@ -43,19 +43,26 @@ __device__ __forceinline__ void load_tile(T* tile, const T* __restrict__ in, int
     }
 }
 
-// EPI 0: out = conv;  1: out = c_in - tau * conv  (COUT == 1 only)
+// EPI 0: out = conv;  1: out = c_in - tau * conv;  2: as 1 into the problem's
+// work buffer u (COUT == 1 only for 1 and 2)
 template <typename T, int CIN, int COUT, int S, int EPI>
 __global__ void __launch_bounds__(64 * S) k_conv_direct(const Prob* __restrict__ P, const T* in, T* out,
-                                                        const T* c_in, double tau, const char* __restrict__ plan,
-                                                        int in_is_caller, int out_is_caller) {
+                                                        const T* c_in, const double* __restrict__ taus,
+                                                        const char* __restrict__ plan, int in_is_caller,
+                                                        int out_is_caller) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.z];
+    if (p.mode != 0 || p.slices != S) return;
+    const T tau = EPI ? T(taus[blockIdx.z]) : T(0);
     const int N = p.n, R = p.radius, tw = p.taps_w;
     const int tiles = (N + kTile - 1) / kTile;
     const int ty0 = blockIdx.y * kTile, tx0 = blockIdx.x * kTile;
     if (blockIdx.x >= tiles || blockIdx.y >= tiles) return;
-    if (in_is_caller) in += p.o_c;
-    if (out_is_caller) out += p.o_c;
+    // caller buffers are offset by the problem's element offset, work buffers
+    // (passed as the work base) by the problem's field offset
+    in = in_is_caller ? in + p.o_c : reinterpret_cast<const T*>(reinterpret_cast<const char*>(in) + p.w_g);
+    if (EPI == 2) out = reinterpret_cast<T*>(reinterpret_cast<char*>(out) + p.w_u);
+    else out = out_is_caller ? out + p.o_c : reinterpret_cast<T*>(reinterpret_cast<char*>(out) + p.w_g);
     if (c_in) c_in += p.o_c;
     const int row_len = direct_row_len(R);
     const int rows = kTile + 2 * R;
@@ -126,7 +133,7 @@ __global__ void __launch_bounds__(64 * S) k_conv_direct(const Prob* __restrict__
                 if (gy < N && gx < N) {
                     const int64_t off = int64_t(o) * N * N + int64_t(gy) * N + gx;
                     if (EPI == 0) out[off] = s;
-                    else out[off] = c_in[off] - T(tau) * s;
+                    else out[off] = c_in[off] - tau * s;
                 }
             }
         }
@@ -136,11 +143,12 @@ __global__ void __launch_bounds__(64 * S) k_conv_direct(const Prob* __restrict__
 // Bilinear gather + contraction for base-cell row b from a field in global
 // memory ([3][N][N]): rows b and b+1 are staged in LDS first.
 template <typename T, bool RESID>
-__global__ void __launch_bounds__(256) k_gather_rows(const Prob* __restrict__ P, const T* __restrict__ G,
-                                                     T* __restrict__ s, const char* __restrict__ plan,
-                                                     char* __restrict__ work) {
+__global__ void __launch_bounds__(256) k_gather_rows(const Prob* __restrict__ P, T* __restrict__ s,
+                                                     const char* __restrict__ plan, char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
+    if (p.mode != 0) return;
+    const T* G = at<T>(work, p.w_g);
     const int N = p.n, nb = p.nb, b = blockIdx.x;
     if (b >= nb) return;
     const int* binstart = at<int>(plan, p.o_binstart);
@@ -153,43 +161,40 @@ __global__ void __launch_bounds__(256) k_gather_rows(const Prob* __restrict__ P,
         g0[i] = G[int64_t(ch) * N * N + int64_t(b + half) * N + x];
     }
     __syncthreads();
-    gather_band<T, RESID>(g0, g1, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int>(plan, p.o_bcell),
-                          at<int>(plan, p.o_perm), at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res),
-                          s + p.o_s, threadIdx.x, blockDim.x);
+    gather_band<T, RESID>(g0, g1, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
+                          at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res), s + p.o_s, threadIdx.x,
+                          blockDim.x);
 }
 
-// Deterministic transpose sampling for a pair of rows into a field in global
+// Deterministic transpose sampling for one grid row into a field in global
 // memory ([3][N][N]).
 template <typename T, bool SORTED>
-__global__ void __launch_bounds__(192) k_scatter_rows(const Prob* __restrict__ P, const T* __restrict__ s,
-                                                      T* __restrict__ G, const char* __restrict__ plan,
-                                                      char* __restrict__ work) {
+__global__ void __launch_bounds__(256) k_scatter_rows(const Prob* __restrict__ P, const T* __restrict__ s,
+                                                      const char* __restrict__ plan, char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
-    const int N = p.n, q = blockIdx.x;
-    const int r0 = 2 * q;
-    if (r0 >= N) return;
-    const int rows = (r0 + 1 < N) ? 2 : 1;
-    auto& sc = *reinterpret_cast<ScatterSmem<T>*>(smem);
-    T* g = reinterpret_cast<T*>(smem + ((sizeof(ScatterSmem<T>) + 15) / 16) * 16);
-    scatter_band<T, SORTED>(g, sc, N, r0, rows, at<int>(plan, p.o_cellstart), at<int>(plan, p.o_items),
-                            at<vec4<T>>(plan, p.o_samp), at<int>(plan, p.o_perm), at<vec2<T>>(work, p.w_res),
-                            s + p.o_s, threadIdx.x);
-    const int nc = rows * N;
-    for (int i = threadIdx.x; i < 3 * nc; i += blockDim.x) {
-        const int ch = i / nc, lc = i % nc;
-        G[int64_t(ch) * N * N + int64_t(r0) * N + lc] = g[i];
+    if (p.mode != 0) return;
+    T* G = at<T>(work, p.w_g);
+    const int N = p.n, j = blockIdx.x;
+    if (j >= N) return;
+    auto& sc = *reinterpret_cast<ScatterSmem<T, 256, 1024>*>(smem);
+    T* g = reinterpret_cast<T*>(smem + ((sizeof(ScatterSmem<T, 256, 1024>) + 15) / 16) * 16);
+    scatter_row<T, SORTED, 256, 1024>(g, sc, N, j, at<int>(plan, p.o_binstart), at<vec4<T>>(plan, p.o_samp),
+                                      at<int2>(plan, p.o_sidx), at<vec2<T>>(work, p.w_res), s + p.o_s, threadIdx.x);
+    for (int i = threadIdx.x; i < 3 * N; i += blockDim.x) {
+        const int ch = i / N, x = i % N;
+        G[int64_t(ch) * N * N + int64_t(j) * N + x] = g[i];
     }
 }
 
-// ysort[p] = s[perm[p]]: the measured signal in cell order.
+// ysort[p] = s[k(p)]: the measured signal in cell order.
 template <typename T>
 __global__ void k_permute_signal(const Prob* __restrict__ P, const T* __restrict__ s, const char* __restrict__ plan,
                                  char* __restrict__ work) {
     const Prob& p = P[blockIdx.y];
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= p.t) return;
-    const int k = at<int>(plan, p.o_perm)[i];
+    const int k = at<int2>(plan, p.o_sidx)[i].y;
     const T* sp = s + p.o_s;
     vec2<T> y;
     y.x = sp[2 * k];
@@ -203,7 +208,7 @@ constexpr int kDnTile = 32;
 constexpr int kDnMaxR = 8;
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_denoise(const Prob* __restrict__ P, const T* __restrict__ u,
+__global__ void __launch_bounds__(256) k_denoise(const Prob* __restrict__ P, const char* __restrict__ work,
                                                  T* __restrict__ c, const double* __restrict__ wts, int rad) {
     __shared__ T a[(kDnTile + 2 * kDnMaxR) * (kDnTile + 2 * kDnMaxR)];
     __shared__ T b[(kDnTile + 2 * kDnMaxR) * kDnTile];
@@ -211,7 +216,7 @@ __global__ void __launch_bounds__(256) k_denoise(const Prob* __restrict__ P, con
     const int N = p.n;
     const int y0 = blockIdx.y * kDnTile, x0 = blockIdx.x * kDnTile;
     if (y0 >= N || x0 >= N) return;
-    const T* up = u + p.o_c;
+    const T* up = at<T>(work, p.w_u);
     T* cp = c + p.o_c;
     const int L = kDnTile + 2 * rad;
     for (int i = threadIdx.x; i < L * L; i += blockDim.x) {

@@ -13,8 +13,8 @@
 //              the three channels (two real rows per complex FFT), then the
 //              bilinear gather and velocity contraction of the row's samples.
 // Transpose (s -> c), three launches:
-//   adj_scatter_rows : per pair of rows: deterministic transpose sampling into
-//              LDS, then one complex row FFT per channel -> T1[ch][kx][row]
+//   adj_scatter_row : per grid row: deterministic transpose sampling into LDS,
+//              then the row FFTs of the three channels -> T1[ch][kx][row]
 //   adj_cols : per column: three forward column FFTs, multiply-accumulate the
 //              channel spectra, one inverse column FFT cropped to N rows
 //   adj_rows : per pair of rows: inverse row FFT -> c, with an optional fused
@@ -39,11 +39,13 @@ template <typename T, int M> struct GatherSmem {   // fwd_rows_gather: three wav
     cx<T> buf[6][M];
     T g[6 * M];
 };
-template <typename T, int M> struct ScatterRowSmem {   // adj_scatter_rows: three waves
+template <typename T, int M> struct ScatterRowSmem {   // adj_scatter_row: four waves
     cx<T> tw[M];
-    cx<T> buf[6][M];
-    T g[6 * M];
-    ScatterSmem<T> sc;
+    T g[3 * M];
+    union {                     // the sampling transpose and the row FFTs run one after the other
+        ScatterSmem<T, 256, M> sc;
+        cx<T> buf[4][M];
+    };
 };
 
 template <typename T, int M>
@@ -168,45 +170,53 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ s, const cha
         g1[wave * N + i] = Gz[i].y;
     }
     __syncthreads();
-    gather_band<T, RESID>(g0, g1, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int>(plan, p.o_bcell),
-                          at<int>(plan, p.o_perm), at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res),
-                          s, tid, 3 * kWave);
+    gather_band<T, RESID>(g0, g1, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
+                          at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res), s, tid, 3 * kWave);
 }
 
 // ----------------------------------------------------------------- adjoint ---
+// One grid row j per work-group of four waves: the deterministic transpose
+// sampling of the row's cells into LDS, then the row FFTs of its three
+// channels: wave 0 transforms xx + i xy (split into the two half spectra),
+// wave 1 transforms yy alone.
 template <typename T, int M, bool SORTED>
-__device__ void adj_scatter_rows_body(const Prob& p, const T* __restrict__ s, const char* __restrict__ plan,
-                                      char* __restrict__ work, char* smem) {
+__device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, const char* __restrict__ plan,
+                                     char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<ScatterRowSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
-    const int N = p.n, q = blockIdx.x;
-    const int r0 = 2 * q, r1 = 2 * q + 1;
-    if (r0 >= N) return;
-    const int rows = (r1 < N) ? 2 : 1;
+    const int N = p.n, j = blockIdx.x;
+    if (j >= N) return;
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    load_twiddles<T, M>(sm.tw, plan, p, tid, 3 * kWave);
-    scatter_band<T, SORTED>(sm.g, sm.sc, N, r0, rows, at<int>(plan, p.o_cellstart), at<int>(plan, p.o_items),
-                            at<vec4<T>>(plan, p.o_samp), at<int>(plan, p.o_perm), at<vec2<T>>(work, p.w_res),
-                            s, tid);
-    const int nc = rows * N;
-    const T* gch = sm.g + wave * nc;
-    cx<T>* a = sm.buf[2 * wave];
-    for (int i = lane; i < M; i += kWave) {
-        cx<T> z{T(0), T(0)};
-        if (i < N) {
-            z.x = gch[i];
-            if (rows == 2) z.y = gch[N + i];
+    load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
+    scatter_row<T, SORTED, 256, M>(sm.g, sm.sc, N, j, at<int>(plan, p.o_binstart), at<vec4<T>>(plan, p.o_samp),
+                                   at<int2>(plan, p.o_sidx), at<vec2<T>>(work, p.w_res), s, tid);
+    const bool active = wave < 2;
+    cx<T>* a = sm.buf[2 * (wave & 1)];
+    if (active) {
+        const T* re = sm.g + (wave == 0 ? 0 : 2 * N);
+        const T* im = sm.g + N;
+        for (int i = lane; i < M; i += kWave) {
+            cx<T> z{T(0), T(0)};
+            if (i < N) {
+                z.x = re[i];
+                if (wave == 0) z.y = im[i];
+            }
+            a[i] = z;
         }
-        a[i] = z;
     }
     __syncthreads();
-    const cx<T>* Z = fft_line<T, false, M>(a, sm.buf[2 * wave + 1], sm.tw, lane, true);
-    cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(wave) * H * N;
+    const cx<T>* Z = fft_line<T, false, M>(a, sm.buf[2 * (wave & 1) + 1], sm.tw, lane, active);
+    if (!active) return;
+    cx<T>* t1 = at<cx<T>>(work, p.w_t1);
     for (int k = lane; k < H; k += kWave) {
-        cx<T> A, B;
-        split_pair<T, M>(Z, k, A, B);
-        t1[int64_t(k) * N + r0] = A;
-        if (rows == 2) t1[int64_t(k) * N + r1] = B;
+        if (wave == 0) {
+            cx<T> A, B;
+            split_pair<T, M>(Z, k, A, B);
+            t1[int64_t(k) * N + j] = A;
+            t1[(int64_t(H) + k) * N + j] = B;
+        } else {
+            t1[(int64_t(2) * H + k) * N + j] = Z[k];
+        }
     }
 }
 
@@ -240,7 +250,7 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
     for (int j = tid; j < N; j += 3 * kWave) t2[int64_t(j) * H + kx] = Cc[j];
 }
 
-// EPI 0: c_out = A^T s;  1: c_out = c_in - tau * A^T r (c_in may alias c_out)
+// EPI 0: c_out = A^T s;  1, 2: c_out = c_in - tau * A^T r (c_in may alias c_out)
 template <typename T, int M, int EPI>
 __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau,
                               const char* __restrict__ plan, char* __restrict__ work, char* smem) {
@@ -286,6 +296,7 @@ __global__ void __launch_bounds__(64) k_fwd_rows(const Prob* __restrict__ P, con
                                                  const char* __restrict__ plan, char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
+    if (p.mode != 1) return;
     MPIK_DISPATCH_M(p.m, (fwd_rows_body<T, MM>(p, c + p.o_c, plan, work, smem)));
 }
 
@@ -294,6 +305,7 @@ __global__ void __launch_bounds__(192) k_fwd_cols(const Prob* __restrict__ P, co
                                                   char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
+    if (p.mode != 1) return;
     MPIK_DISPATCH_M(p.m, (fwd_cols_body<T, MM>(p, plan, work, smem)));
 }
 
@@ -302,15 +314,17 @@ __global__ void __launch_bounds__(192) k_fwd_rows_gather(const Prob* __restrict_
                                                          const char* __restrict__ plan, char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
+    if (p.mode != 1) return;
     MPIK_DISPATCH_M(p.m, (fwd_rows_gather_body<T, MM, RESID>(p, s + p.o_s, plan, work, smem)));
 }
 
 template <typename T, bool SORTED>
-__global__ void __launch_bounds__(192) k_adj_scatter_rows(const Prob* __restrict__ P, const T* __restrict__ s,
-                                                          const char* __restrict__ plan, char* __restrict__ work) {
+__global__ void __launch_bounds__(256) k_adj_scatter_row(const Prob* __restrict__ P, const T* __restrict__ s,
+                                                         const char* __restrict__ plan, char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
-    MPIK_DISPATCH_M(p.m, (adj_scatter_rows_body<T, MM, SORTED>(p, s + p.o_s, plan, work, smem)));
+    if (p.mode != 1) return;
+    MPIK_DISPATCH_M(p.m, (adj_scatter_row_body<T, MM, SORTED>(p, s + p.o_s, plan, work, smem)));
 }
 
 template <typename T>
@@ -318,15 +332,21 @@ __global__ void __launch_bounds__(192) k_adj_cols(const Prob* __restrict__ P, co
                                                   char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
+    if (p.mode != 1) return;
     MPIK_DISPATCH_M(p.m, (adj_cols_body<T, MM>(p, plan, work, smem)));
 }
 
 template <typename T, int EPI>
-__global__ void __launch_bounds__(64) k_adj_rows(const Prob* __restrict__ P, T* c_out, const T* c_in, double tau,
-                                                 const char* __restrict__ plan, char* __restrict__ work) {
+__global__ void __launch_bounds__(64) k_adj_rows(const Prob* __restrict__ P, T* c_out, const T* c_in,
+                                                 const double* __restrict__ taus, const char* __restrict__ plan,
+                                                 char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
-    MPIK_DISPATCH_M(p.m, (adj_rows_body<T, MM, EPI>(p, c_out + p.o_c, c_in + p.o_c, T(tau), plan, work, smem)));
+    if (p.mode != 1) return;
+    const T tau = EPI ? T(taus[blockIdx.y]) : T(0);
+    // EPI 2 writes the step into the problem's work buffer u (before the denoiser)
+    T* out = EPI == 2 ? at<T>(work, p.w_u) : c_out + p.o_c;
+    MPIK_DISPATCH_M(p.m, (adj_rows_body<T, MM, EPI>(p, out, c_in + p.o_c, tau, plan, work, smem)));
 }
 
 }  // namespace mpik

@@ -1,14 +1,25 @@
 // Host side of the C ABI declared in include/mpik.h: descriptor validation,
-// plan/work layout, the plan build, and the launch sequences of the forward
-// operator, its transpose and the iteration (optionally replayed as a HIP
-// graph).  The library never allocates device memory.
+// plan/work layout, the plan build, the convolution-path autotuner, and the
+// launch sequences of the forward operator, its transpose and the iteration
+// (optionally replayed as a HIP graph).
+//
+// Everything is batch-first: a plan holds B >= 1 problems whose descriptors
+// sit contiguously at the start of the plan memory; every stage is one launch
+// over all problems (grid.y or grid.z indexes the problem, work-groups beyond
+// a problem's own extent exit at once).  A single-problem plan is a batch of
+// one.  The library never allocates device memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
+#include <vector>
 
 #include "../../include/mpik.h"
 #include "build.hpp"
@@ -20,125 +31,23 @@ using namespace mpik;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kDirectSlices = 8;
 constexpr int64_t kMaxSamples = int64_t(1) << 26;
+constexpr int kMaxBatch = 4096;
+constexpr int kSliceChoices[3] = {4, 8, 16};
+constexpr size_t kSmemLimit = 160 * 1024;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-struct Layout {
-    Prob p;
-    size_t plan_bytes = 0, work_bytes = 0;
-    // build scratch (bytes from plan base)
-    int64_t o_series = 0, o_tab64 = 0, o_cs = 0, o_U = 0, o_cell = 0, o_frac = 0, o_bincount = 0,
-            o_cellcount = 0, o_cursor = 0;
-    int64_t w_wts = 0;
-    int elem = 4;
-};
-
 int pow2_at_least(int x) {
     int m = 1;
     while (m < x) m *= 2;
     return m;
 }
+int blocks(int64_t n, int b) { return int((n + b - 1) / b); }
 
-size_t direct_smem(int R, int cin, int cout, int elem) {
+size_t direct_smem(int R, int cin, int cout, int slices, int elem) {
     const size_t tile = size_t(cin) * (kTile + 2 * R) * direct_row_len(R);
-    const size_t red = size_t(kDirectSlices) * kWave * cout * kStrip;
+    const size_t red = size_t(slices) * kWave * cout * kStrip;
     return std::max(tile, red) * elem;
-}
-
-// Picks the convolution path and fills the layout.  Returns MPI_OK or an error.
-int make_layout(const mpi_problem* d, Layout& L) {
-    if (!d) return MPI_ERR_ARG;
-    if (d->dtype != MPI_F32 && d->dtype != MPI_F64) return MPI_ERR_DTYPE;
-    if (d->n < 2 || d->n > 1024) return MPI_ERR_ARG;
-    if (!(d->h > 0.0) || !std::isfinite(d->h)) return MPI_ERR_ARG;
-    if (d->radius < 0) return MPI_ERR_ARG;
-    if (d->n_samples < 1 || d->n_samples >= kMaxSamples) return MPI_ERR_ARG;
-    if (d->conv_mode < MPI_CONV_AUTO || d->conv_mode > MPI_CONV_FFT) return MPI_ERR_ARG;
-    if (d->interp != MPI_INTERP_BILINEAR || d->channels != MPI_CH_XY) return MPI_ERR_UNSUPPORTED;
-    const int elem = d->dtype == MPI_F64 ? 8 : 4;
-    L.elem = elem;
-    const int N = d->n, R = std::min(d->radius, N - 1), nb = N - 1;
-    const int64_t T = d->n_samples;
-    const int maxM = elem == 8 ? 512 : 1024;
-    const int M = std::max(64, pow2_at_least(N + R));
-    const bool fft_ok = M <= maxM && N <= 512;
-    const bool direct_ok = direct_smem(R, 3, 1, elem) <= 160 * 1024 && direct_smem(R, 1, 3, elem) <= 160 * 1024;
-    int mode;
-    if (d->conv_mode == MPI_CONV_FFT) {
-        if (!fft_ok) return MPI_ERR_UNSUPPORTED;
-        mode = 1;
-    } else if (d->conv_mode == MPI_CONV_DIRECT) {
-        if (!direct_ok) return MPI_ERR_UNSUPPORTED;
-        mode = 0;
-    } else {
-        // direct while the window is small, FFT otherwise
-        mode = (R <= 7 && direct_ok) ? 0 : (fft_ok ? 1 : (direct_ok ? 0 : -1));
-        if (mode < 0) return MPI_ERR_UNSUPPORTED;
-    }
-    Prob& p = L.p;
-    std::memset(&p, 0, sizeof(p));
-    p.n = N;
-    p.nb = nb;
-    p.radius = R;
-    p.mode = mode;
-    p.m = mode ? M : 0;
-    p.log2m = mode ? __builtin_ctz(M) : 0;
-    p.taps_w = (2 * R + 1 + 3) / 4 * 4;
-    p.t = T;
-    p.h = d->h;
-    const int W = 2 * R + 1, H = M / 2 + 1;
-    size_t off = align_up(sizeof(Prob));
-    auto take = [&off](size_t bytes) { int64_t o = int64_t(off); off = align_up(off + std::max<size_t>(bytes, 1)); return o; };
-    if (mode == 0) p.o_taps = take(size_t(3) * W * p.taps_w * elem);
-    if (mode == 1) {
-        p.o_spec = take(size_t(3) * H * H * elem);
-        p.o_tw = take(size_t(M) * 2 * elem);
-    }
-    p.o_samp = take(size_t(T) * 4 * elem);
-    p.o_perm = take(size_t(T) * 4);
-    p.o_bcell = take(size_t(T) * 4);
-    p.o_binstart = take((size_t(nb) * nb + 1) * 4);
-    p.o_items = take(size_t(4 * T) * 4);
-    p.o_cellstart = take((size_t(N) * N + 1) * 4);
-    p.o_err = take(16);
-    p.o_scratch = int64_t(off);
-    L.o_series = take(kSeriesTerms * 8);
-    L.o_tab64 = take(size_t(3) * W * W * 8);
-    if (mode == 1) {
-        L.o_cs = take(size_t(2) * M * 8);
-        L.o_U = take(size_t(3) * (R + 1) * H * 8);
-    }
-    L.o_cell = take(size_t(T) * 4);
-    L.o_frac = take(size_t(T) * 16);
-    L.o_bincount = take(size_t(nb) * nb * 4);
-    L.o_cellcount = take(size_t(N) * N * 4);
-    L.o_cursor = take(size_t(nb) * nb * 4);
-    L.plan_bytes = off;
-    // work memory
-    off = 0;
-    p.w_g = take(size_t(3) * N * N * elem);
-    if (mode == 1) {
-        p.w_t1 = take(size_t(3) * H * N * 2 * elem);
-        p.w_t2 = take(size_t(3) * N * H * 2 * elem);
-    }
-    p.w_ysort = take(size_t(T) * 2 * elem);
-    p.w_res = take(size_t(T) * 2 * elem);
-    p.w_u = take(size_t(N) * N * elem);
-    p.w_grad = take(size_t(N) * N * elem);
-    L.w_wts = take(32 * 8);
-    L.work_bytes = off;
-    return MPI_OK;
-}
-
-bool misaligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) != 0; }
-
-template <typename K>
-hipError_t allow_smem(K kernel, size_t bytes) {
-    if (bytes <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               int(bytes));
 }
 
 template <typename T, template <typename, int> class S>
@@ -151,20 +60,209 @@ size_t smem_for(int M) {
         default: return sizeof(S<T, 1024>);
     }
 }
+// which: 0 row, 1 column, 2 gather, 3 scatter-row
+size_t smem_for_dt(int elem, int M, int which) {
+    if (elem == 8) {
+        switch (which) {
+            case 0: return smem_for<double, RowSmem>(M);
+            case 1: return smem_for<double, ColSmem>(M);
+            case 2: return smem_for<double, GatherSmem>(M);
+            default: return smem_for<double, ScatterRowSmem>(M);
+        }
+    }
+    switch (which) {
+        case 0: return smem_for<float, RowSmem>(M);
+        case 1: return smem_for<float, ColSmem>(M);
+        case 2: return smem_for<float, GatherSmem>(M);
+        default: return smem_for<float, ScatterRowSmem>(M);
+    }
+}
+size_t scatter_rows_smem(int N, int elem) {
+    const size_t sc = elem == 8 ? sizeof(ScatterSmem<double, 256, 1024>) : sizeof(ScatterSmem<float, 256, 1024>);
+    return (sc + 15) / 16 * 16 + size_t(3) * N * elem;
+}
+
+struct Shape {
+    int n, R, M, elem;
+    int64_t T;
+    bool fft_ok, direct_ok;
+};
+
+int validate(const mpi_problem* d, Shape& sh) {
+    if (!d) return MPI_ERR_ARG;
+    if (d->dtype != MPI_F32 && d->dtype != MPI_F64) return MPI_ERR_DTYPE;
+    if (d->n < 2 || d->n > 1024) return MPI_ERR_ARG;
+    if (!(d->h > 0.0) || !std::isfinite(d->h)) return MPI_ERR_ARG;
+    if (d->radius < 0) return MPI_ERR_ARG;
+    if (d->n_samples < 1 || d->n_samples >= kMaxSamples) return MPI_ERR_ARG;
+    if (d->conv_mode < MPI_CONV_AUTO || d->conv_mode > MPI_CONV_FFT) return MPI_ERR_ARG;
+    if (d->interp != MPI_INTERP_BILINEAR || d->channels != MPI_CH_XY) return MPI_ERR_UNSUPPORTED;
+    sh.elem = d->dtype == MPI_F64 ? 8 : 4;
+    sh.n = d->n;
+    sh.R = std::min(d->radius, d->n - 1);
+    sh.T = d->n_samples;
+    sh.M = std::max(64, pow2_at_least(sh.n + sh.R));
+    const int maxM = sh.elem == 8 ? 512 : 1024;
+    sh.fft_ok = sh.M <= maxM && sh.n <= 512 && smem_for_dt(sh.elem, sh.M, 3) <= kSmemLimit &&
+                smem_for_dt(sh.elem, sh.M, 1) <= kSmemLimit && smem_for_dt(sh.elem, sh.M, 2) <= kSmemLimit;
+    sh.direct_ok = direct_smem(sh.R, 3, 1, 16, sh.elem) <= kSmemLimit &&
+                   direct_smem(sh.R, 1, 3, 16, sh.elem) <= kSmemLimit && scatter_rows_smem(sh.n, sh.elem) <= kSmemLimit;
+    if (d->conv_mode == MPI_CONV_FFT && !sh.fft_ok) return MPI_ERR_UNSUPPORTED;
+    if (d->conv_mode == MPI_CONV_DIRECT && !sh.direct_ok) return MPI_ERR_UNSUPPORTED;
+    if (!sh.fft_ok && !sh.direct_ok) return MPI_ERR_UNSUPPORTED;
+    return MPI_OK;
+}
+
+// Scratch used by the build of one problem; reused problem after problem.
+struct Scratch {
+    int64_t series = 0, tab64 = 0, cs = 0, U = 0, cell = 0, frac = 0, bincount = 0, cursor = 0;
+    size_t end = 0;
+};
+
+size_t take(size_t& off, size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return o;
+}
+
+// Lays out one problem's plan buffers from `poff` and its work buffers from
+// `woff` (both advanced).  `both`: room for either convolution path (tuning).
+void layout_problem(const Shape& sh, int mode, bool both, size_t& poff, size_t& woff, Prob& p) {
+    const int N = sh.n, R = sh.R, nb = N - 1, M = sh.M, H = M / 2 + 1, W = 2 * R + 1, e = sh.elem;
+    const int64_t T = sh.T;
+    std::memset(&p, 0, sizeof(p));
+    p.n = N;
+    p.nb = nb;
+    p.radius = R;
+    p.mode = mode;
+    p.m = M;
+    p.log2m = __builtin_ctz(M);
+    p.taps_w = (W + 3) / 4 * 4;
+    p.slices = 8;
+    p.t = T;
+    const bool dir = both ? sh.direct_ok : mode == 0;
+    const bool fft = both ? sh.fft_ok : mode == 1;
+    if (dir) p.o_taps = take(poff, size_t(3) * W * p.taps_w * e);
+    if (fft) {
+        p.o_spec = take(poff, size_t(3) * H * H * e);
+        p.o_tw = take(poff, size_t(M) * 2 * e);
+    }
+    p.o_samp = take(poff, size_t(T) * 4 * e);
+    p.o_sidx = take(poff, size_t(T) * 8);
+    p.o_binstart = take(poff, (size_t(nb) * nb + 1) * 4);
+    p.o_err = take(poff, 16);
+    p.w_g = take(woff, size_t(3) * N * N * e);
+    if (fft) {
+        p.w_t1 = take(woff, size_t(3) * H * N * 2 * e);
+        p.w_t2 = take(woff, size_t(3) * N * H * 2 * e);
+    }
+    p.w_ysort = take(woff, size_t(T) * 2 * e);
+    p.w_res = take(woff, size_t(T) * 2 * e);
+    p.w_u = take(woff, size_t(N) * N * e);
+    p.w_grad = take(woff, size_t(N) * N * e);
+}
+
+Scratch scratch_layout(const Shape& sh, size_t base) {
+    Scratch s;
+    size_t off = base;
+    const int N = sh.n, R = sh.R, nb = N - 1, W = 2 * R + 1, H = sh.M / 2 + 1;
+    s.series = take(off, kSeriesTerms * 8);
+    s.tab64 = take(off, size_t(3) * W * W * 8);
+    s.cs = take(off, size_t(2) * sh.M * 8);
+    s.U = take(off, size_t(3) * (R + 1) * H * 8);
+    s.cell = take(off, size_t(sh.T) * 4);
+    s.frac = take(off, size_t(sh.T) * 16);
+    s.bincount = take(off, size_t(nb) * nb * 4);
+    s.cursor = take(off, size_t(nb) * nb * 4);
+    s.end = off;
+    return s;
+}
+
+struct BatchLayout {
+    std::vector<Shape> shapes;
+    std::vector<Prob> probs;
+    std::vector<int> requested;   // MPI_CONV_* per problem
+    size_t desc_bytes = 0, plan_bytes = 0, work_bytes = 0, scratch_base = 0;
+    size_t w_taus = 0, w_wts = 0;
+    int64_t c_elems = 0, s_elems = 0;
+    int elem = 4;
+};
+
+// Path before tuning: direct for small windows, FFT otherwise.
+int default_mode(const Shape& sh, int requested) {
+    if (requested == MPI_CONV_DIRECT) return 0;
+    if (requested == MPI_CONV_FFT) return 1;
+    if (sh.R <= 7 && sh.direct_ok) return 0;
+    return sh.fft_ok ? 1 : 0;
+}
+
+int make_batch_layout(const mpi_problem* probs, int count, BatchLayout& B) {
+    if (!probs || count < 1 || count > kMaxBatch) return MPI_ERR_ARG;
+    B.shapes.resize(count);
+    B.probs.resize(count);
+    B.requested.resize(count);
+    for (int b = 0; b < count; ++b) {
+        const int rc = validate(&probs[b], B.shapes[b]);
+        if (rc != MPI_OK) return rc;
+        if (b > 0 && B.shapes[b].elem != B.shapes[0].elem) return MPI_ERR_DTYPE;
+        B.requested[b] = probs[b].conv_mode;
+    }
+    B.elem = B.shapes[0].elem;
+    B.desc_bytes = align_up(sizeof(Prob) * count);
+    size_t poff = B.desc_bytes, woff = 0;
+    int64_t co = 0, so = 0;
+    for (int b = 0; b < count; ++b) {
+        const Shape& sh = B.shapes[b];
+        const bool both = B.requested[b] == MPI_CONV_AUTO && sh.fft_ok && sh.direct_ok;
+        layout_problem(sh, default_mode(sh, B.requested[b]), both, poff, woff, B.probs[b]);
+        B.probs[b].h = probs[b].h;
+        B.probs[b].o_c = co;
+        B.probs[b].o_s = so;
+        co += int64_t(sh.n) * sh.n;
+        so += 2 * sh.T;
+    }
+    B.c_elems = co;
+    B.s_elems = so;
+    B.scratch_base = poff;
+    size_t scratch_end = poff;
+    for (int b = 0; b < count; ++b) scratch_end = std::max(scratch_end, scratch_layout(B.shapes[b], poff).end);
+    B.plan_bytes = scratch_end;
+    B.w_taus = take(woff, sizeof(double) * count);
+    B.w_wts = take(woff, 32 * sizeof(double));
+    B.work_bytes = woff;
+    return MPI_OK;
+}
+
+bool misaligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) != 0; }
+
+template <typename K>
+hipError_t allow_smem(K kernel, size_t bytes) {
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               int(bytes));
+}
 
 }  // namespace
 
 struct mpi_plan {
-    Layout L;
+    BatchLayout L;
+    int count = 1;
     int dtype = MPI_F32;
     char* plan = nullptr;
     const Prob* dprob = nullptr;
     double wts[32] = {0};
+    // launch extents over the batch
+    int max_n = 0, max_rowpairs = 0, max_h = 0, max_nb = 0, max_tiles = 0, max_dntiles = 0;
+    int64_t max_t = 0;
+    size_t smem_row = 0, smem_col = 0, smem_gather = 0, smem_scatter = 0, smem_dfwd = 0, smem_dadj = 0,
+           smem_dgather = 0, smem_dscatter = 0;
+    bool any_fft = false, any_direct = false;
+    int slice_mask = 0;   // bit i: some direct problem uses kSliceChoices[i]
     // cached iteration graph
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     const void *g_s = nullptr, *g_c = nullptr, *g_work = nullptr;
-    double g_tau = 0, g_sigma = 0;
+    double g_sigma = 0;
     int g_rad = -1;
 };
 
@@ -176,156 +274,216 @@ namespace {
         if (e_ != hipSuccess) return MPI_ERR_HIP;   \
     } while (0)
 
-int blocks(int64_t n, int b) { return int((n + b - 1) / b); }
+// Launch extents and dynamic shared memory over the batch.
+void finalize_extents(mpi_plan* pl) {
+    pl->max_n = pl->max_rowpairs = pl->max_h = pl->max_nb = pl->max_tiles = pl->max_dntiles = 0;
+    pl->max_t = 0;
+    pl->smem_row = pl->smem_col = pl->smem_gather = pl->smem_scatter = 0;
+    pl->smem_dfwd = pl->smem_dadj = pl->smem_dgather = pl->smem_dscatter = 0;
+    pl->any_fft = pl->any_direct = false;
+    pl->slice_mask = 0;
+    const int e = pl->L.elem;
+    for (const Prob& p : pl->L.probs) {
+        pl->max_n = std::max(pl->max_n, p.n);
+        pl->max_rowpairs = std::max(pl->max_rowpairs, (p.n + 1) / 2);
+        pl->max_nb = std::max(pl->max_nb, p.nb);
+        pl->max_t = std::max(pl->max_t, p.t);
+        pl->max_dntiles = std::max(pl->max_dntiles, (p.n + kDnTile - 1) / kDnTile);
+        if (p.mode == 1) {
+            pl->any_fft = true;
+            pl->max_h = std::max(pl->max_h, p.m / 2 + 1);
+            pl->smem_row = std::max(pl->smem_row, smem_for_dt(e, p.m, 0));
+            pl->smem_col = std::max(pl->smem_col, smem_for_dt(e, p.m, 1));
+            pl->smem_gather = std::max(pl->smem_gather, smem_for_dt(e, p.m, 2));
+            pl->smem_scatter = std::max(pl->smem_scatter, smem_for_dt(e, p.m, 3));
+        } else {
+            pl->any_direct = true;
+            pl->max_tiles = std::max(pl->max_tiles, (p.n + kTile - 1) / kTile);
+            pl->smem_dfwd = std::max(pl->smem_dfwd, direct_smem(p.radius, 1, 3, p.slices, e));
+            pl->smem_dadj = std::max(pl->smem_dadj, direct_smem(p.radius, 3, 1, p.slices, e));
+            pl->smem_dgather = std::max(pl->smem_dgather, size_t(6) * p.n * e);
+            pl->smem_dscatter = std::max(pl->smem_dscatter, scatter_rows_smem(p.n, e));
+            for (int i = 0; i < 3; ++i)
+                if (p.slices == kSliceChoices[i]) pl->slice_mask |= 1 << i;
+        }
+    }
+}
 
 template <typename T>
-int build_impl(const mpi_problem* d, Layout& L, char* plan, hipStream_t st) {
-    const Prob& p = L.p;
-    const Prob* P = reinterpret_cast<const Prob*>(plan);
-    const int N = p.n, R = p.radius, W = 2 * R + 1, nb = p.nb;
-    HIP_TRY(hipMemcpyAsync(plan, &p, sizeof(Prob), hipMemcpyHostToDevice, st));
+hipError_t set_smem_limits(const mpi_plan* pl) {
+    hipError_t e = hipSuccess;
+    auto chk = [&e](hipError_t x) { if (x != hipSuccess) e = x; };
+    chk(allow_smem(k_fwd_rows<T>, pl->smem_row));
+    chk(allow_smem(k_fwd_cols<T>, pl->smem_col));
+    chk(allow_smem(k_adj_cols<T>, pl->smem_col));
+    chk(allow_smem(k_fwd_rows_gather<T, false>, pl->smem_gather));
+    chk(allow_smem(k_fwd_rows_gather<T, true>, pl->smem_gather));
+    chk(allow_smem(k_adj_scatter_row<T, false>, pl->smem_scatter));
+    chk(allow_smem(k_adj_scatter_row<T, true>, pl->smem_scatter));
+    chk(allow_smem(k_adj_rows<T, 0>, pl->smem_row));
+    chk(allow_smem(k_adj_rows<T, 1>, pl->smem_row));
+    chk(allow_smem(k_conv_direct<T, 1, 3, 4, 0>, pl->smem_dfwd));
+    chk(allow_smem(k_conv_direct<T, 1, 3, 8, 0>, pl->smem_dfwd));
+    chk(allow_smem(k_conv_direct<T, 1, 3, 16, 0>, pl->smem_dfwd));
+    chk(allow_smem(k_conv_direct<T, 3, 1, 4, 0>, pl->smem_dadj));
+    chk(allow_smem(k_conv_direct<T, 3, 1, 8, 0>, pl->smem_dadj));
+    chk(allow_smem(k_conv_direct<T, 3, 1, 16, 0>, pl->smem_dadj));
+    chk(allow_smem(k_conv_direct<T, 3, 1, 4, 1>, pl->smem_dadj));
+    chk(allow_smem(k_conv_direct<T, 3, 1, 8, 1>, pl->smem_dadj));
+    chk(allow_smem(k_conv_direct<T, 3, 1, 16, 1>, pl->smem_dadj));
+    chk(allow_smem(k_conv_direct<T, 3, 1, 4, 2>, pl->smem_dadj));
+    chk(allow_smem(k_conv_direct<T, 3, 1, 8, 2>, pl->smem_dadj));
+    chk(allow_smem(k_conv_direct<T, 3, 1, 16, 2>, pl->smem_dadj));
+    chk(allow_smem(k_adj_rows<T, 2>, pl->smem_row));
+    chk(allow_smem(k_gather_rows<T, false>, pl->smem_dgather));
+    chk(allow_smem(k_gather_rows<T, true>, pl->smem_dgather));
+    chk(allow_smem(k_scatter_rows<T, false>, pl->smem_dscatter));
+    chk(allow_smem(k_scatter_rows<T, true>, pl->smem_dscatter));
+    return e;
+}
+
+// ---------------------------------------------------------------- build ---
+// Builds problem b (its descriptor already in device memory): kernel table,
+// spectra and/or direct taps, binning.  Enqueued on st; no synchronisation.
+template <typename T>
+int build_problem(const mpi_problem* d, const BatchLayout& B, int b, char* plan, hipStream_t st) {
+    const Prob& p = B.probs[b];
+    const Prob* P = reinterpret_cast<const Prob*>(plan) + b;
+    const Scratch sc = scratch_layout(B.shapes[b], B.scratch_base);
+    const int N = p.n, R = p.radius, W = 2 * R + 1, nb = p.nb, M = p.m, H = M / 2 + 1;
     HIP_TRY(hipMemsetAsync(plan + p.o_err, 0, 16, st));
-    HIP_TRY(hipMemsetAsync(plan + L.o_bincount, 0, size_t(nb) * nb * 4, st));
-    double* series = reinterpret_cast<double*>(plan + L.o_series);
-    double* tab64 = reinterpret_cast<double*>(plan + L.o_tab64);
+    HIP_TRY(hipMemsetAsync(plan + sc.bincount, 0, size_t(nb) * nb * 4, st));
+    double* series = reinterpret_cast<double*>(plan + sc.series);
+    double* tab64 = reinterpret_cast<double*>(plan + sc.tab64);
     k_series<<<1, 1, 0, st>>>(series);
-    T* taps = p.mode == 0 ? reinterpret_cast<T*>(plan + p.o_taps) : nullptr;
+    T* taps = p.o_taps ? reinterpret_cast<T*>(plan + p.o_taps) : nullptr;
     k_table<T><<<blocks(int64_t(W) * W, 256), 256, 0, st>>>(P, plan, series, tab64, taps, 0);
-    if (p.mode == 0 && p.taps_w > W)
+    if (taps && p.taps_w > W)
         k_taps_pad<T><<<blocks(int64_t(3) * W * (p.taps_w - W), 256), 256, 0, st>>>(P, taps);
-    if (p.mode == 1) {
-        const int M = p.m, H = M / 2 + 1;
-        double* cs = reinterpret_cast<double*>(plan + L.o_cs);
-        double* U = reinterpret_cast<double*>(plan + L.o_U);
+    if (p.o_spec) {
+        double* cs = reinterpret_cast<double*>(plan + sc.cs);
+        double* U = reinterpret_cast<double*>(plan + sc.U);
         k_trig<T><<<blocks(M, 256), 256, 0, st>>>(P, cs, reinterpret_cast<cx<T>*>(plan + p.o_tw));
         k_spec_rows<<<blocks(int64_t(3) * (R + 1) * H, 256), 256, 0, st>>>(P, tab64, cs, U);
         k_spec_cols<T><<<blocks(int64_t(3) * H * H, 256), 256, 0, st>>>(P, U, cs, reinterpret_cast<T*>(plan + p.o_spec));
     }
-    int* cell = reinterpret_cast<int*>(plan + L.o_cell);
-    double* frac = reinterpret_cast<double*>(plan + L.o_frac);
-    int* bincount = reinterpret_cast<int*>(plan + L.o_bincount);
-    int* cursor = reinterpret_cast<int*>(plan + L.o_cursor);
+    int* cell = reinterpret_cast<int*>(plan + sc.cell);
+    double* frac = reinterpret_cast<double*>(plan + sc.frac);
+    int* bincount = reinterpret_cast<int*>(plan + sc.bincount);
+    int* cursor = reinterpret_cast<int*>(plan + sc.cursor);
     int* err = reinterpret_cast<int*>(plan + p.o_err);
     k_bin_prep<T><<<blocks(p.t, 256), 256, 0, st>>>(P, static_cast<const T*>(d->r), cell, frac, bincount, err);
     k_scan<<<1, 1024, 0, st>>>(bincount, reinterpret_cast<int*>(plan + p.o_binstart), nb * nb, cursor);
     k_place<T><<<1, 1024, 1024 * sizeof(int), st>>>(P, cell, frac, static_cast<const T*>(d->v), cursor, plan);
-    int* cellcount = reinterpret_cast<int*>(plan + L.o_cellcount);
-    k_cell_count<<<blocks(int64_t(N) * N, 256), 256, 0, st>>>(P, plan, cellcount);
-    k_scan<<<1, 1024, 0, st>>>(cellcount, reinterpret_cast<int*>(plan + p.o_cellstart), N * N, nullptr);
-    k_cell_items<<<blocks(int64_t(N) * N, 256), 256, 0, st>>>(P, plan);
     HIP_TRY(hipGetLastError());
-    // smem opt-in for the kernels this plan launches
-    if (p.mode == 1) {
-        HIP_TRY(allow_smem(k_fwd_cols<T>, smem_for<T, ColSmem>(p.m)));
-        HIP_TRY(allow_smem(k_adj_cols<T>, smem_for<T, ColSmem>(p.m)));
-        HIP_TRY(allow_smem(k_fwd_rows_gather<T, false>, smem_for<T, GatherSmem>(p.m)));
-        HIP_TRY(allow_smem(k_fwd_rows_gather<T, true>, smem_for<T, GatherSmem>(p.m)));
-        HIP_TRY(allow_smem(k_adj_scatter_rows<T, false>, smem_for<T, ScatterRowSmem>(p.m)));
-        HIP_TRY(allow_smem(k_adj_scatter_rows<T, true>, smem_for<T, ScatterRowSmem>(p.m)));
-    } else {
-        HIP_TRY(allow_smem(k_conv_direct<T, 1, 3, kDirectSlices, 0>, direct_smem(R, 1, 3, sizeof(T))));
-        HIP_TRY(allow_smem(k_conv_direct<T, 3, 1, kDirectSlices, 0>, direct_smem(R, 3, 1, sizeof(T))));
-        HIP_TRY(allow_smem(k_conv_direct<T, 3, 1, kDirectSlices, 1>, direct_smem(R, 3, 1, sizeof(T))));
-    }
-    int herr[4] = {0, 0, 0, 0};
-    HIP_TRY(hipMemcpyAsync(herr, err, 16, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (herr[0]) return MPI_ERR_DOMAIN;
     return MPI_OK;
 }
 
-size_t scatter_rows_smem(int N, int elem) {
-    return ((sizeof(ScatterSmem<double>) + 15) / 16) * 16 + size_t(6) * N * elem;
+// ---------------------------------------------------------------- apply ---
+// Stages 0..2 are the FFT path, 3..4 the direct path; every launch spans the
+// whole batch and problems of the other path exit at once.
+constexpr int kFwdStages = 5;
+constexpr int kAdjStages = 5;
+
+template <typename T, int S, int EPI>
+void launch_direct_conv(const mpi_plan* pl, bool fwd, const T* in, T* out, const T* c_in, const double* taus,
+                        hipStream_t st) {
+    // EPI 2 addresses the work buffer u: `out` is then the work base
+    constexpr int bit = S == 4 ? 0 : (S == 8 ? 1 : 2);
+    if (!(pl->slice_mask & (1 << bit))) return;
+    const dim3 grid(pl->max_tiles, pl->max_tiles, pl->count);
+    if (fwd)
+        k_conv_direct<T, 1, 3, S, 0><<<grid, 64 * S, pl->smem_dfwd, st>>>(pl->dprob, in, out, nullptr, nullptr,
+                                                                          pl->plan, 1, 0);
+    else
+        k_conv_direct<T, 3, 1, S, EPI><<<grid, 64 * S, pl->smem_dadj, st>>>(pl->dprob, in, out, c_in, taus,
+                                                                            pl->plan, 0, 1);
 }
 
-// Stages of the forward operator: FFT path {rows, columns, rows + gather},
-// direct path {convolution, gather}.  RESID: write A c - y in cell order to the
-// work buffer instead of A c in time order to s.
+// Forward: FFT {rows, columns, rows + gather}, direct {convolution, gather}.
+// RESID: write A c - y in cell order to the work buffer instead of A c in
+// time order to s.
 template <typename T, bool RESID>
 void fwd_stage(const mpi_plan* pl, int k, const T* c, T* s, char* work, hipStream_t st) {
-    const Prob& p = pl->L.p;
     const char* plan = pl->plan;
     const Prob* P = pl->dprob;
-    const int N = p.n;
-    if (p.mode == 1) {
-        const int M = p.m, H = M / 2 + 1;
-        if (k == 0) k_fwd_rows<T><<<dim3((N + 1) / 2, 1), 64, smem_for<T, RowSmem>(M), st>>>(P, c, plan, work);
-        if (k == 1) k_fwd_cols<T><<<dim3(H, 1), 192, smem_for<T, ColSmem>(M), st>>>(P, plan, work);
-        if (k == 2)
-            k_fwd_rows_gather<T, RESID><<<dim3(p.nb, 1), 192, smem_for<T, GatherSmem>(M), st>>>(P, s, plan, work);
-    } else {
-        const int tiles = (N + kTile - 1) / kTile;
-        T* G = reinterpret_cast<T*>(work + p.w_g);
-        if (k == 0)
-            k_conv_direct<T, 1, 3, kDirectSlices, 0><<<dim3(tiles, tiles, 1), 64 * kDirectSlices,
-                                                        direct_smem(p.radius, 1, 3, sizeof(T)), st>>>(
-                P, c, G, nullptr, 0.0, plan, 1, 0);
-        if (k == 1)
-            k_gather_rows<T, RESID><<<dim3(p.nb, 1), 256, size_t(6) * N * sizeof(T), st>>>(P, G, s, plan, work);
+    const int B = pl->count;
+    if (k <= 2 && !pl->any_fft) return;
+    if (k >= 3 && !pl->any_direct) return;
+    switch (k) {
+        case 0: k_fwd_rows<T><<<dim3(pl->max_rowpairs, B), 64, pl->smem_row, st>>>(P, c, plan, work); break;
+        case 1: k_fwd_cols<T><<<dim3(pl->max_h, B), 192, pl->smem_col, st>>>(P, plan, work); break;
+        case 2: k_fwd_rows_gather<T, RESID><<<dim3(pl->max_nb, B), 192, pl->smem_gather, st>>>(P, s, plan, work); break;
+        case 3:
+            launch_direct_conv<T, 4, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st);
+            launch_direct_conv<T, 8, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st);
+            launch_direct_conv<T, 16, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st);
+            break;
+        case 4: k_gather_rows<T, RESID><<<dim3(pl->max_nb, B), 256, pl->smem_dgather, st>>>(P, s, plan, work); break;
+        default: break;
     }
 }
 
-// Stages of the transpose: FFT path {scatter + rows, columns, rows}, direct
-// path {scatter, convolution}.  SORTED: the signal is the residual already in
-// cell order in the work buffer.  EPI 0: c_out = A^T s; EPI 1: c_out = c_in - tau A^T r.
+// Transpose: FFT {scatter + rows, columns, rows}, direct {scatter,
+// convolution}.  SORTED: the residual is already in cell order in the work
+// buffer.  EPI 0: c_out = A^T s; EPI 1: c_out = c_in - tau_b A^T r.
 template <typename T, bool SORTED, int EPI>
-void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, double tau, char* work,
-               hipStream_t st) {
-    const Prob& p = pl->L.p;
+void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, char* work, hipStream_t st) {
     const char* plan = pl->plan;
     const Prob* P = pl->dprob;
-    const int N = p.n;
-    if (p.mode == 1) {
-        const int M = p.m, H = M / 2 + 1;
-        if (k == 0)
-            k_adj_scatter_rows<T, SORTED><<<dim3((N + 1) / 2, 1), 192, smem_for<T, ScatterRowSmem>(M), st>>>(
-                P, s, plan, work);
-        if (k == 1) k_adj_cols<T><<<dim3(H, 1), 192, smem_for<T, ColSmem>(M), st>>>(P, plan, work);
-        if (k == 2)
-            k_adj_rows<T, EPI><<<dim3((N + 1) / 2, 1), 64, smem_for<T, RowSmem>(M), st>>>(P, c_out, c_in, tau, plan,
-                                                                                         work);
-    } else {
-        const int tiles = (N + kTile - 1) / kTile;
-        T* G = reinterpret_cast<T*>(work + p.w_g);
-        if (k == 0)
-            k_scatter_rows<T, SORTED><<<dim3((N + 1) / 2, 1), 192, scatter_rows_smem(N, sizeof(T)), st>>>(
-                P, s, G, plan, work);
-        if (k == 1)
-            k_conv_direct<T, 3, 1, kDirectSlices, EPI><<<dim3(tiles, tiles, 1), 64 * kDirectSlices,
-                                                          direct_smem(p.radius, 3, 1, sizeof(T)), st>>>(
-                P, G, c_out, c_in, tau, plan, 0, 1);
+    const int B = pl->count;
+    const double* taus = reinterpret_cast<const double*>(work + pl->L.w_taus);
+    if (k <= 2 && !pl->any_fft) return;
+    if (k >= 3 && !pl->any_direct) return;
+    switch (k) {
+        case 0: k_adj_scatter_row<T, SORTED><<<dim3(pl->max_n, B), 256, pl->smem_scatter, st>>>(P, s, plan, work); break;
+        case 1: k_adj_cols<T><<<dim3(pl->max_h, B), 192, pl->smem_col, st>>>(P, plan, work); break;
+        case 2:
+            k_adj_rows<T, EPI><<<dim3(pl->max_rowpairs, B), 64, pl->smem_row, st>>>(P, c_out, c_in, taus, plan, work);
+            break;
+        case 3:
+            k_scatter_rows<T, SORTED><<<dim3(pl->max_n, B), 256, pl->smem_dscatter, st>>>(P, s, plan, work);
+            break;
+        case 4: {
+            const T* G = reinterpret_cast<const T*>(work);
+            T* out = EPI == 2 ? reinterpret_cast<T*>(work) : c_out;
+            launch_direct_conv<T, 4, EPI>(pl, false, G, out, c_in, taus, st);
+            launch_direct_conv<T, 8, EPI>(pl, false, G, out, c_in, taus, st);
+            launch_direct_conv<T, 16, EPI>(pl, false, G, out, c_in, taus, st);
+            break;
+        }
+        default: break;
     }
 }
-
-int stage_count(const Prob& p) { return p.mode == 1 ? 3 : 2; }
 
 template <typename T>
 int forward_impl(const mpi_plan* pl, const T* c, T* s, char* work, hipStream_t st) {
-    for (int k = 0; k < stage_count(pl->L.p); ++k) fwd_stage<T, false>(pl, k, c, s, work, st);
+    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, false>(pl, k, c, s, work, st);
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
 template <typename T, bool SORTED, int EPI>
-int adjoint_impl(const mpi_plan* pl, const T* s, T* c_out, const T* c_in, double tau, char* work, hipStream_t st) {
-    for (int k = 0; k < stage_count(pl->L.p); ++k) adj_stage<T, SORTED, EPI>(pl, k, s, c_out, c_in, tau, work, st);
+int adjoint_impl(const mpi_plan* pl, const T* s, T* c_out, const T* c_in, char* work, hipStream_t st) {
+    for (int k = 0; k < kAdjStages; ++k) adj_stage<T, SORTED, EPI>(pl, k, s, c_out, c_in, work, st);
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
-// One iteration c <- D(c - tau A^T (A c - s)); the measured signal is already
-// in cell order (work.ysort).
+// One iteration c <- D(c - tau_b A^T (A c - s)) for every problem; the
+// measured signal is already in cell order (work.ysort).  Without a denoiser
+// the step lands in c directly; with one, in work.u and then D(u) -> c.
 template <typename T>
-int iteration_impl(const mpi_plan* pl, T* c, double tau, bool denoise, int rad, char* work, hipStream_t st) {
-    const Prob& p = pl->L.p;
-    const int N = p.n;
-    for (int k = 0; k < stage_count(p); ++k) fwd_stage<T, true>(pl, k, c, nullptr, work, st);
-    T* u = reinterpret_cast<T*>(work + p.w_u);
-    int rc = adjoint_impl<T, true, 1>(pl, nullptr, denoise ? u : c, c, tau, work, st);
-    if (rc != MPI_OK) return rc;
-    if (denoise) {
-        const int tiles = (N + kDnTile - 1) / kDnTile;
-        k_denoise<T><<<dim3(tiles, tiles, 1), 256, 0, st>>>(pl->dprob, u, c,
-                                                            reinterpret_cast<const double*>(work + pl->L.w_wts), rad);
+int iteration_impl(const mpi_plan* pl, T* c, bool denoise, int rad, char* work, hipStream_t st) {
+    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, true>(pl, k, c, nullptr, work, st);
+    int rc;
+    if (!denoise) {
+        rc = adjoint_impl<T, true, 1>(pl, nullptr, c, c, work, st);
+    } else {
+        rc = adjoint_impl<T, true, 2>(pl, nullptr, reinterpret_cast<T*>(work), c, work, st);
+        if (rc == MPI_OK)
+            k_denoise<T><<<dim3(pl->max_dntiles, pl->max_dntiles, pl->count), 256, 0, st>>>(
+                pl->dprob, work, c, reinterpret_cast<const double*>(work + pl->L.w_wts), rad);
     }
+    if (rc != MPI_OK) return rc;
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
@@ -335,6 +493,265 @@ int check_call(const mpi_plan* pl, const void* a, const void* b, const void* wor
     if (misaligned(work, kAlign)) return MPI_ERR_ARG;
     const size_t el = pl->L.elem;
     if (misaligned(a, el) || misaligned(b, el)) return MPI_ERR_ARG;
+    return MPI_OK;
+}
+
+// ---------------------------------------------------------------- tuning ---
+// Cache: (element size, N, R, T bucket) -> (path, direct-path slices); kept
+// in memory and appended to the file named by MPIK_TUNE_CACHE, if set.
+struct TuneKey {
+    int elem, n, R, tb;
+    bool operator<(const TuneKey& o) const { return std::tie(elem, n, R, tb) < std::tie(o.elem, o.n, o.R, o.tb); }
+};
+std::map<TuneKey, std::pair<int, int>> g_tune;
+std::mutex g_tune_mu;
+bool g_tune_loaded = false;
+
+int t_bucket(int64_t T) {
+    int b = 0;
+    while ((int64_t(1) << (b + 1)) <= T) ++b;
+    return b;
+}
+
+void tune_cache_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("MPIK_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    TuneKey k;
+    int mode, slices;
+    while (std::fscanf(f, "%d %d %d %d %d %d", &k.elem, &k.n, &k.R, &k.tb, &mode, &slices) == 6)
+        g_tune[k] = {mode, slices};
+    std::fclose(f);
+}
+
+void tune_cache_store(const TuneKey& k, int mode, int slices) {
+    g_tune[k] = {mode, slices};
+    const char* path = std::getenv("MPIK_TUNE_CACHE");
+    if (!path) return;
+    if (FILE* f = std::fopen(path, "a")) {
+        std::fprintf(f, "%d %d %d %d %d %d\n", k.elem, k.n, k.R, k.tb, mode, slices);
+        std::fclose(f);
+    }
+}
+
+// Mean time of one forward + transpose pair of a one-problem plan; c and s
+// are taken from the problem's own work scratch (u and res).
+template <typename T>
+float time_pair(const mpi_plan* one, char* work, hipStream_t st, int reps) {
+    const Prob& p = one->L.probs[0];
+    T* c = reinterpret_cast<T*>(work + p.w_u);
+    T* s = reinterpret_cast<T*>(work + p.w_res);
+    if (hipMemsetAsync(c, 0, sizeof(T) * p.n * p.n, st) != hipSuccess) return -1.f;
+    if (hipMemsetAsync(s, 0, sizeof(T) * 2 * p.t, st) != hipSuccess) return -1.f;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1.f;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return -1.f;
+    }
+    for (int i = 0; i < reps + 2; ++i) {
+        if (i == 2) (void)hipEventRecord(a, st);
+        forward_impl<T>(one, c, s, work, st);
+        adjoint_impl<T, false, 0>(one, s, c, nullptr, work, st);
+    }
+    (void)hipEventRecord(b, st);
+    float ms = -1.f;
+    if (hipEventSynchronize(b) == hipSuccess) (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms > 0.f ? ms / reps : -1.f;
+}
+
+// Times every candidate (FFT path; direct path with 4, 8, 16 wave slices) of
+// problem b, whose plan region holds both paths, and returns the fastest.
+// The problem's descriptor slot is rewritten per candidate.
+template <typename T>
+int tune_problem(const mpi_plan* pl, int b, char* work, hipStream_t st, int& mode_out, int& slices_out) {
+    mpi_plan one;
+    one.L = pl->L;
+    one.count = 1;
+    one.dtype = pl->dtype;
+    one.plan = pl->plan;
+    one.dprob = pl->dprob + b;
+    const Shape& sh = pl->L.shapes[b];
+    std::vector<std::pair<int, int>> cands;
+    if (sh.fft_ok) cands.push_back({1, 8});
+    if (sh.direct_ok)
+        for (int i = 0; i < 3; ++i) cands.push_back({0, kSliceChoices[i]});
+    float best = 1e30f;
+    mode_out = pl->L.probs[b].mode;
+    slices_out = pl->L.probs[b].slices;
+    for (const auto& cd : cands) {
+        Prob q = pl->L.probs[b];
+        q.mode = cd.first;
+        q.slices = cd.second;
+        q.o_c = 0;
+        q.o_s = 0;
+        HIP_TRY(hipMemcpyAsync(const_cast<Prob*>(pl->dprob) + b, &q, sizeof(Prob), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        one.L.probs = {q};
+        finalize_extents(&one);
+        HIP_TRY(set_smem_limits<T>(&one));
+        const float ms = time_pair<T>(&one, work, st, 5);
+        if (ms > 0.f && ms < best) {
+            best = ms;
+            mode_out = cd.first;
+            slices_out = cd.second;
+        }
+    }
+    return MPI_OK;
+}
+
+template <typename T>
+int build_batch(const mpi_problem* probs, mpi_plan* pl, void* work, size_t work_bytes, int flags, hipStream_t st) {
+    BatchLayout& B = pl->L;
+    char* plan = pl->plan;
+    HIP_TRY(hipMemcpyAsync(plan, B.probs.data(), sizeof(Prob) * pl->count, hipMemcpyHostToDevice, st));
+    std::vector<int> errs(4 * size_t(pl->count), 0);
+    for (int b = 0; b < pl->count; ++b) {
+        const int rc = build_problem<T>(&probs[b], B, b, plan, st);
+        if (rc != MPI_OK) return rc;
+        HIP_TRY(hipMemcpyAsync(&errs[4 * b], plan + B.probs[b].o_err, 16, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int b = 0; b < pl->count; ++b)
+        if (errs[4 * b]) return MPI_ERR_DOMAIN;
+    // path choice for problems that asked for AUTO and can take either path
+    const bool tune = (flags & MPI_BUILD_TUNE) && work && work_bytes >= B.work_bytes;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_load();
+    for (int b = 0; b < pl->count; ++b) {
+        if (B.requested[b] != MPI_CONV_AUTO) continue;
+        const Shape& sh = B.shapes[b];
+        if (!(sh.fft_ok && sh.direct_ok)) continue;
+        const TuneKey key{sh.elem, sh.n, sh.R, t_bucket(sh.T)};
+        std::pair<int, int> choice{-1, -1};
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) choice = it->second;
+        if (choice.first < 0 && tune) {
+            int mode, slices;
+            const int rc = tune_problem<T>(pl, b, static_cast<char*>(work), st, mode, slices);
+            if (rc != MPI_OK) return rc;
+            choice = {mode, slices};
+            tune_cache_store(key, mode, slices);
+        }
+        if (choice.first >= 0) {
+            B.probs[b].mode = choice.first;
+            B.probs[b].slices = choice.second;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(plan, B.probs.data(), sizeof(Prob) * pl->count, hipMemcpyHostToDevice, st));
+    finalize_extents(pl);
+    HIP_TRY(set_smem_limits<T>(pl));
+    HIP_TRY(hipStreamSynchronize(st));
+    return MPI_OK;
+}
+
+int build_common(const mpi_problem* probs, int count, void* plan_mem, size_t plan_bytes, void* work,
+                 size_t work_bytes, int flags, hipStream_t stream, mpi_plan** out) {
+    if (!out) return MPI_ERR_ARG;
+    *out = nullptr;
+    BatchLayout L;
+    int rc = make_batch_layout(probs, count, L);
+    if (rc != MPI_OK) return rc;
+    if (!plan_mem || misaligned(plan_mem, kAlign)) return MPI_ERR_ARG;
+    for (int b = 0; b < count; ++b) {
+        if (!probs[b].r || !probs[b].v) return MPI_ERR_ARG;
+        if (misaligned(probs[b].r, L.elem) || misaligned(probs[b].v, L.elem)) return MPI_ERR_ARG;
+    }
+    if (plan_bytes < L.plan_bytes) return MPI_ERR_WORKSPACE;
+    if (work && misaligned(work, kAlign)) return MPI_ERR_ARG;
+    mpi_plan* pl = new (std::nothrow) mpi_plan;
+    if (!pl) return MPI_ERR_ARG;
+    pl->L = L;
+    pl->count = count;
+    pl->dtype = probs[0].dtype;
+    pl->plan = static_cast<char*>(plan_mem);
+    pl->dprob = static_cast<const Prob*>(plan_mem);
+    finalize_extents(pl);
+    rc = pl->dtype == MPI_F64 ? build_batch<double>(probs, pl, work, work_bytes, flags, stream)
+                              : build_batch<float>(probs, pl, work, work_bytes, flags, stream);
+    if (rc != MPI_OK) {
+        delete pl;
+        return rc;
+    }
+    *out = pl;
+    return MPI_OK;
+}
+
+template <typename T>
+int iterate_impl(mpi_plan* pl, const T* s, T* c, const mpi_iter_params* ip, const double* taus, char* work,
+                 hipStream_t st) {
+    const bool denoise = ip->denoise_sigma_px > 0.0;
+    const int rad = denoise ? ip->denoise_radius : 0;
+    HIP_TRY(hipMemcpyAsync(work + pl->L.w_taus, taus, sizeof(double) * pl->count, hipMemcpyHostToDevice, st));
+    if (denoise) {
+        double sum = 0.0;
+        for (int k = -rad; k <= rad; ++k) {
+            pl->wts[k + rad] = std::exp(-0.5 * k * k / (ip->denoise_sigma_px * ip->denoise_sigma_px));
+            sum += pl->wts[k + rad];
+        }
+        for (int k = 0; k <= 2 * rad; ++k) pl->wts[k] /= sum;
+        HIP_TRY(hipMemcpyAsync(work + pl->L.w_wts, pl->wts, sizeof(double) * (2 * rad + 1), hipMemcpyHostToDevice, st));
+    }
+    k_permute_signal<T><<<dim3(blocks(pl->max_t, 256), pl->count), 256, 0, st>>>(pl->dprob, s, pl->plan, work);
+    HIP_TRY(hipGetLastError());
+    if (ip->n_iter == 0) return MPI_OK;
+    if (!ip->use_graph) {
+        for (int it = 0; it < ip->n_iter; ++it) {
+            const int rc = iteration_impl<T>(pl, c, denoise, rad, work, st);
+            if (rc != MPI_OK) return rc;
+        }
+        return MPI_OK;
+    }
+    const bool same = pl->gexec && pl->g_s == s && pl->g_c == c && pl->g_work == work &&
+                      pl->g_sigma == (denoise ? ip->denoise_sigma_px : 0.0) && pl->g_rad == rad;
+    if (!same) {
+        if (pl->gexec) {
+            HIP_TRY(hipStreamSynchronize(st));
+            (void)hipGraphExecDestroy(pl->gexec);
+            (void)hipGraphDestroy(pl->graph);
+            pl->gexec = nullptr;
+            pl->graph = nullptr;
+        }
+        hipStream_t cap;
+        HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        int rc = MPI_ERR_HIP;
+        if (e == hipSuccess) {
+            rc = iteration_impl<T>(pl, c, denoise, rad, work, cap);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(cap, &g);
+            if (e == hipSuccess && rc == MPI_OK) {
+                e = hipGraphInstantiate(&pl->gexec, g, nullptr, nullptr, 0);
+                if (e == hipSuccess) pl->graph = g;
+                else (void)hipGraphDestroy(g);
+            } else if (g) {
+                (void)hipGraphDestroy(g);
+            }
+        }
+        (void)hipStreamDestroy(cap);
+        if (e != hipSuccess || rc != MPI_OK || !pl->gexec) {
+            pl->gexec = nullptr;
+            return MPI_ERR_HIP;
+        }
+        pl->g_s = s;
+        pl->g_c = c;
+        pl->g_work = work;
+        pl->g_sigma = denoise ? ip->denoise_sigma_px : 0.0;
+        pl->g_rad = rad;
+    }
+    for (int it = 0; it < ip->n_iter; ++it) HIP_TRY(hipGraphLaunch(pl->gexec, st));
+    return MPI_OK;
+}
+
+int check_iter(const mpi_iter_params* params) {
+    if (!params || params->n_iter < 0) return MPI_ERR_ARG;
+    if (params->denoise_sigma_px > 0.0 && (params->denoise_radius < 0 || params->denoise_radius > kDnMaxR))
+        return MPI_ERR_ARG;
     return MPI_OK;
 }
 
@@ -357,51 +774,59 @@ const char* mpi_status_str(int status) {
     }
 }
 
-int mpi_plan_bytes(const mpi_problem* prob, size_t* plan_bytes, size_t* work_bytes) {
+int mpi_batch_bytes(const mpi_problem* probs, int count, size_t* plan_bytes, size_t* work_bytes) {
     if (!plan_bytes || !work_bytes) return MPI_ERR_ARG;
-    Layout L;
-    const int rc = make_layout(prob, L);
+    BatchLayout L;
+    const int rc = make_batch_layout(probs, count, L);
     if (rc != MPI_OK) return rc;
     *plan_bytes = L.plan_bytes;
     *work_bytes = L.work_bytes;
     return MPI_OK;
 }
 
+int mpi_plan_bytes(const mpi_problem* prob, size_t* plan_bytes, size_t* work_bytes) {
+    return mpi_batch_bytes(prob, 1, plan_bytes, work_bytes);
+}
+
 int mpi_kernel_build(const mpi_problem* prob, void* plan_mem, size_t plan_bytes, hipStream_t stream, mpi_plan** out) {
-    if (!out) return MPI_ERR_ARG;
-    *out = nullptr;
-    Layout L;
-    int rc = make_layout(prob, L);
-    if (rc != MPI_OK) return rc;
-    if (!plan_mem || !prob->r || !prob->v) return MPI_ERR_ARG;
-    if (misaligned(plan_mem, kAlign)) return MPI_ERR_ARG;
-    if (misaligned(prob->r, L.elem) || misaligned(prob->v, L.elem)) return MPI_ERR_ARG;
-    if (plan_bytes < L.plan_bytes) return MPI_ERR_WORKSPACE;
-    mpi_plan* pl = new (std::nothrow) mpi_plan;
-    if (!pl) return MPI_ERR_ARG;
-    pl->L = L;
-    pl->dtype = prob->dtype;
-    pl->plan = static_cast<char*>(plan_mem);
-    pl->dprob = static_cast<const Prob*>(plan_mem);
-    rc = prob->dtype == MPI_F64 ? build_impl<double>(prob, pl->L, pl->plan, stream)
-                                : build_impl<float>(prob, pl->L, pl->plan, stream);
-    if (rc != MPI_OK) {
-        delete pl;
-        return rc;
+    return build_common(prob, 1, plan_mem, plan_bytes, nullptr, 0, 0, stream, out);
+}
+
+int mpi_batch_build(const mpi_problem* probs, int count, void* plan_mem, size_t plan_bytes, void* work,
+                    size_t work_bytes, int flags, hipStream_t stream, mpi_plan** out) {
+    return build_common(probs, count, plan_mem, plan_bytes, work, work_bytes, flags, stream, out);
+}
+
+int mpi_batch_count(const mpi_plan* plan) { return plan ? plan->count : MPI_ERR_ARG; }
+
+int mpi_batch_offsets(const mpi_plan* plan, int64_t* c_offsets, int64_t* s_offsets) {
+    if (!plan) return MPI_ERR_ARG;
+    for (int b = 0; b < plan->count; ++b) {
+        if (c_offsets) c_offsets[b] = plan->L.probs[b].o_c;
+        if (s_offsets) s_offsets[b] = plan->L.probs[b].o_s;
     }
-    *out = pl;
+    if (c_offsets) c_offsets[plan->count] = plan->L.c_elems;
+    if (s_offsets) s_offsets[plan->count] = plan->L.s_elems;
+    return MPI_OK;
+}
+
+int mpi_batch_info(const mpi_plan* plan, int index, int32_t* radius, int32_t* fft_size, int32_t* conv_mode,
+                   int32_t* slices) {
+    if (!plan || index < 0 || index >= plan->count) return MPI_ERR_ARG;
+    const Prob& p = plan->L.probs[index];
+    if (radius) *radius = p.radius;
+    if (fft_size) *fft_size = p.mode ? p.m : 0;
+    if (conv_mode) *conv_mode = p.mode ? MPI_CONV_FFT : MPI_CONV_DIRECT;
+    if (slices) *slices = p.mode ? 0 : p.slices;
     return MPI_OK;
 }
 
 int mpi_plan_info(const mpi_plan* plan, int32_t* radius, int32_t* fft_size, int32_t* conv_mode) {
-    if (!plan) return MPI_ERR_ARG;
-    if (radius) *radius = plan->L.p.radius;
-    if (fft_size) *fft_size = plan->L.p.m;
-    if (conv_mode) *conv_mode = plan->L.p.mode ? MPI_CONV_FFT : MPI_CONV_DIRECT;
-    return MPI_OK;
+    return mpi_batch_info(plan, 0, radius, fft_size, conv_mode, nullptr);
 }
 
-int mpi_forward(const mpi_plan* plan, const void* c, void* s, void* work, size_t work_bytes, hipStream_t stream) {
+int mpi_batch_forward(const mpi_plan* plan, const void* c, void* s, void* work, size_t work_bytes,
+                      hipStream_t stream) {
     int rc = check_call(plan, c, s, work, work_bytes);
     if (rc != MPI_OK) return rc;
     if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
@@ -411,136 +836,87 @@ int mpi_forward(const mpi_plan* plan, const void* c, void* s, void* work, size_t
                : forward_impl<float>(plan, static_cast<const float*>(c), static_cast<float*>(s), w, stream);
 }
 
-int mpi_adjoint(const mpi_plan* plan, const void* s, void* c, void* work, size_t work_bytes, hipStream_t stream) {
+int mpi_batch_adjoint(const mpi_plan* plan, const void* s, void* c, void* work, size_t work_bytes,
+                      hipStream_t stream) {
     int rc = check_call(plan, s, c, work, work_bytes);
     if (rc != MPI_OK) return rc;
     if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
     char* w = static_cast<char*>(work);
     return plan->dtype == MPI_F64
                ? adjoint_impl<double, false, 0>(plan, static_cast<const double*>(s), static_cast<double*>(c), nullptr,
-                                                0.0, w, stream)
-               : adjoint_impl<float, false, 0>(plan, static_cast<const float*>(s), static_cast<float*>(c), nullptr,
-                                               0.0, w, stream);
+                                                w, stream)
+               : adjoint_impl<float, false, 0>(plan, static_cast<const float*>(s), static_cast<float*>(c), nullptr, w,
+                                               stream);
 }
 
-}  // extern "C"
-
-namespace {
-
-template <typename T>
-int iterate_impl(mpi_plan* pl, const T* s, T* c, const mpi_iter_params* ip, char* work, hipStream_t st) {
-    const Prob& p = pl->L.p;
-    const bool denoise = ip->denoise_sigma_px > 0.0;
-    const int rad = denoise ? ip->denoise_radius : 0;
-    if (denoise) {
-        double sum = 0.0;
-        for (int k = -rad; k <= rad; ++k) {
-            pl->wts[k + rad] = std::exp(-0.5 * k * k / (ip->denoise_sigma_px * ip->denoise_sigma_px));
-            sum += pl->wts[k + rad];
-        }
-        for (int k = 0; k <= 2 * rad; ++k) pl->wts[k] /= sum;
-        HIP_TRY(hipMemcpyAsync(work + pl->L.w_wts, pl->wts, sizeof(double) * (2 * rad + 1), hipMemcpyHostToDevice, st));
-    }
-    k_permute_signal<T><<<dim3(blocks(p.t, 256), 1), 256, 0, st>>>(pl->dprob, s, pl->plan, work);
-    HIP_TRY(hipGetLastError());
-    if (ip->n_iter == 0) return MPI_OK;
-    if (!ip->use_graph) {
-        for (int it = 0; it < ip->n_iter; ++it) {
-            const int rc = iteration_impl<T>(pl, c, ip->tau, denoise, rad, work, st);
-            if (rc != MPI_OK) return rc;
-        }
-        return MPI_OK;
-    }
-    const bool same = pl->gexec && pl->g_s == s && pl->g_c == c && pl->g_work == work && pl->g_tau == ip->tau &&
-                      pl->g_sigma == (denoise ? ip->denoise_sigma_px : 0.0) && pl->g_rad == rad;
-    if (!same) {
-        if (pl->gexec) {
-            HIP_TRY(hipStreamSynchronize(st));
-            (void)hipGraphExecDestroy(pl->gexec);
-            (void)hipGraphDestroy(pl->graph);
-            pl->gexec = nullptr;
-            pl->graph = nullptr;
-        }
-        hipStream_t cap;
-        HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-        int rc = MPI_ERR_HIP;
-        if (e == hipSuccess) {
-            rc = iteration_impl<T>(pl, c, ip->tau, denoise, rad, work, cap);
-            hipGraph_t g = nullptr;
-            e = hipStreamEndCapture(cap, &g);
-            if (e == hipSuccess && rc == MPI_OK) {
-                e = hipGraphInstantiate(&pl->gexec, g, nullptr, nullptr, 0);
-                if (e == hipSuccess) pl->graph = g;
-                else (void)hipGraphDestroy(g);
-            } else if (g) {
-                (void)hipGraphDestroy(g);
-            }
-        }
-        (void)hipStreamDestroy(cap);
-        if (e != hipSuccess || rc != MPI_OK || !pl->gexec) {
-            pl->gexec = nullptr;
-            return MPI_ERR_HIP;
-        }
-        pl->g_s = s;
-        pl->g_c = c;
-        pl->g_work = work;
-        pl->g_tau = ip->tau;
-        pl->g_sigma = denoise ? ip->denoise_sigma_px : 0.0;
-        pl->g_rad = rad;
-    }
-    for (int it = 0; it < ip->n_iter; ++it) HIP_TRY(hipGraphLaunch(pl->gexec, st));
-    return MPI_OK;
+int mpi_forward(const mpi_plan* plan, const void* c, void* s, void* work, size_t work_bytes, hipStream_t stream) {
+    if (plan && plan->count != 1) return MPI_ERR_ARG;
+    return mpi_batch_forward(plan, c, s, work, work_bytes, stream);
 }
 
-}  // namespace
+int mpi_adjoint(const mpi_plan* plan, const void* s, void* c, void* work, size_t work_bytes, hipStream_t stream) {
+    if (plan && plan->count != 1) return MPI_ERR_ARG;
+    return mpi_batch_adjoint(plan, s, c, work, work_bytes, stream);
+}
 
-extern "C" {
-
-int mpi_iterate(const mpi_plan* plan, const void* s, void* c, const mpi_iter_params* params, void* work,
-                size_t work_bytes, hipStream_t stream) {
+int mpi_batch_iterate(const mpi_plan* plan, const void* s, void* c, const mpi_iter_params* params,
+                      const double* taus, void* work, size_t work_bytes, hipStream_t stream) {
     int rc = check_call(plan, s, c, work, work_bytes);
     if (rc != MPI_OK) return rc;
-    if (!params || params->n_iter < 0 || !std::isfinite(params->tau)) return MPI_ERR_ARG;
-    if (params->denoise_sigma_px > 0.0 && (params->denoise_radius < 0 || params->denoise_radius > kDnMaxR))
-        return MPI_ERR_ARG;
+    rc = check_iter(params);
+    if (rc != MPI_OK) return rc;
+    if (!taus) return MPI_ERR_ARG;
+    for (int b = 0; b < plan->count; ++b)
+        if (!std::isfinite(taus[b])) return MPI_ERR_ARG;
     if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
     mpi_plan* pl = const_cast<mpi_plan*>(plan);
     char* w = static_cast<char*>(work);
     return plan->dtype == MPI_F64
-               ? iterate_impl<double>(pl, static_cast<const double*>(s), static_cast<double*>(c), params, w, stream)
-               : iterate_impl<float>(pl, static_cast<const float*>(s), static_cast<float*>(c), params, w, stream);
+               ? iterate_impl<double>(pl, static_cast<const double*>(s), static_cast<double*>(c), params, taus, w,
+                                      stream)
+               : iterate_impl<float>(pl, static_cast<const float*>(s), static_cast<float*>(c), params, taus, w,
+                                     stream);
+}
+
+int mpi_iterate(const mpi_plan* plan, const void* s, void* c, const mpi_iter_params* params, void* work,
+                size_t work_bytes, hipStream_t stream) {
+    if (plan && plan->count != 1) return MPI_ERR_ARG;
+    if (check_iter(params) != MPI_OK) return MPI_ERR_ARG;
+    const double tau = params->tau;
+    return mpi_batch_iterate(plan, s, c, params, &tau, work, work_bytes, stream);
 }
 
 int mpi_stage_count(const mpi_plan* plan) {
     if (!plan) return MPI_ERR_ARG;
-    return 2 * stage_count(plan->L.p);
+    return kFwdStages + kAdjStages;
 }
 
 const char* mpi_stage_name(const mpi_plan* plan, int stage) {
-    static const char* fft_names[] = {"fwd_rows", "fwd_cols", "fwd_rows_gather",
-                                      "adj_scatter_rows", "adj_cols", "adj_rows"};
-    static const char* direct_names[] = {"conv_direct_fwd", "gather_rows", "scatter_rows", "conv_direct_adj"};
-    if (!plan || stage < 0 || stage >= 2 * stage_count(plan->L.p)) return nullptr;
-    return plan->L.p.mode == 1 ? fft_names[stage] : direct_names[stage];
+    static const char* names[] = {"fwd_rows", "fwd_cols", "fwd_rows_gather", "conv_direct_fwd", "gather_rows",
+                                  "adj_scatter_row", "adj_cols", "adj_rows", "scatter_rows", "conv_direct_adj"};
+    if (!plan || stage < 0 || stage >= kFwdStages + kAdjStages) return nullptr;
+    return names[stage];
 }
 
-int mpi_stage_launch(const mpi_plan* plan, int stage, int reps, void* c, void* s, void* work,
-                     size_t work_bytes, hipStream_t stream) {
+int mpi_stage_launch(const mpi_plan* plan, int stage, int reps, void* c, void* s, void* work, size_t work_bytes,
+                     hipStream_t stream) {
     int rc = check_call(plan, c, s, work, work_bytes);
     if (rc != MPI_OK) return rc;
-    const int ns = stage_count(plan->L.p);
-    if (stage < 0 || stage >= 2 * ns || reps < 0) return MPI_ERR_ARG;
+    if (stage < 0 || stage >= kFwdStages + kAdjStages || reps < 0) return MPI_ERR_ARG;
     char* w = static_cast<char*>(work);
     for (int r = 0; r < reps; ++r) {
         if (plan->dtype == MPI_F64) {
-            if (stage < ns) fwd_stage<double, false>(plan, stage, static_cast<const double*>(c), static_cast<double*>(s), w, stream);
-            else adj_stage<double, false, 0>(plan, stage - ns, static_cast<const double*>(s), static_cast<double*>(c),
-                                            nullptr, 0.0, w, stream);
+            if (stage < kFwdStages)
+                fwd_stage<double, false>(plan, stage, static_cast<const double*>(c), static_cast<double*>(s), w, stream);
+            else
+                adj_stage<double, false, 0>(plan, stage - kFwdStages, static_cast<const double*>(s),
+                                            static_cast<double*>(c), nullptr, w, stream);
         } else {
-            if (stage < ns) fwd_stage<float, false>(plan, stage, static_cast<const float*>(c), static_cast<float*>(s), w, stream);
-            else adj_stage<float, false, 0>(plan, stage - ns, static_cast<const float*>(s), static_cast<float*>(c),
-                                           nullptr, 0.0, w, stream);
+            if (stage < kFwdStages)
+                fwd_stage<float, false>(plan, stage, static_cast<const float*>(c), static_cast<float*>(s), w, stream);
+            else
+                adj_stage<float, false, 0>(plan, stage - kFwdStages, static_cast<const float*>(s),
+                                           static_cast<float*>(c), nullptr, w, stream);
         }
     }
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;

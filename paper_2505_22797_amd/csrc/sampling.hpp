@@ -3,11 +3,13 @@
 // core:formula) and its exact transpose.  Both work on a band of grid rows
 // held in LDS by one work-group.
 //
-// The transpose is deterministic: contributions (sample, corner) are grouped
-// by target cell at plan time; the work-group splits its contiguous range of
-// contributions evenly over its threads, each thread sums runs of equal cells
-// in order, and partial sums of cells that straddle thread boundaries are
-// combined by the lowest thread in a fixed order.  No floating-point atomics.
+// The transpose is deterministic: samples are sorted by base cell at plan
+// time; a work-group splits its contiguous range of samples evenly over its
+// threads, each thread sums runs of equal base cells in order, partial sums of
+// base cells that straddle thread boundaries are combined by the lowest thread
+// in a fixed order, and every grid cell adds its four base cells in a fixed
+// order.  No floating-point atomics.  Loads are issued in batches so that a
+// thread keeps several in flight.
 #pragma once
 #include "common.hpp"
 
@@ -15,127 +17,187 @@ namespace mpik {
 
 // Gather for the samples of base-cell row b (cell order [p0, p1)).  g0/g1 hold
 // the three channels of grid rows b and b+1: g0[ch * N + i], g1[ch * N + i].
-// RESID: write s - y (cell order) to out_sorted[p]; else s to s_time[perm[p]].
-template <typename T, bool RESID>
+// RESID: write s - y (cell order) to out_sorted[p]; else s to s_time[k].
+template <typename T, bool RESID, int U = 4>
 __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int p0, int p1,
-                                            const vec4<T>* __restrict__ samp, const int* __restrict__ bcell,
-                                            const int* __restrict__ perm, const vec2<T>* __restrict__ ysort,
-                                            vec2<T>* __restrict__ out_sorted, T* __restrict__ s_time,
-                                            int tid, int nthreads) {
-    for (int p = p0 + tid; p < p1; p += nthreads) {
-        const vec4<T> e = samp[p];
-        const int i0 = bcell[p] & 0xffff;
-        const T fx = e.x, fy = e.y, gx = T(1) - fx, gy = T(1) - fy;
-        T g[3];
+                                            const vec4<T>* __restrict__ samp, const int2* __restrict__ sidx,
+                                            const vec2<T>* __restrict__ ysort, vec2<T>* __restrict__ out_sorted,
+                                            T* __restrict__ s_time, int tid, int nthreads) {
+    for (int base = p0 + tid; base < p1; base += U * nthreads) {
+        vec4<T> e[U];
+        int2 id[U];
+        vec2<T> y[U];
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            const T lo = gx * g0[ch * N + i0] + fx * g0[ch * N + i0 + 1];
-            const T hi = gx * g1[ch * N + i0] + fx * g1[ch * N + i0 + 1];
-            g[ch] = gy * lo + fy * hi;
+        for (int u = 0; u < U; ++u) {
+            const int p = base + u * nthreads;
+            if (p < p1) {
+                e[u] = samp[p];
+                id[u] = sidx[p];
+                if (RESID) y[u] = ysort[p];
+            }
         }
-        const T sx = g[0] * e.z + g[1] * e.w;
-        const T sy = g[1] * e.z + g[2] * e.w;
-        if (RESID) {
-            const vec2<T> y = ysort[p];
-            vec2<T> o;
-            o.x = sx - y.x;
-            o.y = sy - y.y;
-            out_sorted[p] = o;
-        } else {
-            const int k = perm[p];
-            s_time[2 * k] = sx;
-            s_time[2 * k + 1] = sy;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = base + u * nthreads;
+            if (p >= p1) break;
+            const int i0 = id[u].x & 0xffff;
+            const T fx = e[u].x, fy = e[u].y, gx = T(1) - fx, gy = T(1) - fy;
+            T g[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const T lo = gx * g0[ch * N + i0] + fx * g0[ch * N + i0 + 1];
+                const T hi = gx * g1[ch * N + i0] + fx * g1[ch * N + i0 + 1];
+                g[ch] = gy * lo + fy * hi;
+            }
+            const T sx = g[0] * e[u].z + g[1] * e[u].w;
+            const T sy = g[1] * e[u].z + g[2] * e[u].w;
+            if (RESID) {
+                vec2<T> o;
+                o.x = sx - y[u].x;
+                o.y = sy - y[u].y;
+                out_sorted[p] = o;
+            } else {
+                const int k = id[u].y;
+                s_time[2 * k] = sx;
+                s_time[2 * k + 1] = sy;
+            }
         }
     }
 }
 
-// Shared-memory layout of scatter_band for a band of `rows` grid rows.
-template <typename T> struct ScatterSmem {
-    static constexpr int kThreads = 192;
-    int cs[2 * 1024 + 1];            // cell starts of the band (<= 2 rows of N <= 1024)
-    int first_cell[kThreads], last_cell[kThreads];
-    T first_val[kThreads][3], last_val[kThreads][3];
+// Shared-memory part of scatter_row for NT threads and rows of N <= NMAX.
+template <typename T, int NT, int NMAX> struct ScatterSmem {
+    static constexpr int kThreads = NT;
+    T K[2 * NMAX * 6];                 // per base cell: (left, right) x 3 channels
+    int first_key[NT], last_key[NT];
+    T first_val[NT][6], last_val[NT][6];
 };
 
-// Transpose of the sampling for the cells of `rows` consecutive grid rows
-// starting at row0.  Writes g[ch * rows * N + local_cell] in LDS (zeroed here).
-// SORTED: signal/residual read in cell order from ys[p]; else in time order
-// from s_time[perm[p]].
-template <typename T, bool SORTED>
-__device__ __forceinline__ void scatter_band(T* g, ScatterSmem<T>& sm, int N, int row0, int rows,
-                                             const int* __restrict__ cellstart, const int* __restrict__ items,
-                                             const vec4<T>* __restrict__ samp, const int* __restrict__ perm,
-                                             const vec2<T>* __restrict__ ys, const T* __restrict__ s_time,
-                                             int tid) {
-    constexpr int NT = ScatterSmem<T>::kThreads;
-    const int nc = rows * N;
-    const int cbase = row0 * N;
-    for (int i = tid; i <= nc; i += NT) sm.cs[i] = cellstart[cbase + i];
-    for (int i = tid; i < 3 * nc; i += NT) g[i] = T(0);
+// Transpose of the sampling for the cells of grid row j.  Those cells receive
+// from the samples of base-cell rows j-1 (weight fy) and j (weight 1 - fy),
+// which are one contiguous range in cell order.  Pass 1 splits that range
+// evenly over the threads; every thread walks its samples in order and sums,
+// per base cell, the contributions to the cell on its left (weight 1 - fx)
+// and on its right (fx); base cells that straddle thread boundaries are
+// combined by their first thread in thread order.  Pass 2 assembles every
+// cell from its (at most) four base cells in a fixed order.  The result goes
+// to g[ch * N + i] in LDS.  SORTED: the signal/residual is read in cell order
+// from ys[p]; else in time order from s_time[k].
+template <typename T, bool SORTED, int NT, int NMAX, int U = 4>
+__device__ __forceinline__ void scatter_row(T* g, ScatterSmem<T, NT, NMAX>& sm, int N, int j,
+                                            const int* __restrict__ binstart, const vec4<T>* __restrict__ samp,
+                                            const int2* __restrict__ sidx, const vec2<T>* __restrict__ ys,
+                                            const T* __restrict__ s_time, int tid) {
+    const int nb = N - 1;
+    const int rlo = max(j - 1, 0), rhi = min(j, nb - 1);       // base-cell rows that reach row j
+    const int nkeys = 2 * nb;
+    for (int i = tid; i < nkeys * 6; i += NT) sm.K[i] = T(0);
+    const int P0 = binstart[rlo * nb], P1 = binstart[(rhi + 1) * nb];
+    const int E = (P1 - P0 + NT - 1) / NT;
+    const int a = min(P0 + tid * E, P1), b = min(a + E, P1);
+    int fk = -1, lk = -1;
+    T acc[6], fv[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc[q] = fv[q] = T(0);
     __syncthreads();
-    const int I0 = sm.cs[0], I1 = sm.cs[nc];
-    const int E = (I1 - I0 + NT - 1) / NT;
-    const int a = min(I0 + tid * E, I1), b = min(a + E, I1);
-    int fc = -1, lc = -1;
-    T acc0 = T(0), acc1 = T(0), acc2 = T(0);
-    T f0 = T(0), f1 = T(0), f2 = T(0);
-    if (a < b) {
-        // largest cell with cs[cell] <= a (it holds item a)
-        int lo = 0, hi = nc;          // invariant: cs[lo] <= a < cs[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (sm.cs[mid] <= a) lo = mid; else hi = mid;
-        }
-        lc = lo;
-        fc = lo;
-        for (int it = a; it < b; ++it) {
-            while (it >= sm.cs[lc + 1]) {       // leaving cell lc
-                if (lc == fc) { f0 = acc0; f1 = acc1; f2 = acc2; }
-                else { g[lc] = acc0; g[nc + lc] = acc1; g[2 * nc + lc] = acc2; }
-                acc0 = acc1 = acc2 = T(0);
-                ++lc;
+    for (int base = a; base < b; base += U) {
+        vec4<T> e[U];
+        int2 id[U];
+        vec2<T> y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (base + u < b) {
+                e[u] = samp[base + u];
+                id[u] = sidx[base + u];
+                if (SORTED) y[u] = ys[base + u];
             }
-            const unsigned item = unsigned(items[it]);
-            const int p = int(item & 0x3fffffffu);
-            const unsigned corner = item >> 30;
-            const vec4<T> e = samp[p];
-            vec2<T> y;
-            if (SORTED) {
-                y = ys[p];
-            } else {
-                const int k = perm[p];
-                y.x = s_time[2 * k];
-                y.y = s_time[2 * k + 1];
-            }
-            const T wx = (corner & 1u) ? e.x : T(1) - e.x;
-            const T wy = (corner & 2u) ? e.y : T(1) - e.y;
-            const T w = wx * wy;
-            acc0 += w * (y.x * e.z);
-            acc1 += w * (y.x * e.w + y.y * e.z);
-            acc2 += w * (y.y * e.w);
         }
-        if (lc == fc) { f0 = acc0; f1 = acc1; f2 = acc2; }
+        if (!SORTED) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (base + u < b) {
+                    const int k = id[u].y;
+                    y[u].x = s_time[2 * k];
+                    y[u].y = s_time[2 * k + 1];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (base + u >= b) break;
+            const int i0 = id[u].x & 0xffff, j0 = id[u].x >> 16;
+            const int key = (j0 - (j - 1)) * nb + i0;      // 0 .. nb-1: row j-1, nb .. 2nb-1: row j
+            if (key != lk) {
+                if (lk >= 0) {
+                    if (lk == fk) {
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) fv[q] = acc[q];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) sm.K[lk * 6 + q] = acc[q];
+                    }
+                } else {
+                    fk = key;
+                }
+#pragma unroll
+                for (int q = 0; q < 6; ++q) acc[q] = T(0);
+                lk = key;
+            }
+            const T wy = (j0 == j) ? T(1) - e[u].y : e[u].y;
+            const T wl = (T(1) - e[u].x) * wy, wr = e[u].x * wy;
+            const T p0 = y[u].x * e[u].z;
+            const T p1 = y[u].x * e[u].w + y[u].y * e[u].z;
+            const T p2 = y[u].y * e[u].w;
+            acc[0] += wl * p0; acc[1] += wl * p1; acc[2] += wl * p2;
+            acc[3] += wr * p0; acc[4] += wr * p1; acc[5] += wr * p2;
+        }
     }
-    sm.first_cell[tid] = fc;
-    sm.last_cell[tid] = lc;
-    sm.first_val[tid][0] = f0; sm.first_val[tid][1] = f1; sm.first_val[tid][2] = f2;
-    sm.last_val[tid][0] = acc0; sm.last_val[tid][1] = acc1; sm.last_val[tid][2] = acc2;
+    if (lk >= 0 && lk == fk) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) fv[q] = acc[q];
+    }
+    sm.first_key[tid] = fk;
+    sm.last_key[tid] = lk;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        sm.first_val[tid][q] = fv[q];
+        sm.last_val[tid][q] = acc[q];
+    }
     __syncthreads();
-    if (a < b) {
-        const bool shared_head = tid > 0 && sm.last_cell[tid - 1] == fc;
-        if (fc != lc && !shared_head) {          // first cell lies wholly in this thread
-            g[fc] = f0; g[nc + fc] = f1; g[2 * nc + fc] = f2;
+    if (lk >= 0) {
+        const bool shared_head = tid > 0 && sm.last_key[tid - 1] == fk;
+        if (fk != lk && !shared_head) {          // first key lies wholly in this thread
+#pragma unroll
+            for (int q = 0; q < 6; ++q) sm.K[fk * 6 + q] = fv[q];
         }
-        if (!(fc == lc && shared_head)) {         // this thread owns its last cell
-            T s0 = acc0, s1 = acc1, s2 = acc2;
-            for (int u = tid + 1; u < NT && sm.first_cell[u] == lc; ++u) {
-                s0 += sm.first_val[u][0];
-                s1 += sm.first_val[u][1];
-                s2 += sm.first_val[u][2];
-                if (sm.last_cell[u] != lc) break;
+        if (!(fk == lk && shared_head)) {         // this thread owns its last key
+            T tot[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) tot[q] = acc[q];
+            for (int u = tid + 1; u < NT && sm.first_key[u] == lk; ++u) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) tot[q] += sm.first_val[u][q];
+                if (sm.last_key[u] != lk) break;
             }
-            g[lc] = s0; g[nc + lc] = s1; g[2 * nc + lc] = s2;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) sm.K[lk * 6 + q] = tot[q];
         }
+    }
+    __syncthreads();
+    // cell (j, i) <- row j base cells i (left) and i-1 (right), then row j-1 likewise
+    for (int i = tid; i < N; i += NT) {
+        T v0 = T(0), v1 = T(0), v2 = T(0);
+        if (j <= nb - 1) {
+            if (i <= nb - 1) { const T* k = sm.K + (nb + i) * 6; v0 += k[0]; v1 += k[1]; v2 += k[2]; }
+            if (i >= 1) { const T* k = sm.K + (nb + i - 1) * 6; v0 += k[3]; v1 += k[4]; v2 += k[5]; }
+        }
+        if (j >= 1) {
+            if (i <= nb - 1) { const T* k = sm.K + i * 6; v0 += k[0]; v1 += k[1]; v2 += k[2]; }
+            if (i >= 1) { const T* k = sm.K + (i - 1) * 6; v0 += k[3]; v1 += k[4]; v2 += k[5]; }
+        }
+        g[i] = v0;
+        g[N + i] = v1;
+        g[2 * N + i] = v2;
     }
     __syncthreads();
 }

@@ -20,8 +20,11 @@ MPI_F32, MPI_F64 = 0, 1
 CONV_MODES = {"auto": 0, "direct": 1, "fft": 2}
 
 EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
-           "mpi_plan_info", "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
+           "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
+           "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_iterate",
+           "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
            "mpi_plan_destroy", "mpi_status_str", "mpi_abi_version")
+MPI_BUILD_TUNE = 1
 
 
 class MpiError(RuntimeError):
@@ -59,6 +62,17 @@ def lib() -> ctypes.CDLL:
         L.mpi_iterate.argtypes = [vp, vp, vp, ctypes.POINTER(IterParams), vp, sz, vp]
         L.mpi_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int32)]
+        i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+        L.mpi_batch_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.mpi_batch_build.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, vp, sz, vp, sz, ctypes.c_int, vp,
+                                      ctypes.POINTER(vp)]
+        L.mpi_batch_count.argtypes = [vp]
+        L.mpi_batch_offsets.argtypes = [vp, i64p, i64p]
+        L.mpi_batch_info.argtypes = [vp, ctypes.c_int, i32p, i32p, i32p, i32p]
+        L.mpi_batch_forward.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.mpi_batch_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.mpi_batch_iterate.argtypes = [vp, vp, vp, ctypes.POINTER(IterParams), ctypes.POINTER(ctypes.c_double),
+                                        vp, sz, vp]
         L.mpi_stage_count.argtypes = [vp]
         L.mpi_stage_name.argtypes = [vp, ctypes.c_int]
         L.mpi_stage_name.restype = ctypes.c_char_p
@@ -68,7 +82,9 @@ def lib() -> ctypes.CDLL:
         L.mpi_status_str.restype = ctypes.c_char_p
         L.mpi_abi_version.argtypes = []
         for name in ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
-                     "mpi_plan_info", "mpi_stage_count", "mpi_stage_launch", "mpi_plan_destroy", "mpi_abi_version"):
+                     "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
+                     "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_iterate",
+                     "mpi_stage_count", "mpi_stage_launch", "mpi_plan_destroy", "mpi_abi_version"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -188,6 +204,113 @@ class Plan:
         self._vec(s, (self.n_samples, 2), "s")
         _check(lib().mpi_stage_launch(self._h, int(stage), int(reps), c.data_ptr(), s.data_ptr(),
                                       self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_stage_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mpi_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent problems in one plan; every stage is one launch over
+    the whole batch.  Concentrations and signals of all problems live
+    concatenated in one flat tensor each (see `c_offsets`, `s_offsets`)."""
+
+    def __init__(self, specs, dtype=torch.float32, tune: bool = True, stream=None):
+        """specs: list of (n, h, radius, r, v[, conv_mode]) with r, v device (T, 2)."""
+        keep = []
+        arr = (Problem * len(specs))()
+        for i, sp in enumerate(specs):
+            n, h, radius, r, v = sp[:5]
+            mode = sp[5] if len(sp) > 5 else "auto"
+            r = r.contiguous()
+            v = v.contiguous()
+            if r.dtype != dtype or v.dtype != dtype:
+                raise ValueError("every problem of a batch shares the dtype")
+            keep += [r, v]
+            arr[i] = problem(n, h, radius, r, v, conv_mode=mode)
+        self.count = len(specs)
+        self.dtype = dtype
+        self.device = specs[0][3].device
+        self.ns = [int(sp[0]) for sp in specs]
+        self.ts = [int(sp[3].shape[0]) for sp in specs]
+        pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().mpi_batch_bytes(arr, self.count, ctypes.byref(pb), ctypes.byref(wb)), "mpi_batch_bytes")
+        self.plan_mem = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
+        self.work = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
+        handle = ctypes.c_void_p()
+        _check(lib().mpi_batch_build(arr, self.count, self.plan_mem.data_ptr(), pb.value, self.work.data_ptr(),
+                                     wb.value, MPI_BUILD_TUNE if tune else 0, _stream(stream),
+                                     ctypes.byref(handle)), "mpi_batch_build")
+        self._h = handle
+        co = (ctypes.c_int64 * (self.count + 1))()
+        so = (ctypes.c_int64 * (self.count + 1))()
+        _check(lib().mpi_batch_offsets(self._h, co, so), "mpi_batch_offsets")
+        self.c_offsets = list(co)
+        self.s_offsets = list(so)
+        self.info = []
+        for b in range(self.count):
+            rad, m, mode, sl = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            _check(lib().mpi_batch_info(self._h, b, ctypes.byref(rad), ctypes.byref(m), ctypes.byref(mode),
+                                        ctypes.byref(sl)), "mpi_batch_info")
+            self.info.append(dict(radius=rad.value, fft_size=m.value,
+                                  conv_mode="fft" if mode.value == 2 else "direct", slices=sl.value))
+
+    def stages(self) -> list[str]:
+        n = lib().mpi_stage_count(self._h)
+        return [lib().mpi_stage_name(self._h, k).decode() for k in range(n)]
+
+    def launch_stage(self, stage: int, reps: int, c_all: torch.Tensor, s_all: torch.Tensor, stream=None):
+        """Enqueue `reps` launches of one kernel of the forward/transpose sequence."""
+        self._flat(c_all, self.c_offsets[-1], "c_all")
+        self._flat(s_all, self.s_offsets[-1], "s_all")
+        _check(lib().mpi_stage_launch(self._h, int(stage), int(reps), c_all.data_ptr(), s_all.data_ptr(),
+                                      self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_stage_launch")
+
+    def c_views(self, c_all):
+        return [c_all[self.c_offsets[b]:self.c_offsets[b + 1]].view(self.ns[b], self.ns[b]) for b in range(self.count)]
+
+    def s_views(self, s_all):
+        return [s_all[self.s_offsets[b]:self.s_offsets[b + 1]].view(self.ts[b], 2) for b in range(self.count)]
+
+    def _flat(self, t, n, name):
+        if t.dtype != self.dtype or t.device != self.device or t.numel() != n or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of {n} elements")
+        return t
+
+    def forward(self, c_all, s_all=None, stream=None):
+        self._flat(c_all, self.c_offsets[-1], "c_all")
+        if s_all is None:
+            s_all = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
+        self._flat(s_all, self.s_offsets[-1], "s_all")
+        _check(lib().mpi_batch_forward(self._h, c_all.data_ptr(), s_all.data_ptr(), self.work.data_ptr(),
+                                       self.work.numel(), _stream(stream)), "mpi_batch_forward")
+        return s_all
+
+    def adjoint(self, s_all, c_all=None, stream=None):
+        self._flat(s_all, self.s_offsets[-1], "s_all")
+        if c_all is None:
+            c_all = torch.empty(self.c_offsets[-1], dtype=self.dtype, device=self.device)
+        self._flat(c_all, self.c_offsets[-1], "c_all")
+        _check(lib().mpi_batch_adjoint(self._h, s_all.data_ptr(), c_all.data_ptr(), self.work.data_ptr(),
+                                       self.work.numel(), _stream(stream)), "mpi_batch_adjoint")
+        return c_all
+
+    def iterate(self, s_all, c_all, n_iter, taus, denoise_sigma_px=0.0, denoise_radius=2, use_graph=True,
+                stream=None):
+        self._flat(s_all, self.s_offsets[-1], "s_all")
+        self._flat(c_all, self.c_offsets[-1], "c_all")
+        tarr = (ctypes.c_double * self.count)(*[float(t) for t in taus])
+        ip = IterParams(int(n_iter), 0.0, float(denoise_sigma_px), int(denoise_radius), int(bool(use_graph)))
+        _check(lib().mpi_batch_iterate(self._h, s_all.data_ptr(), c_all.data_ptr(), ctypes.byref(ip), tarr,
+                                       self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_batch_iterate")
+        return c_all
 
     def close(self):
         if getattr(self, "_h", None):

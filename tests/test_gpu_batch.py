@@ -1,0 +1,125 @@
+"""GPU tests of the batched plan: many uneven problems per launch.
+
+A batch runs the same kernels as single-problem plans, so with the same
+convolution path per problem the results are bitwise identical to the single
+plans; every problem also matches the float64 oracle (1e-5 per apply, 1e-4
+after iterations).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2505_22797_amd import mpik
+from paper_2505_22797_amd import synth as S
+from gpu_helpers import dev, rel_l2, rounded
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_batch():
+    specs = []
+    shapes = [(24, 5, 3000, "direct", 0), (33, 12, 5000, "fft", 1), (48, 31, 9000, "fft", 2),
+              (40, 9, 4000, "direct", 1), (64, 31, 12000, "direct", 0), (17, 16, 1500, "fft", 2)]
+    for i, (n, R, t, mode, kind) in enumerate(shapes):
+        if kind == 0:
+            tr = S.lissajous(t, ax=0.85, ay=0.85)
+        elif kind == 1:
+            tr = S.lissajous(t, ax=0.8, ay=0.85, exc_amp=0.04, exc_cycles=17 * 30)
+        else:
+            tr = S.lissajous(t, ax=0.85, ay=0.85, t0=0.2, t1=0.75)
+        specs.append(dict(n=n, h=S.h_fwhm2(n) * (0.9 + 0.05 * i), R=R, r=rounded(tr.r, torch.float32),
+                          v=rounded(tr.v, torch.float32), c=rounded(S.ellipses_and_line(n, 1000 + i), torch.float32),
+                          mode=mode))
+    return specs
+
+
+def _build(specs, tune=False, modes=True):
+    return mpik.Batch([(sp["n"], sp["h"], sp["R"], dev(sp["r"], torch.float32), dev(sp["v"], torch.float32),
+                        sp["mode"] if modes else "auto") for sp in specs], tune=tune)
+
+
+def _c_all(batch, specs):
+    return torch.cat([dev(sp["c"], torch.float32).reshape(-1) for sp in specs])
+
+
+def test_batch_equals_single_plans():
+    specs = _small_batch()
+    batch = _build(specs)
+    c_all = _c_all(batch, specs)
+    s_all = batch.forward(c_all)
+    rng = np.random.default_rng(0)
+    y_all = dev(rounded(rng.standard_normal(batch.s_offsets[-1]), torch.float32), torch.float32)
+    g_all = batch.adjoint(y_all)
+    torch.cuda.synchronize()
+    for b, sp in enumerate(specs):
+        plan = mpik.Plan(sp["n"], sp["h"], sp["R"], dev(sp["r"], torch.float32), dev(sp["v"], torch.float32),
+                         conv_mode=sp["mode"])
+        assert batch.info[b]["conv_mode"] == sp["mode"] == plan.conv_mode
+        s1 = plan.forward(dev(sp["c"], torch.float32))
+        g1 = plan.adjoint(batch.s_views(y_all)[b].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(batch.s_views(s_all)[b], s1), b
+        assert torch.equal(batch.c_views(g_all)[b], g1), b
+
+
+def test_batch_matches_oracle():
+    specs = _small_batch()
+    batch = _build(specs)
+    c_all = _c_all(batch, specs)
+    s_all = batch.forward(c_all)
+    rng = np.random.default_rng(1)
+    y = rounded(rng.standard_normal(batch.s_offsets[-1]), torch.float32)
+    g_all = batch.adjoint(dev(y, torch.float32))
+    torch.cuda.synchronize()
+    for b, sp in enumerate(specs):
+        M = O.Model(sp["n"], sp["h"], sp["R"], sp["r"], sp["v"])
+        s_ref = M.forward(sp["c"])
+        assert rel_l2(batch.s_views(s_all)[b].double().cpu().numpy(), s_ref) <= 1e-5
+        yb = y[batch.s_offsets[b]:batch.s_offsets[b + 1]].reshape(-1, 2)
+        g_ref = M.adjoint(yb)
+        assert rel_l2(batch.c_views(g_all)[b].double().cpu().numpy(), g_ref) <= 1e-5
+
+
+@pytest.mark.parametrize("denoise", [False, True])
+def test_batch_iterate_matches_oracle(denoise):
+    specs = _small_batch()[:4]
+    batch = _build(specs)
+    taus, s_list, models = [], [], []
+    for sp in specs:
+        M = O.Model(sp["n"], sp["h"], sp["R"], sp["r"], sp["v"])
+        models.append(M)
+        s_list.append(rounded(S.add_noise(M.forward(sp["c"]), 20.0, seed=1), torch.float32))
+        taus.append(0.9 / O.power_lambda_max(M, iters=30))
+    s_all = torch.cat([dev(s, torch.float32).reshape(-1) for s in s_list])
+    c_all = torch.zeros(batch.c_offsets[-1], dtype=torch.float32, device="cuda")
+    n_iter = 12
+    sigma = 0.5 if denoise else 0.0
+    batch.iterate(s_all, c_all, n_iter, taus, denoise_sigma_px=sigma, denoise_radius=2)
+    torch.cuda.synchronize()
+    for b, sp in enumerate(specs):
+        ref = O.iterate(models[b], s_list[b], np.zeros((sp["n"], sp["n"])), taus[b], n_iter,
+                        sigma_px=0.5 if denoise else None, radius=2)
+        assert rel_l2(batch.c_views(c_all)[b].double().cpu().numpy(), ref) <= 1e-4, b
+
+
+def test_uneven_batch_of_64_with_tuning():
+    """64 problems: N from {64,...,256}, 10k-120k samples, Lissajous /
+    perturbed / partial, h within +-20%, window R = 31; the autotuner picks the
+    path per shape.  Every problem's forward and transpose match the oracle."""
+    probs = S.batch_problems(64)
+    specs = [dict(n=P.n, h=P.h, R=P.radius, r=rounded(P.traj.r, torch.float32), v=rounded(P.traj.v, torch.float32),
+                  c=rounded(P.c, torch.float32), mode="auto") for P in probs]
+    batch = _build(specs, tune=True, modes=False)
+    c_all = _c_all(batch, specs)
+    s_all = batch.forward(c_all)
+    g_all = batch.adjoint(s_all)
+    torch.cuda.synchronize()
+    sv, gv = batch.s_views(s_all), batch.c_views(g_all)
+    for b, sp in enumerate(specs):
+        M = O.Model(sp["n"], sp["h"], sp["R"], sp["r"], sp["v"])
+        s_ref = M.forward(sp["c"])
+        s_got = sv[b].double().cpu().numpy()
+        assert rel_l2(s_got, s_ref) <= 1e-5, (b, batch.info[b])
+        g_ref = M.adjoint(rounded(s_got, torch.float32))
+        assert rel_l2(gv[b].double().cpu().numpy(), g_ref) <= 1e-5, (b, batch.info[b])
