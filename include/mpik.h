@@ -147,6 +147,12 @@ int mpi_plan_info(const mpi_plan* plan, int32_t* radius, int32_t* fft_size, int3
  * `stream`.  Choices are cached per (dtype, N, R, log2 T) in the process and
  * appended to the file named by the environment variable MPIK_TUNE_CACHE. */
 enum { MPI_BUILD_TUNE = 1 };
+/* Shape of the column-FFT kernels: by default three waves share a column
+ * when the plan holds one or two problems (shortest latency) and one wave
+ * owns a column otherwise (most columns in flight).  These flags force one
+ * shape.  Both compute the same values; they may differ in the last bit
+ * because the channel sum is contracted into multiply-adds differently. */
+enum { MPI_BUILD_COL_SPLIT = 2, MPI_BUILD_COL_WAVE = 4 };
 
 int mpi_batch_bytes(const mpi_problem* probs, int count, size_t* plan_bytes, size_t* work_bytes);
 int mpi_batch_build(const mpi_problem* probs, int count, void* plan_mem, size_t plan_bytes,

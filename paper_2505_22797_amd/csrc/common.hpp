@@ -77,15 +77,22 @@ template <typename P> __device__ __forceinline__ const P* at(const char* base, i
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // ---------------------------------------------------------------------------
-// Stockham autosort FFT of one line of M points held in LDS, executed by a
-// 64-lane wavefront.  Mixed radix 8/4/2: a pass of radix R with span Ns takes
-// butterfly j (j < M/R) from in[j + r M/R], applies the twiddle
-// w^(r (j mod Ns) M/(Ns R)), does a length-R DFT and writes to
-// out[(j / Ns) Ns R + (j mod Ns) + r Ns]; the result comes out in natural
-// order.  Forward uses e^{-2 pi i/M}, inverse the conjugate; no scaling.
-// All waves of the work-group must call it together (it uses __syncthreads);
-// `active` selects the waves that do arithmetic.
+// Stockham autosort FFT of one line of M points held in LDS, done in place by
+// one 64-lane wavefront with no work-group barrier.  Mixed radix 8 (then 4 or
+// 2 for the remaining factor): a pass of radix R with span Ns takes butterfly
+// j (j < M/R) from line[j + r M/R], applies the twiddle w^(r (j mod Ns)
+// M/(Ns R)), does a length-R DFT and writes line[(j / Ns) Ns R + (j mod Ns)
+// + r Ns]; the result comes out in natural order.  Every lane reads all of its
+// butterfly inputs before any lane writes (a wave executes its LDS operations
+// in order), so one buffer suffices.  Forward uses w = e^{-2 pi i/M}, inverse
+// the conjugate; no scaling.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T, bool INV>
 __device__ __forceinline__ void dft2(cx<T>* v) {
     cx<T> a = v[0], b = v[1];
@@ -124,65 +131,54 @@ __device__ __forceinline__ void dft8(cx<T>* v) {
     v[3] = cadd(e3, t3); v[7] = csub(e3, t3);
 }
 
-template <typename T, bool INV, int R>
-__device__ __forceinline__ void stockham_pass(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-                                              const cx<T>* __restrict__ tw, int M, int Ns, int lane) {
-    const int nb = M / R;
-    const int step = M / (Ns * R);
-    for (int j = lane; j < nb; j += kWave) {
-        const int k = j % Ns;
-        cx<T> v[R];
+template <typename T, bool INV, int R, int M, int NS>
+__device__ __forceinline__ void fft_pass(cx<T>* line, const cx<T>* __restrict__ tw, int lane) {
+    constexpr int NB = M / R;                       // butterflies in the pass
+    constexpr int PER = (NB + kWave - 1) / kWave;   // butterflies per lane
+    constexpr int STEP = M / (NS * R);
+    cx<T> v[PER][R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = in[j + r * nb];
-        if (Ns > 1) {
+    for (int q = 0; q < PER; ++q) {
+        const int j = lane + q * kWave;
+        if (NB % kWave == 0 || j < NB) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                cx<T> w = tw[(r * k * step) & (M - 1)];
-                if (INV) w.y = -w.y;
-                v[r] = cmul(v[r], w);
-            }
+            for (int r = 0; r < R; ++r) v[q][r] = line[j + r * NB];
         }
-        if (R == 8) dft8<T, INV>(v);
-        else if (R == 4) dft4<T, INV>(v);
-        else dft2<T, INV>(v);
-        const int base = (j / Ns) * Ns * R + k;
-#pragma unroll
-        for (int r = 0; r < R; ++r) out[base + r * Ns] = v[r];
     }
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = lane + q * kWave;
+        if (NB % kWave == 0 || j < NB) {
+            const int k = j & (NS - 1);
+            if (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cx<T> w = tw[r * k * STEP];
+                    if (INV) w.y = -w.y;
+                    v[q][r] = cmul(v[q][r], w);
+                }
+            }
+            if (R == 8) dft8<T, INV>(v[q]);
+            else if (R == 4) dft4<T, INV>(v[q]);
+            else dft2<T, INV>(v[q]);
+            const int base = (j / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) line[base + r * NS] = v[q][r];
+        }
+    }
+    wave_sync();
 }
 
-// Returns the buffer that holds the result (a or b).
-template <typename T, bool INV, int M>
-__device__ __forceinline__ cx<T>* fft_line(cx<T>* a, cx<T>* b, const cx<T>* tw, int lane, bool active) {
+template <typename T, bool INV, int M, int NS = 1>
+__device__ __forceinline__ void fft_wave(cx<T>* line, const cx<T>* __restrict__ tw, int lane) {
     static_assert(M >= 64 && (M & (M - 1)) == 0, "M must be a power of two >= 64");
-    constexpr int L = __builtin_ctz(M);
-    constexpr int n8 = L / 3;
-    constexpr int rem = L % 3;   // 0, 1 (radix 2) or 2 (radix 4)
-    cx<T>* in = a;
-    cx<T>* out = b;
-    int Ns = 1;
-#pragma unroll
-    for (int p = 0; p < n8; ++p) {
-        if (active) stockham_pass<T, INV, 8>(in, out, tw, M, Ns, lane);
-        __syncthreads();
-        cx<T>* t = in; in = out; out = t;
-        Ns *= 8;
+    if constexpr (NS < M) {
+        constexpr int REM = M / NS;
+        constexpr int R = (REM % 8 == 0) ? 8 : REM;
+        fft_pass<T, INV, R, M, NS>(line, tw, lane);
+        fft_wave<T, INV, M, NS * R>(line, tw, lane);
     }
-    if (rem == 2) {
-        if (active) stockham_pass<T, INV, 4>(in, out, tw, M, Ns, lane);
-        __syncthreads();
-        cx<T>* t = in; in = out; out = t;
-    } else if (rem == 1) {
-        if (active) stockham_pass<T, INV, 2>(in, out, tw, M, Ns, lane);
-        __syncthreads();
-        cx<T>* t = in; in = out; out = t;
-    }
-    return in;
 }
-
-template <int M> struct FftPasses {
-    static constexpr int L = __builtin_ctz(M);
-    static constexpr int count = L / 3 + (L % 3 != 0);
-};
 
 }  // namespace mpik

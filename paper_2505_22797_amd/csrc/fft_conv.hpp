@@ -19,24 +19,29 @@
 //              channel spectra, one inverse column FFT cropped to N rows
 //   adj_rows : per pair of rows: inverse row FFT -> c, with an optional fused
 //              gradient-step epilogue.
-// Work-groups are one to three 64-lane waves; each wave owns one FFT line.
+// Every FFT line belongs to one 64-lane wave (in place in LDS, no work-group
+// barrier inside the transform).  The column stages come in two shapes: SPLIT
+// spreads one column over three waves (shortest latency for few problems);
+// otherwise each wave owns a whole column (four columns per work-group, most
+// columns in flight for large batches).
 #pragma once
 #include "common.hpp"
 #include "sampling.hpp"
 
 namespace mpik {
 
-template <typename T, int M> struct RowSmem {      // fwd_rows, adj_rows: one wave
+template <typename T, int M> struct RowSmem {      // fwd_rows, adj_rows: four waves, a row pair each
     cx<T> tw[M];
-    cx<T> buf[2][M];
+    cx<T> line[4][M];
 };
-template <typename T, int M> struct ColSmem {      // fwd_cols, adj_cols: three waves
+template <typename T, int M> struct ColSmem {      // column stages: four lines + a shared one
     cx<T> tw[M];
-    cx<T> buf[8][M];
+    cx<T> c[M];
+    cx<T> line[4][M];
 };
-template <typename T, int M> struct GatherSmem {   // fwd_rows_gather: three waves
+template <typename T, int M> struct GatherSmem {   // fwd_rows_gather: three FFT waves, four gather waves
     cx<T> tw[M];
-    cx<T> buf[6][M];
+    cx<T> line[3][M];
     T g[6 * M];
 };
 template <typename T, int M> struct ScatterRowSmem {   // adj_scatter_row: four waves
@@ -44,7 +49,7 @@ template <typename T, int M> struct ScatterRowSmem {   // adj_scatter_row: four 
     T g[3 * M];
     union {                     // the sampling transpose and the row FFTs run one after the other
         ScatterSmem<T, 256, M> sc;
-        cx<T> buf[4][M];
+        cx<T> line[2][M];
     };
 };
 
@@ -65,7 +70,7 @@ __device__ __forceinline__ T spec_at(const T* __restrict__ spec, int ch, int kx,
 }
 
 // Full-length spectrum Z = A + iB of the complex row a + ib from the half
-// spectra A, B of two real rows.
+// spectra A, B of two real rows (B = 0 when `two` is false).
 template <typename T, int M>
 __device__ __forceinline__ cx<T> pair_spectrum(const cx<T>* __restrict__ ra, const cx<T>* __restrict__ rb,
                                                int kx, bool two) {
@@ -97,11 +102,15 @@ __device__ void fwd_rows_body(const Prob& p, const T* __restrict__ c, const char
                               char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<RowSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
-    const int N = p.n, q = blockIdx.x, lane = threadIdx.x;
+    const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    if (2 * 4 * int(blockIdx.x) >= N) return;
+    load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
+    __syncthreads();
+    const int q = 4 * blockIdx.x + wave;
     const int r0 = 2 * q, r1 = 2 * q + 1;
     if (r0 >= N) return;
     const bool two = r1 < N;
-    load_twiddles<T, M>(sm.tw, plan, p, lane, kWave);
+    cx<T>* line = sm.line[wave];
     const T* c0 = c + int64_t(r0) * N;
     const T* c1 = c + int64_t(r1) * N;
     for (int i = lane; i < M; i += kWave) {
@@ -110,38 +119,72 @@ __device__ void fwd_rows_body(const Prob& p, const T* __restrict__ c, const char
             z.x = c0[i];
             if (two) z.y = c1[i];
         }
-        sm.buf[0][i] = z;
+        line[i] = z;
     }
-    __syncthreads();
-    const cx<T>* Z = fft_line<T, false, M>(sm.buf[0], sm.buf[1], sm.tw, lane, true);
+    wave_sync();
+    fft_wave<T, false, M>(line, sm.tw, lane);
     cx<T>* t1 = at<cx<T>>(work, p.w_t1);
     for (int k = lane; k < H; k += kWave) {
         cx<T> A, B;
-        split_pair<T, M>(Z, k, A, B);
+        split_pair<T, M>(line, k, A, B);
         t1[int64_t(k) * N + r0] = A;
         if (two) t1[int64_t(k) * N + r1] = B;
     }
 }
 
-template <typename T, int M>
+// Column kx: forward column FFT of T1[kx][.] (zero-padded), then for each
+// channel the product with its spectrum, the inverse FFT and rows 0..N-1 of
+// the result to T2[ch][row][kx].
+template <typename T, int M, bool SPLIT>
 __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<ColSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
-    const int N = p.n, kx = blockIdx.x;
-    if (kx >= H) return;
-    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    load_twiddles<T, M>(sm.tw, plan, p, tid, 3 * kWave);
-    const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(kx) * N;
-    for (int i = tid; i < M; i += 3 * kWave) sm.buf[0][i] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
-    __syncthreads();
-    const cx<T>* C = fft_line<T, false, M>(sm.buf[0], sm.buf[1], sm.tw, lane, wave == 0);
+    const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const T* spec = at<T>(plan, p.o_spec);
-    cx<T>* a = sm.buf[2 + 2 * wave];
-    for (int ky = lane; ky < M; ky += kWave) a[ky] = cscale(C[ky], spec_at<T, M>(spec, wave, kx, ky));
-    __syncthreads();
-    const cx<T>* G = fft_line<T, true, M>(a, sm.buf[3 + 2 * wave], sm.tw, lane, true);
-    cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(wave) * N * H;
-    for (int j = lane; j < N; j += kWave) t2[int64_t(j) * H + kx] = G[j];
+    cx<T>* t2 = at<cx<T>>(work, p.w_t2);
+    if (SPLIT) {                                    // one column, waves 0..2
+        const int kx = blockIdx.x;
+        if (kx >= H) return;
+        load_twiddles<T, M>(sm.tw, plan, p, tid, 3 * kWave);
+        const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(kx) * N;
+        for (int i = tid; i < M; i += 3 * kWave) sm.c[i] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+        __syncthreads();
+        if (wave == 0) fft_wave<T, false, M>(sm.c, sm.tw, lane);
+        __syncthreads();
+        cx<T>* line = sm.line[wave];
+        for (int ky = lane; ky < M; ky += kWave) line[ky] = cscale(sm.c[ky], spec_at<T, M>(spec, wave, kx, ky));
+        wave_sync();
+        fft_wave<T, true, M>(line, sm.tw, lane);
+        cx<T>* out = t2 + int64_t(wave) * N * H;
+        for (int j = lane; j < N; j += kWave) out[int64_t(j) * H + kx] = line[j];
+    } else {                                        // four columns, one per wave
+        if (4 * int(blockIdx.x) >= H) return;
+        load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
+        __syncthreads();
+        const int kx = 4 * blockIdx.x + wave;
+        if (kx >= H) return;
+        cx<T>* line = sm.line[wave];
+        const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(kx) * N;
+        for (int i = lane; i < M; i += kWave) line[i] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+        wave_sync();
+        fft_wave<T, false, M>(line, sm.tw, lane);
+        constexpr int PL = M / kWave;
+        cx<T> cr[PL];
+#pragma unroll
+        for (int i = 0; i < PL; ++i) cr[i] = line[lane + i * kWave];
+        for (int ch = 0; ch < 3; ++ch) {
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < PL; ++i) {
+                const int ky = lane + i * kWave;
+                line[ky] = cscale(cr[i], spec_at<T, M>(spec, ch, kx, ky));
+            }
+            wave_sync();
+            fft_wave<T, true, M>(line, sm.tw, lane);
+            cx<T>* out = t2 + int64_t(ch) * N * H;
+            for (int j = lane; j < N; j += kWave) out[int64_t(j) * H + kx] = line[j];
+        }
+    }
 }
 
 template <typename T, int M, bool RESID>
@@ -155,23 +198,26 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ s, const cha
     const int p0 = binstart[b * nb], p1 = binstart[(b + 1) * nb];
     if (p0 == p1) return;
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    load_twiddles<T, M>(sm.tw, plan, p, tid, 3 * kWave);
-    const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(wave) * N * H;
-    const cx<T>* ra = t2 + int64_t(b) * H;
-    const cx<T>* rb = t2 + int64_t(b + 1) * H;
-    cx<T>* a = sm.buf[2 * wave];
-    for (int kx = lane; kx < M; kx += kWave) a[kx] = pair_spectrum<T, M>(ra, rb, kx, true);
+    load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
     __syncthreads();
-    const cx<T>* Gz = fft_line<T, true, M>(a, sm.buf[2 * wave + 1], sm.tw, lane, true);
     T* g0 = sm.g;            // row b:   [ch][N]
     T* g1 = sm.g + 3 * N;    // row b+1: [ch][N]
-    for (int i = lane; i < N; i += kWave) {
-        g0[wave * N + i] = Gz[i].x;
-        g1[wave * N + i] = Gz[i].y;
+    if (wave < 3) {
+        const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(wave) * N * H;
+        const cx<T>* ra = t2 + int64_t(b) * H;
+        const cx<T>* rb = t2 + int64_t(b + 1) * H;
+        cx<T>* line = sm.line[wave];
+        for (int kx = lane; kx < M; kx += kWave) line[kx] = pair_spectrum<T, M>(ra, rb, kx, true);
+        wave_sync();
+        fft_wave<T, true, M>(line, sm.tw, lane);
+        for (int i = lane; i < N; i += kWave) {
+            g0[wave * N + i] = line[i].x;
+            g1[wave * N + i] = line[i].y;
+        }
     }
     __syncthreads();
     gather_band<T, RESID>(g0, g1, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
-                          at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res), s, tid, 3 * kWave);
+                          at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res), s, tid, 4 * kWave);
 }
 
 // ----------------------------------------------------------------- adjoint ---
@@ -190,64 +236,89 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
     load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
     scatter_row<T, SORTED, 256, M>(sm.g, sm.sc, N, j, at<int>(plan, p.o_binstart), at<vec4<T>>(plan, p.o_samp),
                                    at<int2>(plan, p.o_sidx), at<vec2<T>>(work, p.w_res), s, tid);
-    const bool active = wave < 2;
-    cx<T>* a = sm.buf[2 * (wave & 1)];
-    if (active) {
-        const T* re = sm.g + (wave == 0 ? 0 : 2 * N);
-        const T* im = sm.g + N;
-        for (int i = lane; i < M; i += kWave) {
-            cx<T> z{T(0), T(0)};
-            if (i < N) {
-                z.x = re[i];
-                if (wave == 0) z.y = im[i];
-            }
-            a[i] = z;
+    if (wave >= 2) return;
+    cx<T>* line = sm.line[wave];
+    const T* re = sm.g + (wave == 0 ? 0 : 2 * N);
+    const T* im = sm.g + N;
+    for (int i = lane; i < M; i += kWave) {
+        cx<T> z{T(0), T(0)};
+        if (i < N) {
+            z.x = re[i];
+            if (wave == 0) z.y = im[i];
         }
+        line[i] = z;
     }
-    __syncthreads();
-    const cx<T>* Z = fft_line<T, false, M>(a, sm.buf[2 * (wave & 1) + 1], sm.tw, lane, active);
-    if (!active) return;
+    wave_sync();
+    fft_wave<T, false, M>(line, sm.tw, lane);
     cx<T>* t1 = at<cx<T>>(work, p.w_t1);
     for (int k = lane; k < H; k += kWave) {
         if (wave == 0) {
             cx<T> A, B;
-            split_pair<T, M>(Z, k, A, B);
+            split_pair<T, M>(line, k, A, B);
             t1[int64_t(k) * N + j] = A;
             t1[(int64_t(H) + k) * N + j] = B;
         } else {
-            t1[(int64_t(2) * H + k) * N + j] = Z[k];
+            t1[(int64_t(2) * H + k) * N + j] = line[k];
         }
     }
 }
 
-template <typename T, int M>
+// Column kx: forward FFTs of the three channels' columns, sum of the
+// products with the channel spectra in the fixed order xx, xy, yy, one
+// inverse FFT, rows 0..N-1 to T2[row][kx].
+template <typename T, int M, bool SPLIT>
 __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<ColSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
-    constexpr int par = FftPasses<M>::count & 1;    // result of a line lands in buf[2w + par]
-    const int N = p.n, kx = blockIdx.x;
-    if (kx >= H) return;
-    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    load_twiddles<T, M>(sm.tw, plan, p, tid, 3 * kWave);
-    const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + (int64_t(wave) * H + kx) * N;
-    cx<T>* a = sm.buf[2 * wave];
-    for (int i = lane; i < M; i += kWave) a[i] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
-    __syncthreads();
-    cx<T>* C = fft_line<T, false, M>(a, sm.buf[2 * wave + 1], sm.tw, lane, true);
+    const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const T* spec = at<T>(plan, p.o_spec);
-    for (int ky = lane; ky < M; ky += kWave) C[ky] = cscale(C[ky], spec_at<T, M>(spec, wave, kx, ky));
-    __syncthreads();
-    // fixed-order channel sum (xx + xy) + yy into wave 0's free line
-    const cx<T>* C0 = sm.buf[par];
-    const cx<T>* C1 = sm.buf[2 + par];
-    const cx<T>* C2 = sm.buf[4 + par];
-    cx<T>* X = sm.buf[1 - par];
-    cx<T>* Y = sm.buf[6];
-    for (int ky = tid; ky < M; ky += 3 * kWave) X[ky] = cadd(cadd(C0[ky], C1[ky]), C2[ky]);
-    __syncthreads();
-    const cx<T>* Cc = fft_line<T, true, M>(X, Y, sm.tw, lane, wave == 0);
     cx<T>* t2 = at<cx<T>>(work, p.w_t2);
-    for (int j = tid; j < N; j += 3 * kWave) t2[int64_t(j) * H + kx] = Cc[j];
+    if (SPLIT) {                                    // one column, waves 0..2
+        const int kx = blockIdx.x;
+        if (kx >= H) return;
+        load_twiddles<T, M>(sm.tw, plan, p, tid, 3 * kWave);
+        __syncthreads();
+        cx<T>* line = sm.line[wave];
+        const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + (int64_t(wave) * H + kx) * N;
+        for (int i = lane; i < M; i += kWave) line[i] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+        wave_sync();
+        fft_wave<T, false, M>(line, sm.tw, lane);
+        for (int ky = lane; ky < M; ky += kWave) line[ky] = cscale(line[ky], spec_at<T, M>(spec, wave, kx, ky));
+        __syncthreads();
+        for (int ky = tid; ky < M; ky += 3 * kWave)
+            sm.c[ky] = cadd(cadd(sm.line[0][ky], sm.line[1][ky]), sm.line[2][ky]);
+        __syncthreads();
+        if (wave != 0) return;
+        fft_wave<T, true, M>(sm.c, sm.tw, lane);
+        for (int j = lane; j < N; j += kWave) t2[int64_t(j) * H + kx] = sm.c[j];
+    } else {                                        // four columns, one per wave
+        if (4 * int(blockIdx.x) >= H) return;
+        load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
+        __syncthreads();
+        const int kx = 4 * blockIdx.x + wave;
+        if (kx >= H) return;
+        cx<T>* line = sm.line[wave];
+        constexpr int PL = M / kWave;
+        cx<T> acc[PL];
+        for (int ch = 0; ch < 3; ++ch) {
+            const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + (int64_t(ch) * H + kx) * N;
+            for (int i = lane; i < M; i += kWave) line[i] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+            wave_sync();
+            fft_wave<T, false, M>(line, sm.tw, lane);
+#pragma unroll
+            for (int i = 0; i < PL; ++i) {
+                const int ky = lane + i * kWave;
+                const cx<T> v = cscale(line[ky], spec_at<T, M>(spec, ch, kx, ky));
+                acc[i] = ch == 0 ? v : cadd(acc[i], v);
+            }
+            wave_sync();
+        }
+#pragma unroll
+        for (int i = 0; i < PL; ++i) line[lane + i * kWave] = acc[i];
+        wave_sync();
+        fft_wave<T, true, M>(line, sm.tw, lane);
+        for (int j = lane; j < N; j += kWave) t2[int64_t(j) * H + kx] = line[j];
+    }
 }
 
 // EPI 0: c_out = A^T s;  1, 2: c_out = c_in - tau * A^T r (c_in may alias c_out)
@@ -256,19 +327,23 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau,
                               const char* __restrict__ plan, char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<RowSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
-    const int N = p.n, q = blockIdx.x, lane = threadIdx.x;
+    const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    if (2 * 4 * int(blockIdx.x) >= N) return;
+    load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
+    __syncthreads();
+    const int q = 4 * blockIdx.x + wave;
     const int r0 = 2 * q, r1 = 2 * q + 1;
     if (r0 >= N) return;
     const bool two = r1 < N;
-    load_twiddles<T, M>(sm.tw, plan, p, lane, kWave);
     const cx<T>* t2 = at<cx<T>>(work, p.w_t2);
     const cx<T>* ra = t2 + int64_t(r0) * H;
     const cx<T>* rb = t2 + int64_t(two ? r1 : r0) * H;
-    for (int kx = lane; kx < M; kx += kWave) sm.buf[0][kx] = pair_spectrum<T, M>(ra, rb, kx, two);
-    __syncthreads();
-    const cx<T>* z = fft_line<T, true, M>(sm.buf[0], sm.buf[1], sm.tw, lane, true);
+    cx<T>* line = sm.line[wave];
+    for (int kx = lane; kx < M; kx += kWave) line[kx] = pair_spectrum<T, M>(ra, rb, kx, two);
+    wave_sync();
+    fft_wave<T, true, M>(line, sm.tw, lane);
     for (int i = lane; i < N; i += kWave) {
-        const T v0 = z[i].x, v1 = z[i].y;
+        const T v0 = line[i].x, v1 = line[i].y;
         const int64_t o0 = int64_t(r0) * N + i, o1 = int64_t(r1) * N + i;
         if (EPI == 0) {
             c_out[o0] = v0;
@@ -281,36 +356,39 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau,
 }
 
 // ------------------------------------------------------------- launchers ---
-#define MPIK_DISPATCH_M(M_, BODY)                         \
-    switch (M_) {                                         \
-        case 64: { constexpr int MM = 64; BODY; } break;  \
-        case 128: { constexpr int MM = 128; BODY; } break; \
-        case 256: { constexpr int MM = 256; BODY; } break; \
-        case 512: { constexpr int MM = 512; BODY; } break; \
+#define MPIK_DISPATCH_M(M_, BODY)                            \
+    switch (M_) {                                            \
+        case 64: { constexpr int MM = 64; BODY; } break;     \
+        case 128: { constexpr int MM = 128; BODY; } break;   \
+        case 256: { constexpr int MM = 256; BODY; } break;   \
+        case 512: { constexpr int MM = 512; BODY; } break;   \
         case 1024: { constexpr int MM = 1024; BODY; } break; \
-        default: break;                                   \
+        default: break;                                      \
     }
 
+// grid.x: ceil(row pairs / 4), grid.y: problem; 256 threads
 template <typename T>
-__global__ void __launch_bounds__(64) k_fwd_rows(const Prob* __restrict__ P, const T* __restrict__ c,
-                                                 const char* __restrict__ plan, char* __restrict__ work) {
+__global__ void __launch_bounds__(256) k_fwd_rows(const Prob* __restrict__ P, const T* __restrict__ c,
+                                                  const char* __restrict__ plan, char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
     if (p.mode != 1) return;
     MPIK_DISPATCH_M(p.m, (fwd_rows_body<T, MM>(p, c + p.o_c, plan, work, smem)));
 }
 
-template <typename T>
-__global__ void __launch_bounds__(192) k_fwd_cols(const Prob* __restrict__ P, const char* __restrict__ plan,
+// SPLIT: grid.x = M/2 + 1, 192 threads; else grid.x = ceil((M/2 + 1)/4), 256 threads
+template <typename T, bool SPLIT>
+__global__ void __launch_bounds__(256) k_fwd_cols(const Prob* __restrict__ P, const char* __restrict__ plan,
                                                   char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
     if (p.mode != 1) return;
-    MPIK_DISPATCH_M(p.m, (fwd_cols_body<T, MM>(p, plan, work, smem)));
+    MPIK_DISPATCH_M(p.m, (fwd_cols_body<T, MM, SPLIT>(p, plan, work, smem)));
 }
 
+// grid.x: base-cell rows, 256 threads
 template <typename T, bool RESID>
-__global__ void __launch_bounds__(192) k_fwd_rows_gather(const Prob* __restrict__ P, T* __restrict__ s,
+__global__ void __launch_bounds__(256) k_fwd_rows_gather(const Prob* __restrict__ P, T* __restrict__ s,
                                                          const char* __restrict__ plan, char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
@@ -318,6 +396,7 @@ __global__ void __launch_bounds__(192) k_fwd_rows_gather(const Prob* __restrict_
     MPIK_DISPATCH_M(p.m, (fwd_rows_gather_body<T, MM, RESID>(p, s + p.o_s, plan, work, smem)));
 }
 
+// grid.x: grid rows, 256 threads
 template <typename T, bool SORTED>
 __global__ void __launch_bounds__(256) k_adj_scatter_row(const Prob* __restrict__ P, const T* __restrict__ s,
                                                          const char* __restrict__ plan, char* __restrict__ work) {
@@ -327,19 +406,21 @@ __global__ void __launch_bounds__(256) k_adj_scatter_row(const Prob* __restrict_
     MPIK_DISPATCH_M(p.m, (adj_scatter_row_body<T, MM, SORTED>(p, s + p.o_s, plan, work, smem)));
 }
 
-template <typename T>
-__global__ void __launch_bounds__(192) k_adj_cols(const Prob* __restrict__ P, const char* __restrict__ plan,
+// SPLIT: grid.x = M/2 + 1, 192 threads; else grid.x = ceil((M/2 + 1)/4), 256 threads
+template <typename T, bool SPLIT>
+__global__ void __launch_bounds__(256) k_adj_cols(const Prob* __restrict__ P, const char* __restrict__ plan,
                                                   char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
     if (p.mode != 1) return;
-    MPIK_DISPATCH_M(p.m, (adj_cols_body<T, MM>(p, plan, work, smem)));
+    MPIK_DISPATCH_M(p.m, (adj_cols_body<T, MM, SPLIT>(p, plan, work, smem)));
 }
 
+// grid.x: ceil(row pairs / 4), 256 threads
 template <typename T, int EPI>
-__global__ void __launch_bounds__(64) k_adj_rows(const Prob* __restrict__ P, T* c_out, const T* c_in,
-                                                 const double* __restrict__ taus, const char* __restrict__ plan,
-                                                 char* __restrict__ work) {
+__global__ void __launch_bounds__(256) k_adj_rows(const Prob* __restrict__ P, T* c_out, const T* c_in,
+                                                  const double* __restrict__ taus, const char* __restrict__ plan,
+                                                  char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
     if (p.mode != 1) return;

@@ -257,7 +257,9 @@ struct mpi_plan {
     size_t smem_row = 0, smem_col = 0, smem_gather = 0, smem_scatter = 0, smem_dfwd = 0, smem_dadj = 0,
            smem_dgather = 0, smem_dscatter = 0;
     bool any_fft = false, any_direct = false;
-    int slice_mask = 0;   // bit i: some direct problem uses kSliceChoices[i]
+    bool col_split = true;   // column stages: three waves per column (few problems) or a wave per column
+    int col_force = 0;       // 1: always split, 2: always a wave per column, 0: by batch size
+    int slice_mask = 0;      // bit i: some direct problem uses kSliceChoices[i]
     // cached iteration graph
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -282,6 +284,7 @@ void finalize_extents(mpi_plan* pl) {
     pl->smem_dfwd = pl->smem_dadj = pl->smem_dgather = pl->smem_dscatter = 0;
     pl->any_fft = pl->any_direct = false;
     pl->slice_mask = 0;
+    pl->col_split = pl->col_force ? pl->col_force == 1 : pl->count <= 2;
     const int e = pl->L.elem;
     for (const Prob& p : pl->L.probs) {
         pl->max_n = std::max(pl->max_n, p.n);
@@ -314,8 +317,10 @@ hipError_t set_smem_limits(const mpi_plan* pl) {
     hipError_t e = hipSuccess;
     auto chk = [&e](hipError_t x) { if (x != hipSuccess) e = x; };
     chk(allow_smem(k_fwd_rows<T>, pl->smem_row));
-    chk(allow_smem(k_fwd_cols<T>, pl->smem_col));
-    chk(allow_smem(k_adj_cols<T>, pl->smem_col));
+    chk(allow_smem(k_fwd_cols<T, true>, pl->smem_col));
+    chk(allow_smem(k_fwd_cols<T, false>, pl->smem_col));
+    chk(allow_smem(k_adj_cols<T, true>, pl->smem_col));
+    chk(allow_smem(k_adj_cols<T, false>, pl->smem_col));
     chk(allow_smem(k_fwd_rows_gather<T, false>, pl->smem_gather));
     chk(allow_smem(k_fwd_rows_gather<T, true>, pl->smem_gather));
     chk(allow_smem(k_adj_scatter_row<T, false>, pl->smem_scatter));
@@ -411,9 +416,14 @@ void fwd_stage(const mpi_plan* pl, int k, const T* c, T* s, char* work, hipStrea
     if (k <= 2 && !pl->any_fft) return;
     if (k >= 3 && !pl->any_direct) return;
     switch (k) {
-        case 0: k_fwd_rows<T><<<dim3(pl->max_rowpairs, B), 64, pl->smem_row, st>>>(P, c, plan, work); break;
-        case 1: k_fwd_cols<T><<<dim3(pl->max_h, B), 192, pl->smem_col, st>>>(P, plan, work); break;
-        case 2: k_fwd_rows_gather<T, RESID><<<dim3(pl->max_nb, B), 192, pl->smem_gather, st>>>(P, s, plan, work); break;
+        case 0:
+            k_fwd_rows<T><<<dim3((pl->max_rowpairs + 3) / 4, B), 256, pl->smem_row, st>>>(P, c, plan, work);
+            break;
+        case 1:
+            if (pl->col_split) k_fwd_cols<T, true><<<dim3(pl->max_h, B), 192, pl->smem_col, st>>>(P, plan, work);
+            else k_fwd_cols<T, false><<<dim3((pl->max_h + 3) / 4, B), 256, pl->smem_col, st>>>(P, plan, work);
+            break;
+        case 2: k_fwd_rows_gather<T, RESID><<<dim3(pl->max_nb, B), 256, pl->smem_gather, st>>>(P, s, plan, work); break;
         case 3:
             launch_direct_conv<T, 4, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st);
             launch_direct_conv<T, 8, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st);
@@ -437,9 +447,13 @@ void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, c
     if (k >= 3 && !pl->any_direct) return;
     switch (k) {
         case 0: k_adj_scatter_row<T, SORTED><<<dim3(pl->max_n, B), 256, pl->smem_scatter, st>>>(P, s, plan, work); break;
-        case 1: k_adj_cols<T><<<dim3(pl->max_h, B), 192, pl->smem_col, st>>>(P, plan, work); break;
+        case 1:
+            if (pl->col_split) k_adj_cols<T, true><<<dim3(pl->max_h, B), 192, pl->smem_col, st>>>(P, plan, work);
+            else k_adj_cols<T, false><<<dim3((pl->max_h + 3) / 4, B), 256, pl->smem_col, st>>>(P, plan, work);
+            break;
         case 2:
-            k_adj_rows<T, EPI><<<dim3(pl->max_rowpairs, B), 64, pl->smem_row, st>>>(P, c_out, c_in, taus, plan, work);
+            k_adj_rows<T, EPI><<<dim3((pl->max_rowpairs + 3) / 4, B), 256, pl->smem_row, st>>>(P, c_out, c_in, taus,
+                                                                                              plan, work);
             break;
         case 3:
             k_scatter_rows<T, SORTED><<<dim3(pl->max_n, B), 256, pl->smem_dscatter, st>>>(P, s, plan, work);
@@ -671,6 +685,7 @@ int build_common(const mpi_problem* probs, int count, void* plan_mem, size_t pla
     pl->dtype = probs[0].dtype;
     pl->plan = static_cast<char*>(plan_mem);
     pl->dprob = static_cast<const Prob*>(plan_mem);
+    pl->col_force = (flags & MPI_BUILD_COL_SPLIT) ? 1 : ((flags & MPI_BUILD_COL_WAVE) ? 2 : 0);
     finalize_extents(pl);
     rc = pl->dtype == MPI_F64 ? build_batch<double>(probs, pl, work, work_bytes, flags, stream)
                               : build_batch<float>(probs, pl, work, work_bytes, flags, stream);

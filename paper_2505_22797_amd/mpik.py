@@ -24,7 +24,7 @@ EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "
            "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_iterate",
            "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
            "mpi_plan_destroy", "mpi_status_str", "mpi_abi_version")
-MPI_BUILD_TUNE = 1
+MPI_BUILD_TUNE, MPI_BUILD_COL_SPLIT, MPI_BUILD_COL_WAVE = 1, 2, 4
 
 
 class MpiError(RuntimeError):
@@ -222,8 +222,9 @@ class Batch:
     the whole batch.  Concentrations and signals of all problems live
     concatenated in one flat tensor each (see `c_offsets`, `s_offsets`)."""
 
-    def __init__(self, specs, dtype=torch.float32, tune: bool = True, stream=None):
-        """specs: list of (n, h, radius, r, v[, conv_mode]) with r, v device (T, 2)."""
+    def __init__(self, specs, dtype=torch.float32, tune: bool = True, columns: str | None = None, stream=None):
+        """specs: list of (n, h, radius, r, v[, conv_mode]) with r, v device (T, 2).
+        columns: None (by batch size), "split" or "wave": shape of the column-FFT kernels."""
         keep = []
         arr = (Problem * len(specs))()
         for i, sp in enumerate(specs):
@@ -245,9 +246,10 @@ class Batch:
         self.plan_mem = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
         self.work = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
         handle = ctypes.c_void_p()
+        flags = (MPI_BUILD_TUNE if tune else 0) | {None: 0, "split": MPI_BUILD_COL_SPLIT,
+                                                   "wave": MPI_BUILD_COL_WAVE}[columns]
         _check(lib().mpi_batch_build(arr, self.count, self.plan_mem.data_ptr(), pb.value, self.work.data_ptr(),
-                                     wb.value, MPI_BUILD_TUNE if tune else 0, _stream(stream),
-                                     ctypes.byref(handle)), "mpi_batch_build")
+                                     wb.value, flags, _stream(stream), ctypes.byref(handle)), "mpi_batch_build")
         self._h = handle
         co = (ctypes.c_int64 * (self.count + 1))()
         so = (ctypes.c_int64 * (self.count + 1))()

@@ -34,9 +34,9 @@ def _small_batch():
     return specs
 
 
-def _build(specs, tune=False, modes=True):
+def _build(specs, tune=False, modes=True, columns=None):
     return mpik.Batch([(sp["n"], sp["h"], sp["R"], dev(sp["r"], torch.float32), dev(sp["v"], torch.float32),
-                        sp["mode"] if modes else "auto") for sp in specs], tune=tune)
+                        sp["mode"] if modes else "auto") for sp in specs], tune=tune, columns=columns)
 
 
 def _c_all(batch, specs):
@@ -44,8 +44,10 @@ def _c_all(batch, specs):
 
 
 def test_batch_equals_single_plans():
+    """With the column kernels in the shape a single plan uses, every problem
+    of the batch is bitwise the single-plan result."""
     specs = _small_batch()
-    batch = _build(specs)
+    batch = _build(specs, columns="split")
     c_all = _c_all(batch, specs)
     s_all = batch.forward(c_all)
     rng = np.random.default_rng(0)
@@ -63,9 +65,10 @@ def test_batch_equals_single_plans():
         assert torch.equal(batch.c_views(g_all)[b], g1), b
 
 
-def test_batch_matches_oracle():
+@pytest.mark.parametrize("columns", ["split", "wave"])
+def test_batch_matches_oracle(columns):
     specs = _small_batch()
-    batch = _build(specs)
+    batch = _build(specs, columns=columns)
     c_all = _c_all(batch, specs)
     s_all = batch.forward(c_all)
     rng = np.random.default_rng(1)
