@@ -76,6 +76,23 @@ template <typename P> __device__ __forceinline__ const P* at(const char* base, i
 
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Work-groups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// their linear index.  With grid.x a multiple of 8, block x runs on XCD x % 8;
+// mapping it to unit (x % 8) * ceil(n/8) + x / 8 gives every XCD one
+// contiguous band of units, so the transposing stores of neighbouring rows or
+// columns fill whole cache lines in one L2.  The map is one-to-one from
+// blocks [0, 8 * ceil(n/8)) onto units; it returns -1 for padding blocks and
+// for blocks beyond that range (a batched launch is sized for its largest
+// problem).
+constexpr int kXcds = 8;
+__host__ __device__ constexpr int xcd_grid(int n) { return (n + kXcds - 1) / kXcds * kXcds; }
+__device__ __forceinline__ int xcd_unit(int x, int n) {
+    const int per = (n + kXcds - 1) / kXcds;
+    if (x / kXcds >= per) return -1;
+    const int u = (x % kXcds) * per + x / kXcds;
+    return u < n ? u : -1;
+}
+
 // ---------------------------------------------------------------------------
 // Stockham autosort FFT of one line of M points held in LDS, done in place by
 // one 64-lane wavefront with no work-group barrier.  Mixed radix 8 (then 4 or

@@ -177,10 +177,11 @@ __global__ void __launch_bounds__(256) k_scatter_rows(const Prob* __restrict__ P
     T* G = at<T>(work, p.w_g);
     const int N = p.n, j = blockIdx.x;
     if (j >= N) return;
-    auto& sc = *reinterpret_cast<ScatterSmem<T, 256, 1024>*>(smem);
-    T* g = reinterpret_cast<T*>(smem + ((sizeof(ScatterSmem<T, 256, 1024>) + 15) / 16) * 16);
-    scatter_row<T, SORTED, 256, 1024>(g, sc, N, j, at<int>(plan, p.o_binstart), at<vec4<T>>(plan, p.o_samp),
-                                      at<int2>(plan, p.o_sidx), at<vec2<T>>(work, p.w_res), s + p.o_s, threadIdx.x);
+    T* g = reinterpret_cast<T*>(smem);
+    char* sc = smem + lds_align(size_t(3) * N * sizeof(T));
+    scatter_row<T, SORTED, 256>(g, scatter_lds<T>(sc, N, 256), N, j, at<int>(plan, p.o_binstart),
+                                at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), at<vec2<T>>(work, p.w_res),
+                                s + p.o_s, threadIdx.x);
     for (int i = threadIdx.x; i < 3 * N; i += blockDim.x) {
         const int ch = i / N, x = i % N;
         G[int64_t(ch) * N * N + int64_t(j) * N + x] = g[i];

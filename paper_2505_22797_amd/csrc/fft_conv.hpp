@@ -39,19 +39,29 @@ template <typename T, int M> struct ColSmem {      // column stages: four lines 
     cx<T> c[M];
     cx<T> line[4][M];
 };
-template <typename T, int M> struct GatherSmem {   // fwd_rows_gather: three FFT waves, four gather waves
+// fwd_rows_gather: twiddles, three FFT lines, then rows b, b+1 of the three
+// channels (6N values).
+template <typename T, int M> struct GatherSmem {
     cx<T> tw[M];
     cx<T> line[3][M];
-    T g[6 * M];
+    T g[1];
 };
-template <typename T, int M> struct ScatterRowSmem {   // adj_scatter_row: four waves
+template <typename T, int M>
+__host__ __device__ constexpr size_t gather_smem_bytes(int N) {
+    return sizeof(GatherSmem<T, M>) + size_t(6) * N * sizeof(T);
+}
+// adj_scatter_row: twiddles, the row's three channels (3N values), then a
+// region shared by the sampling transpose and the two row-FFT lines (they
+// run one after the other).
+template <typename T, int M> struct ScatterRowSmem {
     cx<T> tw[M];
-    T g[3 * M];
-    union {                     // the sampling transpose and the row FFTs run one after the other
-        ScatterSmem<T, 256, M> sc;
-        cx<T> line[2][M];
-    };
+    cx<T> line[2][M];
 };
+template <typename T, int M>
+__host__ __device__ constexpr size_t scatter_row_smem_bytes(int N) {
+    const size_t a = sizeof(cx<T>) * M, lines = 2 * sizeof(cx<T>) * M, sc = scatter_lds_bytes<T>(N, 256);
+    return a + lds_align(size_t(3) * N * sizeof(T)) + (lines > sc ? lines : sc);
+}
 
 template <typename T, int M>
 __device__ __forceinline__ void load_twiddles(cx<T>* tw_s, const char* plan, const Prob& p, int tid, int nt) {
@@ -103,10 +113,11 @@ __device__ void fwd_rows_body(const Prob& p, const T* __restrict__ c, const char
     auto& sm = *reinterpret_cast<RowSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    if (2 * 4 * int(blockIdx.x) >= N) return;
+    const int unit = xcd_unit(blockIdx.x, (N + 7) / 8);   // four row pairs per work-group
+    if (unit < 0) return;
     load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
     __syncthreads();
-    const int q = 4 * blockIdx.x + wave;
+    const int q = 4 * unit + wave;
     const int r0 = 2 * q, r1 = 2 * q + 1;
     if (r0 >= N) return;
     const bool two = r1 < N;
@@ -143,8 +154,8 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
     const T* spec = at<T>(plan, p.o_spec);
     cx<T>* t2 = at<cx<T>>(work, p.w_t2);
     if (SPLIT) {                                    // one column, waves 0..2
-        const int kx = blockIdx.x;
-        if (kx >= H) return;
+        const int kx = xcd_unit(blockIdx.x, H);
+        if (kx < 0) return;
         load_twiddles<T, M>(sm.tw, plan, p, tid, 3 * kWave);
         const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(kx) * N;
         for (int i = tid; i < M; i += 3 * kWave) sm.c[i] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
@@ -158,10 +169,11 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
         cx<T>* out = t2 + int64_t(wave) * N * H;
         for (int j = lane; j < N; j += kWave) out[int64_t(j) * H + kx] = line[j];
     } else {                                        // four columns, one per wave
-        if (4 * int(blockIdx.x) >= H) return;
+        const int unit = xcd_unit(blockIdx.x, (H + 3) / 4);
+        if (unit < 0) return;
         load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
         __syncthreads();
-        const int kx = 4 * blockIdx.x + wave;
+        const int kx = 4 * unit + wave;
         if (kx >= H) return;
         cx<T>* line = sm.line[wave];
         const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(kx) * N;
@@ -192,8 +204,8 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ s, const cha
                                      char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<GatherSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
-    const int N = p.n, nb = p.nb, b = blockIdx.x;
-    if (b >= nb) return;
+    const int N = p.n, nb = p.nb, b = xcd_unit(blockIdx.x, nb);
+    if (b < 0) return;
     const int* binstart = at<int>(plan, p.o_binstart);
     const int p0 = binstart[b * nb], p1 = binstart[(b + 1) * nb];
     if (p0 == p1) return;
@@ -228,18 +240,22 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ s, const cha
 template <typename T, int M, bool SORTED>
 __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, const char* __restrict__ plan,
                                      char* __restrict__ work, char* smem) {
-    auto& sm = *reinterpret_cast<ScatterRowSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
-    const int N = p.n, j = blockIdx.x;
-    if (j >= N) return;
+    const int N = p.n, j = xcd_unit(blockIdx.x, N);
+    if (j < 0) return;
+    cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
+    T* g = reinterpret_cast<T*>(smem + sizeof(cx<T>) * M);
+    char* shared_area = smem + sizeof(cx<T>) * M + lds_align(size_t(3) * N * sizeof(T));
+    cx<T>* lines = reinterpret_cast<cx<T>*>(shared_area);
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
-    scatter_row<T, SORTED, 256, M>(sm.g, sm.sc, N, j, at<int>(plan, p.o_binstart), at<vec4<T>>(plan, p.o_samp),
-                                   at<int2>(plan, p.o_sidx), at<vec2<T>>(work, p.w_res), s, tid);
+    load_twiddles<T, M>(tw, plan, p, tid, 4 * kWave);
+    scatter_row<T, SORTED, 256>(g, scatter_lds<T>(shared_area, N, 256), N, j, at<int>(plan, p.o_binstart),
+                                at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), at<vec2<T>>(work, p.w_res),
+                                s, tid);
     if (wave >= 2) return;
-    cx<T>* line = sm.line[wave];
-    const T* re = sm.g + (wave == 0 ? 0 : 2 * N);
-    const T* im = sm.g + N;
+    cx<T>* line = lines + wave * M;
+    const T* re = g + (wave == 0 ? 0 : 2 * N);
+    const T* im = g + N;
     for (int i = lane; i < M; i += kWave) {
         cx<T> z{T(0), T(0)};
         if (i < N) {
@@ -249,7 +265,7 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
         line[i] = z;
     }
     wave_sync();
-    fft_wave<T, false, M>(line, sm.tw, lane);
+    fft_wave<T, false, M>(line, tw, lane);
     cx<T>* t1 = at<cx<T>>(work, p.w_t1);
     for (int k = lane; k < H; k += kWave) {
         if (wave == 0) {
@@ -274,8 +290,8 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
     const T* spec = at<T>(plan, p.o_spec);
     cx<T>* t2 = at<cx<T>>(work, p.w_t2);
     if (SPLIT) {                                    // one column, waves 0..2
-        const int kx = blockIdx.x;
-        if (kx >= H) return;
+        const int kx = xcd_unit(blockIdx.x, H);
+        if (kx < 0) return;
         load_twiddles<T, M>(sm.tw, plan, p, tid, 3 * kWave);
         __syncthreads();
         cx<T>* line = sm.line[wave];
@@ -292,10 +308,11 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         fft_wave<T, true, M>(sm.c, sm.tw, lane);
         for (int j = lane; j < N; j += kWave) t2[int64_t(j) * H + kx] = sm.c[j];
     } else {                                        // four columns, one per wave
-        if (4 * int(blockIdx.x) >= H) return;
+        const int unit = xcd_unit(blockIdx.x, (H + 3) / 4);
+        if (unit < 0) return;
         load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
         __syncthreads();
-        const int kx = 4 * blockIdx.x + wave;
+        const int kx = 4 * unit + wave;
         if (kx >= H) return;
         cx<T>* line = sm.line[wave];
         constexpr int PL = M / kWave;
@@ -328,10 +345,11 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau,
     auto& sm = *reinterpret_cast<RowSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    if (2 * 4 * int(blockIdx.x) >= N) return;
+    const int unit = xcd_unit(blockIdx.x, (N + 7) / 8);   // four row pairs per work-group
+    if (unit < 0) return;
     load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
     __syncthreads();
-    const int q = 4 * blockIdx.x + wave;
+    const int q = 4 * unit + wave;
     const int r0 = 2 * q, r1 = 2 * q + 1;
     if (r0 >= N) return;
     const bool two = r1 < N;
@@ -366,7 +384,7 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau,
         default: break;                                      \
     }
 
-// grid.x: ceil(row pairs / 4), grid.y: problem; 256 threads
+// grid.x: xcd_grid(ceil(row pairs / 4)), grid.y: problem; 256 threads
 template <typename T>
 __global__ void __launch_bounds__(256) k_fwd_rows(const Prob* __restrict__ P, const T* __restrict__ c,
                                                   const char* __restrict__ plan, char* __restrict__ work) {
@@ -376,7 +394,7 @@ __global__ void __launch_bounds__(256) k_fwd_rows(const Prob* __restrict__ P, co
     MPIK_DISPATCH_M(p.m, (fwd_rows_body<T, MM>(p, c + p.o_c, plan, work, smem)));
 }
 
-// SPLIT: grid.x = M/2 + 1, 192 threads; else grid.x = ceil((M/2 + 1)/4), 256 threads
+// SPLIT: grid.x = xcd_grid(M/2 + 1), 192 threads; else xcd_grid(ceil((M/2 + 1)/4)), 256 threads
 template <typename T, bool SPLIT>
 __global__ void __launch_bounds__(256) k_fwd_cols(const Prob* __restrict__ P, const char* __restrict__ plan,
                                                   char* __restrict__ work) {
@@ -386,7 +404,7 @@ __global__ void __launch_bounds__(256) k_fwd_cols(const Prob* __restrict__ P, co
     MPIK_DISPATCH_M(p.m, (fwd_cols_body<T, MM, SPLIT>(p, plan, work, smem)));
 }
 
-// grid.x: base-cell rows, 256 threads
+// grid.x: xcd_grid(base-cell rows), 256 threads
 template <typename T, bool RESID>
 __global__ void __launch_bounds__(256) k_fwd_rows_gather(const Prob* __restrict__ P, T* __restrict__ s,
                                                          const char* __restrict__ plan, char* __restrict__ work) {
@@ -396,7 +414,7 @@ __global__ void __launch_bounds__(256) k_fwd_rows_gather(const Prob* __restrict_
     MPIK_DISPATCH_M(p.m, (fwd_rows_gather_body<T, MM, RESID>(p, s + p.o_s, plan, work, smem)));
 }
 
-// grid.x: grid rows, 256 threads
+// grid.x: xcd_grid(grid rows), 256 threads
 template <typename T, bool SORTED>
 __global__ void __launch_bounds__(256) k_adj_scatter_row(const Prob* __restrict__ P, const T* __restrict__ s,
                                                          const char* __restrict__ plan, char* __restrict__ work) {
@@ -406,7 +424,7 @@ __global__ void __launch_bounds__(256) k_adj_scatter_row(const Prob* __restrict_
     MPIK_DISPATCH_M(p.m, (adj_scatter_row_body<T, MM, SORTED>(p, s + p.o_s, plan, work, smem)));
 }
 
-// SPLIT: grid.x = M/2 + 1, 192 threads; else grid.x = ceil((M/2 + 1)/4), 256 threads
+// SPLIT: grid.x = xcd_grid(M/2 + 1), 192 threads; else xcd_grid(ceil((M/2 + 1)/4)), 256 threads
 template <typename T, bool SPLIT>
 __global__ void __launch_bounds__(256) k_adj_cols(const Prob* __restrict__ P, const char* __restrict__ plan,
                                                   char* __restrict__ work) {
@@ -416,7 +434,7 @@ __global__ void __launch_bounds__(256) k_adj_cols(const Prob* __restrict__ P, co
     MPIK_DISPATCH_M(p.m, (adj_cols_body<T, MM, SPLIT>(p, plan, work, smem)));
 }
 
-// grid.x: ceil(row pairs / 4), 256 threads
+// grid.x: xcd_grid(ceil(row pairs / 4)), 256 threads
 template <typename T, int EPI>
 __global__ void __launch_bounds__(256) k_adj_rows(const Prob* __restrict__ P, T* c_out, const T* c_in,
                                                   const double* __restrict__ taus, const char* __restrict__ plan,

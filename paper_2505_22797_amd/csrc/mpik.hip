@@ -61,25 +61,31 @@ size_t smem_for(int M) {
     }
 }
 // which: 0 row, 1 column, 2 gather, 3 scatter-row
-size_t smem_for_dt(int elem, int M, int which) {
-    if (elem == 8) {
-        switch (which) {
-            case 0: return smem_for<double, RowSmem>(M);
-            case 1: return smem_for<double, ColSmem>(M);
-            case 2: return smem_for<double, GatherSmem>(M);
-            default: return smem_for<double, ScatterRowSmem>(M);
-        }
-    }
+template <typename T>
+size_t smem_for_t(int M, int N, int which) {
     switch (which) {
-        case 0: return smem_for<float, RowSmem>(M);
-        case 1: return smem_for<float, ColSmem>(M);
-        case 2: return smem_for<float, GatherSmem>(M);
-        default: return smem_for<float, ScatterRowSmem>(M);
+        case 0: return smem_for<T, RowSmem>(M);
+        case 1: return smem_for<T, ColSmem>(M);
+        default: break;
+    }
+    switch (M) {
+#define MPIK_SMEM_CASE(MM) \
+    case MM: return which == 2 ? gather_smem_bytes<T, MM>(N) : scatter_row_smem_bytes<T, MM>(N);
+        MPIK_SMEM_CASE(64)
+        MPIK_SMEM_CASE(128)
+        MPIK_SMEM_CASE(256)
+        MPIK_SMEM_CASE(512)
+        MPIK_SMEM_CASE(1024)
+#undef MPIK_SMEM_CASE
+        default: return 0;
     }
 }
+size_t smem_for_dt(int elem, int M, int N, int which) {
+    return elem == 8 ? smem_for_t<double>(M, N, which) : smem_for_t<float>(M, N, which);
+}
 size_t scatter_rows_smem(int N, int elem) {
-    const size_t sc = elem == 8 ? sizeof(ScatterSmem<double, 256, 1024>) : sizeof(ScatterSmem<float, 256, 1024>);
-    return (sc + 15) / 16 * 16 + size_t(3) * N * elem;
+    const size_t sc = elem == 8 ? scatter_lds_bytes<double>(N, 256) : scatter_lds_bytes<float>(N, 256);
+    return lds_align(size_t(3) * N * elem) + sc;
 }
 
 struct Shape {
@@ -103,8 +109,8 @@ int validate(const mpi_problem* d, Shape& sh) {
     sh.T = d->n_samples;
     sh.M = std::max(64, pow2_at_least(sh.n + sh.R));
     const int maxM = sh.elem == 8 ? 512 : 1024;
-    sh.fft_ok = sh.M <= maxM && sh.n <= 512 && smem_for_dt(sh.elem, sh.M, 3) <= kSmemLimit &&
-                smem_for_dt(sh.elem, sh.M, 1) <= kSmemLimit && smem_for_dt(sh.elem, sh.M, 2) <= kSmemLimit;
+    sh.fft_ok = sh.M <= maxM && sh.n <= 512 && smem_for_dt(sh.elem, sh.M, sh.n, 3) <= kSmemLimit &&
+                smem_for_dt(sh.elem, sh.M, sh.n, 1) <= kSmemLimit && smem_for_dt(sh.elem, sh.M, sh.n, 2) <= kSmemLimit;
     sh.direct_ok = direct_smem(sh.R, 3, 1, 16, sh.elem) <= kSmemLimit &&
                    direct_smem(sh.R, 1, 3, 16, sh.elem) <= kSmemLimit && scatter_rows_smem(sh.n, sh.elem) <= kSmemLimit;
     if (d->conv_mode == MPI_CONV_FFT && !sh.fft_ok) return MPI_ERR_UNSUPPORTED;
@@ -295,10 +301,10 @@ void finalize_extents(mpi_plan* pl) {
         if (p.mode == 1) {
             pl->any_fft = true;
             pl->max_h = std::max(pl->max_h, p.m / 2 + 1);
-            pl->smem_row = std::max(pl->smem_row, smem_for_dt(e, p.m, 0));
-            pl->smem_col = std::max(pl->smem_col, smem_for_dt(e, p.m, 1));
-            pl->smem_gather = std::max(pl->smem_gather, smem_for_dt(e, p.m, 2));
-            pl->smem_scatter = std::max(pl->smem_scatter, smem_for_dt(e, p.m, 3));
+            pl->smem_row = std::max(pl->smem_row, smem_for_dt(e, p.m, p.n, 0));
+            pl->smem_col = std::max(pl->smem_col, smem_for_dt(e, p.m, p.n, 1));
+            pl->smem_gather = std::max(pl->smem_gather, smem_for_dt(e, p.m, p.n, 2));
+            pl->smem_scatter = std::max(pl->smem_scatter, smem_for_dt(e, p.m, p.n, 3));
         } else {
             pl->any_direct = true;
             pl->max_tiles = std::max(pl->max_tiles, (p.n + kTile - 1) / kTile);
@@ -417,13 +423,18 @@ void fwd_stage(const mpi_plan* pl, int k, const T* c, T* s, char* work, hipStrea
     if (k >= 3 && !pl->any_direct) return;
     switch (k) {
         case 0:
-            k_fwd_rows<T><<<dim3((pl->max_rowpairs + 3) / 4, B), 256, pl->smem_row, st>>>(P, c, plan, work);
+            k_fwd_rows<T><<<dim3(xcd_grid((pl->max_rowpairs + 3) / 4), B), 256, pl->smem_row, st>>>(P, c, plan,
+                                                                                                work);
             break;
         case 1:
-            if (pl->col_split) k_fwd_cols<T, true><<<dim3(pl->max_h, B), 192, pl->smem_col, st>>>(P, plan, work);
-            else k_fwd_cols<T, false><<<dim3((pl->max_h + 3) / 4, B), 256, pl->smem_col, st>>>(P, plan, work);
+            if (pl->col_split)
+                k_fwd_cols<T, true><<<dim3(xcd_grid(pl->max_h), B), 192, pl->smem_col, st>>>(P, plan, work);
+            else
+                k_fwd_cols<T, false><<<dim3(xcd_grid((pl->max_h + 3) / 4), B), 256, pl->smem_col, st>>>(P, plan, work);
             break;
-        case 2: k_fwd_rows_gather<T, RESID><<<dim3(pl->max_nb, B), 256, pl->smem_gather, st>>>(P, s, plan, work); break;
+        case 2:
+            k_fwd_rows_gather<T, RESID><<<dim3(xcd_grid(pl->max_nb), B), 256, pl->smem_gather, st>>>(P, s, plan, work);
+            break;
         case 3:
             launch_direct_conv<T, 4, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st);
             launch_direct_conv<T, 8, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st);
@@ -446,14 +457,19 @@ void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, c
     if (k <= 2 && !pl->any_fft) return;
     if (k >= 3 && !pl->any_direct) return;
     switch (k) {
-        case 0: k_adj_scatter_row<T, SORTED><<<dim3(pl->max_n, B), 256, pl->smem_scatter, st>>>(P, s, plan, work); break;
+        case 0:
+            k_adj_scatter_row<T, SORTED><<<dim3(xcd_grid(pl->max_n), B), 256, pl->smem_scatter, st>>>(P, s, plan,
+                                                                                                    work);
+            break;
         case 1:
-            if (pl->col_split) k_adj_cols<T, true><<<dim3(pl->max_h, B), 192, pl->smem_col, st>>>(P, plan, work);
-            else k_adj_cols<T, false><<<dim3((pl->max_h + 3) / 4, B), 256, pl->smem_col, st>>>(P, plan, work);
+            if (pl->col_split)
+                k_adj_cols<T, true><<<dim3(xcd_grid(pl->max_h), B), 192, pl->smem_col, st>>>(P, plan, work);
+            else
+                k_adj_cols<T, false><<<dim3(xcd_grid((pl->max_h + 3) / 4), B), 256, pl->smem_col, st>>>(P, plan, work);
             break;
         case 2:
-            k_adj_rows<T, EPI><<<dim3((pl->max_rowpairs + 3) / 4, B), 256, pl->smem_row, st>>>(P, c_out, c_in, taus,
-                                                                                              plan, work);
+            k_adj_rows<T, EPI><<<dim3(xcd_grid((pl->max_rowpairs + 3) / 4), B), 256, pl->smem_row, st>>>(
+                P, c_out, c_in, taus, plan, work);
             break;
         case 3:
             k_scatter_rows<T, SORTED><<<dim3(pl->max_n, B), 256, pl->smem_dscatter, st>>>(P, s, plan, work);

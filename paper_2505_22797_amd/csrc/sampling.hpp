@@ -65,13 +65,35 @@ __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int
     }
 }
 
-// Shared-memory part of scatter_row for NT threads and rows of N <= NMAX.
-template <typename T, int NT, int NMAX> struct ScatterSmem {
-    static constexpr int kThreads = NT;
-    T K[2 * NMAX * 6];                 // per base cell: (left, right) x 3 channels
-    int first_key[NT], last_key[NT];
-    T first_val[NT][6], last_val[NT][6];
+// Shared-memory part of scatter_row, carved from a dynamic LDS region: per
+// base cell of the two base-cell rows (left, right) x 3 channel sums, and the
+// first/last base cell of every thread with the partial sum of the first.
+template <typename T> struct ScatterLds {
+    T* K;
+    int* first_key;
+    int* last_key;
+    T* first_val;
 };
+
+__host__ __device__ constexpr size_t lds_align(size_t b) { return (b + 15) / 16 * 16; }
+
+template <typename T>
+__host__ __device__ constexpr size_t scatter_lds_bytes(int N, int NT) {
+    return lds_align(size_t(2) * (N - 1) * 6 * sizeof(T)) + lds_align(size_t(2) * NT * sizeof(int)) +
+           lds_align(size_t(NT) * 6 * sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ ScatterLds<T> scatter_lds(char* base, int N, int NT) {
+    ScatterLds<T> v;
+    v.K = reinterpret_cast<T*>(base);
+    base += lds_align(size_t(2) * (N - 1) * 6 * sizeof(T));
+    v.first_key = reinterpret_cast<int*>(base);
+    v.last_key = v.first_key + NT;
+    base += lds_align(size_t(2) * NT * sizeof(int));
+    v.first_val = reinterpret_cast<T*>(base);
+    return v;
+}
 
 // Transpose of the sampling for the cells of grid row j.  Those cells receive
 // from the samples of base-cell rows j-1 (weight fy) and j (weight 1 - fy),
@@ -83,8 +105,8 @@ template <typename T, int NT, int NMAX> struct ScatterSmem {
 // cell from its (at most) four base cells in a fixed order.  The result goes
 // to g[ch * N + i] in LDS.  SORTED: the signal/residual is read in cell order
 // from ys[p]; else in time order from s_time[k].
-template <typename T, bool SORTED, int NT, int NMAX, int U = 4>
-__device__ __forceinline__ void scatter_row(T* g, ScatterSmem<T, NT, NMAX>& sm, int N, int j,
+template <typename T, bool SORTED, int NT, int U = 4>
+__device__ __forceinline__ void scatter_row(T* g, ScatterLds<T> sm, int N, int j,
                                             const int* __restrict__ binstart, const vec4<T>* __restrict__ samp,
                                             const int2* __restrict__ sidx, const vec2<T>* __restrict__ ys,
                                             const T* __restrict__ s_time, int tid) {
@@ -159,10 +181,7 @@ __device__ __forceinline__ void scatter_row(T* g, ScatterSmem<T, NT, NMAX>& sm, 
     sm.first_key[tid] = fk;
     sm.last_key[tid] = lk;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        sm.first_val[tid][q] = fv[q];
-        sm.last_val[tid][q] = acc[q];
-    }
+    for (int q = 0; q < 6; ++q) sm.first_val[tid * 6 + q] = fv[q];
     __syncthreads();
     if (lk >= 0) {
         const bool shared_head = tid > 0 && sm.last_key[tid - 1] == fk;
@@ -176,7 +195,7 @@ __device__ __forceinline__ void scatter_row(T* g, ScatterSmem<T, NT, NMAX>& sm, 
             for (int q = 0; q < 6; ++q) tot[q] = acc[q];
             for (int u = tid + 1; u < NT && sm.first_key[u] == lk; ++u) {
 #pragma unroll
-                for (int q = 0; q < 6; ++q) tot[q] += sm.first_val[u][q];
+                for (int q = 0; q < 6; ++q) tot[q] += sm.first_val[u * 6 + q];
                 if (sm.last_key[u] != lk) break;
             }
 #pragma unroll

@@ -126,3 +126,30 @@ def test_uneven_batch_of_64_with_tuning():
         assert rel_l2(s_got, s_ref) <= 1e-5, (b, batch.info[b])
         g_ref = M.adjoint(rounded(s_got, torch.float32))
         assert rel_l2(gv[b].double().cpu().numpy(), g_ref) <= 1e-5, (b, batch.info[b])
+
+
+@pytest.mark.parametrize("columns", ["split", "wave"])
+def test_uneven_sizes_iterate_matches_oracle(columns):
+    """Problems of very different sizes in one batch: every launch is sized
+    for the largest one, so the block-to-row mapping of the small ones must
+    stay one-to-one (the in-place gradient step would otherwise be applied
+    twice)."""
+    specs = []
+    for i, (n, R, t) in enumerate([(200, 31, 20000), (24, 23, 3000), (72, 40, 8000), (9, 8, 500)]):
+        tr = S.lissajous(t, ax=0.8, ay=0.8)
+        specs.append(dict(n=n, h=S.h_fwhm2(n), R=R, r=rounded(tr.r, torch.float32), v=rounded(tr.v, torch.float32),
+                          c=rounded(S.blobs(n, 40 + i), torch.float32), mode="fft"))
+    batch = _build(specs, columns=columns)
+    taus, s_list, models = [], [], []
+    for sp in specs:
+        M = O.Model(sp["n"], sp["h"], sp["R"], sp["r"], sp["v"])
+        models.append(M)
+        s_list.append(rounded(M.forward(sp["c"]), torch.float32))
+        taus.append(0.9 / O.power_lambda_max(M, iters=20))
+    s_all = torch.cat([dev(s, torch.float32).reshape(-1) for s in s_list])
+    c_all = torch.zeros(batch.c_offsets[-1], dtype=torch.float32, device="cuda")
+    batch.iterate(s_all, c_all, 6, taus)
+    torch.cuda.synchronize()
+    for b, sp in enumerate(specs):
+        ref = O.iterate(models[b], s_list[b], np.zeros((sp["n"], sp["n"])), taus[b], 6)
+        assert rel_l2(batch.c_views(c_all)[b].double().cpu().numpy(), ref) <= 1e-4, b
