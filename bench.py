@@ -113,6 +113,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="only a few batched pairs plus a 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the operator runs on a single MI355X "
@@ -134,6 +136,9 @@ def main() -> int:
     c1 = torch.tensor(P.c, dtype=torch.float32, device=dev)
     b_alg = 56 * n * n + 48 * t
     print(f"bench: headline 256^2 / {t} samples, batch {args.batch}", file=sys.stderr, flush=True)
+
+    if args.profile_batch:
+        return profile_batch(mpik, P, r, v, c1, max(1, args.batch), args.steps)
 
     # ---- one problem per launch
     plan = mpik.Plan(n, P.h, P.radius, r, v)
@@ -208,6 +213,27 @@ def main() -> int:
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_seconds)
     print(json.dumps(out))
+    return 0
+
+
+def profile_batch(mpik, P, r, v, c1, B, steps):
+    """Run for hardware counters: `steps` batched pairs (each kernel launched
+    `steps` times) and one plain device copy of 256 MiB, whose FETCH_SIZE and
+    WRITE_SIZE calibrate the counters against a known byte count."""
+    import torch
+    n, t = P.n, P.n_samples
+    batch = mpik.Batch([(n, P.h, P.radius, r, v, "fft")] * B, tune=False)
+    c_all = c1.reshape(-1).repeat(B).contiguous()
+    s_all = torch.empty(batch.s_offsets[-1], dtype=torch.float32, device=c1.device)
+    g_all = torch.empty(batch.c_offsets[-1], dtype=torch.float32, device=c1.device)
+    for _ in range(max(1, min(steps, 20))):
+        batch.forward(c_all, s_all)
+        batch.adjoint(s_all, g_all)
+    src = torch.ones(64 << 20, dtype=torch.float32, device=c1.device)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_batch": B, "copy_bytes": src.numel() * 4, "grid": n, "samples": t}))
     return 0
 
 
