@@ -27,7 +27,7 @@ __all__ = [
     "kernel_h", "kernel_h_dh", "trace_kernel_h", "kernel_table", "kernel_table_dh",
     "trace_kernel_table", "effective_radius", "fft_size", "conv_direct", "conv_fft", "conv", "conv_adj",
     "bilinear", "gather", "scatter", "forward", "adjoint", "gauss_weights", "denoise",
-    "iterate", "power_lambda_max", "Model",
+    "iterate", "power_lambda_max", "unrolled_gradients", "Model",
 ]
 
 
@@ -257,12 +257,18 @@ def conv_adj(g: np.ndarray, taps: np.ndarray, method: str = "auto") -> np.ndarra
 # sampling along the trajectory and contraction with the velocity
 # (eq. core:formula: s(t) = A[rho](r(t)) v(t)); exact transpose
 # ----------------------------------------------------------------------------
-def bilinear(r: np.ndarray, n: int):
+def bilinear(r: np.ndarray, n: int, frozen=None):
     """Base cell and fractions of every sample.  g = (x+1)/delta - 1/2 is the
     position in cell-centre units; samples need 0 <= g <= N-1 on both axes.
-    i0 = min(floor(g), N-2) so that g = N-1 gives the fraction 1."""
+    i0 = min(floor(g), N-2) so that g = N-1 gives the fraction 1.
+    frozen = (ix, jy): keep those base cells and extend the bilinear patch
+    (fractions may leave [0, 1]) -- the convention under which finite
+    differences in the positions equal the derivative inside the patch."""
     r = np.asarray(r, dtype=np.float64)
     g = (r + 1.0) / (2.0 / n) - 0.5
+    if frozen is not None:
+        ix, jy = frozen
+        return ix, jy, g[:, 0] - ix, g[:, 1] - jy
     if not np.all((g >= 0.0) & (g <= n - 1)):
         raise DomainError("trajectory sample outside the hull of the cell centres")
     i0 = np.minimum(np.floor(g), n - 2).astype(np.int64)
@@ -270,30 +276,30 @@ def bilinear(r: np.ndarray, n: int):
     return i0[:, 0], i0[:, 1], f[:, 0], f[:, 1]
 
 
-def _corners(r, n):
-    ix, jy, fx, fy = bilinear(r, n)
+def _corners(r, n, frozen=None):
+    ix, jy, fx, fy = bilinear(r, n, frozen)
     return [((jy, ix), (1 - fx) * (1 - fy)), ((jy, ix + 1), fx * (1 - fy)),
             ((jy + 1, ix), (1 - fx) * fy), ((jy + 1, ix + 1), fx * fy)]
 
 
-def gather(G: np.ndarray, r: np.ndarray, v: np.ndarray) -> np.ndarray:
+def gather(G: np.ndarray, r: np.ndarray, v: np.ndarray, frozen=None) -> np.ndarray:
     """s_k = G(r_k) v_k with G = [G_xx, G_xy, G_yy] interpolated bilinearly."""
     n = G.shape[-1]
     g = np.zeros((3, r.shape[0]))
-    for (j, i), w in _corners(r, n):
+    for (j, i), w in _corners(r, n, frozen):
         g += w * G[:, j, i]
     v = np.asarray(v, dtype=np.float64)
     return np.stack([g[0] * v[:, 0] + g[1] * v[:, 1], g[1] * v[:, 0] + g[2] * v[:, 1]], 1)
 
 
-def scatter(y: np.ndarray, r: np.ndarray, v: np.ndarray, n: int) -> np.ndarray:
+def scatter(y: np.ndarray, r: np.ndarray, v: np.ndarray, n: int, frozen=None) -> np.ndarray:
     """Transpose of gather: G'_ch(q) = sum_k w_kq p_k,ch with the products
     p = (y_x v_x, y_x v_y + y_y v_x, y_y v_y)."""
     y = np.asarray(y, dtype=np.float64)
     v = np.asarray(v, dtype=np.float64)
     p = np.stack([y[:, 0] * v[:, 0], y[:, 0] * v[:, 1] + y[:, 1] * v[:, 0], y[:, 1] * v[:, 1]])
     out = np.zeros((3, n * n))
-    for (j, i), w in _corners(r, n):
+    for (j, i), w in _corners(r, n, frozen):
         for ch in range(3):
             out[ch] += np.bincount(j * n + i, weights=w * p[ch], minlength=n * n)
     return out.reshape(3, n, n)
@@ -336,26 +342,62 @@ def denoise(c: np.ndarray, sigma_px: float, radius: int) -> np.ndarray:
 
 
 class Model:
-    """A and A^T for one problem with the kernel table and sample cells cached."""
+    """A and A^T for one problem with the kernel table and sample cells cached.
+    frozen = (ix, jy) fixes the base cells (see `bilinear`)."""
 
-    def __init__(self, n, h, radius, r, v, method="auto"):
+    def __init__(self, n, h, radius, r, v, method="auto", frozen=None):
         self.n, self.h, self.radius, self.method = n, h, radius, method
         self.r = np.asarray(r, dtype=np.float64)
         self.v = np.asarray(v, dtype=np.float64)
-        bilinear(self.r, n)                          # domain check up front
+        if frozen is None:
+            bilinear(self.r, n)                      # domain check up front
+        self.frozen = frozen
         self.taps = (2.0 / n) ** 2 * kernel_table(n, h, radius)
+
+    def cells(self):
+        ix, jy, _, _ = bilinear(self.r, self.n, self.frozen)
+        return ix, jy
 
     def field(self, c):
         return conv(c, self.taps, self.method)
 
     def forward(self, c):
-        return gather(self.field(c), self.r, self.v)
+        return gather(self.field(c), self.r, self.v, self.frozen)
 
     def adjoint(self, y):
-        return conv_adj(scatter(y, self.r, self.v, self.n), self.taps, self.method)
+        return conv_adj(scatter(y, self.r, self.v, self.n, self.frozen), self.taps, self.method)
 
     def normal(self, c):
         return self.adjoint(self.forward(c))
+
+    # ---- derivatives (the VJP building blocks) ----
+    def forward_dh(self, x):
+        """(dA/dh) x: the sampling of the convolution with delta^2 dK_h/dh."""
+        dtaps = (2.0 / self.n) ** 2 * kernel_table_dh(self.n, self.h, self.radius)
+        return gather(conv(x, dtaps, self.method), self.r, self.v, self.frozen)
+
+    def traj_vjp(self, x, y):
+        """Gradients of <y, A x> with respect to every sample's position r_k and
+        velocity v_k, base cells fixed (the derivative inside the bilinear
+        patch).  Returns (g_r, g_v), both [T, 2]."""
+        n = self.n
+        G = self.field(x)
+        ix, jy, fx, fy = bilinear(self.r, n, self.frozen)
+        g00, g10 = G[:, jy, ix], G[:, jy, ix + 1]
+        g01, g11 = G[:, jy + 1, ix], G[:, jy + 1, ix + 1]
+        g = (1 - fx) * (1 - fy) * g00 + fx * (1 - fy) * g10 + (1 - fx) * fy * g01 + fx * fy * g11
+        inv_d = n / 2.0                                   # d fraction / d position
+        dgx = inv_d * ((1 - fy) * (g10 - g00) + fy * (g11 - g01))
+        dgy = inv_d * ((1 - fx) * (g01 - g00) + fx * (g11 - g10))
+        y = np.asarray(y, dtype=np.float64)
+        v = self.v
+
+        def contract(m, a):        # M(m) a with M = [[m0, m1], [m1, m2]]
+            return np.stack([m[0] * a[:, 0] + m[1] * a[:, 1], m[1] * a[:, 0] + m[2] * a[:, 1]], 1)
+
+        g_r = np.stack([np.sum(y * contract(dgx, v), 1), np.sum(y * contract(dgy, v), 1)], 1)
+        g_v = contract(g, y)
+        return g_r, g_v
 
 
 def iterate(model: Model, s, c0, tau, n_iter, sigma_px=None, radius=2):
@@ -366,6 +408,43 @@ def iterate(model: Model, s, c0, tau, n_iter, sigma_px=None, radius=2):
         if sigma_px is not None:
             c = denoise(c, sigma_px, radius)
     return c
+
+
+def unrolled_gradients(n, h, radius, ax, ay, rho, nu, s, c_true, c0, tau, n_iter, sigma_px=None, radius_d=2,
+                       frozen=None, method="auto"):
+    """Loss L = |c_K - c_true|^2 after n_iter steps c <- D(c - tau A^T(A c - s))
+    with the trajectory r = (ax rho_x, ay rho_y), v = (ax nu_x, ay nu_y), and
+    its gradients with respect to c0, h, ax and ay by the reverse recursion:
+      u_k = c_k - tau A^T r_k,  r_k = A c_k - s,  c_{k+1} = D u_k;
+      gbar_u = D gbar_{c_{k+1}};  gbar_{c_k} = gbar_u - tau A^T A gbar_u;
+      dL/dtheta += -tau [ <(dA/dtheta) gbar_u, r_k> + <A gbar_u, (dA/dtheta) c_k> ].
+    D is symmetric (an even kernel with zero padding), tau is held fixed."""
+    scale = np.array([ax, ay])
+    r = np.asarray(rho) * scale
+    v = np.asarray(nu) * scale
+    M = Model(n, h, radius, r, v, method=method, frozen=frozen)
+    D = (lambda x: denoise(x, sigma_px, radius_d)) if sigma_px is not None else (lambda x: x)
+    cs, rs = [], []
+    c = np.array(c0, dtype=np.float64)
+    for _ in range(n_iter):
+        res = M.forward(c) - s
+        cs.append(c)
+        rs.append(res)
+        c = D(c - tau * M.adjoint(res))
+    loss = float(np.sum((c - c_true) ** 2))
+    gbar = 2.0 * (c - c_true)
+    gh = gax = gay = 0.0
+    for k in reversed(range(n_iter)):
+        gu = D(gbar)
+        q = M.forward(gu)
+        gh += -tau * (np.sum(M.forward_dh(gu) * rs[k]) + np.sum(q * M.forward_dh(cs[k])))
+        gr1, gv1 = M.traj_vjp(gu, rs[k])
+        gr2, gv2 = M.traj_vjp(cs[k], q)
+        gr, gv = gr1 + gr2, gv1 + gv2
+        gax += -tau * (np.sum(gr[:, 0] * rho[:, 0]) + np.sum(gv[:, 0] * nu[:, 0]))
+        gay += -tau * (np.sum(gr[:, 1] * rho[:, 1]) + np.sum(gv[:, 1] * nu[:, 1]))
+        gbar = gu - tau * M.adjoint(q)
+    return loss, {"c0": gbar, "h": gh, "ax": gax, "ay": gay}
 
 
 def power_lambda_max(model: Model, iters: int = 100, seed: int = 0) -> float:
