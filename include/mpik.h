@@ -153,8 +153,12 @@ enum { MPI_BUILD_TUNE = 1 };
  * shape.  Both compute the same values; they may differ in the last bit
  * because the channel sum is contracted into multiply-adds differently. */
 enum { MPI_BUILD_COL_SPLIT = 2, MPI_BUILD_COL_WAVE = 4 };
+/* Also build the tables of dK_h/dh (plan memory grows by one table or one set
+ * of spectra per problem); needed by mpi_batch_forward_dh. */
+enum { MPI_BUILD_DERIV = 8 };
 
-int mpi_batch_bytes(const mpi_problem* probs, int count, size_t* plan_bytes, size_t* work_bytes);
+/* Plan and work bytes of a batch built with `flags` (MPI_BUILD_*). */
+int mpi_batch_bytes(const mpi_problem* probs, int count, int flags, size_t* plan_bytes, size_t* work_bytes);
 int mpi_batch_build(const mpi_problem* probs, int count, void* plan_mem, size_t plan_bytes,
                     void* work, size_t work_bytes, int flags, hipStream_t stream, mpi_plan** out);
 int mpi_batch_count(const mpi_plan* plan);
@@ -173,6 +177,50 @@ int mpi_batch_adjoint(const mpi_plan* plan, const void* s_all, void* c_all,
 int mpi_batch_iterate(const mpi_plan* plan, const void* s_all, void* c_all,
                       const mpi_iter_params* params, const double* taus,
                       void* work, size_t work_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------ derivatives --
+ * Building blocks of hand-written vector-Jacobian products, all batched like
+ * mpi_batch_forward (concatenated buffers, one launch per stage):
+ *
+ * mpi_batch_forward_dh: s = (dA/dh) x -- the sampling and contraction of the
+ *   convolution of x with delta^2 dK_h/dh, where dK_h/dh =
+ *   -h^-2 [(L'(r) + r L''(r)) P + L'(r)(I - P)] (r = |y|/h, P = y y^T/|y|^2;
+ *   -I/(3h^2) at the origin), the h-derivative of K_h(y) = K(y/h)/h of
+ *   eq. kernel:matrix.  Needs a plan built with MPI_BUILD_DERIV.
+ *
+ * mpi_batch_residual: out = A c - y (y and out signal-shaped, time order).
+ *
+ * mpi_batch_traj_vjp: for the field G = K_h * x and signal-shaped y, the
+ *   gradients of <y, A x> with respect to every sample's position and
+ *   velocity: g_r[k] = (y_k^T M(dG/dx) v_k, y_k^T M(dG/dy) v_k),
+ *   g_v[k] = M(G(r_k)) y_k, with M(g) the symmetric 2x2 field and the spatial
+ *   derivatives taken inside the sample's bilinear patch (its base cell held
+ *   fixed; the interpolant is only piecewise smooth).  Time order, [T][2].
+ *
+ * mpi_batch_adjoint_step: c_out = c_in - taus[b] A^T s (s in time order;
+ *   c_in may equal c_out).  taus is a host array of count values.
+ *
+ * mpi_batch_denoise: c = D(u), the separable Gaussian of mpi_iter_params
+ *   (sigma_px > 0, radius 0..8, weights summing to 1, zero padding); u != c.
+ *   D is symmetric, so it is also its own transpose.
+ *
+ * mpi_batch_dot: out[b] = sum a_b . b_b in float64 for every problem, with a
+ *   fixed summation order (deterministic).  space 0: signal-shaped arrays
+ *   (comp 0: x components only, 1: y only, 2: both); space 1: concentration-
+ *   shaped.  out: device array of count doubles. */
+int mpi_batch_forward_dh(const mpi_plan* plan, const void* x_all, void* s_all,
+                         void* work, size_t work_bytes, hipStream_t stream);
+int mpi_batch_residual(const mpi_plan* plan, const void* c_all, const void* y_all, void* out_all,
+                       void* work, size_t work_bytes, hipStream_t stream);
+int mpi_batch_traj_vjp(const mpi_plan* plan, const void* x_all, const void* y_all,
+                       void* g_r_all, void* g_v_all, void* work, size_t work_bytes, hipStream_t stream);
+int mpi_batch_adjoint_step(const mpi_plan* plan, const void* s_all, const void* c_in_all,
+                           void* c_out_all, const double* taus, void* work, size_t work_bytes,
+                           hipStream_t stream);
+int mpi_batch_denoise(const mpi_plan* plan, const void* u_all, void* c_all, double sigma_px,
+                      int radius, void* work, size_t work_bytes, hipStream_t stream);
+int mpi_batch_dot(const mpi_plan* plan, const void* a_all, const void* b_all, int space, int comp,
+                  double* out, void* work, size_t work_bytes, hipStream_t stream);
 
 /* Diagnostics for timing one kernel at a time.  The forward operator and its
  * transpose each run as a short sequence of kernels (stages); stages

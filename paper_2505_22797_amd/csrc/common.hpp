@@ -51,6 +51,8 @@ struct Prob {
     // plan memory
     int64_t o_taps;      // T [3][2R+1][taps_w]   delta^2 K_h (direct path)
     int64_t o_spec;      // T [3][M/2+1][M/2+1]   delta^2/M^2 * DFT of K_h, [ch][kx][ky]
+    int64_t o_taps_dh;   // as o_taps for dK_h/dh (plans built for derivatives), else 0
+    int64_t o_spec_dh;   // as o_spec for dK_h/dh, else 0
     int64_t o_tw;        // cx<T> [M]             e^{-2 pi i k / M}
     int64_t o_samp;      // vec4<T> [T]           (fx, fy, vx, vy) in cell order
     int64_t o_sidx;      // int2 [T]              (base cell i0 | j0 << 16, time index), cell order

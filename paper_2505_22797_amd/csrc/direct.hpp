@@ -49,7 +49,7 @@ template <typename T, int CIN, int COUT, int S, int EPI>
 __global__ void __launch_bounds__(64 * S) k_conv_direct(const Prob* __restrict__ P, const T* in, T* out,
                                                         const T* c_in, const double* __restrict__ taus,
                                                         const char* __restrict__ plan, int in_is_caller,
-                                                        int out_is_caller) {
+                                                        int out_is_caller, int dh) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.z];
     if (p.mode != 0 || p.slices != S) return;
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(64 * S) k_conv_direct(const Prob* __restrict__
     __syncthreads();
     const int wave = uniform(tid / kWave), lane = tid % kWave;
     const int ly = lane / 4, sx = (lane % 4) * kStrip;
-    const T* taps = at<T>(plan, p.o_taps);
+    const T* taps = at<T>(plan, dh ? p.o_taps_dh : p.o_taps);   // dK/dh for the h-derivative
     const int W = 2 * R + 1;
     T acc[COUT][kStrip];
 #pragma unroll
@@ -142,8 +142,8 @@ __global__ void __launch_bounds__(64 * S) k_conv_direct(const Prob* __restrict__
 
 // Bilinear gather + contraction for base-cell row b from a field in global
 // memory ([3][N][N]): rows b and b+1 are staged in LDS first.
-template <typename T, bool RESID>
-__global__ void __launch_bounds__(256) k_gather_rows(const Prob* __restrict__ P, T* __restrict__ s,
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_gather_rows(const Prob* __restrict__ P, T* out0, const T* in0, T* out1,
                                                      const char* __restrict__ plan, char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
@@ -161,9 +161,9 @@ __global__ void __launch_bounds__(256) k_gather_rows(const Prob* __restrict__ P,
         g0[i] = G[int64_t(ch) * N * N + int64_t(b + half) * N + x];
     }
     __syncthreads();
-    gather_band<T, RESID>(g0, g1, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
-                          at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res), s + p.o_s, threadIdx.x,
-                          blockDim.x);
+    gather_band<T, MODE>(g0, g1, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
+                         at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res), out0 ? out0 + p.o_s : nullptr,
+                         in0 ? in0 + p.o_s : nullptr, out1 ? out1 + p.o_s : nullptr, threadIdx.x, blockDim.x);
 }
 
 // Deterministic transpose sampling for one grid row into a field in global
@@ -208,16 +208,19 @@ __global__ void k_permute_signal(const Prob* __restrict__ P, const T* __restrict
 constexpr int kDnTile = 32;
 constexpr int kDnMaxR = 8;
 
+// u is read from the problem's work buffer, or from the caller's buffer u_in
+// (concentration-shaped) when that is given.
 template <typename T>
 __global__ void __launch_bounds__(256) k_denoise(const Prob* __restrict__ P, const char* __restrict__ work,
-                                                 T* __restrict__ c, const double* __restrict__ wts, int rad) {
+                                                 const T* __restrict__ u_in, T* __restrict__ c,
+                                                 const double* __restrict__ wts, int rad) {
     __shared__ T a[(kDnTile + 2 * kDnMaxR) * (kDnTile + 2 * kDnMaxR)];
     __shared__ T b[(kDnTile + 2 * kDnMaxR) * kDnTile];
     const Prob& p = P[blockIdx.z];
     const int N = p.n;
     const int y0 = blockIdx.y * kDnTile, x0 = blockIdx.x * kDnTile;
     if (y0 >= N || x0 >= N) return;
-    const T* up = at<T>(work, p.w_u);
+    const T* up = u_in ? u_in + p.o_c : at<T>(work, p.w_u);
     T* cp = c + p.o_c;
     const int L = kDnTile + 2 * rad;
     for (int i = threadIdx.x; i < L * L; i += blockDim.x) {
@@ -242,6 +245,38 @@ __global__ void __launch_bounds__(256) k_denoise(const Prob* __restrict__ P, con
         for (int k = 0; k <= 2 * rad; ++k) s += T(wts[k]) * b[ly * L + lx + k];
         cp[int64_t(gy) * N + gx] = s;
     }
+}
+
+// Deterministic per-problem dot products: out[b] = sum_i a_b[i] b_b[i] in
+// float64, one work-group per problem, fixed strided partition and a fixed
+// reduction tree.  space 0: signal arrays ([T][2], comp 0 = x components
+// only, 1 = y only, 2 = both); space 1: concentration arrays ([N][N]).
+template <typename T>
+__global__ void __launch_bounds__(1024) k_dot(const Prob* __restrict__ P, const T* __restrict__ a,
+                                              const T* __restrict__ bb, int space, int comp,
+                                              double* __restrict__ out) {
+    __shared__ double part[1024];
+    const Prob& p = P[blockIdx.x];
+    const int tid = threadIdx.x;
+    int64_t n, off, stride = 1, first = 0;
+    if (space == 0) {
+        off = p.o_s;
+        n = 2 * p.t;
+        if (comp != 2) { stride = 2; first = comp; }
+    } else {
+        off = p.o_c;
+        n = int64_t(p.n) * p.n;
+    }
+    double acc = 0.0;
+    for (int64_t i = first + int64_t(tid) * stride; i < n; i += int64_t(1024) * stride)
+        acc += double(a[off + i]) * double(bb[off + i]);
+    part[tid] = acc;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (tid < w) part[tid] += part[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) out[blockIdx.x] = part[0];
 }
 
 }  // namespace mpik

@@ -147,11 +147,12 @@ __device__ void fwd_rows_body(const Prob& p, const T* __restrict__ c, const char
 // channel the product with its spectrum, the inverse FFT and rows 0..N-1 of
 // the result to T2[ch][row][kx].
 template <typename T, int M, bool SPLIT>
-__device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char* __restrict__ work, char* smem) {
+__device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char* __restrict__ work, char* smem,
+                              int dh) {
     auto& sm = *reinterpret_cast<ColSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    const T* spec = at<T>(plan, p.o_spec);
+    const T* spec = at<T>(plan, dh ? p.o_spec_dh : p.o_spec);   // dK/dh for the h-derivative
     cx<T>* t2 = at<cx<T>>(work, p.w_t2);
     if (SPLIT) {                                    // one column, waves 0..2
         const int kx = xcd_unit(blockIdx.x, H);
@@ -199,9 +200,10 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
     }
 }
 
-template <typename T, int M, bool RESID>
-__device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ s, const char* __restrict__ plan,
-                                     char* __restrict__ work, char* smem) {
+template <typename T, int M, int MODE>
+__device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const T* __restrict__ in0,
+                                     T* __restrict__ out1, const char* __restrict__ plan, char* __restrict__ work,
+                                     char* smem) {
     auto& sm = *reinterpret_cast<GatherSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
     const int N = p.n, nb = p.nb, b = xcd_unit(blockIdx.x, nb);
@@ -228,8 +230,8 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ s, const cha
         }
     }
     __syncthreads();
-    gather_band<T, RESID>(g0, g1, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
-                          at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res), s, tid, 4 * kWave);
+    gather_band<T, MODE>(g0, g1, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
+                         at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res), out0, in0, out1, tid, 4 * kWave);
 }
 
 // ----------------------------------------------------------------- adjoint ---
@@ -397,21 +399,24 @@ __global__ void __launch_bounds__(256) k_fwd_rows(const Prob* __restrict__ P, co
 // SPLIT: grid.x = xcd_grid(M/2 + 1), 192 threads; else xcd_grid(ceil((M/2 + 1)/4)), 256 threads
 template <typename T, bool SPLIT>
 __global__ void __launch_bounds__(256) k_fwd_cols(const Prob* __restrict__ P, const char* __restrict__ plan,
-                                                  char* __restrict__ work) {
+                                                  char* __restrict__ work, int dh) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
     if (p.mode != 1) return;
-    MPIK_DISPATCH_M(p.m, (fwd_cols_body<T, MM, SPLIT>(p, plan, work, smem)));
+    MPIK_DISPATCH_M(p.m, (fwd_cols_body<T, MM, SPLIT>(p, plan, work, smem, dh)));
 }
 
-// grid.x: xcd_grid(base-cell rows), 256 threads
-template <typename T, bool RESID>
-__global__ void __launch_bounds__(256) k_fwd_rows_gather(const Prob* __restrict__ P, T* __restrict__ s,
+// grid.x: xcd_grid(base-cell rows), 256 threads.  MODE as gather_band; the
+// caller buffers out0, in0, out1 are signal-shaped (offset by the problem's o_s).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_fwd_rows_gather(const Prob* __restrict__ P, T* out0, const T* in0, T* out1,
                                                          const char* __restrict__ plan, char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
     if (p.mode != 1) return;
-    MPIK_DISPATCH_M(p.m, (fwd_rows_gather_body<T, MM, RESID>(p, s + p.o_s, plan, work, smem)));
+    MPIK_DISPATCH_M(p.m, (fwd_rows_gather_body<T, MM, MODE>(p, out0 ? out0 + p.o_s : nullptr,
+                                                           in0 ? in0 + p.o_s : nullptr,
+                                                           out1 ? out1 + p.o_s : nullptr, plan, work, smem)));
 }
 
 // grid.x: xcd_grid(grid rows), 256 threads

@@ -133,7 +133,7 @@ size_t take(size_t& off, size_t bytes) {
 
 // Lays out one problem's plan buffers from `poff` and its work buffers from
 // `woff` (both advanced).  `both`: room for either convolution path (tuning).
-void layout_problem(const Shape& sh, int mode, bool both, size_t& poff, size_t& woff, Prob& p) {
+void layout_problem(const Shape& sh, int mode, bool both, bool deriv, size_t& poff, size_t& woff, Prob& p) {
     const int N = sh.n, R = sh.R, nb = N - 1, M = sh.M, H = M / 2 + 1, W = 2 * R + 1, e = sh.elem;
     const int64_t T = sh.T;
     std::memset(&p, 0, sizeof(p));
@@ -153,6 +153,8 @@ void layout_problem(const Shape& sh, int mode, bool both, size_t& poff, size_t& 
         p.o_spec = take(poff, size_t(3) * H * H * e);
         p.o_tw = take(poff, size_t(M) * 2 * e);
     }
+    if (deriv && dir) p.o_taps_dh = take(poff, size_t(3) * W * p.taps_w * e);
+    if (deriv && fft) p.o_spec_dh = take(poff, size_t(3) * H * H * e);
     p.o_samp = take(poff, size_t(T) * 4 * e);
     p.o_sidx = take(poff, size_t(T) * 8);
     p.o_binstart = take(poff, (size_t(nb) * nb + 1) * 4);
@@ -192,6 +194,7 @@ struct BatchLayout {
     size_t w_taus = 0, w_wts = 0;
     int64_t c_elems = 0, s_elems = 0;
     int elem = 4;
+    bool deriv = false;
 };
 
 // Path before tuning: direct for small windows, FFT otherwise.
@@ -202,8 +205,9 @@ int default_mode(const Shape& sh, int requested) {
     return sh.fft_ok ? 1 : 0;
 }
 
-int make_batch_layout(const mpi_problem* probs, int count, BatchLayout& B) {
+int make_batch_layout(const mpi_problem* probs, int count, int flags, BatchLayout& B) {
     if (!probs || count < 1 || count > kMaxBatch) return MPI_ERR_ARG;
+    B.deriv = (flags & MPI_BUILD_DERIV) != 0;
     B.shapes.resize(count);
     B.probs.resize(count);
     B.requested.resize(count);
@@ -220,7 +224,7 @@ int make_batch_layout(const mpi_problem* probs, int count, BatchLayout& B) {
     for (int b = 0; b < count; ++b) {
         const Shape& sh = B.shapes[b];
         const bool both = B.requested[b] == MPI_CONV_AUTO && sh.fft_ok && sh.direct_ok;
-        layout_problem(sh, default_mode(sh, B.requested[b]), both, poff, woff, B.probs[b]);
+        layout_problem(sh, default_mode(sh, B.requested[b]), both, B.deriv, poff, woff, B.probs[b]);
         B.probs[b].h = probs[b].h;
         B.probs[b].o_c = co;
         B.probs[b].o_s = so;
@@ -327,8 +331,10 @@ hipError_t set_smem_limits(const mpi_plan* pl) {
     chk(allow_smem(k_fwd_cols<T, false>, pl->smem_col));
     chk(allow_smem(k_adj_cols<T, true>, pl->smem_col));
     chk(allow_smem(k_adj_cols<T, false>, pl->smem_col));
-    chk(allow_smem(k_fwd_rows_gather<T, false>, pl->smem_gather));
-    chk(allow_smem(k_fwd_rows_gather<T, true>, pl->smem_gather));
+    chk(allow_smem(k_fwd_rows_gather<T, 0>, pl->smem_gather));
+    chk(allow_smem(k_fwd_rows_gather<T, 1>, pl->smem_gather));
+    chk(allow_smem(k_fwd_rows_gather<T, 2>, pl->smem_gather));
+    chk(allow_smem(k_fwd_rows_gather<T, 3>, pl->smem_gather));
     chk(allow_smem(k_adj_scatter_row<T, false>, pl->smem_scatter));
     chk(allow_smem(k_adj_scatter_row<T, true>, pl->smem_scatter));
     chk(allow_smem(k_adj_rows<T, 0>, pl->smem_row));
@@ -346,8 +352,10 @@ hipError_t set_smem_limits(const mpi_plan* pl) {
     chk(allow_smem(k_conv_direct<T, 3, 1, 8, 2>, pl->smem_dadj));
     chk(allow_smem(k_conv_direct<T, 3, 1, 16, 2>, pl->smem_dadj));
     chk(allow_smem(k_adj_rows<T, 2>, pl->smem_row));
-    chk(allow_smem(k_gather_rows<T, false>, pl->smem_dgather));
-    chk(allow_smem(k_gather_rows<T, true>, pl->smem_dgather));
+    chk(allow_smem(k_gather_rows<T, 0>, pl->smem_dgather));
+    chk(allow_smem(k_gather_rows<T, 1>, pl->smem_dgather));
+    chk(allow_smem(k_gather_rows<T, 2>, pl->smem_dgather));
+    chk(allow_smem(k_gather_rows<T, 3>, pl->smem_dgather));
     chk(allow_smem(k_scatter_rows<T, false>, pl->smem_dscatter));
     chk(allow_smem(k_scatter_rows<T, true>, pl->smem_dscatter));
     return e;
@@ -378,6 +386,19 @@ int build_problem(const mpi_problem* d, const BatchLayout& B, int b, char* plan,
         k_spec_rows<<<blocks(int64_t(3) * (R + 1) * H, 256), 256, 0, st>>>(P, tab64, cs, U);
         k_spec_cols<T><<<blocks(int64_t(3) * H * H, 256), 256, 0, st>>>(P, U, cs, reinterpret_cast<T*>(plan + p.o_spec));
     }
+    if (p.o_taps_dh || p.o_spec_dh) {   // the same tables for dK_h/dh
+        T* taps_dh = p.o_taps_dh ? reinterpret_cast<T*>(plan + p.o_taps_dh) : nullptr;
+        k_table<T><<<blocks(int64_t(W) * W, 256), 256, 0, st>>>(P, plan, series, tab64, taps_dh, 1);
+        if (taps_dh && p.taps_w > W)
+            k_taps_pad<T><<<blocks(int64_t(3) * W * (p.taps_w - W), 256), 256, 0, st>>>(P, taps_dh);
+        if (p.o_spec_dh) {
+            double* cs = reinterpret_cast<double*>(plan + sc.cs);
+            double* U = reinterpret_cast<double*>(plan + sc.U);
+            k_spec_rows<<<blocks(int64_t(3) * (R + 1) * H, 256), 256, 0, st>>>(P, tab64, cs, U);
+            k_spec_cols<T><<<blocks(int64_t(3) * H * H, 256), 256, 0, st>>>(P, U, cs,
+                                                                             reinterpret_cast<T*>(plan + p.o_spec_dh));
+        }
+    }
     int* cell = reinterpret_cast<int*>(plan + sc.cell);
     double* frac = reinterpret_cast<double*>(plan + sc.frac);
     int* bincount = reinterpret_cast<int*>(plan + sc.bincount);
@@ -398,24 +419,26 @@ constexpr int kAdjStages = 5;
 
 template <typename T, int S, int EPI>
 void launch_direct_conv(const mpi_plan* pl, bool fwd, const T* in, T* out, const T* c_in, const double* taus,
-                        hipStream_t st) {
+                        hipStream_t st, int dh = 0) {
     // EPI 2 addresses the work buffer u: `out` is then the work base
     constexpr int bit = S == 4 ? 0 : (S == 8 ? 1 : 2);
     if (!(pl->slice_mask & (1 << bit))) return;
     const dim3 grid(pl->max_tiles, pl->max_tiles, pl->count);
     if (fwd)
         k_conv_direct<T, 1, 3, S, 0><<<grid, 64 * S, pl->smem_dfwd, st>>>(pl->dprob, in, out, nullptr, nullptr,
-                                                                          pl->plan, 1, 0);
+                                                                          pl->plan, 1, 0, dh);
     else
         k_conv_direct<T, 3, 1, S, EPI><<<grid, 64 * S, pl->smem_dadj, st>>>(pl->dprob, in, out, c_in, taus,
-                                                                            pl->plan, 0, 1);
+                                                                            pl->plan, 0, 1, 0);
 }
 
 // Forward: FFT {rows, columns, rows + gather}, direct {convolution, gather}.
-// RESID: write A c - y in cell order to the work buffer instead of A c in
-// time order to s.
-template <typename T, bool RESID>
-void fwd_stage(const mpi_plan* pl, int k, const T* c, T* s, char* work, hipStream_t st) {
+// MODE 0: A c (or dA/dh c with dh) to out0 in time order; 1: A c - y in cell
+// order to the work buffer; 2: trajectory gradients of <in0, A c> to out0
+// (positions) and out1 (velocities).
+template <typename T, int MODE>
+void fwd_stage(const mpi_plan* pl, int k, const T* c, T* out0, const T* in0, T* out1, char* work, hipStream_t st,
+               int dh = 0) {
     const char* plan = pl->plan;
     const Prob* P = pl->dprob;
     const int B = pl->count;
@@ -428,19 +451,24 @@ void fwd_stage(const mpi_plan* pl, int k, const T* c, T* s, char* work, hipStrea
             break;
         case 1:
             if (pl->col_split)
-                k_fwd_cols<T, true><<<dim3(xcd_grid(pl->max_h), B), 192, pl->smem_col, st>>>(P, plan, work);
+                k_fwd_cols<T, true><<<dim3(xcd_grid(pl->max_h), B), 192, pl->smem_col, st>>>(P, plan, work, dh);
             else
-                k_fwd_cols<T, false><<<dim3(xcd_grid((pl->max_h + 3) / 4), B), 256, pl->smem_col, st>>>(P, plan, work);
+                k_fwd_cols<T, false><<<dim3(xcd_grid((pl->max_h + 3) / 4), B), 256, pl->smem_col, st>>>(P, plan,
+                                                                                                     work, dh);
             break;
         case 2:
-            k_fwd_rows_gather<T, RESID><<<dim3(xcd_grid(pl->max_nb), B), 256, pl->smem_gather, st>>>(P, s, plan, work);
+            k_fwd_rows_gather<T, MODE><<<dim3(xcd_grid(pl->max_nb), B), 256, pl->smem_gather, st>>>(
+                P, out0, in0, out1, plan, work);
             break;
         case 3:
-            launch_direct_conv<T, 4, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st);
-            launch_direct_conv<T, 8, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st);
-            launch_direct_conv<T, 16, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st);
+            launch_direct_conv<T, 4, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st, dh);
+            launch_direct_conv<T, 8, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st, dh);
+            launch_direct_conv<T, 16, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st, dh);
             break;
-        case 4: k_gather_rows<T, RESID><<<dim3(pl->max_nb, B), 256, pl->smem_dgather, st>>>(P, s, plan, work); break;
+        case 4:
+            k_gather_rows<T, MODE><<<dim3(pl->max_nb, B), 256, pl->smem_dgather, st>>>(P, out0, in0, out1, plan,
+                                                                                       work);
+            break;
         default: break;
     }
 }
@@ -487,8 +515,20 @@ void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, c
 }
 
 template <typename T>
-int forward_impl(const mpi_plan* pl, const T* c, T* s, char* work, hipStream_t st) {
-    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, false>(pl, k, c, s, work, st);
+int forward_impl(const mpi_plan* pl, const T* c, T* s, char* work, hipStream_t st, int dh = 0) {
+    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 0>(pl, k, c, s, nullptr, nullptr, work, st, dh);
+    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+}
+
+template <typename T>
+int residual_impl(const mpi_plan* pl, const T* c, const T* y, T* out, char* work, hipStream_t st) {
+    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 3>(pl, k, c, out, y, nullptr, work, st);
+    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+}
+
+template <typename T>
+int traj_vjp_impl(const mpi_plan* pl, const T* x, const T* y, T* g_r, T* g_v, char* work, hipStream_t st) {
+    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 2>(pl, k, x, g_r, y, g_v, work, st);
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
@@ -503,7 +543,7 @@ int adjoint_impl(const mpi_plan* pl, const T* s, T* c_out, const T* c_in, char* 
 // the step lands in c directly; with one, in work.u and then D(u) -> c.
 template <typename T>
 int iteration_impl(const mpi_plan* pl, T* c, bool denoise, int rad, char* work, hipStream_t st) {
-    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, true>(pl, k, c, nullptr, work, st);
+    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 1>(pl, k, c, nullptr, nullptr, nullptr, work, st);
     int rc;
     if (!denoise) {
         rc = adjoint_impl<T, true, 1>(pl, nullptr, c, c, work, st);
@@ -511,7 +551,7 @@ int iteration_impl(const mpi_plan* pl, T* c, bool denoise, int rad, char* work, 
         rc = adjoint_impl<T, true, 2>(pl, nullptr, reinterpret_cast<T*>(work), c, work, st);
         if (rc == MPI_OK)
             k_denoise<T><<<dim3(pl->max_dntiles, pl->max_dntiles, pl->count), 256, 0, st>>>(
-                pl->dprob, work, c, reinterpret_cast<const double*>(work + pl->L.w_wts), rad);
+                pl->dprob, work, nullptr, c, reinterpret_cast<const double*>(work + pl->L.w_wts), rad);
     }
     if (rc != MPI_OK) return rc;
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
@@ -685,7 +725,7 @@ int build_common(const mpi_problem* probs, int count, void* plan_mem, size_t pla
     if (!out) return MPI_ERR_ARG;
     *out = nullptr;
     BatchLayout L;
-    int rc = make_batch_layout(probs, count, L);
+    int rc = make_batch_layout(probs, count, flags, L);
     if (rc != MPI_OK) return rc;
     if (!plan_mem || misaligned(plan_mem, kAlign)) return MPI_ERR_ARG;
     for (int b = 0; b < count; ++b) {
@@ -805,10 +845,10 @@ const char* mpi_status_str(int status) {
     }
 }
 
-int mpi_batch_bytes(const mpi_problem* probs, int count, size_t* plan_bytes, size_t* work_bytes) {
+int mpi_batch_bytes(const mpi_problem* probs, int count, int flags, size_t* plan_bytes, size_t* work_bytes) {
     if (!plan_bytes || !work_bytes) return MPI_ERR_ARG;
     BatchLayout L;
-    const int rc = make_batch_layout(probs, count, L);
+    const int rc = make_batch_layout(probs, count, flags, L);
     if (rc != MPI_OK) return rc;
     *plan_bytes = L.plan_bytes;
     *work_bytes = L.work_bytes;
@@ -816,7 +856,7 @@ int mpi_batch_bytes(const mpi_problem* probs, int count, size_t* plan_bytes, siz
 }
 
 int mpi_plan_bytes(const mpi_problem* prob, size_t* plan_bytes, size_t* work_bytes) {
-    return mpi_batch_bytes(prob, 1, plan_bytes, work_bytes);
+    return mpi_batch_bytes(prob, 1, 0, plan_bytes, work_bytes);
 }
 
 int mpi_kernel_build(const mpi_problem* prob, void* plan_mem, size_t plan_bytes, hipStream_t stream, mpi_plan** out) {
@@ -917,6 +957,104 @@ int mpi_iterate(const mpi_plan* plan, const void* s, void* c, const mpi_iter_par
     return mpi_batch_iterate(plan, s, c, params, &tau, work, work_bytes, stream);
 }
 
+int mpi_batch_forward_dh(const mpi_plan* plan, const void* x, void* s, void* work, size_t work_bytes,
+                         hipStream_t stream) {
+    int rc = check_call(plan, x, s, work, work_bytes);
+    if (rc != MPI_OK) return rc;
+    if (!plan->L.deriv) return MPI_ERR_UNSUPPORTED;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    char* w = static_cast<char*>(work);
+    return plan->dtype == MPI_F64
+               ? forward_impl<double>(plan, static_cast<const double*>(x), static_cast<double*>(s), w, stream, 1)
+               : forward_impl<float>(plan, static_cast<const float*>(x), static_cast<float*>(s), w, stream, 1);
+}
+
+int mpi_batch_residual(const mpi_plan* plan, const void* c, const void* y, void* out, void* work,
+                       size_t work_bytes, hipStream_t stream) {
+    int rc = check_call(plan, c, y, work, work_bytes);
+    if (rc != MPI_OK) return rc;
+    if (!out || misaligned(out, plan->L.elem)) return MPI_ERR_ARG;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    char* w = static_cast<char*>(work);
+    return plan->dtype == MPI_F64
+               ? residual_impl<double>(plan, static_cast<const double*>(c), static_cast<const double*>(y),
+                                       static_cast<double*>(out), w, stream)
+               : residual_impl<float>(plan, static_cast<const float*>(c), static_cast<const float*>(y),
+                                      static_cast<float*>(out), w, stream);
+}
+
+int mpi_batch_traj_vjp(const mpi_plan* plan, const void* x, const void* y, void* g_r, void* g_v, void* work,
+                       size_t work_bytes, hipStream_t stream) {
+    int rc = check_call(plan, x, y, work, work_bytes);
+    if (rc != MPI_OK) return rc;
+    if (!g_r || !g_v || misaligned(g_r, plan->L.elem) || misaligned(g_v, plan->L.elem)) return MPI_ERR_ARG;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    char* w = static_cast<char*>(work);
+    return plan->dtype == MPI_F64
+               ? traj_vjp_impl<double>(plan, static_cast<const double*>(x), static_cast<const double*>(y),
+                                       static_cast<double*>(g_r), static_cast<double*>(g_v), w, stream)
+               : traj_vjp_impl<float>(plan, static_cast<const float*>(x), static_cast<const float*>(y),
+                                      static_cast<float*>(g_r), static_cast<float*>(g_v), w, stream);
+}
+
+int mpi_batch_adjoint_step(const mpi_plan* plan, const void* s, const void* c_in, void* c_out, const double* taus,
+                           void* work, size_t work_bytes, hipStream_t stream) {
+    int rc = check_call(plan, s, c_in, work, work_bytes);
+    if (rc != MPI_OK) return rc;
+    if (!c_out || misaligned(c_out, plan->L.elem) || !taus) return MPI_ERR_ARG;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    char* w = static_cast<char*>(work);
+    HIP_TRY(hipMemcpyAsync(w + plan->L.w_taus, taus, sizeof(double) * plan->count, hipMemcpyHostToDevice, stream));
+    return plan->dtype == MPI_F64
+               ? adjoint_impl<double, false, 1>(plan, static_cast<const double*>(s), static_cast<double*>(c_out),
+                                                static_cast<const double*>(c_in), w, stream)
+               : adjoint_impl<float, false, 1>(plan, static_cast<const float*>(s), static_cast<float*>(c_out),
+                                               static_cast<const float*>(c_in), w, stream);
+}
+
+int mpi_batch_denoise(const mpi_plan* plan, const void* u, void* c, double sigma_px, int radius, void* work,
+                      size_t work_bytes, hipStream_t stream) {
+    int rc = check_call(plan, u, c, work, work_bytes);
+    if (rc != MPI_OK) return rc;
+    if (!(sigma_px > 0.0) || radius < 0 || radius > kDnMaxR || u == c) return MPI_ERR_ARG;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    mpi_plan* pl = const_cast<mpi_plan*>(plan);
+    char* w = static_cast<char*>(work);
+    double sum = 0.0;
+    for (int k = -radius; k <= radius; ++k) {
+        pl->wts[k + radius] = std::exp(-0.5 * k * k / (sigma_px * sigma_px));
+        sum += pl->wts[k + radius];
+    }
+    for (int k = 0; k <= 2 * radius; ++k) pl->wts[k] /= sum;
+    HIP_TRY(hipMemcpyAsync(w + pl->L.w_wts, pl->wts, sizeof(double) * (2 * radius + 1), hipMemcpyHostToDevice,
+                           stream));
+    const dim3 grid(pl->max_dntiles, pl->max_dntiles, pl->count);
+    if (plan->dtype == MPI_F64)
+        k_denoise<double><<<grid, 256, 0, stream>>>(pl->dprob, w, static_cast<const double*>(u),
+                                                    static_cast<double*>(c),
+                                                    reinterpret_cast<const double*>(w + pl->L.w_wts), radius);
+    else
+        k_denoise<float><<<grid, 256, 0, stream>>>(pl->dprob, w, static_cast<const float*>(u),
+                                                   static_cast<float*>(c),
+                                                   reinterpret_cast<const double*>(w + pl->L.w_wts), radius);
+    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+}
+
+int mpi_batch_dot(const mpi_plan* plan, const void* a, const void* b, int space, int comp, double* out, void* work,
+                  size_t work_bytes, hipStream_t stream) {
+    int rc = check_call(plan, a, b, work, work_bytes);
+    if (rc != MPI_OK) return rc;
+    if (!out || (space != 0 && space != 1) || comp < 0 || comp > 2) return MPI_ERR_ARG;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    if (plan->dtype == MPI_F64)
+        k_dot<double><<<plan->count, 1024, 0, stream>>>(plan->dprob, static_cast<const double*>(a),
+                                                        static_cast<const double*>(b), space, comp, out);
+    else
+        k_dot<float><<<plan->count, 1024, 0, stream>>>(plan->dprob, static_cast<const float*>(a),
+                                                       static_cast<const float*>(b), space, comp, out);
+    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+}
+
 int mpi_stage_count(const mpi_plan* plan) {
     if (!plan) return MPI_ERR_ARG;
     return kFwdStages + kAdjStages;
@@ -938,13 +1076,15 @@ int mpi_stage_launch(const mpi_plan* plan, int stage, int reps, void* c, void* s
     for (int r = 0; r < reps; ++r) {
         if (plan->dtype == MPI_F64) {
             if (stage < kFwdStages)
-                fwd_stage<double, false>(plan, stage, static_cast<const double*>(c), static_cast<double*>(s), w, stream);
+                fwd_stage<double, 0>(plan, stage, static_cast<const double*>(c), static_cast<double*>(s), nullptr,
+                                     nullptr, w, stream);
             else
                 adj_stage<double, false, 0>(plan, stage - kFwdStages, static_cast<const double*>(s),
                                             static_cast<double*>(c), nullptr, w, stream);
         } else {
             if (stage < kFwdStages)
-                fwd_stage<float, false>(plan, stage, static_cast<const float*>(c), static_cast<float*>(s), w, stream);
+                fwd_stage<float, 0>(plan, stage, static_cast<const float*>(c), static_cast<float*>(s), nullptr,
+                                    nullptr, w, stream);
             else
                 adj_stage<float, false, 0>(plan, stage - kFwdStages, static_cast<const float*>(s),
                                            static_cast<float*>(c), nullptr, w, stream);

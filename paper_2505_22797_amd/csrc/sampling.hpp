@@ -17,12 +17,20 @@ namespace mpik {
 
 // Gather for the samples of base-cell row b (cell order [p0, p1)).  g0/g1 hold
 // the three channels of grid rows b and b+1: g0[ch * N + i], g1[ch * N + i].
-// RESID: write s - y (cell order) to out_sorted[p]; else s to s_time[k].
-template <typename T, bool RESID, int U = 4>
+// MODE 0: s = G(r_k) v_k to out0[k] (time order).
+// MODE 1: s - y (y = ysort, cell order) to out_sorted[p].
+// MODE 3: s - y (y = in0, time order) to out0[k].
+// MODE 2: the gradients of <y, s> (y = in0, time order) with respect to the
+//         sample position and velocity, inside the bilinear patch:
+//         out0[k] = (y^T M(dG/dx) v, y^T M(dG/dy) v), out1[k] = M(G) y,
+//         with M(g) = [[g_xx, g_xy], [g_xy, g_yy]] and d/dx = (N/2) d/dfx.
+template <typename T, int MODE, int U = 4>
 __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int p0, int p1,
                                             const vec4<T>* __restrict__ samp, const int2* __restrict__ sidx,
                                             const vec2<T>* __restrict__ ysort, vec2<T>* __restrict__ out_sorted,
-                                            T* __restrict__ s_time, int tid, int nthreads) {
+                                            T* __restrict__ out0, const T* __restrict__ in0, T* __restrict__ out1,
+                                            int tid, int nthreads) {
+    const T inv_d = T(0.5) * T(N);
     for (int base = p0 + tid; base < p1; base += U * nthreads) {
         vec4<T> e[U];
         int2 id[U];
@@ -33,7 +41,17 @@ __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int
             if (p < p1) {
                 e[u] = samp[p];
                 id[u] = sidx[p];
-                if (RESID) y[u] = ysort[p];
+                if (MODE == 1) y[u] = ysort[p];
+            }
+        }
+        if (MODE == 2 || MODE == 3) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = base + u * nthreads;
+                if (p < p1) {
+                    y[u].x = in0[2 * id[u].y];
+                    y[u].y = in0[2 * id[u].y + 1];
+                }
             }
         }
 #pragma unroll
@@ -42,24 +60,42 @@ __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int
             if (p >= p1) break;
             const int i0 = id[u].x & 0xffff;
             const T fx = e[u].x, fy = e[u].y, gx = T(1) - fx, gy = T(1) - fy;
-            T g[3];
+            T g[3], dx[3], dy[3];
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
-                const T lo = gx * g0[ch * N + i0] + fx * g0[ch * N + i0 + 1];
-                const T hi = gx * g1[ch * N + i0] + fx * g1[ch * N + i0 + 1];
+                const T a00 = g0[ch * N + i0], a10 = g0[ch * N + i0 + 1];
+                const T a01 = g1[ch * N + i0], a11 = g1[ch * N + i0 + 1];
+                const T lo = gx * a00 + fx * a10;
+                const T hi = gx * a01 + fx * a11;
                 g[ch] = gy * lo + fy * hi;
+                if (MODE == 2) {
+                    dx[ch] = inv_d * (gy * (a10 - a00) + fy * (a11 - a01));
+                    dy[ch] = inv_d * (gx * (a01 - a00) + fx * (a11 - a10));
+                }
             }
-            const T sx = g[0] * e[u].z + g[1] * e[u].w;
-            const T sy = g[1] * e[u].z + g[2] * e[u].w;
-            if (RESID) {
-                vec2<T> o;
-                o.x = sx - y[u].x;
-                o.y = sy - y[u].y;
-                out_sorted[p] = o;
+            const T vx = e[u].z, vy = e[u].w;
+            const int k = id[u].y;
+            if (MODE == 2) {
+                const T yx = y[u].x, yy = y[u].y;
+                out0[2 * k] = yx * (dx[0] * vx + dx[1] * vy) + yy * (dx[1] * vx + dx[2] * vy);
+                out0[2 * k + 1] = yx * (dy[0] * vx + dy[1] * vy) + yy * (dy[1] * vx + dy[2] * vy);
+                out1[2 * k] = g[0] * yx + g[1] * yy;
+                out1[2 * k + 1] = g[1] * yx + g[2] * yy;
             } else {
-                const int k = id[u].y;
-                s_time[2 * k] = sx;
-                s_time[2 * k + 1] = sy;
+                const T sx = g[0] * vx + g[1] * vy;
+                const T sy = g[1] * vx + g[2] * vy;
+                if (MODE == 1) {
+                    vec2<T> o;
+                    o.x = sx - y[u].x;
+                    o.y = sy - y[u].y;
+                    out_sorted[p] = o;
+                } else if (MODE == 3) {
+                    out0[2 * k] = sx - y[u].x;
+                    out0[2 * k + 1] = sy - y[u].y;
+                } else {
+                    out0[2 * k] = sx;
+                    out0[2 * k + 1] = sy;
+                }
             }
         }
     }

@@ -22,9 +22,10 @@ CONV_MODES = {"auto": 0, "direct": 1, "fft": 2}
 EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
            "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
            "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_iterate",
-           "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
+           "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
+           "mpi_batch_dot", "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
            "mpi_plan_destroy", "mpi_status_str", "mpi_abi_version")
-MPI_BUILD_TUNE, MPI_BUILD_COL_SPLIT, MPI_BUILD_COL_WAVE = 1, 2, 4
+MPI_BUILD_TUNE, MPI_BUILD_COL_SPLIT, MPI_BUILD_COL_WAVE, MPI_BUILD_DERIV = 1, 2, 4, 8
 
 
 class MpiError(RuntimeError):
@@ -63,7 +64,8 @@ def lib() -> ctypes.CDLL:
         L.mpi_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int32)]
         i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
-        L.mpi_batch_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.mpi_batch_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz),
+                                      ctypes.POINTER(sz)]
         L.mpi_batch_build.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, vp, sz, vp, sz, ctypes.c_int, vp,
                                       ctypes.POINTER(vp)]
         L.mpi_batch_count.argtypes = [vp]
@@ -73,6 +75,12 @@ def lib() -> ctypes.CDLL:
         L.mpi_batch_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
         L.mpi_batch_iterate.argtypes = [vp, vp, vp, ctypes.POINTER(IterParams), ctypes.POINTER(ctypes.c_double),
                                         vp, sz, vp]
+        L.mpi_batch_forward_dh.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.mpi_batch_residual.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+        L.mpi_batch_traj_vjp.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+        L.mpi_batch_adjoint_step.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+        L.mpi_batch_denoise.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, vp, sz, vp]
+        L.mpi_batch_dot.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, sz, vp]
         L.mpi_stage_count.argtypes = [vp]
         L.mpi_stage_name.argtypes = [vp, ctypes.c_int]
         L.mpi_stage_name.restype = ctypes.c_char_p
@@ -84,7 +92,9 @@ def lib() -> ctypes.CDLL:
         for name in ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
                      "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
                      "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_iterate",
-                     "mpi_stage_count", "mpi_stage_launch", "mpi_plan_destroy", "mpi_abi_version"):
+                     "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
+                     "mpi_batch_dot", "mpi_stage_count", "mpi_stage_launch", "mpi_plan_destroy",
+                     "mpi_abi_version"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -205,6 +215,68 @@ class Plan:
         _check(lib().mpi_stage_launch(self._h, int(stage), int(reps), c.data_ptr(), s.data_ptr(),
                                       self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_stage_launch")
 
+    # ---- derivative building blocks
+    def forward_dh(self, x_all, s_all=None, stream=None):
+        self._flat(x_all, self.c_offsets[-1], "x_all")
+        if s_all is None:
+            s_all = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
+        self._flat(s_all, self.s_offsets[-1], "s_all")
+        _check(lib().mpi_batch_forward_dh(self._h, x_all.data_ptr(), s_all.data_ptr(), self.work.data_ptr(),
+                                          self.work.numel(), _stream(stream)), "mpi_batch_forward_dh")
+        return s_all
+
+    def residual(self, c_all, y_all, out=None, stream=None):
+        """A c - y, time order."""
+        self._flat(c_all, self.c_offsets[-1], "c_all")
+        self._flat(y_all, self.s_offsets[-1], "y_all")
+        if out is None:
+            out = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
+        _check(lib().mpi_batch_residual(self._h, c_all.data_ptr(), y_all.data_ptr(), out.data_ptr(),
+                                        self.work.data_ptr(), self.work.numel(), _stream(stream)),
+               "mpi_batch_residual")
+        return out
+
+    def traj_vjp(self, x_all, y_all, stream=None):
+        self._flat(x_all, self.c_offsets[-1], "x_all")
+        self._flat(y_all, self.s_offsets[-1], "y_all")
+        g_r = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
+        g_v = torch.empty_like(g_r)
+        _check(lib().mpi_batch_traj_vjp(self._h, x_all.data_ptr(), y_all.data_ptr(), g_r.data_ptr(), g_v.data_ptr(),
+                                        self.work.data_ptr(), self.work.numel(), _stream(stream)),
+               "mpi_batch_traj_vjp")
+        return g_r, g_v
+
+    def adjoint_step(self, s_all, c_in, taus, c_out=None, stream=None):
+        self._flat(s_all, self.s_offsets[-1], "s_all")
+        self._flat(c_in, self.c_offsets[-1], "c_in")
+        if c_out is None:
+            c_out = torch.empty_like(c_in)
+        tarr = (ctypes.c_double * self.count)(*[float(t) for t in taus])
+        _check(lib().mpi_batch_adjoint_step(self._h, s_all.data_ptr(), c_in.data_ptr(), c_out.data_ptr(), tarr,
+                                            self.work.data_ptr(), self.work.numel(), _stream(stream)),
+               "mpi_batch_adjoint_step")
+        return c_out
+
+    def denoise(self, u_all, sigma_px=0.5, radius=2, c_out=None, stream=None):
+        self._flat(u_all, self.c_offsets[-1], "u_all")
+        if c_out is None:
+            c_out = torch.empty_like(u_all)
+        _check(lib().mpi_batch_denoise(self._h, u_all.data_ptr(), c_out.data_ptr(), float(sigma_px), int(radius),
+                                       self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_batch_denoise")
+        return c_out
+
+    def dot(self, a, b, space="signal", comp="both", out=None, stream=None):
+        """Per-problem float64 dot products (device tensor of `count`)."""
+        n = self.s_offsets[-1] if space == "signal" else self.c_offsets[-1]
+        self._flat(a, n, "a")
+        self._flat(b, n, "b")
+        if out is None:
+            out = torch.empty(self.count, dtype=torch.float64, device=self.device)
+        _check(lib().mpi_batch_dot(self._h, a.data_ptr(), b.data_ptr(), 0 if space == "signal" else 1,
+                                   {"x": 0, "y": 1, "both": 2}[comp], out.data_ptr(), self.work.data_ptr(),
+                                   self.work.numel(), _stream(stream)), "mpi_batch_dot")
+        return out
+
     def close(self):
         if getattr(self, "_h", None):
             lib().mpi_plan_destroy(self._h)
@@ -222,9 +294,11 @@ class Batch:
     the whole batch.  Concentrations and signals of all problems live
     concatenated in one flat tensor each (see `c_offsets`, `s_offsets`)."""
 
-    def __init__(self, specs, dtype=torch.float32, tune: bool = True, columns: str | None = None, stream=None):
+    def __init__(self, specs, dtype=torch.float32, tune: bool = True, columns: str | None = None,
+                 deriv: bool = False, stream=None):
         """specs: list of (n, h, radius, r, v[, conv_mode]) with r, v device (T, 2).
-        columns: None (by batch size), "split" or "wave": shape of the column-FFT kernels."""
+        columns: None (by batch size), "split" or "wave": shape of the column-FFT kernels.
+        deriv: also build the dK/dh tables (for forward_dh)."""
         keep = []
         arr = (Problem * len(specs))()
         for i, sp in enumerate(specs):
@@ -241,13 +315,13 @@ class Batch:
         self.device = specs[0][3].device
         self.ns = [int(sp[0]) for sp in specs]
         self.ts = [int(sp[3].shape[0]) for sp in specs]
+        flags = (MPI_BUILD_TUNE if tune else 0) | (MPI_BUILD_DERIV if deriv else 0) | {
+            None: 0, "split": MPI_BUILD_COL_SPLIT, "wave": MPI_BUILD_COL_WAVE}[columns]
         pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
-        _check(lib().mpi_batch_bytes(arr, self.count, ctypes.byref(pb), ctypes.byref(wb)), "mpi_batch_bytes")
+        _check(lib().mpi_batch_bytes(arr, self.count, flags, ctypes.byref(pb), ctypes.byref(wb)), "mpi_batch_bytes")
         self.plan_mem = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
         self.work = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
         handle = ctypes.c_void_p()
-        flags = (MPI_BUILD_TUNE if tune else 0) | {None: 0, "split": MPI_BUILD_COL_SPLIT,
-                                                   "wave": MPI_BUILD_COL_WAVE}[columns]
         _check(lib().mpi_batch_build(arr, self.count, self.plan_mem.data_ptr(), pb.value, self.work.data_ptr(),
                                      wb.value, flags, _stream(stream), ctypes.byref(handle)), "mpi_batch_build")
         self._h = handle
@@ -313,6 +387,68 @@ class Batch:
         _check(lib().mpi_batch_iterate(self._h, s_all.data_ptr(), c_all.data_ptr(), ctypes.byref(ip), tarr,
                                        self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_batch_iterate")
         return c_all
+
+    # ---- derivative building blocks
+    def forward_dh(self, x_all, s_all=None, stream=None):
+        self._flat(x_all, self.c_offsets[-1], "x_all")
+        if s_all is None:
+            s_all = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
+        self._flat(s_all, self.s_offsets[-1], "s_all")
+        _check(lib().mpi_batch_forward_dh(self._h, x_all.data_ptr(), s_all.data_ptr(), self.work.data_ptr(),
+                                          self.work.numel(), _stream(stream)), "mpi_batch_forward_dh")
+        return s_all
+
+    def residual(self, c_all, y_all, out=None, stream=None):
+        """A c - y, time order."""
+        self._flat(c_all, self.c_offsets[-1], "c_all")
+        self._flat(y_all, self.s_offsets[-1], "y_all")
+        if out is None:
+            out = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
+        _check(lib().mpi_batch_residual(self._h, c_all.data_ptr(), y_all.data_ptr(), out.data_ptr(),
+                                        self.work.data_ptr(), self.work.numel(), _stream(stream)),
+               "mpi_batch_residual")
+        return out
+
+    def traj_vjp(self, x_all, y_all, stream=None):
+        self._flat(x_all, self.c_offsets[-1], "x_all")
+        self._flat(y_all, self.s_offsets[-1], "y_all")
+        g_r = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
+        g_v = torch.empty_like(g_r)
+        _check(lib().mpi_batch_traj_vjp(self._h, x_all.data_ptr(), y_all.data_ptr(), g_r.data_ptr(), g_v.data_ptr(),
+                                        self.work.data_ptr(), self.work.numel(), _stream(stream)),
+               "mpi_batch_traj_vjp")
+        return g_r, g_v
+
+    def adjoint_step(self, s_all, c_in, taus, c_out=None, stream=None):
+        self._flat(s_all, self.s_offsets[-1], "s_all")
+        self._flat(c_in, self.c_offsets[-1], "c_in")
+        if c_out is None:
+            c_out = torch.empty_like(c_in)
+        tarr = (ctypes.c_double * self.count)(*[float(t) for t in taus])
+        _check(lib().mpi_batch_adjoint_step(self._h, s_all.data_ptr(), c_in.data_ptr(), c_out.data_ptr(), tarr,
+                                            self.work.data_ptr(), self.work.numel(), _stream(stream)),
+               "mpi_batch_adjoint_step")
+        return c_out
+
+    def denoise(self, u_all, sigma_px=0.5, radius=2, c_out=None, stream=None):
+        self._flat(u_all, self.c_offsets[-1], "u_all")
+        if c_out is None:
+            c_out = torch.empty_like(u_all)
+        _check(lib().mpi_batch_denoise(self._h, u_all.data_ptr(), c_out.data_ptr(), float(sigma_px), int(radius),
+                                       self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_batch_denoise")
+        return c_out
+
+    def dot(self, a, b, space="signal", comp="both", out=None, stream=None):
+        """Per-problem float64 dot products (device tensor of `count`)."""
+        n = self.s_offsets[-1] if space == "signal" else self.c_offsets[-1]
+        self._flat(a, n, "a")
+        self._flat(b, n, "b")
+        if out is None:
+            out = torch.empty(self.count, dtype=torch.float64, device=self.device)
+        _check(lib().mpi_batch_dot(self._h, a.data_ptr(), b.data_ptr(), 0 if space == "signal" else 1,
+                                   {"x": 0, "y": 1, "both": 2}[comp], out.data_ptr(), self.work.data_ptr(),
+                                   self.work.numel(), _stream(stream)), "mpi_batch_dot")
+        return out
 
     def close(self):
         if getattr(self, "_h", None):
