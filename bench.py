@@ -113,6 +113,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--profile-batch", action="store_true",
                     help="only a few batched pairs plus a 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -210,6 +211,8 @@ def main() -> int:
 
     if not args.no_uneven:
         out["uneven_batch"] = uneven_batch(mpik, S, dev)
+    if not args.no_grad:
+        out["differentiation"] = differentiation(S, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_seconds)
     print(json.dumps(out))
@@ -281,6 +284,67 @@ def uneven_batch(mpik, S, dev, n_iter=50):
             "sequential_ms": round(ms_seq, 3), "speedup": round(ms_seq / ms_batched, 3),
             "batched_iterations_per_s": round(len(probs) * n_iter * 1e3 / ms_batched, 1),
             "build_and_tune_s": round(build_s, 3), "paths": modes}
+
+
+def differentiation(S, dev, reps=3):
+    """8 problems at 256^2, 53,856 samples, R = 31: the unrolled K = 20
+    denoised solve with checkpoints every 5, forward and hand-written backward
+    (gradients for c0, h and the two trajectory amplitudes), against the plain
+    K = 20 solve at the same shape, plus the rebuild of the plan with the
+    dK/dh tables that every change of h or of the trajectory needs."""
+    import torch
+    from paper_2505_22797_amd import autograd as AG
+    probs = S.gradient_problems(8)
+    B, n, R, T = len(probs), probs[0].n, probs[0].radius, probs[0].n_samples
+    shape = S.lissajous(T, ax=1.0, ay=1.0)
+    rho = torch.tensor(S.to_f32(shape.r), dtype=torch.float32, device=dev)
+    nu = torch.tensor(S.to_f32(shape.v), dtype=torch.float32, device=dev)
+    op = AG.TrajectoryOperator([n] * B, [R] * B, [rho] * B, [nu] * B)
+    h = torch.tensor([p.h * 1.05 for p in probs], dtype=torch.float64)
+    amp = torch.full((B,), S.AMPLITUDE * 0.98, dtype=torch.float64)
+    truth = torch.cat([torch.tensor(S.to_f32(p.c), dtype=torch.float32, device=dev).reshape(-1) for p in probs])
+    plan = op.plan(h, amp, amp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()        # rebuilds at new parameter values, as after an optimiser step
+    for i in range(3):
+        op.plan(h * (1.0 + 1e-4 * (i + 1)), amp, amp)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3 / 3
+    s_all = plan.forward(truth)
+    x = torch.randn_like(truth)          # step 0.9 / lambda_max from a short power iteration
+    for _ in range(10):
+        x = plan.adjoint(plan.forward(x / x.norm()))
+    taus = [0.9 / float(x.norm())] * B
+    K, every, sigma = 20, 5, 0.5
+
+    def grad_step():
+        c0 = torch.zeros_like(truth, requires_grad=True)
+        hh, ax, ay = (t.clone().requires_grad_(True) for t in (h, amp, amp))
+        c = AG.unrolled_solve(op, s_all, c0, hh, ax, ay, taus, n_iter=K, sigma_px=sigma, radius=2, every=every)
+        loss = torch.sum((c - truth) ** 2)
+        return torch.autograd.grad(loss, (c0, hh, ax, ay))
+
+    grad_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        grad_step()
+    torch.cuda.synchronize()
+    grad_ms = (time.perf_counter() - t0) * 1e3 / reps
+    c = torch.zeros_like(truth)
+    plan.iterate(s_all, c, K, taus, sigma, 2)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        plan.iterate(s_all, c, K, taus, sigma, 2)
+    b.record()
+    torch.cuda.synchronize()
+    plain_ms = a.elapsed_time(b) / reps
+    return {"problems": B, "grid": n, "samples": T, "radius": R, "iterations": K, "checkpoint_every": every,
+            "forward_backward_ms": round(grad_ms, 3), "plain_solve_ms": round(plain_ms, 3),
+            "ratio": round(grad_ms / plain_ms, 2), "plan_rebuild_ms": round(build_ms, 3),
+            "gradient_steps_per_s": round(1e3 / (grad_ms + build_ms), 2)}
 
 
 def cpu_baseline(P, budget_s: float) -> dict:

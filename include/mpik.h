@@ -237,6 +237,12 @@ const char* mpi_stage_name(const mpi_plan* plan, int stage);
 int mpi_stage_launch(const mpi_plan* plan, int stage, int reps, void* c, void* s,
                      void* work, size_t work_bytes, hipStream_t stream);
 
+/* The order in which a plan holds problem `index`'s samples: order[i] is the
+ * time index of the i-th sample and cell[i] its base cell (i0 | j0 << 16),
+ * sorted by base cell (j0 major) and by time inside a cell.  Both are device
+ * arrays of T_index int32 entries owned by the caller; enqueued on `stream`. */
+int mpi_batch_sample_order(const mpi_plan* plan, int index, int32_t* order, int32_t* cell, hipStream_t stream);
+
 int mpi_plan_destroy(mpi_plan* plan);
 const char* mpi_status_str(int status);
 int mpi_abi_version(void);

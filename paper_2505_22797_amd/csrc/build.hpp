@@ -204,68 +204,161 @@ __global__ void k_bin_prep(const Prob* __restrict__ P, const T* __restrict__ r, 
     atomicAdd(&bincount[j0 * (n - 1) + i0], 1);
 }
 
-// Exclusive scan of `count` ints by one work-group of 1024 threads; out has
-// count + 1 entries.  Also resets `cursor` (if given) to the scanned offsets.
-__global__ void k_scan(const int* __restrict__ in, int* __restrict__ out, int count, int* __restrict__ cursor) {
-    __shared__ int part[1024];
-    const int tid = threadIdx.x;
-    const int per = (count + 1023) / 1024;
-    const int a = min(tid * per, count), b = min(a + per, count);
-    int s = 0;
-    for (int i = a; i < b; ++i) s += in[i];
-    part[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int v = (tid >= off) ? part[tid - off] : 0;
+// Exclusive scan of `count` ints by one work-group of 1024 threads, in tiles
+// of 4096 entries (four consecutive entries per thread, wave scans through
+// lane shuffles, a running carry between tiles); out has count + 1 entries,
+// out[count] being the total.
+constexpr int kScanThreads = 1024;
+// In place (in == out) is allowed: a tile is read completely before it is written.
+__global__ void __launch_bounds__(kScanThreads) k_scan(const int* in, int* out, int64_t count) {
+    __shared__ int wsum[kScanThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    constexpr int kWaves = kScanThreads / 64;
+    int carry = 0;
+    for (int64_t base = 0; base < count; base += 4 * kScanThreads) {
+        int v[4];
+        int sum = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t idx = base + 4 * tid + j;
+            v[j] = idx < count ? in[idx] : 0;
+            sum += v[j];
+        }
+        int x = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
         __syncthreads();
-        part[tid] += v;
+        if (w == 0) {
+            int t = lane < kWaves ? wsum[lane] : 0;
+#pragma unroll
+            for (int off = 1; off < kWaves; off <<= 1) {
+                const int y = __shfl_up(t, off, 64);
+                if (lane >= off) t += y;
+            }
+            if (lane < kWaves) wsum[lane] = t;
+        }
         __syncthreads();
+        int run = carry + (w > 0 ? wsum[w - 1] : 0) + x - sum;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t idx = base + 4 * tid + j;
+            if (idx < count) out[idx] = run;
+            run += v[j];
+        }
+        carry += wsum[kWaves - 1];
+        __syncthreads();    // wsum is rewritten by the next tile
     }
-    int run = part[tid] - s;   // exclusive prefix of this thread's chunk
-    for (int i = a; i < b; ++i) {
-        out[i] = run;
-        if (cursor) cursor[i] = run;
-        run += in[i];
-    }
-    if (tid == 1023) out[count] = part[1023];
+    if (tid == 0) out[count] = carry;
 }
 
-// Stable placement of the samples in cell order by one work-group: samples
-// are taken in time order in chunks of blockDim; a sample's rank inside its
-// chunk is the number of earlier chunk members with the same cell, its slot
-// cursor[cell] + rank; after each chunk cursor[cell] advances past the chunk.
-template <typename T>
-__global__ void k_place(const Prob* __restrict__ P, const int* __restrict__ cell, const double* __restrict__ frac,
-                        const T* __restrict__ v, int* __restrict__ cursor, char* __restrict__ plan) {
-    extern __shared__ int s_cell[];
-    const Prob& p = *P;
-    vec4<T>* samp = at<vec4<T>>(plan, p.o_samp);
-    int2* sidx = at<int2>(plan, p.o_sidx);
-    const int nb = p.nb;
-    const int tid = threadIdx.x, bs = blockDim.x;
-    for (int64_t c0 = 0; c0 < p.t; c0 += bs) {
-        const int64_t k = c0 + tid;
-        const int q = (k < p.t) ? cell[k] : -1;
-        s_cell[tid] = q;
-        __syncthreads();
-        int rank = 0;
-        for (int u = 0; u < tid; ++u) rank += (s_cell[u] == q);
-        int pos = -1;
-        if (q >= 0) pos = cursor[q] + rank;
-        __syncthreads();
-        if (q >= 0) {
-            atomicMax(&cursor[q], pos + 1);
-            sidx[pos] = make_int2((q % nb) | ((q / nb) << 16), int(k));
-            vec4<T> e;
-            e.x = T(frac[2 * k]);
-            e.y = T(frac[2 * k + 1]);
-            e.z = v[2 * k];
-            e.w = v[2 * k + 1];
-            samp[pos] = e;
+// Stable sort of the samples by base cell: a least-significant-digit radix
+// sort over 8-bit digits of the cell index.  Per pass: digit histograms of
+// tiles of 2048 consecutive entries (k_sort_hist) into a digit-major table,
+// an exclusive scan of that table (k_scan), and a stable scatter (k_sort_pass)
+// that ranks every entry among the entries of its tile with the same digit
+// (earlier rounds, earlier waves, earlier lanes), the wave-local rank from
+// eight ballots.  Every position is an integer function of the input, so the
+// order is the same on every run: by cell, and by time inside a cell.
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 8;
+constexpr int kSortTile = kSortThreads * kSortRounds;
+
+__global__ void __launch_bounds__(kSortThreads) k_sort_hist(const int* __restrict__ keys, int64_t t, int shift,
+                                                            int* __restrict__ table, int tiles) {
+    __shared__ int hist[256];
+    const int tid = threadIdx.x;
+    hist[tid] = 0;
+    __syncthreads();
+    const int64_t base = int64_t(blockIdx.x) * kSortTile;
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t idx = base + r * kSortThreads + tid;
+        if (idx < t) atomicAdd(&hist[(unsigned(keys[idx]) >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    table[int64_t(tid) * tiles + blockIdx.x] = hist[tid];
+}
+
+// vals_in == nullptr: the values are the input positions (the time index);
+// keys_out == nullptr: only the values are written (the last pass).
+__global__ void __launch_bounds__(kSortThreads) k_sort_pass(const int* __restrict__ keys_in,
+                                                            const int* __restrict__ vals_in,
+                                                            int* __restrict__ keys_out, int* __restrict__ vals_out,
+                                                            int64_t t, int shift, const int* __restrict__ offs,
+                                                            int tiles) {
+    __shared__ int run[256];
+    __shared__ int wcnt[kSortThreads / 64][256];
+    constexpr int kWaves = kSortThreads / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    run[tid] = offs[int64_t(tid) * tiles + blockIdx.x];
+    const uint64_t lt = (uint64_t(1) << lane) - 1;
+    const int64_t base = int64_t(blockIdx.x) * kSortTile;
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t idx = base + r * kSortThreads + tid;
+        const bool valid = idx < t;
+        const int key = valid ? keys_in[idx] : 0;
+        const int val = valid ? (vals_in ? vals_in[idx] : int(idx)) : 0;
+        const unsigned d = (unsigned(key) >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
         }
-        __threadfence_block();
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) wcnt[q][tid] = 0;
+        __syncthreads();
+        const int rank = __popcll(peers & lt);
+        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int pos = run[d] + rank;
+            for (int q = 0; q < w; ++q) pos += wcnt[q][d];
+            if (keys_out) keys_out[pos] = key;
+            vals_out[pos] = val;
+        }
+        __syncthreads();
+        int add = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) add += wcnt[q][tid];
+        run[tid] += add;
         __syncthreads();
     }
+}
+
+// Writes the sorted sample records: position i holds sample k = order[i].
+template <typename T>
+__global__ void k_place(const Prob* __restrict__ P, const int* __restrict__ order, const int* __restrict__ cell,
+                        const double* __restrict__ frac, const T* __restrict__ v, char* __restrict__ plan) {
+    const Prob& p = *P;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= p.t) return;
+    const int k = order[i];
+    const int q = cell[k];
+    if (q < 0) return;        // outside the hull: the build reports the error
+    const int nb = p.nb;
+    at<int2>(plan, p.o_sidx)[i] = make_int2((q % nb) | ((q / nb) << 16), k);
+    vec4<T> e;
+    e.x = T(frac[2 * k]);
+    e.y = T(frac[2 * k + 1]);
+    e.z = v[2 * k];
+    e.w = v[2 * k + 1];
+    at<vec4<T>>(plan, p.o_samp)[i] = e;
+}
+
+// Copies one problem's sorted (base cell, time index) pairs out of the plan.
+__global__ void k_sample_order(const Prob* __restrict__ P, const char* __restrict__ plan, int* __restrict__ order,
+                               int* __restrict__ cell) {
+    const Prob& p = *P;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= p.t) return;
+    const int2 e = at<int2>(plan, p.o_sidx)[i];
+    order[i] = e.y;
+    cell[i] = e.x;
 }
 
 }  // namespace mpik

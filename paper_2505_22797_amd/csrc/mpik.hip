@@ -121,7 +121,8 @@ int validate(const mpi_problem* d, Shape& sh) {
 
 // Scratch used by the build of one problem; reused problem after problem.
 struct Scratch {
-    int64_t series = 0, tab64 = 0, cs = 0, U = 0, cell = 0, frac = 0, bincount = 0, cursor = 0;
+    int64_t series = 0, tab64 = 0, cs = 0, U = 0, cell = 0, frac = 0, bincount = 0;
+    int64_t keys_a = 0, keys_b = 0, vals_a = 0, vals_b = 0, table = 0;   // radix-sort buffers
     size_t end = 0;
 };
 
@@ -170,6 +171,8 @@ void layout_problem(const Shape& sh, int mode, bool both, bool deriv, size_t& po
     p.w_grad = take(woff, size_t(N) * N * e);
 }
 
+int sort_tiles(int64_t T) { return int((T + kSortTile - 1) / kSortTile); }
+
 Scratch scratch_layout(const Shape& sh, size_t base) {
     Scratch s;
     size_t off = base;
@@ -181,7 +184,11 @@ Scratch scratch_layout(const Shape& sh, size_t base) {
     s.cell = take(off, size_t(sh.T) * 4);
     s.frac = take(off, size_t(sh.T) * 16);
     s.bincount = take(off, size_t(nb) * nb * 4);
-    s.cursor = take(off, size_t(nb) * nb * 4);
+    s.keys_a = take(off, size_t(sh.T) * 4);
+    s.keys_b = take(off, size_t(sh.T) * 4);
+    s.vals_a = take(off, size_t(sh.T) * 4);
+    s.vals_b = take(off, size_t(sh.T) * 4);
+    s.table = take(off, (size_t(256) * sort_tiles(sh.T) + 1) * 4);
     s.end = off;
     return s;
 }
@@ -402,11 +409,29 @@ int build_problem(const mpi_problem* d, const BatchLayout& B, int b, char* plan,
     int* cell = reinterpret_cast<int*>(plan + sc.cell);
     double* frac = reinterpret_cast<double*>(plan + sc.frac);
     int* bincount = reinterpret_cast<int*>(plan + sc.bincount);
-    int* cursor = reinterpret_cast<int*>(plan + sc.cursor);
     int* err = reinterpret_cast<int*>(plan + p.o_err);
     k_bin_prep<T><<<blocks(p.t, 256), 256, 0, st>>>(P, static_cast<const T*>(d->r), cell, frac, bincount, err);
-    k_scan<<<1, 1024, 0, st>>>(bincount, reinterpret_cast<int*>(plan + p.o_binstart), nb * nb, cursor);
-    k_place<T><<<1, 1024, 1024 * sizeof(int), st>>>(P, cell, frac, static_cast<const T*>(d->v), cursor, plan);
+    k_scan<<<1, kScanThreads, 0, st>>>(bincount, reinterpret_cast<int*>(plan + p.o_binstart), int64_t(nb) * nb);
+    // stable radix sort of (cell, time index) pairs, 8 bits per pass
+    const int tiles = sort_tiles(p.t);
+    int* table = reinterpret_cast<int*>(plan + sc.table);
+    int* kbuf[2] = {reinterpret_cast<int*>(plan + sc.keys_a), reinterpret_cast<int*>(plan + sc.keys_b)};
+    int* vbuf[2] = {reinterpret_cast<int*>(plan + sc.vals_a), reinterpret_cast<int*>(plan + sc.vals_b)};
+    int passes = 1;
+    while ((int64_t(nb) * nb - 1) >> (8 * passes)) ++passes;
+    const int* kin = cell;          // kept: k_place reads it
+    const int* vin = nullptr;       // pass 0: values are the time indices
+    for (int q = 0; q < passes; ++q) {
+        int* kout = q == passes - 1 ? nullptr : kbuf[q & 1];   // the last pass needs no keys
+        int* vout = vbuf[q & 1];
+        k_sort_hist<<<tiles, kSortThreads, 0, st>>>(kin, p.t, 8 * q, table, tiles);
+        k_scan<<<1, kScanThreads, 0, st>>>(table, table, int64_t(256) * tiles);
+        k_sort_pass<<<tiles, kSortThreads, 0, st>>>(kin, vin, kout, vout, p.t, 8 * q, table, tiles);
+        kin = kout;
+        vin = vout;
+    }
+    const int* order = vin;
+    k_place<T><<<blocks(p.t, 256), 256, 0, st>>>(P, order, cell, frac, static_cast<const T*>(d->v), plan);
     HIP_TRY(hipGetLastError());
     return MPI_OK;
 }
@@ -890,6 +915,14 @@ int mpi_batch_info(const mpi_plan* plan, int index, int32_t* radius, int32_t* ff
     if (conv_mode) *conv_mode = p.mode ? MPI_CONV_FFT : MPI_CONV_DIRECT;
     if (slices) *slices = p.mode ? 0 : p.slices;
     return MPI_OK;
+}
+
+int mpi_batch_sample_order(const mpi_plan* plan, int index, int32_t* order, int32_t* cell, hipStream_t stream) {
+    if (!plan || index < 0 || index >= plan->count || !order || !cell) return MPI_ERR_ARG;
+    if (misaligned(order, 4) || misaligned(cell, 4)) return MPI_ERR_ARG;
+    const Prob& p = plan->L.probs[index];
+    k_sample_order<<<blocks(p.t, 256), 256, 0, stream>>>(plan->dprob + index, plan->plan, order, cell);
+    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
 int mpi_plan_info(const mpi_plan* plan, int32_t* radius, int32_t* fft_size, int32_t* conv_mode) {

@@ -23,7 +23,7 @@ EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "
            "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
            "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_iterate",
            "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
-           "mpi_batch_dot", "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
+           "mpi_batch_dot", "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
            "mpi_plan_destroy", "mpi_status_str", "mpi_abi_version")
 MPI_BUILD_TUNE, MPI_BUILD_COL_SPLIT, MPI_BUILD_COL_WAVE, MPI_BUILD_DERIV = 1, 2, 4, 8
 
@@ -81,6 +81,7 @@ def lib() -> ctypes.CDLL:
         L.mpi_batch_adjoint_step.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
         L.mpi_batch_denoise.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, vp, sz, vp]
         L.mpi_batch_dot.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, sz, vp]
+        L.mpi_batch_sample_order.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.mpi_stage_count.argtypes = [vp]
         L.mpi_stage_name.argtypes = [vp, ctypes.c_int]
         L.mpi_stage_name.restype = ctypes.c_char_p
@@ -93,7 +94,8 @@ def lib() -> ctypes.CDLL:
                      "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
                      "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_iterate",
                      "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
-                     "mpi_batch_dot", "mpi_stage_count", "mpi_stage_launch", "mpi_plan_destroy",
+                     "mpi_batch_dot", "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_launch",
+                     "mpi_plan_destroy",
                      "mpi_abi_version"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -277,6 +279,15 @@ class Plan:
                                    self.work.numel(), _stream(stream)), "mpi_batch_dot")
         return out
 
+    def sample_order(self, stream=None):
+        """(time index, base cell i0 | j0 << 16) of the samples in the order
+        the plan holds them (int32 device tensors)."""
+        order = torch.empty(self.n_samples, dtype=torch.int32, device=self.device)
+        cell = torch.empty_like(order)
+        _check(lib().mpi_batch_sample_order(self._h, 0, order.data_ptr(), cell.data_ptr(), _stream(stream)),
+               "mpi_batch_sample_order")
+        return order, cell
+
     def close(self):
         if getattr(self, "_h", None):
             lib().mpi_plan_destroy(self._h)
@@ -449,6 +460,15 @@ class Batch:
                                    {"x": 0, "y": 1, "both": 2}[comp], out.data_ptr(), self.work.data_ptr(),
                                    self.work.numel(), _stream(stream)), "mpi_batch_dot")
         return out
+
+    def sample_order(self, b, stream=None):
+        """(time index, base cell i0 | j0 << 16) of problem b's samples in the
+        order the plan holds them (int32 device tensors)."""
+        order = torch.empty(self.ts[b], dtype=torch.int32, device=self.device)
+        cell = torch.empty_like(order)
+        _check(lib().mpi_batch_sample_order(self._h, int(b), order.data_ptr(), cell.data_ptr(), _stream(stream)),
+               "mpi_batch_sample_order")
+        return order, cell
 
     def close(self):
         if getattr(self, "_h", None):
