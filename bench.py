@@ -114,6 +114,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-iter", action="store_true")
     ap.add_argument("--profile-batch", action="store_true",
                     help="only a few batched pairs plus a 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -208,15 +209,115 @@ def main() -> int:
     }
     del batch, c_all, s_all, g_all
     torch.cuda.empty_cache()
+    out["window_31_direct"] = window31_line(mpik, P, r, v, c1, B, args)
 
     if not args.no_uneven:
         out["uneven_batch"] = uneven_batch(mpik, S, dev)
     if not args.no_grad:
         out["differentiation"] = differentiation(S, dev)
+    if not args.no_iter:
+        out["iteration_configs"] = iteration_configs(mpik, S, dev, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_seconds)
     print(json.dumps(out))
     return 0
+
+
+def window31_line(mpik, P, r, v, c1, B, args):
+    """The headline shape with the kernel truncated to a 63 x 63 window on the
+    direct path: one problem per launch and B per launch."""
+    import torch
+    n, t = P.n, P.n_samples
+    plan = mpik.Plan(n, P.h, 31, r, v, conv_mode="direct")
+    s1 = torch.empty((t, 2), dtype=torch.float32, device=c1.device)
+    g1 = torch.empty((n, n), dtype=torch.float32, device=c1.device)
+
+    def pair1():
+        plan.forward(c1, s1)
+        plan.adjoint(s1, g1)
+
+    ms1, _ = graph_time(pair1, args.steps, args.graph_pairs, args.warmup)
+    batch = mpik.Batch([(n, P.h, 31, r, v, "direct")] * B, tune=False)
+    c_all = c1.reshape(-1).repeat(B).contiguous()
+    s_all = torch.empty(batch.s_offsets[-1], dtype=torch.float32, device=c1.device)
+    g_all = torch.empty(batch.c_offsets[-1], dtype=torch.float32, device=c1.device)
+
+    def pairB():
+        batch.forward(c_all, s_all)
+        batch.adjoint(s_all, g_all)
+
+    msB, _ = graph_time(pairB, max(10, args.steps // B * 4), max(1, args.graph_pairs // 5), 2)
+    stB = stage_times(batch, g_all, s_all, max(3, args.stage_reps // 4))
+    flop = 2 * 2 * 3 * (2 * 31 + 1) ** 2 * n * n      # multiply-adds of both convolutions per pair
+    return {"radius": 31, "conv_path": "direct", "single_pairs_per_s": round(1e3 / ms1, 1),
+            "batch": B, "batch_pairs_per_s": round(B * 1e3 / msB, 1),
+            "direct_conv_tflops": round(flop * B / (msB * 1e-3) / 1e12, 2),
+            "stage_ms": {k: round(x, 5) for k, x in stB.items()}}
+
+
+def iteration_configs(mpik, S, dev, with_oracle, oracle_seconds=3.0):
+    """Iterations per second of the plain solves: 32^2 / R = 7 / float64 /
+    50 Landweber steps; 128^2 / R = 31 / 200 denoised steps; 256^2 / full
+    kernel / 2^17 samples of the perturbed partial trajectory / 200 denoised
+    steps.  The float64 oracle's iteration rate on the host (one thread, a few
+    steps) is reported beside each."""
+    import numpy as np
+    import torch
+    out = {}
+    for P in (S.plain_f64(), S.plain_f32(), S.independence()):
+        dt = torch.float64 if P.dtype == "f64" else torch.float32
+        tt = lambda a: torch.tensor(np.asarray(a, dtype=np.float64), dtype=dt, device=dev).contiguous()
+        plan = mpik.Plan(P.n, P.h, P.radius, tt(P.traj.r), tt(P.traj.v))
+        s = plan.forward(tt(P.c))
+        x = torch.randn((P.n, P.n), dtype=dt, device=dev)
+        for _ in range(10):
+            x = plan.adjoint(plan.forward(x / x.norm()))
+        tau = 0.9 / float(x.norm())
+        sigma = 0.5 if P.denoise else 0.0
+        c = torch.zeros((P.n, P.n), dtype=dt, device=dev)
+        plan.iterate(s, c, P.n_iter, tau, sigma, 2)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(3):
+            plan.iterate(s, c, P.n_iter, tau, sigma, 2)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 3
+        rec = {"grid": P.n, "samples": P.n_samples, "radius": plan.radius, "conv_path": plan.conv_mode,
+               "dtype": "f64" if dt == torch.float64 else "f32", "iterations": P.n_iter,
+               "denoise": bool(P.denoise), "solve_ms": round(ms, 3),
+               "iterations_per_s": round(P.n_iter * 1e3 / ms, 1)}
+        if with_oracle:
+            rec["oracle_iterations_per_s"] = oracle_iteration_rate(P, tau, oracle_seconds)
+        out[P.name] = rec
+        del plan
+    return out
+
+
+def oracle_iteration_rate(P, tau, budget_s):
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:
+        limiter = None
+    import numpy as np
+    import oracle as O
+    from paper_2505_22797_amd import synth as S
+    rnd = (lambda a: a) if P.dtype == "f64" else S.to_f32
+    model = O.Model(P.n, P.h, P.radius, rnd(P.traj.r), rnd(P.traj.v))
+    s = model.forward(rnd(P.c))
+    c = np.zeros((P.n, P.n))
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        c = O.iterate(model, s, c, tau, 1, sigma_px=0.5 if P.denoise else None, radius=2)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 200:
+            break
+    del limiter
+    return round(steps / el, 3)
 
 
 def profile_batch(mpik, P, r, v, c1, B, steps):
@@ -368,10 +469,23 @@ def cpu_baseline(P, budget_s: float) -> dict:
         if el >= budget_s or pairs >= 400:
             break
     del limiter
+    import numpy
+    import scipy
     return {"value": round(pairs / el, 4), "unit": "pairs/s", "cores": 1, "kind": "oracle",
             "sample": f"{pairs} A+A^T pairs of the 256^2 / 53,856-sample / R=255 operator in float64 numpy "
                       f"(FFT convolution, bincount transpose), {el:.1f} s, one thread of "
-                      f"{os.cpu_count()} visible cores"}
+                      f"{os.cpu_count()} visible cores",
+            "cpu_model": cpu_model(), "numpy": numpy.__version__, "scipy": scipy.__version__}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":
