@@ -222,6 +222,31 @@ int mpi_batch_denoise(const mpi_plan* plan, const void* u_all, void* c_all, doub
 int mpi_batch_dot(const mpi_plan* plan, const void* a_all, const void* b_all, int space, int comp,
                   double* out, void* work, size_t work_bytes, hipStream_t stream);
 
+/* Reverse sweep (vector-Jacobian product) of K = n_iter steps of the
+ * denoised Landweber iteration of the deconvolution stage,
+ *   r_k = A c_k - s,  c_{k+1} = D(c_k - tau_b A^T r_k),
+ * with tau_b fixed and D the Gaussian of mpi_batch_denoise (identity when
+ * denoise_sigma_px <= 0).  The loss gradient gbar = dL/dc_K comes in and
+ * dL/dc_0 goes out in the same buffer; also, per problem,
+ *   g_h[b] = dL/dh (device, count doubles), and per sample, in time order,
+ *   g_r = dL/dr_k, g_v = dL/dv_k (signal-shaped, base cells held fixed).
+ * The reverse recursion is, from k = K-1 down to 0:
+ *   g_u = D gbar,  gbar <- g_u - tau A^T A g_u,
+ *   dL/dtheta += -tau [<(dA/dtheta) g_u, r_k> + <A g_u, (dA/dtheta) c_k>].
+ * checkpoints: ceil(K / every) concentration vectors of the batch, back to
+ * back, c_0, c_every, c_2every, ... (as the forward iteration passed them);
+ * each segment is recomputed from its checkpoint.  The plan must be built with
+ * MPI_BUILD_DERIV.  vjp_work: caller-owned device memory of at least
+ * mpi_batch_unrolled_vjp_bytes(plan, every) bytes, 256-byte aligned; its size
+ * grows with `every` (per step of a segment: two concentration vectors, a
+ * residual and nine planes of the sampled field).  Deterministic: every sum
+ * has a fixed order.  Enqueued on `stream`; nothing is synchronised. */
+int mpi_batch_unrolled_vjp_bytes(const mpi_plan* plan, int32_t every, size_t* vjp_bytes);
+int mpi_batch_unrolled_vjp(const mpi_plan* plan, const void* s_all, const void* checkpoints, int32_t n_iter,
+                           int32_t every, double denoise_sigma_px, int32_t denoise_radius, const double* taus,
+                           void* gbar_all, double* g_h, void* g_r_all, void* g_v_all, void* work,
+                           size_t work_bytes, void* vjp_work, size_t vjp_bytes, hipStream_t stream);
+
 /* Diagnostics for timing one kernel at a time.  The forward operator and its
  * transpose each run as a short sequence of kernels (stages); stages
  * 0 .. count/2-1 are those of mpi_forward, the rest those of mpi_adjoint;

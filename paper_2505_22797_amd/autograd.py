@@ -14,12 +14,11 @@ r_k = (ax rho_x, ay rho_y), v_k = (ax nu_x, ay nu_y).  Gradients:
                   reverse recursion (D symmetric, tau held fixed)
                   gu = D gbar,  gbar <- gu - tau A^T A gu,
                   dL/dtheta += -tau [<(dA/dtheta) gu, r_k> + <A gu, (dA/dtheta) c_k>],
-                  recomputing c_k inside segments from checkpoints kept every
-                  `every` steps.
+                  run by the library from checkpoints kept every `every`
+                  steps (each segment recomputed from its checkpoint).
 
 Every operator application, derivative, reduction and denoising step runs in
-the HIP library; this module only sequences the calls and adds up the
-per-step scalars.
+the HIP library; this module only sequences the calls.
 """
 from __future__ import annotations
 
@@ -132,56 +131,37 @@ class ApplyAT(torch.autograd.Function):
 
 
 class UnrolledSolve(torch.autograd.Function):
-    """c_K after K steps c <- D(c - tau_b A^T (A c - s)) from c_0, with a
-    checkpointed hand-written backward."""
+    """c_K after K steps c <- D(c - tau_b A^T (A c - s)) from c_0.  The forward
+    replays the captured iteration segment by segment and keeps the iterates
+    at the segment starts; the backward is the library's reverse sweep, which
+    recomputes each segment from its checkpoint."""
 
     @staticmethod
     def forward(ctx, c0_all, h, ax, ay, s_all, op, taus, n_iter, sigma_px, radius, every):
         plan = op.plan(h, ax, ay)
-        c = c0_all.detach().contiguous().clone()
         s_all = s_all.contiguous()
-        checkpoints = [c.clone()]
-        for k in range(n_iter):
-            plan.iterate(s_all, c, 1, taus, denoise_sigma_px=sigma_px or 0.0, denoise_radius=radius,
-                         use_graph=False)
-            if (k + 1) % every == 0 and k + 1 < n_iter:
-                checkpoints.append(c.clone())
-        ctx.save_for_backward(h, ax, ay, s_all, *checkpoints)
+        C = plan.c_offsets[-1]
+        nseg = (n_iter + every - 1) // every
+        checkpoints = torch.empty(nseg * C, dtype=c0_all.dtype, device=c0_all.device)
+        c = c0_all.detach().contiguous().clone()
+        for si in range(nseg):
+            checkpoints[si * C:(si + 1) * C].copy_(c)
+            plan.iterate(s_all, c, min(every, n_iter - si * every), taus, denoise_sigma_px=sigma_px or 0.0,
+                         denoise_radius=radius)
+        ctx.save_for_backward(h, ax, ay, s_all, checkpoints)
         ctx.op, ctx.taus, ctx.n_iter, ctx.sigma, ctx.radius, ctx.every = op, list(taus), n_iter, sigma_px, radius, every
         return c
 
     @staticmethod
     def backward(ctx, gbar):
-        h, ax, ay, s_all, *checkpoints = ctx.saved_tensors
-        op, taus, K, sigma, radius, every = ctx.op, ctx.taus, ctx.n_iter, ctx.sigma, ctx.radius, ctx.every
+        h, ax, ay, s_all, checkpoints = ctx.saved_tensors
+        op = ctx.op
         plan = op.plan(h, ax, ay)
-        dev = s_all.device
-        tau = torch.tensor(taus, dtype=torch.float64, device=dev)
-        gh = torch.zeros(op.count, dtype=torch.float64, device=dev)
-        gax = torch.zeros_like(gh)
-        gay = torch.zeros_like(gh)
-        gbar = gbar.contiguous().clone()
-        starts = list(range(0, K, every))
-        for si in reversed(range(len(starts))):
-            a, b = starts[si], min(starts[si] + every, K)
-            cs = [checkpoints[si]]
-            c = checkpoints[si].clone()
-            for _ in range(a, b - 1):               # recompute c_a .. c_{b-1}
-                plan.iterate(s_all, c, 1, taus, denoise_sigma_px=sigma or 0.0, denoise_radius=radius,
-                             use_graph=False)
-                cs.append(c.clone())
-            for k in reversed(range(a, b)):
-                ck = cs[k - a]
-                rk = plan.residual(ck, s_all)
-                gu = plan.denoise(gbar, sigma, radius) if sigma else gbar
-                q = plan.forward(gu)
-                dh1, ax1, ay1 = _param_grads(op, plan, gu, rk)
-                dh2, ax2, ay2 = _param_grads(op, plan, ck, q)
-                gh -= tau * (dh1 + dh2)
-                gax -= tau * (ax1 + ax2)
-                gay -= tau * (ay1 + ay2)
-                gbar = plan.adjoint_step(q, gu, taus)
-        return (gbar, _like(gh, h), _like(gax, ax), _like(gay, ay), None, None, None, None, None, None, None)
+        gbar = gbar.contiguous().clone()          # becomes dL/dc_0
+        g_h, g_r, g_v = plan.unrolled_vjp(s_all, checkpoints, ctx.n_iter, ctx.every, ctx.taus, gbar,
+                                          denoise_sigma_px=ctx.sigma or 0.0, denoise_radius=ctx.radius)
+        gax, gay = op.amp_grads(plan, g_r, g_v)
+        return (gbar, _like(g_h, h), _like(gax, ax), _like(gay, ay), None, None, None, None, None, None, None)
 
 
 def apply_A(op, c_all, h, ax, ay):

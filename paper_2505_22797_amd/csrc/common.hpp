@@ -106,6 +106,17 @@ __device__ __forceinline__ int xcd_unit(int x, int n) {
 // in order), so one buffer suffices.  Forward uses w = e^{-2 pi i/M}, inverse
 // the conjugate; no scaling.
 // ---------------------------------------------------------------------------
+// Caller buffers of a gather launch, all flat over the batch: signal-shaped
+// out0/in0/out1/out2 (problem b at element o_s), and f, nine planes of the
+// sampled field per problem (problem b at element 9 o_s / 2, plane stride T_b).
+template <typename T> struct GatherIO {
+    T* out0 = nullptr;
+    const T* in0 = nullptr;
+    T* out1 = nullptr;
+    T* out2 = nullptr;
+    T* f = nullptr;
+};
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(64 * S) k_conv_direct(const Prob* __restrict__
 // Bilinear gather + contraction for base-cell row b from a field in global
 // memory ([3][N][N]): rows b and b+1 are staged in LDS first.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_gather_rows(const Prob* __restrict__ P, T* out0, const T* in0, T* out1,
+__global__ void __launch_bounds__(256) k_gather_rows(const Prob* __restrict__ P, GatherIO<T> io,
                                                      const char* __restrict__ plan, char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
@@ -162,8 +162,10 @@ __global__ void __launch_bounds__(256) k_gather_rows(const Prob* __restrict__ P,
     }
     __syncthreads();
     gather_band<T, MODE>(g0, g1, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
-                         at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res), out0 ? out0 + p.o_s : nullptr,
-                         in0 ? in0 + p.o_s : nullptr, out1 ? out1 + p.o_s : nullptr, threadIdx.x, blockDim.x);
+                         at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res),
+                         io.out0 ? io.out0 + p.o_s : nullptr, io.in0 ? io.in0 + p.o_s : nullptr,
+                         io.out1 ? io.out1 + p.o_s : nullptr, io.out2 ? io.out2 + p.o_s : nullptr,
+                         io.f ? io.f + 9 * (p.o_s / 2) : nullptr, p.t, threadIdx.x, blockDim.x);
 }
 
 // Deterministic transpose sampling for one grid row into a field in global
@@ -179,9 +181,11 @@ __global__ void __launch_bounds__(256) k_scatter_rows(const Prob* __restrict__ P
     if (j >= N) return;
     T* g = reinterpret_cast<T*>(smem);
     char* sc = smem + lds_align(size_t(3) * N * sizeof(T));
+    const T* sp = s ? s + p.o_s : nullptr;
+    // SORTED: the signal in cell order, from s when given, else the problem's residual in work
+    const vec2<T>* ys = (SORTED && sp) ? reinterpret_cast<const vec2<T>*>(sp) : at<vec2<T>>(work, p.w_res);
     scatter_row<T, SORTED, 256>(g, scatter_lds<T>(sc, N, 256), N, j, at<int>(plan, p.o_binstart),
-                                at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), at<vec2<T>>(work, p.w_res),
-                                s + p.o_s, threadIdx.x);
+                                at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), ys, sp, threadIdx.x);
     for (int i = threadIdx.x; i < 3 * N; i += blockDim.x) {
         const int ch = i / N, x = i % N;
         G[int64_t(ch) * N * N + int64_t(j) * N + x] = g[i];
@@ -254,7 +258,7 @@ __global__ void __launch_bounds__(256) k_denoise(const Prob* __restrict__ P, con
 template <typename T>
 __global__ void __launch_bounds__(1024) k_dot(const Prob* __restrict__ P, const T* __restrict__ a,
                                               const T* __restrict__ bb, int space, int comp,
-                                              double* __restrict__ out) {
+                                              double* __restrict__ out, int accumulate) {
     __shared__ double part[1024];
     const Prob& p = P[blockIdx.x];
     const int tid = threadIdx.x;
@@ -276,7 +280,7 @@ __global__ void __launch_bounds__(1024) k_dot(const Prob* __restrict__ P, const 
         if (tid < w) part[tid] += part[tid + w];
         __syncthreads();
     }
-    if (tid == 0) out[blockIdx.x] = part[0];
+    if (tid == 0) out[blockIdx.x] = (accumulate ? out[blockIdx.x] : 0.0) + part[0];
 }
 
 }  // namespace mpik

@@ -202,8 +202,8 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
 
 template <typename T, int M, int MODE>
 __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const T* __restrict__ in0,
-                                     T* __restrict__ out1, const char* __restrict__ plan, char* __restrict__ work,
-                                     char* smem) {
+                                     T* __restrict__ out1, T* __restrict__ out2, T* __restrict__ f,
+                                     const char* __restrict__ plan, char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<GatherSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
     const int N = p.n, nb = p.nb, b = xcd_unit(blockIdx.x, nb);
@@ -231,7 +231,8 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
     }
     __syncthreads();
     gather_band<T, MODE>(g0, g1, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
-                         at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res), out0, in0, out1, tid, 4 * kWave);
+                         at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res), out0, in0, out1, out2, f, p.t,
+                         tid, 4 * kWave);
 }
 
 // ----------------------------------------------------------------- adjoint ---
@@ -251,8 +252,10 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
     cx<T>* lines = reinterpret_cast<cx<T>*>(shared_area);
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     load_twiddles<T, M>(tw, plan, p, tid, 4 * kWave);
+    // SORTED: the signal in cell order, from s when given, else the problem's residual in work
+    const vec2<T>* ys = (SORTED && s) ? reinterpret_cast<const vec2<T>*>(s) : at<vec2<T>>(work, p.w_res);
     scatter_row<T, SORTED, 256>(g, scatter_lds<T>(shared_area, N, 256), N, j, at<int>(plan, p.o_binstart),
-                                at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), at<vec2<T>>(work, p.w_res),
+                                at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), ys,
                                 s, tid);
     if (wave >= 2) return;
     cx<T>* line = lines + wave * M;
@@ -283,8 +286,9 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
 
 // Column kx: forward FFTs of the three channels' columns, sum of the
 // products with the channel spectra in the fixed order xx, xy, yy, one
-// inverse FFT, rows 0..N-1 to T2[row][kx].
-template <typename T, int M, bool SPLIT>
+// inverse FFT, rows 0..N-1 to T2[row][kx].  DUAL (four-column shape only):
+// the same with the dK/dh spectra as well, to the second T2 slot.
+template <typename T, int M, bool SPLIT, bool DUAL = false>
 __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<ColSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
@@ -318,7 +322,9 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         if (kx >= H) return;
         cx<T>* line = sm.line[wave];
         constexpr int PL = M / kWave;
+        const T* spec_dh = DUAL ? at<T>(plan, p.o_spec_dh) : nullptr;
         cx<T> acc[PL];
+        cx<T> acc2[DUAL ? PL : 1];
         for (int ch = 0; ch < 3; ++ch) {
             const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + (int64_t(ch) * H + kx) * N;
             for (int i = lane; i < M; i += kWave) line[i] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
@@ -327,8 +333,13 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
 #pragma unroll
             for (int i = 0; i < PL; ++i) {
                 const int ky = lane + i * kWave;
-                const cx<T> v = cscale(line[ky], spec_at<T, M>(spec, ch, kx, ky));
+                const cx<T> z = line[ky];
+                const cx<T> v = cscale(z, spec_at<T, M>(spec, ch, kx, ky));
                 acc[i] = ch == 0 ? v : cadd(acc[i], v);
+                if constexpr (DUAL) {
+                    const cx<T> w = cscale(z, spec_at<T, M>(spec_dh, ch, kx, ky));
+                    acc2[i] = ch == 0 ? w : cadd(acc2[i], w);
+                }
             }
             wave_sync();
         }
@@ -337,12 +348,21 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         wave_sync();
         fft_wave<T, true, M>(line, sm.tw, lane);
         for (int j = lane; j < N; j += kWave) t2[int64_t(j) * H + kx] = line[j];
+        if constexpr (DUAL) {
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < PL; ++i) line[lane + i * kWave] = acc2[i];
+            wave_sync();
+            fft_wave<T, true, M>(line, sm.tw, lane);
+            cx<T>* t2b = t2 + int64_t(N) * H;
+            for (int j = lane; j < N; j += kWave) t2b[int64_t(j) * H + kx] = line[j];
+        }
     }
 }
 
 // EPI 0: c_out = A^T s;  1, 2: c_out = c_in - tau * A^T r (c_in may alias c_out)
 template <typename T, int M, int EPI>
-__device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau,
+__device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int slot,
                               const char* __restrict__ plan, char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<RowSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
@@ -355,7 +375,7 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau,
     const int r0 = 2 * q, r1 = 2 * q + 1;
     if (r0 >= N) return;
     const bool two = r1 < N;
-    const cx<T>* t2 = at<cx<T>>(work, p.w_t2);
+    const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(slot) * N * H;
     const cx<T>* ra = t2 + int64_t(r0) * H;
     const cx<T>* rb = t2 + int64_t(two ? r1 : r0) * H;
     cx<T>* line = sm.line[wave];
@@ -407,16 +427,17 @@ __global__ void __launch_bounds__(256) k_fwd_cols(const Prob* __restrict__ P, co
 }
 
 // grid.x: xcd_grid(base-cell rows), 256 threads.  MODE as gather_band; the
-// caller buffers out0, in0, out1 are signal-shaped (offset by the problem's o_s).
+// caller buffers are offset to the problem here.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_fwd_rows_gather(const Prob* __restrict__ P, T* out0, const T* in0, T* out1,
+__global__ void __launch_bounds__(256) k_fwd_rows_gather(const Prob* __restrict__ P, GatherIO<T> io,
                                                          const char* __restrict__ plan, char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
     if (p.mode != 1) return;
-    MPIK_DISPATCH_M(p.m, (fwd_rows_gather_body<T, MM, MODE>(p, out0 ? out0 + p.o_s : nullptr,
-                                                           in0 ? in0 + p.o_s : nullptr,
-                                                           out1 ? out1 + p.o_s : nullptr, plan, work, smem)));
+    MPIK_DISPATCH_M(p.m, (fwd_rows_gather_body<T, MM, MODE>(
+                             p, io.out0 ? io.out0 + p.o_s : nullptr, io.in0 ? io.in0 + p.o_s : nullptr,
+                             io.out1 ? io.out1 + p.o_s : nullptr, io.out2 ? io.out2 + p.o_s : nullptr,
+                             io.f ? io.f + 9 * (p.o_s / 2) : nullptr, plan, work, smem)));
 }
 
 // grid.x: xcd_grid(grid rows), 256 threads
@@ -426,31 +447,34 @@ __global__ void __launch_bounds__(256) k_adj_scatter_row(const Prob* __restrict_
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
     if (p.mode != 1) return;
-    MPIK_DISPATCH_M(p.m, (adj_scatter_row_body<T, MM, SORTED>(p, s + p.o_s, plan, work, smem)));
+    MPIK_DISPATCH_M(p.m, (adj_scatter_row_body<T, MM, SORTED>(p, s ? s + p.o_s : nullptr, plan, work, smem)));
 }
 
-// SPLIT: grid.x = xcd_grid(M/2 + 1), 192 threads; else xcd_grid(ceil((M/2 + 1)/4)), 256 threads
-template <typename T, bool SPLIT>
+// SPLIT: grid.x = xcd_grid(M/2 + 1), 192 threads; else xcd_grid(ceil((M/2 + 1)/4)), 256 threads.
+// DUAL needs the four-column shape.
+template <typename T, bool SPLIT, bool DUAL = false>
 __global__ void __launch_bounds__(256) k_adj_cols(const Prob* __restrict__ P, const char* __restrict__ plan,
                                                   char* __restrict__ work) {
+    static_assert(!(SPLIT && DUAL), "the dual transpose runs in the four-column shape");
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
     if (p.mode != 1) return;
-    MPIK_DISPATCH_M(p.m, (adj_cols_body<T, MM, SPLIT>(p, plan, work, smem)));
+    MPIK_DISPATCH_M(p.m, (adj_cols_body<T, MM, SPLIT, DUAL>(p, plan, work, smem)));
 }
 
-// grid.x: xcd_grid(ceil(row pairs / 4)), 256 threads
+// grid.x: xcd_grid(ceil(row pairs / 4)), 256 threads; slot: which T2 field
 template <typename T, int EPI>
 __global__ void __launch_bounds__(256) k_adj_rows(const Prob* __restrict__ P, T* c_out, const T* c_in,
                                                   const double* __restrict__ taus, const char* __restrict__ plan,
-                                                  char* __restrict__ work) {
+                                                  char* __restrict__ work, int slot) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
     if (p.mode != 1) return;
     const T tau = EPI ? T(taus[blockIdx.y]) : T(0);
     // EPI 2 writes the step into the problem's work buffer u (before the denoiser)
     T* out = EPI == 2 ? at<T>(work, p.w_u) : c_out + p.o_c;
-    MPIK_DISPATCH_M(p.m, (adj_rows_body<T, MM, EPI>(p, out, c_in + p.o_c, tau, plan, work, smem)));
+    MPIK_DISPATCH_M(p.m, (adj_rows_body<T, MM, EPI>(p, out, EPI ? c_in + p.o_c : nullptr, tau, slot, plan, work,
+                                                    smem)));
 }
 
 }  // namespace mpik

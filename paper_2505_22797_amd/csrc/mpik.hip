@@ -25,6 +25,7 @@
 #include "build.hpp"
 #include "direct.hpp"
 #include "fft_conv.hpp"
+#include "grad.hpp"
 
 using namespace mpik;
 
@@ -338,6 +339,13 @@ hipError_t set_smem_limits(const mpi_plan* pl) {
     chk(allow_smem(k_fwd_cols<T, false>, pl->smem_col));
     chk(allow_smem(k_adj_cols<T, true>, pl->smem_col));
     chk(allow_smem(k_adj_cols<T, false>, pl->smem_col));
+    chk(allow_smem(k_adj_cols<T, false, true>, pl->smem_col));
+    chk(allow_smem(k_fwd_rows_gather<T, 4>, pl->smem_gather));
+    chk(allow_smem(k_fwd_rows_gather<T, 5>, pl->smem_gather));
+    chk(allow_smem(k_fwd_rows_gather<T, 6>, pl->smem_gather));
+    chk(allow_smem(k_gather_rows<T, 4>, pl->smem_dgather));
+    chk(allow_smem(k_gather_rows<T, 5>, pl->smem_dgather));
+    chk(allow_smem(k_gather_rows<T, 6>, pl->smem_dgather));
     chk(allow_smem(k_fwd_rows_gather<T, 0>, pl->smem_gather));
     chk(allow_smem(k_fwd_rows_gather<T, 1>, pl->smem_gather));
     chk(allow_smem(k_fwd_rows_gather<T, 2>, pl->smem_gather));
@@ -454,7 +462,7 @@ void launch_direct_conv(const mpi_plan* pl, bool fwd, const T* in, T* out, const
                                                                           pl->plan, 1, 0, dh);
     else
         k_conv_direct<T, 3, 1, S, EPI><<<grid, 64 * S, pl->smem_dadj, st>>>(pl->dprob, in, out, c_in, taus,
-                                                                            pl->plan, 0, 1, 0);
+                                                                            pl->plan, 0, 1, dh);
 }
 
 // Forward: FFT {rows, columns, rows + gather}, direct {convolution, gather}.
@@ -462,8 +470,7 @@ void launch_direct_conv(const mpi_plan* pl, bool fwd, const T* in, T* out, const
 // order to the work buffer; 2: trajectory gradients of <in0, A c> to out0
 // (positions) and out1 (velocities).
 template <typename T, int MODE>
-void fwd_stage(const mpi_plan* pl, int k, const T* c, T* out0, const T* in0, T* out1, char* work, hipStream_t st,
-               int dh = 0) {
+void fwd_stage(const mpi_plan* pl, int k, const T* c, GatherIO<T> io, char* work, hipStream_t st, int dh = 0) {
     const char* plan = pl->plan;
     const Prob* P = pl->dprob;
     const int B = pl->count;
@@ -482,8 +489,8 @@ void fwd_stage(const mpi_plan* pl, int k, const T* c, T* out0, const T* in0, T* 
                                                                                                      work, dh);
             break;
         case 2:
-            k_fwd_rows_gather<T, MODE><<<dim3(xcd_grid(pl->max_nb), B), 256, pl->smem_gather, st>>>(
-                P, out0, in0, out1, plan, work);
+            k_fwd_rows_gather<T, MODE><<<dim3(xcd_grid(pl->max_nb), B), 256, pl->smem_gather, st>>>(P, io, plan,
+                                                                                                     work);
             break;
         case 3:
             launch_direct_conv<T, 4, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st, dh);
@@ -491,8 +498,7 @@ void fwd_stage(const mpi_plan* pl, int k, const T* c, T* out0, const T* in0, T* 
             launch_direct_conv<T, 16, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st, dh);
             break;
         case 4:
-            k_gather_rows<T, MODE><<<dim3(pl->max_nb, B), 256, pl->smem_dgather, st>>>(P, out0, in0, out1, plan,
-                                                                                       work);
+            k_gather_rows<T, MODE><<<dim3(pl->max_nb, B), 256, pl->smem_dgather, st>>>(P, io, plan, work);
             break;
         default: break;
     }
@@ -502,7 +508,9 @@ void fwd_stage(const mpi_plan* pl, int k, const T* c, T* out0, const T* in0, T* 
 // convolution}.  SORTED: the residual is already in cell order in the work
 // buffer.  EPI 0: c_out = A^T s; EPI 1: c_out = c_in - tau_b A^T r.
 template <typename T, bool SORTED, int EPI>
-void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, char* work, hipStream_t st) {
+void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, char* work, hipStream_t st,
+               T* z_out = nullptr) {
+    // z_out: also the transpose with the dK/dh tables (plans built with the derivative tables)
     const char* plan = pl->plan;
     const Prob* P = pl->dprob;
     const int B = pl->count;
@@ -515,14 +523,20 @@ void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, c
                                                                                                     work);
             break;
         case 1:
-            if (pl->col_split)
+            if (z_out)
+                k_adj_cols<T, false, true><<<dim3(xcd_grid((pl->max_h + 3) / 4), B), 256, pl->smem_col, st>>>(
+                    P, plan, work);
+            else if (pl->col_split)
                 k_adj_cols<T, true><<<dim3(xcd_grid(pl->max_h), B), 192, pl->smem_col, st>>>(P, plan, work);
             else
                 k_adj_cols<T, false><<<dim3(xcd_grid((pl->max_h + 3) / 4), B), 256, pl->smem_col, st>>>(P, plan, work);
             break;
         case 2:
             k_adj_rows<T, EPI><<<dim3(xcd_grid((pl->max_rowpairs + 3) / 4), B), 256, pl->smem_row, st>>>(
-                P, c_out, c_in, taus, plan, work);
+                P, c_out, c_in, taus, plan, work, 0);
+            if (z_out)
+                k_adj_rows<T, 0><<<dim3(xcd_grid((pl->max_rowpairs + 3) / 4), B), 256, pl->smem_row, st>>>(
+                    P, z_out, nullptr, taus, plan, work, 1);
             break;
         case 3:
             k_scatter_rows<T, SORTED><<<dim3(pl->max_n, B), 256, pl->smem_dscatter, st>>>(P, s, plan, work);
@@ -533,6 +547,11 @@ void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, c
             launch_direct_conv<T, 4, EPI>(pl, false, G, out, c_in, taus, st);
             launch_direct_conv<T, 8, EPI>(pl, false, G, out, c_in, taus, st);
             launch_direct_conv<T, 16, EPI>(pl, false, G, out, c_in, taus, st);
+            if (z_out) {
+                launch_direct_conv<T, 4, 0>(pl, false, G, z_out, nullptr, taus, st, 1);
+                launch_direct_conv<T, 8, 0>(pl, false, G, z_out, nullptr, taus, st, 1);
+                launch_direct_conv<T, 16, 0>(pl, false, G, z_out, nullptr, taus, st, 1);
+            }
             break;
         }
         default: break;
@@ -541,25 +560,35 @@ void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, c
 
 template <typename T>
 int forward_impl(const mpi_plan* pl, const T* c, T* s, char* work, hipStream_t st, int dh = 0) {
-    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 0>(pl, k, c, s, nullptr, nullptr, work, st, dh);
+    GatherIO<T> io;
+    io.out0 = s;
+    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 0>(pl, k, c, io, work, st, dh);
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
 template <typename T>
 int residual_impl(const mpi_plan* pl, const T* c, const T* y, T* out, char* work, hipStream_t st) {
-    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 3>(pl, k, c, out, y, nullptr, work, st);
+    GatherIO<T> io;
+    io.out0 = out;
+    io.in0 = y;
+    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 3>(pl, k, c, io, work, st);
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
 template <typename T>
 int traj_vjp_impl(const mpi_plan* pl, const T* x, const T* y, T* g_r, T* g_v, char* work, hipStream_t st) {
-    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 2>(pl, k, x, g_r, y, g_v, work, st);
+    GatherIO<T> io;
+    io.out0 = g_r;
+    io.in0 = y;
+    io.out1 = g_v;
+    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 2>(pl, k, x, io, work, st);
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
 template <typename T, bool SORTED, int EPI>
-int adjoint_impl(const mpi_plan* pl, const T* s, T* c_out, const T* c_in, char* work, hipStream_t st) {
-    for (int k = 0; k < kAdjStages; ++k) adj_stage<T, SORTED, EPI>(pl, k, s, c_out, c_in, work, st);
+int adjoint_impl(const mpi_plan* pl, const T* s, T* c_out, const T* c_in, char* work, hipStream_t st,
+                 T* z_out = nullptr) {
+    for (int k = 0; k < kAdjStages; ++k) adj_stage<T, SORTED, EPI>(pl, k, s, c_out, c_in, work, st, z_out);
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
@@ -568,7 +597,7 @@ int adjoint_impl(const mpi_plan* pl, const T* s, T* c_out, const T* c_in, char* 
 // the step lands in c directly; with one, in work.u and then D(u) -> c.
 template <typename T>
 int iteration_impl(const mpi_plan* pl, T* c, bool denoise, int rad, char* work, hipStream_t st) {
-    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 1>(pl, k, c, nullptr, nullptr, nullptr, work, st);
+    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 1>(pl, k, c, GatherIO<T>{}, work, st);
     int rc;
     if (!denoise) {
         rc = adjoint_impl<T, true, 1>(pl, nullptr, c, c, work, st);
@@ -778,21 +807,139 @@ int build_common(const mpi_problem* probs, int count, void* plan_mem, size_t pla
     return MPI_OK;
 }
 
+// Per-problem steps and the normalised Gaussian weights of the denoiser
+// (sigma > 0) into the work buffer.
+hipError_t upload_iter_consts(mpi_plan* pl, double sigma, int rad, const double* taus, char* work, hipStream_t st) {
+    hipError_t e = hipMemcpyAsync(work + pl->L.w_taus, taus, sizeof(double) * pl->count, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess || !(sigma > 0.0)) return e;
+    double sum = 0.0;
+    for (int k = -rad; k <= rad; ++k) {
+        pl->wts[k + rad] = std::exp(-0.5 * k * k / (sigma * sigma));
+        sum += pl->wts[k + rad];
+    }
+    for (int k = 0; k <= 2 * rad; ++k) pl->wts[k] /= sum;
+    return hipMemcpyAsync(work + pl->L.w_wts, pl->wts, sizeof(double) * (2 * rad + 1), hipMemcpyHostToDevice, st);
+}
+
+// ------------------------------------------------------------ unrolled VJP --
+// Buffers of the reverse sweep, all flat over the batch (C elements per
+// concentration vector, S per signal vector), in the caller's VJP workspace:
+// per step of a segment the iterate c_e, z_e = (dA/dh)^T r_e, the residual
+// r_e (cell order) and the nine sampled-field planes of c_e; then g_u, q,
+// the two per-sample gradient accumulators, (dA/dh)^T q and the float64
+// h-gradient accumulator.
+struct VjpLayout {
+    size_t cs = 0, zs = 0, rs = 0, fc = 0, gu = 0, q = 0, gr = 0, gv = 0, zq = 0, acc_h = 0, bytes = 0;
+    int64_t C = 0, S = 0, F = 0;
+};
+
+VjpLayout vjp_layout(const mpi_plan* pl, int every) {
+    VjpLayout v;
+    size_t off = 0;
+    const size_t e = pl->L.elem;
+    v.C = pl->L.c_elems;
+    v.S = pl->L.s_elems;
+    v.F = 9 * (v.S / 2);
+    v.cs = take(off, e * v.C * every);
+    v.zs = take(off, e * v.C * every);
+    v.rs = take(off, e * v.S * every);
+    v.fc = take(off, e * v.F * every);
+    v.gu = take(off, e * v.C);
+    v.q = take(off, e * v.S);
+    v.gr = take(off, e * v.S);
+    v.gv = take(off, e * v.S);
+    v.zq = take(off, e * v.C);
+    v.acc_h = take(off, sizeof(double) * pl->count);
+    v.bytes = off;
+    return v;
+}
+
+// Reverse sweep of K steps c <- D(c - tau A^T (A c - s)) (tau fixed, D
+// symmetric), checkpoints c_0, c_E, c_2E, ... given.  Per segment, from its
+// checkpoint: r_e = A c_e - s with the sampled field of c_e, the transpose of
+// r_e with both tables (the step to c_{e+1}, and z_e); then backwards:
+//   g_u = D gbar;  acc_h += <g_u, z_e>;
+//   q = A g_u;  acc_r += r_e^T (dA g_u / dr) + q^T (dA c_e / dr), acc_v likewise;
+//   gbar = g_u - tau A^T q;  acc_h += <c_e, (dA/dh)^T q>.
+// At the end dL/dh = -tau acc_h and the trajectory gradients -tau acc_{r,v}.
+template <typename T>
+int unrolled_vjp_impl(mpi_plan* pl, const T* s, const T* ckpt, int K, int E, double sigma, int rad,
+                      const double* taus, T* gbar, double* g_h, T* g_r, T* g_v, char* work, char* vj,
+                      hipStream_t st) {
+    const VjpLayout V = vjp_layout(pl, E);
+    const bool den = sigma > 0.0;
+    const Prob* P = pl->dprob;
+    const int B = pl->count;
+    HIP_TRY(upload_iter_consts(pl, sigma, den ? rad : 0, taus, work, st));
+    const double* wts = reinterpret_cast<const double*>(work + pl->L.w_wts);
+    const double* dtaus = reinterpret_cast<const double*>(work + pl->L.w_taus);
+    k_permute_signal<T><<<dim3(blocks(pl->max_t, 256), B), 256, 0, st>>>(P, s, pl->plan, work);
+    T* cs = reinterpret_cast<T*>(vj + V.cs);
+    T* zs = reinterpret_cast<T*>(vj + V.zs);
+    T* rs = reinterpret_cast<T*>(vj + V.rs);
+    T* fc = reinterpret_cast<T*>(vj + V.fc);
+    T* gu = reinterpret_cast<T*>(vj + V.gu);
+    T* q = reinterpret_cast<T*>(vj + V.q);
+    T* gr = reinterpret_cast<T*>(vj + V.gr);
+    T* gv = reinterpret_cast<T*>(vj + V.gv);
+    T* zq = reinterpret_cast<T*>(vj + V.zq);
+    double* acc_h = reinterpret_cast<double*>(vj + V.acc_h);
+    k_fill<T><<<blocks(V.S, 256), 256, 0, st>>>(gr, V.S, T(0));
+    k_fill<T><<<blocks(V.S, 256), 256, 0, st>>>(gv, V.S, T(0));
+    k_fill<double><<<blocks(B, 256), 256, 0, st>>>(acc_h, B, 0.0);
+    const dim3 dn_grid(pl->max_dntiles, pl->max_dntiles, B);
+    const int nseg = (K + E - 1) / E;
+    for (int si = nseg - 1; si >= 0; --si) {
+        const int L = std::min(E, K - si * E);
+        HIP_TRY(hipMemcpyAsync(cs, ckpt + int64_t(si) * V.C, sizeof(T) * V.C, hipMemcpyDeviceToDevice, st));
+        for (int e = 0; e < L; ++e) {
+            T* ce = cs + e * V.C;
+            const T* re = rs + e * V.S;
+            GatherIO<T> io;
+            io.out0 = rs + e * V.S;
+            io.f = fc + e * V.F;
+            for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 5>(pl, k, ce, io, work, st);
+            T* next = e + 1 < L ? cs + (e + 1) * V.C : nullptr;
+            int rc;
+            if (next && !den) {
+                rc = adjoint_impl<T, true, 1>(pl, re, next, ce, work, st, zs + e * V.C);
+            } else {
+                rc = adjoint_impl<T, true, 2>(pl, re, nullptr, ce, work, st, zs + e * V.C);
+                if (rc == MPI_OK && next) k_denoise<T><<<dn_grid, 256, 0, st>>>(P, work, nullptr, next, wts, rad);
+            }
+            if (rc != MPI_OK) return rc;
+        }
+        for (int e = L - 1; e >= 0; --e) {
+            const T* ce = cs + e * V.C;
+            T* g_u = gbar;
+            if (den) {
+                k_denoise<T><<<dn_grid, 256, 0, st>>>(P, work, gbar, gu, wts, rad);
+                g_u = gu;
+            }
+            k_dot<T><<<B, 1024, 0, st>>>(P, g_u, zs + e * V.C, 1, 2, acc_h, 1);
+            GatherIO<T> io;
+            io.out0 = q;
+            io.in0 = rs + e * V.S;
+            io.out1 = gr;
+            io.out2 = gv;
+            io.f = fc + e * V.F;
+            for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 6>(pl, k, g_u, io, work, st);
+            const int rc = adjoint_impl<T, true, 1>(pl, q, gbar, g_u, work, st, zq);
+            if (rc != MPI_OK) return rc;
+            k_dot<T><<<B, 1024, 0, st>>>(P, ce, zq, 1, 2, acc_h, 1);
+        }
+    }
+    k_vjp_finish<T><<<dim3(blocks(pl->max_t, 256), B), 256, 0, st>>>(P, pl->plan, gr, gv, g_r, g_v, acc_h, g_h,
+                                                                      dtaus);
+    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+}
+
 template <typename T>
 int iterate_impl(mpi_plan* pl, const T* s, T* c, const mpi_iter_params* ip, const double* taus, char* work,
                  hipStream_t st) {
     const bool denoise = ip->denoise_sigma_px > 0.0;
     const int rad = denoise ? ip->denoise_radius : 0;
-    HIP_TRY(hipMemcpyAsync(work + pl->L.w_taus, taus, sizeof(double) * pl->count, hipMemcpyHostToDevice, st));
-    if (denoise) {
-        double sum = 0.0;
-        for (int k = -rad; k <= rad; ++k) {
-            pl->wts[k + rad] = std::exp(-0.5 * k * k / (ip->denoise_sigma_px * ip->denoise_sigma_px));
-            sum += pl->wts[k + rad];
-        }
-        for (int k = 0; k <= 2 * rad; ++k) pl->wts[k] /= sum;
-        HIP_TRY(hipMemcpyAsync(work + pl->L.w_wts, pl->wts, sizeof(double) * (2 * rad + 1), hipMemcpyHostToDevice, st));
-    }
+    HIP_TRY(upload_iter_consts(pl, denoise ? ip->denoise_sigma_px : 0.0, rad, taus, work, st));
     k_permute_signal<T><<<dim3(blocks(pl->max_t, 256), pl->count), 256, 0, st>>>(pl->dprob, s, pl->plan, work);
     HIP_TRY(hipGetLastError());
     if (ip->n_iter == 0) return MPI_OK;
@@ -1081,11 +1228,47 @@ int mpi_batch_dot(const mpi_plan* plan, const void* a, const void* b, int space,
     if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
     if (plan->dtype == MPI_F64)
         k_dot<double><<<plan->count, 1024, 0, stream>>>(plan->dprob, static_cast<const double*>(a),
-                                                        static_cast<const double*>(b), space, comp, out);
+                                                        static_cast<const double*>(b), space, comp, out, 0);
     else
         k_dot<float><<<plan->count, 1024, 0, stream>>>(plan->dprob, static_cast<const float*>(a),
-                                                       static_cast<const float*>(b), space, comp, out);
+                                                       static_cast<const float*>(b), space, comp, out, 0);
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+}
+
+int mpi_batch_unrolled_vjp_bytes(const mpi_plan* plan, int32_t every, size_t* vjp_bytes) {
+    if (!plan || every < 1 || !vjp_bytes) return MPI_ERR_ARG;
+    *vjp_bytes = vjp_layout(plan, every).bytes;
+    return MPI_OK;
+}
+
+int mpi_batch_unrolled_vjp(const mpi_plan* plan, const void* s, const void* checkpoints, int32_t n_iter,
+                           int32_t every, double denoise_sigma_px, int32_t denoise_radius, const double* taus,
+                           void* gbar, double* g_h, void* g_r, void* g_v, void* work, size_t work_bytes,
+                           void* vjp_work, size_t vjp_bytes, hipStream_t stream) {
+    int rc = check_call(plan, s, gbar, work, work_bytes);
+    if (rc != MPI_OK) return rc;
+    if (!plan->L.deriv) return MPI_ERR_UNSUPPORTED;
+    if (!checkpoints || !g_h || !g_r || !g_v || !vjp_work || !taus || n_iter < 1 || every < 1) return MPI_ERR_ARG;
+    if (denoise_sigma_px > 0.0 && (denoise_radius < 0 || denoise_radius > kDnMaxR)) return MPI_ERR_ARG;
+    const size_t el = plan->L.elem;
+    if (misaligned(checkpoints, el) || misaligned(g_r, el) || misaligned(g_v, el) || misaligned(g_h, 8) ||
+        misaligned(vjp_work, kAlign))
+        return MPI_ERR_ARG;
+    if (vjp_bytes < vjp_layout(plan, every).bytes) return MPI_ERR_WORKSPACE;
+    for (int b = 0; b < plan->count; ++b)
+        if (!std::isfinite(taus[b])) return MPI_ERR_ARG;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    mpi_plan* pl = const_cast<mpi_plan*>(plan);
+    char* w = static_cast<char*>(work);
+    char* vj = static_cast<char*>(vjp_work);
+    const double sigma = denoise_sigma_px > 0.0 ? denoise_sigma_px : 0.0;
+    if (plan->dtype == MPI_F64)
+        return unrolled_vjp_impl<double>(pl, static_cast<const double*>(s), static_cast<const double*>(checkpoints),
+                                         n_iter, every, sigma, denoise_radius, taus, static_cast<double*>(gbar), g_h,
+                                         static_cast<double*>(g_r), static_cast<double*>(g_v), w, vj, stream);
+    return unrolled_vjp_impl<float>(pl, static_cast<const float*>(s), static_cast<const float*>(checkpoints), n_iter,
+                                    every, sigma, denoise_radius, taus, static_cast<float*>(gbar), g_h,
+                                    static_cast<float*>(g_r), static_cast<float*>(g_v), w, vj, stream);
 }
 
 int mpi_stage_count(const mpi_plan* plan) {
@@ -1109,15 +1292,15 @@ int mpi_stage_launch(const mpi_plan* plan, int stage, int reps, void* c, void* s
     for (int r = 0; r < reps; ++r) {
         if (plan->dtype == MPI_F64) {
             if (stage < kFwdStages)
-                fwd_stage<double, 0>(plan, stage, static_cast<const double*>(c), static_cast<double*>(s), nullptr,
-                                     nullptr, w, stream);
+                fwd_stage<double, 0>(plan, stage, static_cast<const double*>(c),
+                                     GatherIO<double>{static_cast<double*>(s)}, w, stream);
             else
                 adj_stage<double, false, 0>(plan, stage - kFwdStages, static_cast<const double*>(s),
                                             static_cast<double*>(c), nullptr, w, stream);
         } else {
             if (stage < kFwdStages)
-                fwd_stage<float, 0>(plan, stage, static_cast<const float*>(c), static_cast<float*>(s), nullptr,
-                                    nullptr, w, stream);
+                fwd_stage<float, 0>(plan, stage, static_cast<const float*>(c),
+                                    GatherIO<float>{static_cast<float*>(s)}, w, stream);
             else
                 adj_stage<float, false, 0>(plan, stage - kFwdStages, static_cast<const float*>(s),
                                            static_cast<float*>(c), nullptr, w, stream);

@@ -24,12 +24,22 @@ namespace mpik {
 //         sample position and velocity, inside the bilinear patch:
 //         out0[k] = (y^T M(dG/dx) v, y^T M(dG/dy) v), out1[k] = M(G) y,
 //         with M(g) = [[g_xx, g_xy], [g_xy, g_yy]] and d/dx = (N/2) d/dfx.
+// MODE 4: s to out0[p] (cell order).
+// MODE 5: s - y (y = ysort) to out0[p], and the sampled field with its
+//         position gradient, nine planes f[q * fstride + p]:
+//         (G_xx, G_xy, G_yy, dG/dx (3), dG/dy (3)), all in cell order.
+// MODE 6: with y = in0[p] and the field F' of planes f (as MODE 5 wrote them):
+//         q = G v to out0[p]; out1[p] += (y^T M(dG/dx) v + q^T M(dF'/dx) v,
+//         y^T M(dG/dy) v + q^T M(dF'/dy) v); out2[p] += M(G) y + M(F') q;
+//         all in cell order.
 template <typename T, int MODE, int U = 4>
 __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int p0, int p1,
                                             const vec4<T>* __restrict__ samp, const int2* __restrict__ sidx,
                                             const vec2<T>* __restrict__ ysort, vec2<T>* __restrict__ out_sorted,
                                             T* __restrict__ out0, const T* __restrict__ in0, T* __restrict__ out1,
+                                            T* __restrict__ out2, T* __restrict__ f, int64_t fstride,
                                             int tid, int nthreads) {
+    constexpr bool GRAD = MODE == 2 || MODE == 5 || MODE == 6;
     const T inv_d = T(0.5) * T(N);
     for (int base = p0 + tid; base < p1; base += U * nthreads) {
         vec4<T> e[U];
@@ -41,7 +51,11 @@ __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int
             if (p < p1) {
                 e[u] = samp[p];
                 id[u] = sidx[p];
-                if (MODE == 1) y[u] = ysort[p];
+                if (MODE == 1 || MODE == 5) y[u] = ysort[p];
+                if (MODE == 6) {
+                    y[u].x = in0[2 * p];
+                    y[u].y = in0[2 * p + 1];
+                }
             }
         }
         if (MODE == 2 || MODE == 3) {
@@ -68,7 +82,7 @@ __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int
                 const T lo = gx * a00 + fx * a10;
                 const T hi = gx * a01 + fx * a11;
                 g[ch] = gy * lo + fy * hi;
-                if (MODE == 2) {
+                if (GRAD) {
                     dx[ch] = inv_d * (gy * (a10 - a00) + fy * (a11 - a01));
                     dy[ch] = inv_d * (gx * (a01 - a00) + fx * (a11 - a10));
                 }
@@ -81,6 +95,25 @@ __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int
                 out0[2 * k + 1] = yx * (dy[0] * vx + dy[1] * vy) + yy * (dy[1] * vx + dy[2] * vy);
                 out1[2 * k] = g[0] * yx + g[1] * yy;
                 out1[2 * k + 1] = g[1] * yx + g[2] * yy;
+            } else if (MODE == 6) {
+                const T yx = y[u].x, yy = y[u].y;
+                const T qx = g[0] * vx + g[1] * vy;
+                const T qy = g[1] * vx + g[2] * vy;
+                T h[9];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) h[q] = f[q * fstride + p];
+                const T gr_x = (yx * (dx[0] * vx + dx[1] * vy) + yy * (dx[1] * vx + dx[2] * vy)) +
+                               (qx * (h[3] * vx + h[4] * vy) + qy * (h[4] * vx + h[5] * vy));
+                const T gr_y = (yx * (dy[0] * vx + dy[1] * vy) + yy * (dy[1] * vx + dy[2] * vy)) +
+                               (qx * (h[6] * vx + h[7] * vy) + qy * (h[7] * vx + h[8] * vy));
+                const T gv_x = (g[0] * yx + g[1] * yy) + (h[0] * qx + h[1] * qy);
+                const T gv_y = (g[1] * yx + g[2] * yy) + (h[1] * qx + h[2] * qy);
+                out0[2 * p] = qx;
+                out0[2 * p + 1] = qy;
+                out1[2 * p] += gr_x;
+                out1[2 * p + 1] += gr_y;
+                out2[2 * p] += gv_x;
+                out2[2 * p + 1] += gv_y;
             } else {
                 const T sx = g[0] * vx + g[1] * vy;
                 const T sy = g[1] * vx + g[2] * vy;
@@ -89,6 +122,18 @@ __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int
                     o.x = sx - y[u].x;
                     o.y = sy - y[u].y;
                     out_sorted[p] = o;
+                } else if (MODE == 5) {
+                    out0[2 * p] = sx - y[u].x;
+                    out0[2 * p + 1] = sy - y[u].y;
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) {
+                        f[ch * fstride + p] = g[ch];
+                        f[(3 + ch) * fstride + p] = dx[ch];
+                        f[(6 + ch) * fstride + p] = dy[ch];
+                    }
+                } else if (MODE == 4) {
+                    out0[2 * p] = sx;
+                    out0[2 * p + 1] = sy;
                 } else if (MODE == 3) {
                     out0[2 * k] = sx - y[u].x;
                     out0[2 * k + 1] = sy - y[u].y;

@@ -23,7 +23,8 @@ EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "
            "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
            "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_iterate",
            "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
-           "mpi_batch_dot", "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
+           "mpi_batch_dot", "mpi_batch_unrolled_vjp_bytes", "mpi_batch_unrolled_vjp",
+           "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
            "mpi_plan_destroy", "mpi_status_str", "mpi_abi_version")
 MPI_BUILD_TUNE, MPI_BUILD_COL_SPLIT, MPI_BUILD_COL_WAVE, MPI_BUILD_DERIV = 1, 2, 4, 8
 
@@ -82,6 +83,10 @@ def lib() -> ctypes.CDLL:
         L.mpi_batch_denoise.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, vp, sz, vp]
         L.mpi_batch_dot.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, sz, vp]
         L.mpi_batch_sample_order.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.mpi_batch_unrolled_vjp_bytes.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(sz)]
+        L.mpi_batch_unrolled_vjp.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                             ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp, vp, sz,
+                                             vp, sz, vp]
         L.mpi_stage_count.argtypes = [vp]
         L.mpi_stage_name.argtypes = [vp, ctypes.c_int]
         L.mpi_stage_name.restype = ctypes.c_char_p
@@ -94,7 +99,8 @@ def lib() -> ctypes.CDLL:
                      "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
                      "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_iterate",
                      "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
-                     "mpi_batch_dot", "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_launch",
+                     "mpi_batch_dot", "mpi_batch_unrolled_vjp_bytes", "mpi_batch_unrolled_vjp",
+                     "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_launch",
                      "mpi_plan_destroy",
                      "mpi_abi_version"):
             getattr(L, name).restype = ctypes.c_int
@@ -460,6 +466,32 @@ class Batch:
                                    {"x": 0, "y": 1, "both": 2}[comp], out.data_ptr(), self.work.data_ptr(),
                                    self.work.numel(), _stream(stream)), "mpi_batch_dot")
         return out
+
+    def unrolled_vjp(self, s_all, checkpoints, n_iter, every, taus, gbar, denoise_sigma_px=0.0, denoise_radius=2,
+                     stream=None):
+        """Reverse sweep of `n_iter` iteration steps from the checkpoints (a
+        tensor of ceil(n_iter/every) concatenated concentration vectors).
+        gbar (dL/dc_K) is overwritten with dL/dc_0.  Returns (g_h float64 per
+        problem, g_r, g_v per sample in time order)."""
+        self._flat(s_all, self.s_offsets[-1], "s_all")
+        self._flat(gbar, self.c_offsets[-1], "gbar")
+        nseg = (int(n_iter) + int(every) - 1) // int(every)
+        self._flat(checkpoints, nseg * self.c_offsets[-1], "checkpoints")
+        vb = ctypes.c_size_t()
+        _check(lib().mpi_batch_unrolled_vjp_bytes(self._h, int(every), ctypes.byref(vb)),
+               "mpi_batch_unrolled_vjp_bytes")
+        if getattr(self, "_vjp_work", None) is None or self._vjp_work.numel() < vb.value:
+            self._vjp_work = torch.empty(vb.value, dtype=torch.uint8, device=self.device)
+        g_h = torch.empty(self.count, dtype=torch.float64, device=self.device)
+        g_r = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
+        g_v = torch.empty_like(g_r)
+        tarr = (ctypes.c_double * self.count)(*[float(t) for t in taus])
+        _check(lib().mpi_batch_unrolled_vjp(self._h, s_all.data_ptr(), checkpoints.data_ptr(), int(n_iter),
+                                            int(every), float(denoise_sigma_px), int(denoise_radius), tarr,
+                                            gbar.data_ptr(), g_h.data_ptr(), g_r.data_ptr(), g_v.data_ptr(),
+                                            self.work.data_ptr(), self.work.numel(), self._vjp_work.data_ptr(),
+                                            self._vjp_work.numel(), _stream(stream)), "mpi_batch_unrolled_vjp")
+        return g_h, g_r, g_v
 
     def sample_order(self, b, stream=None):
         """(time index, base cell i0 | j0 << 16) of problem b's samples in the

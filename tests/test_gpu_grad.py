@@ -201,11 +201,19 @@ def _unrolled_ref(it, s, tau, c_true, n_iter, sigma, **kw):
                                 frozen=it["model"].cells())
 
 
-@pytest.mark.parametrize("dtype,sigma", [(torch.float32, None), (torch.float32, 0.5), (torch.float64, 0.5)])
-def test_unrolled_gradients_match_oracle(dtype, sigma):
+SHAPES_MIXED = [(32, 7, 2500, "auto"), (48, 31, 5000, "auto"), (40, 12, 3001, "auto")]   # direct + FFT
+
+
+@pytest.mark.parametrize("dtype,sigma,shapes", [
+    (torch.float32, None, SHAPES_FFT), (torch.float32, 0.5, SHAPES_FFT), (torch.float64, 0.5, SHAPES_FFT),
+    (torch.float32, 0.5, SHAPES), (torch.float64, None, SHAPES), (torch.float32, 0.5, SHAPES_MIXED)],
+    ids=["fft-f32", "fft-f32-den", "fft-f64-den", "direct-f32-den", "direct-f64", "mixed-f32-den"])
+def test_unrolled_gradients_match_oracle(dtype, sigma, shapes):
     """K = 7 with checkpoints every 3 (a ragged last segment), three problems
     of different sizes in one batch."""
-    gc = GradCase(SHAPES_FFT, dtype)
+    gc = GradCase(shapes, dtype)
+    if shapes is SHAPES_MIXED:
+        assert {inf["conv_mode"] for inf in gc.plan().info} == {"direct", "fft"}
     s_list, taus, truths = _unrolled_setup(gc)
     K = 7
     loss, g_c0, g_h, g_ax, g_ay = _unrolled_gpu(gc, s_list, taus, truths, K, sigma, every=3)
@@ -218,6 +226,21 @@ def test_unrolled_gradients_match_oracle(dtype, sigma):
         for got, name in ((g_h[b], "h"), (g_ax[b], "ax"), (g_ay[b], "ay")):
             assert _close(got, g[name], tol), (name, b, got, g[name])
     assert _close(loss, total, tol)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_unrolled_gradients_do_not_depend_on_checkpoint_spacing(dtype):
+    """One segment, segments of one step, and a ragged split agree: the reverse
+    sweep recomputes each segment from its checkpoint."""
+    gc = GradCase(SHAPES_MIXED, dtype)
+    s_list, taus, truths = _unrolled_setup(gc)
+    runs = [_unrolled_gpu(gc, s_list, taus, truths, 6, 0.5, every=e) for e in (6, 1, 4)]
+    tol = 1e-5 if dtype == torch.float32 else 1e-12
+    for other in runs[1:]:
+        for b in range(len(gc.items)):
+            assert rel_l2(other[1][b], runs[0][1][b]) <= tol
+        for i in (2, 3, 4):
+            assert np.all(np.abs(other[i] - runs[0][i]) <= tol * np.abs(runs[0][i]))
 
 
 def _oracle_loss(it, s, tau, c_true, n_iter, sigma, **kw):
