@@ -19,7 +19,9 @@
  *     grid); R >= N-1 is the untruncated kernel;
  *   - the field is interpolated bilinearly between cell centres; a sample
  *     needs g = (r + 1)/delta - 1/2 in [0, N-1] on both axes;
- *   - s is [T][2] interleaved (x, y), matching a contiguous (T, 2) tensor.
+ *   - s is [T][2] interleaved (x, y), matching a contiguous (T, 2) tensor;
+ *     signal buffers the library writes must be aligned to two elements
+ *     (else MPI_ERR_ARG).
  *
  * Memory ownership: the caller owns every device buffer -- inputs, outputs,
  * the plan memory and the work memory.  The library never allocates device

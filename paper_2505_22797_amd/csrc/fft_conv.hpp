@@ -63,12 +63,6 @@ __host__ __device__ constexpr size_t scatter_row_smem_bytes(int N) {
     return a + lds_align(size_t(3) * N * sizeof(T)) + (lines > sc ? lines : sc);
 }
 
-template <typename T, int M>
-__device__ __forceinline__ void load_twiddles(cx<T>* tw_s, const char* plan, const Prob& p, int tid, int nt) {
-    const cx<T>* tw = at<cx<T>>(plan, p.o_tw);
-    for (int i = tid; i < M; i += nt) tw_s[i] = tw[i];
-}
-
 // spectrum value of channel ch at (kx, ky), kx in [0, M/2], ky in [0, M)
 template <typename T, int M>
 __device__ __forceinline__ T spec_at(const T* __restrict__ spec, int ch, int kx, int ky) {
@@ -96,6 +90,53 @@ __device__ __forceinline__ cx<T> pair_spectrum(const cx<T>* __restrict__ ra, con
     return cx<T>{A.x - B.y, A.y + B.x};
 }
 
+// Loads issued ahead of the work-group barrier that publishes the twiddles: a
+// kernel first puts its share of the twiddles and its input line in
+// registers, so that every load of the work-group is in flight at once, and
+// only then waits and moves them to LDS.
+template <typename T, int M, int NT> struct TwiddleRegs {
+    static constexpr int PER = (M + NT - 1) / NT;
+    cx<T> v[PER];
+    __device__ __forceinline__ void load(const char* plan, const Prob& p, int tid) {
+        const cx<T>* tw = at<cx<T>>(plan, p.o_tw);
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (M % NT == 0 || tid + q * NT < M) v[q] = tw[tid + q * NT];
+    }
+    __device__ __forceinline__ void store(cx<T>* tw_s, int tid) const {
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (M % NT == 0 || tid + q * NT < M) tw_s[tid + q * NT] = v[q];
+    }
+};
+
+// The half-spectrum values pair_spectrum reads for kx = lane + 64 m, loaded
+// ahead; spectrum(m) then gives the same value as pair_spectrum(ra, rb, kx).
+template <typename T, int M> struct PairRegs {
+    static constexpr int PL = M / kWave;
+    cx<T> a[PL], b[PL];
+    __device__ __forceinline__ void load(const cx<T>* __restrict__ ra, const cx<T>* __restrict__ rb, bool two,
+                                         int lane) {
+#pragma unroll
+        for (int m = 0; m < PL; ++m) {
+            const int kx = lane + m * kWave, k = kx <= M / 2 ? kx : M - kx;
+            a[m] = ra[k];
+            b[m] = two ? rb[k] : cx<T>{T(0), T(0)};
+        }
+    }
+    __device__ __forceinline__ cx<T> spectrum(int m, int lane) const {
+        const int kx = lane + m * kWave;
+        cx<T> A = a[m], B = b[m];
+        if (kx <= M / 2) {
+            if (kx == 0 || kx == M / 2) { A.y = T(0); B.y = T(0); }   // real at DC and Nyquist
+        } else {
+            A = cconj(A);
+            B = cconj(B);
+        }
+        return cx<T>{A.x - B.y, A.y + B.x};
+    }
+};
+
 // Half spectra of two real rows a, b from the spectrum Z of a + ib:
 // A = (Z_k + conj Z_-k)/2, B = (Z_k - conj Z_-k)/(2i), k in [0, M/2].
 template <typename T, int M>
@@ -115,31 +156,48 @@ __device__ void fwd_rows_body(const Prob& p, const T* __restrict__ c, const char
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int unit = xcd_unit(blockIdx.x, (N + 7) / 8);   // four row pairs per work-group
     if (unit < 0) return;
-    load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
-    __syncthreads();
+    TwiddleRegs<T, M, 4 * kWave> twr;
+    twr.load(plan, p, tid);
     const int q = 4 * unit + wave;
     const int r0 = 2 * q, r1 = 2 * q + 1;
-    if (r0 >= N) return;
-    const bool two = r1 < N;
-    cx<T>* line = sm.line[wave];
-    const T* c0 = c + int64_t(r0) * N;
-    const T* c1 = c + int64_t(r1) * N;
-    for (int i = lane; i < M; i += kWave) {
-        cx<T> z{T(0), T(0)};
-        if (i < N) {
-            z.x = c0[i];
-            if (two) z.y = c1[i];
+    const bool active = r0 < N, two = r1 < N;
+    constexpr int PL = M / kWave;
+    cx<T> x[PL];
+    if (active) {
+        const T* c0 = c + int64_t(r0) * N;
+        const T* c1 = c + int64_t(r1) * N;
+#pragma unroll
+        for (int m = 0; m < PL; ++m) {
+            const int i = lane + m * kWave;
+            cx<T> z{T(0), T(0)};
+            if (i < N) {
+                z.x = c0[i];
+                if (two) z.y = c1[i];
+            }
+            x[m] = z;
         }
-        line[i] = z;
     }
-    wave_sync();
-    fft_wave<T, false, M>(line, sm.tw, lane);
+    twr.store(sm.tw, tid);
+    __syncthreads();
+    cx<T>* line = sm.line[wave];
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < PL; ++m) line[lane + m * kWave] = x[m];
+        wave_sync();
+        fft_wave<T, false, M>(line, sm.tw, lane);
+    }
+    __syncthreads();
+    // the work-group's eight rows go out together: T1[k][row0 .. row0+7], so
+    // eight consecutive threads write one contiguous 64-byte run
     cx<T>* t1 = at<cx<T>>(work, p.w_t1);
-    for (int k = lane; k < H; k += kWave) {
+    const int row0 = 8 * unit;
+    for (int i = tid; i < 8 * H; i += 4 * kWave) {
+        const int k = i >> 3, r = i & 7;
+        if (row0 + r >= N) continue;
         cx<T> A, B;
-        split_pair<T, M>(line, k, A, B);
-        t1[int64_t(k) * N + r0] = A;
-        if (two) t1[int64_t(k) * N + r1] = B;
+        split_pair<T, M>(sm.line[r >> 1], k, A, B);
+        const bool odd = r & 1;
+        t1[int64_t(k) * N + row0 + r] = cx<T>{odd ? B.x : A.x, odd ? B.y : A.y};
     }
 }
 
@@ -157,9 +215,20 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
     if (SPLIT) {                                    // one column, waves 0..2
         const int kx = xcd_unit(blockIdx.x, H);
         if (kx < 0) return;
-        load_twiddles<T, M>(sm.tw, plan, p, tid, 3 * kWave);
+        TwiddleRegs<T, M, 3 * kWave> twr;
+        twr.load(plan, p, tid);
         const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(kx) * N;
-        for (int i = tid; i < M; i += 3 * kWave) sm.c[i] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+        constexpr int PC = (M + 3 * kWave - 1) / (3 * kWave);
+        cx<T> x[PC];
+#pragma unroll
+        for (int q = 0; q < PC; ++q) {
+            const int i = tid + q * 3 * kWave;
+            x[q] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+        }
+        twr.store(sm.tw, tid);
+#pragma unroll
+        for (int q = 0; q < PC; ++q)
+            if (tid + q * 3 * kWave < M) sm.c[tid + q * 3 * kWave] = x[q];
         __syncthreads();
         if (wave == 0) fft_wave<T, false, M>(sm.c, sm.tw, lane);
         __syncthreads();
@@ -172,30 +241,51 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
     } else {                                        // four columns, one per wave
         const int unit = xcd_unit(blockIdx.x, (H + 3) / 4);
         if (unit < 0) return;
-        load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
-        __syncthreads();
-        const int kx = 4 * unit + wave;
-        if (kx >= H) return;
+        TwiddleRegs<T, M, 4 * kWave> twr;
+        twr.load(plan, p, tid);
+        const int kx0 = 4 * unit, kx = kx0 + wave;
+        const bool active = kx < H;     // inactive waves stay for the work-group barriers
         cx<T>* line = sm.line[wave];
-        const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(kx) * N;
-        for (int i = lane; i < M; i += kWave) line[i] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
-        wave_sync();
-        fft_wave<T, false, M>(line, sm.tw, lane);
         constexpr int PL = M / kWave;
         cx<T> cr[PL];
+        if (active) {
+            const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(kx) * N;
 #pragma unroll
-        for (int i = 0; i < PL; ++i) cr[i] = line[lane + i * kWave];
-        for (int ch = 0; ch < 3; ++ch) {
-            wave_sync();
-#pragma unroll
-            for (int i = 0; i < PL; ++i) {
-                const int ky = lane + i * kWave;
-                line[ky] = cscale(cr[i], spec_at<T, M>(spec, ch, kx, ky));
+            for (int m = 0; m < PL; ++m) {
+                const int i = lane + m * kWave;
+                cr[m] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
             }
+        }
+        twr.store(sm.tw, tid);
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < PL; ++m) line[lane + m * kWave] = cr[m];
             wave_sync();
-            fft_wave<T, true, M>(line, sm.tw, lane);
+            fft_wave<T, false, M>(line, sm.tw, lane);
+#pragma unroll
+            for (int i = 0; i < PL; ++i) cr[i] = line[lane + i * kWave];
+        }
+        for (int ch = 0; ch < 3; ++ch) {
+            if (active) {
+                wave_sync();
+#pragma unroll
+                for (int i = 0; i < PL; ++i) {
+                    const int ky = lane + i * kWave;
+                    line[ky] = cscale(cr[i], spec_at<T, M>(spec, ch, kx, ky));
+                }
+                wave_sync();
+                fft_wave<T, true, M>(line, sm.tw, lane);
+            }
+            __syncthreads();
+            // the four columns go out together: four consecutive threads write
+            // T2[ch][j][kx0 .. kx0+3], one contiguous 32-byte run
             cx<T>* out = t2 + int64_t(ch) * N * H;
-            for (int j = lane; j < N; j += kWave) out[int64_t(j) * H + kx] = line[j];
+            for (int i = tid; i < 4 * N; i += 4 * kWave) {
+                const int j = i >> 2, cc = i & 3;
+                if (kx0 + cc < H) out[int64_t(j) * H + kx0 + cc] = sm.line[cc][j];
+            }
+            __syncthreads();
         }
     }
 }
@@ -212,16 +302,28 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
     const int p0 = binstart[b * nb], p1 = binstart[(b + 1) * nb];
     if (p0 == p1) return;
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
+    // every load of the work-group in flight together: twiddles, the two
+    // spectrum rows of this wave's channel, and the first samples' records
+    TwiddleRegs<T, M, 4 * kWave> twr;
+    twr.load(plan, p, tid);
+    PairRegs<T, M> pr;
+    if (wave < 3) {
+        const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(wave) * N * H;
+        pr.load(t2 + int64_t(b) * H, t2 + int64_t(b + 1) * H, true, lane);
+    }
+    const vec4<T>* samp = at<vec4<T>>(plan, p.o_samp);
+    const int2* sidx = at<int2>(plan, p.o_sidx);
+    const vec2<T>* ysort = at<vec2<T>>(work, p.w_ysort);
+    GatherRecs<T, 4> first;
+    gather_fetch<T, MODE, 4>(first, p0 + tid, p1, 4 * kWave, samp, sidx, ysort, in0);
+    twr.store(sm.tw, tid);
     __syncthreads();
     T* g0 = sm.g;            // row b:   [ch][N]
     T* g1 = sm.g + 3 * N;    // row b+1: [ch][N]
     if (wave < 3) {
-        const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(wave) * N * H;
-        const cx<T>* ra = t2 + int64_t(b) * H;
-        const cx<T>* rb = t2 + int64_t(b + 1) * H;
         cx<T>* line = sm.line[wave];
-        for (int kx = lane; kx < M; kx += kWave) line[kx] = pair_spectrum<T, M>(ra, rb, kx, true);
+#pragma unroll
+        for (int m = 0; m < M / kWave; ++m) line[lane + m * kWave] = pr.spectrum(m, lane);
         wave_sync();
         fft_wave<T, true, M>(line, sm.tw, lane);
         for (int i = lane; i < N; i += kWave) {
@@ -230,9 +332,8 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
         }
     }
     __syncthreads();
-    gather_band<T, MODE>(g0, g1, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
-                         at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res), out0, in0, out1, out2, f, p.t,
-                         tid, 4 * kWave);
+    gather_band<T, MODE, 4>(g0, g1, N, p0, p1, samp, sidx, ysort, at<vec2<T>>(work, p.w_res), out0, in0, out1, out2,
+                            f, p.t, tid, 4 * kWave, &first);
 }
 
 // ----------------------------------------------------------------- adjoint ---
@@ -251,12 +352,15 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
     char* shared_area = smem + sizeof(cx<T>) * M + lds_align(size_t(3) * N * sizeof(T));
     cx<T>* lines = reinterpret_cast<cx<T>*>(shared_area);
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    load_twiddles<T, M>(tw, plan, p, tid, 4 * kWave);
+    TwiddleRegs<T, M, 4 * kWave> twr;       // in flight during the transpose sampling
+    twr.load(plan, p, tid);
     // SORTED: the signal in cell order, from s when given, else the problem's residual in work
     const vec2<T>* ys = (SORTED && s) ? reinterpret_cast<const vec2<T>*>(s) : at<vec2<T>>(work, p.w_res);
     scatter_row<T, SORTED, 256>(g, scatter_lds<T>(shared_area, N, 256), N, j, at<int>(plan, p.o_binstart),
                                 at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), ys,
                                 s, tid);
+    twr.store(tw, tid);
+    __syncthreads();
     if (wave >= 2) return;
     cx<T>* line = lines + wave * M;
     const T* re = g + (wave == 0 ? 0 : 2 * N);
@@ -298,11 +402,21 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
     if (SPLIT) {                                    // one column, waves 0..2
         const int kx = xcd_unit(blockIdx.x, H);
         if (kx < 0) return;
-        load_twiddles<T, M>(sm.tw, plan, p, tid, 3 * kWave);
+        TwiddleRegs<T, M, 3 * kWave> twr;
+        twr.load(plan, p, tid);
+        constexpr int PL = M / kWave;
+        cx<T> x[PL];
+        const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + (int64_t(wave) * H + kx) * N;
+#pragma unroll
+        for (int m = 0; m < PL; ++m) {
+            const int i = lane + m * kWave;
+            x[m] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+        }
+        twr.store(sm.tw, tid);
         __syncthreads();
         cx<T>* line = sm.line[wave];
-        const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + (int64_t(wave) * H + kx) * N;
-        for (int i = lane; i < M; i += kWave) line[i] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+#pragma unroll
+        for (int m = 0; m < PL; ++m) line[lane + m * kWave] = x[m];
         wave_sync();
         fft_wave<T, false, M>(line, sm.tw, lane);
         for (int ky = lane; ky < M; ky += kWave) line[ky] = cscale(line[ky], spec_at<T, M>(spec, wave, kx, ky));
@@ -316,18 +430,34 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
     } else {                                        // four columns, one per wave
         const int unit = xcd_unit(blockIdx.x, (H + 3) / 4);
         if (unit < 0) return;
-        load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
-        __syncthreads();
-        const int kx = 4 * unit + wave;
-        if (kx >= H) return;
+        TwiddleRegs<T, M, 4 * kWave> twr;
+        twr.load(plan, p, tid);
+        const int kx0 = 4 * unit, kx = kx0 + wave;
+        const bool active = kx < H;     // inactive waves stay for the work-group barriers
         cx<T>* line = sm.line[wave];
         constexpr int PL = M / kWave;
         const T* spec_dh = DUAL ? at<T>(plan, p.o_spec_dh) : nullptr;
         cx<T> acc[PL];
         cx<T> acc2[DUAL ? PL : 1];
-        for (int ch = 0; ch < 3; ++ch) {
-            const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + (int64_t(ch) * H + kx) * N;
-            for (int i = lane; i < M; i += kWave) line[i] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+        cx<T> x[PL];                    // channel 0's column, loaded with the twiddles
+        if (active) {
+            const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(kx) * N;
+#pragma unroll
+            for (int m = 0; m < PL; ++m) {
+                const int i = lane + m * kWave;
+                x[m] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+            }
+        }
+        twr.store(sm.tw, tid);
+        __syncthreads();
+        for (int ch = 0; ch < 3 && active; ++ch) {
+            if (ch == 0) {
+#pragma unroll
+                for (int m = 0; m < PL; ++m) line[lane + m * kWave] = x[m];
+            } else {
+                const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + (int64_t(ch) * H + kx) * N;
+                for (int i = lane; i < M; i += kWave) line[i] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+            }
             wave_sync();
             fft_wave<T, false, M>(line, sm.tw, lane);
 #pragma unroll
@@ -343,20 +473,26 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
             }
             wave_sync();
         }
+        // one or two outputs; the four columns go out together (four
+        // consecutive threads write one contiguous 32-byte run of T2[slot][j])
+        auto emit = [&](const cx<T>* src, int slot) {
+            if (active) {
+                wave_sync();
 #pragma unroll
-        for (int i = 0; i < PL; ++i) line[lane + i * kWave] = acc[i];
-        wave_sync();
-        fft_wave<T, true, M>(line, sm.tw, lane);
-        for (int j = lane; j < N; j += kWave) t2[int64_t(j) * H + kx] = line[j];
-        if constexpr (DUAL) {
-            wave_sync();
-#pragma unroll
-            for (int i = 0; i < PL; ++i) line[lane + i * kWave] = acc2[i];
-            wave_sync();
-            fft_wave<T, true, M>(line, sm.tw, lane);
-            cx<T>* t2b = t2 + int64_t(N) * H;
-            for (int j = lane; j < N; j += kWave) t2b[int64_t(j) * H + kx] = line[j];
-        }
+                for (int i = 0; i < PL; ++i) line[lane + i * kWave] = src[i];
+                wave_sync();
+                fft_wave<T, true, M>(line, sm.tw, lane);
+            }
+            __syncthreads();
+            cx<T>* out = t2 + int64_t(slot) * N * H;
+            for (int i = tid; i < 4 * N; i += 4 * kWave) {
+                const int j = i >> 2, cc = i & 3;
+                if (kx0 + cc < H) out[int64_t(j) * H + kx0 + cc] = sm.line[cc][j];
+            }
+            __syncthreads();
+        };
+        emit(acc, 0);
+        if constexpr (DUAL) emit(acc2, 1);
     }
 }
 
@@ -369,17 +505,22 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int unit = xcd_unit(blockIdx.x, (N + 7) / 8);   // four row pairs per work-group
     if (unit < 0) return;
-    load_twiddles<T, M>(sm.tw, plan, p, tid, 4 * kWave);
-    __syncthreads();
+    TwiddleRegs<T, M, 4 * kWave> twr;
+    twr.load(plan, p, tid);
     const int q = 4 * unit + wave;
     const int r0 = 2 * q, r1 = 2 * q + 1;
-    if (r0 >= N) return;
-    const bool two = r1 < N;
-    const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(slot) * N * H;
-    const cx<T>* ra = t2 + int64_t(r0) * H;
-    const cx<T>* rb = t2 + int64_t(two ? r1 : r0) * H;
+    const bool active = r0 < N, two = r1 < N;
+    PairRegs<T, M> pr;
+    if (active) {
+        const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(slot) * N * H;
+        pr.load(t2 + int64_t(r0) * H, t2 + int64_t(two ? r1 : r0) * H, two, lane);
+    }
+    twr.store(sm.tw, tid);
+    __syncthreads();
+    if (!active) return;
     cx<T>* line = sm.line[wave];
-    for (int kx = lane; kx < M; kx += kWave) line[kx] = pair_spectrum<T, M>(ra, rb, kx, two);
+#pragma unroll
+    for (int m = 0; m < M / kWave; ++m) line[lane + m * kWave] = pr.spectrum(m, lane);
     wave_sync();
     fft_wave<T, true, M>(line, sm.tw, lane);
     for (int i = lane; i < N; i += kWave) {
@@ -396,85 +537,77 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
 }
 
 // ------------------------------------------------------------- launchers ---
-#define MPIK_DISPATCH_M(M_, BODY)                            \
-    switch (M_) {                                            \
-        case 64: { constexpr int MM = 64; BODY; } break;     \
-        case 128: { constexpr int MM = 128; BODY; } break;   \
-        case 256: { constexpr int MM = 256; BODY; } break;   \
-        case 512: { constexpr int MM = 512; BODY; } break;   \
-        case 1024: { constexpr int MM = 1024; BODY; } break; \
-        default: break;                                      \
-    }
+// One instance per FFT size M, so that registers are allocated for that size
+// alone; a launch covers every problem of the batch (grid.y) and problems of
+// another size, or on the direct path, leave at once.
 
 // grid.x: xcd_grid(ceil(row pairs / 4)), grid.y: problem; 256 threads
-template <typename T>
+template <typename T, int M>
 __global__ void __launch_bounds__(256) k_fwd_rows(const Prob* __restrict__ P, const T* __restrict__ c,
                                                   const char* __restrict__ plan, char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
-    if (p.mode != 1) return;
-    MPIK_DISPATCH_M(p.m, (fwd_rows_body<T, MM>(p, c + p.o_c, plan, work, smem)));
+    if (p.mode != 1 || p.m != M) return;
+    fwd_rows_body<T, M>(p, c + p.o_c, plan, work, smem);
 }
 
 // SPLIT: grid.x = xcd_grid(M/2 + 1), 192 threads; else xcd_grid(ceil((M/2 + 1)/4)), 256 threads
-template <typename T, bool SPLIT>
+template <typename T, int M, bool SPLIT>
 __global__ void __launch_bounds__(256) k_fwd_cols(const Prob* __restrict__ P, const char* __restrict__ plan,
                                                   char* __restrict__ work, int dh) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
-    if (p.mode != 1) return;
-    MPIK_DISPATCH_M(p.m, (fwd_cols_body<T, MM, SPLIT>(p, plan, work, smem, dh)));
+    if (p.mode != 1 || p.m != M) return;
+    fwd_cols_body<T, M, SPLIT>(p, plan, work, smem, dh);
 }
 
 // grid.x: xcd_grid(base-cell rows), 256 threads.  MODE as gather_band; the
 // caller buffers are offset to the problem here.
-template <typename T, int MODE>
+template <typename T, int M, int MODE>
 __global__ void __launch_bounds__(256) k_fwd_rows_gather(const Prob* __restrict__ P, GatherIO<T> io,
                                                          const char* __restrict__ plan, char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
-    if (p.mode != 1) return;
-    MPIK_DISPATCH_M(p.m, (fwd_rows_gather_body<T, MM, MODE>(
-                             p, io.out0 ? io.out0 + p.o_s : nullptr, io.in0 ? io.in0 + p.o_s : nullptr,
-                             io.out1 ? io.out1 + p.o_s : nullptr, io.out2 ? io.out2 + p.o_s : nullptr,
-                             io.f ? io.f + 9 * (p.o_s / 2) : nullptr, plan, work, smem)));
+    if (p.mode != 1 || p.m != M) return;
+    fwd_rows_gather_body<T, M, MODE>(p, io.out0 ? io.out0 + p.o_s : nullptr, io.in0 ? io.in0 + p.o_s : nullptr,
+                                     io.out1 ? io.out1 + p.o_s : nullptr, io.out2 ? io.out2 + p.o_s : nullptr,
+                                     io.f ? io.f + 9 * (p.o_s / 2) : nullptr, plan, work, smem);
 }
 
 // grid.x: xcd_grid(grid rows), 256 threads
-template <typename T, bool SORTED>
+template <typename T, int M, bool SORTED>
 __global__ void __launch_bounds__(256) k_adj_scatter_row(const Prob* __restrict__ P, const T* __restrict__ s,
                                                          const char* __restrict__ plan, char* __restrict__ work) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
-    if (p.mode != 1) return;
-    MPIK_DISPATCH_M(p.m, (adj_scatter_row_body<T, MM, SORTED>(p, s ? s + p.o_s : nullptr, plan, work, smem)));
+    if (p.mode != 1 || p.m != M) return;
+    adj_scatter_row_body<T, M, SORTED>(p, s ? s + p.o_s : nullptr, plan, work, smem);
 }
 
 // SPLIT: grid.x = xcd_grid(M/2 + 1), 192 threads; else xcd_grid(ceil((M/2 + 1)/4)), 256 threads.
 // DUAL needs the four-column shape.
-template <typename T, bool SPLIT, bool DUAL = false>
+template <typename T, int M, bool SPLIT, bool DUAL = false>
 __global__ void __launch_bounds__(256) k_adj_cols(const Prob* __restrict__ P, const char* __restrict__ plan,
                                                   char* __restrict__ work) {
     static_assert(!(SPLIT && DUAL), "the dual transpose runs in the four-column shape");
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
-    if (p.mode != 1) return;
-    MPIK_DISPATCH_M(p.m, (adj_cols_body<T, MM, SPLIT, DUAL>(p, plan, work, smem)));
+    if (p.mode != 1 || p.m != M) return;
+    adj_cols_body<T, M, SPLIT, DUAL>(p, plan, work, smem);
 }
 
 // grid.x: xcd_grid(ceil(row pairs / 4)), 256 threads; slot: which T2 field
-template <typename T, int EPI>
+template <typename T, int M, int EPI>
 __global__ void __launch_bounds__(256) k_adj_rows(const Prob* __restrict__ P, T* c_out, const T* c_in,
                                                   const double* __restrict__ taus, const char* __restrict__ plan,
                                                   char* __restrict__ work, int slot) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
-    if (p.mode != 1) return;
+    if (p.mode != 1 || p.m != M) return;
     const T tau = EPI ? T(taus[blockIdx.y]) : T(0);
     // EPI 2 writes the step into the problem's work buffer u (before the denoiser)
     T* out = EPI == 2 ? at<T>(work, p.w_u) : c_out + p.o_c;
-    MPIK_DISPATCH_M(p.m, (adj_rows_body<T, MM, EPI>(p, out, EPI ? c_in + p.o_c : nullptr, tau, slot, plan, work,
-                                                    smem)));
+    adj_rows_body<T, M, EPI>(p, out, EPI ? c_in + p.o_c : nullptr, tau, slot, plan, work, smem);
 }
 
 }  // namespace mpik

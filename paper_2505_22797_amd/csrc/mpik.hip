@@ -19,6 +19,7 @@
 #include <mutex>
 #include <new>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mpik.h"
@@ -275,6 +276,11 @@ struct mpi_plan {
     size_t smem_row = 0, smem_col = 0, smem_gather = 0, smem_scatter = 0, smem_dfwd = 0, smem_dadj = 0,
            smem_dgather = 0, smem_dscatter = 0;
     bool any_fft = false, any_direct = false;
+    // per FFT size M = 64 << li present in the batch: launch extents and LDS bytes
+    // (row, column, gather, scatter-row kernels)
+    int fft_m_mask = 0;
+    int m_rowpairs[5] = {0}, m_h[5] = {0}, m_nb[5] = {0}, m_n[5] = {0};
+    size_t m_smem[5][4] = {};
     bool col_split = true;   // column stages: three waves per column (few problems) or a wave per column
     int col_force = 0;       // 1: always split, 2: always a wave per column, 0: by batch size
     int slice_mask = 0;      // bit i: some direct problem uses kSliceChoices[i]
@@ -302,6 +308,11 @@ void finalize_extents(mpi_plan* pl) {
     pl->smem_dfwd = pl->smem_dadj = pl->smem_dgather = pl->smem_dscatter = 0;
     pl->any_fft = pl->any_direct = false;
     pl->slice_mask = 0;
+    pl->fft_m_mask = 0;
+    for (int li = 0; li < 5; ++li) {
+        pl->m_rowpairs[li] = pl->m_h[li] = pl->m_nb[li] = pl->m_n[li] = 0;
+        for (int k = 0; k < 4; ++k) pl->m_smem[li][k] = 0;
+    }
     pl->col_split = pl->col_force ? pl->col_force == 1 : pl->count <= 2;
     const int e = pl->L.elem;
     for (const Prob& p : pl->L.probs) {
@@ -312,6 +323,13 @@ void finalize_extents(mpi_plan* pl) {
         pl->max_dntiles = std::max(pl->max_dntiles, (p.n + kDnTile - 1) / kDnTile);
         if (p.mode == 1) {
             pl->any_fft = true;
+            const int li = __builtin_ctz(p.m) - 6;
+            pl->fft_m_mask |= 1 << li;
+            pl->m_rowpairs[li] = std::max(pl->m_rowpairs[li], (p.n + 1) / 2);
+            pl->m_h[li] = p.m / 2 + 1;
+            pl->m_nb[li] = std::max(pl->m_nb[li], p.nb);
+            pl->m_n[li] = std::max(pl->m_n[li], p.n);
+            for (int k = 0; k < 4; ++k) pl->m_smem[li][k] = std::max(pl->m_smem[li][k], smem_for_dt(e, p.m, p.n, k));
             pl->max_h = std::max(pl->max_h, p.m / 2 + 1);
             pl->smem_row = std::max(pl->smem_row, smem_for_dt(e, p.m, p.n, 0));
             pl->smem_col = std::max(pl->smem_col, smem_for_dt(e, p.m, p.n, 1));
@@ -330,30 +348,50 @@ void finalize_extents(mpi_plan* pl) {
     }
 }
 
+// Calls f(std::integral_constant<int, M>, li) for every FFT size M = 64 << li
+// that some problem of the plan uses (float64 plans stop at 512).
+template <typename T, typename F>
+void each_fft_size(const mpi_plan* pl, F&& f) {
+    auto one = [&](auto mc, int li) {
+        if (pl->fft_m_mask & (1 << li)) f(mc, li);
+    };
+    one(std::integral_constant<int, 64>{}, 0);
+    one(std::integral_constant<int, 128>{}, 1);
+    one(std::integral_constant<int, 256>{}, 2);
+    one(std::integral_constant<int, 512>{}, 3);
+    if constexpr (sizeof(T) == 4) one(std::integral_constant<int, 1024>{}, 4);
+}
+
 template <typename T>
 hipError_t set_smem_limits(const mpi_plan* pl) {
     hipError_t e = hipSuccess;
     auto chk = [&e](hipError_t x) { if (x != hipSuccess) e = x; };
-    chk(allow_smem(k_fwd_rows<T>, pl->smem_row));
-    chk(allow_smem(k_fwd_cols<T, true>, pl->smem_col));
-    chk(allow_smem(k_fwd_cols<T, false>, pl->smem_col));
-    chk(allow_smem(k_adj_cols<T, true>, pl->smem_col));
-    chk(allow_smem(k_adj_cols<T, false>, pl->smem_col));
-    chk(allow_smem(k_adj_cols<T, false, true>, pl->smem_col));
-    chk(allow_smem(k_fwd_rows_gather<T, 4>, pl->smem_gather));
-    chk(allow_smem(k_fwd_rows_gather<T, 5>, pl->smem_gather));
-    chk(allow_smem(k_fwd_rows_gather<T, 6>, pl->smem_gather));
+    each_fft_size<T>(pl, [&](auto mc, int li) {
+        constexpr int M = decltype(mc)::value;
+        const size_t row = pl->m_smem[li][0], col = pl->m_smem[li][1], gat = pl->m_smem[li][2],
+                     sca = pl->m_smem[li][3];
+        chk(allow_smem(k_fwd_rows<T, M>, row));
+        chk(allow_smem(k_fwd_cols<T, M, true>, col));
+        chk(allow_smem(k_fwd_cols<T, M, false>, col));
+        chk(allow_smem(k_adj_cols<T, M, true>, col));
+        chk(allow_smem(k_adj_cols<T, M, false>, col));
+        chk(allow_smem(k_adj_cols<T, M, false, true>, col));
+        chk(allow_smem(k_fwd_rows_gather<T, M, 0>, gat));
+        chk(allow_smem(k_fwd_rows_gather<T, M, 1>, gat));
+        chk(allow_smem(k_fwd_rows_gather<T, M, 2>, gat));
+        chk(allow_smem(k_fwd_rows_gather<T, M, 3>, gat));
+        chk(allow_smem(k_fwd_rows_gather<T, M, 4>, gat));
+        chk(allow_smem(k_fwd_rows_gather<T, M, 5>, gat));
+        chk(allow_smem(k_fwd_rows_gather<T, M, 6>, gat));
+        chk(allow_smem(k_adj_scatter_row<T, M, false>, sca));
+        chk(allow_smem(k_adj_scatter_row<T, M, true>, sca));
+        chk(allow_smem(k_adj_rows<T, M, 0>, row));
+        chk(allow_smem(k_adj_rows<T, M, 1>, row));
+        chk(allow_smem(k_adj_rows<T, M, 2>, row));
+    });
     chk(allow_smem(k_gather_rows<T, 4>, pl->smem_dgather));
     chk(allow_smem(k_gather_rows<T, 5>, pl->smem_dgather));
     chk(allow_smem(k_gather_rows<T, 6>, pl->smem_dgather));
-    chk(allow_smem(k_fwd_rows_gather<T, 0>, pl->smem_gather));
-    chk(allow_smem(k_fwd_rows_gather<T, 1>, pl->smem_gather));
-    chk(allow_smem(k_fwd_rows_gather<T, 2>, pl->smem_gather));
-    chk(allow_smem(k_fwd_rows_gather<T, 3>, pl->smem_gather));
-    chk(allow_smem(k_adj_scatter_row<T, false>, pl->smem_scatter));
-    chk(allow_smem(k_adj_scatter_row<T, true>, pl->smem_scatter));
-    chk(allow_smem(k_adj_rows<T, 0>, pl->smem_row));
-    chk(allow_smem(k_adj_rows<T, 1>, pl->smem_row));
     chk(allow_smem(k_conv_direct<T, 1, 3, 4, 0>, pl->smem_dfwd));
     chk(allow_smem(k_conv_direct<T, 1, 3, 8, 0>, pl->smem_dfwd));
     chk(allow_smem(k_conv_direct<T, 1, 3, 16, 0>, pl->smem_dfwd));
@@ -366,7 +404,6 @@ hipError_t set_smem_limits(const mpi_plan* pl) {
     chk(allow_smem(k_conv_direct<T, 3, 1, 4, 2>, pl->smem_dadj));
     chk(allow_smem(k_conv_direct<T, 3, 1, 8, 2>, pl->smem_dadj));
     chk(allow_smem(k_conv_direct<T, 3, 1, 16, 2>, pl->smem_dadj));
-    chk(allow_smem(k_adj_rows<T, 2>, pl->smem_row));
     chk(allow_smem(k_gather_rows<T, 0>, pl->smem_dgather));
     chk(allow_smem(k_gather_rows<T, 1>, pl->smem_dgather));
     chk(allow_smem(k_gather_rows<T, 2>, pl->smem_dgather));
@@ -478,19 +515,29 @@ void fwd_stage(const mpi_plan* pl, int k, const T* c, GatherIO<T> io, char* work
     if (k >= 3 && !pl->any_direct) return;
     switch (k) {
         case 0:
-            k_fwd_rows<T><<<dim3(xcd_grid((pl->max_rowpairs + 3) / 4), B), 256, pl->smem_row, st>>>(P, c, plan,
-                                                                                                work);
+            each_fft_size<T>(pl, [&](auto mc, int li) {
+                constexpr int M = decltype(mc)::value;
+                k_fwd_rows<T, M><<<dim3(xcd_grid((pl->m_rowpairs[li] + 3) / 4), B), 256, pl->m_smem[li][0], st>>>(
+                    P, c, plan, work);
+            });
             break;
         case 1:
-            if (pl->col_split)
-                k_fwd_cols<T, true><<<dim3(xcd_grid(pl->max_h), B), 192, pl->smem_col, st>>>(P, plan, work, dh);
-            else
-                k_fwd_cols<T, false><<<dim3(xcd_grid((pl->max_h + 3) / 4), B), 256, pl->smem_col, st>>>(P, plan,
-                                                                                                     work, dh);
+            each_fft_size<T>(pl, [&](auto mc, int li) {
+                constexpr int M = decltype(mc)::value;
+                if (pl->col_split)
+                    k_fwd_cols<T, M, true><<<dim3(xcd_grid(pl->m_h[li]), B), 192, pl->m_smem[li][1], st>>>(P, plan,
+                                                                                                          work, dh);
+                else
+                    k_fwd_cols<T, M, false><<<dim3(xcd_grid((pl->m_h[li] + 3) / 4), B), 256, pl->m_smem[li][1], st>>>(
+                        P, plan, work, dh);
+            });
             break;
         case 2:
-            k_fwd_rows_gather<T, MODE><<<dim3(xcd_grid(pl->max_nb), B), 256, pl->smem_gather, st>>>(P, io, plan,
-                                                                                                     work);
+            each_fft_size<T>(pl, [&](auto mc, int li) {
+                constexpr int M = decltype(mc)::value;
+                k_fwd_rows_gather<T, M, MODE><<<dim3(xcd_grid(pl->m_nb[li]), B), 256, pl->m_smem[li][2], st>>>(
+                    P, io, plan, work);
+            });
             break;
         case 3:
             launch_direct_conv<T, 4, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st, dh);
@@ -519,24 +566,34 @@ void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, c
     if (k >= 3 && !pl->any_direct) return;
     switch (k) {
         case 0:
-            k_adj_scatter_row<T, SORTED><<<dim3(xcd_grid(pl->max_n), B), 256, pl->smem_scatter, st>>>(P, s, plan,
-                                                                                                    work);
+            each_fft_size<T>(pl, [&](auto mc, int li) {
+                constexpr int M = decltype(mc)::value;
+                k_adj_scatter_row<T, M, SORTED><<<dim3(xcd_grid(pl->m_n[li]), B), 256, pl->m_smem[li][3], st>>>(
+                    P, s, plan, work);
+            });
             break;
         case 1:
-            if (z_out)
-                k_adj_cols<T, false, true><<<dim3(xcd_grid((pl->max_h + 3) / 4), B), 256, pl->smem_col, st>>>(
-                    P, plan, work);
-            else if (pl->col_split)
-                k_adj_cols<T, true><<<dim3(xcd_grid(pl->max_h), B), 192, pl->smem_col, st>>>(P, plan, work);
-            else
-                k_adj_cols<T, false><<<dim3(xcd_grid((pl->max_h + 3) / 4), B), 256, pl->smem_col, st>>>(P, plan, work);
+            each_fft_size<T>(pl, [&](auto mc, int li) {
+                constexpr int M = decltype(mc)::value;
+                const size_t sm = pl->m_smem[li][1];
+                if (z_out)
+                    k_adj_cols<T, M, false, true><<<dim3(xcd_grid((pl->m_h[li] + 3) / 4), B), 256, sm, st>>>(
+                        P, plan, work);
+                else if (pl->col_split)
+                    k_adj_cols<T, M, true><<<dim3(xcd_grid(pl->m_h[li]), B), 192, sm, st>>>(P, plan, work);
+                else
+                    k_adj_cols<T, M, false><<<dim3(xcd_grid((pl->m_h[li] + 3) / 4), B), 256, sm, st>>>(P, plan,
+                                                                                                      work);
+            });
             break;
         case 2:
-            k_adj_rows<T, EPI><<<dim3(xcd_grid((pl->max_rowpairs + 3) / 4), B), 256, pl->smem_row, st>>>(
-                P, c_out, c_in, taus, plan, work, 0);
-            if (z_out)
-                k_adj_rows<T, 0><<<dim3(xcd_grid((pl->max_rowpairs + 3) / 4), B), 256, pl->smem_row, st>>>(
-                    P, z_out, nullptr, taus, plan, work, 1);
+            each_fft_size<T>(pl, [&](auto mc, int li) {
+                constexpr int M = decltype(mc)::value;
+                const dim3 grid(xcd_grid((pl->m_rowpairs[li] + 3) / 4), B);
+                k_adj_rows<T, M, EPI><<<grid, 256, pl->m_smem[li][0], st>>>(P, c_out, c_in, taus, plan, work, 0);
+                if (z_out)
+                    k_adj_rows<T, M, 0><<<grid, 256, pl->m_smem[li][0], st>>>(P, z_out, nullptr, taus, plan, work, 1);
+            });
             break;
         case 3:
             k_scatter_rows<T, SORTED><<<dim3(pl->max_n, B), 256, pl->smem_dscatter, st>>>(P, s, plan, work);
@@ -1080,6 +1137,7 @@ int mpi_batch_forward(const mpi_plan* plan, const void* c, void* s, void* work, 
                       hipStream_t stream) {
     int rc = check_call(plan, c, s, work, work_bytes);
     if (rc != MPI_OK) return rc;
+    if (misaligned(s, 2 * plan->L.elem)) return MPI_ERR_ARG;   // written as (x, y) pairs
     if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
     char* w = static_cast<char*>(work);
     return plan->dtype == MPI_F64
@@ -1141,6 +1199,7 @@ int mpi_batch_forward_dh(const mpi_plan* plan, const void* x, void* s, void* wor
                          hipStream_t stream) {
     int rc = check_call(plan, x, s, work, work_bytes);
     if (rc != MPI_OK) return rc;
+    if (misaligned(s, 2 * plan->L.elem)) return MPI_ERR_ARG;   // written as (x, y) pairs
     if (!plan->L.deriv) return MPI_ERR_UNSUPPORTED;
     if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
     char* w = static_cast<char*>(work);
@@ -1153,7 +1212,7 @@ int mpi_batch_residual(const mpi_plan* plan, const void* c, const void* y, void*
                        size_t work_bytes, hipStream_t stream) {
     int rc = check_call(plan, c, y, work, work_bytes);
     if (rc != MPI_OK) return rc;
-    if (!out || misaligned(out, plan->L.elem)) return MPI_ERR_ARG;
+    if (!out || misaligned(out, 2 * plan->L.elem)) return MPI_ERR_ARG;   // written as (x, y) pairs
     if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
     char* w = static_cast<char*>(work);
     return plan->dtype == MPI_F64

@@ -32,117 +32,151 @@ namespace mpik {
 //         q = G v to out0[p]; out1[p] += (y^T M(dG/dx) v + q^T M(dF'/dx) v,
 //         y^T M(dG/dy) v + q^T M(dF'/dy) v); out2[p] += M(G) y + M(F') q;
 //         all in cell order.
+// The sample records of one pass of gather_band: thread tid handles cell-order
+// positions base + u * nthreads, u < U.
+template <typename T, int U> struct GatherRecs {
+    vec4<T> e[U];
+    int2 id[U];
+    vec2<T> y[U];
+};
+
+template <typename T, int MODE, int U>
+__device__ __forceinline__ void gather_fetch(GatherRecs<T, U>& r, int base, int p1, int nthreads,
+                                             const vec4<T>* __restrict__ samp, const int2* __restrict__ sidx,
+                                             const vec2<T>* __restrict__ ysort, const T* __restrict__ in0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int p = base + u * nthreads;
+        if (p < p1) {
+            r.e[u] = samp[p];
+            r.id[u] = sidx[p];
+            if (MODE == 1 || MODE == 5) r.y[u] = ysort[p];
+            if (MODE == 6) {
+                r.y[u].x = in0[2 * p];
+                r.y[u].y = in0[2 * p + 1];
+            }
+        }
+    }
+    if (MODE == 2 || MODE == 3) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = base + u * nthreads;
+            if (p < p1) {
+                r.y[u].x = in0[2 * r.id[u].y];
+                r.y[u].y = in0[2 * r.id[u].y + 1];
+            }
+        }
+    }
+}
+
+template <typename T, int MODE, int U>
+__device__ __forceinline__ void gather_apply(const GatherRecs<T, U>& r, int base, int p1, int nthreads,
+                                             const T* g0, const T* g1, int N, vec2<T>* __restrict__ out_sorted,
+                                             T* __restrict__ out0, T* __restrict__ out1, T* __restrict__ out2,
+                                             T* __restrict__ f, int64_t fstride) {
+    constexpr bool GRAD = MODE == 2 || MODE == 5 || MODE == 6;
+    const T inv_d = T(0.5) * T(N);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int p = base + u * nthreads;
+        if (p >= p1) break;
+        const int i0 = r.id[u].x & 0xffff;
+        const T fx = r.e[u].x, fy = r.e[u].y, gx = T(1) - fx, gy = T(1) - fy;
+        T g[3], dx[3], dy[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const T a00 = g0[ch * N + i0], a10 = g0[ch * N + i0 + 1];
+            const T a01 = g1[ch * N + i0], a11 = g1[ch * N + i0 + 1];
+            const T lo = gx * a00 + fx * a10;
+            const T hi = gx * a01 + fx * a11;
+            g[ch] = gy * lo + fy * hi;
+            if (GRAD) {
+                dx[ch] = inv_d * (gy * (a10 - a00) + fy * (a11 - a01));
+                dy[ch] = inv_d * (gx * (a01 - a00) + fx * (a11 - a10));
+            }
+        }
+        const T vx = r.e[u].z, vy = r.e[u].w;
+        const int k = r.id[u].y;
+        const vec2<T> y = r.y[u];
+        if (MODE == 2) {
+            const T yx = y.x, yy = y.y;
+            out0[2 * k] = yx * (dx[0] * vx + dx[1] * vy) + yy * (dx[1] * vx + dx[2] * vy);
+            out0[2 * k + 1] = yx * (dy[0] * vx + dy[1] * vy) + yy * (dy[1] * vx + dy[2] * vy);
+            out1[2 * k] = g[0] * yx + g[1] * yy;
+            out1[2 * k + 1] = g[1] * yx + g[2] * yy;
+        } else if (MODE == 6) {
+            const T yx = y.x, yy = y.y;
+            const T qx = g[0] * vx + g[1] * vy;
+            const T qy = g[1] * vx + g[2] * vy;
+            T h[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) h[q] = f[q * fstride + p];
+            const T gr_x = (yx * (dx[0] * vx + dx[1] * vy) + yy * (dx[1] * vx + dx[2] * vy)) +
+                           (qx * (h[3] * vx + h[4] * vy) + qy * (h[4] * vx + h[5] * vy));
+            const T gr_y = (yx * (dy[0] * vx + dy[1] * vy) + yy * (dy[1] * vx + dy[2] * vy)) +
+                           (qx * (h[6] * vx + h[7] * vy) + qy * (h[7] * vx + h[8] * vy));
+            const T gv_x = (g[0] * yx + g[1] * yy) + (h[0] * qx + h[1] * qy);
+            const T gv_y = (g[1] * yx + g[2] * yy) + (h[1] * qx + h[2] * qy);
+            out0[2 * p] = qx;
+            out0[2 * p + 1] = qy;
+            out1[2 * p] += gr_x;
+            out1[2 * p + 1] += gr_y;
+            out2[2 * p] += gv_x;
+            out2[2 * p + 1] += gv_y;
+        } else {
+            const T sx = g[0] * vx + g[1] * vy;
+            const T sy = g[1] * vx + g[2] * vy;
+            if (MODE == 1) {
+                vec2<T> o;
+                o.x = sx - y.x;
+                o.y = sy - y.y;
+                out_sorted[p] = o;
+            } else if (MODE == 5) {
+                out0[2 * p] = sx - y.x;
+                out0[2 * p + 1] = sy - y.y;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    f[ch * fstride + p] = g[ch];
+                    f[(3 + ch) * fstride + p] = dx[ch];
+                    f[(6 + ch) * fstride + p] = dy[ch];
+                }
+            } else if (MODE == 4) {
+                out0[2 * p] = sx;
+                out0[2 * p + 1] = sy;
+            } else if (MODE == 3) {
+                vec2<T> o;
+                o.x = sx - y.x;
+                o.y = sy - y.y;
+                reinterpret_cast<vec2<T>*>(out0)[k] = o;
+            } else {
+                vec2<T> o;
+                o.x = sx;
+                o.y = sy;
+                reinterpret_cast<vec2<T>*>(out0)[k] = o;
+            }
+        }
+    }
+}
+
+// `first`, when given, holds the records of the first pass (fetched by the
+// caller ahead of time so that their loads overlap its other work).
 template <typename T, int MODE, int U = 4>
 __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int p0, int p1,
                                             const vec4<T>* __restrict__ samp, const int2* __restrict__ sidx,
                                             const vec2<T>* __restrict__ ysort, vec2<T>* __restrict__ out_sorted,
                                             T* __restrict__ out0, const T* __restrict__ in0, T* __restrict__ out1,
                                             T* __restrict__ out2, T* __restrict__ f, int64_t fstride,
-                                            int tid, int nthreads) {
-    constexpr bool GRAD = MODE == 2 || MODE == 5 || MODE == 6;
-    const T inv_d = T(0.5) * T(N);
-    for (int base = p0 + tid; base < p1; base += U * nthreads) {
-        vec4<T> e[U];
-        int2 id[U];
-        vec2<T> y[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int p = base + u * nthreads;
-            if (p < p1) {
-                e[u] = samp[p];
-                id[u] = sidx[p];
-                if (MODE == 1 || MODE == 5) y[u] = ysort[p];
-                if (MODE == 6) {
-                    y[u].x = in0[2 * p];
-                    y[u].y = in0[2 * p + 1];
-                }
-            }
-        }
-        if (MODE == 2 || MODE == 3) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int p = base + u * nthreads;
-                if (p < p1) {
-                    y[u].x = in0[2 * id[u].y];
-                    y[u].y = in0[2 * id[u].y + 1];
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int p = base + u * nthreads;
-            if (p >= p1) break;
-            const int i0 = id[u].x & 0xffff;
-            const T fx = e[u].x, fy = e[u].y, gx = T(1) - fx, gy = T(1) - fy;
-            T g[3], dx[3], dy[3];
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const T a00 = g0[ch * N + i0], a10 = g0[ch * N + i0 + 1];
-                const T a01 = g1[ch * N + i0], a11 = g1[ch * N + i0 + 1];
-                const T lo = gx * a00 + fx * a10;
-                const T hi = gx * a01 + fx * a11;
-                g[ch] = gy * lo + fy * hi;
-                if (GRAD) {
-                    dx[ch] = inv_d * (gy * (a10 - a00) + fy * (a11 - a01));
-                    dy[ch] = inv_d * (gx * (a01 - a00) + fx * (a11 - a10));
-                }
-            }
-            const T vx = e[u].z, vy = e[u].w;
-            const int k = id[u].y;
-            if (MODE == 2) {
-                const T yx = y[u].x, yy = y[u].y;
-                out0[2 * k] = yx * (dx[0] * vx + dx[1] * vy) + yy * (dx[1] * vx + dx[2] * vy);
-                out0[2 * k + 1] = yx * (dy[0] * vx + dy[1] * vy) + yy * (dy[1] * vx + dy[2] * vy);
-                out1[2 * k] = g[0] * yx + g[1] * yy;
-                out1[2 * k + 1] = g[1] * yx + g[2] * yy;
-            } else if (MODE == 6) {
-                const T yx = y[u].x, yy = y[u].y;
-                const T qx = g[0] * vx + g[1] * vy;
-                const T qy = g[1] * vx + g[2] * vy;
-                T h[9];
-#pragma unroll
-                for (int q = 0; q < 9; ++q) h[q] = f[q * fstride + p];
-                const T gr_x = (yx * (dx[0] * vx + dx[1] * vy) + yy * (dx[1] * vx + dx[2] * vy)) +
-                               (qx * (h[3] * vx + h[4] * vy) + qy * (h[4] * vx + h[5] * vy));
-                const T gr_y = (yx * (dy[0] * vx + dy[1] * vy) + yy * (dy[1] * vx + dy[2] * vy)) +
-                               (qx * (h[6] * vx + h[7] * vy) + qy * (h[7] * vx + h[8] * vy));
-                const T gv_x = (g[0] * yx + g[1] * yy) + (h[0] * qx + h[1] * qy);
-                const T gv_y = (g[1] * yx + g[2] * yy) + (h[1] * qx + h[2] * qy);
-                out0[2 * p] = qx;
-                out0[2 * p + 1] = qy;
-                out1[2 * p] += gr_x;
-                out1[2 * p + 1] += gr_y;
-                out2[2 * p] += gv_x;
-                out2[2 * p + 1] += gv_y;
-            } else {
-                const T sx = g[0] * vx + g[1] * vy;
-                const T sy = g[1] * vx + g[2] * vy;
-                if (MODE == 1) {
-                    vec2<T> o;
-                    o.x = sx - y[u].x;
-                    o.y = sy - y[u].y;
-                    out_sorted[p] = o;
-                } else if (MODE == 5) {
-                    out0[2 * p] = sx - y[u].x;
-                    out0[2 * p + 1] = sy - y[u].y;
-#pragma unroll
-                    for (int ch = 0; ch < 3; ++ch) {
-                        f[ch * fstride + p] = g[ch];
-                        f[(3 + ch) * fstride + p] = dx[ch];
-                        f[(6 + ch) * fstride + p] = dy[ch];
-                    }
-                } else if (MODE == 4) {
-                    out0[2 * p] = sx;
-                    out0[2 * p + 1] = sy;
-                } else if (MODE == 3) {
-                    out0[2 * k] = sx - y[u].x;
-                    out0[2 * k + 1] = sy - y[u].y;
-                } else {
-                    out0[2 * k] = sx;
-                    out0[2 * k + 1] = sy;
-                }
-            }
-        }
+                                            int tid, int nthreads, const GatherRecs<T, U>* first = nullptr) {
+    int base = p0 + tid;
+    if (first) {
+        if (base < p1) gather_apply<T, MODE, U>(*first, base, p1, nthreads, g0, g1, N, out_sorted, out0, out1, out2, f,
+                                                fstride);
+        base += U * nthreads;
+    }
+    for (; base < p1; base += U * nthreads) {
+        GatherRecs<T, U> r;
+        gather_fetch<T, MODE, U>(r, base, p1, nthreads, samp, sidx, ysort, in0);
+        gather_apply<T, MODE, U>(r, base, p1, nthreads, g0, g1, N, out_sorted, out0, out1, out2, f, fstride);
     }
 }
 
