@@ -211,4 +211,70 @@ __device__ __forceinline__ void fft_wave(cx<T>* line, const cx<T>* __restrict__ 
     }
 }
 
+// 512-point FFT of one wave with the data in registers: lane l holds x[l + 64 m]
+// in v[m] on entry and X[l + 64 m] on exit (natural order both ways;
+// unnormalised, conjugate twiddles when INV).  With n = n2 + 64 n1 and
+// k = k1 + 8 k2:  X = sum_n2 W64^(n2 k2) W512^(n2 k1) sum_n1 x W8^(n1 k1), so each
+// lane first takes an 8-point DFT over its registers and applies W512^(l k1);
+// the 64-point DFT over the lanes n2 = a + 8b, k2 = c + 8d is then
+// sum_a W8^(a d) W64^(a c) sum_b W8^(b c), two 8-point DFTs with an exchange
+// through LDS before each.  The exchange buffer xb (the wave's own, 576
+// slots) is padded by one slot in nine so that both exchanges are free of
+// bank conflicts.  Each exchange is one write-then-read round trip; a
+// 512-point transform makes two, against four for the in-LDS passes.
+// Per-lane twiddles of fft512_regs, read once per kernel from the plan's table
+// (tw[j] = W512^j) and kept in registers: w1[k] = W512^(lane k) and
+// w2[k] = W64^((lane >> 3) k), k = 1..7.
+template <typename T> struct Fft512Tw {
+    cx<T> w1[7];
+    cx<T> w2[7];
+    __device__ __forceinline__ void load(const cx<T>* __restrict__ tw, int lane) {
+#pragma unroll
+        for (int k = 1; k < 8; ++k) {
+            w1[k - 1] = tw[(lane * k) & 511];
+            w2[k - 1] = tw[(8 * (lane >> 3) * k) & 511];
+        }
+    }
+};
+
+__device__ __forceinline__ constexpr int xpad(int i) { return i + (i >> 3); }
+constexpr int kXbSlots = 576;
+
+template <typename T, bool INV>
+__device__ __forceinline__ void fft512_regs(cx<T> (&v)[8], cx<T>* xb, const Fft512Tw<T>& tw, int lane) {
+    dft8<T, INV>(v);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+        cx<T> w = tw.w1[k - 1];
+        if (INV) w.y = -w.y;
+        v[k] = cmul(v[k], w);
+    }
+    // exchange 1: lane a + 8b holds index k1 in register k1; lane k1 + 8a gathers b = 0..7
+    {
+        const int a = lane & 7, b = lane >> 3;
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) xb[xpad(k1 * 64 + a * 8 + b)] = v[k1];
+    }
+    wave_sync();
+    const int lo = lane & 7, hi = lane >> 3;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) v[b] = xb[xpad(lo * 64 + hi * 8 + b)];
+    wave_sync();
+    dft8<T, INV>(v);                          // over b: index c
+#pragma unroll
+    for (int c = 1; c < 8; ++c) {
+        cx<T> w = tw.w2[c - 1];
+        if (INV) w.y = -w.y;
+        v[c] = cmul(v[c], w);
+    }
+    // exchange 2: lane k1 + 8a holds c in register c; lane k1 + 8c gathers a = 0..7
+#pragma unroll
+    for (int c = 0; c < 8; ++c) xb[xpad(lo * 64 + c * 8 + hi)] = v[c];
+    wave_sync();
+#pragma unroll
+    for (int a = 0; a < 8; ++a) v[a] = xb[xpad(lo * 64 + hi * 8 + a)];
+    wave_sync();
+    dft8<T, INV>(v);                          // over a: index d, X[lane + 64 d]
+}
+
 }  // namespace mpik

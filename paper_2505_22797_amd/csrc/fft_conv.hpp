@@ -427,6 +427,55 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         if (wave != 0) return;
         fft_wave<T, true, M>(sm.c, sm.tw, lane);
         for (int j = lane; j < N; j += kWave) t2[int64_t(j) * H + kx] = sm.c[j];
+    } else if constexpr (M == 512) {                // four columns, register-resident transforms
+        const int unit = xcd_unit(blockIdx.x, (H + 3) / 4);
+        if (unit < 0) return;
+        const int kx0 = 4 * unit, kx = kx0 + wave;
+        const bool active = kx < H;     // inactive waves stay for the work-group barriers
+        // each wave's exchange buffer, also the staging of its rows for the stores
+        cx<T>(*xb)[kXbSlots] = reinterpret_cast<cx<T>(*)[kXbSlots]>(smem);
+        Fft512Tw<T> tw;
+        tw.load(at<cx<T>>(plan, p.o_tw), lane);
+        const T* spec_dh = DUAL ? at<T>(plan, p.o_spec_dh) : nullptr;
+        cx<T> acc[8], acc2[DUAL ? 8 : 1], v[8];
+        if (active) {
+            for (int ch = 0; ch < 3; ++ch) {
+                const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + (int64_t(ch) * H + kx) * N;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int i = lane + m * kWave;
+                    v[m] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+                }
+                fft512_regs<T, false>(v, xb[wave], tw, lane);
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int ky = lane + m * kWave;
+                    const cx<T> z = cscale(v[m], spec_at<T, M>(spec, ch, kx, ky));
+                    acc[m] = ch == 0 ? z : cadd(acc[m], z);
+                    if constexpr (DUAL) {
+                        const cx<T> w = cscale(v[m], spec_at<T, M>(spec_dh, ch, kx, ky));
+                        acc2[m] = ch == 0 ? w : cadd(acc2[m], w);
+                    }
+                }
+            }
+        }
+        auto emit = [&](cx<T> (&src)[8], int slot) {
+            if (active) {
+                fft512_regs<T, true>(src, xb[wave], tw, lane);
+#pragma unroll
+                for (int m = 0; m < 8; ++m)
+                    if (lane + m * kWave < N) xb[wave][lane + m * kWave] = src[m];
+            }
+            __syncthreads();
+            cx<T>* out = t2 + int64_t(slot) * N * H;
+            for (int i = tid; i < 4 * N; i += 4 * kWave) {
+                const int j = i >> 2, cc = i & 3;
+                if (kx0 + cc < H) out[int64_t(j) * H + kx0 + cc] = xb[cc][j];
+            }
+            __syncthreads();
+        };
+        emit(acc, 0);
+        if constexpr (DUAL) emit(acc2, 1);
     } else {                                        // four columns, one per wave
         const int unit = xcd_unit(blockIdx.x, (H + 3) / 4);
         if (unit < 0) return;
