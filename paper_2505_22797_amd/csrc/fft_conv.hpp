@@ -554,26 +554,10 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int unit = xcd_unit(blockIdx.x, (N + 7) / 8);   // four row pairs per work-group
     if (unit < 0) return;
-    TwiddleRegs<T, M, 4 * kWave> twr;
-    twr.load(plan, p, tid);
     const int q = 4 * unit + wave;
     const int r0 = 2 * q, r1 = 2 * q + 1;
     const bool active = r0 < N, two = r1 < N;
-    PairRegs<T, M> pr;
-    if (active) {
-        const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(slot) * N * H;
-        pr.load(t2 + int64_t(r0) * H, t2 + int64_t(two ? r1 : r0) * H, two, lane);
-    }
-    twr.store(sm.tw, tid);
-    __syncthreads();
-    if (!active) return;
-    cx<T>* line = sm.line[wave];
-#pragma unroll
-    for (int m = 0; m < M / kWave; ++m) line[lane + m * kWave] = pr.spectrum(m, lane);
-    wave_sync();
-    fft_wave<T, true, M>(line, sm.tw, lane);
-    for (int i = lane; i < N; i += kWave) {
-        const T v0 = line[i].x, v1 = line[i].y;
+    auto put = [&](int i, T v0, T v1) {
         const int64_t o0 = int64_t(r0) * N + i, o1 = int64_t(r1) * N + i;
         if (EPI == 0) {
             c_out[o0] = v0;
@@ -582,6 +566,39 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
             c_out[o0] = c_in[o0] - tau * v0;
             if (two) c_out[o1] = c_in[o1] - tau * v1;
         }
+    };
+    if constexpr (M == 512) {                       // register-resident transform, no barrier
+        if (!active) return;
+        Fft512Tw<T> tw;
+        tw.load(at<cx<T>>(plan, p.o_tw), lane);
+        PairRegs<T, M> pr;
+        const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(slot) * N * H;
+        pr.load(t2 + int64_t(r0) * H, t2 + int64_t(two ? r1 : r0) * H, two, lane);
+        cx<T> x[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) x[m] = pr.spectrum(m, lane);
+        cx<T>(*xb)[kXbSlots] = reinterpret_cast<cx<T>(*)[kXbSlots]>(smem);
+        fft512_regs<T, true>(x, xb[wave], tw, lane);
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            if (lane + m * kWave < N) put(lane + m * kWave, x[m].x, x[m].y);
+    } else {
+        TwiddleRegs<T, M, 4 * kWave> twr;
+        twr.load(plan, p, tid);
+        PairRegs<T, M> pr;
+        if (active) {
+            const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(slot) * N * H;
+            pr.load(t2 + int64_t(r0) * H, t2 + int64_t(two ? r1 : r0) * H, two, lane);
+        }
+        twr.store(sm.tw, tid);
+        __syncthreads();
+        if (!active) return;
+        cx<T>* line = sm.line[wave];
+#pragma unroll
+        for (int m = 0; m < M / kWave; ++m) line[lane + m * kWave] = pr.spectrum(m, lane);
+        wave_sync();
+        fft_wave<T, true, M>(line, sm.tw, lane);
+        for (int i = lane; i < N; i += kWave) put(i, line[i].x, line[i].y);
     }
 }
 
