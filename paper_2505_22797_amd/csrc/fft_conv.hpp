@@ -14,7 +14,7 @@
 //              bilinear gather and velocity contraction of the row's samples.
 // Transpose (s -> c), three launches:
 //   adj_scatter_row : per grid row: deterministic transpose sampling into LDS,
-//              then the row FFTs of the three channels -> T1[ch][kx][row]
+//              then the row FFTs of the three channels -> T1[ch][row][kx]
 //   adj_cols : per column: three forward column FFTs, multiply-accumulate the
 //              channel spectra, one inverse column FFT cropped to N rows
 //   adj_rows : per pair of rows: inverse row FFT -> c, with an optional fused
@@ -380,10 +380,10 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
         if (wave == 0) {
             cx<T> A, B;
             split_pair<T, M>(line, k, A, B);
-            t1[int64_t(k) * N + j] = A;
-            t1[(int64_t(H) + k) * N + j] = B;
+            t1[int64_t(j) * H + k] = A;
+            t1[(int64_t(N) + j) * H + k] = B;
         } else {
-            t1[(int64_t(2) * H + k) * N + j] = line[k];
+            t1[(int64_t(2) * N + j) * H + k] = line[k];
         }
     }
 }
@@ -406,11 +406,11 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         twr.load(plan, p, tid);
         constexpr int PL = M / kWave;
         cx<T> x[PL];
-        const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + (int64_t(wave) * H + kx) * N;
+        const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(wave) * N * H + kx;    // column kx of T1[ch]
 #pragma unroll
         for (int m = 0; m < PL; ++m) {
             const int i = lane + m * kWave;
-            x[m] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+            x[m] = (i < N) ? t1[int64_t(i) * H] : cx<T>{T(0), T(0)};
         }
         twr.store(sm.tw, tid);
         __syncthreads();
@@ -440,11 +440,11 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         cx<T> acc[8], acc2[DUAL ? 8 : 1], v[8];
         if (active) {
             for (int ch = 0; ch < 3; ++ch) {
-                const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + (int64_t(ch) * H + kx) * N;
+                const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(ch) * N * H + kx;   // column kx of T1[ch]
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
                     const int i = lane + m * kWave;
-                    v[m] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+                    v[m] = (i < N) ? t1[int64_t(i) * H] : cx<T>{T(0), T(0)};
                 }
                 fft512_regs<T, false>(v, xb[wave], tw, lane);
 #pragma unroll
@@ -490,11 +490,11 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         cx<T> acc2[DUAL ? PL : 1];
         cx<T> x[PL];                    // channel 0's column, loaded with the twiddles
         if (active) {
-            const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(kx) * N;
+            const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + kx;
 #pragma unroll
             for (int m = 0; m < PL; ++m) {
                 const int i = lane + m * kWave;
-                x[m] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+                x[m] = (i < N) ? t1[int64_t(i) * H] : cx<T>{T(0), T(0)};
             }
         }
         twr.store(sm.tw, tid);
@@ -504,8 +504,8 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
 #pragma unroll
                 for (int m = 0; m < PL; ++m) line[lane + m * kWave] = x[m];
             } else {
-                const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + (int64_t(ch) * H + kx) * N;
-                for (int i = lane; i < M; i += kWave) line[i] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+                const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(ch) * N * H + kx;
+                for (int i = lane; i < M; i += kWave) line[i] = (i < N) ? t1[int64_t(i) * H] : cx<T>{T(0), T(0)};
             }
             wave_sync();
             fft_wave<T, false, M>(line, sm.tw, lane);
