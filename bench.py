@@ -115,6 +115,9 @@ def main() -> int:
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-iter", action="store_true")
+    ap.add_argument("--no-window", action="store_true")
+    ap.add_argument("--grad-only", action="store_true",
+                    help="only the differentiation workload (for a kernel trace of its kernels)")
     ap.add_argument("--profile-batch", action="store_true",
                     help="only a few batched pairs plus a 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -133,6 +136,9 @@ def main() -> int:
     P = S.headline()
     n, t = P.n, P.n_samples
     dev = torch.device("cuda:0")
+    if args.grad_only:
+        print(json.dumps({"differentiation": differentiation(S, dev)}))
+        return 0
     r = torch.tensor(S.to_f32(P.traj.r), dtype=torch.float32, device=dev)
     v = torch.tensor(S.to_f32(P.traj.v), dtype=torch.float32, device=dev)
     c1 = torch.tensor(P.c, dtype=torch.float32, device=dev)
@@ -175,7 +181,7 @@ def main() -> int:
     dom_bytes = B * stage_bytes(dom, n, batch.info[0]["fft_size"], t)
     achieved = dom_bytes / (stB[dom] * 1e-3) / 1e9
     traffic = None
-    pmc = os.path.join(HERE, "profiles", f"{dom}_headline_256_b{B}_pmc.json")
+    pmc = os.path.join(HERE, "profiles", f"k_{dom}_headline_256_b{B}_pmc.json")
     if os.path.exists(pmc):
         rec = json.load(open(pmc))
         if rec.get("src_digest") == src_digest():
@@ -209,7 +215,8 @@ def main() -> int:
     }
     del batch, c_all, s_all, g_all
     torch.cuda.empty_cache()
-    out["window_31_direct"] = window31_line(mpik, P, r, v, c1, B, args)
+    if not args.no_window:
+        out["window_31_direct"] = window31_line(mpik, P, r, v, c1, B, args)
 
     if not args.no_uneven:
         out["uneven_batch"] = uneven_batch(mpik, S, dev)

@@ -28,7 +28,10 @@
  * memory.  An mpi_plan is a small host object owned by the library
  * (mpi_plan_destroy frees it); it refers into the caller's plan memory, which
  * must outlive it.  A plan is immutable after the build.  Calls on different
- * streams may run concurrently if each passes its own work buffer.
+ * streams may run concurrently if each passes its own work buffer.  A batch
+ * whose problems use several FFT sizes (or both paths) runs each group on a
+ * side stream of the plan, forked from and joined back to the caller's
+ * stream; the plan creates them at build and destroys them with the plan.
  *
  * Errors: every call returns an mpi_status; nothing throws or aborts across
  * the ABI.  Argument errors are found on the host before anything is

@@ -284,6 +284,11 @@ struct mpi_plan {
     bool col_split = true;   // column stages: three waves per column (few problems) or a wave per column
     int col_force = 0;       // 1: always split, 2: always a wave per column, 0: by batch size
     int slice_mask = 0;      // bit i: some direct problem uses kSliceChoices[i]
+    // independent parts of a batch (each FFT size group, the direct path) run
+    // on their own streams, forked from the caller's stream and joined back
+    hipStream_t side[5] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[5] = {};
+    std::mutex fork_mu;          // one host thread at a time enqueues a fork
     // cached iteration graph
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -351,9 +356,9 @@ void finalize_extents(mpi_plan* pl) {
 // Calls f(std::integral_constant<int, M>, li) for every FFT size M = 64 << li
 // that some problem of the plan uses (float64 plans stop at 512).
 template <typename T, typename F>
-void each_fft_size(const mpi_plan* pl, F&& f) {
+void each_fft_size(const mpi_plan* pl, F&& f, int part = -1) {
     auto one = [&](auto mc, int li) {
-        if (pl->fft_m_mask & (1 << li)) f(mc, li);
+        if ((pl->fft_m_mask & (1 << li)) && (part == -1 || part == li)) f(mc, li);
     };
     one(std::integral_constant<int, 64>{}, 0);
     one(std::integral_constant<int, 128>{}, 1);
@@ -484,6 +489,7 @@ int build_problem(const mpi_problem* d, const BatchLayout& B, int b, char* plan,
 // ---------------------------------------------------------------- apply ---
 // Stages 0..2 are the FFT path, 3..4 the direct path; every launch spans the
 // whole batch and problems of the other path exit at once.
+constexpr int kDirectPart = -2;   // the direct-path part of a batch
 constexpr int kFwdStages = 5;
 constexpr int kAdjStages = 5;
 
@@ -507,19 +513,21 @@ void launch_direct_conv(const mpi_plan* pl, bool fwd, const T* in, T* out, const
 // order to the work buffer; 2: trajectory gradients of <in0, A c> to out0
 // (positions) and out1 (velocities).
 template <typename T, int MODE>
-void fwd_stage(const mpi_plan* pl, int k, const T* c, GatherIO<T> io, char* work, hipStream_t st, int dh = 0) {
+void fwd_stage(const mpi_plan* pl, int k, const T* c, GatherIO<T> io, char* work, hipStream_t st, int dh = 0,
+               int part = -1) {
     const char* plan = pl->plan;
     const Prob* P = pl->dprob;
     const int B = pl->count;
-    if (k <= 2 && !pl->any_fft) return;
-    if (k >= 3 && !pl->any_direct) return;
+    // part: -1 everything, an FFT size index that group only, kDirectPart the direct path only
+    if (k <= 2 && (!pl->any_fft || part == kDirectPart)) return;
+    if (k >= 3 && (!pl->any_direct || part >= 0)) return;
     switch (k) {
         case 0:
             each_fft_size<T>(pl, [&](auto mc, int li) {
                 constexpr int M = decltype(mc)::value;
                 k_fwd_rows<T, M><<<dim3(xcd_grid((pl->m_rowpairs[li] + 3) / 4), B), 256, pl->m_smem[li][0], st>>>(
                     P, c, plan, work);
-            });
+            }, part);
             break;
         case 1:
             each_fft_size<T>(pl, [&](auto mc, int li) {
@@ -530,14 +538,14 @@ void fwd_stage(const mpi_plan* pl, int k, const T* c, GatherIO<T> io, char* work
                 else
                     k_fwd_cols<T, M, false><<<dim3(xcd_grid((pl->m_h[li] + 3) / 4), B), 256, pl->m_smem[li][1], st>>>(
                         P, plan, work, dh);
-            });
+            }, part);
             break;
         case 2:
             each_fft_size<T>(pl, [&](auto mc, int li) {
                 constexpr int M = decltype(mc)::value;
                 k_fwd_rows_gather<T, M, MODE><<<dim3(xcd_grid(pl->m_nb[li]), B), 256, pl->m_smem[li][2], st>>>(
                     P, io, plan, work);
-            });
+            }, part);
             break;
         case 3:
             launch_direct_conv<T, 4, 0>(pl, true, c, reinterpret_cast<T*>(work), nullptr, nullptr, st, dh);
@@ -556,21 +564,22 @@ void fwd_stage(const mpi_plan* pl, int k, const T* c, GatherIO<T> io, char* work
 // buffer.  EPI 0: c_out = A^T s; EPI 1: c_out = c_in - tau_b A^T r.
 template <typename T, bool SORTED, int EPI>
 void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, char* work, hipStream_t st,
-               T* z_out = nullptr) {
+               T* z_out = nullptr, int part = -1) {
     // z_out: also the transpose with the dK/dh tables (plans built with the derivative tables)
     const char* plan = pl->plan;
     const Prob* P = pl->dprob;
     const int B = pl->count;
     const double* taus = reinterpret_cast<const double*>(work + pl->L.w_taus);
-    if (k <= 2 && !pl->any_fft) return;
-    if (k >= 3 && !pl->any_direct) return;
+    // part: -1 everything, an FFT size index that group only, kDirectPart the direct path only
+    if (k <= 2 && (!pl->any_fft || part == kDirectPart)) return;
+    if (k >= 3 && (!pl->any_direct || part >= 0)) return;
     switch (k) {
         case 0:
             each_fft_size<T>(pl, [&](auto mc, int li) {
                 constexpr int M = decltype(mc)::value;
                 k_adj_scatter_row<T, M, SORTED><<<dim3(xcd_grid(pl->m_n[li]), B), 256, pl->m_smem[li][3], st>>>(
                     P, s, plan, work);
-            });
+            }, part);
             break;
         case 1:
             each_fft_size<T>(pl, [&](auto mc, int li) {
@@ -584,7 +593,7 @@ void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, c
                 else
                     k_adj_cols<T, M, false><<<dim3(xcd_grid((pl->m_h[li] + 3) / 4), B), 256, sm, st>>>(P, plan,
                                                                                                       work);
-            });
+            }, part);
             break;
         case 2:
             each_fft_size<T>(pl, [&](auto mc, int li) {
@@ -593,7 +602,7 @@ void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, c
                 k_adj_rows<T, M, EPI><<<grid, 256, pl->m_smem[li][0], st>>>(P, c_out, c_in, taus, plan, work, 0);
                 if (z_out)
                     k_adj_rows<T, M, 0><<<grid, 256, pl->m_smem[li][0], st>>>(P, z_out, nullptr, taus, plan, work, 1);
-            });
+            }, part);
             break;
         case 3:
             k_scatter_rows<T, SORTED><<<dim3(pl->max_n, B), 256, pl->smem_dscatter, st>>>(P, s, plan, work);
@@ -615,12 +624,42 @@ void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, c
     }
 }
 
+// Runs body(stream, part) for each independent part of the batch: every FFT
+// size group on its own side stream (forked from st by an event and joined
+// back), the direct path on st.  A batch of one part runs body(st, -1).
+template <typename F>
+int by_parts(const mpi_plan* pl, hipStream_t st, F&& body) {
+    const int groups = __builtin_popcount(pl->fft_m_mask);
+    if (groups + (pl->any_direct ? 1 : 0) <= 1 || !pl->ev_fork) {
+        body(st, -1);
+        return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lk(const_cast<mpi_plan*>(pl)->fork_mu);
+    HIP_TRY(hipEventRecord(pl->ev_fork, st));
+    for (int li = 0; li < 5; ++li) {
+        if (!(pl->fft_m_mask & (1 << li))) continue;
+        HIP_TRY(hipStreamWaitEvent(pl->side[li], pl->ev_fork, 0));
+        body(pl->side[li], li);
+        HIP_TRY(hipEventRecord(pl->ev_join[li], pl->side[li]));
+    }
+    if (pl->any_direct) body(st, kDirectPart);
+    for (int li = 0; li < 5; ++li)
+        if (pl->fft_m_mask & (1 << li)) HIP_TRY(hipStreamWaitEvent(st, pl->ev_join[li], 0));
+    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+}
+
+template <typename T, int MODE>
+int forward_pass(const mpi_plan* pl, const T* c, GatherIO<T> io, char* work, hipStream_t st, int dh = 0) {
+    return by_parts(pl, st, [&](hipStream_t ps, int part) {
+        for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, MODE>(pl, k, c, io, work, ps, dh, part);
+    });
+}
+
 template <typename T>
 int forward_impl(const mpi_plan* pl, const T* c, T* s, char* work, hipStream_t st, int dh = 0) {
     GatherIO<T> io;
     io.out0 = s;
-    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 0>(pl, k, c, io, work, st, dh);
-    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    return forward_pass<T, 0>(pl, c, io, work, st, dh);
 }
 
 template <typename T>
@@ -628,8 +667,7 @@ int residual_impl(const mpi_plan* pl, const T* c, const T* y, T* out, char* work
     GatherIO<T> io;
     io.out0 = out;
     io.in0 = y;
-    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 3>(pl, k, c, io, work, st);
-    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    return forward_pass<T, 3>(pl, c, io, work, st);
 }
 
 template <typename T>
@@ -638,15 +676,15 @@ int traj_vjp_impl(const mpi_plan* pl, const T* x, const T* y, T* g_r, T* g_v, ch
     io.out0 = g_r;
     io.in0 = y;
     io.out1 = g_v;
-    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 2>(pl, k, x, io, work, st);
-    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    return forward_pass<T, 2>(pl, x, io, work, st);
 }
 
 template <typename T, bool SORTED, int EPI>
 int adjoint_impl(const mpi_plan* pl, const T* s, T* c_out, const T* c_in, char* work, hipStream_t st,
                  T* z_out = nullptr) {
-    for (int k = 0; k < kAdjStages; ++k) adj_stage<T, SORTED, EPI>(pl, k, s, c_out, c_in, work, st, z_out);
-    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    return by_parts(pl, st, [&](hipStream_t ps, int part) {
+        for (int k = 0; k < kAdjStages; ++k) adj_stage<T, SORTED, EPI>(pl, k, s, c_out, c_in, work, ps, z_out, part);
+    });
 }
 
 // One iteration c <- D(c - tau_b A^T (A c - s)) for every problem; the
@@ -654,17 +692,19 @@ int adjoint_impl(const mpi_plan* pl, const T* s, T* c_out, const T* c_in, char* 
 // the step lands in c directly; with one, in work.u and then D(u) -> c.
 template <typename T>
 int iteration_impl(const mpi_plan* pl, T* c, bool denoise, int rad, char* work, hipStream_t st) {
-    for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 1>(pl, k, c, GatherIO<T>{}, work, st);
-    int rc;
-    if (!denoise) {
-        rc = adjoint_impl<T, true, 1>(pl, nullptr, c, c, work, st);
-    } else {
-        rc = adjoint_impl<T, true, 2>(pl, nullptr, reinterpret_cast<T*>(work), c, work, st);
-        if (rc == MPI_OK)
-            k_denoise<T><<<dim3(pl->max_dntiles, pl->max_dntiles, pl->count), 256, 0, st>>>(
-                pl->dprob, work, nullptr, c, reinterpret_cast<const double*>(work + pl->L.w_wts), rad);
-    }
+    const int rc = by_parts(pl, st, [&](hipStream_t ps, int part) {
+        for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 1>(pl, k, c, GatherIO<T>{}, work, ps, 0, part);
+        for (int k = 0; k < kAdjStages; ++k) {
+            if (denoise)
+                adj_stage<T, true, 2>(pl, k, nullptr, reinterpret_cast<T*>(work), c, work, ps, nullptr, part);
+            else
+                adj_stage<T, true, 1>(pl, k, nullptr, c, c, work, ps, nullptr, part);
+        }
+    });
     if (rc != MPI_OK) return rc;
+    if (denoise)
+        k_denoise<T><<<dim3(pl->max_dntiles, pl->max_dntiles, pl->count), 256, 0, st>>>(
+            pl->dprob, work, nullptr, c, reinterpret_cast<const double*>(work + pl->L.w_wts), rad);
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
@@ -831,6 +871,34 @@ int build_batch(const mpi_problem* probs, mpi_plan* pl, void* work, size_t work_
     return MPI_OK;
 }
 
+void release_streams(mpi_plan* pl) {
+    for (int li = 0; li < 5; ++li) {
+        if (pl->side[li]) (void)hipStreamDestroy(pl->side[li]);
+        if (pl->ev_join[li]) (void)hipEventDestroy(pl->ev_join[li]);
+        pl->side[li] = nullptr;
+        pl->ev_join[li] = nullptr;
+    }
+    if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+    pl->ev_fork = nullptr;
+}
+
+// Side streams (default priority) and fork/join events for batches with more
+// than one independent part.
+int create_streams(mpi_plan* pl) {
+    if (__builtin_popcount(pl->fft_m_mask) + (pl->any_direct ? 1 : 0) <= 1) return MPI_OK;
+    bool ok = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (int li = 0; li < 5 && ok; ++li) {
+        if (!(pl->fft_m_mask & (1 << li))) continue;
+        ok = hipStreamCreateWithFlags(&pl->side[li], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&pl->ev_join[li], hipEventDisableTiming) == hipSuccess;
+    }
+    if (!ok) {
+        release_streams(pl);
+        return MPI_ERR_HIP;
+    }
+    return MPI_OK;
+}
+
 int build_common(const mpi_problem* probs, int count, void* plan_mem, size_t plan_bytes, void* work,
                  size_t work_bytes, int flags, hipStream_t stream, mpi_plan** out) {
     if (!out) return MPI_ERR_ARG;
@@ -856,6 +924,7 @@ int build_common(const mpi_problem* probs, int count, void* plan_mem, size_t pla
     finalize_extents(pl);
     rc = pl->dtype == MPI_F64 ? build_batch<double>(probs, pl, work, work_bytes, flags, stream)
                               : build_batch<float>(probs, pl, work, work_bytes, flags, stream);
+    if (rc == MPI_OK) rc = create_streams(pl);
     if (rc != MPI_OK) {
         delete pl;
         return rc;
@@ -955,9 +1024,9 @@ int unrolled_vjp_impl(mpi_plan* pl, const T* s, const T* ckpt, int K, int E, dou
             GatherIO<T> io;
             io.out0 = rs + e * V.S;
             io.f = fc + e * V.F;
-            for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 5>(pl, k, ce, io, work, st);
+            int rc = forward_pass<T, 5>(pl, ce, io, work, st);
+            if (rc != MPI_OK) return rc;
             T* next = e + 1 < L ? cs + (e + 1) * V.C : nullptr;
-            int rc;
             if (next && !den) {
                 rc = adjoint_impl<T, true, 1>(pl, re, next, ce, work, st, zs + e * V.C);
             } else {
@@ -980,8 +1049,9 @@ int unrolled_vjp_impl(mpi_plan* pl, const T* s, const T* ckpt, int K, int E, dou
             io.out1 = gr;
             io.out2 = gv;
             io.f = fc + e * V.F;
-            for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 6>(pl, k, g_u, io, work, st);
-            const int rc = adjoint_impl<T, true, 1>(pl, q, gbar, g_u, work, st, zq);
+            int rc = forward_pass<T, 6>(pl, g_u, io, work, st);
+            if (rc != MPI_OK) return rc;
+            rc = adjoint_impl<T, true, 1>(pl, q, gbar, g_u, work, st, zq);
             if (rc != MPI_OK) return rc;
             k_dot<T><<<B, 1024, 0, st>>>(P, ce, zq, 1, 2, acc_h, 1);
         }
@@ -1375,6 +1445,7 @@ int mpi_plan_destroy(mpi_plan* plan) {
         (void)hipGraphExecDestroy(plan->gexec);
         (void)hipGraphDestroy(plan->graph);
     }
+    release_streams(plan);
     delete plan;
     return MPI_OK;
 }
