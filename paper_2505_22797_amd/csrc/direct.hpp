@@ -252,15 +252,21 @@ __global__ void __launch_bounds__(256) k_denoise(const Prob* __restrict__ P, con
 }
 
 // Deterministic per-problem dot products: out[b] = sum_i a_b[i] b_b[i] in
-// float64, one work-group per problem, fixed strided partition and a fixed
-// reduction tree.  space 0: signal arrays ([T][2], comp 0 = x components
-// only, 1 = y only, 2 = both); space 1: concentration arrays ([N][N]).
+// float64, in two launches.  k_dot_part: grid (kDotParts, problems) of 256
+// threads; part q sums a fixed contiguous slice of the problem's elements
+// (thread-strided inside the slice, then a fixed tree) into part[b][q].
+// k_dot_final: one work-group per problem adds its kDotParts partials by a
+// fixed tree (and to out[b] when accumulating).  space 0: signal arrays
+// ([T][2]; comp 0 = x components only, 1 = y only, 2 = both); space 1:
+// concentration arrays ([N][N]).
+constexpr int kDotParts = 64;
+
 template <typename T>
-__global__ void __launch_bounds__(1024) k_dot(const Prob* __restrict__ P, const T* __restrict__ a,
-                                              const T* __restrict__ bb, int space, int comp,
-                                              double* __restrict__ out, int accumulate) {
-    __shared__ double part[1024];
-    const Prob& p = P[blockIdx.x];
+__global__ void __launch_bounds__(256) k_dot_part(const Prob* __restrict__ P, const T* __restrict__ a,
+                                                  const T* __restrict__ bb, int space, int comp,
+                                                  double* __restrict__ part) {
+    __shared__ double red[256];
+    const Prob& p = P[blockIdx.y];
     const int tid = threadIdx.x;
     int64_t n, off, stride = 1, first = 0;
     if (space == 0) {
@@ -271,16 +277,34 @@ __global__ void __launch_bounds__(1024) k_dot(const Prob* __restrict__ P, const 
         off = p.o_c;
         n = int64_t(p.n) * p.n;
     }
+    const int64_t m = (n - first + stride - 1) / stride;          // elements taken
+    const int64_t per = (m + kDotParts - 1) / kDotParts;
+    const int64_t lo = min(m, per * blockIdx.x), hi = min(m, lo + per);
     double acc = 0.0;
-    for (int64_t i = first + int64_t(tid) * stride; i < n; i += int64_t(1024) * stride)
-        acc += double(a[off + i]) * double(bb[off + i]);
-    part[tid] = acc;
+    for (int64_t e = lo + tid; e < hi; e += 256) {
+        const int64_t i = off + first + e * stride;
+        acc += double(a[i]) * double(bb[i]);
+    }
+    red[tid] = acc;
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (tid < w) part[tid] += part[tid + w];
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
         __syncthreads();
     }
-    if (tid == 0) out[blockIdx.x] = (accumulate ? out[blockIdx.x] : 0.0) + part[0];
+    if (tid == 0) part[int64_t(blockIdx.y) * kDotParts + blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kDotParts) k_dot_final(const double* __restrict__ part, double* __restrict__ out,
+                                                        int accumulate) {
+    __shared__ double red[kDotParts];
+    const int tid = threadIdx.x;
+    red[tid] = part[int64_t(blockIdx.x) * kDotParts + tid];
+    __syncthreads();
+    for (int w = kDotParts / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) out[blockIdx.x] = (accumulate ? out[blockIdx.x] : 0.0) + red[0];
 }
 
 }  // namespace mpik

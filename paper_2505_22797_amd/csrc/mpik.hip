@@ -200,7 +200,7 @@ struct BatchLayout {
     std::vector<Prob> probs;
     std::vector<int> requested;   // MPI_CONV_* per problem
     size_t desc_bytes = 0, plan_bytes = 0, work_bytes = 0, scratch_base = 0;
-    size_t w_taus = 0, w_wts = 0;
+    size_t w_taus = 0, w_wts = 0, w_dot = 0;
     int64_t c_elems = 0, s_elems = 0;
     int elem = 4;
     bool deriv = false;
@@ -248,6 +248,7 @@ int make_batch_layout(const mpi_problem* probs, int count, int flags, BatchLayou
     B.plan_bytes = scratch_end;
     B.w_taus = take(woff, sizeof(double) * count);
     B.w_wts = take(woff, 32 * sizeof(double));
+    B.w_dot = take(woff, sizeof(double) * kDotParts * count);
     B.work_bytes = woff;
     return MPI_OK;
 }
@@ -622,6 +623,15 @@ void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, c
         }
         default: break;
     }
+}
+
+// out[b] (+)= <a_b, b_b> for every problem, deterministic (fixed slices and trees).
+template <typename T>
+void launch_dot(const mpi_plan* pl, const T* a, const T* b, int space, int comp, double* out, int accumulate,
+                char* work, hipStream_t st) {
+    double* part = reinterpret_cast<double*>(work + pl->L.w_dot);
+    k_dot_part<T><<<dim3(kDotParts, pl->count), 256, 0, st>>>(pl->dprob, a, b, space, comp, part);
+    k_dot_final<<<pl->count, kDotParts, 0, st>>>(part, out, accumulate);
 }
 
 // Runs body(stream, part) for each independent part of the batch: every FFT
@@ -1042,7 +1052,7 @@ int unrolled_vjp_impl(mpi_plan* pl, const T* s, const T* ckpt, int K, int E, dou
                 k_denoise<T><<<dn_grid, 256, 0, st>>>(P, work, gbar, gu, wts, rad);
                 g_u = gu;
             }
-            k_dot<T><<<B, 1024, 0, st>>>(P, g_u, zs + e * V.C, 1, 2, acc_h, 1);
+            launch_dot<T>(pl, g_u, zs + e * V.C, 1, 2, acc_h, 1, work, st);
             GatherIO<T> io;
             io.out0 = q;
             io.in0 = rs + e * V.S;
@@ -1053,7 +1063,7 @@ int unrolled_vjp_impl(mpi_plan* pl, const T* s, const T* ckpt, int K, int E, dou
             if (rc != MPI_OK) return rc;
             rc = adjoint_impl<T, true, 1>(pl, q, gbar, g_u, work, st, zq);
             if (rc != MPI_OK) return rc;
-            k_dot<T><<<B, 1024, 0, st>>>(P, ce, zq, 1, 2, acc_h, 1);
+            launch_dot<T>(pl, ce, zq, 1, 2, acc_h, 1, work, st);
         }
     }
     k_vjp_finish<T><<<dim3(blocks(pl->max_t, 256), B), 256, 0, st>>>(P, pl->plan, gr, gv, g_r, g_v, acc_h, g_h,
@@ -1356,11 +1366,11 @@ int mpi_batch_dot(const mpi_plan* plan, const void* a, const void* b, int space,
     if (!out || (space != 0 && space != 1) || comp < 0 || comp > 2) return MPI_ERR_ARG;
     if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
     if (plan->dtype == MPI_F64)
-        k_dot<double><<<plan->count, 1024, 0, stream>>>(plan->dprob, static_cast<const double*>(a),
-                                                        static_cast<const double*>(b), space, comp, out, 0);
+        launch_dot<double>(plan, static_cast<const double*>(a), static_cast<const double*>(b), space, comp, out, 0,
+                           static_cast<char*>(work), stream);
     else
-        k_dot<float><<<plan->count, 1024, 0, stream>>>(plan->dprob, static_cast<const float*>(a),
-                                                       static_cast<const float*>(b), space, comp, out, 0);
+        launch_dot<float>(plan, static_cast<const float*>(a), static_cast<const float*>(b), space, comp, out, 0,
+                          static_cast<char*>(work), stream);
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
