@@ -50,17 +50,13 @@ template <typename T, int M>
 __host__ __device__ constexpr size_t gather_smem_bytes(int N) {
     return sizeof(GatherSmem<T, M>) + size_t(6) * N * sizeof(T);
 }
-// adj_scatter_row: twiddles, the row's three channels (3N values), then a
-// region shared by the sampling transpose and the two row-FFT lines (they
-// run one after the other).
-template <typename T, int M> struct ScatterRowSmem {
-    cx<T> tw[M];
-    cx<T> line[2][M];
-};
+// adj_scatter_row: the row's three channels (3N values), then a region used
+// first by the sampling transpose and then by the twiddles and the two
+// row-FFT lines (the twiddles wait in registers meanwhile).
 template <typename T, int M>
 __host__ __device__ constexpr size_t scatter_row_smem_bytes(int N) {
-    const size_t a = sizeof(cx<T>) * M, lines = 2 * sizeof(cx<T>) * M, sc = scatter_lds_bytes<T>(N, 256);
-    return a + lds_align(size_t(3) * N * sizeof(T)) + (lines > sc ? lines : sc);
+    const size_t fft = 3 * sizeof(cx<T>) * M, sc = scatter_lds_bytes<T>(N, 256);
+    return lds_align(size_t(3) * N * sizeof(T)) + (fft > sc ? fft : sc);
 }
 
 // spectrum value of channel ch at (kx, ky), kx in [0, M/2], ky in [0, M)
@@ -347,10 +343,10 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
     constexpr int H = M / 2 + 1;
     const int N = p.n, j = xcd_unit(blockIdx.x, N);
     if (j < 0) return;
-    cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
-    T* g = reinterpret_cast<T*>(smem + sizeof(cx<T>) * M);
-    char* shared_area = smem + sizeof(cx<T>) * M + lds_align(size_t(3) * N * sizeof(T));
-    cx<T>* lines = reinterpret_cast<cx<T>*>(shared_area);
+    T* g = reinterpret_cast<T*>(smem);
+    char* shared_area = smem + lds_align(size_t(3) * N * sizeof(T));
+    cx<T>* tw = reinterpret_cast<cx<T>*>(shared_area);     // after the sampling
+    cx<T>* lines = tw + M;
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     TwiddleRegs<T, M, 4 * kWave> twr;       // in flight during the transpose sampling
     twr.load(plan, p, tid);

@@ -185,8 +185,8 @@ __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int
 // first/last base cell of every thread with the partial sum of the first.
 template <typename T> struct ScatterLds {
     T* K;
-    int* first_key;
-    int* last_key;
+    short* first_key;      // keys are below 2 (N - 1) <= 2046, or -1
+    short* last_key;
     T* first_val;
 };
 
@@ -194,7 +194,7 @@ __host__ __device__ constexpr size_t lds_align(size_t b) { return (b + 15) / 16 
 
 template <typename T>
 __host__ __device__ constexpr size_t scatter_lds_bytes(int N, int NT) {
-    return lds_align(size_t(2) * (N - 1) * 6 * sizeof(T)) + lds_align(size_t(2) * NT * sizeof(int)) +
+    return lds_align(size_t(2) * (N - 1) * 6 * sizeof(T)) + lds_align(size_t(2) * NT * sizeof(short)) +
            lds_align(size_t(NT) * 6 * sizeof(T));
 }
 
@@ -203,9 +203,9 @@ __device__ __forceinline__ ScatterLds<T> scatter_lds(char* base, int N, int NT) 
     ScatterLds<T> v;
     v.K = reinterpret_cast<T*>(base);
     base += lds_align(size_t(2) * (N - 1) * 6 * sizeof(T));
-    v.first_key = reinterpret_cast<int*>(base);
+    v.first_key = reinterpret_cast<short*>(base);
     v.last_key = v.first_key + NT;
-    base += lds_align(size_t(2) * NT * sizeof(int));
+    base += lds_align(size_t(2) * NT * sizeof(short));
     v.first_val = reinterpret_cast<T*>(base);
     return v;
 }
@@ -293,8 +293,8 @@ __device__ __forceinline__ void scatter_row(T* g, ScatterLds<T> sm, int N, int j
 #pragma unroll
         for (int q = 0; q < 6; ++q) fv[q] = acc[q];
     }
-    sm.first_key[tid] = fk;
-    sm.last_key[tid] = lk;
+    sm.first_key[tid] = short(fk);
+    sm.last_key[tid] = short(lk);
 #pragma unroll
     for (int q = 0; q < 6; ++q) sm.first_val[tid * 6 + q] = fv[q];
     __syncthreads();
