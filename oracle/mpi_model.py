@@ -10,9 +10,12 @@ readings below are the ones the GPU library implements too):
     delta^2 * sum_d K_h(delta d) c[. - d] over integer offsets d with
     |d_x|, |d_y| <= R (square window, zero outside the grid, a linear and not
     a circular convolution); R >= N-1 is the untruncated kernel;
-  * the field is interpolated bilinearly between cell centres and contracted
-    with the velocity, s_k = A[c](r_k) v_k (eq. core:formula), the constant of
-    proportionality taken as +1;
+  * the field is interpolated between the four surrounding cell centres and
+    contracted with the velocity, s_k = A[c](r_k) v_k (eq. core:formula), the
+    constant of proportionality taken as +1.  Two interpolators: bilinear
+    (weights f, 1 - f per axis) and the cosine interpolation the paper names
+    for its core stage, read as the textbook scheme with per-axis weight
+    w(f) = (1 - cos pi f)/2 in place of f (tensor product over the axes);
   * A^T is the exact transpose of that finite linear map.
 """
 from __future__ import annotations
@@ -26,7 +29,7 @@ __all__ = [
     "DomainError", "langevin", "langevin_d1", "langevin_d2",
     "kernel_h", "kernel_h_dh", "trace_kernel_h", "kernel_table", "kernel_table_dh",
     "trace_kernel_table", "effective_radius", "fft_size", "conv_direct", "conv_fft", "conv", "conv_adj",
-    "bilinear", "gather", "scatter", "forward", "adjoint", "gauss_weights", "denoise",
+    "bilinear", "interp_weight", "interp_weight_d", "INTERPS", "gather", "scatter", "forward", "adjoint", "gauss_weights", "denoise",
     "iterate", "power_lambda_max", "unrolled_gradients", "Model",
 ]
 
@@ -276,46 +279,74 @@ def bilinear(r: np.ndarray, n: int, frozen=None):
     return i0[:, 0], i0[:, 1], f[:, 0], f[:, 1]
 
 
-def _corners(r, n, frozen=None):
+INTERPS = ("bilinear", "cosine")
+
+
+def interp_weight(f, interp="bilinear"):
+    """Weight of the upper neighbour along one axis at fraction f (the lower
+    one gets 1 - w): f for bilinear; (1 - cos pi f)/2 for the cosine scheme,
+    which equals the nodes at f = 0, 1, their mean at f = 1/2, and has zero
+    slope at the nodes, so the interpolant is C^1 across cell edges."""
+    f = np.asarray(f, dtype=np.float64)
+    if interp == "bilinear":
+        return f
+    if interp == "cosine":
+        return 0.5 * (1.0 - np.cos(np.pi * f))
+    raise ValueError(f"unknown interpolator {interp!r}")
+
+
+def interp_weight_d(f, interp="bilinear"):
+    """d w / d f of `interp_weight`."""
+    f = np.asarray(f, dtype=np.float64)
+    if interp == "bilinear":
+        return np.ones_like(f)
+    if interp == "cosine":
+        return 0.5 * np.pi * np.sin(np.pi * f)
+    raise ValueError(f"unknown interpolator {interp!r}")
+
+
+def _corners(r, n, frozen=None, interp="bilinear"):
     ix, jy, fx, fy = bilinear(r, n, frozen)
-    return [((jy, ix), (1 - fx) * (1 - fy)), ((jy, ix + 1), fx * (1 - fy)),
-            ((jy + 1, ix), (1 - fx) * fy), ((jy + 1, ix + 1), fx * fy)]
+    wx, wy = interp_weight(fx, interp), interp_weight(fy, interp)
+    return [((jy, ix), (1 - wx) * (1 - wy)), ((jy, ix + 1), wx * (1 - wy)),
+            ((jy + 1, ix), (1 - wx) * wy), ((jy + 1, ix + 1), wx * wy)]
 
 
-def gather(G: np.ndarray, r: np.ndarray, v: np.ndarray, frozen=None) -> np.ndarray:
-    """s_k = G(r_k) v_k with G = [G_xx, G_xy, G_yy] interpolated bilinearly."""
+def gather(G: np.ndarray, r: np.ndarray, v: np.ndarray, frozen=None, interp="bilinear") -> np.ndarray:
+    """s_k = G(r_k) v_k with G = [G_xx, G_xy, G_yy] interpolated from the four
+    surrounding cell centres."""
     n = G.shape[-1]
     g = np.zeros((3, r.shape[0]))
-    for (j, i), w in _corners(r, n, frozen):
+    for (j, i), w in _corners(r, n, frozen, interp):
         g += w * G[:, j, i]
     v = np.asarray(v, dtype=np.float64)
     return np.stack([g[0] * v[:, 0] + g[1] * v[:, 1], g[1] * v[:, 0] + g[2] * v[:, 1]], 1)
 
 
-def scatter(y: np.ndarray, r: np.ndarray, v: np.ndarray, n: int, frozen=None) -> np.ndarray:
+def scatter(y: np.ndarray, r: np.ndarray, v: np.ndarray, n: int, frozen=None, interp="bilinear") -> np.ndarray:
     """Transpose of gather: G'_ch(q) = sum_k w_kq p_k,ch with the products
     p = (y_x v_x, y_x v_y + y_y v_x, y_y v_y)."""
     y = np.asarray(y, dtype=np.float64)
     v = np.asarray(v, dtype=np.float64)
     p = np.stack([y[:, 0] * v[:, 0], y[:, 0] * v[:, 1] + y[:, 1] * v[:, 0], y[:, 1] * v[:, 1]])
     out = np.zeros((3, n * n))
-    for (j, i), w in _corners(r, n, frozen):
+    for (j, i), w in _corners(r, n, frozen, interp):
         for ch in range(3):
             out[ch] += np.bincount(j * n + i, weights=w * p[ch], minlength=n * n)
     return out.reshape(3, n, n)
 
 
-def forward(c, r, v, h, radius, method="auto"):
+def forward(c, r, v, h, radius, method="auto", interp="bilinear"):
     """A c: convolution with delta^2 K_h, then sampling and contraction."""
     n = c.shape[0]
     taps = (2.0 / n) ** 2 * kernel_table(n, h, radius)
-    return gather(conv(c, taps, method), r, v)
+    return gather(conv(c, taps, method), r, v, interp=interp)
 
 
-def adjoint(y, r, v, h, radius, n, method="auto"):
+def adjoint(y, r, v, h, radius, n, method="auto", interp="bilinear"):
     """A^T y: transpose sampling, then the (self-transpose) convolution."""
     taps = (2.0 / n) ** 2 * kernel_table(n, h, radius)
-    return conv_adj(scatter(y, r, v, n), taps, method)
+    return conv_adj(scatter(y, r, v, n, interp=interp), taps, method)
 
 
 # ----------------------------------------------------------------------------
@@ -343,10 +374,13 @@ def denoise(c: np.ndarray, sigma_px: float, radius: int) -> np.ndarray:
 
 class Model:
     """A and A^T for one problem with the kernel table and sample cells cached.
-    frozen = (ix, jy) fixes the base cells (see `bilinear`)."""
+    frozen = (ix, jy) fixes the base cells (see `bilinear`); interp is
+    "bilinear" or "cosine" (see `interp_weight`)."""
 
-    def __init__(self, n, h, radius, r, v, method="auto", frozen=None):
-        self.n, self.h, self.radius, self.method = n, h, radius, method
+    def __init__(self, n, h, radius, r, v, method="auto", frozen=None, interp="bilinear"):
+        if interp not in INTERPS:
+            raise ValueError(f"unknown interpolator {interp!r}")
+        self.n, self.h, self.radius, self.method, self.interp = n, h, radius, method, interp
         self.r = np.asarray(r, dtype=np.float64)
         self.v = np.asarray(v, dtype=np.float64)
         if frozen is None:
@@ -362,10 +396,10 @@ class Model:
         return conv(c, self.taps, self.method)
 
     def forward(self, c):
-        return gather(self.field(c), self.r, self.v, self.frozen)
+        return gather(self.field(c), self.r, self.v, self.frozen, self.interp)
 
     def adjoint(self, y):
-        return conv_adj(scatter(y, self.r, self.v, self.n, self.frozen), self.taps, self.method)
+        return conv_adj(scatter(y, self.r, self.v, self.n, self.frozen, self.interp), self.taps, self.method)
 
     def normal(self, c):
         return self.adjoint(self.forward(c))
@@ -374,21 +408,24 @@ class Model:
     def forward_dh(self, x):
         """(dA/dh) x: the sampling of the convolution with delta^2 dK_h/dh."""
         dtaps = (2.0 / self.n) ** 2 * kernel_table_dh(self.n, self.h, self.radius)
-        return gather(conv(x, dtaps, self.method), self.r, self.v, self.frozen)
+        return gather(conv(x, dtaps, self.method), self.r, self.v, self.frozen, self.interp)
 
     def traj_vjp(self, x, y):
         """Gradients of <y, A x> with respect to every sample's position r_k and
-        velocity v_k, base cells fixed (the derivative inside the bilinear
+        velocity v_k, base cells fixed (the derivative inside the interpolation
         patch).  Returns (g_r, g_v), both [T, 2]."""
         n = self.n
         G = self.field(x)
         ix, jy, fx, fy = bilinear(self.r, n, self.frozen)
+        wx, wy = interp_weight(fx, self.interp), interp_weight(fy, self.interp)
         g00, g10 = G[:, jy, ix], G[:, jy, ix + 1]
         g01, g11 = G[:, jy + 1, ix], G[:, jy + 1, ix + 1]
-        g = (1 - fx) * (1 - fy) * g00 + fx * (1 - fy) * g10 + (1 - fx) * fy * g01 + fx * fy * g11
-        inv_d = n / 2.0                                   # d fraction / d position
-        dgx = inv_d * ((1 - fy) * (g10 - g00) + fy * (g11 - g01))
-        dgy = inv_d * ((1 - fx) * (g01 - g00) + fx * (g11 - g10))
+        g = (1 - wx) * (1 - wy) * g00 + wx * (1 - wy) * g10 + (1 - wx) * wy * g01 + wx * wy * g11
+        # chain rule: d fraction / d position = N/2, d weight / d fraction = w'
+        dwx = (n / 2.0) * interp_weight_d(fx, self.interp)
+        dwy = (n / 2.0) * interp_weight_d(fy, self.interp)
+        dgx = dwx * ((1 - wy) * (g10 - g00) + wy * (g11 - g01))
+        dgy = dwy * ((1 - wx) * (g01 - g00) + wx * (g11 - g10))
         y = np.asarray(y, dtype=np.float64)
         v = self.v
 
@@ -411,7 +448,7 @@ def iterate(model: Model, s, c0, tau, n_iter, sigma_px=None, radius=2):
 
 
 def unrolled_gradients(n, h, radius, ax, ay, rho, nu, s, c_true, c0, tau, n_iter, sigma_px=None, radius_d=2,
-                       frozen=None, method="auto"):
+                       frozen=None, method="auto", interp="bilinear"):
     """Loss L = |c_K - c_true|^2 after n_iter steps c <- D(c - tau A^T(A c - s))
     with the trajectory r = (ax rho_x, ay rho_y), v = (ax nu_x, ay nu_y), and
     its gradients with respect to c0, h, ax and ay by the reverse recursion:
@@ -422,7 +459,7 @@ def unrolled_gradients(n, h, radius, ax, ay, rho, nu, s, c_true, c0, tau, n_iter
     scale = np.array([ax, ay])
     r = np.asarray(rho) * scale
     v = np.asarray(nu) * scale
-    M = Model(n, h, radius, r, v, method=method, frozen=frozen)
+    M = Model(n, h, radius, r, v, method=method, frozen=frozen, interp=interp)
     D = (lambda x: denoise(x, sigma_px, radius_d)) if sigma_px is not None else (lambda x: x)
     cs, rs = [], []
     c = np.array(c0, dtype=np.float64)
