@@ -16,8 +16,9 @@ give the times.
 Also reported: per-kernel durations (each stage launched alone through the
 library's diagnostic entry point), the roofline of the dominant kernel, the
 fraction of HBM peak for the algorithmic bytes of a pair (56 N^2 + 48 T), the
-uneven 64-problem batch iteration against 64 sequential solves, and the
-float64 CPU oracle timed on a bounded sample of pairs on the host.
+uneven 64-problem batch iteration against 64 sequential solves, the same
+workload with the cosine interpolator, and the float64 CPU oracle timed on a
+bounded sample of pairs on the host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
 """
@@ -116,6 +117,7 @@ def main() -> int:
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-iter", action="store_true")
     ap.add_argument("--no-window", action="store_true")
+    ap.add_argument("--no-cosine", action="store_true")
     ap.add_argument("--grad-only", action="store_true",
                     help="only the differentiation workload (for a kernel trace of its kernels)")
     ap.add_argument("--profile-batch", action="store_true",
@@ -217,6 +219,8 @@ def main() -> int:
     torch.cuda.empty_cache()
     if not args.no_window:
         out["window_31_direct"] = window31_line(mpik, P, r, v, c1, B, args)
+    if not args.no_cosine:
+        out["cosine_interp"] = cosine_line(mpik, P, r, v, c1, B, args)
 
     if not args.no_uneven:
         out["uneven_batch"] = uneven_batch(mpik, S, dev)
@@ -260,6 +264,39 @@ def window31_line(mpik, P, r, v, c1, B, args):
             "batch": B, "batch_pairs_per_s": round(B * 1e3 / msB, 1),
             "direct_conv_tflops": round(flop * B / (msB * 1e-3) / 1e12, 2),
             "stage_ms": {k: round(x, 5) for k, x in stB.items()}}
+
+
+def cosine_line(mpik, P, r, v, c1, B, args):
+    """The headline workload with the cosine interpolator: the weights are
+    evaluated once at plan build, so the applies run the same kernels."""
+    import torch
+    n, t = P.n, P.n_samples
+    plan = mpik.Plan(n, P.h, P.radius, r, v, interp="cosine")
+    s1 = torch.empty((t, 2), dtype=torch.float32, device=c1.device)
+    g1 = torch.empty((n, n), dtype=torch.float32, device=c1.device)
+
+    def pair1():
+        plan.forward(c1, s1)
+        plan.adjoint(s1, g1)
+
+    ms1, _ = graph_time(pair1, args.steps, args.graph_pairs, args.warmup)
+    batch = mpik.Batch([(n, P.h, P.radius, r, v, "fft", "cosine")] * B, tune=False)
+    c_all = c1.reshape(-1).repeat(B).contiguous()
+    s_all = torch.empty(batch.s_offsets[-1], dtype=torch.float32, device=c1.device)
+    g_all = torch.empty(batch.c_offsets[-1], dtype=torch.float32, device=c1.device)
+
+    def pairB():
+        batch.forward(c_all, s_all)
+        batch.adjoint(s_all, g_all)
+
+    msB, _ = graph_time(pairB, max(10, args.steps // B * 4), max(1, args.graph_pairs // 5), 2)
+    stB = stage_times(batch, g_all, s_all, max(3, args.stage_reps // 4))
+    out = {"interp": "cosine", "conv_path": plan.conv_mode, "fft_size": plan.fft_size,
+           "single_pairs_per_s": round(1e3 / ms1, 1), "batch": B, "batch_pairs_per_s": round(B * 1e3 / msB, 1),
+           "stage_ms": {k: round(x, 5) for k, x in stB.items()}}
+    del batch, c_all, s_all, g_all
+    torch.cuda.empty_cache()
+    return out
 
 
 def iteration_configs(mpik, S, dev, with_oracle, oracle_seconds=3.0):

@@ -17,8 +17,9 @@
  *   - the convolution is the Riemann sum delta^2 * sum_d K_h(delta d) c[. - d]
  *     over integer offsets |d_x|, |d_y| <= R (square window, zero outside the
  *     grid); R >= N-1 is the untruncated kernel;
- *   - the field is interpolated bilinearly between cell centres; a sample
- *     needs g = (r + 1)/delta - 1/2 in [0, N-1] on both axes;
+ *   - the field is interpolated between the four surrounding cell centres
+ *     (bilinear or cosine weights, see MPI_INTERP_*); a sample needs
+ *     g = (r + 1)/delta - 1/2 in [0, N-1] on both axes;
  *   - s is [T][2] interleaved (x, y), matching a contiguous (T, 2) tensor;
  *     signal buffers the library writes must be aligned to two elements
  *     (else MPI_ERR_ARG).
@@ -65,7 +66,12 @@ typedef enum {
 
 enum { MPI_F32 = 0, MPI_F64 = 1 };
 enum { MPI_CONV_AUTO = 0, MPI_CONV_DIRECT = 1, MPI_CONV_FFT = 2 };
-enum { MPI_INTERP_BILINEAR = 0 };
+/* Interpolation of the field between the four surrounding cell centres, per
+ * axis with weight w(f) on the upper neighbour and 1 - w(f) on the lower one,
+ * f the fraction of the way between them: f (bilinear), or (1 - cos pi f)/2,
+ * the cosine interpolation the paper names for the core stage (section on
+ * the core stage; the formula is the textbook scheme, C^1 across cells). */
+enum { MPI_INTERP_BILINEAR = 0, MPI_INTERP_COSINE = 1 };
 enum { MPI_CH_XY = 0 };
 
 /* One reconstruction problem.  r and v are device pointers to [T][2] arrays
@@ -76,7 +82,7 @@ typedef struct {
     double h;              /* kernel resolution in field-of-view units, > 0    */
     int32_t radius;        /* window half-width R >= 0 in pixels; capped N-1   */
     int32_t conv_mode;     /* MPI_CONV_*: selects speed only, never the result */
-    int32_t interp;        /* MPI_INTERP_BILINEAR                              */
+    int32_t interp;        /* MPI_INTERP_BILINEAR or MPI_INTERP_COSINE         */
     int32_t channels;      /* MPI_CH_XY: both signal channels                  */
     int64_t n_samples;     /* T >= 1, T < 2^26                                 */
     const void* r;         /* device [T][2] sample positions r_k               */
@@ -159,7 +165,9 @@ enum { MPI_BUILD_TUNE = 1 };
  * because the channel sum is contracted into multiply-adds differently. */
 enum { MPI_BUILD_COL_SPLIT = 2, MPI_BUILD_COL_WAVE = 4 };
 /* Also build the tables of dK_h/dh (plan memory grows by one table or one set
- * of spectra per problem); needed by mpi_batch_forward_dh. */
+ * of spectra per problem) and every sample's interpolation-weight slopes
+ * d w/d f (two values per sample); needed by mpi_batch_forward_dh,
+ * mpi_batch_traj_vjp and mpi_batch_unrolled_vjp. */
 enum { MPI_BUILD_DERIV = 8 };
 
 /* Plan and work bytes of a batch built with `flags` (MPI_BUILD_*). */
@@ -199,8 +207,10 @@ int mpi_batch_iterate(const mpi_plan* plan, const void* s_all, void* c_all,
  *   gradients of <y, A x> with respect to every sample's position and
  *   velocity: g_r[k] = (y_k^T M(dG/dx) v_k, y_k^T M(dG/dy) v_k),
  *   g_v[k] = M(G(r_k)) y_k, with M(g) the symmetric 2x2 field and the spatial
- *   derivatives taken inside the sample's bilinear patch (its base cell held
- *   fixed; the interpolant is only piecewise smooth).  Time order, [T][2].
+ *   derivatives taken inside the sample's interpolation patch (its base cell
+ *   held fixed: the bilinear interpolant is only piecewise smooth; the cosine
+ *   one is C^1, so there the result is the derivative itself).  Time order, [T][2].
+ *   Needs a plan built with MPI_BUILD_DERIV.
  *
  * mpi_batch_adjoint_step: c_out = c_in - taus[b] A^T s (s in time order;
  *   c_in may equal c_out).  taus is a host array of count values.

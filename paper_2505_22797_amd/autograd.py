@@ -32,13 +32,14 @@ class TrajectoryOperator:
     built (with the dK/dh tables) for the parameter values in use and cached by
     value."""
 
-    def __init__(self, ns, radii, rhos, nus, dtype=torch.float32, conv_mode="fft", cache=4):
+    def __init__(self, ns, radii, rhos, nus, dtype=torch.float32, conv_mode="fft", cache=4, interp="bilinear"):
         self.ns = [int(n) for n in ns]
         self.radii = [int(r) for r in radii]
         self.rhos = [r.to(dtype).contiguous() for r in rhos]
         self.nus = [v.to(dtype).contiguous() for v in nus]
         self.dtype = dtype
         self.conv_mode = conv_mode
+        self.interp = interp
         self.count = len(self.ns)
         self.rho_all = torch.cat([r.reshape(-1) for r in self.rhos])
         self.nu_all = torch.cat([v.reshape(-1) for v in self.nus])
@@ -57,7 +58,7 @@ class TrajectoryOperator:
         for b in range(B):
             amp = torch.tensor([axs[b], ays[b]], dtype=self.dtype, device=self.rhos[b].device)
             specs.append((self.ns[b], hs[b], self.radii[b], self.rhos[b] * amp, self.nus[b] * amp, self.conv_mode))
-        batch = mpik.Batch(specs, dtype=self.dtype, tune=False, deriv=True)
+        batch = mpik.Batch(specs, dtype=self.dtype, tune=False, deriv=True, interp=self.interp)
         self._cache[key] = batch
         self._order.append(key)
         while len(self._order) > self._cache_size:

@@ -331,6 +331,9 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_pass(const int* __restric
 }
 
 // Writes the sorted sample records: position i holds sample k = order[i].
+// The records carry the per-axis weight of the upper neighbour: the fraction
+// f itself (bilinear) or (1 - cos pi f)/2 (cosine), evaluated in float64; the
+// derivative tables get d w/d f = (pi/2) sin pi f.
 template <typename T>
 __global__ void k_place(const Prob* __restrict__ P, const int* __restrict__ order, const int* __restrict__ cell,
                         const double* __restrict__ frac, const T* __restrict__ v, char* __restrict__ plan) {
@@ -342,9 +345,22 @@ __global__ void k_place(const Prob* __restrict__ P, const int* __restrict__ orde
     if (q < 0) return;        // outside the hull: the build reports the error
     const int nb = p.nb;
     at<int2>(plan, p.o_sidx)[i] = make_int2((q % nb) | ((q / nb) << 16), k);
+    const double fx = frac[2 * k], fy = frac[2 * k + 1];
     vec4<T> e;
-    e.x = T(frac[2 * k]);
-    e.y = T(frac[2 * k + 1]);
+    vec2<T> d;
+    if (p.interp == 1) {
+        constexpr double kPi = 3.14159265358979323846;
+        e.x = T(0.5 * (1.0 - cos(kPi * fx)));
+        e.y = T(0.5 * (1.0 - cos(kPi * fy)));
+        d.x = T(0.5 * kPi * sin(kPi * fx));
+        d.y = T(0.5 * kPi * sin(kPi * fy));
+    } else {
+        e.x = T(fx);
+        e.y = T(fy);
+        d.x = T(1);
+        d.y = T(1);
+    }
+    if (p.o_dw) at<vec2<T>>(plan, p.o_dw)[i] = d;
     e.z = v[2 * k];
     e.w = v[2 * k + 1];
     at<vec4<T>>(plan, p.o_samp)[i] = e;

@@ -44,6 +44,8 @@ struct Prob {
     int32_t mode;      // 0 direct, 1 FFT
     int32_t taps_w;    // padded row length of the direct-path tap table
     int32_t slices;    // direct path: waves splitting the dy range of a tile
+    int32_t interp;    // 0 bilinear, 1 cosine (the weights in o_samp already applied)
+    int32_t pad0;
     int64_t t;         // samples
     double h;
     int64_t o_c;       // element offset of this problem's concentration in the caller's buffer
@@ -54,7 +56,9 @@ struct Prob {
     int64_t o_taps_dh;   // as o_taps for dK_h/dh (plans built for derivatives), else 0
     int64_t o_spec_dh;   // as o_spec for dK_h/dh, else 0
     int64_t o_tw;        // cx<T> [M]             e^{-2 pi i k / M}
-    int64_t o_samp;      // vec4<T> [T]           (fx, fy, vx, vy) in cell order
+    int64_t o_samp;      // vec4<T> [T]           (wx, wy, vx, vy) in cell order, w the upper-neighbour weight
+    int64_t o_dw;        // vec2<T> [T]           (dwx/dfx, dwy/dfy) in cell order (plans built for
+                         //                       derivatives, else 0; all ones when bilinear)
     int64_t o_sidx;      // int2 [T]              (base cell i0 | j0 << 16, time index), cell order
     int64_t o_binstart;  // int32 [nb*nb + 1]     first sample of every base cell
     int64_t o_err;       // int32 [4]             build error flags

@@ -165,7 +165,8 @@ __global__ void __launch_bounds__(256) k_gather_rows(const Prob* __restrict__ P,
                          at<vec2<T>>(work, p.w_ysort), at<vec2<T>>(work, p.w_res),
                          io.out0 ? io.out0 + p.o_s : nullptr, io.in0 ? io.in0 + p.o_s : nullptr,
                          io.out1 ? io.out1 + p.o_s : nullptr, io.out2 ? io.out2 + p.o_s : nullptr,
-                         io.f ? io.f + 9 * (p.o_s / 2) : nullptr, p.t, threadIdx.x, blockDim.x);
+                         io.f ? io.f + 9 * (p.o_s / 2) : nullptr, p.t,
+                         p.o_dw ? at<vec2<T>>(plan, p.o_dw) : nullptr, threadIdx.x, blockDim.x);
 }
 
 // Deterministic transpose sampling for one grid row into a field in global

@@ -310,6 +310,7 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
     const vec4<T>* samp = at<vec4<T>>(plan, p.o_samp);
     const int2* sidx = at<int2>(plan, p.o_sidx);
     const vec2<T>* ysort = at<vec2<T>>(work, p.w_ysort);
+    const vec2<T>* dw = p.o_dw ? at<vec2<T>>(plan, p.o_dw) : nullptr;
     GatherRecs<T, 4> first;
     gather_fetch<T, MODE, 4>(first, p0 + tid, p1, 4 * kWave, samp, sidx, ysort, in0);
     twr.store(sm.tw, tid);
@@ -329,7 +330,7 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
     }
     __syncthreads();
     gather_band<T, MODE, 4>(g0, g1, N, p0, p1, samp, sidx, ysort, at<vec2<T>>(work, p.w_res), out0, in0, out1, out2,
-                            f, p.t, tid, 4 * kWave, &first);
+                            f, p.t, dw, tid, 4 * kWave, &first);
 }
 
 // ----------------------------------------------------------------- adjoint ---

@@ -91,7 +91,7 @@ size_t scatter_rows_smem(int N, int elem) {
 }
 
 struct Shape {
-    int n, R, M, elem;
+    int n, R, M, elem, interp;
     int64_t T;
     bool fft_ok, direct_ok;
 };
@@ -104,8 +104,10 @@ int validate(const mpi_problem* d, Shape& sh) {
     if (d->radius < 0) return MPI_ERR_ARG;
     if (d->n_samples < 1 || d->n_samples >= kMaxSamples) return MPI_ERR_ARG;
     if (d->conv_mode < MPI_CONV_AUTO || d->conv_mode > MPI_CONV_FFT) return MPI_ERR_ARG;
-    if (d->interp != MPI_INTERP_BILINEAR || d->channels != MPI_CH_XY) return MPI_ERR_UNSUPPORTED;
+    if (d->interp != MPI_INTERP_BILINEAR && d->interp != MPI_INTERP_COSINE) return MPI_ERR_ARG;
+    if (d->channels != MPI_CH_XY) return MPI_ERR_UNSUPPORTED;
     sh.elem = d->dtype == MPI_F64 ? 8 : 4;
+    sh.interp = d->interp;
     sh.n = d->n;
     sh.R = std::min(d->radius, d->n - 1);
     sh.T = d->n_samples;
@@ -148,6 +150,7 @@ void layout_problem(const Shape& sh, int mode, bool both, bool deriv, size_t& po
     p.log2m = __builtin_ctz(M);
     p.taps_w = (W + 3) / 4 * 4;
     p.slices = 8;
+    p.interp = sh.interp;
     p.t = T;
     const bool dir = both ? sh.direct_ok : mode == 0;
     const bool fft = both ? sh.fft_ok : mode == 1;
@@ -159,6 +162,7 @@ void layout_problem(const Shape& sh, int mode, bool both, bool deriv, size_t& po
     if (deriv && dir) p.o_taps_dh = take(poff, size_t(3) * W * p.taps_w * e);
     if (deriv && fft) p.o_spec_dh = take(poff, size_t(3) * H * H * e);
     p.o_samp = take(poff, size_t(T) * 4 * e);
+    if (deriv) p.o_dw = take(poff, size_t(T) * 2 * e);
     p.o_sidx = take(poff, size_t(T) * 8);
     p.o_binstart = take(poff, (size_t(nb) * nb + 1) * 4);
     p.o_err = take(poff, 16);
@@ -1307,6 +1311,7 @@ int mpi_batch_traj_vjp(const mpi_plan* plan, const void* x, const void* y, void*
     int rc = check_call(plan, x, y, work, work_bytes);
     if (rc != MPI_OK) return rc;
     if (!g_r || !g_v || misaligned(g_r, plan->L.elem) || misaligned(g_v, plan->L.elem)) return MPI_ERR_ARG;
+    if (!plan->L.deriv) return MPI_ERR_UNSUPPORTED;
     if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
     char* w = static_cast<char*>(work);
     return plan->dtype == MPI_F64

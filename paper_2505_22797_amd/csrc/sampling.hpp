@@ -1,6 +1,7 @@
-// Sampling along the trajectory (bilinear interpolation of the three field
-// channels, contraction with the velocity: s_k = A[c](r_k) v_k, eq.
-// core:formula) and its exact transpose.  Both work on a band of grid rows
+// Sampling along the trajectory (interpolation of the three field channels
+// from the four surrounding cell centres with the per-axis weights stored in
+// the sample records, bilinear or cosine; contraction with the velocity:
+// s_k = A[c](r_k) v_k, eq. core:formula) and its exact transpose.  Both work on a band of grid rows
 // held in LDS by one work-group.
 //
 // The transpose is deterministic: samples are sorted by base cell at plan
@@ -21,9 +22,11 @@ namespace mpik {
 // MODE 1: s - y (y = ysort, cell order) to out_sorted[p].
 // MODE 3: s - y (y = in0, time order) to out0[k].
 // MODE 2: the gradients of <y, s> (y = in0, time order) with respect to the
-//         sample position and velocity, inside the bilinear patch:
+//         sample position and velocity, inside the interpolation patch:
 //         out0[k] = (y^T M(dG/dx) v, y^T M(dG/dy) v), out1[k] = M(G) y,
-//         with M(g) = [[g_xx, g_xy], [g_xy, g_yy]] and d/dx = (N/2) d/dfx.
+//         with M(g) = [[g_xx, g_xy], [g_xy, g_yy]] and
+//         d/dx = (N/2) (dwx/dfx) d/dwx with the slopes dw (plans built for
+//         derivatives; the derivative modes read them unconditionally).
 // MODE 4: s to out0[p] (cell order).
 // MODE 5: s - y (y = ysort) to out0[p], and the sampled field with its
 //         position gradient, nine planes f[q * fstride + p]:
@@ -73,7 +76,7 @@ template <typename T, int MODE, int U>
 __device__ __forceinline__ void gather_apply(const GatherRecs<T, U>& r, int base, int p1, int nthreads,
                                              const T* g0, const T* g1, int N, vec2<T>* __restrict__ out_sorted,
                                              T* __restrict__ out0, T* __restrict__ out1, T* __restrict__ out2,
-                                             T* __restrict__ f, int64_t fstride) {
+                                             T* __restrict__ f, int64_t fstride, const vec2<T>* __restrict__ dw) {
     constexpr bool GRAD = MODE == 2 || MODE == 5 || MODE == 6;
     const T inv_d = T(0.5) * T(N);
 #pragma unroll
@@ -82,6 +85,8 @@ __device__ __forceinline__ void gather_apply(const GatherRecs<T, U>& r, int base
         if (p >= p1) break;
         const int i0 = r.id[u].x & 0xffff;
         const T fx = r.e[u].x, fy = r.e[u].y, gx = T(1) - fx, gy = T(1) - fy;
+        vec2<T> sl;                       // weight slopes (read here: kept out of the prefetched records)
+        if (GRAD) sl = dw[p];
         T g[3], dx[3], dy[3];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
@@ -91,8 +96,8 @@ __device__ __forceinline__ void gather_apply(const GatherRecs<T, U>& r, int base
             const T hi = gx * a01 + fx * a11;
             g[ch] = gy * lo + fy * hi;
             if (GRAD) {
-                dx[ch] = inv_d * (gy * (a10 - a00) + fy * (a11 - a01));
-                dy[ch] = inv_d * (gx * (a01 - a00) + fx * (a11 - a10));
+                dx[ch] = (inv_d * sl.x) * (gy * (a10 - a00) + fy * (a11 - a01));
+                dy[ch] = (inv_d * sl.y) * (gx * (a01 - a00) + fx * (a11 - a10));
             }
         }
         const T vx = r.e[u].z, vy = r.e[u].w;
@@ -166,17 +171,18 @@ __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int
                                             const vec2<T>* __restrict__ ysort, vec2<T>* __restrict__ out_sorted,
                                             T* __restrict__ out0, const T* __restrict__ in0, T* __restrict__ out1,
                                             T* __restrict__ out2, T* __restrict__ f, int64_t fstride,
-                                            int tid, int nthreads, const GatherRecs<T, U>* first = nullptr) {
+                                            const vec2<T>* __restrict__ dw, int tid, int nthreads,
+                                            const GatherRecs<T, U>* first = nullptr) {
     int base = p0 + tid;
     if (first) {
         if (base < p1) gather_apply<T, MODE, U>(*first, base, p1, nthreads, g0, g1, N, out_sorted, out0, out1, out2, f,
-                                                fstride);
+                                                fstride, dw);
         base += U * nthreads;
     }
     for (; base < p1; base += U * nthreads) {
         GatherRecs<T, U> r;
         gather_fetch<T, MODE, U>(r, base, p1, nthreads, samp, sidx, ysort, in0);
-        gather_apply<T, MODE, U>(r, base, p1, nthreads, g0, g1, N, out_sorted, out0, out1, out2, f, fstride);
+        gather_apply<T, MODE, U>(r, base, p1, nthreads, g0, g1, N, out_sorted, out0, out1, out2, f, fstride, dw);
     }
 }
 

@@ -18,6 +18,7 @@ MPI_OK, MPI_ERR_ARG, MPI_ERR_DOMAIN, MPI_ERR_WORKSPACE = 0, -1, -2, -3
 MPI_ERR_DTYPE, MPI_ERR_HIP, MPI_ERR_UNSUPPORTED = -4, -5, -6
 MPI_F32, MPI_F64 = 0, 1
 CONV_MODES = {"auto": 0, "direct": 1, "fft": 2}
+INTERPS = {"bilinear": 0, "cosine": 1}
 
 EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
            "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
@@ -132,12 +133,12 @@ def _dtype_code(dt: torch.dtype) -> int:
 
 def problem(n: int, h: float, radius: int, r: torch.Tensor | None, v: torch.Tensor | None,
             n_samples: int | None = None, dtype: torch.dtype = torch.float32,
-            conv_mode: str = "auto") -> Problem:
+            conv_mode: str = "auto", interp: str = "bilinear") -> Problem:
     p = Problem()
     p.n, p.h, p.radius = int(n), float(h), int(radius)
     p.dtype = _dtype_code(r.dtype if r is not None else dtype)
     p.conv_mode = CONV_MODES[conv_mode]
-    p.interp = 0
+    p.interp = INTERPS[interp]
     p.channels = 0
     p.n_samples = int(r.shape[0] if r is not None else n_samples)
     p.r = r.data_ptr() if r is not None else None
@@ -156,7 +157,7 @@ class Plan:
     device memory owned by this object, plus a reusable work buffer."""
 
     def __init__(self, n: int, h: float, radius: int, r: torch.Tensor, v: torch.Tensor,
-                 conv_mode: str = "auto", stream=None):
+                 conv_mode: str = "auto", stream=None, interp: str = "bilinear"):
         if not (r.is_cuda and v.is_cuda):
             raise ValueError("r and v must be device tensors")
         if r.dtype != v.dtype or r.shape != v.shape or r.ndim != 2 or r.shape[1] != 2:
@@ -165,7 +166,8 @@ class Plan:
         v = v.contiguous()
         self.n, self.h, self.dtype, self.device = int(n), float(h), r.dtype, r.device
         self.n_samples = int(r.shape[0])
-        prob = problem(n, h, radius, r, v, conv_mode=conv_mode)
+        self.interp = interp
+        prob = problem(n, h, radius, r, v, conv_mode=conv_mode, interp=interp)
         pb, wb = plan_bytes(prob)
         self.plan_mem = torch.empty(pb, dtype=torch.uint8, device=r.device)
         self.work = torch.empty(wb, dtype=torch.uint8, device=r.device)
@@ -312,21 +314,24 @@ class Batch:
     concatenated in one flat tensor each (see `c_offsets`, `s_offsets`)."""
 
     def __init__(self, specs, dtype=torch.float32, tune: bool = True, columns: str | None = None,
-                 deriv: bool = False, stream=None):
-        """specs: list of (n, h, radius, r, v[, conv_mode]) with r, v device (T, 2).
+                 deriv: bool = False, stream=None, interp: str = "bilinear"):
+        """specs: list of (n, h, radius, r, v[, conv_mode[, interp]]) with r, v device (T, 2).
         columns: None (by batch size), "split" or "wave": shape of the column-FFT kernels.
-        deriv: also build the dK/dh tables (for forward_dh)."""
+        deriv: also build the dK/dh tables (for forward_dh) and the weight slopes.
+        interp: "bilinear" or "cosine", for specs that do not name one."""
         keep = []
         arr = (Problem * len(specs))()
         for i, sp in enumerate(specs):
             n, h, radius, r, v = sp[:5]
             mode = sp[5] if len(sp) > 5 else "auto"
+            ip = sp[6] if len(sp) > 6 else interp
             r = r.contiguous()
             v = v.contiguous()
             if r.dtype != dtype or v.dtype != dtype:
                 raise ValueError("every problem of a batch shares the dtype")
             keep += [r, v]
-            arr[i] = problem(n, h, radius, r, v, conv_mode=mode)
+            arr[i] = problem(n, h, radius, r, v, conv_mode=mode, interp=ip)
+        self.interps = [sp[6] if len(sp) > 6 else interp for sp in specs]
         self.count = len(specs)
         self.dtype = dtype
         self.device = specs[0][3].device

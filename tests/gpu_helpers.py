@@ -27,13 +27,15 @@ class Case:
     """One problem prepared for both sides: inputs rounded once, the oracle
     model on the rounded values, and the GPU plan on the same values."""
 
-    def __init__(self, n, h, radius, r, v, c, dtype=torch.float32, conv_mode="auto", method="auto"):
+    def __init__(self, n, h, radius, r, v, c, dtype=torch.float32, conv_mode="auto", method="auto",
+                 interp="bilinear"):
         self.n, self.h, self.radius, self.dtype = n, h, radius, dtype
         self.r = rounded(r, dtype)
         self.v = rounded(v, dtype)
         self.c = rounded(c, dtype)
-        self.model = O.Model(n, h, radius, self.r, self.v, method=method)
-        self.plan = mpik.Plan(n, h, radius, dev(self.r, dtype), dev(self.v, dtype), conv_mode=conv_mode)
+        self.model = O.Model(n, h, radius, self.r, self.v, method=method, interp=interp)
+        self.plan = mpik.Plan(n, h, radius, dev(self.r, dtype), dev(self.v, dtype), conv_mode=conv_mode,
+                              interp=interp)
 
     def t(self, a):
         return dev(a, self.dtype)
@@ -44,6 +46,6 @@ class Case:
         return x.double().cpu().numpy()
 
 
-def case_from(problem: S.Problem, dtype=torch.float32, conv_mode="auto", radius=None):
+def case_from(problem: S.Problem, dtype=torch.float32, conv_mode="auto", radius=None, interp="bilinear"):
     return Case(problem.n, problem.h, problem.radius if radius is None else radius,
-                problem.traj.r, problem.traj.v, problem.c, dtype=dtype, conv_mode=conv_mode)
+                problem.traj.r, problem.traj.v, problem.c, dtype=dtype, conv_mode=conv_mode, interp=interp)

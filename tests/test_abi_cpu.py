@@ -66,13 +66,25 @@ def test_plan_bytes_valid(mpik):
 
 @pytest.mark.parametrize("field,value,code", [
     ("n", 1, -1), ("n", 2000, -1), ("h", 0.0, -1), ("h", float("nan"), -1), ("radius", -1, -1),
-    ("n_samples", 0, -1), ("dtype", 7, -4), ("conv_mode", 9, -1), ("interp", 1, -6), ("channels", 1, -6),
+    ("n_samples", 0, -1), ("dtype", 7, -4), ("conv_mode", 9, -1), ("interp", 2, -1), ("interp", -1, -1),
+    ("channels", 1, -6),
 ])
 def test_plan_bytes_rejects(mpik, field, value, code):
     p = _prob(mpik)
     setattr(p, field, value)
     pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
     assert mpik.lib().mpi_plan_bytes(ctypes.byref(p), ctypes.byref(pb), ctypes.byref(wb)) == code
+
+
+def test_both_interpolators_accepted(mpik):
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    sizes = []
+    for interp in (0, 1):
+        p = _prob(mpik)
+        p.interp = interp
+        assert mpik.lib().mpi_plan_bytes(ctypes.byref(p), ctypes.byref(pb), ctypes.byref(wb)) == 0
+        sizes.append((pb.value, wb.value))
+    assert sizes[0] == sizes[1]
 
 
 def test_unsupported_sizes(mpik):

@@ -29,8 +29,9 @@ class GradCase:
     """Problems with unit trajectory shapes, amplitudes and phantoms, prepared
     for both sides."""
 
-    def __init__(self, shapes, dtype, seed=0, amp=(0.85, 0.8)):
+    def __init__(self, shapes, dtype, seed=0, amp=(0.85, 0.8), interp="bilinear"):
         self.dtype = dtype
+        self.interp = interp
         self.items = []
         for i, (n, R, t, mode) in enumerate(shapes):
             tr = S.lissajous(t, ax=1.0, ay=1.0)
@@ -41,12 +42,12 @@ class GradCase:
             v = (nu.astype(NP[dtype]) * NP[dtype](np.array([ax, ay]))).astype(np.float64)
             h = S.h_fwhm2(n) * (1.0 + 0.1 * i)
             self.items.append(dict(n=n, R=R, t=t, mode=mode, rho=rho, nu=nu, ax=ax, ay=ay, r=r, v=v, h=h,
-                                   model=O.Model(n, h, R, r, v),
+                                   model=O.Model(n, h, R, r, v, interp=interp),
                                    c=rounded(S.blobs(n, seed + i), dtype)))
         self.op = AG.TrajectoryOperator([it["n"] for it in self.items], [it["R"] for it in self.items],
                                         [dev(it["rho"], dtype) for it in self.items],
                                         [dev(it["nu"], dtype) for it in self.items], dtype=dtype,
-                                        conv_mode=self.items[0]["mode"])
+                                        conv_mode=self.items[0]["mode"], interp=interp)
         self.h = torch.tensor([it["h"] for it in self.items], dtype=torch.float64)
         self.ax = torch.tensor([it["ax"] for it in self.items], dtype=torch.float64)
         self.ay = torch.tensor([it["ay"] for it in self.items], dtype=torch.float64)
@@ -70,12 +71,14 @@ SHAPES_FFT = [(32, 7, 2500, "fft"), (48, 31, 5000, "fft"), (40, 12, 3001, "fft")
 
 
 # the float64 direct path keeps its input tile in LDS, which limits it to R <= 30
-@pytest.mark.parametrize("dtype,shapes", [
-    (torch.float32, SHAPES), (torch.float64, SHAPES), (torch.float32, SHAPES_WIDE),
-    (torch.float32, SHAPES_FFT), (torch.float64, SHAPES_FFT)],
-    ids=["direct-f32", "direct-f64", "direct63-f32", "fft-f32", "fft-f64"])
-def test_derivative_blocks_match_oracle(dtype, shapes):
-    gc = GradCase(shapes, dtype)
+@pytest.mark.parametrize("dtype,shapes,interp", [
+    (torch.float32, SHAPES, "bilinear"), (torch.float64, SHAPES, "bilinear"), (torch.float32, SHAPES_WIDE, "bilinear"),
+    (torch.float32, SHAPES_FFT, "bilinear"), (torch.float64, SHAPES_FFT, "bilinear"),
+    (torch.float32, SHAPES_FFT, "cosine"), (torch.float64, SHAPES, "cosine"), (torch.float64, SHAPES_FFT, "cosine")],
+    ids=["direct-f32", "direct-f64", "direct63-f32", "fft-f32", "fft-f64", "fft-f32-cos", "direct-f64-cos",
+         "fft-f64-cos"])
+def test_derivative_blocks_match_oracle(dtype, shapes, interp):
+    gc = GradCase(shapes, dtype, interp=interp)
     plan = gc.plan()
     tol = APPLY_TOL[dtype]
     rng = np.random.default_rng(5)
@@ -198,20 +201,23 @@ def _unrolled_ref(it, s, tau, c_true, n_iter, sigma, **kw):
     a.update(kw)
     return O.unrolled_gradients(it["n"], a["h"], it["R"], a["ax"], a["ay"], it["rho"], it["nu"], s, c_true,
                                 np.zeros((it["n"], it["n"])), tau, n_iter, sigma_px=sigma,
-                                frozen=it["model"].cells())
+                                frozen=it["model"].cells(), interp=it["model"].interp)
 
 
 SHAPES_MIXED = [(32, 7, 2500, "auto"), (48, 31, 5000, "auto"), (40, 12, 3001, "auto")]   # direct + FFT
 
 
-@pytest.mark.parametrize("dtype,sigma,shapes", [
-    (torch.float32, None, SHAPES_FFT), (torch.float32, 0.5, SHAPES_FFT), (torch.float64, 0.5, SHAPES_FFT),
-    (torch.float32, 0.5, SHAPES), (torch.float64, None, SHAPES), (torch.float32, 0.5, SHAPES_MIXED)],
-    ids=["fft-f32", "fft-f32-den", "fft-f64-den", "direct-f32-den", "direct-f64", "mixed-f32-den"])
-def test_unrolled_gradients_match_oracle(dtype, sigma, shapes):
+@pytest.mark.parametrize("dtype,sigma,shapes,interp", [
+    (torch.float32, None, SHAPES_FFT, "bilinear"), (torch.float32, 0.5, SHAPES_FFT, "bilinear"),
+    (torch.float64, 0.5, SHAPES_FFT, "bilinear"), (torch.float32, 0.5, SHAPES, "bilinear"),
+    (torch.float64, None, SHAPES, "bilinear"), (torch.float32, 0.5, SHAPES_MIXED, "bilinear"),
+    (torch.float32, 0.5, SHAPES_MIXED, "cosine"), (torch.float64, 0.5, SHAPES_MIXED, "cosine")],
+    ids=["fft-f32", "fft-f32-den", "fft-f64-den", "direct-f32-den", "direct-f64", "mixed-f32-den",
+         "mixed-f32-den-cos", "mixed-f64-den-cos"])
+def test_unrolled_gradients_match_oracle(dtype, sigma, shapes, interp):
     """K = 7 with checkpoints every 3 (a ragged last segment), three problems
     of different sizes in one batch."""
-    gc = GradCase(shapes, dtype)
+    gc = GradCase(shapes, dtype, interp=interp)
     if shapes is SHAPES_MIXED:
         assert {inf["conv_mode"] for inf in gc.plan().info} == {"direct", "fft"}
     s_list, taus, truths = _unrolled_setup(gc)
@@ -306,3 +312,40 @@ def test_differentiation_workload_matches_oracle_and_finite_differences():
             g1 = (it["rho"][:, k] * (val + e) + 1.0) * (n / 2.0) - 0.5
             crossed += int(np.sum(np.floor(g0) != np.floor(g1)))
     print(f"samples whose base cell a +1e-6 relative amplitude step moves: {crossed}")
+
+
+def test_cosine_unrolled_gradients_match_unfrozen_finite_differences():
+    """Under the cosine interpolator the signal is C^1 in the sample
+    positions, so central differences of the oracle's loss taken without
+    freezing the base cells (samples may change cells within the step) agree
+    with the library's gradients; 64^2, 15x15 window, K = 6, every 4."""
+    dtype = torch.float64
+    gc = GradCase([(64, 15, 9000, "fft")], dtype, interp="cosine")
+    s_list, taus, truths = _unrolled_setup(gc)
+    K, sigma = 6, 0.5
+    _, _, g_h, g_ax, g_ay = _unrolled_gpu(gc, s_list, taus, truths, K, sigma, every=4)
+    it = gc.items[0]
+
+    def loss(**kw):
+        a = dict(h=it["h"], ax=it["ax"], ay=it["ay"])
+        a.update(kw)
+        scale = np.array([a["ax"], a["ay"]])
+        M = O.Model(it["n"], a["h"], it["R"], it["rho"] * scale, it["nu"] * scale, interp="cosine")
+        c = O.iterate(M, s_list[0], np.zeros((it["n"], it["n"])), taus[0], K, sigma_px=sigma, radius=2)
+        return float(np.sum((c - truths[0]) ** 2))
+
+    crossed = 0
+    for name, got in (("h", g_h[0]), ("ax", g_ax[0]), ("ay", g_ay[0])):
+        val = it[name]
+        # a step across a node meets a jump of the second derivative, which
+        # makes the difference first order in the step there: 1e-5 relative
+        # keeps that error near 1e-6 while samples still change cells
+        e = 1e-5 * val
+        fd = (loss(**{name: val + e}) - loss(**{name: val - e})) / (2 * e)
+        assert _close(got, fd, 1e-5), (name, got, fd)
+        if name != "h":
+            k = 0 if name == "ax" else 1
+            g0 = (it["rho"][:, k] * (val - e) + 1.0) * (it["n"] / 2.0) - 0.5
+            g1 = (it["rho"][:, k] * (val + e) + 1.0) * (it["n"] / 2.0) - 0.5
+            crossed += int(np.sum(np.floor(g0) != np.floor(g1)))
+    assert crossed > 0, crossed        # some samples change cells within the steps

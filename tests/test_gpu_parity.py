@@ -220,3 +220,98 @@ def test_graph_replay_matches_eager(gpu):
         torch.cuda.synchronize()
         out.append(c.clone())
     assert torch.equal(out[0], out[1]) and torch.equal(out[1], out[2])
+
+
+# ------------------------------------------------------- cosine interpolation --
+def _interp_gap(cs):
+    """Relative gap between the cosine and the bilinear oracle outputs: the
+    parity bar must be far below it for the test to tell the two apart."""
+    other = O.Model(cs.n, cs.h, cs.radius, cs.r, cs.v, interp="bilinear")
+    return rel_l2(other.forward(cs.c), cs.model.forward(cs.c))
+
+
+@pytest.mark.parametrize("n,radius,t,conv_mode", [
+    (37, 9, 3001, "direct"), (37, 9, 3001, "fft"), (61, 60, 2500, "fft"), (20, 3, 999, "direct")])
+def test_cosine_f64_apply(gpu, n, radius, t, conv_mode):
+    tr = S.lissajous(t, ax=0.85, ay=0.8)
+    cs = Case(n, S.h_fwhm2(n) * 1.3, radius, tr.r, tr.v, S.blobs(n, 7), torch.float64, conv_mode, interp="cosine")
+    assert _interp_gap(cs) > 1e4 * F64_APPLY
+    _check_apply(cs, F64_APPLY, seed=n)
+
+
+@pytest.mark.parametrize("n,radius,t,conv_mode", [
+    (37, 7, 3001, "direct"), (128, 31, 53856, "direct"), (128, 31, 53856, "fft")])
+def test_cosine_f32_apply(gpu, n, radius, t, conv_mode):
+    tr = S.lissajous(t)
+    cs = Case(n, S.h_fwhm2(n), radius, tr.r, tr.v, S.ellipses_and_line(n, 0), torch.float32, conv_mode,
+              interp="cosine")
+    assert _interp_gap(cs) > 20 * F32_APPLY
+    _check_apply(cs, F32_APPLY, seed=t)
+
+
+def test_cosine_headline_shape_apply(gpu):
+    """256x256, 53,856 samples, full-size kernel, cosine interpolation."""
+    cs = case_from(S.headline(), torch.float32, interp="cosine")
+    assert cs.plan.conv_mode == "fft" and cs.plan.fft_size == 512 and cs.plan.radius == 255
+    assert _interp_gap(cs) > 20 * F32_APPLY
+    _check_apply(cs, F32_APPLY, seed=5)
+
+
+def test_cosine_nodes_and_hull(gpu):
+    """Samples on cell centres (weights exactly 0 or 1), edge midpoints
+    (weight 1/2) and the hull, float64."""
+    n = 32
+    x = S.centres(n)
+    d = 2.0 / n
+    rng = np.random.default_rng(21)
+    nodes = np.stack([x[rng.integers(0, n, 300)], x[rng.integers(0, n, 300)]], 1)
+    mids = np.stack([x[rng.integers(0, n - 1, 300)] + d / 2, x[rng.integers(0, n, 300)]], 1)
+    hull = np.array([[x[0], x[0]], [x[-1], x[-1]], [x[0], x[-1]], [x[-1], x[0]]])
+    r = np.vstack([nodes, mids, mids[:, ::-1], hull])
+    v = rng.standard_normal(r.shape)
+    for mode in ("direct", "fft"):
+        cs = Case(n, 0.05, 6, r, v, S.blobs(n, 2), torch.float64, mode, interp="cosine")
+        _check_apply(cs, F64_APPLY, seed=2)
+        # at these points the two interpolators coincide
+        bil = O.Model(n, 0.05, 6, cs.r, cs.v).forward(cs.c)
+        assert rel_l2(Case.host(cs.plan.forward(cs.t(cs.c))), bil) <= F64_APPLY
+
+
+def test_mixed_interpolators_in_one_batch(gpu):
+    """The interpolator is chosen per problem: bilinear and cosine problems,
+    direct and FFT, share every launch of a batch."""
+    shapes = [(24, 5, 3000, "direct", "cosine"), (33, 12, 5000, "fft", "bilinear"), (48, 31, 9000, "fft", "cosine"),
+              (40, 9, 4000, "direct", "bilinear")]
+    specs, models, cs_ = [], [], []
+    for i, (n, R, t, mode, interp) in enumerate(shapes):
+        tr = S.lissajous(t, ax=0.85, ay=0.8 + 0.02 * i)
+        r, v = (np.asarray(a, dtype=np.float32).astype(np.float64) for a in (tr.r, tr.v))
+        h = S.h_fwhm2(n) * (0.9 + 0.05 * i)
+        specs.append((n, h, R, torch.tensor(r, dtype=torch.float32, device="cuda"),
+                      torch.tensor(v, dtype=torch.float32, device="cuda"), mode, interp))
+        models.append(O.Model(n, h, R, r, v, interp=interp))
+        cs_.append(np.asarray(S.blobs(n, 30 + i), dtype=np.float32).astype(np.float64))
+    batch = mpik.Batch(specs, tune=False)
+    c_all = torch.cat([torch.tensor(c, dtype=torch.float32, device="cuda").reshape(-1) for c in cs_])
+    s_all = batch.forward(c_all)
+    rng = np.random.default_rng(3)
+    ys = [np.asarray(rng.standard_normal((sp[3].shape[0], 2)), dtype=np.float32).astype(np.float64) for sp in specs]
+    g_all = batch.adjoint(torch.cat([torch.tensor(y, dtype=torch.float32, device="cuda").reshape(-1) for y in ys]))
+    torch.cuda.synchronize()
+    for b, (M, c, y) in enumerate(zip(models, cs_, ys)):
+        s = batch.s_views(s_all)[b].double().cpu().numpy()
+        g = batch.c_views(g_all)[b].double().cpu().numpy()
+        assert rel_l2(s, M.forward(c)) <= F32_APPLY, b
+        assert rel_l2(g, M.adjoint(y)) <= F32_APPLY, b
+
+
+def test_traj_vjp_needs_a_derivative_plan(gpu):
+    tr = S.lissajous(500, ax=0.8, ay=0.8)
+    r = torch.tensor(tr.r, dtype=torch.float32, device="cuda")
+    v = torch.tensor(tr.v, dtype=torch.float32, device="cuda")
+    batch = mpik.Batch([(16, 0.1, 5, r, v, "direct", "cosine")], tune=False)
+    x = torch.zeros(256, dtype=torch.float32, device="cuda")
+    y = torch.zeros(1000, dtype=torch.float32, device="cuda")
+    with pytest.raises(mpik.MpiError) as ei:
+        batch.traj_vjp(x, y)
+    assert ei.value.status == mpik.MPI_ERR_UNSUPPORTED
