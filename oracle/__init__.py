@@ -16,4 +16,7 @@ closed forms, mpmath, brute force, library special cases or invariants; the
 paper prints no operator values, so no value of the paper itself pins them.
 """
 from .mpi_model import *  # noqa: F401,F403
-from .mpi_model import __all__  # noqa: F401
+from .deconv import *  # noqa: F401,F403
+from . import deconv as _deconv, mpi_model as _mpi_model
+
+__all__ = list(_mpi_model.__all__) + list(_deconv.__all__)
