@@ -118,6 +118,9 @@ def main() -> int:
     ap.add_argument("--no-iter", action="store_true")
     ap.add_argument("--no-window", action="store_true")
     ap.add_argument("--no-cosine", action="store_true")
+    ap.add_argument("--no-deconv", action="store_true")
+    ap.add_argument("--deconv-only", action="store_true",
+                    help="only the deconvolution workload (for a kernel trace of its kernels)")
     ap.add_argument("--grad-only", action="store_true",
                     help="only the differentiation workload (for a kernel trace of its kernels)")
     ap.add_argument("--profile-batch", action="store_true",
@@ -140,6 +143,9 @@ def main() -> int:
     dev = torch.device("cuda:0")
     if args.grad_only:
         print(json.dumps({"differentiation": differentiation(S, dev)}))
+        return 0
+    if args.deconv_only:
+        print(json.dumps({"deconvolution": deconvolution(mpik, S, dev, False)}))
         return 0
     r = torch.tensor(S.to_f32(P.traj.r), dtype=torch.float32, device=dev)
     v = torch.tensor(S.to_f32(P.traj.v), dtype=torch.float32, device=dev)
@@ -228,6 +234,8 @@ def main() -> int:
         out["differentiation"] = differentiation(S, dev)
     if not args.no_iter:
         out["iteration_configs"] = iteration_configs(mpik, S, dev, not args.no_cpu_baseline)
+    if not args.no_deconv:
+        out["deconvolution"] = deconvolution(mpik, S, dev, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_seconds)
     print(json.dumps(out))
@@ -297,6 +305,82 @@ def cosine_line(mpik, P, r, v, c1, B, args):
     del batch, c_all, s_all, g_all
     torch.cuda.empty_cache()
     return out
+
+
+def deconvolution(mpik, S, dev, with_oracle, count=64, n_it=9, snr_db=30.0):
+    """The Deconvolution Stage at the headline grid: `count` problems of
+    256^2 with the full trace kernel (R = 255, FFT with M = 512), ZeroShot-PnP
+    with ten passes, nu0 = 1e-5, CG tolerance 1e-3, 5% trimming and the
+    Gaussian stand-in for the denoiser, float32.  The trace images
+    u = C rho + noise (ellipse-and-line phantoms, 30 dB) are made on the
+    device before the timed region.  One problem per call is timed too, and
+    the float64 oracle runs the same deconvolution of one problem on the host
+    (one thread) as the CPU reference."""
+    import numpy as np
+    import torch
+    P = S.headline()
+    n, R, h = P.n, 255, P.h
+    tr = S.lissajous(64, ax=0.8, ay=0.8)                      # the plan's samples play no part
+    r = torch.tensor(S.to_f32(tr.r), dtype=torch.float32, device=dev)
+    v = torch.tensor(S.to_f32(tr.v), dtype=torch.float32, device=dev)
+    kw = dict(n_it=n_it, nu0=1e-5, tol=1e-3, max_iter=10000, clip_pct=5.0, sigma_px=0.5, radius=2)
+
+    def inputs(B):
+        batch = mpik.Batch([(n, h, R, r, v, "fft")] * B, tune=False)
+        rho = np.stack([S.ellipses_and_line(n, 100 + b) for b in range(B)])
+        clean = batch.trace_conv(torch.tensor(rho, dtype=torch.float32, device=dev).reshape(-1))
+        clean = clean.double().cpu().numpy().reshape(B, n, n)
+        u = np.stack([S.add_noise(clean[b], snr_db, seed=b) for b in range(B)])
+        return batch, torch.tensor(S.to_f32(u), dtype=torch.float32, device=dev).reshape(-1), rho
+
+    def timed(batch, u, reps):
+        batch.pnp(u, **kw)                                    # warm: workspace, code paths
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            out, info = batch.pnp(u, **kw)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps, out, info
+
+    batch, u, rho = inputs(count)
+    ms, out, info = timed(batch, u, 2)
+    steps = np.array(info["cg_steps"])                        # [problem][pass]
+    rec_err = [float(np.linalg.norm(x.double().cpu().numpy().reshape(n, n) - rho[b]) / np.linalg.norm(rho[b]))
+               for b, x in enumerate(batch.c_views(out))]
+    rec = {"workload": f"deconvolution_256: {count} x 256^2 trace images, R=255 (FFT, M=512), "
+                       f"ZeroShot-PnP {n_it + 1} passes, nu0=1e-5, CG tol 1e-3, 5% trim, Gaussian stand-in",
+           "problems": count, "grid": n, "radius": batch.info[0]["radius"], "fft_size": batch.info[0]["fft_size"],
+           "passes": n_it + 1, "dtype": "f32", "ms": round(ms, 3),
+           "deconvolutions_per_s": round(count * 1e3 / ms, 2),
+           "cg_steps_per_problem": round(float(steps.sum(axis=1).mean()), 1),
+           "cg_steps_max_pass": int(steps.max()),
+           "ms_per_batched_cg_step": round(ms / float(steps.max(axis=0).sum()), 4),
+           "relative_error_to_phantom": round(float(np.mean(rec_err)), 4)}
+    del batch, u
+    b1, u1, _ = inputs(1)
+    ms1, _, info1 = timed(b1, u1, 3)
+    rec["single_problem"] = {"ms": round(ms1, 3), "deconvolutions_per_s": round(1e3 / ms1, 2),
+                             "cg_steps": int(np.sum(info1["cg_steps"][0]))}
+    if with_oracle:
+        try:
+            from threadpoolctl import threadpool_limits
+            limiter = threadpool_limits(1)
+        except Exception:
+            limiter = None
+        import oracle as O
+        u0 = u1.double().cpu().numpy().reshape(n, n)
+        t0 = time.perf_counter()
+        O.zeroshot_pnp(u0, h, R, n_it, 1e-5, tol=1e-3, max_iter=10000, clip_pct=5.0, sigma_px=0.5, radius_d=2)
+        dt = time.perf_counter() - t0
+        if limiter is not None:
+            limiter.restore_original_limits()
+        rec["oracle_deconvolutions_per_s"] = round(1.0 / dt, 4)
+        rec["oracle_sample"] = "one 256^2 problem, the same ten passes, float64 numpy on one host thread"
+    del b1, u1
+    torch.cuda.empty_cache()
+    return rec
 
 
 def iteration_configs(mpik, S, dev, with_oracle, oracle_seconds=3.0):

@@ -262,6 +262,71 @@ int mpi_batch_unrolled_vjp(const mpi_plan* plan, const void* s_all, const void* 
                            void* gbar_all, double* g_h, void* g_r_all, void* g_v_all, void* work,
                            size_t work_bytes, void* vjp_work, size_t vjp_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------ deconvolution --
+ * The Deconvolution Stage (Section "Deconvolution Stage", Algorithm
+ * "ZeroShot-PnP", Section "Denoiser Artifact Reduction") on the grids of a
+ * built plan; the plan's samples are not used.  Buffers are concentration-
+ * shaped and concatenated like c_all; dwork is caller-owned device memory of
+ * at least mpi_batch_deconv_bytes(plan) bytes, 256-byte aligned, shared by
+ * the calls below (none of them keeps anything in it between calls).
+ *
+ * mpi_batch_trace_conv: y_b = C_b x_b, the convolution with delta^2 kappa_h,
+ *   kappa_h = tr K_h the trace kernel (eq. kernel:trace), on the problem's
+ *   window and path: the trace of the operator's field (eq.
+ *   convolution:trace).  C_b is symmetric.  x != y.  Enqueued on `stream`.
+ *
+ * mpi_batch_cg: for every problem, conjugate gradients on
+ *   (C_b^T C_b + nus[b] I) x_b = rhs_b started from x_b = 0 (the normal
+ *   equations of the Tikhonov sub-step, eq. dec:sub:tik); a problem stops
+ *   once its recursively updated residual meets |r| <= tol |rhs_b| (tested
+ *   before every step) or after max_iter steps.  nus: host array of count
+ *   values >= 0; iters: host array of count entries for the steps taken (may
+ *   be NULL).  rhs != x.  Synchronises `stream`: the host polls the stop flags
+ *   between batches of steps.
+ *
+ * mpi_batch_trim_sigma: for every problem, when pct >= 0 the values of x_b
+ *   below their pct-th percentile (linear interpolation between the two
+ *   neighbouring order statistics) are raised to it (in place; q[b] receives
+ *   the percentile when q is not NULL), then sigma[b] = sqrt of the
+ *   population variance of x_b over its pixels (the noise estimate).  q and
+ *   sigma are host arrays of count doubles (either may be NULL).  pct > 100
+ *   is an error.  Synchronises `stream`.
+ *
+ * mpi_batch_pnp: the ZeroShot-PnP deconvolution of the trace images u_b into
+ *   rho_b: passes k = 0 .. n_it of
+ *     rho_1 = the CG of mpi_batch_cg on (C^T C + nu_k I) rho_1 = C u + nu_k rho_2,
+ *     trimming of rho_1 below its clip_percentile-th percentile,
+ *     sigma_{k+1} = sqrt(Var rho_1), lambda = nu0 sigma_1^2 (first pass),
+ *     rho_2 = D(rho_1), nu_{k+1} = lambda / sigma_{k+1}^2 (kept if sigma = 0),
+ *   from rho_2 = 0 and nu_0 = nu0; rho receives the last rho_2.  D is the
+ *   Gaussian of mpi_batch_denoise standing in for the learned denoiser
+ *   (identity when denoise_sigma_px <= 0).  cg_iters, sigmas and nus are host
+ *   arrays of (n_it + 1) * count entries, pass-major, for the steps, noise
+ *   estimates and Tikhonov weights of every pass (each may be NULL).  u != rho.
+ *   Synchronises `stream`. */
+typedef struct {
+    int32_t n_it;              /* passes k = 0 .. n_it, n_it >= 0                  */
+    int32_t cg_max_iter;       /* CG steps per pass at most, >= 0                  */
+    double nu0;                /* starting Tikhonov weight, > 0                     */
+    double cg_tol;             /* relative residual of the CG stop rule, >= 0       */
+    double clip_percentile;    /* trimming percentile in [0, 100]; < 0: no trimming */
+    double denoise_sigma_px;   /* Gaussian stand-in, pixels; <= 0: identity         */
+    int32_t denoise_radius;    /* 0 .. 8 when the Gaussian is on                    */
+    int32_t reserved;
+} mpi_pnp_params;
+
+int mpi_batch_deconv_bytes(const mpi_plan* plan, size_t* bytes);
+int mpi_batch_trace_conv(const mpi_plan* plan, const void* x_all, void* y_all, void* work, size_t work_bytes,
+                         hipStream_t stream);
+int mpi_batch_cg(const mpi_plan* plan, const void* rhs_all, void* x_all, const double* nus, double tol,
+                 int32_t max_iter, int32_t* iters, void* work, size_t work_bytes, void* dwork, size_t dbytes,
+                 hipStream_t stream);
+int mpi_batch_trim_sigma(const mpi_plan* plan, void* x_all, double pct, double* q, double* sigma, void* work,
+                         size_t work_bytes, void* dwork, size_t dbytes, hipStream_t stream);
+int mpi_batch_pnp(const mpi_plan* plan, const void* u_all, void* rho_all, const mpi_pnp_params* params,
+                  int32_t* cg_iters, double* sigmas, double* nus, void* work, size_t work_bytes, void* dwork,
+                  size_t dbytes, hipStream_t stream);
+
 /* Diagnostics for timing one kernel at a time.  The forward operator and its
  * transpose each run as a short sequence of kernels (stages); stages
  * 0 .. count/2-1 are those of mpi_forward, the rest those of mpi_adjoint;

@@ -104,7 +104,8 @@ def zeroshot_pnp(u, h, radius, n_it, nu0, tol=1e-3, max_iter=10000, clip_pct=5.0
     Returns (rho_2, info) with the CG step counts, the noise estimates, the
     nu used by every pass and lambda."""
     u = np.asarray(u, dtype=np.float64)
-    apply_c = lambda x: trace_conv(x, h, radius, method)
+    taps = trace_taps(u.shape[0], h, radius)          # the table of C, built once
+    apply_c = lambda x: conv(x, taps, method)
     cu = apply_c(u)                                   # C^T u (C symmetric)
     rho2 = np.zeros_like(u)
     nu = nu0

@@ -1,0 +1,306 @@
+// Kernels of the Deconvolution Stage (Section "Deconvolution Stage"): the
+// batched conjugate-gradient solver of the Tikhonov sub-step (eq. dec:sub:tik)
+// on its normal equations (C^T C + nu I) x = b, the percentile trimming
+// (Section "Denoiser Artifact Reduction") and the noise estimate
+// sigma = sqrt(Var) that drives the ZeroShot-PnP schedule.
+//
+// Every problem of a batch runs its own CG; the scalars live in device memory
+// and every kernel of a step skips problems whose flag done[b] is set, so the
+// host only polls the flags from time to time.  All sums are float64 in a
+// fixed order: kDotParts contiguous slices per problem (thread-strided inside
+// a slice, then a fixed tree), and the slices added one after another by
+// every work-group that needs the total, so all of them see the same value.
+#pragma once
+#include <type_traits>
+
+#include "common.hpp"
+#include "direct.hpp"
+
+namespace mpik {
+
+// per-problem solver state, arrays of `count` entries each
+struct CgState {
+    double* rr;     // |r|^2 of the current residual
+    double* bb;     // |b|^2
+    double* nu;     // Tikhonov weight of the problem
+    int* iters;     // steps taken
+    int* done;      // 1 once |r| <= tol |b| or iters == max_iter
+};
+
+__device__ __forceinline__ double sum_parts(const double* __restrict__ part) {
+    double s = 0.0;
+    for (int q = 0; q < kDotParts; ++q) s += part[q];
+    return s;
+}
+
+// The work-group's slice [lo, hi) of a problem with m elements.
+__device__ __forceinline__ void slice_of(int64_t m, int64_t& lo, int64_t& hi) {
+    const int64_t per = (m + kDotParts - 1) / kDotParts;
+    lo = min(m, per * int64_t(blockIdx.x));
+    hi = min(m, lo + per);
+}
+
+// Fixed tree over the 256 threads' values; thread 0 writes part[b][slice].
+__device__ __forceinline__ void reduce_to_part(double v, double* red, double* __restrict__ part) {
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) part[int64_t(blockIdx.y) * kDotParts + blockIdx.x] = red[0];
+}
+
+// Shares one float64 value computed by thread 0 with the work-group.
+__device__ __forceinline__ double broadcast0(double v, double* slot) {
+    if (threadIdx.x == 0) *slot = v;
+    __syncthreads();
+    return *slot;
+}
+
+// ------------------------------------------------------------------ CG ---
+// grid (kDotParts, problems), 256 threads.  b = cu + nu rho2 (rho2 may be
+// null: b = cu); x = 0, r = p = b; part = slices of |b|^2.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_init(const Prob* __restrict__ P, const T* __restrict__ cu,
+                                                 const T* __restrict__ rho2, CgState s, T* __restrict__ x,
+                                                 T* __restrict__ r, T* __restrict__ pv, double* __restrict__ part) {
+    __shared__ double red[256];
+    const Prob& p = P[blockIdx.y];
+    const int64_t m = int64_t(p.n) * p.n, o = p.o_c;
+    int64_t lo, hi;
+    slice_of(m, lo, hi);
+    const T nu = T(s.nu[blockIdx.y]);
+    double acc = 0.0;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
+        const T b = rho2 ? cu[o + e] + nu * rho2[o + e] : cu[o + e];
+        x[o + e] = T(0);
+        r[o + e] = b;
+        pv[o + e] = b;
+        acc += double(b) * double(b);
+    }
+    reduce_to_part(acc, red, part);
+}
+
+// one thread per problem: rr = bb = |b|^2, no step taken yet.
+__global__ void k_cg_begin(int count, CgState s, const double* __restrict__ part, double tol, int max_iter) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const double rr = sum_parts(part + int64_t(b) * kDotParts);
+    s.rr[b] = rr;
+    s.bb[b] = rr;
+    s.iters[b] = 0;
+    s.done[b] = (0 < max_iter && rr > tol * tol * rr) ? 0 : 1;
+}
+
+// q <- q + nu p (q holds C^T C p); part = slices of <p, q>.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_pq(const Prob* __restrict__ P, CgState s, const T* __restrict__ pv,
+                                               T* __restrict__ q, double* __restrict__ part) {
+    __shared__ double red[256];
+    if (s.done[blockIdx.y]) return;
+    const Prob& p = P[blockIdx.y];
+    const int64_t m = int64_t(p.n) * p.n, o = p.o_c;
+    int64_t lo, hi;
+    slice_of(m, lo, hi);
+    const T nu = T(s.nu[blockIdx.y]);
+    double acc = 0.0;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
+        const T pe = pv[o + e];
+        const T qe = q[o + e] + nu * pe;
+        q[o + e] = qe;
+        acc += double(pe) * double(qe);
+    }
+    reduce_to_part(acc, red, part);
+}
+
+// alpha = rr / <p, q>; x += alpha p; r -= alpha q; part_rr = slices of |r|^2.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_update(const Prob* __restrict__ P, CgState s, const T* __restrict__ pv,
+                                                   const T* __restrict__ q, T* __restrict__ x, T* __restrict__ r,
+                                                   const double* __restrict__ part_pq, double* __restrict__ part_rr) {
+    __shared__ double red[256];
+    __shared__ double slot;
+    if (s.done[blockIdx.y]) return;
+    const Prob& p = P[blockIdx.y];
+    const int64_t m = int64_t(p.n) * p.n, o = p.o_c;
+    int64_t lo, hi;
+    slice_of(m, lo, hi);
+    const double alpha =
+        broadcast0(threadIdx.x == 0 ? s.rr[blockIdx.y] / sum_parts(part_pq + int64_t(blockIdx.y) * kDotParts) : 0.0,
+                   &slot);
+    const T a = T(alpha);
+    double acc = 0.0;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
+        x[o + e] += a * pv[o + e];
+        const T re = r[o + e] - a * q[o + e];
+        r[o + e] = re;
+        acc += double(re) * double(re);
+    }
+    reduce_to_part(acc, red, part_rr);
+}
+
+// beta = |r_new|^2 / rr; p = r + beta p.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_dir(const Prob* __restrict__ P, CgState s, const T* __restrict__ r,
+                                                T* __restrict__ pv, const double* __restrict__ part_rr) {
+    __shared__ double slot;
+    if (s.done[blockIdx.y]) return;
+    const Prob& p = P[blockIdx.y];
+    const int64_t m = int64_t(p.n) * p.n, o = p.o_c;
+    int64_t lo, hi;
+    slice_of(m, lo, hi);
+    const double beta =
+        broadcast0(threadIdx.x == 0 ? sum_parts(part_rr + int64_t(blockIdx.y) * kDotParts) / s.rr[blockIdx.y] : 0.0,
+                   &slot);
+    const T bt = T(beta);
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) pv[o + e] = r[o + e] + bt * pv[o + e];
+}
+
+// one thread per problem, after the step: rr = |r_new|^2, one more step
+// counted, and the stop rule (|r| <= tol |b| or max_iter steps).
+__global__ void k_cg_state(int count, CgState s, const double* __restrict__ part_rr, double tol, int max_iter) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count || s.done[b]) return;
+    const double rr = sum_parts(part_rr + int64_t(b) * kDotParts);
+    const int it = s.iters[b] + 1;
+    s.rr[b] = rr;
+    s.iters[b] = it;
+    s.done[b] = (it < max_iter && rr > tol * tol * s.bb[b]) ? 0 : 1;
+}
+
+// ------------------------------------------------------ percentile trim ---
+// Order-preserving unsigned keys of IEEE values: flip the sign bit of
+// non-negative values, every bit of negative ones.
+__device__ __forceinline__ uint32_t order_key(float v) {
+    const uint32_t b = __float_as_uint(v);
+    return b ^ ((b >> 31) ? 0xffffffffu : 0x80000000u);
+}
+__device__ __forceinline__ uint64_t order_key(double v) {
+    const uint64_t b = uint64_t(__double_as_longlong(v));
+    return b ^ ((b >> 63) ? ~uint64_t(0) : (uint64_t(1) << 63));
+}
+__device__ __forceinline__ float key_value(uint32_t k) {
+    return __uint_as_float(k ^ ((k >> 31) ? 0x80000000u : 0xffffffffu));
+}
+__device__ __forceinline__ double key_value(uint64_t k) {
+    return __longlong_as_double(int64_t(k ^ ((k >> 63) ? (uint64_t(1) << 63) : ~uint64_t(0))));
+}
+
+// One work-group of 1024 threads per problem: the pct-th percentile of the
+// problem's n^2 values with the linear rule -- the order statistics of rank
+// i = floor(pos) and i + 1, pos = pct/100 (n^2 - 1), found together by an
+// 8-bit radix select over the keys (most significant digit first, one read of
+// the data per digit, integer histograms in LDS), then
+// q = v_i + (pos - i)(v_{i+1} - v_i) in float64 (v_i itself when i is the last
+// rank).
+template <typename T>
+__global__ void __launch_bounds__(1024) k_percentile(const Prob* __restrict__ P, const T* __restrict__ x,
+                                                     double pct, double* __restrict__ q_out) {
+    using K = typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type;
+    constexpr int kBits = 8 * int(sizeof(T));
+    __shared__ int hist[2][256];
+    __shared__ K prefix[2];
+    __shared__ int64_t rank[2];
+    const Prob& p = P[blockIdx.x];
+    const int64_t m = int64_t(p.n) * p.n;
+    const T* xp = x + p.o_c;
+    const double pos = pct / 100.0 * double(m - 1);
+    const int64_t i0 = int64_t(floor(pos));
+    const double f = pos - double(i0);
+    const bool last = i0 + 1 >= m;
+    const int tid = threadIdx.x;
+    if (tid < 2) {
+        prefix[tid] = K(0);
+        rank[tid] = tid == 0 ? i0 : (last ? i0 : i0 + 1);
+    }
+    for (int shift = kBits - 8; shift >= 0; shift -= 8) {
+        for (int i = tid; i < 512; i += 1024) hist[i >> 8][i & 255] = 0;
+        __syncthreads();
+        const K hi_mask = shift + 8 >= kBits ? K(0) : ~K(0) << (shift + 8);
+        const K pa = prefix[0] & hi_mask, pb = prefix[1] & hi_mask;
+        for (int64_t e = tid; e < m; e += 1024) {
+            const K k = order_key(xp[e]);
+            const int d = int((k >> shift) & K(255));
+            if ((k & hi_mask) == pa) atomicAdd(&hist[0][d], 1);
+            if ((k & hi_mask) == pb) atomicAdd(&hist[1][d], 1);
+        }
+        __syncthreads();
+        if (tid < 2) {
+            int64_t r = rank[tid], cum = 0;
+            int d = 0;
+            while (d < 255 && cum + hist[tid][d] <= r) cum += hist[tid][d++];
+            rank[tid] = r - cum;
+            prefix[tid] |= K(d) << shift;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+#pragma clang fp contract(off)
+        // rounded step by step (no fused multiply-add), as the linear rule reads
+        const double v0 = double(key_value(prefix[0])), v1 = double(key_value(prefix[1]));
+        const double d = v1 - v0;
+        const double fd = f * d;
+        q_out[blockIdx.x] = last ? v0 : v0 + fd;
+    }
+}
+
+// -------------------------------------------------- trim and moments ---
+// grid (kDotParts, problems), 256 threads: x <- max(x, q_b) when q is given
+// (values below the percentile raised to it), part = slices of sum x.
+template <typename T>
+__global__ void __launch_bounds__(256) k_clamp_sum(const Prob* __restrict__ P, T* __restrict__ x,
+                                                   const double* __restrict__ q, double* __restrict__ part) {
+    __shared__ double red[256];
+    const Prob& p = P[blockIdx.y];
+    const int64_t m = int64_t(p.n) * p.n, o = p.o_c;
+    int64_t lo, hi;
+    slice_of(m, lo, hi);
+    const T qb = q ? T(q[blockIdx.y]) : T(0);
+    double acc = 0.0;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
+        T v = x[o + e];
+        if (q && v < qb) {
+            v = qb;
+            x[o + e] = v;
+        }
+        acc += double(v);
+    }
+    reduce_to_part(acc, red, part);
+}
+
+// part = slices of sum (x - mean_b)^2.
+template <typename T>
+__global__ void __launch_bounds__(256) k_sq_dev(const Prob* __restrict__ P, const T* __restrict__ x,
+                                                const double* __restrict__ mean, double* __restrict__ part) {
+    __shared__ double red[256];
+    const Prob& p = P[blockIdx.y];
+    const int64_t m = int64_t(p.n) * p.n, o = p.o_c;
+    int64_t lo, hi;
+    slice_of(m, lo, hi);
+    const double mu = mean[blockIdx.y];
+    double acc = 0.0;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
+        const double d = double(x[o + e]) - mu;
+        acc += d * d;
+    }
+    reduce_to_part(acc, red, part);
+}
+
+// one thread per problem: out[b] = (sum of the problem's slices) / n^2.
+__global__ void k_part_mean(const Prob* __restrict__ P, int count, const double* __restrict__ part,
+                            double* __restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    out[b] = sum_parts(part + int64_t(b) * kDotParts) / double(int64_t(P[b].n) * P[b].n);
+}
+
+// y = x over the problems' grids (concatenated layout), n elements.
+template <typename T>
+__global__ void k_copy(const T* __restrict__ x, T* __restrict__ y, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i];
+}
+
+}  // namespace mpik

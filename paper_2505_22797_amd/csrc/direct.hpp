@@ -13,6 +13,8 @@
 // are summed in wave order in LDS (deterministic).
 //   CIN = 1, COUT = 3: the forward field (one input, three kernel channels)
 //   CIN = 3, COUT = 1: the transpose (sum over channels; each K_ch is even)
+//   CIN = 1, COUT = 1: the scalar convolution with the trace kernel
+//                      kappa_h = K_xx + K_yy (eq. kernel:trace)
 #pragma once
 #include "common.hpp"
 #include "sampling.hpp"
@@ -44,15 +46,17 @@ __device__ __forceinline__ void load_tile(T* tile, const T* __restrict__ in, int
 }
 
 // EPI 0: out = conv;  1: out = c_in - tau * conv;  2: as 1 into the problem's
-// work buffer u (COUT == 1 only for 1 and 2)
+// work buffer u (COUT == 1 only for 1 and 2).  skip (optional): problems with a
+// nonzero flag leave at once.
 template <typename T, int CIN, int COUT, int S, int EPI>
 __global__ void __launch_bounds__(64 * S) k_conv_direct(const Prob* __restrict__ P, const T* in, T* out,
                                                         const T* c_in, const double* __restrict__ taus,
                                                         const char* __restrict__ plan, int in_is_caller,
-                                                        int out_is_caller, int dh) {
+                                                        int out_is_caller, int dh, const int* __restrict__ skip) {
+    static_assert(!(CIN == 1 && COUT == 1 && EPI != 0), "the trace convolution has no epilogue");
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.z];
-    if (p.mode != 0 || p.slices != S) return;
+    if (p.mode != 0 || p.slices != S || (skip && skip[blockIdx.z])) return;
     const T tau = EPI ? T(taus[blockIdx.z]) : T(0);
     const int N = p.n, R = p.radius, tw = p.taps_w;
     const int tiles = (N + kTile - 1) / kTile;
@@ -102,6 +106,10 @@ __global__ void __launch_bounds__(64 * S) k_conv_direct(const Prob* __restrict__
                             acc[COUT > 1 ? 1 : 0][w] += k1 * x[u + w];
                             acc[COUT > 2 ? 2 : 0][w] += k2 * x[u + w];
                         }
+                    } else if (CIN == 1) {   // trace kernel: the two diagonal channels
+                        const T k = taps[trow + t0 + u] + taps[2 * W * tw + trow + t0 + u];
+#pragma unroll
+                        for (int w = 0; w < kStrip; ++w) acc[0][w] += k * x[u + w];
                     } else {
                         const T k = taps[ci * W * tw + trow + t0 + u];
 #pragma unroll

@@ -199,10 +199,13 @@ __device__ void fwd_rows_body(const Prob& p, const T* __restrict__ c, const char
 
 // Column kx: forward column FFT of T1[kx][.] (zero-padded), then for each
 // channel the product with its spectrum, the inverse FFT and rows 0..N-1 of
-// the result to T2[ch][row][kx].
-template <typename T, int M, bool SPLIT>
+// the result to T2[ch][row][kx].  TRACE (four-column shape): one channel, the
+// trace kernel kappa_h = K_xx + K_yy (eq. kernel:trace), whose spectrum is the
+// sum of the two diagonal channels' spectra.
+template <typename T, int M, bool SPLIT, bool TRACE = false>
 __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char* __restrict__ work, char* smem,
                               int dh) {
+    static_assert(!(SPLIT && TRACE), "the trace convolution runs in the four-column shape");
     auto& sm = *reinterpret_cast<ColSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
@@ -262,13 +265,15 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
 #pragma unroll
             for (int i = 0; i < PL; ++i) cr[i] = line[lane + i * kWave];
         }
-        for (int ch = 0; ch < 3; ++ch) {
+        for (int ch = 0; ch < (TRACE ? 1 : 3); ++ch) {
             if (active) {
                 wave_sync();
 #pragma unroll
                 for (int i = 0; i < PL; ++i) {
                     const int ky = lane + i * kWave;
-                    line[ky] = cscale(cr[i], spec_at<T, M>(spec, ch, kx, ky));
+                    const T k = TRACE ? spec_at<T, M>(spec, 0, kx, ky) + spec_at<T, M>(spec, 2, kx, ky)
+                                      : spec_at<T, M>(spec, ch, kx, ky);
+                    line[ky] = cscale(cr[i], k);
                 }
                 wave_sync();
                 fft_wave<T, true, M>(line, sm.tw, lane);
@@ -602,26 +607,29 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
 // ------------------------------------------------------------- launchers ---
 // One instance per FFT size M, so that registers are allocated for that size
 // alone; a launch covers every problem of the batch (grid.y) and problems of
-// another size, or on the direct path, leave at once.
+// another size, or on the direct path, leave at once.  skip (optional, one
+// flag per problem): problems with a nonzero flag leave at once as well (the
+// batched solvers use it for problems that have converged).
 
 // grid.x: xcd_grid(ceil(row pairs / 4)), grid.y: problem; 256 threads
 template <typename T, int M>
 __global__ void __launch_bounds__(256) k_fwd_rows(const Prob* __restrict__ P, const T* __restrict__ c,
-                                                  const char* __restrict__ plan, char* __restrict__ work) {
+                                                  const char* __restrict__ plan, char* __restrict__ work,
+                                                  const int* __restrict__ skip) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
-    if (p.mode != 1 || p.m != M) return;
+    if (p.mode != 1 || p.m != M || (skip && skip[blockIdx.y])) return;
     fwd_rows_body<T, M>(p, c + p.o_c, plan, work, smem);
 }
 
 // SPLIT: grid.x = xcd_grid(M/2 + 1), 192 threads; else xcd_grid(ceil((M/2 + 1)/4)), 256 threads
-template <typename T, int M, bool SPLIT>
+template <typename T, int M, bool SPLIT, bool TRACE = false>
 __global__ void __launch_bounds__(256) k_fwd_cols(const Prob* __restrict__ P, const char* __restrict__ plan,
-                                                  char* __restrict__ work, int dh) {
+                                                  char* __restrict__ work, int dh, const int* __restrict__ skip) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
-    if (p.mode != 1 || p.m != M) return;
-    fwd_cols_body<T, M, SPLIT>(p, plan, work, smem, dh);
+    if (p.mode != 1 || p.m != M || (skip && skip[blockIdx.y])) return;
+    fwd_cols_body<T, M, SPLIT, TRACE>(p, plan, work, smem, dh);
 }
 
 // grid.x: xcd_grid(base-cell rows), 256 threads.  MODE as gather_band; the
@@ -663,10 +671,10 @@ __global__ void __launch_bounds__(256) k_adj_cols(const Prob* __restrict__ P, co
 template <typename T, int M, int EPI>
 __global__ void __launch_bounds__(256) k_adj_rows(const Prob* __restrict__ P, T* c_out, const T* c_in,
                                                   const double* __restrict__ taus, const char* __restrict__ plan,
-                                                  char* __restrict__ work, int slot) {
+                                                  char* __restrict__ work, int slot, const int* __restrict__ skip) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
-    if (p.mode != 1 || p.m != M) return;
+    if (p.mode != 1 || p.m != M || (skip && skip[blockIdx.y])) return;
     const T tau = EPI ? T(taus[blockIdx.y]) : T(0);
     // EPI 2 writes the step into the problem's work buffer u (before the denoiser)
     T* out = EPI == 2 ? at<T>(work, p.w_u) : c_out + p.o_c;

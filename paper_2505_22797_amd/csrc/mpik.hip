@@ -26,6 +26,7 @@
 #include "build.hpp"
 #include "direct.hpp"
 #include "fft_conv.hpp"
+#include "deconv.hpp"
 #include "grad.hpp"
 
 using namespace mpik;
@@ -383,6 +384,7 @@ hipError_t set_smem_limits(const mpi_plan* pl) {
         chk(allow_smem(k_fwd_rows<T, M>, row));
         chk(allow_smem(k_fwd_cols<T, M, true>, col));
         chk(allow_smem(k_fwd_cols<T, M, false>, col));
+        chk(allow_smem(k_fwd_cols<T, M, false, true>, col));
         chk(allow_smem(k_adj_cols<T, M, true>, col));
         chk(allow_smem(k_adj_cols<T, M, false>, col));
         chk(allow_smem(k_adj_cols<T, M, false, true>, col));
@@ -405,6 +407,9 @@ hipError_t set_smem_limits(const mpi_plan* pl) {
     chk(allow_smem(k_conv_direct<T, 1, 3, 4, 0>, pl->smem_dfwd));
     chk(allow_smem(k_conv_direct<T, 1, 3, 8, 0>, pl->smem_dfwd));
     chk(allow_smem(k_conv_direct<T, 1, 3, 16, 0>, pl->smem_dfwd));
+    chk(allow_smem(k_conv_direct<T, 1, 1, 4, 0>, pl->smem_dfwd));
+    chk(allow_smem(k_conv_direct<T, 1, 1, 8, 0>, pl->smem_dfwd));
+    chk(allow_smem(k_conv_direct<T, 1, 1, 16, 0>, pl->smem_dfwd));
     chk(allow_smem(k_conv_direct<T, 3, 1, 4, 0>, pl->smem_dadj));
     chk(allow_smem(k_conv_direct<T, 3, 1, 8, 0>, pl->smem_dadj));
     chk(allow_smem(k_conv_direct<T, 3, 1, 16, 0>, pl->smem_dadj));
@@ -507,10 +512,10 @@ void launch_direct_conv(const mpi_plan* pl, bool fwd, const T* in, T* out, const
     const dim3 grid(pl->max_tiles, pl->max_tiles, pl->count);
     if (fwd)
         k_conv_direct<T, 1, 3, S, 0><<<grid, 64 * S, pl->smem_dfwd, st>>>(pl->dprob, in, out, nullptr, nullptr,
-                                                                          pl->plan, 1, 0, dh);
+                                                                          pl->plan, 1, 0, dh, nullptr);
     else
         k_conv_direct<T, 3, 1, S, EPI><<<grid, 64 * S, pl->smem_dadj, st>>>(pl->dprob, in, out, c_in, taus,
-                                                                            pl->plan, 0, 1, dh);
+                                                                            pl->plan, 0, 1, dh, nullptr);
 }
 
 // Forward: FFT {rows, columns, rows + gather}, direct {convolution, gather}.
@@ -531,18 +536,18 @@ void fwd_stage(const mpi_plan* pl, int k, const T* c, GatherIO<T> io, char* work
             each_fft_size<T>(pl, [&](auto mc, int li) {
                 constexpr int M = decltype(mc)::value;
                 k_fwd_rows<T, M><<<dim3(xcd_grid((pl->m_rowpairs[li] + 3) / 4), B), 256, pl->m_smem[li][0], st>>>(
-                    P, c, plan, work);
+                    P, c, plan, work, nullptr);
             }, part);
             break;
         case 1:
             each_fft_size<T>(pl, [&](auto mc, int li) {
                 constexpr int M = decltype(mc)::value;
                 if (pl->col_split)
-                    k_fwd_cols<T, M, true><<<dim3(xcd_grid(pl->m_h[li]), B), 192, pl->m_smem[li][1], st>>>(P, plan,
-                                                                                                          work, dh);
+                    k_fwd_cols<T, M, true><<<dim3(xcd_grid(pl->m_h[li]), B), 192, pl->m_smem[li][1], st>>>(
+                        P, plan, work, dh, nullptr);
                 else
                     k_fwd_cols<T, M, false><<<dim3(xcd_grid((pl->m_h[li] + 3) / 4), B), 256, pl->m_smem[li][1], st>>>(
-                        P, plan, work, dh);
+                        P, plan, work, dh, nullptr);
             }, part);
             break;
         case 2:
@@ -604,9 +609,11 @@ void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, c
             each_fft_size<T>(pl, [&](auto mc, int li) {
                 constexpr int M = decltype(mc)::value;
                 const dim3 grid(xcd_grid((pl->m_rowpairs[li] + 3) / 4), B);
-                k_adj_rows<T, M, EPI><<<grid, 256, pl->m_smem[li][0], st>>>(P, c_out, c_in, taus, plan, work, 0);
+                k_adj_rows<T, M, EPI><<<grid, 256, pl->m_smem[li][0], st>>>(P, c_out, c_in, taus, plan, work, 0,
+                                                                            nullptr);
                 if (z_out)
-                    k_adj_rows<T, M, 0><<<grid, 256, pl->m_smem[li][0], st>>>(P, z_out, nullptr, taus, plan, work, 1);
+                    k_adj_rows<T, M, 0><<<grid, 256, pl->m_smem[li][0], st>>>(P, z_out, nullptr, taus, plan, work, 1,
+                                                                              nullptr);
             }, part);
             break;
         case 3:
@@ -1139,6 +1146,217 @@ int check_iter(const mpi_iter_params* params) {
     return MPI_OK;
 }
 
+
+// ------------------------------------------------------- deconvolution ---
+// Workspace of the Deconvolution Stage entry points (caller memory): the CG
+// vectors r, p, t = C p, q = C t, for the PnP loop also C u and rho_1, then
+// the per-problem solver state, partial sums and statistics.
+struct DeconvLayout {
+    size_t r = 0, p = 0, t = 0, q = 0, cu = 0, rho1 = 0;
+    size_t rr = 0, bb = 0, nu = 0, iters = 0, done = 0, part_a = 0, part_b = 0, st_q = 0, st_mean = 0, st_var = 0;
+    size_t bytes = 0;
+};
+
+DeconvLayout deconv_layout(const mpi_plan* pl) {
+    DeconvLayout L;
+    size_t off = 0;
+    const size_t v = size_t(pl->L.c_elems) * pl->L.elem, B = size_t(pl->count);
+    L.r = take(off, v);
+    L.p = take(off, v);
+    L.t = take(off, v);
+    L.q = take(off, v);
+    L.cu = take(off, v);
+    L.rho1 = take(off, v);
+    L.rr = take(off, 8 * B);
+    L.bb = take(off, 8 * B);
+    L.nu = take(off, 8 * B);
+    L.iters = take(off, 4 * B);
+    L.done = take(off, 4 * B);
+    L.part_a = take(off, 8 * B * kDotParts);
+    L.part_b = take(off, 8 * B * kDotParts);
+    L.st_q = take(off, 8 * B);
+    L.st_mean = take(off, 8 * B);
+    L.st_var = take(off, 8 * B);
+    L.bytes = off;
+    return L;
+}
+
+CgState cg_state(const DeconvLayout& L, char* dw) {
+    CgState s;
+    s.rr = reinterpret_cast<double*>(dw + L.rr);
+    s.bb = reinterpret_cast<double*>(dw + L.bb);
+    s.nu = reinterpret_cast<double*>(dw + L.nu);
+    s.iters = reinterpret_cast<int*>(dw + L.iters);
+    s.done = reinterpret_cast<int*>(dw + L.done);
+    return s;
+}
+
+// out = C in for every problem (the trace-kernel convolution): FFT path
+// {rows, trace columns, inverse rows}, direct path one 1 -> 1 convolution.
+template <typename T>
+void trace_conv_impl(const mpi_plan* pl, const T* in, T* out, char* work, hipStream_t st, const int* skip) {
+    const Prob* P = pl->dprob;
+    const char* plan = pl->plan;
+    const int B = pl->count;
+    if (pl->any_fft)
+        each_fft_size<T>(pl, [&](auto mc, int li) {
+            constexpr int M = decltype(mc)::value;
+            const dim3 rows(xcd_grid((pl->m_rowpairs[li] + 3) / 4), B);
+            k_fwd_rows<T, M><<<rows, 256, pl->m_smem[li][0], st>>>(P, in, plan, work, skip);
+            k_fwd_cols<T, M, false, true><<<dim3(xcd_grid((pl->m_h[li] + 3) / 4), B), 256, pl->m_smem[li][1], st>>>(
+                P, plan, work, 0, skip);
+            k_adj_rows<T, M, 0><<<rows, 256, pl->m_smem[li][0], st>>>(P, out, nullptr, nullptr, plan, work, 0, skip);
+        });
+    if (pl->any_direct) {
+        const dim3 grid(pl->max_tiles, pl->max_tiles, B);
+        if (pl->slice_mask & 1)
+            k_conv_direct<T, 1, 1, 4, 0><<<grid, 256, pl->smem_dfwd, st>>>(P, in, out, nullptr, nullptr, plan, 1, 1,
+                                                                           0, skip);
+        if (pl->slice_mask & 2)
+            k_conv_direct<T, 1, 1, 8, 0><<<grid, 512, pl->smem_dfwd, st>>>(P, in, out, nullptr, nullptr, plan, 1, 1,
+                                                                           0, skip);
+        if (pl->slice_mask & 4)
+            k_conv_direct<T, 1, 1, 16, 0><<<grid, 1024, pl->smem_dfwd, st>>>(P, in, out, nullptr, nullptr, plan, 1, 1,
+                                                                             0, skip);
+    }
+}
+
+// CG on (C^T C + nu_b I) x = cu + nu_b rho2 (rho2 may be null) from x = 0 for
+// every problem; nu_b already in the state.  The host polls the stop flags
+// after 4, 8, 16, 32, 32, ... steps; steps of converged problems are skipped
+// by every kernel.  iters (host, may be null) receives the steps taken.
+template <typename T>
+int cg_impl(const mpi_plan* pl, const T* cu, const T* rho2, T* x, double tol, int max_iter, char* work, char* dw,
+            const DeconvLayout& L, hipStream_t st, int32_t* iters) {
+    const Prob* P = pl->dprob;
+    const int B = pl->count;
+    const CgState s = cg_state(L, dw);
+    T* r = reinterpret_cast<T*>(dw + L.r);
+    T* pv = reinterpret_cast<T*>(dw + L.p);
+    T* t = reinterpret_cast<T*>(dw + L.t);
+    T* q = reinterpret_cast<T*>(dw + L.q);
+    double* pa = reinterpret_cast<double*>(dw + L.part_a);
+    double* pb = reinterpret_cast<double*>(dw + L.part_b);
+    const dim3 el(kDotParts, B);
+    k_cg_init<T><<<el, 256, 0, st>>>(P, cu, rho2, s, x, r, pv, pa);
+    k_cg_begin<<<blocks(B, 256), 256, 0, st>>>(B, s, pa, tol, max_iter);
+    HIP_TRY(hipGetLastError());
+    std::vector<int> done(B);
+    int taken = 0, chunk = 4;
+    while (taken < max_iter) {
+        const int n = std::min(chunk, max_iter - taken);
+        for (int i = 0; i < n; ++i) {
+            trace_conv_impl<T>(pl, pv, t, work, st, s.done);
+            trace_conv_impl<T>(pl, t, q, work, st, s.done);
+            k_cg_pq<T><<<el, 256, 0, st>>>(P, s, pv, q, pa);
+            k_cg_update<T><<<el, 256, 0, st>>>(P, s, pv, q, x, r, pa, pb);
+            k_cg_dir<T><<<el, 256, 0, st>>>(P, s, r, pv, pb);
+            k_cg_state<<<blocks(B, 256), 256, 0, st>>>(B, s, pb, tol, max_iter);
+        }
+        HIP_TRY(hipGetLastError());
+        taken += n;
+        chunk = std::min(2 * chunk, 32);
+        HIP_TRY(hipMemcpyAsync(done.data(), s.done, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (std::all_of(done.begin(), done.end(), [](int d) { return d != 0; })) break;
+    }
+    if (iters) HIP_TRY(hipMemcpyAsync(iters, s.iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return MPI_OK;
+}
+
+// Percentile trim (pct < 0: none) and the noise estimate of x for every
+// problem: q_b, mean_b and var_b land in the statistics area; var copied to
+// the host array var (count entries), q to q_host when given.
+template <typename T>
+int trim_and_variance(const mpi_plan* pl, T* x, double pct, char* dw, const DeconvLayout& L, hipStream_t st,
+                      double* var, double* q_host) {
+    const Prob* P = pl->dprob;
+    const int B = pl->count;
+    double* pa = reinterpret_cast<double*>(dw + L.part_a);
+    double* q = reinterpret_cast<double*>(dw + L.st_q);
+    double* mean = reinterpret_cast<double*>(dw + L.st_mean);
+    double* v = reinterpret_cast<double*>(dw + L.st_var);
+    const dim3 el(kDotParts, B);
+    if (pct >= 0.0) k_percentile<T><<<B, 1024, 0, st>>>(P, x, pct, q);
+    k_clamp_sum<T><<<el, 256, 0, st>>>(P, x, pct >= 0.0 ? q : nullptr, pa);
+    k_part_mean<<<blocks(B, 256), 256, 0, st>>>(P, B, pa, mean);
+    k_sq_dev<T><<<el, 256, 0, st>>>(P, x, mean, pa);
+    k_part_mean<<<blocks(B, 256), 256, 0, st>>>(P, B, pa, v);
+    HIP_TRY(hipGetLastError());
+    if (var) HIP_TRY(hipMemcpyAsync(var, v, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+    if (q_host && pct >= 0.0) HIP_TRY(hipMemcpyAsync(q_host, q, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return MPI_OK;
+}
+
+// Gaussian weights of the denoiser stand-in into the plan's work buffer.
+hipError_t upload_gauss(mpi_plan* pl, double sigma_px, int radius, char* work, hipStream_t st) {
+    double sum = 0.0;
+    for (int k = -radius; k <= radius; ++k) {
+        pl->wts[k + radius] = std::exp(-0.5 * k * k / (sigma_px * sigma_px));
+        sum += pl->wts[k + radius];
+    }
+    for (int k = 0; k <= 2 * radius; ++k) pl->wts[k] /= sum;
+    return hipMemcpyAsync(work + pl->L.w_wts, pl->wts, sizeof(double) * (2 * radius + 1), hipMemcpyHostToDevice, st);
+}
+
+// The ZeroShot-PnP loop (Algorithm "ZeroShot-PnP"): per pass k = 0..n_it,
+// rho_1 = CG on (C^T C + nu I) rho_1 = C u + nu rho_2, trim, sigma =
+// sqrt(Var rho_1), lambda = nu0 sigma^2 on the first pass, rho_2 = D(rho_1),
+// nu = lambda / sigma^2 (kept when sigma = 0).  The schedule scalars are
+// float64 on the host; rho (the caller's output) holds rho_2.
+template <typename T>
+int pnp_impl(mpi_plan* pl, const T* u, T* rho, const mpi_pnp_params* pp, int32_t* cg_iters, double* sigmas,
+             double* nus, char* work, char* dw, hipStream_t st) {
+    const DeconvLayout L = deconv_layout(pl);
+    const Prob* P = pl->dprob;
+    const int B = pl->count;
+    const int64_t C = pl->L.c_elems;
+    T* cu = reinterpret_cast<T*>(dw + L.cu);
+    T* rho1 = reinterpret_cast<T*>(dw + L.rho1);
+    trace_conv_impl<T>(pl, u, cu, work, st, nullptr);                 // C^T u = C u
+    k_fill<T><<<blocks(C, 256), 256, 0, st>>>(rho, C, T(0));
+    const bool den = pp->denoise_sigma_px > 0.0;
+    if (den) HIP_TRY(upload_gauss(pl, pp->denoise_sigma_px, pp->denoise_radius, work, st));
+    const double* wts = reinterpret_cast<const double*>(work + pl->L.w_wts);
+    std::vector<double> nu(B, pp->nu0), lam(B, 0.0), var(B, 0.0);
+    std::vector<int32_t> it(B, 0);
+    for (int k = 0; k <= pp->n_it; ++k) {
+        HIP_TRY(hipMemcpyAsync(dw + L.nu, nu.data(), sizeof(double) * B, hipMemcpyHostToDevice, st));
+        int rc = cg_impl<T>(pl, cu, rho, rho1, pp->cg_tol, pp->cg_max_iter, work, dw, L, st, it.data());
+        if (rc != MPI_OK) return rc;
+        rc = trim_and_variance<T>(pl, rho1, pp->clip_percentile, dw, L, st, var.data(), nullptr);
+        if (rc != MPI_OK) return rc;
+        if (den)
+            k_denoise<T><<<dim3(pl->max_dntiles, pl->max_dntiles, B), 256, 0, st>>>(P, work, rho1, rho, wts,
+                                                                                  pp->denoise_radius);
+        else
+            k_copy<T><<<blocks(C, 256), 256, 0, st>>>(rho1, rho, C);
+        HIP_TRY(hipGetLastError());
+        for (int b = 0; b < B; ++b) {
+            const double sigma = std::sqrt(var[b]);
+            if (k == 0) lam[b] = pp->nu0 * sigma * sigma;
+            if (cg_iters) cg_iters[int64_t(k) * B + b] = it[b];
+            if (sigmas) sigmas[int64_t(k) * B + b] = sigma;
+            if (nus) nus[int64_t(k) * B + b] = nu[b];
+            if (sigma > 0.0) nu[b] = lam[b] / (sigma * sigma);
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return MPI_OK;
+}
+
+int check_deconv(const mpi_plan* pl, const void* a, const void* b, const void* work, size_t work_bytes,
+                 const void* dw, size_t dbytes) {
+    const int rc = check_call(pl, a, b, work, work_bytes);
+    if (rc != MPI_OK) return rc;
+    if (!dw || misaligned(dw, kAlign)) return MPI_ERR_ARG;
+    if (dbytes < deconv_layout(pl).bytes) return MPI_ERR_WORKSPACE;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    return MPI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1413,6 +1631,81 @@ int mpi_batch_unrolled_vjp(const mpi_plan* plan, const void* s, const void* chec
     return unrolled_vjp_impl<float>(pl, static_cast<const float*>(s), static_cast<const float*>(checkpoints), n_iter,
                                     every, sigma, denoise_radius, taus, static_cast<float*>(gbar), g_h,
                                     static_cast<float*>(g_r), static_cast<float*>(g_v), w, vj, stream);
+}
+
+int mpi_batch_deconv_bytes(const mpi_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return MPI_ERR_ARG;
+    *bytes = deconv_layout(plan).bytes;
+    return MPI_OK;
+}
+
+int mpi_batch_trace_conv(const mpi_plan* plan, const void* x, void* y, void* work, size_t work_bytes,
+                         hipStream_t stream) {
+    int rc = check_call(plan, x, y, work, work_bytes);
+    if (rc != MPI_OK) return rc;
+    if (x == y) return MPI_ERR_ARG;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    char* w = static_cast<char*>(work);
+    if (plan->dtype == MPI_F64)
+        trace_conv_impl<double>(plan, static_cast<const double*>(x), static_cast<double*>(y), w, stream, nullptr);
+    else
+        trace_conv_impl<float>(plan, static_cast<const float*>(x), static_cast<float*>(y), w, stream, nullptr);
+    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+}
+
+int mpi_batch_cg(const mpi_plan* plan, const void* rhs, void* x, const double* nus, double tol, int32_t max_iter,
+                 int32_t* iters, void* work, size_t work_bytes, void* dwork, size_t dbytes, hipStream_t stream) {
+    int rc = check_deconv(plan, rhs, x, work, work_bytes, dwork, dbytes);
+    if (rc != MPI_OK) return rc;
+    if (!nus || rhs == x || !(tol >= 0.0) || max_iter < 0) return MPI_ERR_ARG;
+    for (int b = 0; b < plan->count; ++b)
+        if (!(nus[b] >= 0.0) || !std::isfinite(nus[b])) return MPI_ERR_ARG;
+    const DeconvLayout L = deconv_layout(plan);
+    char* w = static_cast<char*>(work);
+    char* dw = static_cast<char*>(dwork);
+    HIP_TRY(hipMemcpyAsync(dw + L.nu, nus, sizeof(double) * plan->count, hipMemcpyHostToDevice, stream));
+    return plan->dtype == MPI_F64
+               ? cg_impl<double>(plan, static_cast<const double*>(rhs), nullptr, static_cast<double*>(x), tol,
+                                 max_iter, w, dw, L, stream, iters)
+               : cg_impl<float>(plan, static_cast<const float*>(rhs), nullptr, static_cast<float*>(x), tol, max_iter,
+                                w, dw, L, stream, iters);
+}
+
+int mpi_batch_trim_sigma(const mpi_plan* plan, void* x, double pct, double* q, double* sigma, void* work,
+                         size_t work_bytes, void* dwork, size_t dbytes, hipStream_t stream) {
+    int rc = check_deconv(plan, x, x, work, work_bytes, dwork, dbytes);
+    if (rc != MPI_OK) return rc;
+    if (!(pct <= 100.0) || std::isnan(pct)) return MPI_ERR_ARG;
+    const DeconvLayout L = deconv_layout(plan);
+    std::vector<double> var(plan->count);
+    char* dw = static_cast<char*>(dwork);
+    rc = plan->dtype == MPI_F64
+             ? trim_and_variance<double>(plan, static_cast<double*>(x), pct, dw, L, stream, var.data(), q)
+             : trim_and_variance<float>(plan, static_cast<float*>(x), pct, dw, L, stream, var.data(), q);
+    if (rc != MPI_OK) return rc;
+    if (sigma)
+        for (int b = 0; b < plan->count; ++b) sigma[b] = std::sqrt(var[b]);
+    return MPI_OK;
+}
+
+int mpi_batch_pnp(const mpi_plan* plan, const void* u, void* rho, const mpi_pnp_params* params, int32_t* cg_iters,
+                  double* sigmas, double* nus, void* work, size_t work_bytes, void* dwork, size_t dbytes,
+                  hipStream_t stream) {
+    int rc = check_deconv(plan, u, rho, work, work_bytes, dwork, dbytes);
+    if (rc != MPI_OK) return rc;
+    if (!params || u == rho || params->n_it < 0 || params->cg_max_iter < 0 || !(params->nu0 > 0.0) ||
+        !std::isfinite(params->nu0) || !(params->cg_tol >= 0.0) || !(params->clip_percentile <= 100.0))
+        return MPI_ERR_ARG;
+    if (params->denoise_sigma_px > 0.0 && (params->denoise_radius < 0 || params->denoise_radius > kDnMaxR))
+        return MPI_ERR_ARG;
+    mpi_plan* pl = const_cast<mpi_plan*>(plan);
+    char* w = static_cast<char*>(work);
+    char* dw = static_cast<char*>(dwork);
+    return plan->dtype == MPI_F64
+               ? pnp_impl<double>(pl, static_cast<const double*>(u), static_cast<double*>(rho), params, cg_iters,
+                                  sigmas, nus, w, dw, stream)
+               : pnp_impl<float>(pl, static_cast<const float*>(u), static_cast<float*>(rho), params, cg_iters, sigmas,
+                                 nus, w, dw, stream);
 }
 
 int mpi_stage_count(const mpi_plan* plan) {

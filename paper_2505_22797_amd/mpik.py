@@ -26,6 +26,7 @@ EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "
            "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
            "mpi_batch_dot", "mpi_batch_unrolled_vjp_bytes", "mpi_batch_unrolled_vjp",
            "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
+           "mpi_batch_deconv_bytes", "mpi_batch_trace_conv", "mpi_batch_cg", "mpi_batch_trim_sigma", "mpi_batch_pnp",
            "mpi_plan_destroy", "mpi_status_str", "mpi_abi_version")
 MPI_BUILD_TUNE, MPI_BUILD_COL_SPLIT, MPI_BUILD_COL_WAVE, MPI_BUILD_DERIV = 1, 2, 4, 8
 
@@ -46,6 +47,13 @@ class Problem(ctypes.Structure):
 class IterParams(ctypes.Structure):
     _fields_ = [("n_iter", ctypes.c_int32), ("tau", ctypes.c_double), ("denoise_sigma_px", ctypes.c_double),
                 ("denoise_radius", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class PnpParams(ctypes.Structure):
+    _fields_ = [("n_it", ctypes.c_int32), ("cg_max_iter", ctypes.c_int32), ("nu0", ctypes.c_double),
+                ("cg_tol", ctypes.c_double), ("clip_percentile", ctypes.c_double),
+                ("denoise_sigma_px", ctypes.c_double), ("denoise_radius", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -88,6 +96,12 @@ def lib() -> ctypes.CDLL:
         L.mpi_batch_unrolled_vjp.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                              ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp, vp, sz,
                                              vp, sz, vp]
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.mpi_batch_deconv_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.mpi_batch_trace_conv.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.mpi_batch_cg.argtypes = [vp, vp, vp, dp, ctypes.c_double, ctypes.c_int32, i32p, vp, sz, vp, sz, vp]
+        L.mpi_batch_trim_sigma.argtypes = [vp, vp, ctypes.c_double, dp, dp, vp, sz, vp, sz, vp]
+        L.mpi_batch_pnp.argtypes = [vp, vp, vp, ctypes.POINTER(PnpParams), i32p, dp, dp, vp, sz, vp, sz, vp]
         L.mpi_stage_count.argtypes = [vp]
         L.mpi_stage_name.argtypes = [vp, ctypes.c_int]
         L.mpi_stage_name.restype = ctypes.c_char_p
@@ -102,7 +116,8 @@ def lib() -> ctypes.CDLL:
                      "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
                      "mpi_batch_dot", "mpi_batch_unrolled_vjp_bytes", "mpi_batch_unrolled_vjp",
                      "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_launch",
-                     "mpi_plan_destroy",
+                     "mpi_batch_deconv_bytes", "mpi_batch_trace_conv", "mpi_batch_cg", "mpi_batch_trim_sigma",
+                     "mpi_batch_pnp", "mpi_plan_destroy",
                      "mpi_abi_version"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -497,6 +512,69 @@ class Batch:
                                             self.work.data_ptr(), self.work.numel(), self._vjp_work.data_ptr(),
                                             self._vjp_work.numel(), _stream(stream)), "mpi_batch_unrolled_vjp")
         return g_h, g_r, g_v
+
+    # ---- the Deconvolution Stage (trace-kernel convolution, CG, ZeroShot-PnP)
+    def _deconv_work(self):
+        if getattr(self, "_dwork", None) is None:
+            nb = ctypes.c_size_t()
+            _check(lib().mpi_batch_deconv_bytes(self._h, ctypes.byref(nb)), "mpi_batch_deconv_bytes")
+            self._dwork = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        return self._dwork
+
+    def trace_conv(self, x_all, out=None, stream=None):
+        """C_b x_b for every problem (the trace-kernel convolution)."""
+        self._flat(x_all, self.c_offsets[-1], "x_all")
+        if out is None:
+            out = torch.empty_like(x_all)
+        _check(lib().mpi_batch_trace_conv(self._h, x_all.data_ptr(), out.data_ptr(), self.work.data_ptr(),
+                                          self.work.numel(), _stream(stream)), "mpi_batch_trace_conv")
+        return out
+
+    def cg(self, rhs_all, nus, tol=1e-3, max_iter=10000, x_out=None, stream=None):
+        """CG on (C^T C + nu_b I) x = rhs from x = 0; returns (x, steps per problem)."""
+        self._flat(rhs_all, self.c_offsets[-1], "rhs_all")
+        if x_out is None:
+            x_out = torch.empty_like(rhs_all)
+        dw = self._deconv_work()
+        nu = (ctypes.c_double * self.count)(*[float(v) for v in nus])
+        it = (ctypes.c_int32 * self.count)()
+        _check(lib().mpi_batch_cg(self._h, rhs_all.data_ptr(), x_out.data_ptr(), nu, float(tol), int(max_iter), it,
+                                  self.work.data_ptr(), self.work.numel(), dw.data_ptr(), dw.numel(), _stream(stream)),
+               "mpi_batch_cg")
+        return x_out, list(it)
+
+    def trim_sigma(self, x_all, pct=5.0, stream=None):
+        """In place: trim x below its pct-th percentile (pct < 0: no trim);
+        returns (percentiles, sigmas) per problem."""
+        self._flat(x_all, self.c_offsets[-1], "x_all")
+        dw = self._deconv_work()
+        q = (ctypes.c_double * self.count)()
+        sg = (ctypes.c_double * self.count)()
+        _check(lib().mpi_batch_trim_sigma(self._h, x_all.data_ptr(), float(pct), q, sg, self.work.data_ptr(),
+                                          self.work.numel(), dw.data_ptr(), dw.numel(), _stream(stream)),
+               "mpi_batch_trim_sigma")
+        return list(q), list(sg)
+
+    def pnp(self, u_all, n_it=9, nu0=1e-5, tol=1e-3, max_iter=10000, clip_pct=5.0, sigma_px=0.5, radius=2,
+            rho_out=None, stream=None):
+        """ZeroShot-PnP deconvolution of the trace images; returns (rho, info)
+        with per-pass CG steps, noise estimates and Tikhonov weights."""
+        self._flat(u_all, self.c_offsets[-1], "u_all")
+        if rho_out is None:
+            rho_out = torch.empty_like(u_all)
+        dw = self._deconv_work()
+        prm = PnpParams(int(n_it), int(max_iter), float(nu0), float(tol), float(-1.0 if clip_pct is None else clip_pct),
+                        float(0.0 if sigma_px is None else sigma_px), int(radius), 0)
+        m = (n_it + 1) * self.count
+        it, sg, nu = (ctypes.c_int32 * m)(), (ctypes.c_double * m)(), (ctypes.c_double * m)()
+        _check(lib().mpi_batch_pnp(self._h, u_all.data_ptr(), rho_out.data_ptr(), ctypes.byref(prm), it, sg, nu,
+                                   self.work.data_ptr(), self.work.numel(), dw.data_ptr(), dw.numel(),
+                                   _stream(stream)), "mpi_batch_pnp")
+        B = self.count
+        info = {"cg_steps": [[it[k * B + b] for k in range(n_it + 1)] for b in range(B)],
+                "sigma": [[sg[k * B + b] for k in range(n_it + 1)] for b in range(B)],
+                "nu": [[nu[k * B + b] for k in range(n_it + 1)] for b in range(B)]}
+        return rho_out, info
 
     def sample_order(self, b, stream=None):
         """(time index, base cell i0 | j0 << 16) of problem b's samples in the
