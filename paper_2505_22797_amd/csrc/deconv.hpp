@@ -6,19 +6,24 @@
 //
 // Every problem of a batch runs its own CG; the scalars live in device memory
 // and every kernel of a step skips problems whose flag done[b] is set, so the
-// host only polls the flags from time to time.  All sums are float64 in a
-// fixed order: kDotParts contiguous slices per problem (thread-strided inside
-// a slice, then a fixed tree), and the slices added one after another by
+// host only polls the flags from time to time.  The residual norm and the flag
+// are double-buffered by the parity of the step: step i reads slot i & 1 and
+// its last kernel writes slot (i + 1) & 1, so no kernel writes what another
+// work-group of the same launch still reads.  All sums are float64 in a fixed
+// order: per problem, fixed partial sums (kDotParts contiguous slices, or one
+// per row pair where the FFT row stage forms them) added one after another by
 // every work-group that needs the total, so all of them see the same value.
 #pragma once
 #include <type_traits>
 
 #include "common.hpp"
 #include "direct.hpp"
+#include "fft_conv.hpp"
 
 namespace mpik {
 
-// per-problem solver state, arrays of `count` entries each
+// per-problem solver state, arrays of `count` entries each (rr and done: two
+// slots of `count`, by step parity)
 struct CgState {
     double* rr;     // |r|^2 of the current residual
     double* bb;     // |b|^2
@@ -27,11 +32,15 @@ struct CgState {
     int* done;      // 1 once |r| <= tol |b| or iters == max_iter
 };
 
-__device__ __forceinline__ double sum_parts(const double* __restrict__ part) {
+__device__ __forceinline__ double sum_parts(const double* __restrict__ part, int n = kDotParts) {
     double s = 0.0;
-    for (int q = 0; q < kDotParts; ++q) s += part[q];
+    for (int q = 0; q < n; ++q) s += part[q];
     return s;
 }
+
+// Partial sums of <p, q> per problem: kCgRowParts slots; the FFT row stage
+// fills one per row pair, the direct path's k_cg_pq the first kDotParts.
+__device__ __forceinline__ int pq_parts(const Prob& p) { return p.mode == 1 ? (p.n + 1) / 2 : kDotParts; }
 
 // The work-group's slice [lo, hi) of a problem with m elements.
 __device__ __forceinline__ void slice_of(int64_t m, int64_t& lo, int64_t& hi) {
@@ -40,8 +49,10 @@ __device__ __forceinline__ void slice_of(int64_t m, int64_t& lo, int64_t& hi) {
     hi = min(m, lo + per);
 }
 
-// Fixed tree over the 256 threads' values; thread 0 writes part[b][slice].
-__device__ __forceinline__ void reduce_to_part(double v, double* red, double* __restrict__ part) {
+// Fixed tree over the 256 threads' values; thread 0 writes part[b][slice]
+// (`stride` slots per problem).
+__device__ __forceinline__ void reduce_to_part(double v, double* red, double* __restrict__ part,
+                                               int stride = kDotParts) {
     const int tid = threadIdx.x;
     red[tid] = v;
     __syncthreads();
@@ -49,7 +60,7 @@ __device__ __forceinline__ void reduce_to_part(double v, double* red, double* __
         if (tid < w) red[tid] += red[tid + w];
         __syncthreads();
     }
-    if (tid == 0) part[int64_t(blockIdx.y) * kDotParts + blockIdx.x] = red[0];
+    if (tid == 0) part[int64_t(blockIdx.y) * stride + blockIdx.x] = red[0];
 }
 
 // Shares one float64 value computed by thread 0 with the work-group.
@@ -83,7 +94,7 @@ __global__ void __launch_bounds__(256) k_cg_init(const Prob* __restrict__ P, con
     reduce_to_part(acc, red, part);
 }
 
-// one thread per problem: rr = bb = |b|^2, no step taken yet.
+// one thread per problem: rr = bb = |b|^2, no step taken yet (slot 0).
 __global__ void k_cg_begin(int count, CgState s, const double* __restrict__ part, double tol, int max_iter) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= count) return;
@@ -94,12 +105,15 @@ __global__ void k_cg_begin(int count, CgState s, const double* __restrict__ part
     s.done[b] = (0 < max_iter && rr > tol * tol * rr) ? 0 : 1;
 }
 
-// q <- q + nu p (q holds C^T C p); part = slices of <p, q>.
+// Direct-path problems: q <- q + nu p (q holds C^T C p); part = slices of
+// <p, q>.  (The FFT row stage does this for the FFT problems.)
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_pq(const Prob* __restrict__ P, CgState s, const T* __restrict__ pv,
-                                               T* __restrict__ q, double* __restrict__ part) {
+__global__ void __launch_bounds__(256) k_cg_pq(const Prob* __restrict__ P, CgState s, int par,
+                                               const T* __restrict__ pv, T* __restrict__ q,
+                                               double* __restrict__ part) {
     __shared__ double red[256];
-    if (s.done[blockIdx.y]) return;
+    const int cnt = gridDim.y;
+    if (s.done[par * cnt + blockIdx.y] || P[blockIdx.y].mode == 1) return;
     const Prob& p = P[blockIdx.y];
     const int64_t m = int64_t(p.n) * p.n, o = p.o_c;
     int64_t lo, hi;
@@ -112,24 +126,26 @@ __global__ void __launch_bounds__(256) k_cg_pq(const Prob* __restrict__ P, CgSta
         q[o + e] = qe;
         acc += double(pe) * double(qe);
     }
-    reduce_to_part(acc, red, part);
+    reduce_to_part(acc, red, part, kCgRowParts);
 }
 
 // alpha = rr / <p, q>; x += alpha p; r -= alpha q; part_rr = slices of |r|^2.
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_update(const Prob* __restrict__ P, CgState s, const T* __restrict__ pv,
-                                                   const T* __restrict__ q, T* __restrict__ x, T* __restrict__ r,
+__global__ void __launch_bounds__(256) k_cg_update(const Prob* __restrict__ P, CgState s, int par,
+                                                   const T* __restrict__ pv, const T* __restrict__ q,
+                                                   T* __restrict__ x, T* __restrict__ r,
                                                    const double* __restrict__ part_pq, double* __restrict__ part_rr) {
     __shared__ double red[256];
     __shared__ double slot;
-    if (s.done[blockIdx.y]) return;
-    const Prob& p = P[blockIdx.y];
+    const int b = blockIdx.y, cnt = gridDim.y;
+    if (s.done[par * cnt + b]) return;
+    const Prob& p = P[b];
     const int64_t m = int64_t(p.n) * p.n, o = p.o_c;
     int64_t lo, hi;
     slice_of(m, lo, hi);
-    const double alpha =
-        broadcast0(threadIdx.x == 0 ? s.rr[blockIdx.y] / sum_parts(part_pq + int64_t(blockIdx.y) * kDotParts) : 0.0,
-                   &slot);
+    const double alpha = broadcast0(
+        threadIdx.x == 0 ? s.rr[par * cnt + b] / sum_parts(part_pq + int64_t(b) * kCgRowParts, pq_parts(p)) : 0.0,
+        &slot);
     const T a = T(alpha);
     double acc = 0.0;
     for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
@@ -141,33 +157,38 @@ __global__ void __launch_bounds__(256) k_cg_update(const Prob* __restrict__ P, C
     reduce_to_part(acc, red, part_rr);
 }
 
-// beta = |r_new|^2 / rr; p = r + beta p.
+// beta = |r_new|^2 / rr; p = r + beta p.  The first work-group of a problem
+// also writes the next slot of the state: rr = |r_new|^2, one more step
+// counted, and the stop rule (|r| <= tol |b| or max_iter steps); a stopped
+// problem's state is carried over unchanged.
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_dir(const Prob* __restrict__ P, CgState s, const T* __restrict__ r,
-                                                T* __restrict__ pv, const double* __restrict__ part_rr) {
+__global__ void __launch_bounds__(256) k_cg_dir(const Prob* __restrict__ P, CgState s, int par,
+                                                const T* __restrict__ r, T* __restrict__ pv,
+                                                const double* __restrict__ part_rr, double tol, int max_iter) {
     __shared__ double slot;
-    if (s.done[blockIdx.y]) return;
-    const Prob& p = P[blockIdx.y];
+    const int b = blockIdx.y, cnt = gridDim.y;
+    const int cur = par * cnt + b, nxt = (1 - par) * cnt + b;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (s.done[cur]) {
+        if (lead) {
+            s.done[nxt] = 1;
+            s.rr[nxt] = s.rr[cur];
+        }
+        return;
+    }
+    const Prob& p = P[b];
     const int64_t m = int64_t(p.n) * p.n, o = p.o_c;
     int64_t lo, hi;
     slice_of(m, lo, hi);
-    const double beta =
-        broadcast0(threadIdx.x == 0 ? sum_parts(part_rr + int64_t(blockIdx.y) * kDotParts) / s.rr[blockIdx.y] : 0.0,
-                   &slot);
-    const T bt = T(beta);
+    const double rr_new = broadcast0(threadIdx.x == 0 ? sum_parts(part_rr + int64_t(b) * kDotParts) : 0.0, &slot);
+    const T bt = T(rr_new / s.rr[cur]);
     for (int64_t e = lo + threadIdx.x; e < hi; e += 256) pv[o + e] = r[o + e] + bt * pv[o + e];
-}
-
-// one thread per problem, after the step: rr = |r_new|^2, one more step
-// counted, and the stop rule (|r| <= tol |b| or max_iter steps).
-__global__ void k_cg_state(int count, CgState s, const double* __restrict__ part_rr, double tol, int max_iter) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= count || s.done[b]) return;
-    const double rr = sum_parts(part_rr + int64_t(b) * kDotParts);
-    const int it = s.iters[b] + 1;
-    s.rr[b] = rr;
-    s.iters[b] = it;
-    s.done[b] = (it < max_iter && rr > tol * tol * s.bb[b]) ? 0 : 1;
+    if (lead) {
+        const int it = s.iters[b] + 1;
+        s.iters[b] = it;
+        s.rr[nxt] = rr_new;
+        s.done[nxt] = (it < max_iter && rr_new > tol * tol * s.bb[b]) ? 0 : 1;
+    }
 }
 
 // ------------------------------------------------------ percentile trim ---

@@ -547,10 +547,23 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
     }
 }
 
-// EPI 0: c_out = A^T s;  1, 2: c_out = c_in - tau * A^T r (c_in may alias c_out)
+// Sum over the 64 lanes of a wave in a fixed butterfly order; every lane gets it.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = kWave / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, kWave);
+    return v;
+}
+
+// Partial sums of the conjugate-gradient epilogue: one per row pair.
+constexpr int kCgRowParts = 512;
+
+// EPI 0: c_out = A^T s;  1, 2: c_out = c_in - tau * A^T r (c_in may alias c_out);
+// 3 (conjugate gradients): c_out = conv + tau * c_in with tau = nu and c_in = p,
+// and part[row pair] = the row pair's sum of c_in * c_out in float64.
 template <typename T, int M, int EPI>
 __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int slot,
-                              const char* __restrict__ plan, char* __restrict__ work, char* smem) {
+                              const char* __restrict__ plan, char* __restrict__ work, char* smem,
+                              double* __restrict__ part) {
     auto& sm = *reinterpret_cast<RowSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
@@ -559,14 +572,30 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
     const int q = 4 * unit + wave;
     const int r0 = 2 * q, r1 = 2 * q + 1;
     const bool active = r0 < N, two = r1 < N;
+    double acc = 0.0;
     auto put = [&](int i, T v0, T v1) {
         const int64_t o0 = int64_t(r0) * N + i, o1 = int64_t(r1) * N + i;
         if (EPI == 0) {
             c_out[o0] = v0;
             if (two) c_out[o1] = v1;
+        } else if (EPI == 3) {
+            const T p0 = c_in[o0], a0 = v0 + tau * p0;
+            c_out[o0] = a0;
+            acc += double(p0) * double(a0);
+            if (two) {
+                const T p1 = c_in[o1], a1 = v1 + tau * p1;
+                c_out[o1] = a1;
+                acc += double(p1) * double(a1);
+            }
         } else {
             c_out[o0] = c_in[o0] - tau * v0;
             if (two) c_out[o1] = c_in[o1] - tau * v1;
+        }
+    };
+    auto finish = [&]() {
+        if (EPI == 3) {
+            const double tot = wave_sum(acc);
+            if (lane == 0) part[q] = tot;
         }
     };
     if constexpr (M == 512) {                       // register-resident transform, no barrier
@@ -584,6 +613,7 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
 #pragma unroll
         for (int m = 0; m < 8; ++m)
             if (lane + m * kWave < N) put(lane + m * kWave, x[m].x, x[m].y);
+        finish();
     } else {
         TwiddleRegs<T, M, 4 * kWave> twr;
         twr.load(plan, p, tid);
@@ -601,6 +631,81 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
         wave_sync();
         fft_wave<T, true, M>(line, sm.tw, lane);
         for (int i = lane; i < N; i += kWave) put(i, line[i].x, line[i].y);
+        finish();
+    }
+}
+
+// The composition of an inverse row stage and the next forward row stage on
+// the same rows (the middle of C^T C p = C (C p) without writing C p): per row
+// pair, the inverse FFT of T2 rows r0, r1 gives the pair as one complex line;
+// the entries beyond the N grid columns are cut (the convolution's output is
+// the N x N window), and the forward FFT of the cut line gives the half
+// spectra of the two rows, stored to T1[kx][row] as the forward row stage
+// does.
+template <typename T, int M>
+__device__ void rows_inv_fwd_body(const Prob& p, const char* __restrict__ plan, char* __restrict__ work, char* smem) {
+    constexpr int H = M / 2 + 1;
+    const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    const int unit = xcd_unit(blockIdx.x, (N + 7) / 8);   // four row pairs per work-group
+    if (unit < 0) return;
+    const int q = 4 * unit + wave;
+    const int r0 = 2 * q, r1 = 2 * q + 1;
+    const bool active = r0 < N, two = r1 < N;
+    const cx<T>* t2 = at<cx<T>>(work, p.w_t2);
+    const cx<T>* lines;                          // the four waves' forward spectra, natural order
+    int stride;
+    if constexpr (M == 512) {                    // register-resident transforms
+        cx<T>(*xb)[kXbSlots] = reinterpret_cast<cx<T>(*)[kXbSlots]>(smem);
+        if (active) {
+            Fft512Tw<T> tw;
+            tw.load(at<cx<T>>(plan, p.o_tw), lane);
+            PairRegs<T, M> pr;
+            pr.load(t2 + int64_t(r0) * H, t2 + int64_t(two ? r1 : r0) * H, two, lane);
+            cx<T> x[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) x[m] = pr.spectrum(m, lane);
+            fft512_regs<T, true>(x, xb[wave], tw, lane);
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+                if (lane + m * kWave >= N) x[m] = cx<T>{T(0), T(0)};
+            fft512_regs<T, false>(x, xb[wave], tw, lane);
+            wave_sync();
+#pragma unroll
+            for (int m = 0; m < 8; ++m) xb[wave][lane + m * kWave] = x[m];
+        }
+        lines = &xb[0][0];
+        stride = kXbSlots;
+    } else {
+        auto& sm = *reinterpret_cast<RowSmem<T, M>*>(smem);
+        TwiddleRegs<T, M, 4 * kWave> twr;
+        twr.load(plan, p, tid);
+        PairRegs<T, M> pr;
+        if (active) pr.load(t2 + int64_t(r0) * H, t2 + int64_t(two ? r1 : r0) * H, two, lane);
+        twr.store(sm.tw, tid);
+        __syncthreads();
+        if (active) {
+            cx<T>* line = sm.line[wave];
+#pragma unroll
+            for (int m = 0; m < M / kWave; ++m) line[lane + m * kWave] = pr.spectrum(m, lane);
+            wave_sync();
+            fft_wave<T, true, M>(line, sm.tw, lane);
+            for (int i = N + lane; i < M; i += kWave) line[i] = cx<T>{T(0), T(0)};
+            wave_sync();
+            fft_wave<T, false, M>(line, sm.tw, lane);
+        }
+        lines = &sm.line[0][0];
+        stride = M;
+    }
+    __syncthreads();
+    cx<T>* t1 = at<cx<T>>(work, p.w_t1);
+    const int row0 = 8 * unit;
+    for (int i = tid; i < 8 * H; i += 4 * kWave) {
+        const int k = i >> 3, r = i & 7;
+        if (row0 + r >= N) continue;
+        cx<T> A, B;
+        split_pair<T, M>(lines + (r >> 1) * stride, k, A, B);
+        const bool odd = r & 1;
+        t1[int64_t(k) * N + row0 + r] = cx<T>{odd ? B.x : A.x, odd ? B.y : A.y};
     }
 }
 
@@ -667,18 +772,31 @@ __global__ void __launch_bounds__(256) k_adj_cols(const Prob* __restrict__ P, co
     adj_cols_body<T, M, SPLIT, DUAL>(p, plan, work, smem);
 }
 
-// grid.x: xcd_grid(ceil(row pairs / 4)), 256 threads; slot: which T2 field
+// grid.x: xcd_grid(ceil(row pairs / 4)), 256 threads; slot: which T2 field.
+// EPI 3: taus holds nu per problem, part kCgRowParts partial sums per problem.
 template <typename T, int M, int EPI>
 __global__ void __launch_bounds__(256) k_adj_rows(const Prob* __restrict__ P, T* c_out, const T* c_in,
                                                   const double* __restrict__ taus, const char* __restrict__ plan,
-                                                  char* __restrict__ work, int slot, const int* __restrict__ skip) {
+                                                  char* __restrict__ work, int slot, const int* __restrict__ skip,
+                                                  double* __restrict__ part) {
     extern __shared__ __align__(16) char smem[];
     const Prob& p = P[blockIdx.y];
     if (p.mode != 1 || p.m != M || (skip && skip[blockIdx.y])) return;
     const T tau = EPI ? T(taus[blockIdx.y]) : T(0);
     // EPI 2 writes the step into the problem's work buffer u (before the denoiser)
     T* out = EPI == 2 ? at<T>(work, p.w_u) : c_out + p.o_c;
-    adj_rows_body<T, M, EPI>(p, out, EPI ? c_in + p.o_c : nullptr, tau, slot, plan, work, smem);
+    adj_rows_body<T, M, EPI>(p, out, EPI ? c_in + p.o_c : nullptr, tau, slot, plan, work, smem,
+                             EPI == 3 ? part + int64_t(blockIdx.y) * kCgRowParts : nullptr);
+}
+
+// grid.x: xcd_grid(ceil(row pairs / 4)), 256 threads
+template <typename T, int M>
+__global__ void __launch_bounds__(256) k_rows_inv_fwd(const Prob* __restrict__ P, const char* __restrict__ plan,
+                                                      char* __restrict__ work, const int* __restrict__ skip) {
+    extern __shared__ __align__(16) char smem[];
+    const Prob& p = P[blockIdx.y];
+    if (p.mode != 1 || p.m != M || (skip && skip[blockIdx.y])) return;
+    rows_inv_fwd_body<T, M>(p, plan, work, smem);
 }
 
 }  // namespace mpik

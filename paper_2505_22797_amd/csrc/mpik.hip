@@ -301,6 +301,12 @@ struct mpi_plan {
     const void *g_s = nullptr, *g_c = nullptr, *g_work = nullptr;
     double g_sigma = 0;
     int g_rad = -1;
+    // cached graph of a block of CG steps (deconvolution), keyed by its buffers and stop rule
+    hipGraphExec_t cg_exec = nullptr;
+    hipGraph_t cg_graph = nullptr;
+    const void *cg_x = nullptr, *cg_work = nullptr, *cg_dw = nullptr;
+    double cg_tol = -1.0;
+    int cg_max = -1;
 };
 
 namespace {
@@ -400,6 +406,8 @@ hipError_t set_smem_limits(const mpi_plan* pl) {
         chk(allow_smem(k_adj_rows<T, M, 0>, row));
         chk(allow_smem(k_adj_rows<T, M, 1>, row));
         chk(allow_smem(k_adj_rows<T, M, 2>, row));
+        chk(allow_smem(k_adj_rows<T, M, 3>, row));
+        chk(allow_smem(k_rows_inv_fwd<T, M>, row));
     });
     chk(allow_smem(k_gather_rows<T, 4>, pl->smem_dgather));
     chk(allow_smem(k_gather_rows<T, 5>, pl->smem_dgather));
@@ -610,10 +618,10 @@ void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, c
                 constexpr int M = decltype(mc)::value;
                 const dim3 grid(xcd_grid((pl->m_rowpairs[li] + 3) / 4), B);
                 k_adj_rows<T, M, EPI><<<grid, 256, pl->m_smem[li][0], st>>>(P, c_out, c_in, taus, plan, work, 0,
-                                                                            nullptr);
+                                                                            nullptr, nullptr);
                 if (z_out)
                     k_adj_rows<T, M, 0><<<grid, 256, pl->m_smem[li][0], st>>>(P, z_out, nullptr, taus, plan, work, 1,
-                                                                              nullptr);
+                                                                              nullptr, nullptr);
             }, part);
             break;
         case 3:
@@ -1167,12 +1175,12 @@ DeconvLayout deconv_layout(const mpi_plan* pl) {
     L.q = take(off, v);
     L.cu = take(off, v);
     L.rho1 = take(off, v);
-    L.rr = take(off, 8 * B);
+    L.rr = take(off, 2 * 8 * B);             // two slots (step parity)
     L.bb = take(off, 8 * B);
     L.nu = take(off, 8 * B);
     L.iters = take(off, 4 * B);
-    L.done = take(off, 4 * B);
-    L.part_a = take(off, 8 * B * kDotParts);
+    L.done = take(off, 2 * 4 * B);
+    L.part_a = take(off, 8 * B * kCgRowParts);
     L.part_b = take(off, 8 * B * kDotParts);
     L.st_q = take(off, 8 * B);
     L.st_mean = take(off, 8 * B);
@@ -1205,7 +1213,8 @@ void trace_conv_impl(const mpi_plan* pl, const T* in, T* out, char* work, hipStr
             k_fwd_rows<T, M><<<rows, 256, pl->m_smem[li][0], st>>>(P, in, plan, work, skip);
             k_fwd_cols<T, M, false, true><<<dim3(xcd_grid((pl->m_h[li] + 3) / 4), B), 256, pl->m_smem[li][1], st>>>(
                 P, plan, work, 0, skip);
-            k_adj_rows<T, M, 0><<<rows, 256, pl->m_smem[li][0], st>>>(P, out, nullptr, nullptr, plan, work, 0, skip);
+            k_adj_rows<T, M, 0><<<rows, 256, pl->m_smem[li][0], st>>>(P, out, nullptr, nullptr, plan, work, 0, skip,
+                                                                     nullptr);
         });
     if (pl->any_direct) {
         const dim3 grid(pl->max_tiles, pl->max_tiles, B);
@@ -1221,16 +1230,20 @@ void trace_conv_impl(const mpi_plan* pl, const T* in, T* out, char* work, hipStr
     }
 }
 
-// CG on (C^T C + nu_b I) x = cu + nu_b rho2 (rho2 may be null) from x = 0 for
-// every problem; nu_b already in the state.  The host polls the stop flags
-// after 4, 8, 16, 32, 32, ... steps; steps of converged problems are skipped
-// by every kernel.  iters (host, may be null) receives the steps taken.
+// One CG step (parity par) for every problem that has not stopped:
+// q = C(C p) + nu p with the partial sums of <p, q>, then the updates of x, r,
+// p and the next slot of the state.  FFT problems: rows, trace columns, the
+// fused inverse-then-forward rows (C p stays in the transforms), trace
+// columns, and the inverse rows with the CG epilogue -- five launches per size
+// group.  Direct problems: two 1 -> 1 convolutions and k_cg_pq.
 template <typename T>
-int cg_impl(const mpi_plan* pl, const T* cu, const T* rho2, T* x, double tol, int max_iter, char* work, char* dw,
-            const DeconvLayout& L, hipStream_t st, int32_t* iters) {
+void cg_step(const mpi_plan* pl, int par, T* x, double tol, int max_iter, char* work, char* dw,
+             const DeconvLayout& L, hipStream_t st) {
     const Prob* P = pl->dprob;
+    const char* plan = pl->plan;
     const int B = pl->count;
     const CgState s = cg_state(L, dw);
+    const int* skip = s.done + par * B;
     T* r = reinterpret_cast<T*>(dw + L.r);
     T* pv = reinterpret_cast<T*>(dw + L.p);
     T* t = reinterpret_cast<T*>(dw + L.t);
@@ -1238,24 +1251,107 @@ int cg_impl(const mpi_plan* pl, const T* cu, const T* rho2, T* x, double tol, in
     double* pa = reinterpret_cast<double*>(dw + L.part_a);
     double* pb = reinterpret_cast<double*>(dw + L.part_b);
     const dim3 el(kDotParts, B);
-    k_cg_init<T><<<el, 256, 0, st>>>(P, cu, rho2, s, x, r, pv, pa);
+    if (pl->any_fft)
+        each_fft_size<T>(pl, [&](auto mc, int li) {
+            constexpr int M = decltype(mc)::value;
+            const dim3 rows(xcd_grid((pl->m_rowpairs[li] + 3) / 4), B);
+            const dim3 cols(xcd_grid((pl->m_h[li] + 3) / 4), B);
+            const size_t rs = pl->m_smem[li][0], cs = pl->m_smem[li][1];
+            k_fwd_rows<T, M><<<rows, 256, rs, st>>>(P, pv, plan, work, skip);
+            k_fwd_cols<T, M, false, true><<<cols, 256, cs, st>>>(P, plan, work, 0, skip);
+            k_rows_inv_fwd<T, M><<<rows, 256, rs, st>>>(P, plan, work, skip);
+            k_fwd_cols<T, M, false, true><<<cols, 256, cs, st>>>(P, plan, work, 0, skip);
+            k_adj_rows<T, M, 3><<<rows, 256, rs, st>>>(P, q, pv, s.nu, plan, work, 0, skip, pa);
+        });
+    if (pl->any_direct) {
+        const dim3 grid(pl->max_tiles, pl->max_tiles, B);
+        const size_t sm = pl->smem_dfwd;
+        for (int pass = 0; pass < 2; ++pass) {
+            const T* in = pass ? t : pv;
+            T* out = pass ? q : t;
+            if (pl->slice_mask & 1)
+                k_conv_direct<T, 1, 1, 4, 0><<<grid, 256, sm, st>>>(P, in, out, nullptr, nullptr, plan, 1, 1, 0, skip);
+            if (pl->slice_mask & 2)
+                k_conv_direct<T, 1, 1, 8, 0><<<grid, 512, sm, st>>>(P, in, out, nullptr, nullptr, plan, 1, 1, 0, skip);
+            if (pl->slice_mask & 4)
+                k_conv_direct<T, 1, 1, 16, 0><<<grid, 1024, sm, st>>>(P, in, out, nullptr, nullptr, plan, 1, 1, 0,
+                                                                      skip);
+        }
+        k_cg_pq<T><<<el, 256, 0, st>>>(P, s, par, pv, q, pa);
+    }
+    k_cg_update<T><<<el, 256, 0, st>>>(P, s, par, pv, q, x, r, pa, pb);
+    k_cg_dir<T><<<el, 256, 0, st>>>(P, s, par, r, pv, pb, tol, max_iter);
+}
+
+constexpr int kCgBlock = 4;   // CG steps per captured graph (even: each block starts on state slot 0)
+
+// Captures kCgBlock steps into the plan's cached graph unless it already
+// holds them for these buffers and this stop rule.
+template <typename T>
+int cg_graph(mpi_plan* pl, T* x, double tol, int max_iter, char* work, char* dw, const DeconvLayout& L,
+             hipStream_t st) {
+    if (pl->cg_exec && pl->cg_x == x && pl->cg_work == work && pl->cg_dw == dw && pl->cg_tol == tol &&
+        pl->cg_max == max_iter)
+        return MPI_OK;
+    if (pl->cg_exec) {
+        HIP_TRY(hipStreamSynchronize(st));
+        (void)hipGraphExecDestroy(pl->cg_exec);
+        (void)hipGraphDestroy(pl->cg_graph);
+        pl->cg_exec = nullptr;
+        pl->cg_graph = nullptr;
+    }
+    hipStream_t cap;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int i = 0; i < kCgBlock; ++i) cg_step<T>(pl, i & 1, x, tol, max_iter, work, dw, L, cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cap, &g);
+        if (e == hipSuccess) {
+            e = hipGraphInstantiate(&pl->cg_exec, g, nullptr, nullptr, 0);
+            if (e == hipSuccess) pl->cg_graph = g;
+            else (void)hipGraphDestroy(g);
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    }
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess || !pl->cg_exec) {
+        pl->cg_exec = nullptr;
+        return MPI_ERR_HIP;
+    }
+    pl->cg_x = x;
+    pl->cg_work = work;
+    pl->cg_dw = dw;
+    pl->cg_tol = tol;
+    pl->cg_max = max_iter;
+    return MPI_OK;
+}
+
+// CG on (C^T C + nu_b I) x = cu + nu_b rho2 (rho2 may be null) from x = 0 for
+// every problem; nu_b already in the state.  Steps run in captured blocks of
+// kCgBlock (the stop flags make the steps after a problem's last one no-ops);
+// the host polls the flags (slot 0) after every block.  iters (host, may be
+// null) receives the steps taken.
+template <typename T>
+int cg_impl(mpi_plan* pl, const T* cu, const T* rho2, T* x, double tol, int max_iter, char* work, char* dw,
+            const DeconvLayout& L, hipStream_t st, int32_t* iters) {
+    const Prob* P = pl->dprob;
+    const int B = pl->count;
+    const CgState s = cg_state(L, dw);
+    T* r = reinterpret_cast<T*>(dw + L.r);
+    T* pv = reinterpret_cast<T*>(dw + L.p);
+    double* pa = reinterpret_cast<double*>(dw + L.part_a);
+    k_cg_init<T><<<dim3(kDotParts, B), 256, 0, st>>>(P, cu, rho2, s, x, r, pv, pa);
     k_cg_begin<<<blocks(B, 256), 256, 0, st>>>(B, s, pa, tol, max_iter);
     HIP_TRY(hipGetLastError());
+    if (max_iter > 0) {
+        const int rc = cg_graph<T>(pl, x, tol, max_iter, work, dw, L, st);
+        if (rc != MPI_OK) return rc;
+    }
     std::vector<int> done(B);
-    int taken = 0, chunk = 4;
-    while (taken < max_iter) {
-        const int n = std::min(chunk, max_iter - taken);
-        for (int i = 0; i < n; ++i) {
-            trace_conv_impl<T>(pl, pv, t, work, st, s.done);
-            trace_conv_impl<T>(pl, t, q, work, st, s.done);
-            k_cg_pq<T><<<el, 256, 0, st>>>(P, s, pv, q, pa);
-            k_cg_update<T><<<el, 256, 0, st>>>(P, s, pv, q, x, r, pa, pb);
-            k_cg_dir<T><<<el, 256, 0, st>>>(P, s, r, pv, pb);
-            k_cg_state<<<blocks(B, 256), 256, 0, st>>>(B, s, pb, tol, max_iter);
-        }
-        HIP_TRY(hipGetLastError());
-        taken += n;
-        chunk = std::min(2 * chunk, 32);
+    for (int taken = 0; taken < max_iter; taken += kCgBlock) {
+        HIP_TRY(hipGraphLaunch(pl->cg_exec, st));
         HIP_TRY(hipMemcpyAsync(done.data(), s.done, sizeof(int) * B, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (std::all_of(done.begin(), done.end(), [](int d) { return d != 0; })) break;
@@ -1664,11 +1760,12 @@ int mpi_batch_cg(const mpi_plan* plan, const void* rhs, void* x, const double* n
     char* w = static_cast<char*>(work);
     char* dw = static_cast<char*>(dwork);
     HIP_TRY(hipMemcpyAsync(dw + L.nu, nus, sizeof(double) * plan->count, hipMemcpyHostToDevice, stream));
+    mpi_plan* pl = const_cast<mpi_plan*>(plan);
     return plan->dtype == MPI_F64
-               ? cg_impl<double>(plan, static_cast<const double*>(rhs), nullptr, static_cast<double*>(x), tol,
+               ? cg_impl<double>(pl, static_cast<const double*>(rhs), nullptr, static_cast<double*>(x), tol,
                                  max_iter, w, dw, L, stream, iters)
-               : cg_impl<float>(plan, static_cast<const float*>(rhs), nullptr, static_cast<float*>(x), tol, max_iter,
-                                w, dw, L, stream, iters);
+               : cg_impl<float>(pl, static_cast<const float*>(rhs), nullptr, static_cast<float*>(x), tol, max_iter, w,
+                                dw, L, stream, iters);
 }
 
 int mpi_batch_trim_sigma(const mpi_plan* plan, void* x, double pct, double* q, double* sigma, void* work,
@@ -1752,6 +1849,11 @@ int mpi_plan_destroy(mpi_plan* plan) {
         (void)hipDeviceSynchronize();
         (void)hipGraphExecDestroy(plan->gexec);
         (void)hipGraphDestroy(plan->graph);
+    }
+    if (plan->cg_exec) {
+        (void)hipDeviceSynchronize();
+        (void)hipGraphExecDestroy(plan->cg_exec);
+        (void)hipGraphDestroy(plan->cg_graph);
     }
     release_streams(plan);
     delete plan;
