@@ -17,6 +17,7 @@ paper prints no operator values, so no value of the paper itself pins them.
 """
 from .mpi_model import *  # noqa: F401,F403
 from .deconv import *  # noqa: F401,F403
-from . import deconv as _deconv, mpi_model as _mpi_model
+from .core import *  # noqa: F401,F403
+from . import core as _core, deconv as _deconv, mpi_model as _mpi_model
 
-__all__ = list(_mpi_model.__all__) + list(_deconv.__all__)
+__all__ = list(_mpi_model.__all__) + list(_deconv.__all__) + list(_core.__all__)
