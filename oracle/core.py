@@ -21,6 +21,9 @@ Readings (the paper names the functional, the regulariser and the solver):
     with W = diag(1, 2, 1) over the channels, L the number of samples.
   * They are solved by the conjugate gradients of the Deconvolution Stage's
     oracle (from a = 0, relative residual tolerance, step cap).
+  * With only the x receive channel (channels "x", Section "Experiment 2")
+    the data term has s_x alone; A_yy then only meets the regulariser and
+    stays 0 from a = 0.
 """
 from __future__ import annotations
 
@@ -47,34 +50,37 @@ def laplacian(a: np.ndarray) -> np.ndarray:
     return out * (n / 2.0) ** 2
 
 
-def core_objective(a, s, r, v, gamma, interp="cosine") -> float:
+def core_objective(a, s, r, v, gamma, interp="cosine", channels="xy") -> float:
     """(1/L) sum_k |s_k - M(a(r_k)) v_k|^2 + gamma * delta^2 * sum |Delta a|_F^2
     (eq. first:step, discretised as above)."""
     a = np.asarray(a, dtype=np.float64)
     n = a.shape[-1]
-    res = np.asarray(s, dtype=np.float64) - gather(a, r, v, interp=interp)
+    s = np.array(s, dtype=np.float64)
+    if channels == "x":
+        s[:, 1] = 0.0
+    res = s - gather(a, r, v, interp=interp, channels=channels)
     lap = laplacian(a)
     reg = (2.0 / n) ** 2 * float(np.sum(CHANNEL_WEIGHTS[:, None, None] * lap * lap))
     return float(np.sum(res * res)) / res.shape[0] + gamma * reg
 
 
-def core_normal(a, r, v, gamma, interp="cosine") -> np.ndarray:
+def core_normal(a, r, v, gamma, interp="cosine", channels="xy") -> np.ndarray:
     """(1/L) I^T I a + gamma delta^2 W Delta Delta a."""
     a = np.asarray(a, dtype=np.float64)
     n = a.shape[-1]
     L = np.asarray(r).shape[0]
-    data = scatter(gather(a, r, v, interp=interp), r, v, n, interp=interp) / L
+    data = scatter(gather(a, r, v, interp=interp, channels=channels), r, v, n, interp=interp, channels=channels) / L
     return data + gamma * (2.0 / n) ** 2 * CHANNEL_WEIGHTS[:, None, None] * laplacian(laplacian(a))
 
 
-def core_rhs(s, r, v, n, interp="cosine") -> np.ndarray:
+def core_rhs(s, r, v, n, interp="cosine", channels="xy") -> np.ndarray:
     """(1/L) I^T s."""
-    return scatter(s, r, v, n, interp=interp) / np.asarray(r).shape[0]
+    return scatter(s, r, v, n, interp=interp, channels=channels) / np.asarray(r).shape[0]
 
 
-def core_stage(s, r, v, n, gamma, tol=1e-3, max_iter=10000, interp="cosine"):
+def core_stage(s, r, v, n, gamma, tol=1e-3, max_iter=10000, interp="cosine", channels="xy"):
     """The field minimising eq. first:step by CG on its Euler-Lagrange
     equations from a = 0.  Returns (field [3, N, N], CG steps)."""
-    b = core_rhs(s, r, v, n, interp)
-    a, steps, _ = cg(lambda x: core_normal(x, r, v, gamma, interp), b, tol, max_iter)
+    b = core_rhs(s, r, v, n, interp, channels)
+    a, steps, _ = cg(lambda x: core_normal(x, r, v, gamma, interp, channels), b, tol, max_iter)
     return a, steps

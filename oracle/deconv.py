@@ -25,6 +25,10 @@ Readings (the paper gives the loop, not every detail):
   * The learned denoiser is replaced by the separable Gaussian of the
     iteration (its noise-level argument has no role in the stand-in); None
     means the identity.
+  * With only the x receive channel (Section "Experiment 2") the trace is not
+    available and the first diagonal entry is deconvolved with the first
+    diagonal entry of the kernel: `which="xx"` uses delta^2 K_xx in place of
+    delta^2 kappa_h.  `grad` is the kernel's gradient as in the operator.
 """
 from __future__ import annotations
 
@@ -32,20 +36,26 @@ import math
 
 import numpy as np
 
-from .mpi_model import conv, denoise, trace_kernel_table
+from .mpi_model import conv, denoise, kernel_table, trace_kernel_table
 
 __all__ = ["trace_taps", "trace_conv", "cg", "percentile", "percentile_clamp", "noise_sigma", "zeroshot_pnp"]
 
 
-def trace_taps(n: int, h: float, radius: int) -> np.ndarray:
-    """delta^2 kappa_h at the integer offsets of the window, [2R+1, 2R+1]."""
-    return (2.0 / n) ** 2 * trace_kernel_table(n, h, radius)
+def trace_taps(n: int, h: float, radius: int, which: str = "trace", grad=(1.0, 1.0)) -> np.ndarray:
+    """delta^2 kappa_h (which "trace") or delta^2 K_h,xx (which "xx") at the
+    integer offsets of the window, [2R+1, 2R+1]."""
+    if which == "trace":
+        return (2.0 / n) ** 2 * trace_kernel_table(n, h, radius, grad)
+    if which == "xx":
+        return (2.0 / n) ** 2 * kernel_table(n, h, radius, grad)[0]
+    raise ValueError(f"unknown deconvolution kernel {which!r}")
 
 
-def trace_conv(x: np.ndarray, h: float, radius: int, method: str = "auto") -> np.ndarray:
+def trace_conv(x: np.ndarray, h: float, radius: int, method: str = "auto", which: str = "trace",
+               grad=(1.0, 1.0)) -> np.ndarray:
     """C_h x (eq. convolution:trace): zero outside the grid, linear convolution."""
     x = np.asarray(x, dtype=np.float64)
-    return conv(x, trace_taps(x.shape[0], h, radius), method)
+    return conv(x, trace_taps(x.shape[0], h, radius, which, grad), method)
 
 
 def cg(apply, b: np.ndarray, tol: float, max_iter: int):
@@ -98,13 +108,13 @@ def noise_sigma(x: np.ndarray) -> float:
 
 
 def zeroshot_pnp(u, h, radius, n_it, nu0, tol=1e-3, max_iter=10000, clip_pct=5.0, sigma_px=0.5, radius_d=2,
-                 method="auto"):
+                 method="auto", which="trace", grad=(1.0, 1.0)):
     """The ZeroShot-PnP deconvolution of the trace image u.  clip_pct None
     disables trimming, sigma_px None makes the denoiser the identity.
     Returns (rho_2, info) with the CG step counts, the noise estimates, the
     nu used by every pass and lambda."""
     u = np.asarray(u, dtype=np.float64)
-    taps = trace_taps(u.shape[0], h, radius)          # the table of C, built once
+    taps = trace_taps(u.shape[0], h, radius, which, grad)   # the table of C, built once
     apply_c = lambda x: conv(x, taps, method)
     cu = apply_c(u)                                   # C^T u (C symmetric)
     rho2 = np.zeros_like(u)

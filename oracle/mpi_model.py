@@ -29,7 +29,7 @@ __all__ = [
     "DomainError", "langevin", "langevin_d1", "langevin_d2",
     "kernel_h", "kernel_h_dh", "trace_kernel_h", "kernel_table", "kernel_table_dh",
     "trace_kernel_table", "effective_radius", "fft_size", "conv_direct", "conv_fft", "conv", "conv_adj",
-    "bilinear", "interp_weight", "interp_weight_d", "INTERPS", "gather", "scatter", "forward", "adjoint", "gauss_weights", "denoise",
+    "bilinear", "interp_weight", "interp_weight_d", "INTERPS", "CHANNELS", "gather", "velocity_forward_difference", "scatter", "forward", "adjoint", "gauss_weights", "denoise",
     "iterate", "power_lambda_max", "unrolled_gradients", "Model",
 ]
 
@@ -168,20 +168,24 @@ def effective_radius(n: int, radius: int) -> int:
     return min(int(radius), n - 1)
 
 
-def kernel_table(n: int, h: float, radius: int) -> np.ndarray:
-    """[3, 2R+1, 2R+1] point samples K_h(delta (dx, dy)), index [ch, dy+R, dx+R]."""
+# The selection-field gradient G = diag(gx, gy) (Section "Experiment 2"): the
+# kernel is evaluated at G y, K_h(G y), and the velocity that multiplies it is
+# -G dr/dt (the caller's).  The isotropic setting of the rest of the paper is
+# G = -I, for which K_h(G y) = K_h(y) (K is even); grad=(1, 1) gives the same.
+def kernel_table(n: int, h: float, radius: int, grad=(1.0, 1.0)) -> np.ndarray:
+    """[3, 2R+1, 2R+1] point samples K_h(G delta (dx, dy)), index [ch, dy+R, dx+R]."""
     R, DX, DY, d = _offsets(n, radius)
-    return np.stack(kernel_h(d * DX, d * DY, h))
+    return np.stack(kernel_h(grad[0] * d * DX, grad[1] * d * DY, h))
 
 
-def kernel_table_dh(n: int, h: float, radius: int) -> np.ndarray:
+def kernel_table_dh(n: int, h: float, radius: int, grad=(1.0, 1.0)) -> np.ndarray:
     R, DX, DY, d = _offsets(n, radius)
-    return np.stack(kernel_h_dh(d * DX, d * DY, h))
+    return np.stack(kernel_h_dh(grad[0] * d * DX, grad[1] * d * DY, h))
 
 
-def trace_kernel_table(n: int, h: float, radius: int) -> np.ndarray:
+def trace_kernel_table(n: int, h: float, radius: int, grad=(1.0, 1.0)) -> np.ndarray:
     R, DX, DY, d = _offsets(n, radius)
-    return trace_kernel_h(d * DX, d * DY, h)
+    return trace_kernel_h(grad[0] * d * DX, grad[1] * d * DY, h)
 
 
 # ----------------------------------------------------------------------------
@@ -312,21 +316,29 @@ def _corners(r, n, frozen=None, interp="bilinear"):
             ((jy + 1, ix), (1 - wx) * wy), ((jy + 1, ix + 1), wx * wy)]
 
 
-def gather(G: np.ndarray, r: np.ndarray, v: np.ndarray, frozen=None, interp="bilinear") -> np.ndarray:
+CHANNELS = ("xy", "x")
+
+
+def gather(G: np.ndarray, r: np.ndarray, v: np.ndarray, frozen=None, interp="bilinear", channels="xy") -> np.ndarray:
     """s_k = G(r_k) v_k with G = [G_xx, G_xy, G_yy] interpolated from the four
-    surrounding cell centres."""
+    surrounding cell centres.  channels "x": only the x receive channel is
+    measured (Section "Experiment 2"): s_x = (G_xx, G_xy) v, and s_y is 0."""
     n = G.shape[-1]
     g = np.zeros((3, r.shape[0]))
     for (j, i), w in _corners(r, n, frozen, interp):
         g += w * G[:, j, i]
     v = np.asarray(v, dtype=np.float64)
-    return np.stack([g[0] * v[:, 0] + g[1] * v[:, 1], g[1] * v[:, 0] + g[2] * v[:, 1]], 1)
+    sy = np.zeros(r.shape[0]) if channels == "x" else g[1] * v[:, 0] + g[2] * v[:, 1]
+    return np.stack([g[0] * v[:, 0] + g[1] * v[:, 1], sy], 1)
 
 
-def scatter(y: np.ndarray, r: np.ndarray, v: np.ndarray, n: int, frozen=None, interp="bilinear") -> np.ndarray:
+def scatter(y: np.ndarray, r: np.ndarray, v: np.ndarray, n: int, frozen=None, interp="bilinear",
+            channels="xy") -> np.ndarray:
     """Transpose of gather: G'_ch(q) = sum_k w_kq p_k,ch with the products
-    p = (y_x v_x, y_x v_y + y_y v_x, y_y v_y)."""
-    y = np.asarray(y, dtype=np.float64)
+    p = (y_x v_x, y_x v_y + y_y v_x, y_y v_y) (y_y taken as 0 for channels "x")."""
+    y = np.array(y, dtype=np.float64)
+    if channels == "x":
+        y[:, 1] = 0.0
     v = np.asarray(v, dtype=np.float64)
     p = np.stack([y[:, 0] * v[:, 0], y[:, 0] * v[:, 1] + y[:, 1] * v[:, 0], y[:, 1] * v[:, 1]])
     out = np.zeros((3, n * n))
@@ -334,6 +346,16 @@ def scatter(y: np.ndarray, r: np.ndarray, v: np.ndarray, n: int, frozen=None, in
         for ch in range(3):
             out[ch] += np.bincount(j * n + i, weights=w * p[ch], minlength=n * n)
     return out.reshape(3, n, n)
+
+
+def velocity_forward_difference(r: np.ndarray, dt: float) -> np.ndarray:
+    """v_k = (r_{k+1} - r_k) / dt from the sampled positions (Section
+    "Experiment 2"); the last sample repeats the previous difference."""
+    r = np.asarray(r, dtype=np.float64)
+    v = np.empty_like(r)
+    v[:-1] = (r[1:] - r[:-1]) / dt
+    v[-1] = v[-2] if r.shape[0] > 1 else 0.0
+    return v
 
 
 def forward(c, r, v, h, radius, method="auto", interp="bilinear"):
@@ -375,18 +397,23 @@ def denoise(c: np.ndarray, sigma_px: float, radius: int) -> np.ndarray:
 class Model:
     """A and A^T for one problem with the kernel table and sample cells cached.
     frozen = (ix, jy) fixes the base cells (see `bilinear`); interp is
-    "bilinear" or "cosine" (see `interp_weight`)."""
+    "bilinear" or "cosine" (see `interp_weight`); grad = (gx, gy) the gradient
+    of the kernel table; channels "xy" or "x" (see `gather`)."""
 
-    def __init__(self, n, h, radius, r, v, method="auto", frozen=None, interp="bilinear"):
+    def __init__(self, n, h, radius, r, v, method="auto", frozen=None, interp="bilinear", grad=(1.0, 1.0),
+                 channels="xy"):
         if interp not in INTERPS:
             raise ValueError(f"unknown interpolator {interp!r}")
+        if channels not in CHANNELS:
+            raise ValueError(f"unknown channels {channels!r}")
         self.n, self.h, self.radius, self.method, self.interp = n, h, radius, method, interp
+        self.grad, self.channels = (float(grad[0]), float(grad[1])), channels
         self.r = np.asarray(r, dtype=np.float64)
         self.v = np.asarray(v, dtype=np.float64)
         if frozen is None:
             bilinear(self.r, n)                      # domain check up front
         self.frozen = frozen
-        self.taps = (2.0 / n) ** 2 * kernel_table(n, h, radius)
+        self.taps = (2.0 / n) ** 2 * kernel_table(n, h, radius, self.grad)
 
     def cells(self):
         ix, jy, _, _ = bilinear(self.r, self.n, self.frozen)
@@ -396,10 +423,11 @@ class Model:
         return conv(c, self.taps, self.method)
 
     def forward(self, c):
-        return gather(self.field(c), self.r, self.v, self.frozen, self.interp)
+        return gather(self.field(c), self.r, self.v, self.frozen, self.interp, self.channels)
 
     def adjoint(self, y):
-        return conv_adj(scatter(y, self.r, self.v, self.n, self.frozen, self.interp), self.taps, self.method)
+        return conv_adj(scatter(y, self.r, self.v, self.n, self.frozen, self.interp, self.channels), self.taps,
+                        self.method)
 
     def normal(self, c):
         return self.adjoint(self.forward(c))
@@ -407,8 +435,8 @@ class Model:
     # ---- derivatives (the VJP building blocks) ----
     def forward_dh(self, x):
         """(dA/dh) x: the sampling of the convolution with delta^2 dK_h/dh."""
-        dtaps = (2.0 / self.n) ** 2 * kernel_table_dh(self.n, self.h, self.radius)
-        return gather(conv(x, dtaps, self.method), self.r, self.v, self.frozen, self.interp)
+        dtaps = (2.0 / self.n) ** 2 * kernel_table_dh(self.n, self.h, self.radius, self.grad)
+        return gather(conv(x, dtaps, self.method), self.r, self.v, self.frozen, self.interp, self.channels)
 
     def traj_vjp(self, x, y):
         """Gradients of <y, A x> with respect to every sample's position r_k and
@@ -426,7 +454,9 @@ class Model:
         dwy = (n / 2.0) * interp_weight_d(fy, self.interp)
         dgx = dwx * ((1 - wy) * (g10 - g00) + wy * (g11 - g01))
         dgy = dwy * ((1 - wx) * (g01 - g00) + wx * (g11 - g10))
-        y = np.asarray(y, dtype=np.float64)
+        y = np.array(y, dtype=np.float64)
+        if self.channels == "x":
+            y[:, 1] = 0.0
         v = self.v
 
         def contract(m, a):        # M(m) a with M = [[m0, m1], [m1, m2]]
