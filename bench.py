@@ -119,6 +119,9 @@ def main() -> int:
     ap.add_argument("--no-window", action="store_true")
     ap.add_argument("--no-cosine", action="store_true")
     ap.add_argument("--no-deconv", action="store_true")
+    ap.add_argument("--no-two-stage", action="store_true")
+    ap.add_argument("--two-stage-only", action="store_true",
+                    help="only the two-stage reconstruction (for a kernel trace of its kernels)")
     ap.add_argument("--deconv-only", action="store_true",
                     help="only the deconvolution workload (for a kernel trace of its kernels)")
     ap.add_argument("--grad-only", action="store_true",
@@ -146,6 +149,9 @@ def main() -> int:
         return 0
     if args.deconv_only:
         print(json.dumps({"deconvolution": deconvolution(mpik, S, dev, False)}))
+        return 0
+    if args.two_stage_only:
+        print(json.dumps({"two_stage": two_stage(mpik, S, dev, False)}))
         return 0
     r = torch.tensor(S.to_f32(P.traj.r), dtype=torch.float32, device=dev)
     v = torch.tensor(S.to_f32(P.traj.v), dtype=torch.float32, device=dev)
@@ -236,6 +242,8 @@ def main() -> int:
         out["iteration_configs"] = iteration_configs(mpik, S, dev, not args.no_cpu_baseline)
     if not args.no_deconv:
         out["deconvolution"] = deconvolution(mpik, S, dev, not args.no_cpu_baseline)
+    if not args.no_two_stage:
+        out["two_stage"] = two_stage(mpik, S, dev, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_seconds)
     print(json.dumps(out))
@@ -379,6 +387,79 @@ def deconvolution(mpik, S, dev, with_oracle, count=64, n_it=9, snr_db=30.0):
         rec["oracle_deconvolutions_per_s"] = round(1.0 / dt, 4)
         rec["oracle_sample"] = "one 256^2 problem, the same ten passes, float64 numpy on one host thread"
     del b1, u1
+    torch.cuda.empty_cache()
+    return rec
+
+
+def two_stage(mpik, S, dev, with_oracle, count=64, snr_db=30.0, gamma=1e-3):
+    """The paper's reconstruction from the signals: Core Stage (variational
+    field reconstruction with cosine interpolation, gamma = 1e-3, CG tolerance
+    1e-3), trace image, then the ZeroShot-PnP deconvolution (ten passes,
+    nu0 = 1e-5, tolerance 1e-3, 5% trimming, Gaussian stand-in).  `count`
+    problems of the headline shape (256^2, 53,856 Lissajous samples, full
+    kernel R = 255 for the trace convolution), float32; the signals
+    s = A c + noise (ellipse-and-line phantoms, 30 dB) are made on the device
+    before the timed region.  The float64 oracle's Core Stage step rate is
+    measured on a bounded sample of steps of one problem."""
+    import numpy as np
+    import torch
+    P = S.headline()
+    n, R, t = P.n, 255, P.n_samples
+    r = torch.tensor(S.to_f32(P.traj.r), dtype=torch.float32, device=dev)
+    v = torch.tensor(S.to_f32(P.traj.v), dtype=torch.float32, device=dev)
+    batch = mpik.Batch([(n, P.h, R, r, v, "fft", "cosine")] * count, tune=False)
+    c = np.stack([S.ellipses_and_line(n, 200 + b) for b in range(count)])
+    clean = batch.forward(torch.tensor(c, dtype=torch.float32, device=dev).reshape(-1))
+    clean = clean.double().cpu().numpy().reshape(count, t, 2)
+    s_all = torch.tensor(S.to_f32(np.stack([S.add_noise(clean[b], snr_db, seed=b) for b in range(count)])),
+                         dtype=torch.float32, device=dev).reshape(-1)
+    pnp_kw = dict(n_it=9, nu0=1e-5, tol=1e-3, max_iter=10000, clip_pct=5.0, sigma_px=0.5, radius=2)
+
+    def run():
+        field, steps = batch.core_stage(s_all, gamma=gamma, tol=1e-3, max_iter=10000)
+        u = batch.field_trace(field)
+        rho, info = batch.pnp(u, **pnp_kw)
+        return field, steps, rho, info
+
+    run()                                                     # warm: workspaces, graphs
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    field, steps = batch.core_stage(s_all, gamma=gamma, tol=1e-3, max_iter=10000)
+    ev[1].record()
+    rho, info = batch.pnp(batch.field_trace(field), **pnp_kw)
+    ev[2].record()
+    torch.cuda.synchronize()
+    core_ms, pnp_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    rho_h = rho.double().cpu().numpy().reshape(count, n, n)
+    err = float(np.mean([np.linalg.norm(rho_h[b] - c[b]) / np.linalg.norm(c[b]) for b in range(count)]))
+    rec = {"workload": f"two_stage_256: {count} x (256^2 grid, 53,856 samples, cosine interpolation) Core Stage "
+                       f"gamma={gamma:g} tol 1e-3, trace, ZeroShot-PnP 10 passes (R=255 FFT)",
+           "problems": count, "dtype": "f32", "ms": round(core_ms + pnp_ms, 3),
+           "reconstructions_per_s": round(count * 1e3 / (core_ms + pnp_ms), 2),
+           "core_stage_ms": round(core_ms, 3), "core_cg_steps_max": int(max(steps)),
+           "ms_per_batched_core_step": round(core_ms / max(1, max(steps)), 4),
+           "deconvolution_ms": round(pnp_ms, 3),
+           "relative_error_to_phantom": round(err, 4)}
+    if with_oracle:
+        try:
+            from threadpoolctl import threadpool_limits
+            limiter = threadpool_limits(1)
+        except Exception:
+            limiter = None
+        import oracle as O
+        rr, vv = S.to_f32(P.traj.r), S.to_f32(P.traj.v)
+        s0 = s_all[:2 * t].double().cpu().numpy().reshape(t, 2)
+        b0 = O.core_rhs(s0, rr, vv, n)
+        k = 40
+        t0 = time.perf_counter()
+        O.cg(lambda a: O.core_normal(a, rr, vv, gamma), b0, 0.0, k)
+        dt = time.perf_counter() - t0
+        if limiter is not None:
+            limiter.restore_original_limits()
+        rec["oracle_core_steps_per_s"] = round(k / dt, 2)
+        rec["oracle_sample"] = f"{k} Core Stage CG steps of one 256^2 problem, float64 numpy, one host thread"
+    del batch, s_all, field, rho
     torch.cuda.empty_cache()
     return rec
 

@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define MPIK_ABI_VERSION 1
+#define MPIK_ABI_VERSION 2
 
 typedef enum {
     MPI_OK = 0,
@@ -72,7 +72,11 @@ enum { MPI_CONV_AUTO = 0, MPI_CONV_DIRECT = 1, MPI_CONV_FFT = 2 };
  * the cosine interpolation the paper names for the core stage (section on
  * the core stage; the formula is the textbook scheme, C^1 across cells). */
 enum { MPI_INTERP_BILINEAR = 0, MPI_INTERP_COSINE = 1 };
-enum { MPI_CH_XY = 0 };
+/* Receive channels: both, or the x channel alone (Section "Experiment 2":
+ * s_x = (A_xx, A_xy) v; the library writes s_y = 0 and ignores the y
+ * components of the signals it reads; the Deconvolution Stage then inverts
+ * the convolution with K_xx in place of the trace kernel). */
+enum { MPI_CH_XY = 0, MPI_CH_X = 1 };
 
 /* One reconstruction problem.  r and v are device pointers to [T][2] arrays
  * of the given dtype, read only during mpi_kernel_build. */
@@ -83,10 +87,15 @@ typedef struct {
     int32_t radius;        /* window half-width R >= 0 in pixels; capped N-1   */
     int32_t conv_mode;     /* MPI_CONV_*: selects speed only, never the result */
     int32_t interp;        /* MPI_INTERP_BILINEAR or MPI_INTERP_COSINE         */
-    int32_t channels;      /* MPI_CH_XY: both signal channels                  */
+    int32_t channels;      /* MPI_CH_XY or MPI_CH_X                            */
     int64_t n_samples;     /* T >= 1, T < 2^26                                 */
     const void* r;         /* device [T][2] sample positions r_k               */
-    const void* v;         /* device [T][2] velocities v_k = dr/dt(t_k)        */
+    const void* v;         /* device [T][2] velocities: -G dr/dt(t_k) (= dr/dt  */
+                           /* for the isotropic G = -I)                        */
+    double grad_x, grad_y; /* selection-field gradient G = diag(grad_x, grad_y) */
+                           /* in units of the isotropic one: the kernel is     */
+                           /* evaluated at G y (Section "Experiment 2"); both  */
+                           /* 0 means (1, 1), else both finite and nonzero     */
 } mpi_problem;
 
 /* Parameters of mpi_iterate: c <- D(c - tau A^T (A c - s)), n_iter times.
@@ -273,7 +282,9 @@ int mpi_batch_unrolled_vjp(const mpi_plan* plan, const void* s_all, const void* 
  * mpi_batch_trace_conv: y_b = C_b x_b, the convolution with delta^2 kappa_h,
  *   kappa_h = tr K_h the trace kernel (eq. kernel:trace), on the problem's
  *   window and path: the trace of the operator's field (eq.
- *   convolution:trace).  C_b is symmetric.  x != y.  Enqueued on `stream`.
+ *   convolution:trace); for MPI_CH_X problems delta^2 K_xx instead (the
+ *   trace is not measured; Section "Experiment 2").  Both include the
+ *   problem's gradient G.  C_b is symmetric.  x != y.  Enqueued on `stream`.
  *
  * mpi_batch_cg: for every problem, conjugate gradients on
  *   (C_b^T C_b + nus[b] I) x_b = rhs_b started from x_b = 0 (the normal
@@ -326,6 +337,47 @@ int mpi_batch_trim_sigma(const mpi_plan* plan, void* x_all, double pct, double* 
 int mpi_batch_pnp(const mpi_plan* plan, const void* u_all, void* rho_all, const mpi_pnp_params* params,
                   int32_t* cg_iters, double* sigmas, double* nus, void* work, size_t work_bytes, void* dwork,
                   size_t dbytes, hipStream_t stream);
+
+/* ---------------------------------------------------------- core stage --
+ * The Core Stage (Section "MPI Core Stage", eq. first:step): for every
+ * problem, the symmetric core-operator field a = [A_xx, A_xy, A_yy] on the
+ * N x N grid that minimises
+ *   (1/L) sum_k |s_k - M(a(r_k)) v_k|^2 + gamma * delta^2 * sum |Delta a|_F^2,
+ * with the plan's samples, velocities and interpolation weights (the paper
+ * uses MPI_INTERP_COSINE), L = T, delta = 2/N, Delta the 5-point graph
+ * Laplacian over in-grid neighbours (over delta^2) and the Frobenius norm of
+ * the symmetric 2x2 field (the off-diagonal channel counted twice).  Solved
+ * by conjugate gradients on the Euler-Lagrange equations
+ *   (1/L) I^T I a + gamma delta^2 W Delta Delta a = (1/L) I^T s,  W = diag(1, 2, 1),
+ * from a = 0, stopping per problem once the recursively updated residual
+ * meets |r| <= tol |rhs| or after max_iter steps (the paper: tol 1e-3,
+ * 10,000 steps).  s_all: signals in time order as for mpi_batch_forward;
+ * field_all: 3 * c_elems values, problem b's [3][N][N] field (channels xx,
+ * xy, yy) at element offset 3 * c_offsets[b].  iters: host array of count
+ * step counts (may be NULL).  cwork: caller-owned device memory of at least
+ * mpi_batch_core_bytes(plan) bytes, 256-byte aligned.  MPI_ERR_UNSUPPORTED
+ * when the row-wise sampling of the largest grid does not fit in LDS.
+ * Synchronises `stream` (the stop flags are polled between blocks of steps).
+ *
+ * mpi_batch_field_trace: u_b = A_xx + A_yy of every problem's field (the
+ * trace image that the Deconvolution Stage inverts, eq. convolution:trace);
+ * u_all concentration-shaped.  For MPI_CH_X problems the Core Stage leaves
+ * A_yy = 0 (no data reaches it), so u_b = A_xx, the image the Deconvolution
+ * Stage then inverts with K_xx.  Enqueued on `stream`. */
+int mpi_batch_core_bytes(const mpi_plan* plan, size_t* bytes);
+int mpi_batch_core_stage(const mpi_plan* plan, const void* s_all, void* field_all, double gamma, double tol,
+                         int32_t max_iter, int32_t* iters, void* work, size_t work_bytes, void* cwork, size_t cbytes,
+                         hipStream_t stream);
+int mpi_batch_field_trace(const mpi_plan* plan, const void* field_all, void* u_all, hipStream_t stream);
+
+/* Velocities by forward differences of sampled positions (Section
+ * "Experiment 2"): v_k = (r_{k+1} - r_k) / dt for k < T-1, and v_{T-1} =
+ * v_{T-2}; evaluated in float64 and rounded to the dtype.  r, v: device
+ * [T][2] arrays of `dtype`, r != v, T >= 2, dt > 0.  For a gradient G the
+ * operator's velocity is -G times this (the caller's scaling).  Enqueued on
+ * `stream`. */
+int mpi_velocity_forward_difference(const void* r, void* v, int64_t n_samples, double dt, int32_t dtype,
+                                    hipStream_t stream);
 
 /* Diagnostics for timing one kernel at a time.  The forward operator and its
  * transpose each run as a short sequence of kernels (stages); stages

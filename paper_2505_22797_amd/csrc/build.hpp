@@ -66,7 +66,9 @@ __global__ void k_table(const Prob* __restrict__ P, char* __restrict__ plan, con
     if (idx >= W * W) return;
     const int dy = idx / W - R, dx = idx % W - R;
     const double h = p.h, delta = 2.0 / p.n;
-    const double q = double(dx * dx + dy * dy);
+    // the kernel at G y (selection-field gradient G = diag(gx, gy); exact for G = I)
+    const double ex = p.gx * dx, ey = p.gy * dy;
+    const double q = ex * ex + ey * ey;
     double kxx, kxy, kyy;
     if (q == 0.0) {
         kxx = kyy = deriv ? -1.0 / (3.0 * h * h) : 1.0 / (3.0 * h);
@@ -78,9 +80,9 @@ __global__ void k_table(const Prob* __restrict__ P, char* __restrict__ plan, con
         double a, b, s;
         if (!deriv) { a = L1; b = L / r; s = 1.0 / (q * h); }
         else { a = L1 + r * L2; b = L1; s = -1.0 / (q * h * h); }
-        kxx = (a * dx * dx + b * dy * dy) * s;
-        kxy = (a - b) * dx * dy * s;
-        kyy = (a * dy * dy + b * dx * dx) * s;
+        kxx = (a * ex * ex + b * ey * ey) * s;
+        kxy = (a - b) * ex * ey * s;
+        kyy = (a * ey * ey + b * ex * ex) * s;
     }
     const int plane = W * W;
     if (tab64) {

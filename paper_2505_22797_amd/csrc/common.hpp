@@ -45,7 +45,8 @@ struct Prob {
     int32_t taps_w;    // padded row length of the direct-path tap table
     int32_t slices;    // direct path: waves splitting the dy range of a tile
     int32_t interp;    // 0 bilinear, 1 cosine (the weights in o_samp already applied)
-    int32_t pad0;
+    int32_t chan;      // 0 both receive channels, 1 the x channel alone
+    double gx, gy;     // selection-field gradient G = diag(gx, gy): the kernel is K_h(G y)
     int64_t t;         // samples
     double h;
     int64_t o_c;       // element offset of this problem's concentration in the caller's buffer

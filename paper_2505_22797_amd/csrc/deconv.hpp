@@ -38,9 +38,12 @@ __device__ __forceinline__ double sum_parts(const double* __restrict__ part, int
     return s;
 }
 
-// Partial sums of <p, q> per problem: kCgRowParts slots; the FFT row stage
-// fills one per row pair, the direct path's k_cg_pq the first kDotParts.
-__device__ __forceinline__ int pq_parts(const Prob& p) { return p.mode == 1 ? (p.n + 1) / 2 : kDotParts; }
+// Partial sums of <p, q> per problem (`stride` slots): the FFT row stage
+// fills one per row pair, the direct path's k_cg_pq the first kDotParts, the
+// Core Stage's transpose sampling one per grid row (pq_kind 1).
+__device__ __forceinline__ int pq_parts(const Prob& p, int pq_kind) {
+    return pq_kind == 1 ? p.n : (p.mode == 1 ? (p.n + 1) / 2 : kDotParts);
+}
 
 // The work-group's slice [lo, hi) of a problem with m elements.
 __device__ __forceinline__ void slice_of(int64_t m, int64_t& lo, int64_t& hi) {
@@ -71,15 +74,18 @@ __device__ __forceinline__ double broadcast0(double v, double* slot) {
 }
 
 // ------------------------------------------------------------------ CG ---
+// The CG vectors hold `comps` values per grid cell (1: concentrations, 3:
+// the Core Stage's field), at element offset comps * o_c.
+//
 // grid (kDotParts, problems), 256 threads.  b = cu + nu rho2 (rho2 may be
 // null: b = cu); x = 0, r = p = b; part = slices of |b|^2.
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_init(const Prob* __restrict__ P, const T* __restrict__ cu,
+__global__ void __launch_bounds__(256) k_cg_init(const Prob* __restrict__ P, int comps, const T* __restrict__ cu,
                                                  const T* __restrict__ rho2, CgState s, T* __restrict__ x,
                                                  T* __restrict__ r, T* __restrict__ pv, double* __restrict__ part) {
     __shared__ double red[256];
     const Prob& p = P[blockIdx.y];
-    const int64_t m = int64_t(p.n) * p.n, o = p.o_c;
+    const int64_t m = int64_t(comps) * p.n * p.n, o = int64_t(comps) * p.o_c;
     int64_t lo, hi;
     slice_of(m, lo, hi);
     const T nu = T(s.nu[blockIdx.y]);
@@ -131,20 +137,22 @@ __global__ void __launch_bounds__(256) k_cg_pq(const Prob* __restrict__ P, CgSta
 
 // alpha = rr / <p, q>; x += alpha p; r -= alpha q; part_rr = slices of |r|^2.
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_update(const Prob* __restrict__ P, CgState s, int par,
-                                                   const T* __restrict__ pv, const T* __restrict__ q,
-                                                   T* __restrict__ x, T* __restrict__ r,
+__global__ void __launch_bounds__(256) k_cg_update(const Prob* __restrict__ P, CgState s, int par, int comps,
+                                                   int pq_kind, int pq_stride, const T* __restrict__ pv,
+                                                   const T* __restrict__ q, T* __restrict__ x, T* __restrict__ r,
                                                    const double* __restrict__ part_pq, double* __restrict__ part_rr) {
     __shared__ double red[256];
     __shared__ double slot;
     const int b = blockIdx.y, cnt = gridDim.y;
     if (s.done[par * cnt + b]) return;
     const Prob& p = P[b];
-    const int64_t m = int64_t(p.n) * p.n, o = p.o_c;
+    const int64_t m = int64_t(comps) * p.n * p.n, o = int64_t(comps) * p.o_c;
     int64_t lo, hi;
     slice_of(m, lo, hi);
     const double alpha = broadcast0(
-        threadIdx.x == 0 ? s.rr[par * cnt + b] / sum_parts(part_pq + int64_t(b) * kCgRowParts, pq_parts(p)) : 0.0,
+        threadIdx.x == 0
+            ? s.rr[par * cnt + b] / sum_parts(part_pq + int64_t(b) * pq_stride, pq_parts(p, pq_kind))
+            : 0.0,
         &slot);
     const T a = T(alpha);
     double acc = 0.0;
@@ -162,7 +170,7 @@ __global__ void __launch_bounds__(256) k_cg_update(const Prob* __restrict__ P, C
 // counted, and the stop rule (|r| <= tol |b| or max_iter steps); a stopped
 // problem's state is carried over unchanged.
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_dir(const Prob* __restrict__ P, CgState s, int par,
+__global__ void __launch_bounds__(256) k_cg_dir(const Prob* __restrict__ P, CgState s, int par, int comps,
                                                 const T* __restrict__ r, T* __restrict__ pv,
                                                 const double* __restrict__ part_rr, double tol, int max_iter) {
     __shared__ double slot;
@@ -177,7 +185,7 @@ __global__ void __launch_bounds__(256) k_cg_dir(const Prob* __restrict__ P, CgSt
         return;
     }
     const Prob& p = P[b];
-    const int64_t m = int64_t(p.n) * p.n, o = p.o_c;
+    const int64_t m = int64_t(comps) * p.n * p.n, o = int64_t(comps) * p.o_c;
     int64_t lo, hi;
     slice_of(m, lo, hi);
     const double rr_new = broadcast0(threadIdx.x == 0 ? sum_parts(part_rr + int64_t(b) * kDotParts) : 0.0, &slot);

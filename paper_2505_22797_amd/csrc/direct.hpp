@@ -106,8 +106,9 @@ __global__ void __launch_bounds__(64 * S) k_conv_direct(const Prob* __restrict__
                             acc[COUT > 1 ? 1 : 0][w] += k1 * x[u + w];
                             acc[COUT > 2 ? 2 : 0][w] += k2 * x[u + w];
                         }
-                    } else if (CIN == 1) {   // trace kernel: the two diagonal channels
-                        const T k = taps[trow + t0 + u] + taps[2 * W * tw + trow + t0 + u];
+                    } else if (CIN == 1) {   // trace kernel (the two diagonal channels), or K_xx for x-channel problems
+                        const T k = p.chan == 1 ? taps[trow + t0 + u]
+                                                : taps[trow + t0 + u] + taps[2 * W * tw + trow + t0 + u];
 #pragma unroll
                         for (int w = 0; w < kStrip; ++w) acc[0][w] += k * x[u + w];
                     } else {
@@ -174,7 +175,7 @@ __global__ void __launch_bounds__(256) k_gather_rows(const Prob* __restrict__ P,
                          io.out0 ? io.out0 + p.o_s : nullptr, io.in0 ? io.in0 + p.o_s : nullptr,
                          io.out1 ? io.out1 + p.o_s : nullptr, io.out2 ? io.out2 + p.o_s : nullptr,
                          io.f ? io.f + 9 * (p.o_s / 2) : nullptr, p.t,
-                         p.o_dw ? at<vec2<T>>(plan, p.o_dw) : nullptr, threadIdx.x, blockDim.x);
+                         p.o_dw ? at<vec2<T>>(plan, p.o_dw) : nullptr, p.chan == 1, threadIdx.x, blockDim.x);
 }
 
 // Deterministic transpose sampling for one grid row into a field in global
@@ -194,7 +195,8 @@ __global__ void __launch_bounds__(256) k_scatter_rows(const Prob* __restrict__ P
     // SORTED: the signal in cell order, from s when given, else the problem's residual in work
     const vec2<T>* ys = (SORTED && sp) ? reinterpret_cast<const vec2<T>*>(sp) : at<vec2<T>>(work, p.w_res);
     scatter_row<T, SORTED, 256>(g, scatter_lds<T>(sc, N, 256), N, j, at<int>(plan, p.o_binstart),
-                                at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), ys, sp, threadIdx.x);
+                                at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), ys, sp, threadIdx.x,
+                                p.chan == 1);
     for (int i = threadIdx.x; i < 3 * N; i += blockDim.x) {
         const int ch = i / N, x = i % N;
         G[int64_t(ch) * N * N + int64_t(j) * N + x] = g[i];

@@ -271,7 +271,9 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
 #pragma unroll
                 for (int i = 0; i < PL; ++i) {
                     const int ky = lane + i * kWave;
-                    const T k = TRACE ? spec_at<T, M>(spec, 0, kx, ky) + spec_at<T, M>(spec, 2, kx, ky)
+                    // the trace kernel, or K_xx alone for x-channel problems
+                    const T k = TRACE ? (p.chan == 1 ? spec_at<T, M>(spec, 0, kx, ky)
+                                                     : spec_at<T, M>(spec, 0, kx, ky) + spec_at<T, M>(spec, 2, kx, ky))
                                       : spec_at<T, M>(spec, ch, kx, ky);
                     line[ky] = cscale(cr[i], k);
                 }
@@ -317,7 +319,7 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
     const vec2<T>* ysort = at<vec2<T>>(work, p.w_ysort);
     const vec2<T>* dw = p.o_dw ? at<vec2<T>>(plan, p.o_dw) : nullptr;
     GatherRecs<T, 4> first;
-    gather_fetch<T, MODE, 4>(first, p0 + tid, p1, 4 * kWave, samp, sidx, ysort, in0);
+    gather_fetch<T, MODE, 4>(first, p0 + tid, p1, 4 * kWave, samp, sidx, ysort, in0, p.chan == 1);
     twr.store(sm.tw, tid);
     __syncthreads();
     T* g0 = sm.g;            // row b:   [ch][N]
@@ -335,7 +337,7 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
     }
     __syncthreads();
     gather_band<T, MODE, 4>(g0, g1, N, p0, p1, samp, sidx, ysort, at<vec2<T>>(work, p.w_res), out0, in0, out1, out2,
-                            f, p.t, dw, tid, 4 * kWave, &first);
+                            f, p.t, dw, p.chan == 1, tid, 4 * kWave, &first);
 }
 
 // ----------------------------------------------------------------- adjoint ---
@@ -360,7 +362,7 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
     const vec2<T>* ys = (SORTED && s) ? reinterpret_cast<const vec2<T>*>(s) : at<vec2<T>>(work, p.w_res);
     scatter_row<T, SORTED, 256>(g, scatter_lds<T>(shared_area, N, 256), N, j, at<int>(plan, p.o_binstart),
                                 at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), ys,
-                                s, tid);
+                                s, tid, p.chan == 1);
     twr.store(tw, tid);
     __syncthreads();
     if (wave >= 2) return;

@@ -26,6 +26,7 @@
 #include "build.hpp"
 #include "direct.hpp"
 #include "fft_conv.hpp"
+#include "core.hpp"
 #include "deconv.hpp"
 #include "grad.hpp"
 
@@ -92,7 +93,8 @@ size_t scatter_rows_smem(int N, int elem) {
 }
 
 struct Shape {
-    int n, R, M, elem, interp;
+    int n, R, M, elem, interp, chan;
+    double gx, gy;
     int64_t T;
     bool fft_ok, direct_ok;
 };
@@ -106,7 +108,13 @@ int validate(const mpi_problem* d, Shape& sh) {
     if (d->n_samples < 1 || d->n_samples >= kMaxSamples) return MPI_ERR_ARG;
     if (d->conv_mode < MPI_CONV_AUTO || d->conv_mode > MPI_CONV_FFT) return MPI_ERR_ARG;
     if (d->interp != MPI_INTERP_BILINEAR && d->interp != MPI_INTERP_COSINE) return MPI_ERR_ARG;
-    if (d->channels != MPI_CH_XY) return MPI_ERR_UNSUPPORTED;
+    if (d->channels != MPI_CH_XY && d->channels != MPI_CH_X) return MPI_ERR_ARG;
+    const bool iso = d->grad_x == 0.0 && d->grad_y == 0.0;
+    if (!iso && (!std::isfinite(d->grad_x) || !std::isfinite(d->grad_y) || d->grad_x == 0.0 || d->grad_y == 0.0))
+        return MPI_ERR_ARG;
+    sh.chan = d->channels;
+    sh.gx = iso ? 1.0 : d->grad_x;
+    sh.gy = iso ? 1.0 : d->grad_y;
     sh.elem = d->dtype == MPI_F64 ? 8 : 4;
     sh.interp = d->interp;
     sh.n = d->n;
@@ -152,6 +160,9 @@ void layout_problem(const Shape& sh, int mode, bool both, bool deriv, size_t& po
     p.taps_w = (W + 3) / 4 * 4;
     p.slices = 8;
     p.interp = sh.interp;
+    p.chan = sh.chan;
+    p.gx = sh.gx;
+    p.gy = sh.gy;
     p.t = T;
     const bool dir = both ? sh.direct_ok : mode == 0;
     const bool fft = both ? sh.fft_ok : mode == 1;
@@ -301,12 +312,13 @@ struct mpi_plan {
     const void *g_s = nullptr, *g_c = nullptr, *g_work = nullptr;
     double g_sigma = 0;
     int g_rad = -1;
-    // cached graph of a block of CG steps (deconvolution), keyed by its buffers and stop rule
-    hipGraphExec_t cg_exec = nullptr;
-    hipGraph_t cg_graph = nullptr;
-    const void *cg_x = nullptr, *cg_work = nullptr, *cg_dw = nullptr;
-    double cg_tol = -1.0;
-    int cg_max = -1;
+    // cached graphs of a block of CG steps (Deconvolution and Core Stage), keyed
+    // by their buffers and parameters
+    struct GraphCache {
+        hipGraphExec_t exec = nullptr;
+        hipGraph_t graph = nullptr;
+        std::vector<double> key;
+    } cg_gc, core_gc;
 };
 
 namespace {
@@ -1279,52 +1291,60 @@ void cg_step(const mpi_plan* pl, int par, T* x, double tol, int max_iter, char* 
         }
         k_cg_pq<T><<<el, 256, 0, st>>>(P, s, par, pv, q, pa);
     }
-    k_cg_update<T><<<el, 256, 0, st>>>(P, s, par, pv, q, x, r, pa, pb);
-    k_cg_dir<T><<<el, 256, 0, st>>>(P, s, par, r, pv, pb, tol, max_iter);
+    k_cg_update<T><<<el, 256, 0, st>>>(P, s, par, 1, 0, kCgRowParts, pv, q, x, r, pa, pb);
+    k_cg_dir<T><<<el, 256, 0, st>>>(P, s, par, 1, r, pv, pb, tol, max_iter);
 }
 
 constexpr int kCgBlock = 4;   // CG steps per captured graph (even: each block starts on state slot 0)
 
-// Captures kCgBlock steps into the plan's cached graph unless it already
-// holds them for these buffers and this stop rule.
-template <typename T>
-int cg_graph(mpi_plan* pl, T* x, double tol, int max_iter, char* work, char* dw, const DeconvLayout& L,
-             hipStream_t st) {
-    if (pl->cg_exec && pl->cg_x == x && pl->cg_work == work && pl->cg_dw == dw && pl->cg_tol == tol &&
-        pl->cg_max == max_iter)
-        return MPI_OK;
-    if (pl->cg_exec) {
+double key_of(const void* ptr) { return double(reinterpret_cast<uintptr_t>(ptr)); }
+
+// Records what `record(stream)` launches into the cache unless it already
+// holds a graph for `key` (the buffers and parameters baked into the launches).
+template <typename F>
+int cached_graph(mpi_plan::GraphCache& gc, const std::vector<double>& key, hipStream_t st, F&& record) {
+    if (gc.exec && gc.key == key) return MPI_OK;
+    if (gc.exec) {
         HIP_TRY(hipStreamSynchronize(st));
-        (void)hipGraphExecDestroy(pl->cg_exec);
-        (void)hipGraphDestroy(pl->cg_graph);
-        pl->cg_exec = nullptr;
-        pl->cg_graph = nullptr;
+        (void)hipGraphExecDestroy(gc.exec);
+        (void)hipGraphDestroy(gc.graph);
+        gc.exec = nullptr;
+        gc.graph = nullptr;
     }
     hipStream_t cap;
     HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        for (int i = 0; i < kCgBlock; ++i) cg_step<T>(pl, i & 1, x, tol, max_iter, work, dw, L, cap);
+        record(cap);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(cap, &g);
         if (e == hipSuccess) {
-            e = hipGraphInstantiate(&pl->cg_exec, g, nullptr, nullptr, 0);
-            if (e == hipSuccess) pl->cg_graph = g;
+            e = hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0);
+            if (e == hipSuccess) gc.graph = g;
             else (void)hipGraphDestroy(g);
         } else if (g) {
             (void)hipGraphDestroy(g);
         }
     }
     (void)hipStreamDestroy(cap);
-    if (e != hipSuccess || !pl->cg_exec) {
-        pl->cg_exec = nullptr;
+    if (e != hipSuccess || !gc.exec) {
+        gc.exec = nullptr;
         return MPI_ERR_HIP;
     }
-    pl->cg_x = x;
-    pl->cg_work = work;
-    pl->cg_dw = dw;
-    pl->cg_tol = tol;
-    pl->cg_max = max_iter;
+    gc.key = key;
+    return MPI_OK;
+}
+
+// Launches captured blocks of kCgBlock steps and polls the stop flags (slot
+// 0) after each block until every problem has stopped or max_iter steps ran.
+int run_cg_blocks(hipGraphExec_t exec, const int* done_dev, int count, int max_iter, hipStream_t st) {
+    std::vector<int> done(count);
+    for (int taken = 0; taken < max_iter; taken += kCgBlock) {
+        HIP_TRY(hipGraphLaunch(exec, st));
+        HIP_TRY(hipMemcpyAsync(done.data(), done_dev, sizeof(int) * count, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (std::all_of(done.begin(), done.end(), [](int d) { return d != 0; })) break;
+    }
     return MPI_OK;
 }
 
@@ -1342,19 +1362,17 @@ int cg_impl(mpi_plan* pl, const T* cu, const T* rho2, T* x, double tol, int max_
     T* r = reinterpret_cast<T*>(dw + L.r);
     T* pv = reinterpret_cast<T*>(dw + L.p);
     double* pa = reinterpret_cast<double*>(dw + L.part_a);
-    k_cg_init<T><<<dim3(kDotParts, B), 256, 0, st>>>(P, cu, rho2, s, x, r, pv, pa);
+    k_cg_init<T><<<dim3(kDotParts, B), 256, 0, st>>>(P, 1, cu, rho2, s, x, r, pv, pa);
     k_cg_begin<<<blocks(B, 256), 256, 0, st>>>(B, s, pa, tol, max_iter);
     HIP_TRY(hipGetLastError());
     if (max_iter > 0) {
-        const int rc = cg_graph<T>(pl, x, tol, max_iter, work, dw, L, st);
+        const std::vector<double> key{key_of(x), key_of(work), key_of(dw), tol, double(max_iter)};
+        int rc = cached_graph(pl->cg_gc, key, st, [&](hipStream_t cap) {
+            for (int i = 0; i < kCgBlock; ++i) cg_step<T>(pl, i & 1, x, tol, max_iter, work, dw, L, cap);
+        });
         if (rc != MPI_OK) return rc;
-    }
-    std::vector<int> done(B);
-    for (int taken = 0; taken < max_iter; taken += kCgBlock) {
-        HIP_TRY(hipGraphLaunch(pl->cg_exec, st));
-        HIP_TRY(hipMemcpyAsync(done.data(), s.done, sizeof(int) * B, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        if (std::all_of(done.begin(), done.end(), [](int d) { return d != 0; })) break;
+        rc = run_cg_blocks(pl->cg_gc.exec, s.done, B, max_iter, st);
+        if (rc != MPI_OK) return rc;
     }
     if (iters) HIP_TRY(hipMemcpyAsync(iters, s.iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1439,6 +1457,113 @@ int pnp_impl(mpi_plan* pl, const T* u, T* rho, const mpi_pnp_params* pp, int32_t
             if (sigma > 0.0) nu[b] = lam[b] / (sigma * sigma);
         }
     }
+    HIP_TRY(hipStreamSynchronize(st));
+    return MPI_OK;
+}
+
+// ---------------------------------------------------------- core stage ---
+// Workspace of mpi_batch_core_stage: the CG vectors r, p, q and the Laplacian
+// l (three channels per cell), the signal-shaped y = I p in cell order, the
+// solver state and partial sums.
+struct CoreLayout {
+    size_t r = 0, p = 0, q = 0, l = 0, y = 0, rr = 0, bb = 0, nu = 0, iters = 0, done = 0, part_a = 0, part_b = 0;
+    size_t bytes = 0;
+};
+
+CoreLayout core_layout(const mpi_plan* pl) {
+    CoreLayout L;
+    size_t off = 0;
+    const size_t v = size_t(3) * pl->L.c_elems * pl->L.elem, B = size_t(pl->count);
+    L.r = take(off, v);
+    L.p = take(off, v);
+    L.q = take(off, v);
+    L.l = take(off, v);
+    L.y = take(off, size_t(pl->L.s_elems) * pl->L.elem);
+    L.rr = take(off, 2 * 8 * B);
+    L.bb = take(off, 8 * B);
+    L.nu = take(off, 8 * B);
+    L.iters = take(off, 4 * B);
+    L.done = take(off, 2 * 4 * B);
+    L.part_a = take(off, 8 * B * kCoreParts);
+    L.part_b = take(off, 8 * B * kDotParts);
+    L.bytes = off;
+    return L;
+}
+
+size_t core_gather_smem(const mpi_plan* pl) { return size_t(6) * pl->max_n * pl->L.elem; }
+size_t core_scatter_smem(const mpi_plan* pl) { return scatter_rows_smem(pl->max_n, pl->L.elem); }
+
+// One Core Stage CG step (parity par): y = I p, l = Delta p (unscaled),
+// q = (1/L) I^T y + gamma delta^2 W Delta l with the per-row <p, q>, then the
+// x, r and p updates and the next state slot.
+template <typename T>
+void core_step(const mpi_plan* pl, int par, T* x, double gamma, double tol, int max_iter, char* cw,
+               const CoreLayout& L, hipStream_t st) {
+    const Prob* P = pl->dprob;
+    const char* plan = pl->plan;
+    const int B = pl->count;
+    CgState s;
+    s.rr = reinterpret_cast<double*>(cw + L.rr);
+    s.bb = reinterpret_cast<double*>(cw + L.bb);
+    s.nu = reinterpret_cast<double*>(cw + L.nu);
+    s.iters = reinterpret_cast<int*>(cw + L.iters);
+    s.done = reinterpret_cast<int*>(cw + L.done);
+    const int* skip = s.done + par * B;
+    T* r = reinterpret_cast<T*>(cw + L.r);
+    T* pv = reinterpret_cast<T*>(cw + L.p);
+    T* q = reinterpret_cast<T*>(cw + L.q);
+    T* l = reinterpret_cast<T*>(cw + L.l);
+    T* y = reinterpret_cast<T*>(cw + L.y);
+    double* pa = reinterpret_cast<double*>(cw + L.part_a);
+    double* pb = reinterpret_cast<double*>(cw + L.part_b);
+    const dim3 el(kDotParts, B);
+    k_core_gather<T><<<dim3(pl->max_nb, B), 256, core_gather_smem(pl), st>>>(P, pv, y, plan, skip);
+    k_core_lap<T><<<dim3(blocks(int64_t(3) * pl->max_n * pl->max_n, 256), B), 256, 0, st>>>(P, pv, l, skip);
+    k_core_scatter<T, 1><<<dim3(pl->max_n, B), 256, core_scatter_smem(pl), st>>>(P, y, q, pv, l, gamma, pa, plan,
+                                                                                 skip);
+    k_cg_update<T><<<el, 256, 0, st>>>(P, s, par, 3, 1, kCoreParts, pv, q, x, r, pa, pb);
+    k_cg_dir<T><<<el, 256, 0, st>>>(P, s, par, 3, r, pv, pb, tol, max_iter);
+}
+
+// The Core Stage: CG on the Euler-Lagrange equations of eq. first:step from
+// a = 0 for every problem, with the plan's samples and interpolation weights.
+template <typename T>
+int core_impl(mpi_plan* pl, const T* sig, T* field, double gamma, double tol, int max_iter, char* cw,
+              hipStream_t st, int32_t* iters) {
+    const CoreLayout L = core_layout(pl);
+    const Prob* P = pl->dprob;
+    const int B = pl->count;
+    HIP_TRY(allow_smem(k_core_gather<T>, core_gather_smem(pl)));
+    HIP_TRY(allow_smem(k_core_scatter<T, 0>, core_scatter_smem(pl)));
+    HIP_TRY(allow_smem(k_core_scatter<T, 1>, core_scatter_smem(pl)));
+    CgState s;
+    s.rr = reinterpret_cast<double*>(cw + L.rr);
+    s.bb = reinterpret_cast<double*>(cw + L.bb);
+    s.nu = reinterpret_cast<double*>(cw + L.nu);
+    s.iters = reinterpret_cast<int*>(cw + L.iters);
+    s.done = reinterpret_cast<int*>(cw + L.done);
+    T* r = reinterpret_cast<T*>(cw + L.r);
+    T* pv = reinterpret_cast<T*>(cw + L.p);
+    T* q = reinterpret_cast<T*>(cw + L.q);
+    T* y = reinterpret_cast<T*>(cw + L.y);
+    double* pb = reinterpret_cast<double*>(cw + L.part_b);
+    // right-hand side (1/L) I^T s into q, then x = 0, r = p = q
+    k_core_permute<T><<<dim3(blocks(pl->max_t, 256), B), 256, 0, st>>>(P, sig, y, pl->plan);
+    k_core_scatter<T, 0><<<dim3(pl->max_n, B), 256, core_scatter_smem(pl), st>>>(P, y, q, nullptr, nullptr, 0.0,
+                                                                                 nullptr, pl->plan, nullptr);
+    k_cg_init<T><<<dim3(kDotParts, B), 256, 0, st>>>(P, 3, q, nullptr, s, field, r, pv, pb);
+    k_cg_begin<<<blocks(B, 256), 256, 0, st>>>(B, s, pb, tol, max_iter);
+    HIP_TRY(hipGetLastError());
+    if (max_iter > 0) {
+        const std::vector<double> key{key_of(field), key_of(cw), gamma, tol, double(max_iter)};
+        int rc = cached_graph(pl->core_gc, key, st, [&](hipStream_t cap) {
+            for (int i = 0; i < kCgBlock; ++i) core_step<T>(pl, i & 1, field, gamma, tol, max_iter, cw, L, cap);
+        });
+        if (rc != MPI_OK) return rc;
+        rc = run_cg_blocks(pl->core_gc.exec, s.done, B, max_iter, st);
+        if (rc != MPI_OK) return rc;
+    }
+    if (iters) HIP_TRY(hipMemcpyAsync(iters, s.iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     return MPI_OK;
 }
@@ -1805,6 +1930,61 @@ int mpi_batch_pnp(const mpi_plan* plan, const void* u, void* rho, const mpi_pnp_
                                  nus, w, dw, stream);
 }
 
+int mpi_batch_core_bytes(const mpi_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return MPI_ERR_ARG;
+    *bytes = core_layout(plan).bytes;
+    return MPI_OK;
+}
+
+int mpi_batch_core_stage(const mpi_plan* plan, const void* s, void* field, double gamma, double tol, int32_t max_iter,
+                         int32_t* iters, void* work, size_t work_bytes, void* cwork, size_t cbytes,
+                         hipStream_t stream) {
+    int rc = check_call(plan, s, field, work, work_bytes);
+    if (rc != MPI_OK) return rc;
+    if (!cwork || misaligned(cwork, kAlign) || !(gamma >= 0.0) || !std::isfinite(gamma) || !(tol >= 0.0) ||
+        max_iter < 0)
+        return MPI_ERR_ARG;
+    if (cbytes < core_layout(plan).bytes) return MPI_ERR_WORKSPACE;
+    if (core_scatter_smem(plan) > kSmemLimit || core_gather_smem(plan) > kSmemLimit) return MPI_ERR_UNSUPPORTED;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    mpi_plan* pl = const_cast<mpi_plan*>(plan);
+    char* cw = static_cast<char*>(cwork);
+    return plan->dtype == MPI_F64
+               ? core_impl<double>(pl, static_cast<const double*>(s), static_cast<double*>(field), gamma, tol,
+                                   max_iter, cw, stream, iters)
+               : core_impl<float>(pl, static_cast<const float*>(s), static_cast<float*>(field), gamma, tol, max_iter,
+                                  cw, stream, iters);
+}
+
+int mpi_velocity_forward_difference(const void* r, void* v, int64_t n_samples, double dt, int32_t dtype,
+                                    hipStream_t stream) {
+    if (!r || !v || r == v || n_samples < 2 || !(dt > 0.0) || !std::isfinite(dt)) return MPI_ERR_ARG;
+    if (dtype != MPI_F32 && dtype != MPI_F64) return MPI_ERR_DTYPE;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    if (dtype == MPI_F64)
+        k_forward_difference<double><<<blocks(n_samples, 256), 256, 0, stream>>>(
+            static_cast<const double*>(r), static_cast<double*>(v), n_samples, dt);
+    else
+        k_forward_difference<float><<<blocks(n_samples, 256), 256, 0, stream>>>(
+            static_cast<const float*>(r), static_cast<float*>(v), n_samples, dt);
+    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+}
+
+int mpi_batch_field_trace(const mpi_plan* plan, const void* field, void* u, hipStream_t stream) {
+    if (!plan || !field || !u || field == u) return MPI_ERR_ARG;
+    const size_t el = plan->L.elem;
+    if (misaligned(field, el) || misaligned(u, el)) return MPI_ERR_ARG;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    const dim3 grid(blocks(int64_t(plan->max_n) * plan->max_n, 256), plan->count);
+    if (plan->dtype == MPI_F64)
+        k_field_trace<double><<<grid, 256, 0, stream>>>(plan->dprob, static_cast<const double*>(field),
+                                                        static_cast<double*>(u));
+    else
+        k_field_trace<float><<<grid, 256, 0, stream>>>(plan->dprob, static_cast<const float*>(field),
+                                                       static_cast<float*>(u));
+    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+}
+
 int mpi_stage_count(const mpi_plan* plan) {
     if (!plan) return MPI_ERR_ARG;
     return kFwdStages + kAdjStages;
@@ -1850,11 +2030,12 @@ int mpi_plan_destroy(mpi_plan* plan) {
         (void)hipGraphExecDestroy(plan->gexec);
         (void)hipGraphDestroy(plan->graph);
     }
-    if (plan->cg_exec) {
-        (void)hipDeviceSynchronize();
-        (void)hipGraphExecDestroy(plan->cg_exec);
-        (void)hipGraphDestroy(plan->cg_graph);
-    }
+    for (mpi_plan::GraphCache* gc : {&plan->cg_gc, &plan->core_gc})
+        if (gc->exec) {
+            (void)hipDeviceSynchronize();
+            (void)hipGraphExecDestroy(gc->exec);
+            (void)hipGraphDestroy(gc->graph);
+        }
     release_streams(plan);
     delete plan;
     return MPI_OK;

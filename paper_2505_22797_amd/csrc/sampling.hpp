@@ -43,10 +43,13 @@ template <typename T, int U> struct GatherRecs {
     vec2<T> y[U];
 };
 
+// chx (x receive channel alone): the y components of the signals read are
+// taken as 0, and the y components written are 0.
 template <typename T, int MODE, int U>
 __device__ __forceinline__ void gather_fetch(GatherRecs<T, U>& r, int base, int p1, int nthreads,
                                              const vec4<T>* __restrict__ samp, const int2* __restrict__ sidx,
-                                             const vec2<T>* __restrict__ ysort, const T* __restrict__ in0) {
+                                             const vec2<T>* __restrict__ ysort, const T* __restrict__ in0,
+                                             bool chx) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int p = base + u * nthreads;
@@ -70,13 +73,18 @@ __device__ __forceinline__ void gather_fetch(GatherRecs<T, U>& r, int base, int 
             }
         }
     }
+    if (MODE != 0 && MODE != 4 && chx) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) r.y[u].y = T(0);
+    }
 }
 
 template <typename T, int MODE, int U>
 __device__ __forceinline__ void gather_apply(const GatherRecs<T, U>& r, int base, int p1, int nthreads,
                                              const T* g0, const T* g1, int N, vec2<T>* __restrict__ out_sorted,
                                              T* __restrict__ out0, T* __restrict__ out1, T* __restrict__ out2,
-                                             T* __restrict__ f, int64_t fstride, const vec2<T>* __restrict__ dw) {
+                                             T* __restrict__ f, int64_t fstride, const vec2<T>* __restrict__ dw,
+                                             bool chx) {
     constexpr bool GRAD = MODE == 2 || MODE == 5 || MODE == 6;
     const T inv_d = T(0.5) * T(N);
 #pragma unroll
@@ -112,7 +120,7 @@ __device__ __forceinline__ void gather_apply(const GatherRecs<T, U>& r, int base
         } else if (MODE == 6) {
             const T yx = y.x, yy = y.y;
             const T qx = g[0] * vx + g[1] * vy;
-            const T qy = g[1] * vx + g[2] * vy;
+            const T qy = chx ? T(0) : g[1] * vx + g[2] * vy;
             T h[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) h[q] = f[q * fstride + p];
@@ -130,7 +138,7 @@ __device__ __forceinline__ void gather_apply(const GatherRecs<T, U>& r, int base
             out2[2 * p + 1] += gv_y;
         } else {
             const T sx = g[0] * vx + g[1] * vy;
-            const T sy = g[1] * vx + g[2] * vy;
+            const T sy = chx ? T(0) : g[1] * vx + g[2] * vy;
             if (MODE == 1) {
                 vec2<T> o;
                 o.x = sx - y.x;
@@ -171,18 +179,18 @@ __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int
                                             const vec2<T>* __restrict__ ysort, vec2<T>* __restrict__ out_sorted,
                                             T* __restrict__ out0, const T* __restrict__ in0, T* __restrict__ out1,
                                             T* __restrict__ out2, T* __restrict__ f, int64_t fstride,
-                                            const vec2<T>* __restrict__ dw, int tid, int nthreads,
+                                            const vec2<T>* __restrict__ dw, bool chx, int tid, int nthreads,
                                             const GatherRecs<T, U>* first = nullptr) {
     int base = p0 + tid;
     if (first) {
         if (base < p1) gather_apply<T, MODE, U>(*first, base, p1, nthreads, g0, g1, N, out_sorted, out0, out1, out2, f,
-                                                fstride, dw);
+                                                fstride, dw, chx);
         base += U * nthreads;
     }
     for (; base < p1; base += U * nthreads) {
         GatherRecs<T, U> r;
-        gather_fetch<T, MODE, U>(r, base, p1, nthreads, samp, sidx, ysort, in0);
-        gather_apply<T, MODE, U>(r, base, p1, nthreads, g0, g1, N, out_sorted, out0, out1, out2, f, fstride, dw);
+        gather_fetch<T, MODE, U>(r, base, p1, nthreads, samp, sidx, ysort, in0, chx);
+        gather_apply<T, MODE, U>(r, base, p1, nthreads, g0, g1, N, out_sorted, out0, out1, out2, f, fstride, dw, chx);
     }
 }
 
@@ -225,12 +233,13 @@ __device__ __forceinline__ ScatterLds<T> scatter_lds(char* base, int N, int NT) 
 // combined by their first thread in thread order.  Pass 2 assembles every
 // cell from its (at most) four base cells in a fixed order.  The result goes
 // to g[ch * N + i] in LDS.  SORTED: the signal/residual is read in cell order
-// from ys[p]; else in time order from s_time[k].
+// from ys[p]; else in time order from s_time[k].  chx: the y components
+// are taken as 0 (x receive channel alone).
 template <typename T, bool SORTED, int NT, int U = 4>
 __device__ __forceinline__ void scatter_row(T* g, ScatterLds<T> sm, int N, int j,
                                             const int* __restrict__ binstart, const vec4<T>* __restrict__ samp,
                                             const int2* __restrict__ sidx, const vec2<T>* __restrict__ ys,
-                                            const T* __restrict__ s_time, int tid) {
+                                            const T* __restrict__ s_time, int tid, bool chx) {
     const int nb = N - 1;
     const int rlo = max(j - 1, 0), rhi = min(j, nb - 1);       // base-cell rows that reach row j
     const int nkeys = 2 * nb;
@@ -264,6 +273,10 @@ __device__ __forceinline__ void scatter_row(T* g, ScatterLds<T> sm, int N, int j
                     y[u].y = s_time[2 * k + 1];
                 }
             }
+        }
+        if (chx) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) y[u].y = T(0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {

@@ -19,6 +19,7 @@ MPI_ERR_DTYPE, MPI_ERR_HIP, MPI_ERR_UNSUPPORTED = -4, -5, -6
 MPI_F32, MPI_F64 = 0, 1
 CONV_MODES = {"auto": 0, "direct": 1, "fft": 2}
 INTERPS = {"bilinear": 0, "cosine": 1}
+CHANNELS = {"xy": 0, "x": 1}
 
 EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
            "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
@@ -27,6 +28,7 @@ EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "
            "mpi_batch_dot", "mpi_batch_unrolled_vjp_bytes", "mpi_batch_unrolled_vjp",
            "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
            "mpi_batch_deconv_bytes", "mpi_batch_trace_conv", "mpi_batch_cg", "mpi_batch_trim_sigma", "mpi_batch_pnp",
+           "mpi_batch_core_bytes", "mpi_batch_core_stage", "mpi_batch_field_trace", "mpi_velocity_forward_difference",
            "mpi_plan_destroy", "mpi_status_str", "mpi_abi_version")
 MPI_BUILD_TUNE, MPI_BUILD_COL_SPLIT, MPI_BUILD_COL_WAVE, MPI_BUILD_DERIV = 1, 2, 4, 8
 
@@ -41,7 +43,7 @@ class Problem(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("dtype", ctypes.c_int32), ("h", ctypes.c_double),
                 ("radius", ctypes.c_int32), ("conv_mode", ctypes.c_int32), ("interp", ctypes.c_int32),
                 ("channels", ctypes.c_int32), ("n_samples", ctypes.c_int64),
-                ("r", ctypes.c_void_p), ("v", ctypes.c_void_p)]
+                ("r", ctypes.c_void_p), ("v", ctypes.c_void_p), ("grad_x", ctypes.c_double), ("grad_y", ctypes.c_double)]
 
 
 class IterParams(ctypes.Structure):
@@ -102,6 +104,11 @@ def lib() -> ctypes.CDLL:
         L.mpi_batch_cg.argtypes = [vp, vp, vp, dp, ctypes.c_double, ctypes.c_int32, i32p, vp, sz, vp, sz, vp]
         L.mpi_batch_trim_sigma.argtypes = [vp, vp, ctypes.c_double, dp, dp, vp, sz, vp, sz, vp]
         L.mpi_batch_pnp.argtypes = [vp, vp, vp, ctypes.POINTER(PnpParams), i32p, dp, dp, vp, sz, vp, sz, vp]
+        L.mpi_batch_core_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.mpi_batch_core_stage.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, i32p, vp, sz,
+                                           vp, sz, vp]
+        L.mpi_batch_field_trace.argtypes = [vp, vp, vp, vp]
+        L.mpi_velocity_forward_difference.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, vp]
         L.mpi_stage_count.argtypes = [vp]
         L.mpi_stage_name.argtypes = [vp, ctypes.c_int]
         L.mpi_stage_name.restype = ctypes.c_char_p
@@ -117,7 +124,9 @@ def lib() -> ctypes.CDLL:
                      "mpi_batch_dot", "mpi_batch_unrolled_vjp_bytes", "mpi_batch_unrolled_vjp",
                      "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_launch",
                      "mpi_batch_deconv_bytes", "mpi_batch_trace_conv", "mpi_batch_cg", "mpi_batch_trim_sigma",
-                     "mpi_batch_pnp", "mpi_plan_destroy",
+                     "mpi_batch_pnp", "mpi_batch_core_bytes", "mpi_batch_core_stage", "mpi_batch_field_trace",
+                     "mpi_velocity_forward_difference",
+                     "mpi_plan_destroy",
                      "mpi_abi_version"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -148,13 +157,15 @@ def _dtype_code(dt: torch.dtype) -> int:
 
 def problem(n: int, h: float, radius: int, r: torch.Tensor | None, v: torch.Tensor | None,
             n_samples: int | None = None, dtype: torch.dtype = torch.float32,
-            conv_mode: str = "auto", interp: str = "bilinear") -> Problem:
+            conv_mode: str = "auto", interp: str = "bilinear", channels: str = "xy",
+            grad=(1.0, 1.0)) -> Problem:
     p = Problem()
     p.n, p.h, p.radius = int(n), float(h), int(radius)
     p.dtype = _dtype_code(r.dtype if r is not None else dtype)
     p.conv_mode = CONV_MODES[conv_mode]
     p.interp = INTERPS[interp]
-    p.channels = 0
+    p.channels = CHANNELS[channels]
+    p.grad_x, p.grad_y = float(grad[0]), float(grad[1])
     p.n_samples = int(r.shape[0] if r is not None else n_samples)
     p.r = r.data_ptr() if r is not None else None
     p.v = v.data_ptr() if v is not None else None
@@ -172,7 +183,8 @@ class Plan:
     device memory owned by this object, plus a reusable work buffer."""
 
     def __init__(self, n: int, h: float, radius: int, r: torch.Tensor, v: torch.Tensor,
-                 conv_mode: str = "auto", stream=None, interp: str = "bilinear"):
+                 conv_mode: str = "auto", stream=None, interp: str = "bilinear", channels: str = "xy",
+                 grad=(1.0, 1.0)):
         if not (r.is_cuda and v.is_cuda):
             raise ValueError("r and v must be device tensors")
         if r.dtype != v.dtype or r.shape != v.shape or r.ndim != 2 or r.shape[1] != 2:
@@ -182,7 +194,7 @@ class Plan:
         self.n, self.h, self.dtype, self.device = int(n), float(h), r.dtype, r.device
         self.n_samples = int(r.shape[0])
         self.interp = interp
-        prob = problem(n, h, radius, r, v, conv_mode=conv_mode, interp=interp)
+        prob = problem(n, h, radius, r, v, conv_mode=conv_mode, interp=interp, channels=channels, grad=grad)
         pb, wb = plan_bytes(prob)
         self.plan_mem = torch.empty(pb, dtype=torch.uint8, device=r.device)
         self.work = torch.empty(wb, dtype=torch.uint8, device=r.device)
@@ -329,11 +341,13 @@ class Batch:
     concatenated in one flat tensor each (see `c_offsets`, `s_offsets`)."""
 
     def __init__(self, specs, dtype=torch.float32, tune: bool = True, columns: str | None = None,
-                 deriv: bool = False, stream=None, interp: str = "bilinear"):
+                 deriv: bool = False, stream=None, interp: str = "bilinear", channels: str = "xy",
+                 grad=(1.0, 1.0)):
         """specs: list of (n, h, radius, r, v[, conv_mode[, interp]]) with r, v device (T, 2).
         columns: None (by batch size), "split" or "wave": shape of the column-FFT kernels.
         deriv: also build the dK/dh tables (for forward_dh) and the weight slopes.
-        interp: "bilinear" or "cosine", for specs that do not name one."""
+        interp: "bilinear" or "cosine", for specs that do not name one.
+        channels ("xy" or "x") and grad (the selection-field gradient) apply to every problem."""
         keep = []
         arr = (Problem * len(specs))()
         for i, sp in enumerate(specs):
@@ -345,7 +359,7 @@ class Batch:
             if r.dtype != dtype or v.dtype != dtype:
                 raise ValueError("every problem of a batch shares the dtype")
             keep += [r, v]
-            arr[i] = problem(n, h, radius, r, v, conv_mode=mode, interp=ip)
+            arr[i] = problem(n, h, radius, r, v, conv_mode=mode, interp=ip, channels=channels, grad=grad)
         self.interps = [sp[6] if len(sp) > 6 else interp for sp in specs]
         self.count = len(specs)
         self.dtype = dtype
@@ -576,6 +590,39 @@ class Batch:
                 "nu": [[nu[k * B + b] for k in range(n_it + 1)] for b in range(B)]}
         return rho_out, info
 
+    # ---- the Core Stage (variational field reconstruction) and the trace image
+    def field_views(self, field_all):
+        """Per-problem [3, N, N] views (channels xx, xy, yy) of a field buffer."""
+        return [field_all[3 * self.c_offsets[b]:3 * self.c_offsets[b + 1]].view(3, n, n)
+                for b, n in enumerate(self.ns)]
+
+    def core_stage(self, s_all, gamma=1e-3, tol=1e-3, max_iter=10000, field_out=None, stream=None):
+        """The field minimising the Core Stage functional for every problem;
+        returns (field, CG steps per problem)."""
+        self._flat(s_all, self.s_offsets[-1], "s_all")
+        if field_out is None:
+            field_out = torch.empty(3 * self.c_offsets[-1], dtype=self.dtype, device=self.device)
+        self._flat(field_out, 3 * self.c_offsets[-1], "field_out")
+        if getattr(self, "_cwork", None) is None:
+            nb = ctypes.c_size_t()
+            _check(lib().mpi_batch_core_bytes(self._h, ctypes.byref(nb)), "mpi_batch_core_bytes")
+            self._cwork = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        it = (ctypes.c_int32 * self.count)()
+        _check(lib().mpi_batch_core_stage(self._h, s_all.data_ptr(), field_out.data_ptr(), float(gamma), float(tol),
+                                          int(max_iter), it, self.work.data_ptr(), self.work.numel(),
+                                          self._cwork.data_ptr(), self._cwork.numel(), _stream(stream)),
+               "mpi_batch_core_stage")
+        return field_out, list(it)
+
+    def field_trace(self, field_all, u_out=None, stream=None):
+        """u = A_xx + A_yy per problem (concentration-shaped)."""
+        self._flat(field_all, 3 * self.c_offsets[-1], "field_all")
+        if u_out is None:
+            u_out = torch.empty(self.c_offsets[-1], dtype=self.dtype, device=self.device)
+        _check(lib().mpi_batch_field_trace(self._h, field_all.data_ptr(), u_out.data_ptr(), _stream(stream)),
+               "mpi_batch_field_trace")
+        return u_out
+
     def sample_order(self, b, stream=None):
         """(time index, base cell i0 | j0 << 16) of problem b's samples in the
         order the plan holds them (int32 device tensors)."""
@@ -595,3 +642,16 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def velocity_forward_difference(r: torch.Tensor, dt: float, out: torch.Tensor | None = None, stream=None):
+    """v_k = (r_{k+1} - r_k) / dt on the device (the last sample repeats the
+    previous difference)."""
+    if r.ndim != 2 or r.shape[1] != 2 or not r.is_cuda or not r.is_contiguous():
+        raise ValueError("r must be a contiguous (T, 2) device tensor")
+    if out is None:
+        out = torch.empty_like(r)
+    _check(lib().mpi_velocity_forward_difference(r.data_ptr(), out.data_ptr(), r.shape[0], float(dt),
+                                                 _dtype_code(r.dtype), _stream(stream)),
+           "mpi_velocity_forward_difference")
+    return out

@@ -88,6 +88,23 @@ def lissajous(n_samples: int, ax: float = AMPLITUDE, ay: float = AMPLITUDE,
                            exc_amp=exc_amp, exc_cycles=exc_cycles))
 
 
+def experiment2(n_samples: int, ax: float = 0.8, ay: float = 0.85, ae: float = 0.05, fx: float = 50.0,
+                fy: float = 1.0, fe: float = 25000.0) -> Trajectory:
+    """The non-Lissajous figure of Section "Experiment 2", over one period of
+    the slow y drive: r(t) = (ax sin 2 pi fx t + ae sin 2 pi fe t, ay sin 2 pi
+    fy t) (the y drive at f_y, the reading of the printed formula), sampled at
+    n_samples points; v is the analytic derivative (the experiment itself
+    takes forward differences of the positions)."""
+    t = sample_times(n_samples)
+    w = 2.0 * math.pi
+    rx = ax * np.sin(w * fx * t) + ae * np.sin(w * fe * t)
+    vx = ax * w * fx * np.cos(w * fx * t) + ae * w * fe * np.cos(w * fe * t)
+    ry = ay * np.sin(w * fy * t)
+    vy = ay * w * fy * np.cos(w * fy * t)
+    return Trajectory(t, np.stack([rx, ry], 1), np.stack([vx, vy], 1), "experiment2",
+                      dict(ax=ax, ay=ay, ae=ae, fx=fx, fy=fy, fe=fe))
+
+
 def trajectory_independence(n_samples: int = 1 << 17) -> Trajectory:
     """Lissajous 17:16 plus an x excitation of amplitude 0.05 at 40x the x
     frequency, observed on the window t in [0, 0.6) (partial data)."""
@@ -109,6 +126,18 @@ def blobs(n: int, seed: int = 0, count: int = 3) -> np.ndarray:
         sig = rng.uniform(1.0, 3.0) * d
         amp = rng.uniform(0.2, 1.0)
         c += amp * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2.0 * sig * sig))
+    return c
+
+
+def bars(n: int, gap: float, length: float = 0.5, width: float = 0.06) -> np.ndarray:
+    """Two parallel vertical bars `gap` apart (field-of-view units, edge to
+    edge), the resolution phantoms of the experiments."""
+    x = centres(n)
+    X, Y = np.meshgrid(x, x)
+    c = np.zeros((n, n))
+    for sign in (-1.0, 1.0):
+        xc = sign * (gap + width) / 2.0
+        c[(np.abs(X - xc) <= width / 2.0) & (np.abs(Y) <= length / 2.0)] = 1.0
     return c
 
 

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol(mpik):
 
 
 def test_abi_version_and_status_strings(mpik):
-    assert mpik.lib().mpi_abi_version() == 1
+    assert mpik.lib().mpi_abi_version() == 2
     seen = set()
     for code in (0, -1, -2, -3, -4, -5, -6):
         s = mpik.status_str(code)
@@ -67,13 +67,21 @@ def test_plan_bytes_valid(mpik):
 @pytest.mark.parametrize("field,value,code", [
     ("n", 1, -1), ("n", 2000, -1), ("h", 0.0, -1), ("h", float("nan"), -1), ("radius", -1, -1),
     ("n_samples", 0, -1), ("dtype", 7, -4), ("conv_mode", 9, -1), ("interp", 2, -1), ("interp", -1, -1),
-    ("channels", 1, -6),
+    ("channels", 2, -1), ("grad_x", float("inf"), -1), ("grad_y", 0.0, -1),
 ])
 def test_plan_bytes_rejects(mpik, field, value, code):
     p = _prob(mpik)
     setattr(p, field, value)
     pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
     assert mpik.lib().mpi_plan_bytes(ctypes.byref(p), ctypes.byref(pb), ctypes.byref(wb)) == code
+
+
+def test_channels_and_gradients_accepted(mpik):
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    for ch, gx, gy in ((1, 1.39, -3.16), (0, 0.0, 0.0), (0, -1.0, -1.0)):
+        p = _prob(mpik)
+        p.channels, p.grad_x, p.grad_y = ch, gx, gy
+        assert mpik.lib().mpi_plan_bytes(ctypes.byref(p), ctypes.byref(pb), ctypes.byref(wb)) == 0
 
 
 def test_both_interpolators_accepted(mpik):
