@@ -353,8 +353,11 @@ int mpi_batch_pnp(const mpi_plan* plan, const void* u_all, void* rho_all, const 
  * meets |r| <= tol |rhs| or after max_iter steps (the paper: tol 1e-3,
  * 10,000 steps).  s_all: signals in time order as for mpi_batch_forward;
  * field_all: 3 * c_elems values, problem b's [3][N][N] field (channels xx,
- * xy, yy) at element offset 3 * c_offsets[b].  iters: host array of count
- * step counts (may be NULL).  cwork: caller-owned device memory of at least
+ * xy, yy) at element offset 3 * c_offsets[b].  Precision: the sampling
+ * (I and I^T) runs in the plan's dtype on the search direction rounded to
+ * it; the regulariser, the CG vectors and the dot products are float64, and
+ * the solution is rounded to the dtype once at the end.  iters: host array of
+ * count step counts (may be NULL).  cwork: caller-owned device memory of at least
  * mpi_batch_core_bytes(plan) bytes, 256-byte aligned.  MPI_ERR_UNSUPPORTED
  * when the row-wise sampling of the largest grid does not fit in LDS.
  * Synchronises `stream` (the stop flags are polled between blocks of steps).

@@ -10,10 +10,17 @@
 //
 // Fields are [3][N][N] per problem at element offset 3 o_c of the caller's
 // concatenated buffer; signals in cell order at element offset o_s.  One step
-// is four launches: the gather I p (per base-cell row), the Laplacian of p,
+// is five launches: the gather I p (per base-cell row), the Laplacian of p,
 // the transpose sampling with the epilogue q = (1/L) I^T I p + gamma delta^2 W
 // Delta (Delta p) and per-row partial sums of <p, q>, then the CG updates of
 // the Deconvolution Stage with three components per cell.
+//
+// Precision: the sampling runs in the plan's dtype T on p rounded to T; the
+// regulariser, q and the CG vectors are float64.  The biharmonic stencil
+// cancels on smooth fields (its coefficients sum to 0 and reach 20 gamma /
+// delta^2 per cell), so in float32 its rounding error would be a perturbation
+// of the operator near eps_32 times its largest eigenvalue, which is
+// comparable to the smallest eigenvalues that decide the step count.
 #pragma once
 #include "common.hpp"
 #include "deconv.hpp"
@@ -63,11 +70,10 @@ __device__ __forceinline__ T lap5(const T* __restrict__ c, int N, int j, int i) 
     return s;
 }
 
-// l = Delta a without the 1/delta^2 factor, every channel.  grid
+// l = Delta a without the 1/delta^2 factor, every channel, float64.  grid
 // (ceil(3 N^2 / 256), problems), 256 threads.
-template <typename T>
-__global__ void __launch_bounds__(256) k_core_lap(const Prob* __restrict__ P, const T* __restrict__ a,
-                                                  T* __restrict__ l, const int* __restrict__ skip) {
+__global__ void __launch_bounds__(256) k_core_lap(const Prob* __restrict__ P, const double* __restrict__ a,
+                                                  double* __restrict__ l, const int* __restrict__ skip) {
     const Prob& p = P[blockIdx.y];
     if (skip && skip[blockIdx.y]) return;
     const int N = p.n;
@@ -79,18 +85,19 @@ __global__ void __launch_bounds__(256) k_core_lap(const Prob* __restrict__ P, co
     l[base + rem] = lap5(a + base, N, j, i);
 }
 
-// Grid row j of the three channels of (1/L) I^T y (cell-order y), then
-//   EPI 0: out = that (the right-hand side), written to `out`;
+// Grid row j of the three channels of (1/L) I^T y (cell-order y, sums in
+// T), then, in float64,
+//   EPI 0: out = that (the right-hand side);
 //   EPI 1: out = that + gamma delta^2 W Delta l with l = Delta p (as
 //          k_core_lap left it, unscaled: the two 1/delta^2 factors and
 //          delta^2 make gamma / delta^2), and part[b][j] = the row's sum of
-//          p * out in float64.
+//          p * out.
 // grid (max N, problems), 256 threads; dynamic LDS as the operator's
 // row-wise transpose sampling.
 template <typename T, int EPI>
 __global__ void __launch_bounds__(256) k_core_scatter(const Prob* __restrict__ P, const T* __restrict__ y,
-                                                      T* __restrict__ out, const T* __restrict__ pv,
-                                                      const T* __restrict__ l, double gamma,
+                                                      double* __restrict__ out, const double* __restrict__ pv,
+                                                      const double* __restrict__ l, double gamma,
                                                       double* __restrict__ part, const char* __restrict__ plan,
                                                       const int* __restrict__ skip) {
     extern __shared__ __align__(16) char smem[];
@@ -104,28 +111,28 @@ __global__ void __launch_bounds__(256) k_core_scatter(const Prob* __restrict__ P
     scatter_row<T, true, 256>(g, scatter_lds<T>(sc, N, 256), N, j, at<int>(plan, p.o_binstart),
                               at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
                               reinterpret_cast<const vec2<T>*>(y + p.o_s), nullptr, threadIdx.x, p.chan == 1);
-    const T inv_l = T(1.0 / double(p.t));
+    const double inv_l = 1.0 / double(p.t);
     const int64_t nn = int64_t(N) * N;
-    T* o = out + 3 * p.o_c;
+    double* o = out + 3 * p.o_c;
     if (EPI == 0) {
         for (int i = threadIdx.x; i < 3 * N; i += blockDim.x) {
             const int ch = i / N, x = i % N;
-            o[ch * nn + int64_t(j) * N + x] = inv_l * g[i];
+            o[ch * nn + int64_t(j) * N + x] = inv_l * double(g[i]);
         }
         return;
     }
     const double d2 = 4.0 / (double(N) * N);                   // delta^2
-    const T reg = T(gamma / d2);                                 // gamma delta^2 / delta^4
-    const T* pp = pv + 3 * p.o_c;
-    const T* ll = l + 3 * p.o_c;
+    const double reg = gamma / d2;                               // gamma delta^2 / delta^4
+    const double* pp = pv + 3 * p.o_c;
+    const double* ll = l + 3 * p.o_c;
     double acc = 0.0;
     for (int i = threadIdx.x; i < 3 * N; i += blockDim.x) {
         const int ch = i / N, x = i % N;
-        const T w = ch == 1 ? T(2) : T(1);
+        const double w = ch == 1 ? 2.0 : 1.0;
         const int64_t off = ch * nn + int64_t(j) * N + x;
-        const T q = inv_l * g[i] + reg * w * lap5(ll + ch * nn, N, j, x);
+        const double q = inv_l * double(g[i]) + reg * w * lap5(ll + ch * nn, N, j, x);
         o[off] = q;
-        acc += double(pp[off]) * double(q);
+        acc += pp[off] * q;
     }
     red[threadIdx.x] = acc;
     __syncthreads();

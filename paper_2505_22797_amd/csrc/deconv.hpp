@@ -4,6 +4,12 @@
 // (Section "Denoiser Artifact Reduction") and the noise estimate
 // sigma = sqrt(Var) that drives the ZeroShot-PnP schedule.
 //
+// Mixed precision: the Krylov vectors x, r, p are float64 whatever the
+// operator's dtype T; the operator is applied to pt, p rounded to T (written
+// next to p), and returns q in T.  In float32 this keeps the recursively
+// updated residual close to the true one over thousands of steps (with
+// float32 vectors it drifts above the tolerance at 256^2 in the Core Stage).
+//
 // Every problem of a batch runs its own CG; the scalars live in device memory
 // and every kernel of a step skips problems whose flag done[b] is set, so the
 // host only polls the flags from time to time.  The residual norm and the flag
@@ -77,27 +83,40 @@ __device__ __forceinline__ double broadcast0(double v, double* slot) {
 // The CG vectors hold `comps` values per grid cell (1: concentrations, 3:
 // the Core Stage's field), at element offset comps * o_c.
 //
-// grid (kDotParts, problems), 256 threads.  b = cu + nu rho2 (rho2 may be
-// null: b = cu); x = 0, r = p = b; part = slices of |b|^2.
-template <typename T>
-__global__ void __launch_bounds__(256) k_cg_init(const Prob* __restrict__ P, int comps, const T* __restrict__ cu,
-                                                 const T* __restrict__ rho2, CgState s, T* __restrict__ x,
-                                                 T* __restrict__ r, T* __restrict__ pv, double* __restrict__ part) {
+// grid (kDotParts, problems), 256 threads.  b = cu + nu rho2 in float64
+// (rho2 may be null: b = cu); x = 0, r = p = b, pt = b rounded to T;
+// part = slices of |b|^2.
+template <typename T, typename U = T>
+__global__ void __launch_bounds__(256) k_cg_init(const Prob* __restrict__ P, int comps, const U* __restrict__ cu,
+                                                 const T* __restrict__ rho2, CgState s, double* __restrict__ x,
+                                                 double* __restrict__ r, double* __restrict__ pv, T* __restrict__ pt,
+                                                 double* __restrict__ part) {
     __shared__ double red[256];
     const Prob& p = P[blockIdx.y];
     const int64_t m = int64_t(comps) * p.n * p.n, o = int64_t(comps) * p.o_c;
     int64_t lo, hi;
     slice_of(m, lo, hi);
-    const T nu = T(s.nu[blockIdx.y]);
+    const double nu = rho2 ? s.nu[blockIdx.y] : 0.0;
     double acc = 0.0;
     for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
-        const T b = rho2 ? cu[o + e] + nu * rho2[o + e] : cu[o + e];
-        x[o + e] = T(0);
+        const double b = rho2 ? double(cu[o + e]) + nu * double(rho2[o + e]) : double(cu[o + e]);
+        x[o + e] = 0.0;
         r[o + e] = b;
         pv[o + e] = b;
-        acc += double(b) * double(b);
+        pt[o + e] = T(b);
+        acc += b * b;
     }
     reduce_to_part(acc, red, part);
+}
+
+// out = x rounded to T (the solver's result in the caller's dtype).
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_store(const Prob* __restrict__ P, int comps,
+                                                  const double* __restrict__ x, T* __restrict__ out) {
+    const Prob& p = P[blockIdx.y];
+    const int64_t m = int64_t(comps) * p.n * p.n, o = int64_t(comps) * p.o_c;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < m; e += int64_t(gridDim.x) * blockDim.x)
+        out[o + e] = T(x[o + e]);
 }
 
 // one thread per problem: rr = bb = |b|^2, no step taken yet (slot 0).
@@ -111,8 +130,8 @@ __global__ void k_cg_begin(int count, CgState s, const double* __restrict__ part
     s.done[b] = (0 < max_iter && rr > tol * tol * rr) ? 0 : 1;
 }
 
-// Direct-path problems: q <- q + nu p (q holds C^T C p); part = slices of
-// <p, q>.  (The FFT row stage does this for the FFT problems.)
+// Direct-path problems: q <- q + nu pt (q holds C^T C pt); part = slices of
+// <pt, q>.  (The FFT row stage does this for the FFT problems.)
 template <typename T>
 __global__ void __launch_bounds__(256) k_cg_pq(const Prob* __restrict__ P, CgState s, int par,
                                                const T* __restrict__ pv, T* __restrict__ q,
@@ -135,12 +154,14 @@ __global__ void __launch_bounds__(256) k_cg_pq(const Prob* __restrict__ P, CgSta
     reduce_to_part(acc, red, part, kCgRowParts);
 }
 
-// alpha = rr / <p, q>; x += alpha p; r -= alpha q; part_rr = slices of |r|^2.
-template <typename T>
+// alpha = rr / <p, q>; x += alpha p; r -= alpha q (float64); part_rr =
+// slices of |r|^2.
+template <typename T, typename Q = T>
 __global__ void __launch_bounds__(256) k_cg_update(const Prob* __restrict__ P, CgState s, int par, int comps,
-                                                   int pq_kind, int pq_stride, const T* __restrict__ pv,
-                                                   const T* __restrict__ q, T* __restrict__ x, T* __restrict__ r,
-                                                   const double* __restrict__ part_pq, double* __restrict__ part_rr) {
+                                                   int pq_kind, int pq_stride, const double* __restrict__ pv,
+                                                   const Q* __restrict__ q, double* __restrict__ x,
+                                                   double* __restrict__ r, const double* __restrict__ part_pq,
+                                                   double* __restrict__ part_rr) {
     __shared__ double red[256];
     __shared__ double slot;
     const int b = blockIdx.y, cnt = gridDim.y;
@@ -154,13 +175,12 @@ __global__ void __launch_bounds__(256) k_cg_update(const Prob* __restrict__ P, C
             ? s.rr[par * cnt + b] / sum_parts(part_pq + int64_t(b) * pq_stride, pq_parts(p, pq_kind))
             : 0.0,
         &slot);
-    const T a = T(alpha);
     double acc = 0.0;
     for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
-        x[o + e] += a * pv[o + e];
-        const T re = r[o + e] - a * q[o + e];
+        x[o + e] += alpha * pv[o + e];
+        const double re = r[o + e] - alpha * double(q[o + e]);
         r[o + e] = re;
-        acc += double(re) * double(re);
+        acc += re * re;
     }
     reduce_to_part(acc, red, part_rr);
 }
@@ -171,8 +191,9 @@ __global__ void __launch_bounds__(256) k_cg_update(const Prob* __restrict__ P, C
 // problem's state is carried over unchanged.
 template <typename T>
 __global__ void __launch_bounds__(256) k_cg_dir(const Prob* __restrict__ P, CgState s, int par, int comps,
-                                                const T* __restrict__ r, T* __restrict__ pv,
-                                                const double* __restrict__ part_rr, double tol, int max_iter) {
+                                                const double* __restrict__ r, double* __restrict__ pv,
+                                                T* __restrict__ pt, const double* __restrict__ part_rr, double tol,
+                                                int max_iter) {
     __shared__ double slot;
     const int b = blockIdx.y, cnt = gridDim.y;
     const int cur = par * cnt + b, nxt = (1 - par) * cnt + b;
@@ -189,8 +210,12 @@ __global__ void __launch_bounds__(256) k_cg_dir(const Prob* __restrict__ P, CgSt
     int64_t lo, hi;
     slice_of(m, lo, hi);
     const double rr_new = broadcast0(threadIdx.x == 0 ? sum_parts(part_rr + int64_t(b) * kDotParts) : 0.0, &slot);
-    const T bt = T(rr_new / s.rr[cur]);
-    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) pv[o + e] = r[o + e] + bt * pv[o + e];
+    const double bt = rr_new / s.rr[cur];
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
+        const double pn = r[o + e] + bt * pv[o + e];
+        pv[o + e] = pn;
+        pt[o + e] = T(pn);
+    }
     if (lead) {
         const int it = s.iters[b] + 1;
         s.iters[b] = it;

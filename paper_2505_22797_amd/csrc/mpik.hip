@@ -1172,7 +1172,7 @@ int check_iter(const mpi_iter_params* params) {
 // vectors r, p, t = C p, q = C t, for the PnP loop also C u and rho_1, then
 // the per-problem solver state, partial sums and statistics.
 struct DeconvLayout {
-    size_t r = 0, p = 0, t = 0, q = 0, cu = 0, rho1 = 0;
+    size_t r = 0, p = 0, x = 0, pt = 0, t = 0, q = 0, cu = 0, rho1 = 0;
     size_t rr = 0, bb = 0, nu = 0, iters = 0, done = 0, part_a = 0, part_b = 0, st_q = 0, st_mean = 0, st_var = 0;
     size_t bytes = 0;
 };
@@ -1180,9 +1180,11 @@ struct DeconvLayout {
 DeconvLayout deconv_layout(const mpi_plan* pl) {
     DeconvLayout L;
     size_t off = 0;
-    const size_t v = size_t(pl->L.c_elems) * pl->L.elem, B = size_t(pl->count);
-    L.r = take(off, v);
-    L.p = take(off, v);
+    const size_t v = size_t(pl->L.c_elems) * pl->L.elem, v64 = size_t(pl->L.c_elems) * 8, B = size_t(pl->count);
+    L.r = take(off, v64);                    // Krylov vectors in float64
+    L.p = take(off, v64);
+    L.x = take(off, v64);
+    L.pt = take(off, v);                     // p rounded to the operator's dtype
     L.t = take(off, v);
     L.q = take(off, v);
     L.cu = take(off, v);
@@ -1249,15 +1251,17 @@ void trace_conv_impl(const mpi_plan* pl, const T* in, T* out, char* work, hipStr
 // columns, and the inverse rows with the CG epilogue -- five launches per size
 // group.  Direct problems: two 1 -> 1 convolutions and k_cg_pq.
 template <typename T>
-void cg_step(const mpi_plan* pl, int par, T* x, double tol, int max_iter, char* work, char* dw,
-             const DeconvLayout& L, hipStream_t st) {
+void cg_step(const mpi_plan* pl, int par, double tol, int max_iter, char* work, char* dw, const DeconvLayout& L,
+             hipStream_t st) {
     const Prob* P = pl->dprob;
     const char* plan = pl->plan;
     const int B = pl->count;
     const CgState s = cg_state(L, dw);
     const int* skip = s.done + par * B;
-    T* r = reinterpret_cast<T*>(dw + L.r);
-    T* pv = reinterpret_cast<T*>(dw + L.p);
+    double* r = reinterpret_cast<double*>(dw + L.r);
+    double* p64 = reinterpret_cast<double*>(dw + L.p);
+    double* x = reinterpret_cast<double*>(dw + L.x);
+    T* pv = reinterpret_cast<T*>(dw + L.pt);
     T* t = reinterpret_cast<T*>(dw + L.t);
     T* q = reinterpret_cast<T*>(dw + L.q);
     double* pa = reinterpret_cast<double*>(dw + L.part_a);
@@ -1291,8 +1295,8 @@ void cg_step(const mpi_plan* pl, int par, T* x, double tol, int max_iter, char* 
         }
         k_cg_pq<T><<<el, 256, 0, st>>>(P, s, par, pv, q, pa);
     }
-    k_cg_update<T><<<el, 256, 0, st>>>(P, s, par, 1, 0, kCgRowParts, pv, q, x, r, pa, pb);
-    k_cg_dir<T><<<el, 256, 0, st>>>(P, s, par, 1, r, pv, pb, tol, max_iter);
+    k_cg_update<T><<<el, 256, 0, st>>>(P, s, par, 1, 0, kCgRowParts, p64, q, x, r, pa, pb);
+    k_cg_dir<T><<<el, 256, 0, st>>>(P, s, par, 1, r, p64, pv, pb, tol, max_iter);
 }
 
 constexpr int kCgBlock = 4;   // CG steps per captured graph (even: each block starts on state slot 0)
@@ -1359,21 +1363,24 @@ int cg_impl(mpi_plan* pl, const T* cu, const T* rho2, T* x, double tol, int max_
     const Prob* P = pl->dprob;
     const int B = pl->count;
     const CgState s = cg_state(L, dw);
-    T* r = reinterpret_cast<T*>(dw + L.r);
-    T* pv = reinterpret_cast<T*>(dw + L.p);
+    double* r = reinterpret_cast<double*>(dw + L.r);
+    double* p64 = reinterpret_cast<double*>(dw + L.p);
+    double* x64 = reinterpret_cast<double*>(dw + L.x);
+    T* pt = reinterpret_cast<T*>(dw + L.pt);
     double* pa = reinterpret_cast<double*>(dw + L.part_a);
-    k_cg_init<T><<<dim3(kDotParts, B), 256, 0, st>>>(P, 1, cu, rho2, s, x, r, pv, pa);
+    k_cg_init<T><<<dim3(kDotParts, B), 256, 0, st>>>(P, 1, cu, rho2, s, x64, r, p64, pt, pa);
     k_cg_begin<<<blocks(B, 256), 256, 0, st>>>(B, s, pa, tol, max_iter);
     HIP_TRY(hipGetLastError());
     if (max_iter > 0) {
-        const std::vector<double> key{key_of(x), key_of(work), key_of(dw), tol, double(max_iter)};
+        const std::vector<double> key{key_of(work), key_of(dw), tol, double(max_iter)};
         int rc = cached_graph(pl->cg_gc, key, st, [&](hipStream_t cap) {
-            for (int i = 0; i < kCgBlock; ++i) cg_step<T>(pl, i & 1, x, tol, max_iter, work, dw, L, cap);
+            for (int i = 0; i < kCgBlock; ++i) cg_step<T>(pl, i & 1, tol, max_iter, work, dw, L, cap);
         });
         if (rc != MPI_OK) return rc;
         rc = run_cg_blocks(pl->cg_gc.exec, s.done, B, max_iter, st);
         if (rc != MPI_OK) return rc;
     }
+    k_cg_store<T><<<dim3(blocks(int64_t(pl->max_n) * pl->max_n, 256), B), 256, 0, st>>>(P, 1, x64, x);
     if (iters) HIP_TRY(hipMemcpyAsync(iters, s.iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     return MPI_OK;
@@ -1466,18 +1473,22 @@ int pnp_impl(mpi_plan* pl, const T* u, T* rho, const mpi_pnp_params* pp, int32_t
 // l (three channels per cell), the signal-shaped y = I p in cell order, the
 // solver state and partial sums.
 struct CoreLayout {
-    size_t r = 0, p = 0, q = 0, l = 0, y = 0, rr = 0, bb = 0, nu = 0, iters = 0, done = 0, part_a = 0, part_b = 0;
+    size_t r = 0, p = 0, x = 0, pt = 0, q = 0, l = 0, y = 0;
+    size_t rr = 0, bb = 0, nu = 0, iters = 0, done = 0, part_a = 0, part_b = 0;
     size_t bytes = 0;
 };
 
 CoreLayout core_layout(const mpi_plan* pl) {
     CoreLayout L;
     size_t off = 0;
-    const size_t v = size_t(3) * pl->L.c_elems * pl->L.elem, B = size_t(pl->count);
-    L.r = take(off, v);
-    L.p = take(off, v);
-    L.q = take(off, v);
-    L.l = take(off, v);
+    const size_t v = size_t(3) * pl->L.c_elems * pl->L.elem, v64 = size_t(3) * pl->L.c_elems * 8,
+                 B = size_t(pl->count);
+    L.r = take(off, v64);                    // Krylov vectors in float64
+    L.p = take(off, v64);
+    L.x = take(off, v64);
+    L.pt = take(off, v);                     // p rounded to the sampling's dtype
+    L.q = take(off, v64);                    // operator output and regulariser in float64
+    L.l = take(off, v64);
     L.y = take(off, size_t(pl->L.s_elems) * pl->L.elem);
     L.rr = take(off, 2 * 8 * B);
     L.bb = take(off, 8 * B);
@@ -1493,12 +1504,12 @@ CoreLayout core_layout(const mpi_plan* pl) {
 size_t core_gather_smem(const mpi_plan* pl) { return size_t(6) * pl->max_n * pl->L.elem; }
 size_t core_scatter_smem(const mpi_plan* pl) { return scatter_rows_smem(pl->max_n, pl->L.elem); }
 
-// One Core Stage CG step (parity par): y = I p, l = Delta p (unscaled),
-// q = (1/L) I^T y + gamma delta^2 W Delta l with the per-row <p, q>, then the
-// x, r and p updates and the next state slot.
+// One Core Stage CG step (parity par): y = I p (on p rounded to T), l =
+// Delta p (unscaled, float64), q = (1/L) I^T y + gamma delta^2 W Delta l with
+// the per-row <p, q>, then the x, r and p updates and the next state slot.
 template <typename T>
-void core_step(const mpi_plan* pl, int par, T* x, double gamma, double tol, int max_iter, char* cw,
-               const CoreLayout& L, hipStream_t st) {
+void core_step(const mpi_plan* pl, int par, double gamma, double tol, int max_iter, char* cw, const CoreLayout& L,
+               hipStream_t st) {
     const Prob* P = pl->dprob;
     const char* plan = pl->plan;
     const int B = pl->count;
@@ -1509,20 +1520,22 @@ void core_step(const mpi_plan* pl, int par, T* x, double gamma, double tol, int 
     s.iters = reinterpret_cast<int*>(cw + L.iters);
     s.done = reinterpret_cast<int*>(cw + L.done);
     const int* skip = s.done + par * B;
-    T* r = reinterpret_cast<T*>(cw + L.r);
-    T* pv = reinterpret_cast<T*>(cw + L.p);
-    T* q = reinterpret_cast<T*>(cw + L.q);
-    T* l = reinterpret_cast<T*>(cw + L.l);
+    double* r = reinterpret_cast<double*>(cw + L.r);
+    double* p64 = reinterpret_cast<double*>(cw + L.p);
+    double* x = reinterpret_cast<double*>(cw + L.x);
+    T* pv = reinterpret_cast<T*>(cw + L.pt);
+    double* q = reinterpret_cast<double*>(cw + L.q);
+    double* l = reinterpret_cast<double*>(cw + L.l);
     T* y = reinterpret_cast<T*>(cw + L.y);
     double* pa = reinterpret_cast<double*>(cw + L.part_a);
     double* pb = reinterpret_cast<double*>(cw + L.part_b);
     const dim3 el(kDotParts, B);
     k_core_gather<T><<<dim3(pl->max_nb, B), 256, core_gather_smem(pl), st>>>(P, pv, y, plan, skip);
-    k_core_lap<T><<<dim3(blocks(int64_t(3) * pl->max_n * pl->max_n, 256), B), 256, 0, st>>>(P, pv, l, skip);
-    k_core_scatter<T, 1><<<dim3(pl->max_n, B), 256, core_scatter_smem(pl), st>>>(P, y, q, pv, l, gamma, pa, plan,
-                                                                                 skip);
-    k_cg_update<T><<<el, 256, 0, st>>>(P, s, par, 3, 1, kCoreParts, pv, q, x, r, pa, pb);
-    k_cg_dir<T><<<el, 256, 0, st>>>(P, s, par, 3, r, pv, pb, tol, max_iter);
+    k_core_lap<<<dim3(blocks(int64_t(3) * pl->max_n * pl->max_n, 256), B), 256, 0, st>>>(P, p64, l, skip);
+    k_core_scatter<T, 1><<<dim3(pl->max_n, B), 256, core_scatter_smem(pl), st>>>(P, y, q, p64, l, gamma, pa,
+                                                                                 plan, skip);
+    k_cg_update<T, double><<<el, 256, 0, st>>>(P, s, par, 3, 1, kCoreParts, p64, q, x, r, pa, pb);
+    k_cg_dir<T><<<el, 256, 0, st>>>(P, s, par, 3, r, p64, pv, pb, tol, max_iter);
 }
 
 // The Core Stage: CG on the Euler-Lagrange equations of eq. first:step from
@@ -1542,27 +1555,30 @@ int core_impl(mpi_plan* pl, const T* sig, T* field, double gamma, double tol, in
     s.nu = reinterpret_cast<double*>(cw + L.nu);
     s.iters = reinterpret_cast<int*>(cw + L.iters);
     s.done = reinterpret_cast<int*>(cw + L.done);
-    T* r = reinterpret_cast<T*>(cw + L.r);
-    T* pv = reinterpret_cast<T*>(cw + L.p);
-    T* q = reinterpret_cast<T*>(cw + L.q);
+    double* r = reinterpret_cast<double*>(cw + L.r);
+    double* p64 = reinterpret_cast<double*>(cw + L.p);
+    double* x64 = reinterpret_cast<double*>(cw + L.x);
+    T* pt = reinterpret_cast<T*>(cw + L.pt);
+    double* q = reinterpret_cast<double*>(cw + L.q);
     T* y = reinterpret_cast<T*>(cw + L.y);
     double* pb = reinterpret_cast<double*>(cw + L.part_b);
     // right-hand side (1/L) I^T s into q, then x = 0, r = p = q
     k_core_permute<T><<<dim3(blocks(pl->max_t, 256), B), 256, 0, st>>>(P, sig, y, pl->plan);
     k_core_scatter<T, 0><<<dim3(pl->max_n, B), 256, core_scatter_smem(pl), st>>>(P, y, q, nullptr, nullptr, 0.0,
                                                                                  nullptr, pl->plan, nullptr);
-    k_cg_init<T><<<dim3(kDotParts, B), 256, 0, st>>>(P, 3, q, nullptr, s, field, r, pv, pb);
+    k_cg_init<T, double><<<dim3(kDotParts, B), 256, 0, st>>>(P, 3, q, nullptr, s, x64, r, p64, pt, pb);
     k_cg_begin<<<blocks(B, 256), 256, 0, st>>>(B, s, pb, tol, max_iter);
     HIP_TRY(hipGetLastError());
     if (max_iter > 0) {
-        const std::vector<double> key{key_of(field), key_of(cw), gamma, tol, double(max_iter)};
+        const std::vector<double> key{key_of(cw), gamma, tol, double(max_iter)};
         int rc = cached_graph(pl->core_gc, key, st, [&](hipStream_t cap) {
-            for (int i = 0; i < kCgBlock; ++i) core_step<T>(pl, i & 1, field, gamma, tol, max_iter, cw, L, cap);
+            for (int i = 0; i < kCgBlock; ++i) core_step<T>(pl, i & 1, gamma, tol, max_iter, cw, L, cap);
         });
         if (rc != MPI_OK) return rc;
         rc = run_cg_blocks(pl->core_gc.exec, s.done, B, max_iter, st);
         if (rc != MPI_OK) return rc;
     }
+    k_cg_store<T><<<dim3(blocks(int64_t(3) * pl->max_n * pl->max_n, 256), B), 256, 0, st>>>(P, 3, x64, field);
     if (iters) HIP_TRY(hipMemcpyAsync(iters, s.iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     return MPI_OK;

@@ -3,14 +3,21 @@ reconstruction by conjugate gradients on its Euler-Lagrange equations) and of
 the two-stage pipeline (Core Stage, trace image, ZeroShot-PnP deconvolution)
 through the C ABI against the float64 oracle.
 
-At gamma = 1e-3 the Core Stage's normal equations are well conditioned enough
-for CG to be stable under rounding (measured on the CPU: two float64 solvers
-that differ in summation order agree to 1e-15 and a float32 one to 1e-6 after
-135 steps at 64^2), so the library matches the oracle element by element
-(float64 1e-10, float32 1e-5) with identical step counts.  At the full 256^2
-shape the oracle's solve is too slow for a test; there the library's field
-must meet the stop rule in the true residual that the oracle evaluates.
+The Core Stage's normal equations are ill conditioned (the regulariser's
+Delta^2 grows like N^4): perturbations of the operator at the level of float64
+rounding (the device's cosine, x (1/L) against x / L, another summation order)
+move the converged solution by about kappa * 1e-16, measured 1e-10 .. 4e-7 in
+float64.  So the tests compare element by element where CG has taken few steps
+(a fixed count of 12: float64 1e-10, float32 1e-5), and otherwise check what
+the method specifies: the stop rule in the true residual (evaluated by the
+oracle in float64), the step count (float64: the oracle's +-1; float32: not
+below it) and the accuracy against the true field, within 10 % of the
+oracle's.  The library's CG keeps its vectors in float64 for float32
+operators, which keeps the recursive residual honest over thousands of steps.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -54,21 +61,49 @@ SHAPES = [(16, 400, 15, "fft"), (24, 900, 5, "direct"), (32, 2000, 31, "fft")]
 TOL = {torch.float64: 1e-10, torch.float32: 1e-5}
 
 
+def check_solve(it, a, steps, ref_steps, ref, dtype, gamma, tol, interp="cosine"):
+    """The stop rule in the true residual, the step count, and the accuracy
+    against the true field within 10 % of the oracle's."""
+    b = O.core_rhs(it["s"], it["r"], it["v"], it["n"], interp)
+    res = O.core_normal(a, it["r"], it["v"], gamma, interp) - b
+    slack = 1e-6 if dtype == torch.float64 else 0.05
+    assert np.linalg.norm(res) <= tol * (1 + slack) * np.linalg.norm(b), np.linalg.norm(res) / np.linalg.norm(b)
+    if dtype == torch.float64:
+        assert abs(steps - ref_steps) <= 1, (steps, ref_steps)
+    else:
+        assert ref_steps - 1 <= steps <= 2 * ref_steps + 2, (steps, ref_steps)
+    assert rel_l2(a, it["G"]) <= 1.1 * rel_l2(ref, it["G"]), (rel_l2(a, it["G"]), rel_l2(ref, it["G"]))
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("mode", ["tol", "fixed"])
-def test_core_stage_matches_oracle(dtype, mode):
+def test_core_stage_fixed_steps_match_oracle(dtype):
+    """12 CG steps: element-wise parity on a batch mixing grids, windows and paths."""
     cc = CoreCase(SHAPES, dtype)
-    tol, max_iter = (1e-3, 10000) if mode == "tol" else (0.0, 12)
-    field, steps = cc.batch.core_stage(cc.s_all(), gamma=1e-3, tol=tol, max_iter=max_iter)
+    field, steps = cc.batch.core_stage(cc.s_all(), gamma=1e-3, tol=0.0, max_iter=12)
     got = cc.fields(field)
     for i, it in enumerate(cc.items):
-        ref, k = O.core_stage(it["s"], it["r"], it["v"], it["n"], 1e-3, tol=tol, max_iter=max_iter)
-        assert steps[i] == k, (i, steps[i], k)
+        ref, k = O.core_stage(it["s"], it["r"], it["v"], it["n"], 1e-3, tol=0.0, max_iter=12)
+        assert steps[i] == k == 12
         assert rel_l2(got[i], ref) <= TOL[dtype], (i, rel_l2(got[i], ref))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_core_stage_to_tolerance(dtype):
+    cc = CoreCase(SHAPES, dtype)
+    field, steps = cc.batch.core_stage(cc.s_all(), gamma=1e-3, tol=1e-3, max_iter=10000)
+    got = cc.fields(field)
+    for i, it in enumerate(cc.items):
+        ref, k = O.core_stage(it["s"], it["r"], it["v"], it["n"], 1e-3, tol=1e-3)
+        check_solve(it, got[i], steps[i], k, ref, dtype, 1e-3, 1e-3)
 
 
 def test_core_stage_bilinear_plan_and_field_trace():
     cc = CoreCase(SHAPES, torch.float64, interp="bilinear", seed=3)
+    field, steps = cc.batch.core_stage(cc.s_all(), gamma=3e-3, tol=0.0, max_iter=12)
+    got = cc.fields(field)
+    for i, it in enumerate(cc.items):
+        ref, _ = O.core_stage(it["s"], it["r"], it["v"], it["n"], 3e-3, tol=0.0, max_iter=12, interp="bilinear")
+        assert rel_l2(got[i], ref) <= 1e-10
     field, steps = cc.batch.core_stage(cc.s_all(), gamma=3e-3, tol=1e-6, max_iter=5000)
     got = cc.fields(field)
     u = cc.batch.field_trace(field)
@@ -76,8 +111,7 @@ def test_core_stage_bilinear_plan_and_field_trace():
     us = [x.double().cpu().numpy() for x in cc.batch.c_views(u)]
     for i, it in enumerate(cc.items):
         ref, k = O.core_stage(it["s"], it["r"], it["v"], it["n"], 3e-3, tol=1e-6, max_iter=5000, interp="bilinear")
-        assert steps[i] == k
-        assert rel_l2(got[i], ref) <= 1e-10
+        check_solve(it, got[i], steps[i], k, ref, torch.float64, 3e-3, 1e-6, interp="bilinear")
         assert np.array_equal(us[i], got[i][0] + got[i][2])
 
 
@@ -94,25 +128,32 @@ def test_core_stage_degenerate_inputs():
 def test_core_stage_full_size_meets_the_stop_rule():
     """256^2, 53,856 samples of the Lissajous figure, cosine interpolation,
     float32, gamma = 1e-3: the true residual of the Euler-Lagrange equations
-    (oracle, float64) meets the tolerance and the field is close to the true
-    one."""
+    (oracle, float64) meets the tolerance, the step count is in the float32
+    window around the float64 oracle's and the field is as close to the true
+    one as the oracle's (figures stored by tests/golden/make_core_headline.py,
+    about 90 s of oracle time)."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "core_headline_256.json")) as f:
+        ref = json.load(f)
     P = S.headline()
-    cc = CoreCase([(P.n, P.n_samples, 31, "fft")], torch.float32, seed=5)
-    field, steps = cc.batch.core_stage(cc.s_all(), gamma=1e-3, tol=1e-3, max_iter=10000)
+    assert (P.n, P.n_samples) == (ref["n"], ref["n_samples"])
+    cc = CoreCase([(P.n, P.n_samples, ref["radius"], "fft")], torch.float32, seed=ref["seed"])
+    field, steps = cc.batch.core_stage(cc.s_all(), gamma=ref["gamma"], tol=ref["tol"], max_iter=10000)
     a = cc.fields(field)[0]
     it = cc.items[0]
     b = O.core_rhs(it["s"], it["r"], it["v"], it["n"])
-    true = np.linalg.norm(O.core_normal(a, it["r"], it["v"], 1e-3) - b) / np.linalg.norm(b)
-    assert true <= 1.05e-3, (true, steps)
-    assert rel_l2(a, it["G"]) <= 0.1, rel_l2(a, it["G"])
+    true = np.linalg.norm(O.core_normal(a, it["r"], it["v"], ref["gamma"]) - b) / np.linalg.norm(b)
+    assert true <= ref["tol"] * 1.05, (true, steps)
+    k = ref["steps"]
+    assert k - 1 <= steps[0] <= 2 * k + 2, (steps, k)
+    assert rel_l2(a, it["G"]) <= 1.1 * ref["field_error"], (rel_l2(a, it["G"]), ref["field_error"])
 
 
 def test_two_stage_pipeline_reconstructs_like_the_oracle():
     """Signals -> Core Stage field -> trace image -> ZeroShot-PnP, on 48^2
     and 64^2 problems with the full kernel, float64: the library's
     reconstruction is as close to the phantom as the oracle's pipeline (within
-    10 % of its relative error), and the intermediate field matches the
-    oracle's to 1e-10."""
+    10 % of its relative error), and the intermediate field solves its
+    equations like the oracle's (stop rule, steps, accuracy)."""
     shapes = [(48, 2400, 47, "fft"), (64, 3400, 63, "fft")]
     cc = CoreCase(shapes, torch.float64, seed=9)
     field, steps = cc.batch.core_stage(cc.s_all(), gamma=1e-3, tol=1e-3, max_iter=10000)
@@ -123,7 +164,7 @@ def test_two_stage_pipeline_reconstructs_like_the_oracle():
     rho = [x.double().cpu().numpy() for x in cc.batch.c_views(rho)]
     for i, it in enumerate(cc.items):
         a, k = O.core_stage(it["s"], it["r"], it["v"], it["n"], 1e-3)
-        assert steps[i] == k and rel_l2(got_f[i], a) <= 1e-10, i
+        check_solve(it, got_f[i], steps[i], k, a, torch.float64, 1e-3, 1e-3)
         ref, _ = O.zeroshot_pnp(a[0] + a[2], it["h"], it["R"], 9, 1e-5)
         err = lambda x: np.linalg.norm(x - it["c"]) / np.linalg.norm(it["c"])
         assert err(rho[i]) <= 1.1 * err(ref), (i, err(rho[i]), err(ref))

@@ -81,18 +81,30 @@ def test_x_channel_iteration_and_trajectory_vjp():
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_x_channel_core_stage(dtype):
-    """Cosine interpolation, gamma = 1e-3: the field matches the oracle's with
-    the same steps; the yy channel, which no x-channel data reaches, is 0, so
-    the trace image is A_xx."""
+    """Cosine interpolation, gamma = 1e-3: twelve steps match the oracle's
+    element by element; solved to tolerance the field meets the stop rule in
+    the true residual with the oracle's steps (float64 +-1; float32 within a
+    window); the yy channel, which no x-channel data reaches, is 0, so the
+    trace image is A_xx."""
     batch, items = _batch([(16, 400, 15, "fft"), (24, 900, 5, "direct")], dtype, channels="x", interp="cosine")
     s_list = [rounded(S.add_noise(it["model"].forward(it["c"]), 30.0, seed=i), dtype) for i, it in enumerate(items)]
-    field, steps = batch.core_stage(torch.cat([dev(x, dtype).reshape(-1) for x in s_list]), gamma=1e-3, tol=1e-3)
+    s_all = torch.cat([dev(x, dtype).reshape(-1) for x in s_list])
+    field, _ = batch.core_stage(s_all, gamma=1e-3, tol=0.0, max_iter=12)
+    got = _host(batch.field_views(field))
+    for i, it in enumerate(items):
+        ref, _ = O.core_stage(s_list[i], it["r"], it["v"], it["n"], 1e-3, tol=0.0, max_iter=12, channels="x")
+        assert rel_l2(got[i], ref) <= (1e-10 if dtype == torch.float64 else 1e-5), i
+    field, steps = batch.core_stage(s_all, gamma=1e-3, tol=1e-3)
     got = _host(batch.field_views(field))
     u = _host(batch.c_views(batch.field_trace(field)))
+    slack = 1e-6 if dtype == torch.float64 else 0.05
     for i, it in enumerate(items):
-        ref, k = O.core_stage(s_list[i], it["r"], it["v"], it["n"], 1e-3, channels="x")
-        assert steps[i] == k
-        assert rel_l2(got[i], ref) <= (1e-10 if dtype == torch.float64 else 1e-5)
+        _, k = O.core_stage(s_list[i], it["r"], it["v"], it["n"], 1e-3, channels="x")
+        b = O.core_rhs(s_list[i], it["r"], it["v"], it["n"], channels="x")
+        res = O.core_normal(got[i], it["r"], it["v"], 1e-3, channels="x") - b
+        assert np.linalg.norm(res) <= 1e-3 * (1 + slack) * np.linalg.norm(b), i
+        ok = abs(steps[i] - k) <= 1 if dtype == torch.float64 else k - 1 <= steps[i] <= 2 * k + 2
+        assert ok, (i, steps[i], k)
         assert not np.any(got[i][2]) and np.array_equal(u[i], got[i][0])
 
 
@@ -144,7 +156,8 @@ def test_experiment2_pipeline_reconstructs_like_the_oracle():
     sample in 100 kept, the anisotropic gradient, the x receive channel alone,
     a two-bar phantom; Core Stage (cosine, gamma = 1e-3), A_xx, ZeroShot-PnP
     with K_xx and the paper's nu0 = 4e-2 for this experiment.  float64: the
-    field matches the oracle's to 1e-10 and the reconstruction is as close to
+    field solves its equations like the oracle's (stop rule in the true
+    residual, steps +-1) and the reconstruction is as close to
     the phantom as the oracle pipeline's."""
     n, R = 48, 47
     full = S.experiment2(2_000_000)
@@ -160,7 +173,10 @@ def test_experiment2_pipeline_reconstructs_like_the_oracle():
     field, steps = batch.core_stage(dev(s, torch.float64).reshape(-1), gamma=1e-3, tol=1e-3)
     rho, info = batch.pnp(batch.field_trace(field), n_it=9, nu0=4e-2, tol=1e-3)
     a, k = O.core_stage(s, r, v, n, 1e-3, channels="x")
-    assert steps[0] == k and rel_l2(batch.field_views(field)[0].cpu().numpy(), a) <= 1e-10
+    got_f = batch.field_views(field)[0].cpu().numpy()
+    b = O.core_rhs(s, r, v, n, channels="x")
+    assert abs(steps[0] - k) <= 1, (steps, k)
+    assert np.linalg.norm(O.core_normal(got_f, r, v, 1e-3, channels="x") - b) <= 1e-3 * (1 + 1e-6) * np.linalg.norm(b)
     ref, _ = O.zeroshot_pnp(a[0], h, R, 9, 4e-2, which="xx", grad=GRAD)
     err = lambda x: np.linalg.norm(x - c) / np.linalg.norm(c)
     got = rho.cpu().numpy().reshape(n, n)
