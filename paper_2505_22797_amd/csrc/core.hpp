@@ -9,18 +9,34 @@
 // neighbours, spacing delta = 2/N), L the number of samples.
 //
 // Fields are [3][N][N] per problem at element offset 3 o_c of the caller's
-// concatenated buffer; signals in cell order at element offset o_s.  One step
-// is five launches: the gather I p (per base-cell row), the Laplacian of p,
-// the transpose sampling with the epilogue q = (1/L) I^T I p + gamma delta^2 W
-// Delta (Delta p) and per-row partial sums of <p, q>, then the CG updates of
-// the Deconvolution Stage with three components per cell.
+// concatenated buffer; signals in cell order at element offset o_s.
 //
-// Precision: the sampling runs in the plan's dtype T on p rounded to T; the
-// regulariser, q and the CG vectors are float64.  The biharmonic stencil
-// cancels on smooth fields (its coefficients sum to 0 and reach 20 gamma /
-// delta^2 per cell), so in float32 its rounding error would be a perturbation
-// of the operator near eps_32 times its largest eigenvalue, which is
-// comparable to the smallest eigenvalues that decide the step count.
+// One CG step is two launches over the grid rows of every problem:
+//   A (k_core_dir_gather): the stop rule on |r|^2, then the new search
+//     direction p = r + beta p_prev for grid rows j-1 .. j+1 (row j stored),
+//     l = Delta p for row j (unscaled), the sampling y = I p of the samples in
+//     base-cell row j, and per-row partial sums of sum_ch w_ch |l|^2 and |y|^2;
+//   B (k_core_update): alpha = |r|^2 / <p, A p> with
+//     <p, A p> = (1/L) |I p|^2 + gamma delta^2 sum_ch w_ch |Delta p|^2
+//     (A = (1/L) I^T I + gamma delta^2 W Delta^2 with Delta symmetric), the
+//     transpose sampling of y for grid row j, q = (1/L) I^T y + gamma delta^2
+//     W Delta l for that row, x += alpha p, r -= alpha q, and the row's |r|^2.
+// So q never goes to memory, and the direction update needs no pass of its
+// own.  The search direction is double-buffered (a step reads the previous
+// one while writing the next).
+//
+// Precision: the sampling runs in T on p rounded to T; the Laplacians, q, the
+// CG vectors and all sums are float64.  The biharmonic stencil cancels on
+// smooth fields, so in float32 its rounding would perturb the operator by
+// about eps_32 times its largest eigenvalue, comparable to the smallest
+// eigenvalues that decide the step count.
+//
+// Control: every problem runs its own CG.  Steps run in captured blocks; the
+// state (|r|^2 of the step's residual, steps taken, stop flag) is double-
+// buffered by step parity: launch A of step i reads slot i & 1 and its first
+// work-group writes slot (i + 1) & 1, which launch B of the same step reads.
+// Totals of partial sums are taken by every work-group that needs them in the
+// same fixed order (tree_sum), so all of them see the same value.
 #pragma once
 #include "common.hpp"
 #include "deconv.hpp"
@@ -28,33 +44,33 @@
 
 namespace mpik {
 
-constexpr int kCoreParts = 1024;       // partial sums of <p, q> per problem: one per grid row
+constexpr int kCoreParts = 1024;       // partial sums per problem: one per grid row
 
-// y = I a in cell order.  grid (base-cell rows, problems), 256 threads;
-// dynamic LDS 6 N values (rows b and b+1 of the three channels).
-template <typename T>
-__global__ void __launch_bounds__(256) k_core_gather(const Prob* __restrict__ P, const T* __restrict__ a,
-                                                     T* __restrict__ y, const char* __restrict__ plan,
-                                                     const int* __restrict__ skip) {
-    extern __shared__ __align__(16) char smem[];
-    const Prob& p = P[blockIdx.y];
-    if (skip && skip[blockIdx.y]) return;
-    const int N = p.n, nb = p.nb, b = blockIdx.x;
-    if (b >= nb) return;
-    const int* binstart = at<int>(plan, p.o_binstart);
-    const int p0 = binstart[b * nb], p1 = binstart[(b + 1) * nb];
-    if (p0 == p1) return;
-    const T* A = a + 3 * p.o_c;
-    T* g0 = reinterpret_cast<T*>(smem);
-    T* g1 = g0 + 3 * N;
-    for (int i = threadIdx.x; i < 6 * N; i += blockDim.x) {
-        const int half = i / (3 * N), rem = i % (3 * N), ch = rem / N, x = rem % N;
-        g0[i] = A[int64_t(ch) * N * N + int64_t(b + half) * N + x];
-    }
+struct CoreCg {
+    double* rr;      // [2][count] |r|^2 of the residual a step starts from
+    double* bb;      // [count] |b|^2
+    int* steps;      // [2][count] steps taken before the slot's step
+    int* done;       // [2][count] 1: stopped
+    double* part_r;  // [count][kCoreParts] per grid row: |r|^2
+    double* part_l;  // per grid row: sum_ch w_ch |lap5 p|^2
+    double* part_y;  // per base-cell row: |I p|^2 (0 for the last grid row)
+};
+
+// Fixed-order total of n partial sums, the same value in every work-group of
+// 256 threads: thread t adds parts t, t + 256, ... in turn, then a fixed
+// tree over the threads.
+__device__ __forceinline__ double tree_sum(const double* __restrict__ part, int n, double* red) {
+    double v = 0.0;
+    for (int q = threadIdx.x; q < n; q += 256) v += part[q];
+    red[threadIdx.x] = v;
     __syncthreads();
-    gather_band<T, 4>(g0, g1, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), nullptr, nullptr,
-                      y + p.o_s, nullptr, nullptr, nullptr, nullptr, p.t, nullptr, p.chan == 1, threadIdx.x,
-                      blockDim.x);
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double t = red[0];
+    __syncthreads();
+    return t;
 }
 
 // Graph Laplacian of one value of a [N][N] channel (in-grid neighbours only,
@@ -70,40 +86,14 @@ __device__ __forceinline__ T lap5(const T* __restrict__ c, int N, int j, int i) 
     return s;
 }
 
-// l = Delta a without the 1/delta^2 factor, every channel, float64.  grid
-// (ceil(3 N^2 / 256), problems), 256 threads.
-__global__ void __launch_bounds__(256) k_core_lap(const Prob* __restrict__ P, const double* __restrict__ a,
-                                                  double* __restrict__ l, const int* __restrict__ skip) {
-    const Prob& p = P[blockIdx.y];
-    if (skip && skip[blockIdx.y]) return;
-    const int N = p.n;
-    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x, nn = int64_t(N) * N;
-    if (e >= 3 * nn) return;
-    const int64_t ch = e / nn, rem = e % nn;
-    const int j = int(rem / N), i = int(rem % N);
-    const int64_t base = 3 * p.o_c + ch * nn;
-    l[base + rem] = lap5(a + base, N, j, i);
-}
-
-// Grid row j of the three channels of (1/L) I^T y (cell-order y, sums in
-// T), then, in float64,
-//   EPI 0: out = that (the right-hand side);
-//   EPI 1: out = that + gamma delta^2 W Delta l with l = Delta p (as
-//          k_core_lap left it, unscaled: the two 1/delta^2 factors and
-//          delta^2 make gamma / delta^2), and part[b][j] = the row's sum of
-//          p * out.
-// grid (max N, problems), 256 threads; dynamic LDS as the operator's
-// row-wise transpose sampling.
-template <typename T, int EPI>
-__global__ void __launch_bounds__(256) k_core_scatter(const Prob* __restrict__ P, const T* __restrict__ y,
-                                                      double* __restrict__ out, const double* __restrict__ pv,
-                                                      const double* __restrict__ l, double gamma,
-                                                      double* __restrict__ part, const char* __restrict__ plan,
-                                                      const int* __restrict__ skip) {
+// Grid row j of the three channels of (1/L) I^T y, y in cell order (sums in
+// T, the result in float64): the right-hand side.  grid (max N, problems),
+// 256 threads; dynamic LDS as the operator's row-wise transpose sampling.
+template <typename T>
+__global__ void __launch_bounds__(256) k_core_rhs(const Prob* __restrict__ P, const T* __restrict__ y,
+                                                  double* __restrict__ out, const char* __restrict__ plan) {
     extern __shared__ __align__(16) char smem[];
-    __shared__ double red[256];
     const Prob& p = P[blockIdx.y];
-    if (skip && skip[blockIdx.y]) return;
     const int N = p.n, j = blockIdx.x;
     if (j >= N) return;
     T* g = reinterpret_cast<T*>(smem);
@@ -114,33 +104,173 @@ __global__ void __launch_bounds__(256) k_core_scatter(const Prob* __restrict__ P
     const double inv_l = 1.0 / double(p.t);
     const int64_t nn = int64_t(N) * N;
     double* o = out + 3 * p.o_c;
-    if (EPI == 0) {
-        for (int i = threadIdx.x; i < 3 * N; i += blockDim.x) {
-            const int ch = i / N, x = i % N;
-            o[ch * nn + int64_t(j) * N + x] = inv_l * double(g[i]);
+    for (int i = threadIdx.x; i < 3 * N; i += blockDim.x) {
+        const int ch = i / N, x = i % N;
+        o[ch * nn + int64_t(j) * N + x] = inv_l * double(g[i]);
+    }
+}
+
+// x = 0, r = b, p_prev = 0 and part_r = the rows' |b|^2.  grid (max N,
+// problems), 256 threads.
+__global__ void __launch_bounds__(256) k_core_init(const Prob* __restrict__ P, const double* __restrict__ rhs,
+                                                   double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ p_prev, CoreCg s) {
+    __shared__ double red[256];
+    const Prob& p = P[blockIdx.y];
+    const int N = p.n, j = blockIdx.x;
+    if (j >= N) return;
+    const int64_t nn = int64_t(N) * N, o = 3 * p.o_c;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < 3 * N; i += 256) {
+        const int ch = i / N, xx = i - ch * N;
+        const int64_t off = o + ch * nn + int64_t(j) * N + xx;
+        const double b = rhs[off];
+        x[off] = 0.0;
+        r[off] = b;
+        p_prev[off] = 0.0;
+        acc += b * b;
+    }
+    reduce_to_part(acc, red, s.part_r, kCoreParts);
+}
+
+// One work-group per problem: bb = rr = |b|^2 (slot 0), no step taken, and
+// stopped at once when b = 0 or max_iter = 0.
+__global__ void __launch_bounds__(256) k_core_begin(const Prob* __restrict__ P, CoreCg s, int max_iter) {
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    const double bb = tree_sum(s.part_r + int64_t(b) * kCoreParts, P[b].n, red);
+    if (threadIdx.x == 0) {
+        s.bb[b] = bb;
+        s.rr[b] = bb;
+        s.steps[b] = 0;
+        s.done[b] = (max_iter > 0 && bb > 0.0) ? 0 : 1;
+    }
+}
+
+__host__ __device__ constexpr size_t core_dir_lds_bytes(int N, int elem) {
+    return size_t(9) * N * 8 + lds_align(size_t(6) * N * elem);
+}
+
+// Launch A of step par (see the file comment).  Stops the problem (state
+// slot 1 - par) once |r| <= tol |b| or max_iter steps were taken; otherwise
+// beta = |r|^2 / |r_prev|^2 (1 on the first step, where p_prev = 0).  grid
+// (max N, problems), 256 threads; dynamic LDS core_dir_lds_bytes: rows j-1 ..
+// j+1 of p in float64, then rows j, j+1 rounded to T for the sampling.
+template <typename T>
+__global__ void __launch_bounds__(256) k_core_dir_gather(const Prob* __restrict__ P, CoreCg s, int par,
+                                                         const double* __restrict__ r,
+                                                         const double* __restrict__ p_prev,
+                                                         double* __restrict__ p_new, double* __restrict__ l,
+                                                         T* __restrict__ y, double tol, int max_iter,
+                                                         const char* __restrict__ plan) {
+    extern __shared__ __align__(16) char smem[];
+    __shared__ double red[256];
+    const int b = blockIdx.y, cnt = gridDim.y, cur = par * cnt + b, nxt = (1 - par) * cnt + b;
+    const Prob& p = P[b];
+    const int N = p.n, j = blockIdx.x, tid = threadIdx.x;
+    if (j >= N) return;
+    const bool lead = j == 0 && tid == 0;
+    if (s.done[cur]) {
+        if (lead) {
+            s.done[nxt] = 1;
+            s.rr[nxt] = s.rr[cur];
+            s.steps[nxt] = s.steps[cur];
         }
         return;
     }
+    const double rr = tree_sum(s.part_r + int64_t(b) * kCoreParts, N, red);
+    const int taken = s.steps[cur];
+    const bool stop = taken >= max_iter || !(rr > tol * tol * s.bb[b]);
+    if (lead) {
+        s.done[nxt] = stop ? 1 : 0;
+        s.rr[nxt] = rr;
+        s.steps[nxt] = stop ? taken : taken + 1;
+    }
+    if (stop) return;
+    const double beta = rr / s.rr[cur];
+    const int64_t nn = int64_t(N) * N, o = 3 * p.o_c;
+    const int W = 3 * N;
+    double* pd = reinterpret_cast<double*>(smem);                  // [3 rows][3 ch][N]
+    T* pr = reinterpret_cast<T*>(smem + size_t(9) * N * 8);        // [2 rows][3 ch][N]
+    for (int i = tid; i < 3 * W; i += 256) {
+        const int rw = i / W, rem = i - rw * W, ch = rem / N, xx = rem - ch * N;
+        const int row = j - 1 + rw;
+        if (row >= 0 && row < N) {
+            const int64_t off = o + ch * nn + int64_t(row) * N + xx;
+            const double v = r[off] + beta * p_prev[off];
+            pd[i] = v;
+            if (rw == 1) p_new[off] = v;
+            if (rw >= 1) pr[i - W] = T(v);
+        }
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int i = tid; i < W; i += 256) {
+        const int ch = i / N, xx = i - ch * N;
+        const double* m = pd + W + ch * N;                          // row j of channel ch
+        const double v = m[xx];
+        double sl = 0.0;                                             // lap5's order
+        if (j > 0) sl += m[xx - W] - v;
+        if (j + 1 < N) sl += m[xx + W] - v;
+        if (xx > 0) sl += m[xx - 1] - v;
+        if (xx + 1 < N) sl += m[xx + 1] - v;
+        l[o + ch * nn + int64_t(j) * N + xx] = sl;
+        acc += (ch == 1 ? 2.0 : 1.0) * sl * sl;
+    }
+    reduce_to_part(acc, red, s.part_l, kCoreParts);
+    acc = 0.0;
+    if (j < p.nb) {
+        const int nb = p.nb;
+        const int* binstart = at<int>(plan, p.o_binstart);
+        const int p0 = binstart[j * nb], p1 = binstart[(j + 1) * nb];
+        T* yo = y + p.o_s;
+        gather_band<T, 4>(pr, pr + W, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), nullptr,
+                          nullptr, yo, nullptr, nullptr, nullptr, nullptr, p.t, nullptr, p.chan == 1, tid, 256);
+        for (int e = p0 + tid; e < p1; e += 256) {          // the positions this thread wrote
+            const double a0 = double(yo[2 * e]), a1 = double(yo[2 * e + 1]);
+            acc += a0 * a0 + a1 * a1;
+        }
+    }
+    reduce_to_part(acc, red, s.part_y, kCoreParts);
+}
+
+// Launch B of step par (see the file comment).  grid (max N, problems), 256
+// threads; dynamic LDS as the operator's row-wise transpose sampling.
+template <typename T>
+__global__ void __launch_bounds__(256) k_core_update(const Prob* __restrict__ P, CoreCg s, int par,
+                                                     const T* __restrict__ y, const double* __restrict__ l,
+                                                     const double* __restrict__ p_new, double* __restrict__ x,
+                                                     double* __restrict__ r, double gamma,
+                                                     const char* __restrict__ plan) {
+    extern __shared__ __align__(16) char smem[];
+    __shared__ double red[256];
+    const int b = blockIdx.y, cnt = gridDim.y, nxt = (1 - par) * cnt + b;
+    const Prob& p = P[b];
+    const int N = p.n, j = blockIdx.x, tid = threadIdx.x;
+    if (j >= N || s.done[nxt]) return;
     const double d2 = 4.0 / (double(N) * N);                   // delta^2
     const double reg = gamma / d2;                               // gamma delta^2 / delta^4
-    const double* pp = pv + 3 * p.o_c;
-    const double* ll = l + 3 * p.o_c;
+    const double inv_l = 1.0 / double(p.t);
+    const double yy = tree_sum(s.part_y + int64_t(b) * kCoreParts, N, red);
+    const double ll = tree_sum(s.part_l + int64_t(b) * kCoreParts, N, red);
+    const double alpha = s.rr[nxt] / (inv_l * yy + reg * ll);
+    T* g = reinterpret_cast<T*>(smem);
+    char* sc = smem + lds_align(size_t(3) * N * sizeof(T));
+    scatter_row<T, true, 256>(g, scatter_lds<T>(sc, N, 256), N, j, at<int>(plan, p.o_binstart),
+                              at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
+                              reinterpret_cast<const vec2<T>*>(y + p.o_s), nullptr, tid, p.chan == 1);
+    const int64_t nn = int64_t(N) * N, o = 3 * p.o_c;
     double acc = 0.0;
-    for (int i = threadIdx.x; i < 3 * N; i += blockDim.x) {
-        const int ch = i / N, x = i % N;
-        const double w = ch == 1 ? 2.0 : 1.0;
-        const int64_t off = ch * nn + int64_t(j) * N + x;
-        const double q = inv_l * double(g[i]) + reg * w * lap5(ll + ch * nn, N, j, x);
-        o[off] = q;
-        acc += pp[off] * q;
+    for (int i = tid; i < 3 * N; i += 256) {
+        const int ch = i / N, xx = i - ch * N;
+        const int64_t off = o + ch * nn + int64_t(j) * N + xx;
+        const double q = inv_l * double(g[i]) + reg * (ch == 1 ? 2.0 : 1.0) * lap5(l + o + ch * nn, N, j, xx);
+        x[off] += alpha * p_new[off];
+        const double re = r[off] - alpha * q;
+        r[off] = re;
+        acc += re * re;
     }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[int64_t(blockIdx.y) * kCoreParts + j] = red[0];
+    reduce_to_part(acc, red, s.part_r, kCoreParts);
 }
 
 // y[o_s + 2i..] = s[o_s + 2k(i)..]: the caller's time-ordered signal in cell

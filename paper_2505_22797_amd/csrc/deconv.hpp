@@ -8,7 +8,7 @@
 // operator's dtype T; the operator is applied to pt, p rounded to T (written
 // next to p), and returns q in T.  In float32 this keeps the recursively
 // updated residual close to the true one over thousands of steps (with
-// float32 vectors it drifts above the tolerance at 256^2 in the Core Stage).
+// float32 vectors it drifts above the tolerance in long solves).
 //
 // Every problem of a batch runs its own CG; the scalars live in device memory
 // and every kernel of a step skips problems whose flag done[b] is set, so the
@@ -45,11 +45,8 @@ __device__ __forceinline__ double sum_parts(const double* __restrict__ part, int
 }
 
 // Partial sums of <p, q> per problem (`stride` slots): the FFT row stage
-// fills one per row pair, the direct path's k_cg_pq the first kDotParts, the
-// Core Stage's transpose sampling one per grid row (pq_kind 1).
-__device__ __forceinline__ int pq_parts(const Prob& p, int pq_kind) {
-    return pq_kind == 1 ? p.n : (p.mode == 1 ? (p.n + 1) / 2 : kDotParts);
-}
+// fills one per row pair, the direct path's k_cg_pq the first kDotParts.
+__device__ __forceinline__ int pq_parts(const Prob& p) { return p.mode == 1 ? (p.n + 1) / 2 : kDotParts; }
 
 // The work-group's slice [lo, hi) of a problem with m elements.
 __device__ __forceinline__ void slice_of(int64_t m, int64_t& lo, int64_t& hi) {
@@ -86,8 +83,8 @@ __device__ __forceinline__ double broadcast0(double v, double* slot) {
 // grid (kDotParts, problems), 256 threads.  b = cu + nu rho2 in float64
 // (rho2 may be null: b = cu); x = 0, r = p = b, pt = b rounded to T;
 // part = slices of |b|^2.
-template <typename T, typename U = T>
-__global__ void __launch_bounds__(256) k_cg_init(const Prob* __restrict__ P, int comps, const U* __restrict__ cu,
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_init(const Prob* __restrict__ P, int comps, const T* __restrict__ cu,
                                                  const T* __restrict__ rho2, CgState s, double* __restrict__ x,
                                                  double* __restrict__ r, double* __restrict__ pv, T* __restrict__ pt,
                                                  double* __restrict__ part) {
@@ -156,10 +153,10 @@ __global__ void __launch_bounds__(256) k_cg_pq(const Prob* __restrict__ P, CgSta
 
 // alpha = rr / <p, q>; x += alpha p; r -= alpha q (float64); part_rr =
 // slices of |r|^2.
-template <typename T, typename Q = T>
+template <typename T>
 __global__ void __launch_bounds__(256) k_cg_update(const Prob* __restrict__ P, CgState s, int par, int comps,
-                                                   int pq_kind, int pq_stride, const double* __restrict__ pv,
-                                                   const Q* __restrict__ q, double* __restrict__ x,
+                                                   int pq_stride, const double* __restrict__ pv,
+                                                   const T* __restrict__ q, double* __restrict__ x,
                                                    double* __restrict__ r, const double* __restrict__ part_pq,
                                                    double* __restrict__ part_rr) {
     __shared__ double red[256];
@@ -172,7 +169,7 @@ __global__ void __launch_bounds__(256) k_cg_update(const Prob* __restrict__ P, C
     slice_of(m, lo, hi);
     const double alpha = broadcast0(
         threadIdx.x == 0
-            ? s.rr[par * cnt + b] / sum_parts(part_pq + int64_t(b) * pq_stride, pq_parts(p, pq_kind))
+            ? s.rr[par * cnt + b] / sum_parts(part_pq + int64_t(b) * pq_stride, pq_parts(p))
             : 0.0,
         &slot);
     double acc = 0.0;

@@ -1295,7 +1295,7 @@ void cg_step(const mpi_plan* pl, int par, double tol, int max_iter, char* work, 
         }
         k_cg_pq<T><<<el, 256, 0, st>>>(P, s, par, pv, q, pa);
     }
-    k_cg_update<T><<<el, 256, 0, st>>>(P, s, par, 1, 0, kCgRowParts, p64, q, x, r, pa, pb);
+    k_cg_update<T><<<el, 256, 0, st>>>(P, s, par, 1, kCgRowParts, p64, q, x, r, pa, pb);
     k_cg_dir<T><<<el, 256, 0, st>>>(P, s, par, 1, r, p64, pv, pb, tol, max_iter);
 }
 
@@ -1473,101 +1473,94 @@ int pnp_impl(mpi_plan* pl, const T* u, T* rho, const mpi_pnp_params* pp, int32_t
 // l (three channels per cell), the signal-shaped y = I p in cell order, the
 // solver state and partial sums.
 struct CoreLayout {
-    size_t r = 0, p = 0, x = 0, pt = 0, q = 0, l = 0, y = 0;
-    size_t rr = 0, bb = 0, nu = 0, iters = 0, done = 0, part_a = 0, part_b = 0;
+    size_t r = 0, x = 0, p0 = 0, p1 = 0, l = 0, rhs = 0, y = 0;
+    size_t rr = 0, bb = 0, steps = 0, done = 0, part_r = 0, part_l = 0, part_y = 0;
     size_t bytes = 0;
 };
 
 CoreLayout core_layout(const mpi_plan* pl) {
     CoreLayout L;
     size_t off = 0;
-    const size_t v = size_t(3) * pl->L.c_elems * pl->L.elem, v64 = size_t(3) * pl->L.c_elems * 8,
-                 B = size_t(pl->count);
-    L.r = take(off, v64);                    // Krylov vectors in float64
-    L.p = take(off, v64);
+    const size_t v64 = size_t(3) * pl->L.c_elems * 8, B = size_t(pl->count), parts = 8 * B * kCoreParts;
+    L.r = take(off, v64);                    // CG vectors, Laplacian and right-hand side in float64
     L.x = take(off, v64);
-    L.pt = take(off, v);                     // p rounded to the sampling's dtype
-    L.q = take(off, v64);                    // operator output and regulariser in float64
+    L.p0 = take(off, v64);                   // search directions of even / odd steps
+    L.p1 = take(off, v64);
     L.l = take(off, v64);
+    L.rhs = take(off, v64);
     L.y = take(off, size_t(pl->L.s_elems) * pl->L.elem);
     L.rr = take(off, 2 * 8 * B);
     L.bb = take(off, 8 * B);
-    L.nu = take(off, 8 * B);
-    L.iters = take(off, 4 * B);
+    L.steps = take(off, 2 * 4 * B);
     L.done = take(off, 2 * 4 * B);
-    L.part_a = take(off, 8 * B * kCoreParts);
-    L.part_b = take(off, 8 * B * kDotParts);
+    L.part_r = take(off, parts);
+    L.part_l = take(off, parts);
+    L.part_y = take(off, parts);
     L.bytes = off;
     return L;
 }
 
-size_t core_gather_smem(const mpi_plan* pl) { return size_t(6) * pl->max_n * pl->L.elem; }
+CoreCg core_state(const CoreLayout& L, char* cw) {
+    CoreCg s;
+    s.rr = reinterpret_cast<double*>(cw + L.rr);
+    s.bb = reinterpret_cast<double*>(cw + L.bb);
+    s.steps = reinterpret_cast<int*>(cw + L.steps);
+    s.done = reinterpret_cast<int*>(cw + L.done);
+    s.part_r = reinterpret_cast<double*>(cw + L.part_r);
+    s.part_l = reinterpret_cast<double*>(cw + L.part_l);
+    s.part_y = reinterpret_cast<double*>(cw + L.part_y);
+    return s;
+}
+
+size_t core_dir_smem(const mpi_plan* pl) { return core_dir_lds_bytes(pl->max_n, pl->L.elem); }
 size_t core_scatter_smem(const mpi_plan* pl) { return scatter_rows_smem(pl->max_n, pl->L.elem); }
 
-// One Core Stage CG step (parity par): y = I p (on p rounded to T), l =
-// Delta p (unscaled, float64), q = (1/L) I^T y + gamma delta^2 W Delta l with
-// the per-row <p, q>, then the x, r and p updates and the next state slot.
+// One Core Stage CG step (parity par): launch A (stop rule, search direction,
+// Laplacian, sampling and their partial sums) and launch B (transpose
+// sampling, x and r updates, |r|^2 partial sums).  Even steps write p0, odd
+// steps p1.
 template <typename T>
 void core_step(const mpi_plan* pl, int par, double gamma, double tol, int max_iter, char* cw, const CoreLayout& L,
                hipStream_t st) {
     const Prob* P = pl->dprob;
-    const char* plan = pl->plan;
     const int B = pl->count;
-    CgState s;
-    s.rr = reinterpret_cast<double*>(cw + L.rr);
-    s.bb = reinterpret_cast<double*>(cw + L.bb);
-    s.nu = reinterpret_cast<double*>(cw + L.nu);
-    s.iters = reinterpret_cast<int*>(cw + L.iters);
-    s.done = reinterpret_cast<int*>(cw + L.done);
-    const int* skip = s.done + par * B;
+    const CoreCg s = core_state(L, cw);
     double* r = reinterpret_cast<double*>(cw + L.r);
-    double* p64 = reinterpret_cast<double*>(cw + L.p);
     double* x = reinterpret_cast<double*>(cw + L.x);
-    T* pv = reinterpret_cast<T*>(cw + L.pt);
-    double* q = reinterpret_cast<double*>(cw + L.q);
+    double* p_new = reinterpret_cast<double*>(cw + (par ? L.p1 : L.p0));
+    double* p_prev = reinterpret_cast<double*>(cw + (par ? L.p0 : L.p1));
     double* l = reinterpret_cast<double*>(cw + L.l);
     T* y = reinterpret_cast<T*>(cw + L.y);
-    double* pa = reinterpret_cast<double*>(cw + L.part_a);
-    double* pb = reinterpret_cast<double*>(cw + L.part_b);
-    const dim3 el(kDotParts, B);
-    k_core_gather<T><<<dim3(pl->max_nb, B), 256, core_gather_smem(pl), st>>>(P, pv, y, plan, skip);
-    k_core_lap<<<dim3(blocks(int64_t(3) * pl->max_n * pl->max_n, 256), B), 256, 0, st>>>(P, p64, l, skip);
-    k_core_scatter<T, 1><<<dim3(pl->max_n, B), 256, core_scatter_smem(pl), st>>>(P, y, q, p64, l, gamma, pa,
-                                                                                 plan, skip);
-    k_cg_update<T, double><<<el, 256, 0, st>>>(P, s, par, 3, 1, kCoreParts, p64, q, x, r, pa, pb);
-    k_cg_dir<T><<<el, 256, 0, st>>>(P, s, par, 3, r, p64, pv, pb, tol, max_iter);
+    const dim3 grid(pl->max_n, B);
+    k_core_dir_gather<T><<<grid, 256, core_dir_smem(pl), st>>>(P, s, par, r, p_prev, p_new, l, y, tol, max_iter,
+                                                               pl->plan);
+    k_core_update<T><<<grid, 256, core_scatter_smem(pl), st>>>(P, s, par, y, l, p_new, x, r, gamma, pl->plan);
 }
 
 // The Core Stage: CG on the Euler-Lagrange equations of eq. first:step from
 // a = 0 for every problem, with the plan's samples and interpolation weights.
+// Steps run in captured blocks of kCgBlock; the host polls the stop flags
+// (slot 0) after every block.
 template <typename T>
 int core_impl(mpi_plan* pl, const T* sig, T* field, double gamma, double tol, int max_iter, char* cw,
               hipStream_t st, int32_t* iters) {
     const CoreLayout L = core_layout(pl);
     const Prob* P = pl->dprob;
     const int B = pl->count;
-    HIP_TRY(allow_smem(k_core_gather<T>, core_gather_smem(pl)));
-    HIP_TRY(allow_smem(k_core_scatter<T, 0>, core_scatter_smem(pl)));
-    HIP_TRY(allow_smem(k_core_scatter<T, 1>, core_scatter_smem(pl)));
-    CgState s;
-    s.rr = reinterpret_cast<double*>(cw + L.rr);
-    s.bb = reinterpret_cast<double*>(cw + L.bb);
-    s.nu = reinterpret_cast<double*>(cw + L.nu);
-    s.iters = reinterpret_cast<int*>(cw + L.iters);
-    s.done = reinterpret_cast<int*>(cw + L.done);
+    HIP_TRY(allow_smem(k_core_rhs<T>, core_scatter_smem(pl)));
+    HIP_TRY(allow_smem(k_core_update<T>, core_scatter_smem(pl)));
+    HIP_TRY(allow_smem(k_core_dir_gather<T>, core_dir_smem(pl)));
+    const CoreCg s = core_state(L, cw);
     double* r = reinterpret_cast<double*>(cw + L.r);
-    double* p64 = reinterpret_cast<double*>(cw + L.p);
     double* x64 = reinterpret_cast<double*>(cw + L.x);
-    T* pt = reinterpret_cast<T*>(cw + L.pt);
-    double* q = reinterpret_cast<double*>(cw + L.q);
+    double* rhs = reinterpret_cast<double*>(cw + L.rhs);
     T* y = reinterpret_cast<T*>(cw + L.y);
-    double* pb = reinterpret_cast<double*>(cw + L.part_b);
-    // right-hand side (1/L) I^T s into q, then x = 0, r = p = q
+    const dim3 grid(pl->max_n, B);
+    // right-hand side (1/L) I^T s, then x = 0, r = b, the odd direction 0
     k_core_permute<T><<<dim3(blocks(pl->max_t, 256), B), 256, 0, st>>>(P, sig, y, pl->plan);
-    k_core_scatter<T, 0><<<dim3(pl->max_n, B), 256, core_scatter_smem(pl), st>>>(P, y, q, nullptr, nullptr, 0.0,
-                                                                                 nullptr, pl->plan, nullptr);
-    k_cg_init<T, double><<<dim3(kDotParts, B), 256, 0, st>>>(P, 3, q, nullptr, s, x64, r, p64, pt, pb);
-    k_cg_begin<<<blocks(B, 256), 256, 0, st>>>(B, s, pb, tol, max_iter);
+    k_core_rhs<T><<<grid, 256, core_scatter_smem(pl), st>>>(P, y, rhs, pl->plan);
+    k_core_init<<<grid, 256, 0, st>>>(P, rhs, x64, r, reinterpret_cast<double*>(cw + L.p1), s);
+    k_core_begin<<<B, 256, 0, st>>>(P, s, max_iter);
     HIP_TRY(hipGetLastError());
     if (max_iter > 0) {
         const std::vector<double> key{key_of(cw), gamma, tol, double(max_iter)};
@@ -1579,7 +1572,7 @@ int core_impl(mpi_plan* pl, const T* sig, T* field, double gamma, double tol, in
         if (rc != MPI_OK) return rc;
     }
     k_cg_store<T><<<dim3(blocks(int64_t(3) * pl->max_n * pl->max_n, 256), B), 256, 0, st>>>(P, 3, x64, field);
-    if (iters) HIP_TRY(hipMemcpyAsync(iters, s.iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+    if (iters) HIP_TRY(hipMemcpyAsync(iters, s.steps, sizeof(int) * B, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     return MPI_OK;
 }
@@ -1961,7 +1954,7 @@ int mpi_batch_core_stage(const mpi_plan* plan, const void* s, void* field, doubl
         max_iter < 0)
         return MPI_ERR_ARG;
     if (cbytes < core_layout(plan).bytes) return MPI_ERR_WORKSPACE;
-    if (core_scatter_smem(plan) > kSmemLimit || core_gather_smem(plan) > kSmemLimit) return MPI_ERR_UNSUPPORTED;
+    if (core_scatter_smem(plan) > kSmemLimit || core_dir_smem(plan) > kSmemLimit) return MPI_ERR_UNSUPPORTED;
     if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
     mpi_plan* pl = const_cast<mpi_plan*>(plan);
     char* cw = static_cast<char*>(cwork);
