@@ -115,11 +115,10 @@ def test_core_stage_bilinear_plan_and_field_trace():
         assert np.array_equal(us[i], got[i][0] + got[i][2])
 
 
-def test_core_stage_large_grid_unfused_path():
-    """A float64 960^2 grid is too large for the fused operator kernel's LDS,
-    so its steps run as gather, Laplacian and transpose sampling: 12 steps
-    match the oracle element by element, next to a small problem in the same
-    batch."""
+def test_core_stage_large_grid():
+    """A float64 960^2 grid (LDS rows of the direction near their largest)
+    next to a small problem in the same batch: 12 steps match the oracle
+    element by element."""
     cc = CoreCase([(960, 20000, 5, "direct"), (24, 900, 5, "direct")], torch.float64, seed=7)
     field, steps = cc.batch.core_stage(cc.s_all(), gamma=1e-3, tol=0.0, max_iter=12)
     got = cc.fields(field)
