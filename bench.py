@@ -7,9 +7,14 @@ path with M = 512), float32, the ellipse-and-line phantom.  One pair is
 s = A c followed by c' = A^T s, with every input resident in device memory.
 
 `value` is the whole-job pair rate when `--batch` independent problems of that
-shape are processed per launch (one launch per kernel stage covers the whole
-batch; a step is one pair for every problem of the batch).  The same figure
-for a single problem per launch is reported under "single_problem".  Timed
+shape are processed per call: a step is one call of the library's pair entry
+(s = A c, then A^T s, for every problem of the batch), and exactly `--steps`
+steps are timed after `--warmup` untimed ones.  The library splits such a
+batch into four problem ranges on side streams, and each range's transpose
+follows its own forward with no join in between, as inside the library's
+iteration.  The same pairs as a forward call then a transpose call are
+reported under "separate_calls", the single-problem rate under
+"single_problem".  Timed
 steps are replayed from captured HIP graphs; HIP events on the launch stream
 give the times.
 
@@ -59,8 +64,14 @@ def stage_bytes(name: str, n: int, m: int, t: int, elem: int = 4) -> float:
     }[name]
 
 
+def group_for(steps):
+    """The largest graph size in (10, 8, 5, 4, 2, 1) that divides `steps`."""
+    return next(g for g in (10, 8, 5, 4, 2, 1) if steps % g == 0)
+
+
 def graph_time(fn, steps, group, warmup):
-    """ms per call of fn() over `steps` calls replayed from a graph of `group` calls."""
+    """ms per call of fn() over `steps` calls replayed from a graph of `group`
+    calls (exactly `steps` when group divides it)."""
     import torch
     for _ in range(warmup):
         fn()
@@ -183,10 +194,15 @@ def main() -> int:
     g_all = torch.empty(batch.c_offsets[-1], dtype=torch.float32, device=dev)
 
     def pairB():
+        batch.pair(c_all, s_all, g_all)
+
+    def pairB_separate():
         batch.forward(c_all, s_all)
         batch.adjoint(s_all, g_all)
 
-    msB, steps = graph_time(pairB, max(10, args.steps // B * 4), max(1, args.graph_pairs // 5), 2)
+    # the timed region: exactly --steps batch steps, after --warmup untimed ones
+    msB, steps = graph_time(pairB, args.steps, group_for(args.steps), args.warmup)
+    msB_sep, _ = graph_time(pairB_separate, args.steps, group_for(args.steps), args.warmup)
     stB = stage_times(batch, g_all, s_all, max(3, args.stage_reps // 4))
     pairs_per_s = B * 1e3 / msB
     print(f"bench: batch {B}: {msB * 1e3:.1f} us/step, {pairs_per_s:.0f} pairs/s", file=sys.stderr, flush=True)
@@ -223,6 +239,9 @@ def main() -> int:
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                      "algorithmic_bytes_per_launch": dom_bytes},
+        "separate_calls": {"value": round(B * 1e3 / msB_sep, 1), "unit": "pairs/s", "ms_per_step": round(msB_sep, 5),
+                           "note": "the same pairs as a forward call then a transpose call (a join of the "
+                                   "problem ranges between them)"},
         "single_problem": {"value": round(1e3 / ms1, 1), "unit": "pairs/s", "ms_per_pair": round(ms1, 5),
                            "hbm_fraction": round(b_alg * 1e3 / ms1 / (HBM_PEAK_GBS * 1e9), 5),
                            "stage_ms": {k: round(x, 5) for k, x in st1.items()}},
@@ -273,7 +292,7 @@ def window31_line(mpik, P, r, v, c1, B, args):
         batch.forward(c_all, s_all)
         batch.adjoint(s_all, g_all)
 
-    msB, _ = graph_time(pairB, max(10, args.steps // B * 4), max(1, args.graph_pairs // 5), 2)
+    msB, _ = graph_time(pairB, args.steps, group_for(args.steps), args.warmup)
     stB = stage_times(batch, g_all, s_all, max(3, args.stage_reps // 4))
     flop = 2 * 2 * 3 * (2 * 31 + 1) ** 2 * n * n      # multiply-adds of both convolutions per pair
     return {"radius": 31, "conv_path": "direct", "single_pairs_per_s": round(1e3 / ms1, 1),
@@ -302,10 +321,9 @@ def cosine_line(mpik, P, r, v, c1, B, args):
     g_all = torch.empty(batch.c_offsets[-1], dtype=torch.float32, device=c1.device)
 
     def pairB():
-        batch.forward(c_all, s_all)
-        batch.adjoint(s_all, g_all)
+        batch.pair(c_all, s_all, g_all)
 
-    msB, _ = graph_time(pairB, max(10, args.steps // B * 4), max(1, args.graph_pairs // 5), 2)
+    msB, _ = graph_time(pairB, args.steps, group_for(args.steps), args.warmup)
     stB = stage_times(batch, g_all, s_all, max(3, args.stage_reps // 4))
     out = {"interp": "cosine", "conv_path": plan.conv_mode, "fft_size": plan.fft_size,
            "single_pairs_per_s": round(1e3 / ms1, 1), "batch": B, "batch_pairs_per_s": round(B * 1e3 / msB, 1),
@@ -530,18 +548,19 @@ def oracle_iteration_rate(P, tau, budget_s):
 
 
 def profile_batch(mpik, P, r, v, c1, B, steps):
-    """Run for hardware counters: `steps` batched pairs (each kernel launched
-    `steps` times) and one plain device copy of 256 MiB, whose FETCH_SIZE and
-    WRITE_SIZE calibrate the counters against a known byte count."""
+    """Run for hardware counters: one batched pair, then every kernel stage
+    launched `steps` times over the whole batch (the launches whose durations
+    give the roofline), and one plain device copy of 256 MiB, whose FETCH_SIZE
+    and WRITE_SIZE calibrate the counters against a known byte count."""
     import torch
     n, t = P.n, P.n_samples
     batch = mpik.Batch([(n, P.h, P.radius, r, v, "fft")] * B, tune=False)
     c_all = c1.reshape(-1).repeat(B).contiguous()
     s_all = torch.empty(batch.s_offsets[-1], dtype=torch.float32, device=c1.device)
     g_all = torch.empty(batch.c_offsets[-1], dtype=torch.float32, device=c1.device)
-    for _ in range(max(1, min(steps, 20))):
-        batch.forward(c_all, s_all)
-        batch.adjoint(s_all, g_all)
+    batch.pair(c_all, s_all, g_all)
+    for k in range(len(batch.stages())):
+        batch.launch_stage(k, max(1, min(steps, 20)), g_all, s_all)
     src = torch.ones(64 << 20, dtype=torch.float32, device=c1.device)
     dst = torch.empty_like(src)
     dst.copy_(src)

@@ -194,6 +194,17 @@ int mpi_batch_forward(const mpi_plan* plan, const void* c_all, void* s_all,
 /* c_all = A_b^T s_b for every problem b */
 int mpi_batch_adjoint(const mpi_plan* plan, const void* s_all, void* c_all,
                       void* work, size_t work_bytes, hipStream_t stream);
+/* s_all = A_b c_b and then g_all = A_b^T s_b for every problem b in one call
+ * (the operator of eq. model and its exact transpose, the pair applied in
+ * Landweber, power and normal-equation iterations).  Same buffers and layout
+ * as mpi_batch_forward (c_all, s_all) and mpi_batch_adjoint (s_all -> g_all);
+ * g_all must not alias c_all or s_all.  Results are those of the two separate
+ * calls, bitwise.  Unlike the two calls, each problem range of a batch (the
+ * plan splits batches of 16 or more problems into ranges on its own side
+ * streams) starts its transpose as soon as its own forward is done.
+ * Enqueued on `stream`. */
+int mpi_batch_pair(const mpi_plan* plan, const void* c_all, void* s_all, void* g_all,
+                   void* work, size_t work_bytes, hipStream_t stream);
 /* c_b <- D(c_b - taus[b] A_b^T (A_b c_b - s_b)), params->n_iter times for all
  * problems at once (params->tau is ignored; taus is a host array of count). */
 int mpi_batch_iterate(const mpi_plan* plan, const void* s_all, void* c_all,

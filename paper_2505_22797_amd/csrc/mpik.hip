@@ -39,6 +39,7 @@ constexpr int64_t kMaxSamples = int64_t(1) << 26;
 constexpr int kMaxBatch = 4096;
 constexpr int kSliceChoices[3] = {4, 8, 16};
 constexpr size_t kSmemLimit = 160 * 1024;
+constexpr int kMaxSide = 8;              // side streams of a plan
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int pow2_at_least(int x) {
@@ -301,10 +302,13 @@ struct mpi_plan {
     bool col_split = true;   // column stages: three waves per column (few problems) or a wave per column
     int col_force = 0;       // 1: always split, 2: always a wave per column, 0: by batch size
     int slice_mask = 0;      // bit i: some direct problem uses kSliceChoices[i]
-    // independent parts of a batch (each FFT size group, the direct path) run
-    // on their own streams, forked from the caller's stream and joined back
-    hipStream_t side[5] = {};
-    hipEvent_t ev_fork = nullptr, ev_join[5] = {};
+    // independent parts of a batch run on their own streams, forked from the
+    // caller's stream and joined back: each FFT size group, split into
+    // `chunks` contiguous problem ranges, and the direct path (on the
+    // caller's stream)
+    hipStream_t side[kMaxSide] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kMaxSide] = {};
+    int chunks = 1;
     std::mutex fork_mu;          // one host thread at a time enqueues a fork
     // cached iteration graph
     hipGraphExec_t gexec = nullptr;
@@ -544,10 +548,11 @@ void launch_direct_conv(const mpi_plan* pl, bool fwd, const T* in, T* out, const
 // (positions) and out1 (velocities).
 template <typename T, int MODE>
 void fwd_stage(const mpi_plan* pl, int k, const T* c, GatherIO<T> io, char* work, hipStream_t st, int dh = 0,
-               int part = -1) {
+               int part = -1, int b0 = 0, int nb = -1) {
+    // b0, nb: the FFT launches cover problems b0 .. b0+nb-1 (nb < 0: all)
     const char* plan = pl->plan;
-    const Prob* P = pl->dprob;
-    const int B = pl->count;
+    const Prob* P = pl->dprob + b0;
+    const int B = nb < 0 ? pl->count : nb;
     // part: -1 everything, an FFT size index that group only, kDirectPart the direct path only
     if (k <= 2 && (!pl->any_fft || part == kDirectPart)) return;
     if (k >= 3 && (!pl->any_direct || part >= 0)) return;
@@ -594,12 +599,13 @@ void fwd_stage(const mpi_plan* pl, int k, const T* c, GatherIO<T> io, char* work
 // buffer.  EPI 0: c_out = A^T s; EPI 1: c_out = c_in - tau_b A^T r.
 template <typename T, bool SORTED, int EPI>
 void adj_stage(const mpi_plan* pl, int k, const T* s, T* c_out, const T* c_in, char* work, hipStream_t st,
-               T* z_out = nullptr, int part = -1) {
+               T* z_out = nullptr, int part = -1, int b0 = 0, int nb = -1) {
     // z_out: also the transpose with the dK/dh tables (plans built with the derivative tables)
+    // b0, nb: the FFT launches cover problems b0 .. b0+nb-1 (nb < 0: all)
     const char* plan = pl->plan;
-    const Prob* P = pl->dprob;
-    const int B = pl->count;
-    const double* taus = reinterpret_cast<const double*>(work + pl->L.w_taus);
+    const Prob* P = pl->dprob + b0;
+    const int B = nb < 0 ? pl->count : nb;
+    const double* taus = reinterpret_cast<const double*>(work + pl->L.w_taus) + b0;
     // part: -1 everything, an FFT size index that group only, kDirectPart the direct path only
     if (k <= 2 && (!pl->any_fft || part == kDirectPart)) return;
     if (k >= 3 && (!pl->any_direct || part >= 0)) return;
@@ -665,34 +671,39 @@ void launch_dot(const mpi_plan* pl, const T* a, const T* b, int space, int comp,
     k_dot_final<<<pl->count, kDotParts, 0, st>>>(part, out, accumulate);
 }
 
-// Runs body(stream, part) for each independent part of the batch: every FFT
-// size group on its own side stream (forked from st by an event and joined
-// back), the direct path on st.  A batch of one part runs body(st, -1).
+// Runs body(stream, part, b0, nb) for each independent part of the batch:
+// every FFT size group, split into pl->chunks contiguous problem ranges
+// [b0, b0 + nb), each on its own side stream (forked from st by an event and
+// joined back), and the direct path on st.  Problems of another size or path
+// in a range exit at once.  A batch of one part runs body(st, -1, 0, count).
 template <typename F>
 int by_parts(const mpi_plan* pl, hipStream_t st, F&& body) {
-    const int groups = __builtin_popcount(pl->fft_m_mask);
-    if (groups + (pl->any_direct ? 1 : 0) <= 1 || !pl->ev_fork) {
-        body(st, -1);
+    const int B = pl->count;
+    if (!pl->ev_fork) {
+        body(st, -1, 0, B);
         return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
     }
     std::lock_guard<std::mutex> lk(const_cast<mpi_plan*>(pl)->fork_mu);
     HIP_TRY(hipEventRecord(pl->ev_fork, st));
+    int k = 0;
     for (int li = 0; li < 5; ++li) {
         if (!(pl->fft_m_mask & (1 << li))) continue;
-        HIP_TRY(hipStreamWaitEvent(pl->side[li], pl->ev_fork, 0));
-        body(pl->side[li], li);
-        HIP_TRY(hipEventRecord(pl->ev_join[li], pl->side[li]));
+        for (int ch = 0; ch < pl->chunks; ++ch, ++k) {
+            const int b0 = int(int64_t(ch) * B / pl->chunks), b1 = int(int64_t(ch + 1) * B / pl->chunks);
+            HIP_TRY(hipStreamWaitEvent(pl->side[k], pl->ev_fork, 0));
+            body(pl->side[k], li, b0, b1 - b0);
+            HIP_TRY(hipEventRecord(pl->ev_join[k], pl->side[k]));
+        }
     }
-    if (pl->any_direct) body(st, kDirectPart);
-    for (int li = 0; li < 5; ++li)
-        if (pl->fft_m_mask & (1 << li)) HIP_TRY(hipStreamWaitEvent(st, pl->ev_join[li], 0));
+    if (pl->any_direct) body(st, kDirectPart, 0, B);
+    for (int i = 0; i < k; ++i) HIP_TRY(hipStreamWaitEvent(st, pl->ev_join[i], 0));
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
 template <typename T, int MODE>
 int forward_pass(const mpi_plan* pl, const T* c, GatherIO<T> io, char* work, hipStream_t st, int dh = 0) {
-    return by_parts(pl, st, [&](hipStream_t ps, int part) {
-        for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, MODE>(pl, k, c, io, work, ps, dh, part);
+    return by_parts(pl, st, [&](hipStream_t ps, int part, int b0, int nb) {
+        for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, MODE>(pl, k, c, io, work, ps, dh, part, b0, nb);
     });
 }
 
@@ -723,8 +734,22 @@ int traj_vjp_impl(const mpi_plan* pl, const T* x, const T* y, T* g_r, T* g_v, ch
 template <typename T, bool SORTED, int EPI>
 int adjoint_impl(const mpi_plan* pl, const T* s, T* c_out, const T* c_in, char* work, hipStream_t st,
                  T* z_out = nullptr) {
-    return by_parts(pl, st, [&](hipStream_t ps, int part) {
-        for (int k = 0; k < kAdjStages; ++k) adj_stage<T, SORTED, EPI>(pl, k, s, c_out, c_in, work, ps, z_out, part);
+    return by_parts(pl, st, [&](hipStream_t ps, int part, int b0, int nb) {
+        for (int k = 0; k < kAdjStages; ++k)
+            adj_stage<T, SORTED, EPI>(pl, k, s, c_out, c_in, work, ps, z_out, part, b0, nb);
+    });
+}
+
+// s = A c, then g = A^T s, per part: a problem range's transpose follows its
+// own forward on its stream, with no join in between.
+template <typename T>
+int pair_impl(const mpi_plan* pl, const T* c, T* s, T* g, char* work, hipStream_t st) {
+    GatherIO<T> io;
+    io.out0 = s;
+    return by_parts(pl, st, [&](hipStream_t ps, int part, int b0, int nb) {
+        for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 0>(pl, k, c, io, work, ps, 0, part, b0, nb);
+        for (int k = 0; k < kAdjStages; ++k)
+            adj_stage<T, false, 0>(pl, k, s, g, nullptr, work, ps, nullptr, part, b0, nb);
     });
 }
 
@@ -733,13 +758,14 @@ int adjoint_impl(const mpi_plan* pl, const T* s, T* c_out, const T* c_in, char* 
 // the step lands in c directly; with one, in work.u and then D(u) -> c.
 template <typename T>
 int iteration_impl(const mpi_plan* pl, T* c, bool denoise, int rad, char* work, hipStream_t st) {
-    const int rc = by_parts(pl, st, [&](hipStream_t ps, int part) {
-        for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 1>(pl, k, c, GatherIO<T>{}, work, ps, 0, part);
+    const int rc = by_parts(pl, st, [&](hipStream_t ps, int part, int b0, int nb) {
+        for (int k = 0; k < kFwdStages; ++k) fwd_stage<T, 1>(pl, k, c, GatherIO<T>{}, work, ps, 0, part, b0, nb);
         for (int k = 0; k < kAdjStages; ++k) {
             if (denoise)
-                adj_stage<T, true, 2>(pl, k, nullptr, reinterpret_cast<T*>(work), c, work, ps, nullptr, part);
+                adj_stage<T, true, 2>(pl, k, nullptr, reinterpret_cast<T*>(work), c, work, ps, nullptr, part, b0,
+                                      nb);
             else
-                adj_stage<T, true, 1>(pl, k, nullptr, c, c, work, ps, nullptr, part);
+                adj_stage<T, true, 1>(pl, k, nullptr, c, c, work, ps, nullptr, part, b0, nb);
         }
     });
     if (rc != MPI_OK) return rc;
@@ -913,26 +939,33 @@ int build_batch(const mpi_problem* probs, mpi_plan* pl, void* work, size_t work_
 }
 
 void release_streams(mpi_plan* pl) {
-    for (int li = 0; li < 5; ++li) {
-        if (pl->side[li]) (void)hipStreamDestroy(pl->side[li]);
-        if (pl->ev_join[li]) (void)hipEventDestroy(pl->ev_join[li]);
-        pl->side[li] = nullptr;
-        pl->ev_join[li] = nullptr;
+    for (int i = 0; i < kMaxSide; ++i) {
+        if (pl->side[i]) (void)hipStreamDestroy(pl->side[i]);
+        if (pl->ev_join[i]) (void)hipEventDestroy(pl->ev_join[i]);
+        pl->side[i] = nullptr;
+        pl->ev_join[i] = nullptr;
     }
     if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
     pl->ev_fork = nullptr;
+    pl->chunks = 1;
 }
 
 // Side streams (default priority) and fork/join events for batches with more
-// than one independent part.
+// than one independent part.  A batch of at least 16 problems with one or two
+// FFT sizes splits each size group into 4 or 2 problem ranges: kernels of
+// different ranges overlap, filling each other's ramp-up and drain between
+// dependent stages.
 int create_streams(mpi_plan* pl) {
-    if (__builtin_popcount(pl->fft_m_mask) + (pl->any_direct ? 1 : 0) <= 1) return MPI_OK;
-    bool ok = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) == hipSuccess;
-    for (int li = 0; li < 5 && ok; ++li) {
-        if (!(pl->fft_m_mask & (1 << li))) continue;
-        ok = hipStreamCreateWithFlags(&pl->side[li], hipStreamNonBlocking) == hipSuccess &&
-             hipEventCreateWithFlags(&pl->ev_join[li], hipEventDisableTiming) == hipSuccess;
+    const int groups = __builtin_popcount(pl->fft_m_mask);
+    pl->chunks = (pl->count >= 16 && groups == 1) ? 4 : (pl->count >= 16 && groups == 2) ? 2 : 1;
+    if (groups * pl->chunks + (pl->any_direct ? 1 : 0) <= 1) {
+        pl->chunks = 1;
+        return MPI_OK;
     }
+    bool ok = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < groups * pl->chunks && ok; ++i)
+        ok = hipStreamCreateWithFlags(&pl->side[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&pl->ev_join[i], hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         release_streams(pl);
         return MPI_ERR_HIP;
@@ -1675,6 +1708,21 @@ int mpi_batch_forward(const mpi_plan* plan, const void* c, void* s, void* work, 
     return plan->dtype == MPI_F64
                ? forward_impl<double>(plan, static_cast<const double*>(c), static_cast<double*>(s), w, stream)
                : forward_impl<float>(plan, static_cast<const float*>(c), static_cast<float*>(s), w, stream);
+}
+
+int mpi_batch_pair(const mpi_plan* plan, const void* c, void* s, void* g, void* work, size_t work_bytes,
+                   hipStream_t stream) {
+    int rc = check_call(plan, c, s, work, work_bytes);
+    if (rc != MPI_OK) return rc;
+    if (!g || misaligned(g, plan->L.elem) || misaligned(s, 2 * plan->L.elem)) return MPI_ERR_ARG;
+    if (g == c || g == s) return MPI_ERR_ARG;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    char* w = static_cast<char*>(work);
+    return plan->dtype == MPI_F64
+               ? pair_impl<double>(plan, static_cast<const double*>(c), static_cast<double*>(s),
+                                   static_cast<double*>(g), w, stream)
+               : pair_impl<float>(plan, static_cast<const float*>(c), static_cast<float*>(s), static_cast<float*>(g),
+                                  w, stream);
 }
 
 int mpi_batch_adjoint(const mpi_plan* plan, const void* s, void* c, void* work, size_t work_bytes,

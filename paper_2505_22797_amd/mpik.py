@@ -23,7 +23,7 @@ CHANNELS = {"xy": 0, "x": 1}
 
 EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
            "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
-           "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_iterate",
+           "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_pair", "mpi_batch_iterate",
            "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
            "mpi_batch_dot", "mpi_batch_unrolled_vjp_bytes", "mpi_batch_unrolled_vjp",
            "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
@@ -85,6 +85,7 @@ def lib() -> ctypes.CDLL:
         L.mpi_batch_info.argtypes = [vp, ctypes.c_int, i32p, i32p, i32p, i32p]
         L.mpi_batch_forward.argtypes = [vp, vp, vp, vp, sz, vp]
         L.mpi_batch_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.mpi_batch_pair.argtypes = [vp, vp, vp, vp, vp, sz, vp]
         L.mpi_batch_iterate.argtypes = [vp, vp, vp, ctypes.POINTER(IterParams), ctypes.POINTER(ctypes.c_double),
                                         vp, sz, vp]
         L.mpi_batch_forward_dh.argtypes = [vp, vp, vp, vp, sz, vp]
@@ -119,7 +120,7 @@ def lib() -> ctypes.CDLL:
         L.mpi_abi_version.argtypes = []
         for name in ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
                      "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
-                     "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_iterate",
+                     "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_pair", "mpi_batch_iterate",
                      "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
                      "mpi_batch_dot", "mpi_batch_unrolled_vjp_bytes", "mpi_batch_unrolled_vjp",
                      "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_launch",
@@ -229,6 +230,19 @@ class Plan:
         _check(lib().mpi_adjoint(self._h, s.data_ptr(), c.data_ptr(), self.work.data_ptr(), self.work.numel(),
                                  _stream(stream)), "mpi_adjoint")
         return c
+
+    def pair(self, c: torch.Tensor, s: torch.Tensor | None = None, g: torch.Tensor | None = None, stream=None):
+        """s = A c and g = A^T s in one call (mpi_batch_pair on this one-problem plan)."""
+        self._vec(c, (self.n, self.n), "c")
+        if s is None:
+            s = torch.empty((self.n_samples, 2), dtype=self.dtype, device=self.device)
+        if g is None:
+            g = torch.empty((self.n, self.n), dtype=self.dtype, device=self.device)
+        self._vec(s, (self.n_samples, 2), "s")
+        self._vec(g, (self.n, self.n), "g")
+        _check(lib().mpi_batch_pair(self._h, c.data_ptr(), s.data_ptr(), g.data_ptr(), self.work.data_ptr(),
+                                    self.work.numel(), _stream(stream)), "mpi_batch_pair")
+        return s, g
 
     def iterate(self, s: torch.Tensor, c: torch.Tensor, n_iter: int, tau: float,
                 denoise_sigma_px: float = 0.0, denoise_radius: int = 2, use_graph: bool = True,
@@ -428,6 +442,19 @@ class Batch:
         _check(lib().mpi_batch_adjoint(self._h, s_all.data_ptr(), c_all.data_ptr(), self.work.data_ptr(),
                                        self.work.numel(), _stream(stream)), "mpi_batch_adjoint")
         return c_all
+
+    def pair(self, c_all, s_all=None, g_all=None, stream=None):
+        """s_all = A c_all and g_all = A^T s_all in one call (mpi_batch_pair)."""
+        self._flat(c_all, self.c_offsets[-1], "c_all")
+        if s_all is None:
+            s_all = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
+        if g_all is None:
+            g_all = torch.empty(self.c_offsets[-1], dtype=self.dtype, device=self.device)
+        self._flat(s_all, self.s_offsets[-1], "s_all")
+        self._flat(g_all, self.c_offsets[-1], "g_all")
+        _check(lib().mpi_batch_pair(self._h, c_all.data_ptr(), s_all.data_ptr(), g_all.data_ptr(),
+                                    self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_batch_pair")
+        return s_all, g_all
 
     def iterate(self, s_all, c_all, n_iter, taus, denoise_sigma_px=0.0, denoise_radius=2, use_graph=True,
                 stream=None):

@@ -153,3 +153,71 @@ def test_uneven_sizes_iterate_matches_oracle(columns):
     for b, sp in enumerate(specs):
         ref = O.iterate(models[b], s_list[b], np.zeros((sp["n"], sp["n"])), taus[b], 6)
         assert rel_l2(batch.c_views(c_all)[b].double().cpu().numpy(), ref) <= 1e-4, b
+
+
+def _chunk_specs(shapes, seed):
+    specs = []
+    for i, (n, R, t, mode) in enumerate(shapes):
+        tr = S.lissajous(t, ax=0.85 - 0.01 * (i % 5), ay=0.85)
+        specs.append(dict(n=n, h=S.h_fwhm2(n) * (0.9 + 0.01 * i), R=R, r=rounded(tr.r, torch.float32),
+                          v=rounded(tr.v, torch.float32), c=rounded(S.blobs(n, seed + i), torch.float32), mode=mode))
+    return specs
+
+
+CHUNKED = {
+    # 17 problems of one FFT size: each launch sequence splits into four problem ranges on side streams
+    "one_size": [(24 + (i % 3), 5 + i % 4, 1500 + 100 * i, "fft") for i in range(17)],
+    # 18 problems, two FFT sizes and two direct problems: two ranges per size, the direct path beside them
+    "two_sizes": [(24, 7, 2000, "fft"), (48, 31, 5000, "fft")] * 8 + [(20, 4, 1200, "direct"), (28, 6, 1800, "direct")],
+}
+
+
+@pytest.mark.parametrize("kind", sorted(CHUNKED))
+def test_chunked_batch_equals_single_plans(kind):
+    """Batches of at least 16 problems run each FFT size group as several
+    problem ranges on side streams; every problem is still bitwise the
+    single-plan result (column kernels in the single-plan shape), and the
+    pair call bitwise the forward and transpose calls."""
+    specs = _chunk_specs(CHUNKED[kind], 300)
+    batch = _build(specs, columns="split")
+    c_all = _c_all(batch, specs)
+    s_all = batch.forward(c_all)
+    rng = np.random.default_rng(5)
+    y_all = dev(rounded(rng.standard_normal(batch.s_offsets[-1]), torch.float32), torch.float32)
+    g_all = batch.adjoint(y_all)
+    # the pair call gives the two separate calls' results, bitwise
+    s_p, g_p = batch.pair(c_all)
+    g_sep = batch.adjoint(s_all)
+    torch.cuda.synchronize()
+    assert torch.equal(s_p, s_all) and torch.equal(g_p, g_sep)
+    for b, sp in enumerate(specs):
+        plan = mpik.Plan(sp["n"], sp["h"], sp["R"], dev(sp["r"], torch.float32), dev(sp["v"], torch.float32),
+                         conv_mode=sp["mode"])
+        s1 = plan.forward(dev(sp["c"], torch.float32))
+        g1 = plan.adjoint(batch.s_views(y_all)[b].contiguous())
+        s2, g2 = plan.pair(dev(sp["c"], torch.float32))
+        torch.cuda.synchronize()
+        assert torch.equal(batch.s_views(s_all)[b], s1), b
+        assert torch.equal(batch.c_views(g_all)[b], g1), b
+        assert torch.equal(s2, s1) and torch.equal(g2, plan.adjoint(s1)), b
+
+
+@pytest.mark.parametrize("kind", sorted(CHUNKED))
+def test_chunked_batch_iterate_matches_oracle(kind):
+    """The per-problem step tau_b follows its problem into its range: a
+    different tau per problem, 6 iterations, each against the oracle."""
+    specs = _chunk_specs(CHUNKED[kind], 400)
+    batch = _build(specs)
+    taus, s_list, models = [], [], []
+    for i, sp in enumerate(specs):
+        M = O.Model(sp["n"], sp["h"], sp["R"], sp["r"], sp["v"])
+        models.append(M)
+        s_list.append(rounded(M.forward(sp["c"]), torch.float32))
+        taus.append((0.5 + 0.02 * i) / O.power_lambda_max(M, iters=20))
+    s_all = torch.cat([dev(s, torch.float32).reshape(-1) for s in s_list])
+    c_all = torch.zeros(batch.c_offsets[-1], dtype=torch.float32, device="cuda")
+    batch.iterate(s_all, c_all, 6, taus)
+    torch.cuda.synchronize()
+    for b, sp in enumerate(specs):
+        ref = O.iterate(models[b], s_list[b], np.zeros((sp["n"], sp["n"])), taus[b], 6)
+        assert rel_l2(batch.c_views(c_all)[b].double().cpu().numpy(), ref) <= 1e-4, b
