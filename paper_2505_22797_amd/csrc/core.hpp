@@ -73,6 +73,25 @@ __device__ __forceinline__ double tree_sum(const double* __restrict__ part, int 
     return t;
 }
 
+// The fixed tree of tree_sum over two values per thread at once (red holds
+// 512 entries); every thread gets both totals.
+__device__ __forceinline__ void tree_sum2(double& a, double& b, double* red) {
+    const int t = threadIdx.x;
+    red[t] = a;
+    red[256 + t] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            red[t] += red[t + w];
+            red[256 + t] += red[256 + t + w];
+        }
+        __syncthreads();
+    }
+    a = red[0];
+    b = red[256];
+    __syncthreads();
+}
+
 // Graph Laplacian of one value of a [N][N] channel (in-grid neighbours only,
 // without the 1/delta^2 factor).
 template <typename T>
@@ -147,15 +166,23 @@ __global__ void __launch_bounds__(256) k_core_begin(const Prob* __restrict__ P, 
     }
 }
 
+// Launch A's dynamic LDS: rows j-1 .. j+1 of p in float64 (at least 512
+// doubles: the region also holds the reductions' scratch while the rows are
+// not live), then rows j, j+1 rounded to T.
+__host__ __device__ constexpr size_t core_dir_rows_bytes(int N) {
+    return size_t(9) * N * 8 > 4096 ? size_t(9) * N * 8 : 4096;
+}
 __host__ __device__ constexpr size_t core_dir_lds_bytes(int N, int elem) {
-    return size_t(9) * N * 8 + lds_align(size_t(6) * N * elem);
+    return core_dir_rows_bytes(N) + lds_align(size_t(6) * N * elem);
 }
 
 // Launch A of step par (see the file comment).  Stops the problem (state
 // slot 1 - par) once |r| <= tol |b| or max_iter steps were taken; otherwise
 // beta = |r|^2 / |r_prev|^2 (1 on the first step, where p_prev = 0).  grid
-// (max N, problems), 256 threads; dynamic LDS core_dir_lds_bytes: rows j-1 ..
-// j+1 of p in float64, then rows j, j+1 rounded to T for the sampling.
+// (xcd_grid(max N), problems), 256 threads, grid rows dealt to the XCDs in
+// contiguous bands (the neighbouring rows a work-group reads then share an
+// L2); dynamic LDS core_dir_lds_bytes: rows j-1 .. j+1 of p in float64, then
+// rows j, j+1 rounded to T for the sampling.
 template <typename T>
 __global__ void __launch_bounds__(256) k_core_dir_gather(const Prob* __restrict__ P, CoreCg s, int par,
                                                          const double* __restrict__ r,
@@ -164,11 +191,11 @@ __global__ void __launch_bounds__(256) k_core_dir_gather(const Prob* __restrict_
                                                          T* __restrict__ y, double tol, int max_iter,
                                                          const char* __restrict__ plan) {
     extern __shared__ __align__(16) char smem[];
-    __shared__ double red[256];
+    double* red = reinterpret_cast<double*>(smem);                 // reductions, while pd is not live
     const int b = blockIdx.y, cnt = gridDim.y, cur = par * cnt + b, nxt = (1 - par) * cnt + b;
     const Prob& p = P[b];
-    const int N = p.n, j = blockIdx.x, tid = threadIdx.x;
-    if (j >= N) return;
+    const int N = p.n, j = xcd_unit(blockIdx.x, N), tid = threadIdx.x;
+    if (j < 0) return;
     const bool lead = j == 0 && tid == 0;
     if (s.done[cur]) {
         if (lead) {
@@ -191,7 +218,7 @@ __global__ void __launch_bounds__(256) k_core_dir_gather(const Prob* __restrict_
     const int64_t nn = int64_t(N) * N, o = 3 * p.o_c;
     const int W = 3 * N;
     double* pd = reinterpret_cast<double*>(smem);                  // [3 rows][3 ch][N]
-    T* pr = reinterpret_cast<T*>(smem + size_t(9) * N * 8);        // [2 rows][3 ch][N]
+    T* pr = reinterpret_cast<T*>(smem + core_dir_rows_bytes(N));   // [2 rows][3 ch][N]
     for (int i = tid; i < 3 * W; i += 256) {
         const int rw = i / W, rem = i - rw * W, ch = rem / N, xx = rem - ch * N;
         const int row = j - 1 + rw;
@@ -204,7 +231,7 @@ __global__ void __launch_bounds__(256) k_core_dir_gather(const Prob* __restrict_
         }
     }
     __syncthreads();
-    double acc = 0.0;
+    double accl = 0.0, accy = 0.0;
     for (int i = tid; i < W; i += 256) {
         const int ch = i / N, xx = i - ch * N;
         const double* m = pd + W + ch * N;                          // row j of channel ch
@@ -215,27 +242,27 @@ __global__ void __launch_bounds__(256) k_core_dir_gather(const Prob* __restrict_
         if (xx > 0) sl += m[xx - 1] - v;
         if (xx + 1 < N) sl += m[xx + 1] - v;
         l[o + ch * nn + int64_t(j) * N + xx] = sl;
-        acc += (ch == 1 ? 2.0 : 1.0) * sl * sl;
+        accl += (ch == 1 ? 2.0 : 1.0) * sl * sl;
     }
-    reduce_to_part(acc, red, s.part_l, kCoreParts);
-    acc = 0.0;
     if (j < p.nb) {
         const int nb = p.nb;
         const int* binstart = at<int>(plan, p.o_binstart);
         const int p0 = binstart[j * nb], p1 = binstart[(j + 1) * nb];
-        T* yo = y + p.o_s;
-        gather_band<T, 4>(pr, pr + W, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), nullptr,
-                          nullptr, yo, nullptr, nullptr, nullptr, nullptr, p.t, nullptr, p.chan == 1, tid, 256);
-        for (int e = p0 + tid; e < p1; e += 256) {          // the positions this thread wrote
-            const double a0 = double(yo[2 * e]), a1 = double(yo[2 * e + 1]);
-            acc += a0 * a0 + a1 * a1;
-        }
+        gather_band<T, 4, 4>(pr, pr + W, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), nullptr,
+                          nullptr, y + p.o_s, nullptr, nullptr, nullptr, nullptr, p.t, nullptr, p.chan == 1, tid, 256,
+                          nullptr, &accy);
     }
-    reduce_to_part(acc, red, s.part_y, kCoreParts);
+    __syncthreads();                                                 // pd is read no more
+    tree_sum2(accl, accy, red);
+    if (tid == 0) {
+        s.part_l[int64_t(b) * kCoreParts + j] = accl;
+        s.part_y[int64_t(b) * kCoreParts + j] = accy;
+    }
 }
 
-// Launch B of step par (see the file comment).  grid (max N, problems), 256
-// threads; dynamic LDS as the operator's row-wise transpose sampling.
+// Launch B of step par (see the file comment).  grid (xcd_grid(max N),
+// problems), 256 threads, rows in contiguous bands per XCD as in launch A;
+// dynamic LDS as the operator's row-wise transpose sampling.
 template <typename T>
 __global__ void __launch_bounds__(256) k_core_update(const Prob* __restrict__ P, CoreCg s, int par,
                                                      const T* __restrict__ y, const double* __restrict__ l,
@@ -243,22 +270,29 @@ __global__ void __launch_bounds__(256) k_core_update(const Prob* __restrict__ P,
                                                      double* __restrict__ r, double gamma,
                                                      const char* __restrict__ plan) {
     extern __shared__ __align__(16) char smem[];
-    __shared__ double red[256];
     const int b = blockIdx.y, cnt = gridDim.y, nxt = (1 - par) * cnt + b;
     const Prob& p = P[b];
-    const int N = p.n, j = blockIdx.x, tid = threadIdx.x;
-    if (j >= N || s.done[nxt]) return;
+    const int N = p.n, j = xcd_unit(blockIdx.x, N), tid = threadIdx.x;
+    if (j < 0 || s.done[nxt]) return;
     const double d2 = 4.0 / (double(N) * N);                   // delta^2
     const double reg = gamma / d2;                               // gamma delta^2 / delta^4
     const double inv_l = 1.0 / double(p.t);
-    const double yy = tree_sum(s.part_y + int64_t(b) * kCoreParts, N, red);
-    const double ll = tree_sum(s.part_l + int64_t(b) * kCoreParts, N, red);
-    const double alpha = s.rr[nxt] / (inv_l * yy + reg * ll);
+    // this thread's shares of the |I p|^2 and |Delta p|^2 partials, loaded
+    // before the transpose sampling and reduced after it (tree_sum's order)
+    double yy = 0.0, ll = 0.0;
+    for (int q = tid; q < N; q += 256) {
+        yy += s.part_y[int64_t(b) * kCoreParts + q];
+        ll += s.part_l[int64_t(b) * kCoreParts + q];
+    }
     T* g = reinterpret_cast<T*>(smem);
     char* sc = smem + lds_align(size_t(3) * N * sizeof(T));
     scatter_row<T, true, 256>(g, scatter_lds<T>(sc, N, 256), N, j, at<int>(plan, p.o_binstart),
                               at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
                               reinterpret_cast<const vec2<T>*>(y + p.o_s), nullptr, tid, p.chan == 1);
+    // the sampling's scratch (at least 6 * 256 values of T after g) now holds the reductions
+    double* red = reinterpret_cast<double*>(sc);
+    tree_sum2(yy, ll, red);
+    const double alpha = s.rr[nxt] / (inv_l * yy + reg * ll);
     const int64_t nn = int64_t(N) * N, o = 3 * p.o_c;
     double acc = 0.0;
     for (int i = tid; i < 3 * N; i += 256) {
@@ -270,7 +304,9 @@ __global__ void __launch_bounds__(256) k_core_update(const Prob* __restrict__ P,
         r[off] = re;
         acc += re * re;
     }
-    reduce_to_part(acc, red, s.part_r, kCoreParts);
+    double unused = 0.0;
+    tree_sum2(acc, unused, red);
+    if (tid == 0) s.part_r[int64_t(b) * kCoreParts + j] = acc;
 }
 
 // y[o_s + 2i..] = s[o_s + 2k(i)..]: the caller's time-ordered signal in cell

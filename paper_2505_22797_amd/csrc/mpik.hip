@@ -1564,7 +1564,7 @@ void core_step(const mpi_plan* pl, int par, double gamma, double tol, int max_it
     double* p_prev = reinterpret_cast<double*>(cw + (par ? L.p0 : L.p1));
     double* l = reinterpret_cast<double*>(cw + L.l);
     T* y = reinterpret_cast<T*>(cw + L.y);
-    const dim3 grid(pl->max_n, B);
+    const dim3 grid(xcd_grid(pl->max_n), B);
     k_core_dir_gather<T><<<grid, 256, core_dir_smem(pl), st>>>(P, s, par, r, p_prev, p_new, l, y, tol, max_iter,
                                                                pl->plan);
     k_core_update<T><<<grid, 256, core_scatter_smem(pl), st>>>(P, s, par, y, l, p_new, x, r, gamma, pl->plan);

@@ -79,12 +79,14 @@ __device__ __forceinline__ void gather_fetch(GatherRecs<T, U>& r, int base, int 
     }
 }
 
+// sq (MODE 4 only, may be null): the thread's running sum of |s_k|^2 in
+// float64, of the values as stored.
 template <typename T, int MODE, int U>
 __device__ __forceinline__ void gather_apply(const GatherRecs<T, U>& r, int base, int p1, int nthreads,
                                              const T* g0, const T* g1, int N, vec2<T>* __restrict__ out_sorted,
                                              T* __restrict__ out0, T* __restrict__ out1, T* __restrict__ out2,
                                              T* __restrict__ f, int64_t fstride, const vec2<T>* __restrict__ dw,
-                                             bool chx) {
+                                             bool chx, double* sq = nullptr) {
     constexpr bool GRAD = MODE == 2 || MODE == 5 || MODE == 6;
     const T inv_d = T(0.5) * T(N);
 #pragma unroll
@@ -156,6 +158,7 @@ __device__ __forceinline__ void gather_apply(const GatherRecs<T, U>& r, int base
             } else if (MODE == 4) {
                 out0[2 * p] = sx;
                 out0[2 * p + 1] = sy;
+                if (sq) *sq += double(sx) * double(sx) + double(sy) * double(sy);
             } else if (MODE == 3) {
                 vec2<T> o;
                 o.x = sx - y.x;
@@ -180,17 +183,18 @@ __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int
                                             T* __restrict__ out0, const T* __restrict__ in0, T* __restrict__ out1,
                                             T* __restrict__ out2, T* __restrict__ f, int64_t fstride,
                                             const vec2<T>* __restrict__ dw, bool chx, int tid, int nthreads,
-                                            const GatherRecs<T, U>* first = nullptr) {
+                                            const GatherRecs<T, U>* first = nullptr, double* sq = nullptr) {
     int base = p0 + tid;
     if (first) {
         if (base < p1) gather_apply<T, MODE, U>(*first, base, p1, nthreads, g0, g1, N, out_sorted, out0, out1, out2, f,
-                                                fstride, dw, chx);
+                                                fstride, dw, chx, sq);
         base += U * nthreads;
     }
     for (; base < p1; base += U * nthreads) {
         GatherRecs<T, U> r;
         gather_fetch<T, MODE, U>(r, base, p1, nthreads, samp, sidx, ysort, in0, chx);
-        gather_apply<T, MODE, U>(r, base, p1, nthreads, g0, g1, N, out_sorted, out0, out1, out2, f, fstride, dw, chx);
+        gather_apply<T, MODE, U>(r, base, p1, nthreads, g0, g1, N, out_sorted, out0, out1, out2, f, fstride, dw, chx,
+                                 sq);
     }
 }
 
