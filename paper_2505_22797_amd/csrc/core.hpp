@@ -295,14 +295,46 @@ __global__ void __launch_bounds__(256) k_core_update(const Prob* __restrict__ P,
     const double alpha = s.rr[nxt] / (inv_l * yy + reg * ll);
     const int64_t nn = int64_t(N) * N, o = 3 * p.o_c;
     double acc = 0.0;
-    for (int i = tid; i < 3 * N; i += 256) {
-        const int ch = i / N, xx = i - ch * N;
-        const int64_t off = o + ch * nn + int64_t(j) * N + xx;
-        const double q = inv_l * double(g[i]) + reg * (ch == 1 ? 2.0 : 1.0) * lap5(l + o + ch * nn, N, j, xx);
-        x[off] += alpha * p_new[off];
-        const double re = r[off] - alpha * q;
-        r[off] = re;
-        acc += re * re;
+    // K elements per thread at a time, all their loads issued before the first use
+    constexpr int K = 3;
+    for (int i0 = tid; i0 < 3 * N; i0 += K * 256) {
+        double lv[K][5], pv_[K], xv[K], rv[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int i = i0 + u * 256;
+            if (i < 3 * N) {
+                const int ch = i / N, xx = i - ch * N;
+                const double* lc = l + o + ch * nn + int64_t(j) * N + xx;
+                const int64_t off = o + ch * nn + int64_t(j) * N + xx;
+                lv[u][0] = lc[0];
+                lv[u][1] = j > 0 ? lc[-N] : 0.0;
+                lv[u][2] = j + 1 < N ? lc[N] : 0.0;
+                lv[u][3] = xx > 0 ? lc[-1] : 0.0;
+                lv[u][4] = xx + 1 < N ? lc[1] : 0.0;
+                pv_[u] = p_new[off];
+                xv[u] = x[off];
+                rv[u] = r[off];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int i = i0 + u * 256;
+            if (i < 3 * N) {
+                const int ch = i / N, xx = i - ch * N;
+                const int64_t off = o + ch * nn + int64_t(j) * N + xx;
+                const double v = lv[u][0];
+                double sl = 0.0;                                     // lap5's order
+                if (j > 0) sl += lv[u][1] - v;
+                if (j + 1 < N) sl += lv[u][2] - v;
+                if (xx > 0) sl += lv[u][3] - v;
+                if (xx + 1 < N) sl += lv[u][4] - v;
+                const double q = inv_l * double(g[i]) + reg * (ch == 1 ? 2.0 : 1.0) * sl;
+                x[off] = xv[u] + alpha * pv_[u];
+                const double re = rv[u] - alpha * q;
+                r[off] = re;
+                acc += re * re;
+            }
+        }
     }
     double unused = 0.0;
     tree_sum2(acc, unused, red);
