@@ -318,8 +318,11 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
     const int2* sidx = at<int2>(plan, p.o_sidx);
     const vec2<T>* ysort = at<vec2<T>>(work, p.w_ysort);
     const vec2<T>* dw = p.o_dw ? at<vec2<T>>(plan, p.o_dw) : nullptr;
-    GatherRecs<T, 4> first;
-    gather_fetch<T, MODE, 4>(first, p0 + tid, p1, 4 * kWave, samp, sidx, ysort, in0, p.chan == 1);
+    // records per thread and pass: 4, or 2 for the modes that also read a
+    // signal by time index (trajectory gradients, residual), which would spill
+    constexpr int U = (MODE == 2 || MODE == 3) ? 2 : 4;
+    GatherRecs<T, U> first;
+    gather_fetch<T, MODE, U>(first, p0 + tid, p1, 4 * kWave, samp, sidx, ysort, in0, p.chan == 1);
     twr.store(sm.tw, tid);
     __syncthreads();
     T* g0 = sm.g;            // row b:   [ch][N]
@@ -336,7 +339,7 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
         }
     }
     __syncthreads();
-    gather_band<T, MODE, 4>(g0, g1, N, p0, p1, samp, sidx, ysort, at<vec2<T>>(work, p.w_res), out0, in0, out1, out2,
+    gather_band<T, MODE, U>(g0, g1, N, p0, p1, samp, sidx, ysort, at<vec2<T>>(work, p.w_res), out0, in0, out1, out2,
                             f, p.t, dw, p.chan == 1, tid, 4 * kWave, &first);
 }
 
