@@ -205,6 +205,24 @@ __global__ void __launch_bounds__(256) k_core_dir_gather(const Prob* __restrict_
         }
         return;
     }
+    const int64_t nn = int64_t(N) * N, o = 3 * p.o_c;
+    const int W = 3 * N;
+    double* pd = reinterpret_cast<double*>(smem);                  // [3 rows][3 ch][N]
+    T* pr = reinterpret_cast<T*>(smem + core_dir_rows_bytes(N));   // [2 rows][3 ch][N]
+    // The thread's first column of r and p_prev on rows j-1 .. j+1 (all nine
+    // row-channel pairs) is loaded before the |r|^2 total, so the loads
+    // overlap its reduction; later columns (N > 256) follow in the loop below.
+    double rv[9], pv9[9];
+    const int x0 = tid;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int rw = q / 3, ch = q % 3, row = j - 1 + rw;
+        if (x0 < N && row >= 0 && row < N) {
+            const int64_t off = o + ch * nn + int64_t(row) * N + x0;
+            rv[q] = r[off];
+            pv9[q] = p_prev[off];
+        }
+    }
     const double rr = tree_sum(s.part_r + int64_t(b) * kCoreParts, N, red);
     const int taken = s.steps[cur];
     const bool stop = taken >= max_iter || !(rr > tol * tol * s.bb[b]);
@@ -215,19 +233,27 @@ __global__ void __launch_bounds__(256) k_core_dir_gather(const Prob* __restrict_
     }
     if (stop) return;
     const double beta = rr / s.rr[cur];
-    const int64_t nn = int64_t(N) * N, o = 3 * p.o_c;
-    const int W = 3 * N;
-    double* pd = reinterpret_cast<double*>(smem);                  // [3 rows][3 ch][N]
-    T* pr = reinterpret_cast<T*>(smem + core_dir_rows_bytes(N));   // [2 rows][3 ch][N]
-    for (int i = tid; i < 3 * W; i += 256) {
-        const int rw = i / W, rem = i - rw * W, ch = rem / N, xx = rem - ch * N;
-        const int row = j - 1 + rw;
-        if (row >= 0 && row < N) {
-            const int64_t off = o + ch * nn + int64_t(row) * N + xx;
-            const double v = r[off] + beta * p_prev[off];
-            pd[i] = v;
-            if (rw == 1) p_new[off] = v;
-            if (rw >= 1) pr[i - W] = T(v);
+    for (int x = x0; x < N; x += 256) {
+        if (x != x0) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int rw = q / 3, ch = q % 3, row = j - 1 + rw;
+                if (row >= 0 && row < N) {
+                    const int64_t off = o + ch * nn + int64_t(row) * N + x;
+                    rv[q] = r[off];
+                    pv9[q] = p_prev[off];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int rw = q / 3, ch = q % 3, row = j - 1 + rw;
+            if (row >= 0 && row < N) {
+                const double v = rv[q] + beta * pv9[q];
+                pd[rw * W + ch * N + x] = v;
+                if (rw == 1) p_new[o + ch * nn + int64_t(row) * N + x] = v;
+                if (rw >= 1) pr[(rw - 1) * W + ch * N + x] = T(v);
+            }
         }
     }
     __syncthreads();
@@ -284,21 +310,13 @@ __global__ void __launch_bounds__(256) k_core_update(const Prob* __restrict__ P,
         yy += s.part_y[int64_t(b) * kCoreParts + q];
         ll += s.part_l[int64_t(b) * kCoreParts + q];
     }
-    T* g = reinterpret_cast<T*>(smem);
-    char* sc = smem + lds_align(size_t(3) * N * sizeof(T));
-    scatter_row<T, true, 256>(g, scatter_lds<T>(sc, N, 256), N, j, at<int>(plan, p.o_binstart),
-                              at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
-                              reinterpret_cast<const vec2<T>*>(y + p.o_s), nullptr, tid, p.chan == 1);
-    // the sampling's scratch (at least 6 * 256 values of T after g) now holds the reductions
-    double* red = reinterpret_cast<double*>(sc);
-    tree_sum2(yy, ll, red);
-    const double alpha = s.rr[nxt] / (inv_l * yy + reg * ll);
     const int64_t nn = int64_t(N) * N, o = 3 * p.o_c;
-    double acc = 0.0;
-    // K elements per thread at a time, all their loads issued before the first use
+    // K elements per thread at a time; the first K elements' loads (Laplacian
+    // neighbours, direction, field, residual) are issued before the transpose
+    // sampling, which they do not depend on, so their latency overlaps it
     constexpr int K = 3;
-    for (int i0 = tid; i0 < 3 * N; i0 += K * 256) {
-        double lv[K][5], pv_[K], xv[K], rv[K];
+    double lv[K][5], pv_[K], xv[K], rv[K];
+    auto load_k = [&](int i0) {
 #pragma unroll
         for (int u = 0; u < K; ++u) {
             const int i = i0 + u * 256;
@@ -316,6 +334,20 @@ __global__ void __launch_bounds__(256) k_core_update(const Prob* __restrict__ P,
                 rv[u] = r[off];
             }
         }
+    };
+    load_k(tid);
+    T* g = reinterpret_cast<T*>(smem);
+    char* sc = smem + lds_align(size_t(3) * N * sizeof(T));
+    scatter_row<T, true, 256>(g, scatter_lds<T>(sc, N, 256), N, j, at<int>(plan, p.o_binstart),
+                              at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
+                              reinterpret_cast<const vec2<T>*>(y + p.o_s), nullptr, tid, p.chan == 1);
+    // the sampling's scratch (at least 6 * 256 values of T after g) now holds the reductions
+    double* red = reinterpret_cast<double*>(sc);
+    tree_sum2(yy, ll, red);
+    const double alpha = s.rr[nxt] / (inv_l * yy + reg * ll);
+    double acc = 0.0;
+    for (int i0 = tid; i0 < 3 * N; i0 += K * 256) {
+        if (i0 != tid) load_k(i0);
 #pragma unroll
         for (int u = 0; u < K; ++u) {
             const int i = i0 + u * 256;
