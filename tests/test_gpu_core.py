@@ -181,3 +181,30 @@ def test_two_stage_pipeline_reconstructs_like_the_oracle():
         ref, _ = O.zeroshot_pnp(a[0] + a[2], it["h"], it["R"], 9, 1e-5)
         err = lambda x: np.linalg.norm(x - it["c"]) / np.linalg.norm(it["c"])
         assert err(rho[i]) <= 1.1 * err(ref), (i, err(rho[i]), err(ref))
+
+
+def test_paper_runtime_workload_21():
+    """The shape of the paper's runtime table: a 21 x 21 grid, one
+    1632-sample period of the Lissajous figure, cosine interpolation, the full
+    kernel, float32; Core Stage then ten ZeroShot-PnP passes.  The field meets
+    the tolerance-mode checks against the oracle, and the reconstruction is as
+    close to the phantom as the oracle pipeline's (within 10 % of its error)."""
+    n = 21
+    tr = S.lissajous(S.SAMPLES_PER_PERIOD, ax=0.95, ay=0.95)
+    r, v = rounded(tr.r, torch.float32), rounded(tr.v, torch.float32)
+    h = S.h_fwhm2(n)
+    c = S.ellipses_and_line(n, 7)
+    M = O.Model(n, h, n - 1, r, v, interp="cosine")
+    s = rounded(S.add_noise(M.forward(c), 30.0, seed=n), torch.float32)
+    batch = mpik.Batch([(n, h, n - 1, dev(r, torch.float32), dev(v, torch.float32), "fft", "cosine")],
+                       dtype=torch.float32, tune=False)
+    field, steps = batch.core_stage(dev(s, torch.float32).reshape(-1), gamma=1e-3, tol=1e-3)
+    rho, _ = batch.pnp(batch.field_trace(field), n_it=9, nu0=1e-5, tol=1e-3)
+    torch.cuda.synchronize()
+    a_ref, k = O.core_stage(s, r, v, n, 1e-3)
+    it = dict(s=s, r=r, v=v, n=n, G=M.field(c))
+    check_solve(it, batch.field_views(field)[0].double().cpu().numpy(), steps[0], k, a_ref, torch.float32, 1e-3, 1e-3)
+    ref, _ = O.zeroshot_pnp(a_ref[0] + a_ref[2], h, n - 1, 9, 1e-5)
+    err = lambda x: np.linalg.norm(x - c) / np.linalg.norm(c)
+    got = rho.double().cpu().numpy().reshape(n, n)
+    assert err(got) <= 1.1 * err(ref), (err(got), err(ref))
