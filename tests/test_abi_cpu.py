@@ -124,3 +124,23 @@ def test_apply_argument_errors_need_no_gpu(mpik):
     assert L.mpi_batch_pair(None, 256, 256, 512, 256, 1 << 20, None) == -1
     assert L.mpi_plan_destroy(None) == -1
     assert L.mpi_plan_info(None, None, None, None) == -1
+
+
+def test_size_limits(mpik):
+    """The edges that the GPU limit tests run at are accepted, one past each is rejected."""
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+
+    def code(**kw):
+        p = _prob(mpik, **{k: v for k, v in kw.items() if k in ("n", "radius", "conv_mode")})
+        for k, v in kw.items():
+            if k not in ("n", "radius", "conv_mode"):
+                setattr(p, k, v)
+        return mpik.lib().mpi_plan_bytes(ctypes.byref(p), ctypes.byref(pb), ctypes.byref(wb))
+
+    assert code(n=1024, radius=7, conv_mode="direct", n_samples=(1 << 26) - 1) == 0
+    assert code(n=1024, radius=7, conv_mode="direct", n_samples=1 << 26) == -1
+    assert code(n=1025, radius=7, conv_mode="direct") == -1
+    assert code(n=512, radius=511, conv_mode="fft") == 0          # M = 1024, float32
+    assert code(n=513, radius=7, conv_mode="fft") == -6           # the FFT path stops at 512^2
+    assert code(n=400, radius=112, conv_mode="fft", dtype=1) == 0  # M = 512, float64
+    assert code(n=400, radius=113, conv_mode="fft", dtype=1) == -6
