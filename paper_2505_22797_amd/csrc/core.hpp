@@ -56,12 +56,9 @@ struct CoreCg {
     double* part_y;  // per base-cell row: |I p|^2 (0 for the last grid row)
 };
 
-// Fixed-order total of n partial sums, the same value in every work-group of
-// 256 threads: thread t adds parts t, t + 256, ... in turn, then a fixed
-// tree over the threads.
-__device__ __forceinline__ double tree_sum(const double* __restrict__ part, int n, double* red) {
-    double v = 0.0;
-    for (int q = threadIdx.x; q < n; q += 256) v += part[q];
+// Total of one value per thread over a work-group of 256 threads by a fixed
+// tree (red: 256 entries); every thread gets it.
+__device__ __forceinline__ double block_total(double v, double* red) {
     red[threadIdx.x] = v;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -71,6 +68,14 @@ __device__ __forceinline__ double tree_sum(const double* __restrict__ part, int 
     const double t = red[0];
     __syncthreads();
     return t;
+}
+
+// Fixed-order total of n partial sums, the same value in every work-group of
+// 256 threads: thread t adds parts t, t + 256, ... in turn, then block_total.
+__device__ __forceinline__ double tree_sum(const double* __restrict__ part, int n, double* red) {
+    double v = 0.0;
+    for (int q = threadIdx.x; q < n; q += 256) v += part[q];
+    return block_total(v, red);
 }
 
 // The fixed tree of tree_sum over two values per thread at once (red holds
@@ -368,8 +373,7 @@ __global__ void __launch_bounds__(256) k_core_update(const Prob* __restrict__ P,
             }
         }
     }
-    double unused = 0.0;
-    tree_sum2(acc, unused, red);
+    acc = block_total(acc, red);
     if (tid == 0) s.part_r[int64_t(b) * kCoreParts + j] = acc;
 }
 
