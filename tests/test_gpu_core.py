@@ -39,7 +39,8 @@ class CoreCase:
         self.items = []
         specs = []
         for i, (n, t, R, mode) in enumerate(shapes):
-            tr = S.lissajous(t, ax=0.85, ay=0.85 - 0.02 * i)
+            amp = 0.95 * (1.0 - 1.0 / n)                   # inside the hull of the cell centres
+            tr = S.lissajous(t, ax=min(0.85, amp), ay=min(0.85 - 0.02 * i, amp))
             r, v = rounded(tr.r, dtype), rounded(tr.v, dtype)
             h = S.h_fwhm2(n) * (1.0 + 0.05 * i)
             c = S.ellipses_and_line(n, seed + i)
@@ -208,3 +209,17 @@ def test_paper_runtime_workload_21():
     err = lambda x: np.linalg.norm(x - c) / np.linalg.norm(c)
     got = rho.double().cpu().numpy().reshape(n, n)
     assert err(got) <= 1.1 * err(ref), (err(got), err(ref))
+
+
+def test_core_stage_smallest_grids():
+    """2^2, 3^2 and 5^2 grids (one base-cell row at 2^2) on both paths,
+    float64, with a larger grid in the same batch: 8 steps (fewer than the
+    12 unknowns at 2^2) element by element against the oracle."""
+    cc = CoreCase([(2, 60, 1, "fft"), (3, 90, 2, "direct"), (5, 200, 4, "fft"), (16, 400, 15, "fft")],
+                  torch.float64, seed=13)
+    field, steps = cc.batch.core_stage(cc.s_all(), gamma=1e-3, tol=0.0, max_iter=8)
+    got = cc.fields(field)
+    for i, it in enumerate(cc.items):
+        ref, k = O.core_stage(it["s"], it["r"], it["v"], it["n"], 1e-3, tol=0.0, max_iter=8)
+        assert steps[i] == k == 8
+        assert rel_l2(got[i], ref) <= 1e-10, (i, rel_l2(got[i], ref))

@@ -37,7 +37,8 @@ class DeconvCase:
         self.items = []
         specs = []
         for i, (n, R, mode) in enumerate(shapes):
-            tr = S.lissajous(64, ax=0.8, ay=0.8)          # the samples play no part here
+            amp = min(0.8, 0.95 * (1.0 - 1.0 / n))      # the samples play no part here
+            tr = S.lissajous(64, ax=amp, ay=amp)
             h = S.h_fwhm2(n) * (1.0 + 0.05 * i)
             rho = S.blobs(n, seed + i)
             u = rounded(S.add_noise(O.trace_conv(rho, h, R), snr_db, seed=seed + i), dtype)
@@ -254,3 +255,20 @@ def test_cg_full_size_meets_the_stop_rule():
         true = np.linalg.norm(Cf(Cf(x[i])) + 1e-5 * x[i] - rhs[i]) / np.linalg.norm(rhs[i])
         assert true <= 1.05e-3, (i, true, steps[i])
         assert steps[i] > 0
+
+
+def test_smallest_grids():
+    """2^2, 3^2 and 5^2 grids on both paths, float64: the trace convolution
+    element by element, and CG at nu = lambda_max with the oracle's steps."""
+    dc = DeconvCase([(2, 1, "fft"), (3, 2, "direct"), (5, 4, "fft"), (2, 1, "direct")], torch.float64, seed=21)
+    xs = [np.random.default_rng(30 + i).standard_normal((it["n"], it["n"])) for i, it in enumerate(dc.items)]
+    out = dc.split(dc.batch.trace_conv(dc.cat(xs)))
+    for i, it in enumerate(dc.items):
+        assert rel_l2(out[i], O.trace_conv(xs[i], it["h"], it["R"])) <= 1e-12, i
+    nus = [dc.lam_max(i) for i in range(len(dc.items))]
+    x, steps = dc.batch.cg(dc.cat(xs), nus, tol=1e-8, max_iter=50)
+    x = dc.split(x)
+    for i, it in enumerate(dc.items):
+        Cf = dc.C(i)
+        ref, k, _ = O.cg(lambda v: Cf(Cf(v)) + nus[i] * v, xs[i], 1e-8, 50)
+        assert abs(steps[i] - k) <= 1 and rel_l2(x[i], ref) <= 1e-10, (i, steps[i], k)
