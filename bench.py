@@ -411,6 +411,20 @@ def deconvolution(mpik, S, dev, with_oracle, count=64, n_it=9, snr_db=30.0):
     return rec
 
 
+def core_step_roofline(count, n, t, ms_per_step):
+    """HBM roofline of one batched Core Stage CG step (float32 sampling,
+    float64 vectors).  Compulsory bytes per problem: launch A reads r and the
+    previous direction and writes the new direction and the Laplacian
+    (4 x 24 N^2), reads the sample records (24 T) and writes I p (8 T);
+    launch B reads I p and the records (32 T), the Laplacian and the
+    direction (2 x 24 N^2), and reads and writes x and r (4 x 24 N^2):
+    240 N^2 + 64 T bytes."""
+    per = 240 * n * n + 64 * t
+    achieved = count * per / (ms_per_step * 1e-3) / 1e9
+    return {"bound": "hbm", "algorithmic_bytes_per_step": count * per, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
+
+
 def two_stage(mpik, S, dev, with_oracle, count=64, snr_db=30.0, gamma=1e-3):
     """The paper's reconstruction from the signals: Core Stage (variational
     field reconstruction with cosine interpolation, gamma = 1e-3, CG tolerance
@@ -459,6 +473,7 @@ def two_stage(mpik, S, dev, with_oracle, count=64, snr_db=30.0, gamma=1e-3):
            "reconstructions_per_s": round(count * 1e3 / (core_ms + pnp_ms), 2),
            "core_stage_ms": round(core_ms, 3), "core_cg_steps_max": int(max(steps)),
            "ms_per_batched_core_step": round(core_ms / max(1, max(steps)), 4),
+           "core_step_roofline": core_step_roofline(count, n, t, core_ms / max(1, max(steps))),
            "deconvolution_ms": round(pnp_ms, 3),
            "relative_error_to_phantom": round(err, 4)}
     if with_oracle:
