@@ -48,6 +48,9 @@ def src_digest() -> str:
     return h.hexdigest()[:16]
 
 
+STAGE_NAMES = ("fwd_rows", "fwd_cols", "fwd_rows_gather", "adj_scatter_row", "adj_cols", "adj_rows")
+
+
 def stage_bytes(name: str, n: int, m: int, t: int, elem: int = 4) -> float:
     """Compulsory bytes of one launch of a stage for one problem: every input
     and output of the stage moved once (plan constants included)."""
@@ -207,6 +210,7 @@ def main() -> int:
     pairs_per_s = B * 1e3 / msB
     print(f"bench: batch {B}: {msB * 1e3:.1f} us/step, {pairs_per_s:.0f} pairs/s", file=sys.stderr, flush=True)
 
+    batch_fft = batch.info[0]["fft_size"]
     dom = max(stB, key=stB.get)
     dom_bytes = B * stage_bytes(dom, n, batch.info[0]["fft_size"], t)
     achieved = dom_bytes / (stB[dom] * 1e-3) / 1e9
@@ -236,6 +240,9 @@ def main() -> int:
         "hbm_fraction": round(b_alg * pairs_per_s / (HBM_PEAK_GBS * 1e9), 5),
         "algorithmic_bytes_per_pair": b_alg,
         "stage_ms": {k: round(x, 5) for k, x in stB.items()},
+        # every FFT-path stage: compulsory bytes of the batch / HIP-event duration, against HBM peak
+        "stage_hbm_frac": {k: round(B * stage_bytes(k, n, batch_fft, t) / (x * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                           for k, x in stB.items() if k in STAGE_NAMES},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                      "algorithmic_bytes_per_launch": dom_bytes},
