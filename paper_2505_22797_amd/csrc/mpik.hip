@@ -40,6 +40,7 @@ constexpr int kMaxBatch = 4096;
 constexpr int kSliceChoices[3] = {4, 8, 16};
 constexpr size_t kSmemLimit = 160 * 1024;
 constexpr int kMaxSide = 8;              // side streams of a plan
+constexpr int kIterBlock = 8;            // iterations per graph launch of a long mpi_iterate
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int pow2_at_least(int x) {
@@ -322,7 +323,7 @@ struct mpi_plan {
         hipGraphExec_t exec = nullptr;
         hipGraph_t graph = nullptr;
         std::vector<double> key;
-    } cg_gc, core_gc;
+    } cg_gc, core_gc, iter_gc;   // iter_gc: a block of kIterBlock iterations
 };
 
 namespace {
@@ -1135,6 +1136,44 @@ int unrolled_vjp_impl(mpi_plan* pl, const T* s, const T* ckpt, int K, int E, dou
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
+double key_of(const void* ptr) { return double(reinterpret_cast<uintptr_t>(ptr)); }
+
+// Records what `record(stream)` launches into the cache unless it already
+// holds a graph for `key` (the buffers and parameters baked into the launches).
+template <typename F>
+int cached_graph(mpi_plan::GraphCache& gc, const std::vector<double>& key, hipStream_t st, F&& record) {
+    if (gc.exec && gc.key == key) return MPI_OK;
+    if (gc.exec) {
+        HIP_TRY(hipStreamSynchronize(st));
+        (void)hipGraphExecDestroy(gc.exec);
+        (void)hipGraphDestroy(gc.graph);
+        gc.exec = nullptr;
+        gc.graph = nullptr;
+    }
+    hipStream_t cap;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        record(cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cap, &g);
+        if (e == hipSuccess) {
+            e = hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0);
+            if (e == hipSuccess) gc.graph = g;
+            else (void)hipGraphDestroy(g);
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    }
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess || !gc.exec) {
+        gc.exec = nullptr;
+        return MPI_ERR_HIP;
+    }
+    gc.key = key;
+    return MPI_OK;
+}
+
 template <typename T>
 int iterate_impl(mpi_plan* pl, const T* s, T* c, const mpi_iter_params* ip, const double* taus, char* work,
                  hipStream_t st) {
@@ -1188,7 +1227,18 @@ int iterate_impl(mpi_plan* pl, const T* s, T* c, const mpi_iter_params* ip, cons
         pl->g_sigma = denoise ? ip->denoise_sigma_px : 0.0;
         pl->g_rad = rad;
     }
-    for (int it = 0; it < ip->n_iter; ++it) HIP_TRY(hipGraphLaunch(pl->gexec, st));
+    // blocks of kIterBlock iterations from a second cached graph (fewer graph
+    // launches, each with its fork and join), the remainder one by one
+    int it = 0;
+    if (ip->n_iter >= kIterBlock) {
+        const std::vector<double> key{key_of(s), key_of(c), key_of(work), pl->g_sigma, double(rad)};
+        const int rc = cached_graph(pl->iter_gc, key, st, [&](hipStream_t cap) {
+            for (int i = 0; i < kIterBlock; ++i) (void)iteration_impl<T>(pl, c, denoise, rad, work, cap);
+        });
+        if (rc != MPI_OK) return rc;
+        for (; it + kIterBlock <= ip->n_iter; it += kIterBlock) HIP_TRY(hipGraphLaunch(pl->iter_gc.exec, st));
+    }
+    for (; it < ip->n_iter; ++it) HIP_TRY(hipGraphLaunch(pl->gexec, st));
     return MPI_OK;
 }
 
@@ -1333,44 +1383,6 @@ void cg_step(const mpi_plan* pl, int par, double tol, int max_iter, char* work, 
 }
 
 constexpr int kCgBlock = 4;   // CG steps per captured graph (even: each block starts on state slot 0)
-
-double key_of(const void* ptr) { return double(reinterpret_cast<uintptr_t>(ptr)); }
-
-// Records what `record(stream)` launches into the cache unless it already
-// holds a graph for `key` (the buffers and parameters baked into the launches).
-template <typename F>
-int cached_graph(mpi_plan::GraphCache& gc, const std::vector<double>& key, hipStream_t st, F&& record) {
-    if (gc.exec && gc.key == key) return MPI_OK;
-    if (gc.exec) {
-        HIP_TRY(hipStreamSynchronize(st));
-        (void)hipGraphExecDestroy(gc.exec);
-        (void)hipGraphDestroy(gc.graph);
-        gc.exec = nullptr;
-        gc.graph = nullptr;
-    }
-    hipStream_t cap;
-    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        record(cap);
-        hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(cap, &g);
-        if (e == hipSuccess) {
-            e = hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0);
-            if (e == hipSuccess) gc.graph = g;
-            else (void)hipGraphDestroy(g);
-        } else if (g) {
-            (void)hipGraphDestroy(g);
-        }
-    }
-    (void)hipStreamDestroy(cap);
-    if (e != hipSuccess || !gc.exec) {
-        gc.exec = nullptr;
-        return MPI_ERR_HIP;
-    }
-    gc.key = key;
-    return MPI_OK;
-}
 
 // Launches captured blocks of kCgBlock steps and polls the stop flags (slot
 // 0) after each block until every problem has stopped or max_iter steps ran.
@@ -2087,7 +2099,7 @@ int mpi_plan_destroy(mpi_plan* plan) {
         (void)hipGraphExecDestroy(plan->gexec);
         (void)hipGraphDestroy(plan->graph);
     }
-    for (mpi_plan::GraphCache* gc : {&plan->cg_gc, &plan->core_gc})
+    for (mpi_plan::GraphCache* gc : {&plan->cg_gc, &plan->core_gc, &plan->iter_gc})
         if (gc->exec) {
             (void)hipDeviceSynchronize();
             (void)hipGraphExecDestroy(gc->exec);

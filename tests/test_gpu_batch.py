@@ -205,7 +205,8 @@ def test_chunked_batch_equals_single_plans(kind):
 @pytest.mark.parametrize("kind", sorted(CHUNKED))
 def test_chunked_batch_iterate_matches_oracle(kind):
     """The per-problem step tau_b follows its problem into its range: a
-    different tau per problem, 6 iterations, each against the oracle."""
+    different tau per problem, 10 iterations (one captured block of eight,
+    then two single ones), each against the oracle."""
     specs = _chunk_specs(CHUNKED[kind], 400)
     batch = _build(specs)
     taus, s_list, models = [], [], []
@@ -216,8 +217,8 @@ def test_chunked_batch_iterate_matches_oracle(kind):
         taus.append((0.5 + 0.02 * i) / O.power_lambda_max(M, iters=20))
     s_all = torch.cat([dev(s, torch.float32).reshape(-1) for s in s_list])
     c_all = torch.zeros(batch.c_offsets[-1], dtype=torch.float32, device="cuda")
-    batch.iterate(s_all, c_all, 6, taus)
+    batch.iterate(s_all, c_all, 10, taus)
     torch.cuda.synchronize()
     for b, sp in enumerate(specs):
-        ref = O.iterate(models[b], s_list[b], np.zeros((sp["n"], sp["n"])), taus[b], 6)
+        ref = O.iterate(models[b], s_list[b], np.zeros((sp["n"], sp["n"])), taus[b], 10)
         assert rel_l2(batch.c_views(c_all)[b].double().cpu().numpy(), ref) <= 1e-4, b
