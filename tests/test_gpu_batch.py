@@ -222,3 +222,37 @@ def test_chunked_batch_iterate_matches_oracle(kind):
     for b, sp in enumerate(specs):
         ref = O.iterate(models[b], s_list[b], np.zeros((sp["n"], sp["n"])), taus[b], 10)
         assert rel_l2(batch.c_views(c_all)[b].double().cpu().numpy(), ref) <= 1e-4, b
+
+
+def test_pair_in_a_captured_graph_replays_like_eager():
+    """The pair call of a batch split into problem ranges (side streams
+    forked and joined inside the call), captured in a graph: three replays,
+    each after new inputs are copied in and other eager work has run, equal
+    the eager results bitwise."""
+    specs = _chunk_specs(CHUNKED["one_size"], 700)
+    batch = _build(specs, columns="wave")
+    n_c, n_s = batch.c_offsets[-1], batch.s_offsets[-1]
+    c_in = torch.empty(n_c, dtype=torch.float32, device="cuda")
+    s_out = torch.empty(n_s, dtype=torch.float32, device="cuda")
+    g_out = torch.empty(n_c, dtype=torch.float32, device="cuda")
+    c_in.copy_(_c_all(batch, specs))
+    batch.pair(c_in, s_out, g_out)                 # warm: workspaces
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batch.pair(c_in, s_out, g_out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.pair(c_in, s_out, g_out)
+    rng = np.random.default_rng(9)
+    for rep in range(3):
+        x = torch.tensor(rounded(rng.standard_normal(n_c), torch.float32), dtype=torch.float32, device="cuda")
+        s_ref, g_ref = batch.pair(x)              # eager, other buffers
+        torch.cuda.synchronize()
+        c_in.copy_(x)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(s_out, s_ref) and torch.equal(g_out, g_ref), rep
