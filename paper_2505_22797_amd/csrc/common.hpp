@@ -223,30 +223,84 @@ __device__ __forceinline__ void fft_wave(cx<T>* line, const cx<T>* __restrict__ 
 // lane first takes an 8-point DFT over its registers and applies W512^(l k1);
 // the 64-point DFT over the lanes n2 = a + 8b, k2 = c + 8d is then
 // sum_a W8^(a d) W64^(a c) sum_b W8^(b c), two 8-point DFTs with an exchange
-// through LDS before each.  The exchange buffer xb (the wave's own, 576
-// slots) is padded by one slot in nine so that both exchanges are free of
-// bank conflicts.  Each exchange is one write-then-read round trip; a
+// through LDS before each.  Each exchange is one write-then-read round trip; a
 // 512-point transform makes two, against four for the in-LDS passes.
-// Per-lane twiddles of fft512_regs, read once per kernel from the plan's table
-// (tw[j] = W512^j) and kept in registers: w1[k] = W512^(lane k) and
-// w2[k] = W64^((lane >> 3) k), k = 1..7.
+//
+// Exchange layout.  Element i = 64x + 8y + z (x, y, z in [0, 8)) goes to slot
+// XbLayout<T>::slot(i) of the wave's buffer.  The three access shapes are: lane a + 8b
+// writes (x, y, z) = (k, a, b) for k = 0..7; lane lo + 8hi reads (lo, hi, k);
+// lane lo + 8hi writes (lo, k, hi).
+//  * float32 (8-byte elements): slot = XOR of a fixed 9-bit image of each set
+//    bit of i (a bijection of [0, 512), linear over GF(2)).  The images are
+//    chosen so that every 16-lane group of every access touches 16 distinct
+//    bank pairs (32 four-byte banks) and every 32-lane group 32 distinct
+//    ones (64 banks); a plain padding of one slot in nine leaves 4-way
+//    conflicts in the read and the second write.  Linearity splits every
+//    slot into a per-lane part (computed once, in Fft512Tw) XOR a constant
+//    per register.
+//  * float64 (16-byte elements): slot = i + i/8 (one pad slot in nine), which
+//    keeps every 8-lane group on 8 distinct four-bank groups.
+// kXbStride<T> is the distance between the waves' buffers, chosen so that the
+// column stages' four-wave staging reads (thread t reads element t/4 of wave
+// t%4) spread over the banks as well.
+template <typename T> struct XbLayout;
+template <> struct XbLayout<float> {
+    static constexpr int kImage[9] = {140, 16, 256, 8, 49, 66, 1, 2, 4};
+    static constexpr int kSlots = 512;
+    static constexpr int kStride = 516;
+    __host__ __device__ static constexpr int slot(int i) {
+        int s = 0;
+        for (int b = 0; b < 9; ++b) s ^= ((i >> b) & 1) ? kImage[b] : 0;
+        return s;
+    }
+};
+template <> struct XbLayout<double> {
+    static constexpr int kSlots = 576;
+    static constexpr int kStride = 578;
+    __host__ __device__ static constexpr int slot(int i) { return i + (i >> 3); }
+};
+template <typename T> inline constexpr int kXbStride = XbLayout<T>::kStride;
+
+namespace detail {
+template <typename T> __host__ __device__ constexpr bool xb_layout_ok() {
+    int seen[XbLayout<T>::kSlots] = {};
+    for (int i = 0; i < 512; ++i) {
+        const int s = XbLayout<T>::slot(i);
+        if (s < 0 || s >= XbLayout<T>::kSlots || seen[s]) return false;
+        seen[s] = 1;
+    }
+    return XbLayout<T>::kSlots <= XbLayout<T>::kStride;
+}
+static_assert(xb_layout_ok<float>() && xb_layout_ok<double>(), "exchange layout must be a bijection into the buffer");
+}  // namespace detail
+
+// Per-lane constants of fft512_regs, read or computed once per kernel:
+// twiddles from the plan's table (tw[j] = W512^j), w1[k] = W512^(lane k) and
+// w2[k] = W64^((lane >> 3) k), k = 1..7; and the lane's exchange slots
+// (float32 only): s1 for the first write, s2 for both reads, s3 for the
+// second write.
 template <typename T> struct Fft512Tw {
     cx<T> w1[7];
     cx<T> w2[7];
+    int s1, s2, s3;
     __device__ __forceinline__ void load(const cx<T>* __restrict__ tw, int lane) {
 #pragma unroll
         for (int k = 1; k < 8; ++k) {
             w1[k - 1] = tw[(lane * k) & 511];
             w2[k - 1] = tw[(8 * (lane >> 3) * k) & 511];
         }
+        const int lo = lane & 7, hi = lane >> 3;
+        s1 = XbLayout<T>::slot(8 * lo + hi);
+        s2 = XbLayout<T>::slot(64 * lo + 8 * hi);
+        s3 = XbLayout<T>::slot(64 * lo + hi);
     }
 };
 
-__device__ __forceinline__ constexpr int xpad(int i) { return i + (i >> 3); }
-constexpr int kXbSlots = 576;
-
 template <typename T, bool INV>
 __device__ __forceinline__ void fft512_regs(cx<T> (&v)[8], cx<T>* xb, const Fft512Tw<T>& tw, int lane) {
+    using L = XbLayout<T>;
+    constexpr bool kSwz = sizeof(T) == 4;
+    const int lo = lane & 7, hi = lane >> 3;
     dft8<T, INV>(v);
 #pragma unroll
     for (int k = 1; k < 8; ++k) {
@@ -255,15 +309,11 @@ __device__ __forceinline__ void fft512_regs(cx<T> (&v)[8], cx<T>* xb, const Fft5
         v[k] = cmul(v[k], w);
     }
     // exchange 1: lane a + 8b holds index k1 in register k1; lane k1 + 8a gathers b = 0..7
-    {
-        const int a = lane & 7, b = lane >> 3;
 #pragma unroll
-        for (int k1 = 0; k1 < 8; ++k1) xb[xpad(k1 * 64 + a * 8 + b)] = v[k1];
-    }
+    for (int k1 = 0; k1 < 8; ++k1) xb[kSwz ? (tw.s1 ^ L::slot(64 * k1)) : L::slot(k1 * 64 + lo * 8 + hi)] = v[k1];
     wave_sync();
-    const int lo = lane & 7, hi = lane >> 3;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) v[b] = xb[xpad(lo * 64 + hi * 8 + b)];
+    for (int b = 0; b < 8; ++b) v[b] = xb[kSwz ? (tw.s2 ^ L::slot(b)) : L::slot(lo * 64 + hi * 8 + b)];
     wave_sync();
     dft8<T, INV>(v);                          // over b: index c
 #pragma unroll
@@ -274,10 +324,10 @@ __device__ __forceinline__ void fft512_regs(cx<T> (&v)[8], cx<T>* xb, const Fft5
     }
     // exchange 2: lane k1 + 8a holds c in register c; lane k1 + 8c gathers a = 0..7
 #pragma unroll
-    for (int c = 0; c < 8; ++c) xb[xpad(lo * 64 + c * 8 + hi)] = v[c];
+    for (int c = 0; c < 8; ++c) xb[kSwz ? (tw.s3 ^ L::slot(8 * c)) : L::slot(lo * 64 + c * 8 + hi)] = v[c];
     wave_sync();
 #pragma unroll
-    for (int a = 0; a < 8; ++a) v[a] = xb[xpad(lo * 64 + hi * 8 + a)];
+    for (int a = 0; a < 8; ++a) v[a] = xb[kSwz ? (tw.s2 ^ L::slot(a)) : L::slot(lo * 64 + hi * 8 + a)];
     wave_sync();
     dft8<T, INV>(v);                          // over a: index d, X[lane + 64 d]
 }

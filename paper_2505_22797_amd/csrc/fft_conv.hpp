@@ -237,6 +237,50 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
         fft_wave<T, true, M>(line, sm.tw, lane);
         cx<T>* out = t2 + int64_t(wave) * N * H;
         for (int j = lane; j < N; j += kWave) out[int64_t(j) * H + kx] = line[j];
+    } else if constexpr (M == 512) {                // four columns, register-resident transforms
+        static_assert(4 * kXbStride<T> * sizeof(cx<T>) <= sizeof(ColSmem<T, M>), "exchange buffers exceed the LDS");
+        const int unit = xcd_unit(blockIdx.x, (H + 3) / 4);
+        if (unit < 0) return;
+        const int kx0 = 4 * unit, kx = kx0 + wave;
+        const bool active = kx < H;     // inactive waves stay for the work-group barriers
+        // each wave's exchange buffer, also the staging of its rows for the stores
+        cx<T>(*xb)[kXbStride<T>] = reinterpret_cast<cx<T>(*)[kXbStride<T>]>(smem);
+        Fft512Tw<T> tw;
+        cx<T> cr[8], v[8];
+        if (active) {
+            const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(kx) * N;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int i = lane + m * kWave;
+                cr[m] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+            }
+            tw.load(at<cx<T>>(plan, p.o_tw), lane);
+            fft512_regs<T, false>(cr, xb[wave], tw, lane);
+        }
+        for (int ch = 0; ch < (TRACE ? 1 : 3); ++ch) {
+            if (active) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int ky = lane + m * kWave;
+                    const T k = TRACE ? (p.chan == 1 ? spec_at<T, M>(spec, 0, kx, ky)
+                                                     : spec_at<T, M>(spec, 0, kx, ky) + spec_at<T, M>(spec, 2, kx, ky))
+                                      : spec_at<T, M>(spec, ch, kx, ky);
+                    v[m] = cscale(cr[m], k);
+                }
+                fft512_regs<T, true>(v, xb[wave], tw, lane);
+                wave_sync();
+#pragma unroll
+                for (int m = 0; m < 8; ++m)
+                    if (lane + m * kWave < N) xb[wave][lane + m * kWave] = v[m];
+            }
+            __syncthreads();
+            cx<T>* out = t2 + int64_t(ch) * N * H;
+            for (int i = tid; i < 4 * N; i += 4 * kWave) {
+                const int j = i >> 2, cc = i & 3;
+                if (kx0 + cc < H) out[int64_t(j) * H + kx0 + cc] = xb[cc][j];
+            }
+            __syncthreads();
+        }
     } else {                                        // four columns, one per wave
         const int unit = xcd_unit(blockIdx.x, (H + 3) / 4);
         if (unit < 0) return;
@@ -435,12 +479,13 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         fft_wave<T, true, M>(sm.c, sm.tw, lane);
         for (int j = lane; j < N; j += kWave) t2[int64_t(j) * H + kx] = sm.c[j];
     } else if constexpr (M == 512) {                // four columns, register-resident transforms
+        static_assert(4 * kXbStride<T> * sizeof(cx<T>) <= sizeof(ColSmem<T, M>), "exchange buffers exceed the LDS");
         const int unit = xcd_unit(blockIdx.x, (H + 3) / 4);
         if (unit < 0) return;
         const int kx0 = 4 * unit, kx = kx0 + wave;
         const bool active = kx < H;     // inactive waves stay for the work-group barriers
         // each wave's exchange buffer, also the staging of its rows for the stores
-        cx<T>(*xb)[kXbSlots] = reinterpret_cast<cx<T>(*)[kXbSlots]>(smem);
+        cx<T>(*xb)[kXbStride<T>] = reinterpret_cast<cx<T>(*)[kXbStride<T>]>(smem);
         Fft512Tw<T> tw;
         tw.load(at<cx<T>>(plan, p.o_tw), lane);
         const T* spec_dh = DUAL ? at<T>(plan, p.o_spec_dh) : nullptr;
@@ -604,6 +649,7 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
         }
     };
     if constexpr (M == 512) {                       // register-resident transform, no barrier
+        static_assert(4 * kXbStride<T> * sizeof(cx<T>) <= sizeof(RowSmem<T, M>), "exchange buffers exceed the LDS");
         if (!active) return;
         Fft512Tw<T> tw;
         tw.load(at<cx<T>>(plan, p.o_tw), lane);
@@ -613,7 +659,7 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
         cx<T> x[8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) x[m] = pr.spectrum(m, lane);
-        cx<T>(*xb)[kXbSlots] = reinterpret_cast<cx<T>(*)[kXbSlots]>(smem);
+        cx<T>(*xb)[kXbStride<T>] = reinterpret_cast<cx<T>(*)[kXbStride<T>]>(smem);
         fft512_regs<T, true>(x, xb[wave], tw, lane);
 #pragma unroll
         for (int m = 0; m < 8; ++m)
@@ -660,7 +706,8 @@ __device__ void rows_inv_fwd_body(const Prob& p, const char* __restrict__ plan, 
     const cx<T>* lines;                          // the four waves' forward spectra, natural order
     int stride;
     if constexpr (M == 512) {                    // register-resident transforms
-        cx<T>(*xb)[kXbSlots] = reinterpret_cast<cx<T>(*)[kXbSlots]>(smem);
+        static_assert(4 * kXbStride<T> * sizeof(cx<T>) <= sizeof(RowSmem<T, M>), "exchange buffers exceed the LDS");
+        cx<T>(*xb)[kXbStride<T>] = reinterpret_cast<cx<T>(*)[kXbStride<T>]>(smem);
         if (active) {
             Fft512Tw<T> tw;
             tw.load(at<cx<T>>(plan, p.o_tw), lane);
@@ -679,7 +726,7 @@ __device__ void rows_inv_fwd_body(const Prob& p, const char* __restrict__ plan, 
             for (int m = 0; m < 8; ++m) xb[wave][lane + m * kWave] = x[m];
         }
         lines = &xb[0][0];
-        stride = kXbSlots;
+        stride = kXbStride<T>;
     } else {
         auto& sm = *reinterpret_cast<RowSmem<T, M>*>(smem);
         TwiddleRegs<T, M, 4 * kWave> twr;

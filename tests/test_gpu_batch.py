@@ -84,6 +84,35 @@ def test_batch_matches_oracle(columns):
         assert rel_l2(batch.c_views(g_all)[b].double().cpu().numpy(), g_ref) <= 1e-5
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_wave_columns_full_kernel(dtype):
+    """The column stages in the one-wave-per-column shape at M = 512, where
+    every column transform is register-resident: three problems with full-size
+    kernels (N + R > 256), among them a ragged last group of four columns
+    (H = 257) and a grid far smaller than M, forward and transpose against
+    the oracle in both precisions."""
+    shapes = [(256, 255, 20000), (200, 199, 12000), (130, 129, 6000)]
+    specs, models, cs, ys = [], [], [], []
+    rng = np.random.default_rng(11)
+    for i, (n, R, t) in enumerate(shapes):
+        tr = S.lissajous(t, ax=0.85, ay=0.8 + 0.03 * i)
+        r, v = rounded(tr.r, dtype), rounded(tr.v, dtype)
+        h = S.h_fwhm2(n) * (0.95 + 0.05 * i)
+        specs.append((n, h, R, dev(r, dtype), dev(v, dtype), "fft"))
+        models.append(O.Model(n, h, R, r, v))
+        cs.append(rounded(S.ellipses_and_line(n, 40 + i), dtype))
+        ys.append(rounded(rng.standard_normal((t, 2)), dtype))
+    batch = mpik.Batch(specs, dtype=dtype, tune=False, columns="wave")
+    assert all(info["fft_size"] == 512 for info in batch.info)
+    s_all = batch.forward(torch.cat([dev(c, dtype).reshape(-1) for c in cs]))
+    g_all = batch.adjoint(torch.cat([dev(y, dtype).reshape(-1) for y in ys]))
+    torch.cuda.synchronize()
+    tol = 1e-5 if dtype == torch.float32 else 1e-12
+    for b, M in enumerate(models):
+        assert rel_l2(batch.s_views(s_all)[b].double().cpu().numpy(), M.forward(cs[b])) <= tol, b
+        assert rel_l2(batch.c_views(g_all)[b].double().cpu().numpy(), M.adjoint(ys[b])) <= tol, b
+
+
 @pytest.mark.parametrize("denoise", [False, True])
 def test_batch_iterate_matches_oracle(denoise):
     specs = _small_batch()[:4]
