@@ -404,12 +404,52 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
     cx<T>* lines = tw + M;
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     TwiddleRegs<T, M, 4 * kWave> twr;       // in flight during the transpose sampling
-    twr.load(plan, p, tid);
+    if constexpr (M != 512 || sizeof(T) != 4) twr.load(plan, p, tid);
     // SORTED: the signal in cell order, from s when given, else the problem's residual in work
     const vec2<T>* ys = (SORTED && s) ? reinterpret_cast<const vec2<T>*>(s) : at<vec2<T>>(work, p.w_res);
     scatter_row<T, SORTED, 256>(g, scatter_lds<T>(shared_area, N, 256), N, j, at<int>(plan, p.o_binstart),
                                 at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), ys,
                                 s, tid, p.chan == 1);
+    if constexpr (M == 512 && sizeof(T) == 4) {   // register-resident transforms (float32)
+        static_assert(2 * kXbStride<T> <= 3 * M, "exchange buffers exceed the transform region");
+        __syncthreads();
+        if (wave >= 2) return;
+        Fft512Tw<T> tw5;
+        tw5.load(at<cx<T>>(plan, p.o_tw), lane);
+        const T* re = g + (wave == 0 ? 0 : 2 * N);
+        const T* im = g + N;
+        cx<T> x[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int i = lane + m * kWave;
+            x[m] = cx<T>{T(0), T(0)};
+            if (i < N) {
+                x[m].x = re[i];
+                if (wave == 0) x[m].y = im[i];
+            }
+        }
+        cx<T>* xb = reinterpret_cast<cx<T>*>(shared_area) + wave * kXbStride<T>;
+        fft512_regs<T, false>(x, xb, tw5, lane);
+        cx<T>* t1 = at<cx<T>>(work, p.w_t1);
+        if (wave == 1) {
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                const int k = lane + m * kWave;
+                if (k < H) t1[(int64_t(2) * N + j) * H + k] = x[m];
+            }
+            return;
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) xb[lane + m * kWave] = x[m];
+        wave_sync();
+        for (int k = lane; k < H; k += kWave) {
+            cx<T> A, B;
+            split_pair<T, M>(xb, k, A, B);
+            t1[int64_t(j) * H + k] = A;
+            t1[(int64_t(N) + j) * H + k] = B;
+        }
+        return;
+    }
     twr.store(tw, tid);
     __syncthreads();
     if (wave >= 2) return;
