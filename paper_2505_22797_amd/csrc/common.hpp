@@ -275,36 +275,55 @@ static_assert(xb_layout_ok<float>() && xb_layout_ok<double>(), "exchange layout 
 }  // namespace detail
 
 // Per-lane constants of fft512_regs, read or computed once per kernel:
-// twiddles from the plan's table (tw[j] = W512^j), w1[k] = W512^(lane k) and
-// w2[k] = W64^((lane >> 3) k), k = 1..7; and the lane's exchange slots
-// (float32 only): s1 for the first write, s2 for both reads, s3 for the
-// second write.
+// twiddles from the plan's table (tw[j] = W512^j), w1(k) = W512^(lane k) and
+// w2(k) = W64^((lane >> 3) k), k = 1..7, kept in registers; and the lane's
+// exchange slots (float32 only): s1 for the first write, s2 for both reads,
+// s3 for the second write.
 template <typename T> struct Fft512Tw {
-    cx<T> w1[7];
-    cx<T> w2[7];
+    cx<T> w1_[7];
+    cx<T> w2_[7];
     int s1, s2, s3;
     __device__ __forceinline__ void load(const cx<T>* __restrict__ tw, int lane) {
 #pragma unroll
         for (int k = 1; k < 8; ++k) {
-            w1[k - 1] = tw[(lane * k) & 511];
-            w2[k - 1] = tw[(8 * (lane >> 3) * k) & 511];
+            w1_[k - 1] = tw[(lane * k) & 511];
+            w2_[k - 1] = tw[(8 * (lane >> 3) * k) & 511];
         }
         const int lo = lane & 7, hi = lane >> 3;
         s1 = XbLayout<T>::slot(8 * lo + hi);
         s2 = XbLayout<T>::slot(64 * lo + 8 * hi);
         s3 = XbLayout<T>::slot(64 * lo + hi);
     }
+    __device__ __forceinline__ cx<T> w1(int k) const { return w1_[k - 1]; }
+    __device__ __forceinline__ cx<T> w2(int k) const { return w2_[k - 1]; }
 };
 
-template <typename T, bool INV>
-__device__ __forceinline__ void fft512_regs(cx<T> (&v)[8], cx<T>* xb, const Fft512Tw<T>& tw, int lane) {
+// The same constants with the twiddles read from a table already in LDS at
+// each use: fewer registers, for kernels whose occupancy they would limit.
+template <typename T> struct Fft512TwLds {
+    const cx<T>* tw;
+    int lane, s1, s2, s3;
+    __device__ __forceinline__ void init(const cx<T>* tw_lds, int ln) {
+        tw = tw_lds;
+        lane = ln;
+        const int lo = lane & 7, hi = lane >> 3;
+        s1 = XbLayout<T>::slot(8 * lo + hi);
+        s2 = XbLayout<T>::slot(64 * lo + 8 * hi);
+        s3 = XbLayout<T>::slot(64 * lo + hi);
+    }
+    __device__ __forceinline__ cx<T> w1(int k) const { return tw[(lane * k) & 511]; }
+    __device__ __forceinline__ cx<T> w2(int k) const { return tw[(8 * (lane >> 3) * k) & 511]; }
+};
+
+template <typename T, bool INV, class TW>
+__device__ __forceinline__ void fft512_regs(cx<T> (&v)[8], cx<T>* xb, const TW& tw, int lane) {
     using L = XbLayout<T>;
     constexpr bool kSwz = sizeof(T) == 4;
     const int lo = lane & 7, hi = lane >> 3;
     dft8<T, INV>(v);
 #pragma unroll
     for (int k = 1; k < 8; ++k) {
-        cx<T> w = tw.w1[k - 1];
+        cx<T> w = tw.w1(k);
         if (INV) w.y = -w.y;
         v[k] = cmul(v[k], w);
     }
@@ -318,7 +337,7 @@ __device__ __forceinline__ void fft512_regs(cx<T> (&v)[8], cx<T>* xb, const Fft5
     dft8<T, INV>(v);                          // over b: index c
 #pragma unroll
     for (int c = 1; c < 8; ++c) {
-        cx<T> w = tw.w2[c - 1];
+        cx<T> w = tw.w2(c);
         if (INV) w.y = -w.y;
         v[c] = cmul(v[c], w);
     }

@@ -372,14 +372,35 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
     T* g0 = sm.g;            // row b:   [ch][N]
     T* g1 = sm.g + 3 * N;    // row b+1: [ch][N]
     if (wave < 3) {
-        cx<T>* line = sm.line[wave];
+        if constexpr (M == 512 && sizeof(T) == 4) {
+            // register-resident transform with the twiddles read from the LDS
+            // table (registers for them would cost occupancy here); the
+            // wave's line holds the exchange
+            static_assert(XbLayout<T>::kSlots <= M, "exchange exceeds the line");
+            Fft512TwLds<T> tl;
+            tl.init(sm.tw, lane);
+            cx<T> x[8];
 #pragma unroll
-        for (int m = 0; m < M / kWave; ++m) line[lane + m * kWave] = pr.spectrum(m, lane);
-        wave_sync();
-        fft_wave<T, true, M>(line, sm.tw, lane);
-        for (int i = lane; i < N; i += kWave) {
-            g0[wave * N + i] = line[i].x;
-            g1[wave * N + i] = line[i].y;
+            for (int m = 0; m < 8; ++m) x[m] = pr.spectrum(m, lane);
+            fft512_regs<T, true>(x, sm.line[wave], tl, lane);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int i = lane + m * kWave;
+                if (i < N) {
+                    g0[wave * N + i] = x[m].x;
+                    g1[wave * N + i] = x[m].y;
+                }
+            }
+        } else {
+            cx<T>* line = sm.line[wave];
+#pragma unroll
+            for (int m = 0; m < M / kWave; ++m) line[lane + m * kWave] = pr.spectrum(m, lane);
+            wave_sync();
+            fft_wave<T, true, M>(line, sm.tw, lane);
+            for (int i = lane; i < N; i += kWave) {
+                g0[wave * N + i] = line[i].x;
+                g1[wave * N + i] = line[i].y;
+            }
         }
     }
     __syncthreads();
