@@ -50,13 +50,26 @@ template <typename T, int M>
 __host__ __device__ constexpr size_t gather_smem_bytes(int N) {
     return sizeof(GatherSmem<T, M>) + size_t(6) * N * sizeof(T);
 }
-// adj_scatter_row: the row's three channels (3N values), then a region used
-// first by the sampling transpose and then by the twiddles and the two
-// row-FFT lines (the twiddles wait in registers meanwhile).
+// adj_scatter_row: a region used first by the sampling transpose and then by
+// the twiddles and the two row-FFT lines (the twiddles wait in registers
+// meanwhile), or by the two waves' exchange buffers at M = 512 in float32.
+// The row's three channels (3N values) are assembled once the transpose's
+// per-thread partial sums (first_val) are consumed, so they take that part of
+// the region when the transforms stay clear of it, and otherwise a part of
+// their own in front of the region.
+template <typename T, int M>
+__host__ __device__ constexpr size_t scatter_fft_bytes() {
+    return (M == 512 && sizeof(T) == 4) ? 2 * kXbStride<T> * sizeof(cx<T>) : 3 * sizeof(cx<T>) * M;
+}
+template <typename T, int M>
+__host__ __device__ constexpr bool scatter_g_in_region(int N) {
+    return scatter_fft_bytes<T, M>() <= scatter_lds_first_val<T>(N, 256) && 3 * N <= 6 * 256;
+}
 template <typename T, int M>
 __host__ __device__ constexpr size_t scatter_row_smem_bytes(int N) {
-    const size_t fft = 3 * sizeof(cx<T>) * M, sc = scatter_lds_bytes<T>(N, 256);
-    return lds_align(size_t(3) * N * sizeof(T)) + (fft > sc ? fft : sc);
+    const size_t fft = scatter_fft_bytes<T, M>(), sc = scatter_lds_bytes<T>(N, 256);
+    const size_t region = fft > sc ? fft : sc;
+    return scatter_g_in_region<T, M>(N) ? region : lds_align(size_t(3) * N * sizeof(T)) + region;
 }
 
 // spectrum value of channel ch at (kx, ky), kx in [0, M/2], ky in [0, M)
@@ -419,8 +432,10 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
     constexpr int H = M / 2 + 1;
     const int N = p.n, j = xcd_unit(blockIdx.x, N);
     if (j < 0) return;
-    T* g = reinterpret_cast<T*>(smem);
-    char* shared_area = smem + lds_align(size_t(3) * N * sizeof(T));
+    const bool g_in = scatter_g_in_region<T, M>(N);
+    char* shared_area = smem + (g_in ? 0 : lds_align(size_t(3) * N * sizeof(T)));
+    const ScatterLds<T> sl = scatter_lds<T>(shared_area, N, 256);
+    T* g = g_in ? sl.first_val : reinterpret_cast<T*>(smem);
     cx<T>* tw = reinterpret_cast<cx<T>*>(shared_area);     // after the sampling
     cx<T>* lines = tw + M;
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
@@ -428,7 +443,7 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
     if constexpr (M != 512 || sizeof(T) != 4) twr.load(plan, p, tid);
     // SORTED: the signal in cell order, from s when given, else the problem's residual in work
     const vec2<T>* ys = (SORTED && s) ? reinterpret_cast<const vec2<T>*>(s) : at<vec2<T>>(work, p.w_res);
-    scatter_row<T, SORTED, 256>(g, scatter_lds<T>(shared_area, N, 256), N, j, at<int>(plan, p.o_binstart),
+    scatter_row<T, SORTED, 256>(g, sl, N, j, at<int>(plan, p.o_binstart),
                                 at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), ys,
                                 s, tid, p.chan == 1);
     if constexpr (M == 512 && sizeof(T) == 4) {   // register-resident transforms (float32)

@@ -210,21 +210,24 @@ template <typename T> struct ScatterLds {
 
 __host__ __device__ constexpr size_t lds_align(size_t b) { return (b + 15) / 16 * 16; }
 
+// byte offset of first_val in the region (the sums K and the keys come first)
+template <typename T>
+__host__ __device__ constexpr size_t scatter_lds_first_val(int N, int NT) {
+    return lds_align(size_t(2) * (N - 1) * 6 * sizeof(T)) + lds_align(size_t(2) * NT * sizeof(short));
+}
+
 template <typename T>
 __host__ __device__ constexpr size_t scatter_lds_bytes(int N, int NT) {
-    return lds_align(size_t(2) * (N - 1) * 6 * sizeof(T)) + lds_align(size_t(2) * NT * sizeof(short)) +
-           lds_align(size_t(NT) * 6 * sizeof(T));
+    return scatter_lds_first_val<T>(N, NT) + lds_align(size_t(NT) * 6 * sizeof(T));
 }
 
 template <typename T>
 __device__ __forceinline__ ScatterLds<T> scatter_lds(char* base, int N, int NT) {
     ScatterLds<T> v;
     v.K = reinterpret_cast<T*>(base);
-    base += lds_align(size_t(2) * (N - 1) * 6 * sizeof(T));
-    v.first_key = reinterpret_cast<short*>(base);
+    v.first_key = reinterpret_cast<short*>(base + lds_align(size_t(2) * (N - 1) * 6 * sizeof(T)));
     v.last_key = v.first_key + NT;
-    base += lds_align(size_t(2) * NT * sizeof(short));
-    v.first_val = reinterpret_cast<T*>(base);
+    v.first_val = reinterpret_cast<T*>(base + scatter_lds_first_val<T>(N, NT));
     return v;
 }
 
