@@ -10,7 +10,8 @@ s = A c followed by c' = A^T s, with every input resident in device memory.
 shape are processed per call: a step is one call of the library's pair entry
 (s = A c, then A^T s, for every problem of the batch), and exactly `--steps`
 steps are timed after `--warmup` untimed ones.  The library splits such a
-batch into four problem ranges on side streams, and each range's transpose
+batch into problem ranges on side streams (two at 64 problems, four below 48),
+and each range's transpose
 follows its own forward with no join in between, as inside the library's
 iteration.  The same pairs as a forward call then a transpose call are
 reported under "separate_calls", the single-problem rate under

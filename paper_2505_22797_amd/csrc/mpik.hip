@@ -953,12 +953,16 @@ void release_streams(mpi_plan* pl) {
 
 // Side streams (default priority) and fork/join events for batches with more
 // than one independent part.  A batch of at least 16 problems with one or two
-// FFT sizes splits each size group into 4 or 2 problem ranges: kernels of
-// different ranges overlap, filling each other's ramp-up and drain between
-// dependent stages.
+// FFT sizes splits each size group into problem ranges: kernels of different
+// ranges overlap, filling each other's ramp-up and drain between dependent
+// stages.  One size group: four ranges below 48 problems, two from 48 on
+// (measured at 16, 32 and 64 headline problems: four ranges are best at 16
+// and 32, two at 64, and ranges queued one after another on a shared stream
+// lose the overlap); two size groups: two ranges each.
 int create_streams(mpi_plan* pl) {
     const int groups = __builtin_popcount(pl->fft_m_mask);
-    pl->chunks = (pl->count >= 16 && groups == 1) ? 4 : (pl->count >= 16 && groups == 2) ? 2 : 1;
+    pl->chunks = (pl->count >= 16 && groups == 1) ? (pl->count >= 48 ? 2 : 4)
+                                                   : (pl->count >= 16 && groups == 2) ? 2 : 1;
     if (groups * pl->chunks + (pl->any_direct ? 1 : 0) <= 1) {
         pl->chunks = 1;
         return MPI_OK;

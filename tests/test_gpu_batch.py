@@ -198,6 +198,8 @@ CHUNKED = {
     "one_size": [(24 + (i % 3), 5 + i % 4, 1500 + 100 * i, "fft") for i in range(17)],
     # 18 problems, two FFT sizes and two direct problems: two ranges per size, the direct path beside them
     "two_sizes": [(24, 7, 2000, "fft"), (48, 31, 5000, "fft")] * 8 + [(20, 4, 1200, "direct"), (28, 6, 1800, "direct")],
+    # 49 problems of one FFT size: two problem ranges of uneven length (24 and 25)
+    "many_one_size": [(20 + (i % 5), 4 + i % 3, 600 + 20 * i, "fft") for i in range(49)],
 }
 
 
