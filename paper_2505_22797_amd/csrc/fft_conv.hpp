@@ -230,6 +230,42 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
         TwiddleRegs<T, M, 3 * kWave> twr;
         twr.load(plan, p, tid);
         const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(kx) * N;
+        if constexpr (M == 512 && sizeof(T) == 4) {
+            // register-resident transforms, twiddles from the LDS table, each
+            // wave's line its exchange buffer
+            static_assert(XbLayout<T>::kSlots <= M, "exchange exceeds the line");
+            cx<T> x[8];
+            if (wave == 0) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int i = lane + m * kWave;
+                    x[m] = (i < N) ? t1[i] : cx<T>{T(0), T(0)};
+                }
+            }
+            twr.store(sm.tw, tid);
+            __syncthreads();
+            Fft512TwLds<T> tl;
+            tl.init(sm.tw, lane);
+            if (wave == 0) {
+                fft512_regs<T, false>(x, sm.line[0], tl, lane);
+#pragma unroll
+                for (int m = 0; m < 8; ++m) sm.c[lane + m * kWave] = x[m];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int ky = lane + m * kWave;
+                x[m] = cscale(sm.c[ky], spec_at<T, M>(spec, wave, kx, ky));
+            }
+            fft512_regs<T, true>(x, sm.line[wave], tl, lane);
+            cx<T>* out = t2 + int64_t(wave) * N * H;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int j = lane + m * kWave;
+                if (j < N) out[int64_t(j) * H + kx] = x[m];
+            }
+            return;
+        }
         constexpr int PC = (M + 3 * kWave - 1) / (3 * kWave);
         cx<T> x[PC];
 #pragma unroll
@@ -541,6 +577,34 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         }
         twr.store(sm.tw, tid);
         __syncthreads();
+        if constexpr (M == 512 && sizeof(T) == 4) {
+            // register-resident transforms, twiddles from the LDS table, each
+            // wave's line its exchange buffer
+            static_assert(XbLayout<T>::kSlots <= M, "exchange exceeds the line");
+            Fft512TwLds<T> tl;
+            tl.init(sm.tw, lane);
+            fft512_regs<T, false>(x, sm.line[wave], tl, lane);
+            wave_sync();
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int ky = lane + m * kWave;
+                sm.line[wave][ky] = cscale(x[m], spec_at<T, M>(spec, wave, kx, ky));
+            }
+            __syncthreads();
+            if (wave != 0) return;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int ky = lane + m * kWave;
+                x[m] = cadd(cadd(sm.line[0][ky], sm.line[1][ky]), sm.line[2][ky]);
+            }
+            fft512_regs<T, true>(x, sm.line[0], tl, lane);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int j = lane + m * kWave;
+                if (j < N) t2[int64_t(j) * H + kx] = x[m];
+            }
+            return;
+        }
         cx<T>* line = sm.line[wave];
 #pragma unroll
         for (int m = 0; m < PL; ++m) line[lane + m * kWave] = x[m];
