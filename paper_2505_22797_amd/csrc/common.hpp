@@ -236,8 +236,8 @@ __device__ __forceinline__ void fft_wave(cx<T>* line, const cx<T>* __restrict__ 
 //    bank pairs (32 four-byte banks) and every 32-lane group 32 distinct
 //    ones (64 banks); a plain padding of one slot in nine leaves 4-way
 //    conflicts in the read and the second write.  Linearity splits every
-//    slot into a per-lane part (computed once, in Fft512Tw) XOR a constant
-//    per register.
+//    slot into a per-lane part (computed once per kernel with the twiddles)
+//    XOR a constant per register.
 //  * float64 (16-byte elements): slot = i + i/8 (one pad slot in nine), which
 //    keeps every 8-lane group on 8 distinct four-bank groups.
 // kXbStride<T> is the distance between the waves' buffers, chosen so that the
