@@ -626,8 +626,18 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         const bool active = kx < H;     // inactive waves stay for the work-group barriers
         // each wave's exchange buffer, also the staging of its rows for the stores
         cx<T>(*xb)[kXbStride<T>] = reinterpret_cast<cx<T>(*)[kXbStride<T>]>(smem);
-        Fft512Tw<T> tw;
-        tw.load(at<cx<T>>(plan, p.o_tw), lane);
+        // twiddles from a table staged after the exchange buffers (registers
+        // for them measured slower here)
+        cx<T>* tws = reinterpret_cast<cx<T>*>(smem) + 4 * kXbStride<T>;
+        static_assert((4 * kXbStride<T> + M) * sizeof(cx<T>) <= sizeof(ColSmem<T, M>), "twiddle table exceeds the LDS");
+        {
+            TwiddleRegs<T, M, 4 * kWave> twr;
+            twr.load(plan, p, tid);
+            twr.store(tws, tid);
+        }
+        __syncthreads();
+        Fft512TwLds<T> tw;
+        tw.init(tws, lane);
         const T* spec_dh = DUAL ? at<T>(plan, p.o_spec_dh) : nullptr;
         cx<T> acc[8], acc2[DUAL ? 8 : 1], v[8];
         if (active) {
