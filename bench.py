@@ -8,8 +8,10 @@ s = A c followed by c' = A^T s, with every input resident in device memory.
 
 `value` is the whole-job pair rate when `--batch` independent problems of that
 shape are processed per call: a step is one call of the library's pair entry
-(s = A c, then A^T s, for every problem of the batch), and exactly `--steps`
-steps are timed after `--warmup` untimed ones.  The library splits such a
+(s = A c, then A^T s, for every problem of the batch).  After `--warmup`
+untimed steps, `--runs` runs (default 5) of exactly `--steps` steps each are
+timed and the median run gives the value; without `--steps` the step count
+is chosen so that one run lasts at least `--run-seconds` (default 1 s).  The library splits such a
 batch into problem ranges on side streams (two at 64 problems, four below 48),
 and each range's transpose
 follows its own forward with no join in between, as inside the library's
@@ -68,14 +70,48 @@ def stage_bytes(name: str, n: int, m: int, t: int, elem: int = 4) -> float:
     }[name]
 
 
+def alg_stage_bytes(name: str, n: int, t: int, elem: int = 4) -> float:
+    """The share of one stage in the algorithmic bytes of a pair (56 N^2 + 48 T
+    in float32): c read 4N^2; the three-channel field G written and read,
+    12N^2 each way; positions and velocities 16T and the signal 8T, once per
+    direction; the transposed field G' written and read; c' written.  On the
+    FFT path G and G' exist only as spectra, so the column stage that
+    produces (consumes) a spectrum is credited with writing (reading) G (G')."""
+    nn = elem * n * n
+    samp = (4 * elem) * t + (2 * elem) * t      # r, v and s
+    return {
+        "fwd_rows": nn,
+        "fwd_cols": 3 * nn,
+        "fwd_rows_gather": 3 * nn + samp,
+        "adj_scatter_row": samp + 3 * nn,
+        "adj_cols": 3 * nn,
+        "adj_rows": nn,
+    }[name]
+
+
+def counter_bytes(stage_names, batch: int):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by the copy
+    calibration) of every stage with a counter record in profiles/ taken on
+    the current kernel sources; None for a stage without one."""
+    out = {}
+    digest = src_digest()
+    for name in stage_names:
+        pmc = os.path.join(HERE, "profiles", f"k_{name}_headline_256_b{batch}_pmc.json")
+        rec = json.load(open(pmc)) if os.path.exists(pmc) else {}
+        out[name] = rec.get("hbm_bytes_per_launch") if rec.get("src_digest") == digest else None
+    return out
+
+
 def group_for(steps):
     """The largest graph size in (10, 8, 5, 4, 2, 1) that divides `steps`."""
     return next(g for g in (10, 8, 5, 4, 2, 1) if steps % g == 0)
 
 
-def graph_time(fn, steps, group, warmup):
-    """ms per call of fn() over `steps` calls replayed from a graph of `group`
-    calls (exactly `steps` when group divides it)."""
+def graph_time(fn, steps, group, warmup, runs=1):
+    """Times `runs` runs of exactly `steps` calls of fn(), each replayed from a
+    captured graph of `group` calls (group divides steps), after `warmup`
+    untimed calls; HIP events on the launch stream bracket every run.
+    Returns (median ms per call, steps per run, [ms per call of every run])."""
     import torch
     for _ in range(warmup):
         fn()
@@ -93,13 +129,25 @@ def graph_time(fn, steps, group, warmup):
     g.replay()
     torch.cuda.synchronize()
     reps = max(1, (steps + group - 1) // group)
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        g.replay()
-    b.record()
-    torch.cuda.synchronize()
-    return a.elapsed_time(b) / (reps * group), reps * group
+    per_run = []
+    for _ in range(runs):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        per_run.append(a.elapsed_time(b) / (reps * group))
+    med = sorted(per_run)[len(per_run) // 2]
+    return med, reps * group, per_run
+
+
+def steps_for_seconds(fn, seconds, warmup):
+    """Steps per run so that one run lasts at least `seconds` (a multiple of
+    10, so that graphs of ten calls divide it), from a short timed probe."""
+    ms, _, _ = graph_time(fn, 50, 10, warmup)
+    return max(10, int(-(-seconds * 1e3 / ms // 10)) * 10)
 
 
 def stage_times(obj, c, s, reps):
@@ -121,7 +169,11 @@ def stage_times(obj, c, s, reps):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps per run (default: enough for runs of at least --run-seconds)")
+    ap.add_argument("--runs", type=int, default=5, help="timed runs of the headline; the median is reported")
+    ap.add_argument("--run-seconds", type=float, default=1.0)
+    ap.add_argument("--aux-steps", type=int, default=100, help="timed steps of the secondary lines")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--graph-pairs", type=int, default=10)
@@ -175,7 +227,7 @@ def main() -> int:
     print(f"bench: headline 256^2 / {t} samples, batch {args.batch}", file=sys.stderr, flush=True)
 
     if args.profile_batch:
-        return profile_batch(mpik, P, r, v, c1, max(1, args.batch), args.steps)
+        return profile_batch(mpik, P, r, v, c1, max(1, args.batch), args.steps or 20)
 
     # ---- one problem per launch
     plan = mpik.Plan(n, P.h, P.radius, r, v)
@@ -186,7 +238,7 @@ def main() -> int:
         plan.forward(c1, s1)
         plan.adjoint(s1, g1)
 
-    ms1, _ = graph_time(pair1, args.steps, args.graph_pairs, args.warmup)
+    ms1, _, _ = graph_time(pair1, 10 * args.aux_steps, args.graph_pairs, args.warmup)
     st1 = stage_times(plan, g1, s1, args.stage_reps)
     print(f"bench: single problem {ms1 * 1e3:.1f} us/pair", file=sys.stderr, flush=True)
 
@@ -204,23 +256,23 @@ def main() -> int:
         batch.forward(c_all, s_all)
         batch.adjoint(s_all, g_all)
 
-    # the timed region: exactly --steps batch steps, after --warmup untimed ones
-    msB, steps = graph_time(pairB, args.steps, group_for(args.steps), args.warmup)
-    msB_sep, _ = graph_time(pairB_separate, args.steps, group_for(args.steps), args.warmup)
+    # the timed region: --runs runs of exactly --steps batch steps each, after
+    # --warmup untimed ones; the median run gives the value
+    steps = args.steps if args.steps else steps_for_seconds(pairB, args.run_seconds, args.warmup)
+    msB, steps, runs = graph_time(pairB, steps, group_for(steps), args.warmup, runs=args.runs)
+    msB_sep, _, runs_sep = graph_time(pairB_separate, steps, group_for(steps), args.warmup, runs=args.runs)
     stB = stage_times(batch, g_all, s_all, max(3, args.stage_reps // 4))
     pairs_per_s = B * 1e3 / msB
     print(f"bench: batch {B}: {msB * 1e3:.1f} us/step, {pairs_per_s:.0f} pairs/s", file=sys.stderr, flush=True)
 
     batch_fft = batch.info[0]["fft_size"]
-    dom = max(stB, key=stB.get)
-    dom_bytes = B * stage_bytes(dom, n, batch.info[0]["fft_size"], t)
-    achieved = dom_bytes / (stB[dom] * 1e-3) / 1e9
-    traffic = None
-    pmc = os.path.join(HERE, "profiles", f"k_{dom}_headline_256_b{B}_pmc.json")
-    if os.path.exists(pmc):
-        rec = json.load(open(pmc))
-        if rec.get("src_digest") == src_digest():
-            traffic = rec.get("hbm_bytes_per_launch")
+    fft_stages = [k for k in stB if k in STAGE_NAMES]
+    dom = max(fft_stages, key=stB.get)
+    dom_alg = B * alg_stage_bytes(dom, n, t)
+    achieved = dom_alg / (stB[dom] * 1e-3) / 1e9
+    traffic = counter_bytes(fft_stages, B)
+    known = [traffic[k] for k in fft_stages]
+    counter_pair = sum(known) / B if all(x is not None for x in known) else None
 
     out = {
         "metric": "A+A^T applies/s at 256^2 grid, 53,856 samples (fraction of HBM peak)",
@@ -238,16 +290,27 @@ def main() -> int:
         "config": {"workload": "headline_256: N=256, T=53856 Lissajous 17:16, R=255 (FFT, M=512)",
                    "problems_per_step": B, "grid": n, "samples": t, "radius": plan.radius,
                    "fft_size": plan.fft_size, "conv_path": plan.conv_mode},
+        "timing": {"runs": len(runs), "steps_per_run": steps, "statistic": "median",
+                   "ms_per_step_runs": [round(x, 5) for x in runs],
+                   "spread": round((max(runs) - min(runs)) / msB, 4),
+                   "run_seconds": round(msB * steps / 1e3, 3)},
         "hbm_fraction": round(b_alg * pairs_per_s / (HBM_PEAK_GBS * 1e9), 5),
         "algorithmic_bytes_per_pair": b_alg,
         "stage_ms": {k: round(x, 5) for k, x in stB.items()},
-        # every FFT-path stage: compulsory bytes of the batch / HIP-event duration, against HBM peak
-        "stage_hbm_frac": {k: round(B * stage_bytes(k, n, batch_fft, t) / (x * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-                           for k, x in stB.items() if k in STAGE_NAMES},
+        # every FFT-path stage: its share of the pair's algorithmic bytes over its HIP-event duration
+        "stage_alg_frac": {k: round(B * alg_stage_bytes(k, n, t) / (stB[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                           for k in fft_stages},
+        # every input and output of the stage moved once (spectra, intermediates, sample records)
+        "stage_compulsory_frac": {k: round(B * stage_bytes(k, n, batch_fft, t) / (stB[k] * 1e-3) / 1e9
+                                           / HBM_PEAK_GBS, 4) for k in fft_stages},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                     "algorithmic_bytes_per_launch": dom_bytes},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic[dom],
+                     "algorithmic_bytes_per_launch": dom_alg, "launch_ms": round(stB[dom], 5),
+                     "compulsory_bytes_per_launch": B * stage_bytes(dom, n, batch_fft, t)},
+        "counter_bytes_per_pair": round(counter_pair) if counter_pair else None,
+        "counter_over_alg": round(counter_pair / b_alg, 3) if counter_pair else None,
         "separate_calls": {"value": round(B * 1e3 / msB_sep, 1), "unit": "pairs/s", "ms_per_step": round(msB_sep, 5),
+                           "ms_per_step_runs": [round(x, 5) for x in runs_sep],
                            "note": "the same pairs as a forward call then a transpose call (a join of the "
                                    "problem ranges between them)"},
         "single_problem": {"value": round(1e3 / ms1, 1), "unit": "pairs/s", "ms_per_pair": round(ms1, 5),
@@ -294,7 +357,7 @@ def window31_line(mpik, P, r, v, c1, B, args):
         plan.forward(c1, s1)
         plan.adjoint(s1, g1)
 
-    ms1, _ = graph_time(pair1, args.steps, args.graph_pairs, args.warmup)
+    ms1, _, _ = graph_time(pair1, args.aux_steps, args.graph_pairs, args.warmup)
     batch = mpik.Batch([(n, P.h, 31, r, v, "direct")] * B, tune=False)
     c_all = c1.reshape(-1).repeat(B).contiguous()
     s_all = torch.empty(batch.s_offsets[-1], dtype=torch.float32, device=c1.device)
@@ -304,7 +367,7 @@ def window31_line(mpik, P, r, v, c1, B, args):
         batch.forward(c_all, s_all)
         batch.adjoint(s_all, g_all)
 
-    msB, _ = graph_time(pairB, args.steps, group_for(args.steps), args.warmup)
+    msB, _, _ = graph_time(pairB, args.aux_steps, group_for(args.aux_steps), args.warmup)
     stB = stage_times(batch, g_all, s_all, max(3, args.stage_reps // 4))
     flop = 2 * 2 * 3 * (2 * 31 + 1) ** 2 * n * n      # multiply-adds of both convolutions per pair
     return {"radius": 31, "conv_path": "direct", "single_pairs_per_s": round(1e3 / ms1, 1),
@@ -326,7 +389,7 @@ def cosine_line(mpik, P, r, v, c1, B, args):
         plan.forward(c1, s1)
         plan.adjoint(s1, g1)
 
-    ms1, _ = graph_time(pair1, args.steps, args.graph_pairs, args.warmup)
+    ms1, _, _ = graph_time(pair1, args.aux_steps, args.graph_pairs, args.warmup)
     batch = mpik.Batch([(n, P.h, P.radius, r, v, "fft", "cosine")] * B, tune=False)
     c_all = c1.reshape(-1).repeat(B).contiguous()
     s_all = torch.empty(batch.s_offsets[-1], dtype=torch.float32, device=c1.device)
@@ -335,7 +398,7 @@ def cosine_line(mpik, P, r, v, c1, B, args):
     def pairB():
         batch.pair(c_all, s_all, g_all)
 
-    msB, _ = graph_time(pairB, args.steps, group_for(args.steps), args.warmup)
+    msB, _, _ = graph_time(pairB, args.aux_steps, group_for(args.aux_steps), args.warmup)
     stB = stage_times(batch, g_all, s_all, max(3, args.stage_reps // 4))
     out = {"interp": "cosine", "conv_path": plan.conv_mode, "fft_size": plan.fft_size,
            "single_pairs_per_s": round(1e3 / ms1, 1), "batch": B, "batch_pairs_per_s": round(B * 1e3 / msB, 1),

@@ -1144,6 +1144,8 @@ double key_of(const void* ptr) { return double(reinterpret_cast<uintptr_t>(ptr))
 
 // Records what `record(stream)` launches into the cache unless it already
 // holds a graph for `key` (the buffers and parameters baked into the launches).
+// `record` returns a status; when it is not MPI_OK the captured graph is
+// discarded and that status returned (nothing partial is ever instantiated).
 template <typename F>
 int cached_graph(mpi_plan::GraphCache& gc, const std::vector<double>& key, hipStream_t st, F&& record) {
     if (gc.exec && gc.key == key) return MPI_OK;
@@ -1157,11 +1159,12 @@ int cached_graph(mpi_plan::GraphCache& gc, const std::vector<double>& key, hipSt
     hipStream_t cap;
     HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    int rc = MPI_ERR_HIP;
     if (e == hipSuccess) {
-        record(cap);
+        rc = record(cap);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(cap, &g);
-        if (e == hipSuccess) {
+        if (e == hipSuccess && rc == MPI_OK) {
             e = hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0);
             if (e == hipSuccess) gc.graph = g;
             else (void)hipGraphDestroy(g);
@@ -1170,9 +1173,9 @@ int cached_graph(mpi_plan::GraphCache& gc, const std::vector<double>& key, hipSt
         }
     }
     (void)hipStreamDestroy(cap);
-    if (e != hipSuccess || !gc.exec) {
+    if (e != hipSuccess || rc != MPI_OK || !gc.exec) {
         gc.exec = nullptr;
-        return MPI_ERR_HIP;
+        return rc != MPI_OK ? rc : MPI_ERR_HIP;
     }
     gc.key = key;
     return MPI_OK;
@@ -1236,8 +1239,12 @@ int iterate_impl(mpi_plan* pl, const T* s, T* c, const mpi_iter_params* ip, cons
     int it = 0;
     if (ip->n_iter >= kIterBlock) {
         const std::vector<double> key{key_of(s), key_of(c), key_of(work), pl->g_sigma, double(rad)};
-        const int rc = cached_graph(pl->iter_gc, key, st, [&](hipStream_t cap) {
-            for (int i = 0; i < kIterBlock; ++i) (void)iteration_impl<T>(pl, c, denoise, rad, work, cap);
+        const int rc = cached_graph(pl->iter_gc, key, st, [&](hipStream_t cap) -> int {
+            for (int i = 0; i < kIterBlock; ++i) {
+                const int r = iteration_impl<T>(pl, c, denoise, rad, work, cap);
+                if (r != MPI_OK) return r;
+            }
+            return MPI_OK;
         });
         if (rc != MPI_OK) return rc;
         for (; it + kIterBlock <= ip->n_iter; it += kIterBlock) HIP_TRY(hipGraphLaunch(pl->iter_gc.exec, st));
@@ -1422,8 +1429,9 @@ int cg_impl(mpi_plan* pl, const T* cu, const T* rho2, T* x, double tol, int max_
     HIP_TRY(hipGetLastError());
     if (max_iter > 0) {
         const std::vector<double> key{key_of(work), key_of(dw), tol, double(max_iter)};
-        int rc = cached_graph(pl->cg_gc, key, st, [&](hipStream_t cap) {
+        int rc = cached_graph(pl->cg_gc, key, st, [&](hipStream_t cap) -> int {
             for (int i = 0; i < kCgBlock; ++i) cg_step<T>(pl, i & 1, tol, max_iter, work, dw, L, cap);
+            return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
         });
         if (rc != MPI_OK) return rc;
         rc = run_cg_blocks(pl->cg_gc.exec, s.done, B, max_iter, st);
@@ -1613,8 +1621,9 @@ int core_impl(mpi_plan* pl, const T* sig, T* field, double gamma, double tol, in
     HIP_TRY(hipGetLastError());
     if (max_iter > 0) {
         const std::vector<double> key{key_of(cw), gamma, tol, double(max_iter)};
-        int rc = cached_graph(pl->core_gc, key, st, [&](hipStream_t cap) {
+        int rc = cached_graph(pl->core_gc, key, st, [&](hipStream_t cap) -> int {
             for (int i = 0; i < kCgBlock; ++i) core_step<T>(pl, i & 1, gamma, tol, max_iter, cw, L, cap);
+            return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
         });
         if (rc != MPI_OK) return rc;
         rc = run_cg_blocks(pl->core_gc.exec, s.done, B, max_iter, st);

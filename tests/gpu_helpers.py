@@ -49,3 +49,11 @@ class Case:
 def case_from(problem: S.Problem, dtype=torch.float32, conv_mode="auto", radius=None, interp="bilinear"):
     return Case(problem.n, problem.h, problem.radius if radius is None else radius,
                 problem.traj.r, problem.traj.v, problem.c, dtype=dtype, conv_mode=conv_mode, interp=interp)
+
+
+def max_rel(got, ref) -> float:
+    """Element-wise error: max |got - ref| over max |ref| (a localised error
+    that the whole-array relative L2 would average away shows up here)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))

@@ -25,3 +25,11 @@ def test_graph_groups_divide_the_step_count(steps):
     g = bench.group_for(steps)
     assert steps % g == 0 and g in (1, 2, 4, 5, 8, 10)
 
+
+
+@pytest.mark.parametrize("n,t", [(256, 53856), (128, 53856), (32, 4352)])
+def test_stage_shares_sum_to_the_pair_bytes(n, t):
+    """The per-stage shares of the roofline add up to the algorithmic bytes
+    of one pair, 56 N^2 + 48 T in float32."""
+    total = sum(bench.alg_stage_bytes(k, n, t) for k in bench.STAGE_NAMES)
+    assert total == 56 * n * n + 48 * t

@@ -13,7 +13,7 @@ import torch
 import oracle as O
 from paper_2505_22797_amd import mpik
 from paper_2505_22797_amd import synth as S
-from gpu_helpers import dev, rel_l2, rounded
+from gpu_helpers import max_rel, dev, rel_l2, rounded
 
 pytestmark = pytest.mark.gpu
 
@@ -54,7 +54,9 @@ def test_largest_fft_size(dtype, n, R):
     M = O.Model(n, h, R, r, v)
     tol = 1e-5 if dtype == torch.float32 else 1e-12
     s = plan.forward(dev(c, dtype)).double().cpu().numpy()
-    assert rel_l2(s, M.forward(c)) <= tol
+    s_ref = M.forward(c)
+    assert rel_l2(s, s_ref) <= tol and max_rel(s, s_ref) <= tol
     y = rounded(np.random.default_rng(4).standard_normal((t, 2)), dtype)
     g = plan.adjoint(dev(y, dtype)).double().cpu().numpy()
-    assert rel_l2(g, M.adjoint(y)) <= tol
+    g_ref = M.adjoint(y)
+    assert rel_l2(g, g_ref) <= tol and max_rel(g, g_ref) <= tol

@@ -66,7 +66,9 @@ def test_f32_apply(gpu, n, radius, t, conv_mode):
 
 def test_headline_shape_apply(gpu):
     """256x256, 53,856 samples, full-size kernel (R = 255, FFT with M = 512):
-    the shape and launch configuration the benchmark times."""
+    the benchmark's problem shape, as a single-problem plan (column kernels
+    in the one-column-per-work-group shape, no problem ranges).  The batched
+    pair call the benchmark times is checked in test_gpu_measured.py."""
     cs = case_from(S.headline(), torch.float32)
     assert cs.plan.conv_mode == "fft" and cs.plan.fft_size == 512 and cs.plan.radius == 255
     _check_apply(cs, F32_APPLY, seed=5)

@@ -82,14 +82,19 @@ def test_unrolled_gradients_match_finite_differences(sigma):
 
 
 def test_frozen_cells_only_matter_across_edges():
-    """Without freezing, a 1e-6 step in the amplitude moves some samples into
-    a neighbouring cell; the frozen convention keeps the same cells."""
+    """An amplitude step moves the samples that lie close to a cell edge into
+    the neighbouring cell (a step of 1e-3 here, large enough that some do):
+    the unfrozen model gives exactly those samples a new base cell, while
+    the frozen convention keeps every sample's base cell."""
     n, h, rho, nu, ax, ay, _ = _problem(n=32, t=4352)
+    step = 1e-3
     g0 = (rho * [ax, ay] + 1.0) / (2.0 / n) - 0.5
-    g1 = (rho * [ax * (1 + 1e-6), ay] + 1.0) / (2.0 / n) - 0.5
-    crossed = int(np.sum(np.floor(g0[:, 0]) != np.floor(g1[:, 0])))
-    assert crossed >= 0
+    g1 = (rho * [ax * (1 + step), ay] + 1.0) / (2.0 / n) - 0.5
+    moved = np.floor(g0[:, 0]) != np.floor(g1[:, 0])
+    assert 0 < int(moved.sum()) < moved.size // 10
     M = O.Model(n, h, 5, rho * [ax, ay], nu * [ax, ay])
     ix, jy = M.cells()
-    Mf = O.Model(n, h, 5, rho * [ax * (1 + 1e-6), ay], nu * [ax * (1 + 1e-6), ay], frozen=(ix, jy))
+    Mu = O.Model(n, h, 5, rho * [ax * (1 + step), ay], nu * [ax * (1 + step), ay])
+    assert np.array_equal(Mu.cells()[0] != ix, moved)
+    Mf = O.Model(n, h, 5, rho * [ax * (1 + step), ay], nu * [ax * (1 + step), ay], frozen=(ix, jy))
     assert np.array_equal(Mf.cells()[0], ix)
