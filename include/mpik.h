@@ -205,6 +205,22 @@ int mpi_batch_adjoint(const mpi_plan* plan, const void* s_all, void* c_all,
  * Enqueued on `stream`. */
 int mpi_batch_pair(const mpi_plan* plan, const void* c_all, void* s_all, void* g_all,
                    void* work, size_t work_bytes, hipStream_t stream);
+/* Allocation-free pair, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): mpi_batch_pair with the work memory taken from a fixed array
+ * that the library's code object holds on every GPU it is loaded on (one
+ * array per GPU, MPI_NOALLOC_SCRATCH_BYTES bytes, kept until the process
+ * ends; the plan records its GPU's copy at the build).  The caller still
+ * passes the inputs and outputs, with mpi_batch_pair's layouts and rules.
+ * Plans whose work memory (mpi_batch_bytes) exceeds the array return
+ * MPI_ERR_WORKSPACE before anything is enqueued.  Nothing is allocated:
+ * no hipMalloc, hipFree or allocating library call.  Every call on one GPU
+ * shares that GPU's array, so calls that overlap in time on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller;
+ * nothing in the array needs to start at zero.  Enqueued on `stream`. */
+#define MPI_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mpi_batch_pair_noalloc(const mpi_plan* plan, const void* c_all, void* s_all, void* g_all,
+                           hipStream_t stream);
 /* c_b <- D(c_b - taus[b] A_b^T (A_b c_b - s_b)), params->n_iter times for all
  * problems at once (params->tau is ignored; taus is a host array of count). */
 int mpi_batch_iterate(const mpi_plan* plan, const void* s_all, void* c_all,

@@ -7,7 +7,9 @@
 // sit contiguously at the start of the plan memory; every stage is one launch
 // over all problems (grid.y or grid.z indexes the problem, work-groups beyond
 // a problem's own extent exit at once).  A single-problem plan is a batch of
-// one.  The library never allocates device memory.
+// one.  The library never allocates device memory; the one fixed array it
+// holds (the work memory of the allocation-free pair entry) is part of its
+// code object, placed on a GPU when the library is loaded there.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -282,8 +284,20 @@ hipError_t allow_smem(K kernel, size_t bytes) {
 
 }  // namespace
 
+// Work memory of mpi_batch_pair_noalloc: a fixed array in the code object's
+// device memory, one copy on every GPU that loads the library, held until the
+// process ends and shared by every call on that GPU.  In host code the name
+// `scratch` stands for a host-side shadow, not for a device address: the
+// address of each GPU's copy comes from hipGetSymbolAddress, once per device
+// with that device current (scratch_address, at the first plan build there).
+constexpr size_t kNoAllocScratchBytes = size_t(MPI_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 struct mpi_plan {
     BatchLayout L;
+    int device = -1;             // the GPU current at the build
+    void* noalloc_work = nullptr;    // that GPU's copy of `scratch` (device address)
+    int noalloc_rc = MPI_OK;     // status of resolving it
     int count = 1;
     int dtype = MPI_F32;
     char* plan = nullptr;
@@ -333,6 +347,25 @@ namespace {
         hipError_t e_ = (expr);                     \
         if (e_ != hipSuccess) return MPI_ERR_HIP;   \
     } while (0)
+
+// Device address of the current GPU's copy of `scratch`, resolved once per
+// device (hipGetSymbolAddress with that device current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+int scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return MPI_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return MPI_ERR_HIP;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return MPI_OK;
+}
 
 // Launch extents and dynamic shared memory over the batch.
 void finalize_extents(mpi_plan* pl) {
@@ -1008,6 +1041,10 @@ int build_common(const mpi_problem* probs, int count, void* plan_mem, size_t pla
         delete pl;
         return rc;
     }
+    // the allocation-free pair's work memory on this GPU; a failure here only
+    // disables that entry point (it returns the status)
+    if (hipGetDevice(&pl->device) != hipSuccess) pl->device = -1;
+    pl->noalloc_rc = scratch_address(pl->device, &pl->noalloc_work);
     *out = pl;
     return MPI_OK;
 }
@@ -1748,6 +1785,13 @@ int mpi_batch_pair(const mpi_plan* plan, const void* c, void* s, void* g, void* 
                                    static_cast<double*>(g), w, stream)
                : pair_impl<float>(plan, static_cast<const float*>(c), static_cast<float*>(s), static_cast<float*>(g),
                                   w, stream);
+}
+
+int mpi_batch_pair_noalloc(const mpi_plan* plan, const void* c, void* s, void* g, hipStream_t stream) {
+    if (!plan) return MPI_ERR_ARG;
+    if (plan->L.work_bytes > kNoAllocScratchBytes) return MPI_ERR_WORKSPACE;
+    if (plan->noalloc_rc != MPI_OK) return plan->noalloc_rc;
+    return mpi_batch_pair(plan, c, s, g, plan->noalloc_work, kNoAllocScratchBytes, stream);
 }
 
 int mpi_batch_adjoint(const mpi_plan* plan, const void* s, void* c, void* work, size_t work_bytes,

@@ -23,7 +23,7 @@ CHANNELS = {"xy": 0, "x": 1}
 
 EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
            "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
-           "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_pair", "mpi_batch_iterate",
+           "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_pair", "mpi_batch_pair_noalloc", "mpi_batch_iterate",
            "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
            "mpi_batch_dot", "mpi_batch_unrolled_vjp_bytes", "mpi_batch_unrolled_vjp",
            "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
@@ -31,6 +31,7 @@ EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "
            "mpi_batch_core_bytes", "mpi_batch_core_stage", "mpi_batch_field_trace", "mpi_velocity_forward_difference",
            "mpi_plan_destroy", "mpi_status_str", "mpi_abi_version")
 MPI_BUILD_TUNE, MPI_BUILD_COL_SPLIT, MPI_BUILD_COL_WAVE, MPI_BUILD_DERIV = 1, 2, 4, 8
+NOALLOC_SCRATCH_BYTES = 64 << 20     # MPI_NOALLOC_SCRATCH_BYTES: the allocation-free pair's work memory
 
 
 class MpiError(RuntimeError):
@@ -86,6 +87,7 @@ def lib() -> ctypes.CDLL:
         L.mpi_batch_forward.argtypes = [vp, vp, vp, vp, sz, vp]
         L.mpi_batch_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
         L.mpi_batch_pair.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+        L.mpi_batch_pair_noalloc.argtypes = [vp, vp, vp, vp, vp]
         L.mpi_batch_iterate.argtypes = [vp, vp, vp, ctypes.POINTER(IterParams), ctypes.POINTER(ctypes.c_double),
                                         vp, sz, vp]
         L.mpi_batch_forward_dh.argtypes = [vp, vp, vp, vp, sz, vp]
@@ -120,8 +122,8 @@ def lib() -> ctypes.CDLL:
         L.mpi_abi_version.argtypes = []
         for name in ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
                      "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
-                     "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_pair", "mpi_batch_iterate",
-                     "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
+                     "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_pair",
+                     "mpi_batch_pair_noalloc", "mpi_batch_iterate", "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
                      "mpi_batch_dot", "mpi_batch_unrolled_vjp_bytes", "mpi_batch_unrolled_vjp",
                      "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_launch",
                      "mpi_batch_deconv_bytes", "mpi_batch_trace_conv", "mpi_batch_cg", "mpi_batch_trim_sigma",
@@ -454,6 +456,17 @@ class Batch:
         self._flat(g_all, self.c_offsets[-1], "g_all")
         _check(lib().mpi_batch_pair(self._h, c_all.data_ptr(), s_all.data_ptr(), g_all.data_ptr(),
                                     self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_batch_pair")
+        return s_all, g_all
+
+    def pair_noalloc(self, c_all, s_all, g_all, stream=None):
+        """As pair(), through the allocation-free entry (mpi_batch_pair_noalloc):
+        the library's fixed per-GPU array serves as the work memory, so the
+        outputs must be given.  Calls overlapping on one GPU race."""
+        self._flat(c_all, self.c_offsets[-1], "c_all")
+        self._flat(s_all, self.s_offsets[-1], "s_all")
+        self._flat(g_all, self.c_offsets[-1], "g_all")
+        _check(lib().mpi_batch_pair_noalloc(self._h, c_all.data_ptr(), s_all.data_ptr(), g_all.data_ptr(),
+                                            _stream(stream)), "mpi_batch_pair_noalloc")
         return s_all, g_all
 
     def iterate(self, s_all, c_all, n_iter, taus, denoise_sigma_px=0.0, denoise_radius=2, use_graph=True,
