@@ -273,6 +273,30 @@ int mpi_batch_denoise(const mpi_plan* plan, const void* u_all, void* c_all, doub
 int mpi_batch_dot(const mpi_plan* plan, const void* a_all, const void* b_all, int space, int comp,
                   double* out, void* work, size_t work_bytes, hipStream_t stream);
 
+/* The amplitudes of a trajectory as parameters (the Lissajous figure of eq.
+ * lissajous, r = (a_x rho_x, a_y rho_y) over unit-amplitude shapes rho, and
+ * v = (a_x nu_x, a_y nu_y)).
+ *
+ * mpi_scale_trajectory: r_k = (ax rho_k,x, ay rho_k,y), v_k = (ax nu_k,x,
+ *   ay nu_k,y) for k < n_samples, each product in float64 rounded once to
+ *   `dtype`; device [T][2] arrays, r and v distinct from each other and from
+ *   rho and nu.  The result feeds the problem descriptor of a plan build.
+ *
+ * mpi_reduce_lissajous: the chain rule from per-sample gradients to the
+ *   amplitudes' for every problem b of the plan:
+ *     g_ax[b] = sum_k g_r,k,x rho_k,x + g_v,k,x nu_k,x,
+ *     g_ay[b] = sum_k g_r,k,y rho_k,y + g_v,k,y nu_k,y,
+ *   with g_r = dL/dr_k and g_v = dL/dv_k (as mpi_batch_traj_vjp or
+ *   mpi_batch_unrolled_vjp give them) and the unit shapes rho, nu, all
+ *   signal-shaped over the batch (time order).  One pass in float64 with a
+ *   fixed order (fixed slices, then fixed trees): bitwise repeatable.  g_ax,
+ *   g_ay: device arrays of count doubles.  Uses the plan's work memory. */
+int mpi_scale_trajectory(const void* rho, const void* nu, int64_t n_samples, double ax, double ay,
+                         int32_t dtype, void* r, void* v, hipStream_t stream);
+int mpi_reduce_lissajous(const mpi_plan* plan, const void* g_r_all, const void* g_v_all, const void* rho_all,
+                         const void* nu_all, double* g_ax, double* g_ay, void* work, size_t work_bytes,
+                         hipStream_t stream);
+
 /* Reverse sweep (vector-Jacobian product) of K = n_iter steps of the
  * denoised Landweber iteration of the deconvolution stage,
  *   r_k = A c_k - s,  c_{k+1} = D(c_k - tau_b A^T r_k),

@@ -56,8 +56,8 @@ class TrajectoryOperator:
         hs, axs, ays = key[:B], key[B:2 * B], key[2 * B:]
         specs = []
         for b in range(B):
-            amp = torch.tensor([axs[b], ays[b]], dtype=self.dtype, device=self.rhos[b].device)
-            specs.append((self.ns[b], hs[b], self.radii[b], self.rhos[b] * amp, self.nus[b] * amp, self.conv_mode))
+            r, v = mpik.scale_trajectory(self.rhos[b], self.nus[b], axs[b], ays[b])
+            specs.append((self.ns[b], hs[b], self.radii[b], r, v, self.conv_mode))
         batch = mpik.Batch(specs, dtype=self.dtype, tune=False, deriv=True, interp=self.interp)
         self._cache[key] = batch
         self._order.append(key)
@@ -67,10 +67,8 @@ class TrajectoryOperator:
 
     def amp_grads(self, plan, g_r, g_v):
         """dL/dax, dL/day per problem from the per-sample position and velocity
-        gradients (float64)."""
-        gax = plan.dot(g_r, self.rho_all, comp="x") + plan.dot(g_v, self.nu_all, comp="x")
-        gay = plan.dot(g_r, self.rho_all, comp="y") + plan.dot(g_v, self.nu_all, comp="y")
-        return gax, gay
+        gradients (float64, the library's reduction)."""
+        return plan.reduce_lissajous(g_r, g_v, self.rho_all, self.nu_all)
 
 
 def _like(g, ref):

@@ -268,7 +268,7 @@ int make_batch_layout(const mpi_problem* probs, int count, int flags, BatchLayou
     B.plan_bytes = scratch_end;
     B.w_taus = take(woff, sizeof(double) * count);
     B.w_wts = take(woff, 32 * sizeof(double));
-    B.w_dot = take(woff, sizeof(double) * kDotParts * count);
+    B.w_dot = take(woff, sizeof(double) * 2 * kDotParts * count);   // two components (amplitude gradients)
     B.work_bytes = woff;
     return MPI_OK;
 }
@@ -1941,6 +1941,48 @@ int mpi_batch_dot(const mpi_plan* plan, const void* a, const void* b, int space,
     else
         launch_dot<float>(plan, static_cast<const float*>(a), static_cast<const float*>(b), space, comp, out, 0,
                           static_cast<char*>(work), stream);
+    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+}
+
+int mpi_reduce_lissajous(const mpi_plan* plan, const void* g_r, const void* g_v, const void* rho, const void* nu,
+                         double* g_ax, double* g_ay, void* work, size_t work_bytes, hipStream_t stream) {
+    int rc = check_call(plan, g_r, g_v, work, work_bytes);
+    if (rc != MPI_OK) return rc;
+    if (!rho || !nu || !g_ax || !g_ay || g_ax == g_ay) return MPI_ERR_ARG;
+    const size_t el = plan->L.elem;
+    if (misaligned(rho, el) || misaligned(nu, el) || misaligned(g_ax, 8) || misaligned(g_ay, 8)) return MPI_ERR_ARG;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    double* part = reinterpret_cast<double*>(static_cast<char*>(work) + plan->L.w_dot);
+    const dim3 grid(kDotParts, plan->count);
+    if (plan->dtype == MPI_F64)
+        k_amp_part<double><<<grid, 256, 0, stream>>>(plan->dprob, static_cast<const double*>(g_r),
+                                                     static_cast<const double*>(g_v), static_cast<const double*>(rho),
+                                                     static_cast<const double*>(nu), part);
+    else
+        k_amp_part<float><<<grid, 256, 0, stream>>>(plan->dprob, static_cast<const float*>(g_r),
+                                                    static_cast<const float*>(g_v), static_cast<const float*>(rho),
+                                                    static_cast<const float*>(nu), part);
+    k_amp_final<<<plan->count, kDotParts, 0, stream>>>(part, g_ax, g_ay);
+    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+}
+
+int mpi_scale_trajectory(const void* rho, const void* nu, int64_t n_samples, double ax, double ay, int32_t dtype,
+                         void* r, void* v, hipStream_t stream) {
+    if (!rho || !nu || !r || !v || n_samples < 1 || n_samples >= kMaxSamples) return MPI_ERR_ARG;
+    if (!std::isfinite(ax) || !std::isfinite(ay)) return MPI_ERR_ARG;
+    if (dtype != MPI_F32 && dtype != MPI_F64) return MPI_ERR_DTYPE;
+    const size_t el = dtype == MPI_F64 ? 8 : 4;
+    if (misaligned(rho, el) || misaligned(nu, el) || misaligned(r, el) || misaligned(v, el)) return MPI_ERR_ARG;
+    if (r == v || r == rho || r == nu || v == rho || v == nu) return MPI_ERR_ARG;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    const int nblk = blocks(n_samples, 256);
+    if (dtype == MPI_F64)
+        k_scale_traj<double><<<nblk, 256, 0, stream>>>(static_cast<const double*>(rho), static_cast<const double*>(nu),
+                                                        n_samples, ax, ay, static_cast<double*>(r),
+                                                        static_cast<double*>(v));
+    else
+        k_scale_traj<float><<<nblk, 256, 0, stream>>>(static_cast<const float*>(rho), static_cast<const float*>(nu),
+                                                       n_samples, ax, ay, static_cast<float*>(r), static_cast<float*>(v));
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 

@@ -29,6 +29,7 @@ EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "
            "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
            "mpi_batch_deconv_bytes", "mpi_batch_trace_conv", "mpi_batch_cg", "mpi_batch_trim_sigma", "mpi_batch_pnp",
            "mpi_batch_core_bytes", "mpi_batch_core_stage", "mpi_batch_field_trace", "mpi_velocity_forward_difference",
+           "mpi_scale_trajectory", "mpi_reduce_lissajous",
            "mpi_plan_destroy", "mpi_status_str", "mpi_abi_version")
 MPI_BUILD_TUNE, MPI_BUILD_COL_SPLIT, MPI_BUILD_COL_WAVE, MPI_BUILD_DERIV = 1, 2, 4, 8
 NOALLOC_SCRATCH_BYTES = 64 << 20     # MPI_NOALLOC_SCRATCH_BYTES: the allocation-free pair's work memory
@@ -112,6 +113,9 @@ def lib() -> ctypes.CDLL:
                                            vp, sz, vp]
         L.mpi_batch_field_trace.argtypes = [vp, vp, vp, vp]
         L.mpi_velocity_forward_difference.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, vp]
+        L.mpi_scale_trajectory.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                           vp, vp, vp]
+        L.mpi_reduce_lissajous.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.mpi_stage_count.argtypes = [vp]
         L.mpi_stage_name.argtypes = [vp, ctypes.c_int]
         L.mpi_stage_name.restype = ctypes.c_char_p
@@ -128,7 +132,7 @@ def lib() -> ctypes.CDLL:
                      "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_launch",
                      "mpi_batch_deconv_bytes", "mpi_batch_trace_conv", "mpi_batch_cg", "mpi_batch_trim_sigma",
                      "mpi_batch_pnp", "mpi_batch_core_bytes", "mpi_batch_core_stage", "mpi_batch_field_trace",
-                     "mpi_velocity_forward_difference",
+                     "mpi_velocity_forward_difference", "mpi_scale_trajectory", "mpi_reduce_lissajous",
                      "mpi_plan_destroy",
                      "mpi_abi_version"):
             getattr(L, name).restype = ctypes.c_int
@@ -663,6 +667,20 @@ class Batch:
                "mpi_batch_field_trace")
         return u_out
 
+    def reduce_lissajous(self, g_r, g_v, rho_all, nu_all, stream=None):
+        """Per-problem amplitude gradients (float64 device tensors of `count`):
+        dL/dax = sum_k g_r,x rho_x + g_v,x nu_x and dL/day likewise, from the
+        per-sample gradients and the unit shapes (mpi_reduce_lissajous)."""
+        n = self.s_offsets[-1]
+        for t, name in ((g_r, "g_r"), (g_v, "g_v"), (rho_all, "rho_all"), (nu_all, "nu_all")):
+            self._flat(t, n, name)
+        gax = torch.empty(self.count, dtype=torch.float64, device=self.device)
+        gay = torch.empty(self.count, dtype=torch.float64, device=self.device)
+        _check(lib().mpi_reduce_lissajous(self._h, g_r.data_ptr(), g_v.data_ptr(), rho_all.data_ptr(),
+                                          nu_all.data_ptr(), gax.data_ptr(), gay.data_ptr(), self.work.data_ptr(),
+                                          self.work.numel(), _stream(stream)), "mpi_reduce_lissajous")
+        return gax, gay
+
     def sample_order(self, b, stream=None):
         """(time index, base cell i0 | j0 << 16) of problem b's samples in the
         order the plan holds them (int32 device tensors)."""
@@ -695,3 +713,21 @@ def velocity_forward_difference(r: torch.Tensor, dt: float, out: torch.Tensor | 
                                                  _dtype_code(r.dtype), _stream(stream)),
            "mpi_velocity_forward_difference")
     return out
+
+
+def scale_trajectory(rho: torch.Tensor, nu: torch.Tensor, ax: float, ay: float, stream=None):
+    """r = (ax rho_x, ay rho_y), v = (ax nu_x, ay nu_y) on the device
+    (mpi_scale_trajectory): the trajectory of amplitudes (ax, ay) over
+    unit-amplitude shapes rho, nu, each product in float64 rounded once."""
+    for t, name in ((rho, "rho"), (nu, "nu")):
+        if t.ndim != 2 or t.shape[1] != 2 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous (T, 2) device tensor")
+    if nu.shape != rho.shape or nu.dtype != rho.dtype:
+        raise ValueError("rho and nu must have the same shape and dtype")
+    r = torch.empty_like(rho)
+    v = torch.empty_like(nu)
+    _check(lib().mpi_scale_trajectory(rho.data_ptr(), nu.data_ptr(), rho.shape[0], float(ax), float(ay),
+                                      _dtype_code(rho.dtype), r.data_ptr(), v.data_ptr(), _stream(stream)),
+           "mpi_scale_trajectory")
+    return r, v
+

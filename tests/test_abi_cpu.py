@@ -126,6 +126,21 @@ def test_apply_argument_errors_need_no_gpu(mpik):
     assert L.mpi_plan_info(None, None, None, None) == -1
 
 
+def test_trajectory_amplitude_entries_reject_bad_arguments(mpik):
+    """mpi_scale_trajectory and mpi_reduce_lissajous check their arguments on
+    the host: null or aliased pointers, sample counts, dtypes, a null plan."""
+    L = mpik.lib()
+    assert L.mpi_scale_trajectory(None, 512, 10, 1.0, 1.0, 0, 1024, 2048, None) == -1
+    assert L.mpi_scale_trajectory(256, 512, 0, 1.0, 1.0, 0, 1024, 2048, None) == -1
+    assert L.mpi_scale_trajectory(256, 512, 1 << 26, 1.0, 1.0, 0, 1024, 2048, None) == -1
+    assert L.mpi_scale_trajectory(256, 512, 10, float("nan"), 1.0, 0, 1024, 2048, None) == -1
+    assert L.mpi_scale_trajectory(256, 512, 10, 1.0, 1.0, 3, 1024, 2048, None) == -4
+    assert L.mpi_scale_trajectory(256, 512, 10, 1.0, 1.0, 0, 1024, 1024, None) == -1     # r == v
+    assert L.mpi_scale_trajectory(256, 512, 10, 1.0, 1.0, 0, 256, 2048, None) == -1      # r == rho
+    assert L.mpi_scale_trajectory(256, 512, 10, 1.0, 1.0, 1, 1028, 2048, None) == -1     # misaligned
+    assert L.mpi_reduce_lissajous(None, 256, 512, 768, 1024, 1280, 1536, 4096, 1 << 20, None) == -1
+
+
 def test_size_limits(mpik):
     """The edges that the GPU limit tests run at are accepted, one past each is rejected."""
     pb, wb = ctypes.c_size_t(), ctypes.c_size_t()

@@ -124,6 +124,41 @@ def test_dot_is_exact_per_problem(dtype):
         assert abs(grid[i] - np.sum(p[i] * q[i])) <= 1e-13 * np.sum(np.abs(p[i] * q[i])), i
 
 
+def test_scale_trajectory_rounds_once():
+    """r = (ax rho_x, ay rho_y), v = (ax nu_x, ay nu_y): each product formed in
+    float64 and rounded once, bitwise, in both dtypes."""
+    rng = np.random.default_rng(21)
+    for dtype, npd in ((torch.float32, np.float32), (torch.float64, np.float64)):
+        rho = rng.standard_normal((5001, 2)).astype(npd)
+        nu = (50.0 * rng.standard_normal((5001, 2))).astype(npd)
+        ax, ay = 0.8819, 1.0234567
+        r, v = mpik.scale_trajectory(torch.tensor(rho, device="cuda"), torch.tensor(nu, device="cuda"), ax, ay)
+        torch.cuda.synchronize()
+        amp = np.array([ax, ay])
+        assert np.array_equal(r.cpu().numpy(), (rho.astype(np.float64) * amp).astype(npd))
+        assert np.array_equal(v.cpu().numpy(), (nu.astype(np.float64) * amp).astype(npd))
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_reduce_lissajous_is_exact_per_problem(dtype):
+    """The amplitude chain rule of the library, per problem: sum_k g_r,x rho_x +
+    g_v,x nu_x (and y) in float64 against the float64 sums of the same values,
+    bitwise repeatable."""
+    gc = GradCase(SHAPES, dtype)
+    plan = gc.plan()
+    rng = np.random.default_rng(23)
+    g_r, g_v, rho, nu = ([rounded(rng.standard_normal((it["t"], 2)), dtype) for it in gc.items] for _ in range(4))
+    args = [gc.cat(x) for x in (g_r, g_v, rho, nu)]
+    gax, gay = plan.reduce_lissajous(*args)
+    gax2, gay2 = plan.reduce_lissajous(*args)
+    gax, gay = gax.cpu().numpy(), gay.cpu().numpy()
+    assert np.array_equal(gax, gax2.cpu().numpy()) and np.array_equal(gay, gay2.cpu().numpy())
+    for i in range(len(gc.items)):
+        for c, got in ((0, gax[i]), (1, gay[i])):
+            terms = g_r[i][:, c] * rho[i][:, c] + g_v[i][:, c] * nu[i][:, c]
+            assert abs(got - np.sum(terms)) <= 1e-13 * np.sum(np.abs(terms)), (i, c)
+
+
 def _param_grads_ref(it, x, y):
     """Oracle gradients of <y, A x> with respect to h, ax, ay."""
     M = it["model"]
