@@ -39,6 +39,15 @@ template <typename T, int M> struct ColSmem {      // column stages: four lines 
     cx<T> c[M];
     cx<T> line[4][M];
 };
+// The transpose column stage at M = 512 in the four-column shape: four
+// exchange buffers, the twiddle table and one channel's four columns, each
+// padded to SN elements (four more than N, so that the staging stores of four
+// columns fall on different banks).
+__host__ __device__ constexpr int adj_cols_stage_stride(int N) { return N + 4; }
+template <typename T>
+__host__ __device__ constexpr size_t adj_cols_smem_bytes(int N) {
+    return sizeof(cx<T>) * (size_t(4) * kXbStride<T> + 512 + size_t(4) * adj_cols_stage_stride(N));
+}
 // fwd_rows_gather: twiddles, three FFT lines, then rows b, b+1 of the three
 // channels (6N values).
 template <typename T, int M> struct GatherSmem {
@@ -619,7 +628,6 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         fft_wave<T, true, M>(sm.c, sm.tw, lane);
         for (int j = lane; j < N; j += kWave) t2[int64_t(j) * H + kx] = sm.c[j];
     } else if constexpr (M == 512) {                // four columns, register-resident transforms
-        static_assert(4 * kXbStride<T> * sizeof(cx<T>) <= sizeof(ColSmem<T, M>), "exchange buffers exceed the LDS");
         const int unit = xcd_unit(blockIdx.x, (H + 3) / 4);
         if (unit < 0) return;
         const int kx0 = 4 * unit, kx = kx0 + wave;
@@ -627,26 +635,49 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         // each wave's exchange buffer, also the staging of its rows for the stores
         cx<T>(*xb)[kXbStride<T>] = reinterpret_cast<cx<T>(*)[kXbStride<T>]>(smem);
         // twiddles from a table staged after the exchange buffers (registers
-        // for them measured slower here)
+        // for them measured slower here), then one channel's four columns
         cx<T>* tws = reinterpret_cast<cx<T>*>(smem) + 4 * kXbStride<T>;
-        static_assert((4 * kXbStride<T> + M) * sizeof(cx<T>) <= sizeof(ColSmem<T, M>), "twiddle table exceeds the LDS");
+        cx<T>* stg = tws + M;                       // [4][SN]: column c of the channel at stg[c * SN]
+        const int SN = adj_cols_stage_stride(N);
+        // The work-group reads a channel's four columns row by row (element
+        // e = row * 4 + column, four consecutive threads one row's 32 contiguous
+        // bytes, as T1 is stored row-major) and stages them in LDS, where each
+        // wave takes its own column: four times fewer cache lines per load
+        // than a wave reading its column alone.  The next channel's loads are
+        // issued before the current channel's transform.
+        constexpr int PT = (4 * 512 + 4 * kWave - 1) / (4 * kWave);   // elements per thread (N < 512)
+        cx<T> rg[PT];
+        auto load_channel = [&](int ch) {
+            const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(ch) * N * H + kx0;
+#pragma unroll
+            for (int q = 0; q < PT; ++q) {
+                const int e = tid + q * 4 * kWave, row = e >> 2, col = e & 3;
+                rg[q] = (row < N && kx0 + col < H) ? t1[int64_t(row) * H + col] : cx<T>{T(0), T(0)};
+            }
+        };
+        load_channel(0);
         {
             TwiddleRegs<T, M, 4 * kWave> twr;
             twr.load(plan, p, tid);
             twr.store(tws, tid);
         }
-        __syncthreads();
         Fft512TwLds<T> tw;
         tw.init(tws, lane);
         const T* spec_dh = DUAL ? at<T>(plan, p.o_spec_dh) : nullptr;
         cx<T> acc[8], acc2[DUAL ? 8 : 1], v[8];
-        if (active) {
-            for (int ch = 0; ch < 3; ++ch) {
-                const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(ch) * N * H + kx;   // column kx of T1[ch]
+        for (int ch = 0; ch < 3; ++ch) {
+#pragma unroll
+            for (int q = 0; q < PT; ++q) {
+                const int e = tid + q * 4 * kWave, row = e >> 2, col = e & 3;
+                if (row < N) stg[col * SN + row] = rg[q];
+            }
+            __syncthreads();
+            if (ch < 2) load_channel(ch + 1);
+            if (active) {
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
                     const int i = lane + m * kWave;
-                    v[m] = (i < N) ? t1[int64_t(i) * H] : cx<T>{T(0), T(0)};
+                    v[m] = (i < N) ? stg[wave * SN + i] : cx<T>{T(0), T(0)};
                 }
                 fft512_regs<T, false>(v, xb[wave], tw, lane);
 #pragma unroll
@@ -660,6 +691,7 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
                     }
                 }
             }
+            __syncthreads();                        // the staging area is read before the next channel's stores
         }
         auto emit = [&](cx<T> (&src)[8], int slot) {
             if (active) {

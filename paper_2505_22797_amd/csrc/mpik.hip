@@ -73,7 +73,8 @@ template <typename T>
 size_t smem_for_t(int M, int N, int which) {
     switch (which) {
         case 0: return smem_for<T, RowSmem>(M);
-        case 1: return smem_for<T, ColSmem>(M);
+        case 1: return M == 512 ? std::max(smem_for<T, ColSmem>(M), adj_cols_smem_bytes<T>(N))
+                                : smem_for<T, ColSmem>(M);
         default: break;
     }
     switch (M) {
