@@ -61,7 +61,8 @@ typedef enum {
     MPI_ERR_WORKSPACE = -3,    /* plan or work buffer smaller than required   */
     MPI_ERR_DTYPE = -4,        /* unknown dtype                               */
     MPI_ERR_HIP = -5,          /* HIP runtime error (incl. earlier faults)    */
-    MPI_ERR_UNSUPPORTED = -6   /* valid but not implemented option            */
+    MPI_ERR_UNSUPPORTED = -6,  /* valid but not implemented option            */
+    MPI_ERR_ALLOC = -7         /* host memory allocation failed               */
 } mpi_status;
 
 enum { MPI_F32 = 0, MPI_F64 = 1 };
@@ -453,6 +454,33 @@ int mpi_stage_launch(const mpi_plan* plan, int stage, int reps, void* c, void* s
  * sorted by base cell (j0 major) and by time inside a cell.  Both are device
  * arrays of T_index int32 entries owned by the caller; enqueued on `stream`. */
 int mpi_batch_sample_order(const mpi_plan* plan, int index, int32_t* order, int32_t* cell, hipStream_t stream);
+
+/* ---------------------------------------------------------- diagnostics --
+ * Not part of the operator: debugging and test hooks.
+ *
+ * mpi_checks_enabled: 1 if this library is the bounds-checked debug build
+ * (compiled with -DMPIK_CHECK, libmpik_check.so), else 0.  In that build the
+ * kernels check every index they read from the plan's sample tables (a
+ * sample's base cell and time index, the sample range of a base-cell row)
+ * before it addresses memory; a failed check skips the access it guards and
+ * sets a bit in the problem's check word (1: base cell, 2: time index,
+ * 4: sample range), and every kernel runs to its normal end.  The release
+ * build compiles the checks away and its words stay 0.
+ *
+ * mpi_plan_check: OR of the check words of every problem of the plan into
+ * *word (0: no check failed since the build).  Synchronises `stream` after
+ * enqueueing the copies.
+ *
+ * mpi_debug_fail_alloc: arms a process-wide test hook: the k-th resource
+ * acquisition made by the library after this call fails once -- a host
+ * allocation of the plan sizing, build or graph caches (the call returns
+ * MPI_ERR_ALLOC), or a side stream, event or captured graph (MPI_ERR_HIP) --
+ * so that tests can drive every error path; k = 0 disarms it, k < 0 is
+ * MPI_ERR_ARG.  A failed call leaves no plan, stream or graph behind and
+ * later calls behave normally. */
+int mpi_checks_enabled(void);
+int mpi_plan_check(const mpi_plan* plan, int32_t* word, hipStream_t stream);
+int mpi_debug_fail_alloc(int32_t k);
 
 int mpi_plan_destroy(mpi_plan* plan);
 const char* mpi_status_str(int status);

@@ -343,9 +343,12 @@ __global__ void k_place(const Prob* __restrict__ P, const int* __restrict__ orde
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= p.t) return;
     const int k = order[i];
+    const Chk ck = chk_of(p, plan);
+    if (!ck.time(k)) return;
     const int q = cell[k];
     if (q < 0) return;        // outside the hull: the build reports the error
     const int nb = p.nb;
+    if (!ck.ok(q < nb * nb, kChkCell)) return;
     at<int2>(plan, p.o_sidx)[i] = make_int2((q % nb) | ((q / nb) << 16), k);
     const double fx = frac[2 * k], fy = frac[2 * k + 1];
     vec4<T> e;

@@ -81,6 +81,97 @@ template <typename P> __device__ __forceinline__ const P* at(const char* base, i
     return reinterpret_cast<const P*>(base + off);
 }
 
+// ---------------------------------------------------------------------------
+// Bounds checks of the debug build (-DMPIK_CHECK).  The indices that kernels
+// read from the plan's sample tables -- a sample's base cell and time index,
+// the sample range of a base-cell row -- are checked before they address
+// memory.  A failed check ORs its bit into the problem's check word (the
+// second int32 at o_err in plan memory) and the access it guards is skipped,
+// so every kernel still runs to its normal end; the host reads the word with
+// mpi_plan_check.  Without MPIK_CHECK every check is `true` and compiles away.
+// ---------------------------------------------------------------------------
+enum : int { kChkCell = 1, kChkTime = 2, kChkRange = 4 };
+
+struct Chk {
+#ifdef MPIK_CHECK
+    int* word;
+    int nb;          // base cells per side
+    int row;         // base-cell row the samples must lie in, or -1: any
+    int64_t t;       // samples
+#endif
+    __device__ __forceinline__ bool ok(bool cond, int bit) const {
+#ifdef MPIK_CHECK
+        if (!cond) atomicOr(word, bit);
+        return cond;
+#else
+        (void)cond;
+        (void)bit;
+        return true;
+#endif
+    }
+    // base cell (i0, j0) of a sample: inside the grid, and in `row` if set
+    __device__ __forceinline__ bool cell(int packed) const {
+#ifdef MPIK_CHECK
+        const int i0 = packed & 0xffff, j0 = packed >> 16;
+        return ok(i0 < nb && j0 >= 0 && j0 < nb && (row < 0 || j0 == row), kChkCell);
+#else
+        (void)packed;
+        return true;
+#endif
+    }
+    // base cell of a sample that reaches grid row j: base-cell row j-1 or j
+    __device__ __forceinline__ bool cell_near(int packed, int j) const {
+#ifdef MPIK_CHECK
+        const int i0 = packed & 0xffff, j0 = packed >> 16;
+        return ok(i0 < nb && j0 >= 0 && j0 < nb && (j0 == j || j0 == j - 1), kChkCell);
+#else
+        (void)packed;
+        (void)j;
+        return true;
+#endif
+    }
+    __device__ __forceinline__ bool time(int64_t k) const {
+#ifdef MPIK_CHECK
+        return ok(k >= 0 && k < t, kChkTime);
+#else
+        (void)k;
+        return true;
+#endif
+    }
+    // a cell-order sample range [p0, p1); an invalid one becomes empty
+    __device__ __forceinline__ void range(int& p0, int& p1) const {
+#ifdef MPIK_CHECK
+        if (!ok(p0 >= 0 && p0 <= p1 && p1 <= t, kChkRange)) p0 = p1 = 0;
+#else
+        (void)p0;
+        (void)p1;
+#endif
+    }
+    __device__ __forceinline__ Chk in_row(int r) const {
+        Chk c = *this;
+#ifdef MPIK_CHECK
+        c.row = r;
+#else
+        (void)r;
+#endif
+        return c;
+    }
+};
+
+__device__ __forceinline__ Chk chk_of(const Prob& p, const char* plan) {
+    Chk c;
+#ifdef MPIK_CHECK
+    c.word = reinterpret_cast<int*>(const_cast<char*>(plan) + p.o_err) + 1;
+    c.nb = p.nb;
+    c.row = -1;
+    c.t = p.t;
+#else
+    (void)p;
+    (void)plan;
+#endif
+    return c;
+}
+
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // Work-groups are dealt to the 8 XCDs (each with its own L2) round-robin by

@@ -124,7 +124,8 @@ __global__ void __launch_bounds__(256) k_core_rhs(const Prob* __restrict__ P, co
     char* sc = smem + lds_align(size_t(3) * N * sizeof(T));
     scatter_row<T, true, 256>(g, scatter_lds<T>(sc, N, 256), N, j, at<int>(plan, p.o_binstart),
                               at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
-                              reinterpret_cast<const vec2<T>*>(y + p.o_s), nullptr, threadIdx.x, p.chan == 1);
+                              reinterpret_cast<const vec2<T>*>(y + p.o_s), nullptr, threadIdx.x, p.chan == 1,
+                              chk_of(p, plan));
     const double inv_l = 1.0 / double(p.t);
     const int64_t nn = int64_t(N) * N;
     double* o = out + 3 * p.o_c;
@@ -278,10 +279,12 @@ __global__ void __launch_bounds__(256) k_core_dir_gather(const Prob* __restrict_
     if (j < p.nb) {
         const int nb = p.nb;
         const int* binstart = at<int>(plan, p.o_binstart);
-        const int p0 = binstart[j * nb], p1 = binstart[(j + 1) * nb];
+        int p0 = binstart[j * nb], p1 = binstart[(j + 1) * nb];
+        const Chk ck = chk_of(p, plan).in_row(j);
+        ck.range(p0, p1);
         gather_band<T, 4, 4>(pr, pr + W, N, p0, p1, at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), nullptr,
                           nullptr, y + p.o_s, nullptr, nullptr, nullptr, nullptr, p.t, nullptr, p.chan == 1, tid, 256,
-                          nullptr, &accy);
+                          ck, nullptr, &accy);
     }
     __syncthreads();                                                 // pd is read no more
     tree_sum2(accl, accy, red);
@@ -345,7 +348,8 @@ __global__ void __launch_bounds__(256) k_core_update(const Prob* __restrict__ P,
     char* sc = smem + lds_align(size_t(3) * N * sizeof(T));
     scatter_row<T, true, 256>(g, scatter_lds<T>(sc, N, 256), N, j, at<int>(plan, p.o_binstart),
                               at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx),
-                              reinterpret_cast<const vec2<T>*>(y + p.o_s), nullptr, tid, p.chan == 1);
+                              reinterpret_cast<const vec2<T>*>(y + p.o_s), nullptr, tid, p.chan == 1,
+                              chk_of(p, plan));
     // the sampling's scratch (at least 6 * 256 values of T after g) now holds the reductions
     double* red = reinterpret_cast<double*>(sc);
     tree_sum2(yy, ll, red);
@@ -386,6 +390,7 @@ __global__ void k_core_permute(const Prob* __restrict__ P, const T* __restrict__
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= p.t) return;
     const int64_t k = at<int2>(plan, p.o_sidx)[i].y;
+    if (!chk_of(p, plan).time(k)) return;
     y[p.o_s + 2 * i] = s[p.o_s + 2 * k];
     y[p.o_s + 2 * i + 1] = s[p.o_s + 2 * k + 1];
 }

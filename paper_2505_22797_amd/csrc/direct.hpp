@@ -161,7 +161,9 @@ __global__ void __launch_bounds__(256) k_gather_rows(const Prob* __restrict__ P,
     const int N = p.n, nb = p.nb, b = blockIdx.x;
     if (b >= nb) return;
     const int* binstart = at<int>(plan, p.o_binstart);
-    const int p0 = binstart[b * nb], p1 = binstart[(b + 1) * nb];
+    int p0 = binstart[b * nb], p1 = binstart[(b + 1) * nb];
+    const Chk ck = chk_of(p, plan).in_row(b);
+    ck.range(p0, p1);
     if (p0 == p1) return;
     T* g0 = reinterpret_cast<T*>(smem);
     T* g1 = g0 + 3 * N;
@@ -175,7 +177,7 @@ __global__ void __launch_bounds__(256) k_gather_rows(const Prob* __restrict__ P,
                          io.out0 ? io.out0 + p.o_s : nullptr, io.in0 ? io.in0 + p.o_s : nullptr,
                          io.out1 ? io.out1 + p.o_s : nullptr, io.out2 ? io.out2 + p.o_s : nullptr,
                          io.f ? io.f + 9 * (p.o_s / 2) : nullptr, p.t,
-                         p.o_dw ? at<vec2<T>>(plan, p.o_dw) : nullptr, p.chan == 1, threadIdx.x, blockDim.x);
+                         p.o_dw ? at<vec2<T>>(plan, p.o_dw) : nullptr, p.chan == 1, threadIdx.x, blockDim.x, ck);
 }
 
 // Deterministic transpose sampling for one grid row into a field in global
@@ -196,7 +198,7 @@ __global__ void __launch_bounds__(256) k_scatter_rows(const Prob* __restrict__ P
     const vec2<T>* ys = (SORTED && sp) ? reinterpret_cast<const vec2<T>*>(sp) : at<vec2<T>>(work, p.w_res);
     scatter_row<T, SORTED, 256>(g, scatter_lds<T>(sc, N, 256), N, j, at<int>(plan, p.o_binstart),
                                 at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), ys, sp, threadIdx.x,
-                                p.chan == 1);
+                                p.chan == 1, chk_of(p, plan));
     for (int i = threadIdx.x; i < 3 * N; i += blockDim.x) {
         const int ch = i / N, x = i % N;
         G[int64_t(ch) * N * N + int64_t(j) * N + x] = g[i];
@@ -211,6 +213,7 @@ __global__ void k_permute_signal(const Prob* __restrict__ P, const T* __restrict
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= p.t) return;
     const int k = at<int2>(plan, p.o_sidx)[i].y;
+    if (!chk_of(p, plan).time(k)) return;
     const T* sp = s + p.o_s;
     vec2<T> y;
     y.x = sp[2 * k];

@@ -404,7 +404,9 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
     const int N = p.n, nb = p.nb, b = xcd_unit(blockIdx.x, nb);
     if (b < 0) return;
     const int* binstart = at<int>(plan, p.o_binstart);
-    const int p0 = binstart[b * nb], p1 = binstart[(b + 1) * nb];
+    int p0 = binstart[b * nb], p1 = binstart[(b + 1) * nb];
+    const Chk ck = chk_of(p, plan).in_row(b);
+    ck.range(p0, p1);
     if (p0 == p1) return;
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     // every load of the work-group in flight together: twiddles, the two
@@ -424,7 +426,7 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
     // signal by time index (trajectory gradients, residual), which would spill
     constexpr int U = (MODE == 2 || MODE == 3) ? 2 : 4;
     GatherRecs<T, U> first;
-    gather_fetch<T, MODE, U>(first, p0 + tid, p1, 4 * kWave, samp, sidx, ysort, in0, p.chan == 1);
+    gather_fetch<T, MODE, U>(first, p0 + tid, p1, 4 * kWave, samp, sidx, ysort, in0, p.chan == 1, ck);
     twr.store(sm.tw, tid);
     __syncthreads();
     T* g0 = sm.g;            // row b:   [ch][N]
@@ -463,7 +465,7 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
     }
     __syncthreads();
     gather_band<T, MODE, U>(g0, g1, N, p0, p1, samp, sidx, ysort, at<vec2<T>>(work, p.w_res), out0, in0, out1, out2,
-                            f, p.t, dw, p.chan == 1, tid, 4 * kWave, &first);
+                            f, p.t, dw, p.chan == 1, tid, 4 * kWave, ck, &first);
 }
 
 // ----------------------------------------------------------------- adjoint ---
@@ -490,7 +492,7 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
     const vec2<T>* ys = (SORTED && s) ? reinterpret_cast<const vec2<T>*>(s) : at<vec2<T>>(work, p.w_res);
     scatter_row<T, SORTED, 256>(g, sl, N, j, at<int>(plan, p.o_binstart),
                                 at<vec4<T>>(plan, p.o_samp), at<int2>(plan, p.o_sidx), ys,
-                                s, tid, p.chan == 1);
+                                s, tid, p.chan == 1, chk_of(p, plan));
     if constexpr (M == 512 && sizeof(T) == 4) {   // register-resident transforms (float32)
         static_assert(2 * kXbStride<T> <= 3 * M, "exchange buffers exceed the transform region");
         __syncthreads();

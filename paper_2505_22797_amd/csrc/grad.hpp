@@ -27,6 +27,7 @@ __global__ void k_vjp_finish(const Prob* __restrict__ P, const char* __restrict_
     if (i == 0) g_h[blockIdx.y] = -tau * acc_h[blockIdx.y];
     if (i >= p.t) return;
     const int64_t k = at<int2>(plan, p.o_sidx)[i].y;
+    if (!chk_of(p, plan).time(k)) return;
     const T t = T(-tau);
     const int64_t a = p.o_s + 2 * i, o = p.o_s + 2 * k;
     g_r[o] = t * acc_r[a];

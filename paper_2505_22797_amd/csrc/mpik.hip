@@ -13,11 +13,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <tuple>
@@ -35,6 +37,38 @@
 using namespace mpik;
 
 namespace {
+
+// Injected resource failure (mpi_debug_fail_alloc): the k-th resource point
+// reached after arming fails once -- a host allocation throws std::bad_alloc
+// (the entry point returns MPI_ERR_ALLOC), a HIP stream, event or graph
+// reports a runtime error (MPI_ERR_HIP) -- so that every unwinding path can be
+// driven from a test.  Process-wide; off unless armed.
+std::atomic<int> g_fail_at{0};
+std::atomic<int> g_points_seen{0};
+
+bool injected_failure() {
+    const int k = g_fail_at.load(std::memory_order_relaxed);
+    if (k <= 0 || g_points_seen.fetch_add(1, std::memory_order_relaxed) + 1 != k) return false;
+    g_fail_at.store(0, std::memory_order_relaxed);
+    return true;
+}
+
+// before every host allocation of the plan sizing and build
+void alloc_point() {
+    if (injected_failure()) throw std::bad_alloc();
+}
+
+// Every entry point runs its body through this: no exception crosses the ABI.
+// The host code can throw only from the standard containers and locks, i.e.
+// when the process runs out of memory or another resource.
+template <class F>
+int guarded(F&& body) noexcept {
+    try {
+        return body();
+    } catch (...) {
+        return MPI_ERR_ALLOC;
+    }
+}
 
 constexpr size_t kAlign = 256;
 constexpr int64_t kMaxSamples = int64_t(1) << 26;
@@ -238,8 +272,11 @@ int default_mode(const Shape& sh, int requested) {
 int make_batch_layout(const mpi_problem* probs, int count, int flags, BatchLayout& B) {
     if (!probs || count < 1 || count > kMaxBatch) return MPI_ERR_ARG;
     B.deriv = (flags & MPI_BUILD_DERIV) != 0;
+    alloc_point();
     B.shapes.resize(count);
+    alloc_point();
     B.probs.resize(count);
+    alloc_point();
     B.requested.resize(count);
     for (int b = 0; b < count; ++b) {
         const int rc = validate(&probs[b], B.shapes[b]);
@@ -326,19 +363,14 @@ struct mpi_plan {
     hipEvent_t ev_fork = nullptr, ev_join[kMaxSide] = {};
     int chunks = 1;
     std::mutex fork_mu;          // one host thread at a time enqueues a fork
-    // cached iteration graph
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    const void *g_s = nullptr, *g_c = nullptr, *g_work = nullptr;
-    double g_sigma = 0;
-    int g_rad = -1;
-    // cached graphs of a block of CG steps (Deconvolution and Core Stage), keyed
-    // by their buffers and parameters
+    // cached graphs, keyed by their buffers and parameters: one iteration,
+    // a block of kIterBlock iterations, a block of CG steps (Deconvolution
+    // and Core Stage)
     struct GraphCache {
         hipGraphExec_t exec = nullptr;
         hipGraph_t graph = nullptr;
         std::vector<double> key;
-    } cg_gc, core_gc, iter_gc;   // iter_gc: a block of kIterBlock iterations
+    } one_gc, iter_gc, cg_gc, core_gc;
 };
 
 namespace {
@@ -348,6 +380,7 @@ namespace {
         hipError_t e_ = (expr);                     \
         if (e_ != hipSuccess) return MPI_ERR_HIP;   \
     } while (0)
+
 
 // Device address of the current GPU's copy of `scratch`, resolved once per
 // device (hipGetSymbolAddress with that device current) and kept.
@@ -933,6 +966,7 @@ int build_batch(const mpi_problem* probs, mpi_plan* pl, void* work, size_t work_
     BatchLayout& B = pl->L;
     char* plan = pl->plan;
     HIP_TRY(hipMemcpyAsync(plan, B.probs.data(), sizeof(Prob) * pl->count, hipMemcpyHostToDevice, st));
+    alloc_point();
     std::vector<int> errs(4 * size_t(pl->count), 0);
     for (int b = 0; b < pl->count; ++b) {
         const int rc = build_problem<T>(&probs[b], B, b, plan, st);
@@ -1001,16 +1035,25 @@ int create_streams(mpi_plan* pl) {
         pl->chunks = 1;
         return MPI_OK;
     }
-    bool ok = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) == hipSuccess;
+    bool ok = !injected_failure() && hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) == hipSuccess;
     for (int i = 0; i < groups * pl->chunks && ok; ++i)
-        ok = hipStreamCreateWithFlags(&pl->side[i], hipStreamNonBlocking) == hipSuccess &&
-             hipEventCreateWithFlags(&pl->ev_join[i], hipEventDisableTiming) == hipSuccess;
+        ok = !injected_failure() && hipStreamCreateWithFlags(&pl->side[i], hipStreamNonBlocking) == hipSuccess &&
+             !injected_failure() && hipEventCreateWithFlags(&pl->ev_join[i], hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         release_streams(pl);
         return MPI_ERR_HIP;
     }
     return MPI_OK;
 }
+
+// Releases a plan that a build abandons (an error status or an exception):
+// its side streams and events, then the object.
+struct PlanRelease {
+    void operator()(mpi_plan* pl) const {
+        release_streams(pl);
+        delete pl;
+    }
+};
 
 int build_common(const mpi_problem* probs, int count, void* plan_mem, size_t plan_bytes, void* work,
                  size_t work_bytes, int flags, hipStream_t stream, mpi_plan** out) {
@@ -1026,9 +1069,11 @@ int build_common(const mpi_problem* probs, int count, void* plan_mem, size_t pla
     }
     if (plan_bytes < L.plan_bytes) return MPI_ERR_WORKSPACE;
     if (work && misaligned(work, kAlign)) return MPI_ERR_ARG;
-    mpi_plan* pl = new (std::nothrow) mpi_plan;
-    if (!pl) return MPI_ERR_ARG;
-    pl->L = L;
+    alloc_point();
+    std::unique_ptr<mpi_plan, PlanRelease> owner(new (std::nothrow) mpi_plan);
+    if (!owner) return MPI_ERR_ALLOC;
+    mpi_plan* pl = owner.get();
+    pl->L = std::move(L);
     pl->count = count;
     pl->dtype = probs[0].dtype;
     pl->plan = static_cast<char*>(plan_mem);
@@ -1038,15 +1083,12 @@ int build_common(const mpi_problem* probs, int count, void* plan_mem, size_t pla
     rc = pl->dtype == MPI_F64 ? build_batch<double>(probs, pl, work, work_bytes, flags, stream)
                               : build_batch<float>(probs, pl, work, work_bytes, flags, stream);
     if (rc == MPI_OK) rc = create_streams(pl);
-    if (rc != MPI_OK) {
-        delete pl;
-        return rc;
-    }
+    if (rc != MPI_OK) return rc;      // the owner releases the plan
     // the allocation-free pair's work memory on this GPU; a failure here only
     // disables that entry point (it returns the status)
     if (hipGetDevice(&pl->device) != hipSuccess) pl->device = -1;
     pl->noalloc_rc = scratch_address(pl->device, &pl->noalloc_work);
-    *out = pl;
+    *out = owner.release();
     return MPI_OK;
 }
 
@@ -1187,6 +1229,8 @@ double key_of(const void* ptr) { return double(reinterpret_cast<uintptr_t>(ptr))
 template <typename F>
 int cached_graph(mpi_plan::GraphCache& gc, const std::vector<double>& key, hipStream_t st, F&& record) {
     if (gc.exec && gc.key == key) return MPI_OK;
+    alloc_point();
+    std::vector<double> new_key(key);     // allocated before anything is captured
     if (gc.exec) {
         HIP_TRY(hipStreamSynchronize(st));
         (void)hipGraphExecDestroy(gc.exec);
@@ -1194,6 +1238,7 @@ int cached_graph(mpi_plan::GraphCache& gc, const std::vector<double>& key, hipSt
         gc.exec = nullptr;
         gc.graph = nullptr;
     }
+    if (injected_failure()) return MPI_ERR_HIP;
     hipStream_t cap;
     HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
@@ -1215,7 +1260,7 @@ int cached_graph(mpi_plan::GraphCache& gc, const std::vector<double>& key, hipSt
         gc.exec = nullptr;
         return rc != MPI_OK ? rc : MPI_ERR_HIP;
     }
-    gc.key = key;
+    gc.key.swap(new_key);
     return MPI_OK;
 }
 
@@ -1235,48 +1280,17 @@ int iterate_impl(mpi_plan* pl, const T* s, T* c, const mpi_iter_params* ip, cons
         }
         return MPI_OK;
     }
-    const bool same = pl->gexec && pl->g_s == s && pl->g_c == c && pl->g_work == work &&
-                      pl->g_sigma == (denoise ? ip->denoise_sigma_px : 0.0) && pl->g_rad == rad;
-    if (!same) {
-        if (pl->gexec) {
-            HIP_TRY(hipStreamSynchronize(st));
-            (void)hipGraphExecDestroy(pl->gexec);
-            (void)hipGraphDestroy(pl->graph);
-            pl->gexec = nullptr;
-            pl->graph = nullptr;
-        }
-        hipStream_t cap;
-        HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-        int rc = MPI_ERR_HIP;
-        if (e == hipSuccess) {
-            rc = iteration_impl<T>(pl, c, denoise, rad, work, cap);
-            hipGraph_t g = nullptr;
-            e = hipStreamEndCapture(cap, &g);
-            if (e == hipSuccess && rc == MPI_OK) {
-                e = hipGraphInstantiate(&pl->gexec, g, nullptr, nullptr, 0);
-                if (e == hipSuccess) pl->graph = g;
-                else (void)hipGraphDestroy(g);
-            } else if (g) {
-                (void)hipGraphDestroy(g);
-            }
-        }
-        (void)hipStreamDestroy(cap);
-        if (e != hipSuccess || rc != MPI_OK || !pl->gexec) {
-            pl->gexec = nullptr;
-            return MPI_ERR_HIP;
-        }
-        pl->g_s = s;
-        pl->g_c = c;
-        pl->g_work = work;
-        pl->g_sigma = denoise ? ip->denoise_sigma_px : 0.0;
-        pl->g_rad = rad;
-    }
+    const double sigma = denoise ? ip->denoise_sigma_px : 0.0;
+    alloc_point();
+    const std::vector<double> key{key_of(s), key_of(c), key_of(work), sigma, double(rad)};
+    const int rc = cached_graph(pl->one_gc, key, st, [&](hipStream_t cap) -> int {
+        return iteration_impl<T>(pl, c, denoise, rad, work, cap);
+    });
+    if (rc != MPI_OK) return rc;
     // blocks of kIterBlock iterations from a second cached graph (fewer graph
     // launches, each with its fork and join), the remainder one by one
     int it = 0;
     if (ip->n_iter >= kIterBlock) {
-        const std::vector<double> key{key_of(s), key_of(c), key_of(work), pl->g_sigma, double(rad)};
         const int rc = cached_graph(pl->iter_gc, key, st, [&](hipStream_t cap) -> int {
             for (int i = 0; i < kIterBlock; ++i) {
                 const int r = iteration_impl<T>(pl, c, denoise, rad, work, cap);
@@ -1287,7 +1301,7 @@ int iterate_impl(mpi_plan* pl, const T* s, T* c, const mpi_iter_params* ip, cons
         if (rc != MPI_OK) return rc;
         for (; it + kIterBlock <= ip->n_iter; it += kIterBlock) HIP_TRY(hipGraphLaunch(pl->iter_gc.exec, st));
     }
-    for (; it < ip->n_iter; ++it) HIP_TRY(hipGraphLaunch(pl->gexec, st));
+    for (; it < ip->n_iter; ++it) HIP_TRY(hipGraphLaunch(pl->one_gc.exec, st));
     return MPI_OK;
 }
 
@@ -1466,6 +1480,7 @@ int cg_impl(mpi_plan* pl, const T* cu, const T* rho2, T* x, double tol, int max_
     k_cg_begin<<<blocks(B, 256), 256, 0, st>>>(B, s, pa, tol, max_iter);
     HIP_TRY(hipGetLastError());
     if (max_iter > 0) {
+        alloc_point();
         const std::vector<double> key{key_of(work), key_of(dw), tol, double(max_iter)};
         int rc = cached_graph(pl->cg_gc, key, st, [&](hipStream_t cap) -> int {
             for (int i = 0; i < kCgBlock; ++i) cg_step<T>(pl, i & 1, tol, max_iter, work, dw, L, cap);
@@ -1658,6 +1673,7 @@ int core_impl(mpi_plan* pl, const T* sig, T* field, double gamma, double tol, in
     k_core_begin<<<B, 256, 0, st>>>(P, s, max_iter);
     HIP_TRY(hipGetLastError());
     if (max_iter > 0) {
+        alloc_point();
         const std::vector<double> key{key_of(cw), gamma, tol, double(max_iter)};
         int rc = cached_graph(pl->core_gc, key, st, [&](hipStream_t cap) -> int {
             for (int i = 0; i < kCgBlock; ++i) core_step<T>(pl, i & 1, gamma, tol, max_iter, cw, L, cap);
@@ -1698,465 +1714,538 @@ const char* mpi_status_str(int status) {
         case MPI_ERR_DTYPE: return "unknown dtype";
         case MPI_ERR_HIP: return "HIP runtime error";
         case MPI_ERR_UNSUPPORTED: return "unsupported option";
+        case MPI_ERR_ALLOC: return "host memory allocation failed";
         default: return "unknown status";
     }
 }
 
 int mpi_batch_bytes(const mpi_problem* probs, int count, int flags, size_t* plan_bytes, size_t* work_bytes) {
-    if (!plan_bytes || !work_bytes) return MPI_ERR_ARG;
-    BatchLayout L;
-    const int rc = make_batch_layout(probs, count, flags, L);
-    if (rc != MPI_OK) return rc;
-    *plan_bytes = L.plan_bytes;
-    *work_bytes = L.work_bytes;
-    return MPI_OK;
+    return guarded([&]() -> int {
+        if (!plan_bytes || !work_bytes) return MPI_ERR_ARG;
+        BatchLayout L;
+        const int rc = make_batch_layout(probs, count, flags, L);
+        if (rc != MPI_OK) return rc;
+        *plan_bytes = L.plan_bytes;
+        *work_bytes = L.work_bytes;
+        return MPI_OK;
+    });
 }
 
 int mpi_plan_bytes(const mpi_problem* prob, size_t* plan_bytes, size_t* work_bytes) {
-    return mpi_batch_bytes(prob, 1, 0, plan_bytes, work_bytes);
+    return guarded([&]() -> int {
+        return mpi_batch_bytes(prob, 1, 0, plan_bytes, work_bytes);
+    });
 }
 
 int mpi_kernel_build(const mpi_problem* prob, void* plan_mem, size_t plan_bytes, hipStream_t stream, mpi_plan** out) {
-    return build_common(prob, 1, plan_mem, plan_bytes, nullptr, 0, 0, stream, out);
+    return guarded([&]() -> int {
+        return build_common(prob, 1, plan_mem, plan_bytes, nullptr, 0, 0, stream, out);
+    });
 }
 
 int mpi_batch_build(const mpi_problem* probs, int count, void* plan_mem, size_t plan_bytes, void* work,
                     size_t work_bytes, int flags, hipStream_t stream, mpi_plan** out) {
-    return build_common(probs, count, plan_mem, plan_bytes, work, work_bytes, flags, stream, out);
+    return guarded([&]() -> int {
+        return build_common(probs, count, plan_mem, plan_bytes, work, work_bytes, flags, stream, out);
+    });
 }
 
 int mpi_batch_count(const mpi_plan* plan) { return plan ? plan->count : MPI_ERR_ARG; }
 
 int mpi_batch_offsets(const mpi_plan* plan, int64_t* c_offsets, int64_t* s_offsets) {
-    if (!plan) return MPI_ERR_ARG;
-    for (int b = 0; b < plan->count; ++b) {
-        if (c_offsets) c_offsets[b] = plan->L.probs[b].o_c;
-        if (s_offsets) s_offsets[b] = plan->L.probs[b].o_s;
-    }
-    if (c_offsets) c_offsets[plan->count] = plan->L.c_elems;
-    if (s_offsets) s_offsets[plan->count] = plan->L.s_elems;
-    return MPI_OK;
+    return guarded([&]() -> int {
+        if (!plan) return MPI_ERR_ARG;
+        for (int b = 0; b < plan->count; ++b) {
+            if (c_offsets) c_offsets[b] = plan->L.probs[b].o_c;
+            if (s_offsets) s_offsets[b] = plan->L.probs[b].o_s;
+        }
+        if (c_offsets) c_offsets[plan->count] = plan->L.c_elems;
+        if (s_offsets) s_offsets[plan->count] = plan->L.s_elems;
+        return MPI_OK;
+    });
 }
 
 int mpi_batch_info(const mpi_plan* plan, int index, int32_t* radius, int32_t* fft_size, int32_t* conv_mode,
                    int32_t* slices) {
-    if (!plan || index < 0 || index >= plan->count) return MPI_ERR_ARG;
-    const Prob& p = plan->L.probs[index];
-    if (radius) *radius = p.radius;
-    if (fft_size) *fft_size = p.mode ? p.m : 0;
-    if (conv_mode) *conv_mode = p.mode ? MPI_CONV_FFT : MPI_CONV_DIRECT;
-    if (slices) *slices = p.mode ? 0 : p.slices;
-    return MPI_OK;
+    return guarded([&]() -> int {
+        if (!plan || index < 0 || index >= plan->count) return MPI_ERR_ARG;
+        const Prob& p = plan->L.probs[index];
+        if (radius) *radius = p.radius;
+        if (fft_size) *fft_size = p.mode ? p.m : 0;
+        if (conv_mode) *conv_mode = p.mode ? MPI_CONV_FFT : MPI_CONV_DIRECT;
+        if (slices) *slices = p.mode ? 0 : p.slices;
+        return MPI_OK;
+    });
 }
 
 int mpi_batch_sample_order(const mpi_plan* plan, int index, int32_t* order, int32_t* cell, hipStream_t stream) {
-    if (!plan || index < 0 || index >= plan->count || !order || !cell) return MPI_ERR_ARG;
-    if (misaligned(order, 4) || misaligned(cell, 4)) return MPI_ERR_ARG;
-    const Prob& p = plan->L.probs[index];
-    k_sample_order<<<blocks(p.t, 256), 256, 0, stream>>>(plan->dprob + index, plan->plan, order, cell);
-    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    return guarded([&]() -> int {
+        if (!plan || index < 0 || index >= plan->count || !order || !cell) return MPI_ERR_ARG;
+        if (misaligned(order, 4) || misaligned(cell, 4)) return MPI_ERR_ARG;
+        const Prob& p = plan->L.probs[index];
+        k_sample_order<<<blocks(p.t, 256), 256, 0, stream>>>(plan->dprob + index, plan->plan, order, cell);
+        return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    });
 }
 
 int mpi_plan_info(const mpi_plan* plan, int32_t* radius, int32_t* fft_size, int32_t* conv_mode) {
-    return mpi_batch_info(plan, 0, radius, fft_size, conv_mode, nullptr);
+    return guarded([&]() -> int {
+        return mpi_batch_info(plan, 0, radius, fft_size, conv_mode, nullptr);
+    });
 }
 
 int mpi_batch_forward(const mpi_plan* plan, const void* c, void* s, void* work, size_t work_bytes,
                       hipStream_t stream) {
-    int rc = check_call(plan, c, s, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    if (misaligned(s, 2 * plan->L.elem)) return MPI_ERR_ARG;   // written as (x, y) pairs
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    char* w = static_cast<char*>(work);
-    return plan->dtype == MPI_F64
-               ? forward_impl<double>(plan, static_cast<const double*>(c), static_cast<double*>(s), w, stream)
-               : forward_impl<float>(plan, static_cast<const float*>(c), static_cast<float*>(s), w, stream);
+    return guarded([&]() -> int {
+        int rc = check_call(plan, c, s, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (misaligned(s, 2 * plan->L.elem)) return MPI_ERR_ARG;   // written as (x, y) pairs
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        char* w = static_cast<char*>(work);
+        return plan->dtype == MPI_F64
+                   ? forward_impl<double>(plan, static_cast<const double*>(c), static_cast<double*>(s), w, stream)
+                   : forward_impl<float>(plan, static_cast<const float*>(c), static_cast<float*>(s), w, stream);
+    });
 }
 
 int mpi_batch_pair(const mpi_plan* plan, const void* c, void* s, void* g, void* work, size_t work_bytes,
                    hipStream_t stream) {
-    int rc = check_call(plan, c, s, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    if (!g || misaligned(g, plan->L.elem) || misaligned(s, 2 * plan->L.elem)) return MPI_ERR_ARG;
-    if (g == c || g == s) return MPI_ERR_ARG;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    char* w = static_cast<char*>(work);
-    return plan->dtype == MPI_F64
-               ? pair_impl<double>(plan, static_cast<const double*>(c), static_cast<double*>(s),
-                                   static_cast<double*>(g), w, stream)
-               : pair_impl<float>(plan, static_cast<const float*>(c), static_cast<float*>(s), static_cast<float*>(g),
-                                  w, stream);
+    return guarded([&]() -> int {
+        int rc = check_call(plan, c, s, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (!g || misaligned(g, plan->L.elem) || misaligned(s, 2 * plan->L.elem)) return MPI_ERR_ARG;
+        if (g == c || g == s) return MPI_ERR_ARG;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        char* w = static_cast<char*>(work);
+        return plan->dtype == MPI_F64
+                   ? pair_impl<double>(plan, static_cast<const double*>(c), static_cast<double*>(s),
+                                       static_cast<double*>(g), w, stream)
+                   : pair_impl<float>(plan, static_cast<const float*>(c), static_cast<float*>(s), static_cast<float*>(g),
+                                      w, stream);
+    });
 }
 
 int mpi_batch_pair_noalloc(const mpi_plan* plan, const void* c, void* s, void* g, hipStream_t stream) {
-    if (!plan) return MPI_ERR_ARG;
-    if (plan->L.work_bytes > kNoAllocScratchBytes) return MPI_ERR_WORKSPACE;
-    if (plan->noalloc_rc != MPI_OK) return plan->noalloc_rc;
-    return mpi_batch_pair(plan, c, s, g, plan->noalloc_work, kNoAllocScratchBytes, stream);
+    return guarded([&]() -> int {
+        if (!plan) return MPI_ERR_ARG;
+        if (plan->L.work_bytes > kNoAllocScratchBytes) return MPI_ERR_WORKSPACE;
+        if (plan->noalloc_rc != MPI_OK) return plan->noalloc_rc;
+        return mpi_batch_pair(plan, c, s, g, plan->noalloc_work, kNoAllocScratchBytes, stream);
+    });
 }
 
 int mpi_batch_adjoint(const mpi_plan* plan, const void* s, void* c, void* work, size_t work_bytes,
                       hipStream_t stream) {
-    int rc = check_call(plan, s, c, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    char* w = static_cast<char*>(work);
-    return plan->dtype == MPI_F64
-               ? adjoint_impl<double, false, 0>(plan, static_cast<const double*>(s), static_cast<double*>(c), nullptr,
-                                                w, stream)
-               : adjoint_impl<float, false, 0>(plan, static_cast<const float*>(s), static_cast<float*>(c), nullptr, w,
-                                               stream);
+    return guarded([&]() -> int {
+        int rc = check_call(plan, s, c, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        char* w = static_cast<char*>(work);
+        return plan->dtype == MPI_F64
+                   ? adjoint_impl<double, false, 0>(plan, static_cast<const double*>(s), static_cast<double*>(c), nullptr,
+                                                    w, stream)
+                   : adjoint_impl<float, false, 0>(plan, static_cast<const float*>(s), static_cast<float*>(c), nullptr, w,
+                                                   stream);
+    });
 }
 
 int mpi_forward(const mpi_plan* plan, const void* c, void* s, void* work, size_t work_bytes, hipStream_t stream) {
-    if (plan && plan->count != 1) return MPI_ERR_ARG;
-    return mpi_batch_forward(plan, c, s, work, work_bytes, stream);
+    return guarded([&]() -> int {
+        if (plan && plan->count != 1) return MPI_ERR_ARG;
+        return mpi_batch_forward(plan, c, s, work, work_bytes, stream);
+    });
 }
 
 int mpi_adjoint(const mpi_plan* plan, const void* s, void* c, void* work, size_t work_bytes, hipStream_t stream) {
-    if (plan && plan->count != 1) return MPI_ERR_ARG;
-    return mpi_batch_adjoint(plan, s, c, work, work_bytes, stream);
+    return guarded([&]() -> int {
+        if (plan && plan->count != 1) return MPI_ERR_ARG;
+        return mpi_batch_adjoint(plan, s, c, work, work_bytes, stream);
+    });
 }
 
 int mpi_batch_iterate(const mpi_plan* plan, const void* s, void* c, const mpi_iter_params* params,
                       const double* taus, void* work, size_t work_bytes, hipStream_t stream) {
-    int rc = check_call(plan, s, c, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    rc = check_iter(params);
-    if (rc != MPI_OK) return rc;
-    if (!taus) return MPI_ERR_ARG;
-    for (int b = 0; b < plan->count; ++b)
-        if (!std::isfinite(taus[b])) return MPI_ERR_ARG;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    mpi_plan* pl = const_cast<mpi_plan*>(plan);
-    char* w = static_cast<char*>(work);
-    return plan->dtype == MPI_F64
-               ? iterate_impl<double>(pl, static_cast<const double*>(s), static_cast<double*>(c), params, taus, w,
-                                      stream)
-               : iterate_impl<float>(pl, static_cast<const float*>(s), static_cast<float*>(c), params, taus, w,
-                                     stream);
+    return guarded([&]() -> int {
+        int rc = check_call(plan, s, c, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        rc = check_iter(params);
+        if (rc != MPI_OK) return rc;
+        if (!taus) return MPI_ERR_ARG;
+        for (int b = 0; b < plan->count; ++b)
+            if (!std::isfinite(taus[b])) return MPI_ERR_ARG;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        mpi_plan* pl = const_cast<mpi_plan*>(plan);
+        char* w = static_cast<char*>(work);
+        return plan->dtype == MPI_F64
+                   ? iterate_impl<double>(pl, static_cast<const double*>(s), static_cast<double*>(c), params, taus, w,
+                                          stream)
+                   : iterate_impl<float>(pl, static_cast<const float*>(s), static_cast<float*>(c), params, taus, w,
+                                         stream);
+    });
 }
 
 int mpi_iterate(const mpi_plan* plan, const void* s, void* c, const mpi_iter_params* params, void* work,
                 size_t work_bytes, hipStream_t stream) {
-    if (plan && plan->count != 1) return MPI_ERR_ARG;
-    if (check_iter(params) != MPI_OK) return MPI_ERR_ARG;
-    const double tau = params->tau;
-    return mpi_batch_iterate(plan, s, c, params, &tau, work, work_bytes, stream);
+    return guarded([&]() -> int {
+        if (plan && plan->count != 1) return MPI_ERR_ARG;
+        if (check_iter(params) != MPI_OK) return MPI_ERR_ARG;
+        const double tau = params->tau;
+        return mpi_batch_iterate(plan, s, c, params, &tau, work, work_bytes, stream);
+    });
 }
 
 int mpi_batch_forward_dh(const mpi_plan* plan, const void* x, void* s, void* work, size_t work_bytes,
                          hipStream_t stream) {
-    int rc = check_call(plan, x, s, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    if (misaligned(s, 2 * plan->L.elem)) return MPI_ERR_ARG;   // written as (x, y) pairs
-    if (!plan->L.deriv) return MPI_ERR_UNSUPPORTED;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    char* w = static_cast<char*>(work);
-    return plan->dtype == MPI_F64
-               ? forward_impl<double>(plan, static_cast<const double*>(x), static_cast<double*>(s), w, stream, 1)
-               : forward_impl<float>(plan, static_cast<const float*>(x), static_cast<float*>(s), w, stream, 1);
+    return guarded([&]() -> int {
+        int rc = check_call(plan, x, s, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (misaligned(s, 2 * plan->L.elem)) return MPI_ERR_ARG;   // written as (x, y) pairs
+        if (!plan->L.deriv) return MPI_ERR_UNSUPPORTED;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        char* w = static_cast<char*>(work);
+        return plan->dtype == MPI_F64
+                   ? forward_impl<double>(plan, static_cast<const double*>(x), static_cast<double*>(s), w, stream, 1)
+                   : forward_impl<float>(plan, static_cast<const float*>(x), static_cast<float*>(s), w, stream, 1);
+    });
 }
 
 int mpi_batch_residual(const mpi_plan* plan, const void* c, const void* y, void* out, void* work,
                        size_t work_bytes, hipStream_t stream) {
-    int rc = check_call(plan, c, y, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    if (!out || misaligned(out, 2 * plan->L.elem)) return MPI_ERR_ARG;   // written as (x, y) pairs
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    char* w = static_cast<char*>(work);
-    return plan->dtype == MPI_F64
-               ? residual_impl<double>(plan, static_cast<const double*>(c), static_cast<const double*>(y),
-                                       static_cast<double*>(out), w, stream)
-               : residual_impl<float>(plan, static_cast<const float*>(c), static_cast<const float*>(y),
-                                      static_cast<float*>(out), w, stream);
+    return guarded([&]() -> int {
+        int rc = check_call(plan, c, y, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (!out || misaligned(out, 2 * plan->L.elem)) return MPI_ERR_ARG;   // written as (x, y) pairs
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        char* w = static_cast<char*>(work);
+        return plan->dtype == MPI_F64
+                   ? residual_impl<double>(plan, static_cast<const double*>(c), static_cast<const double*>(y),
+                                           static_cast<double*>(out), w, stream)
+                   : residual_impl<float>(plan, static_cast<const float*>(c), static_cast<const float*>(y),
+                                          static_cast<float*>(out), w, stream);
+    });
 }
 
 int mpi_batch_traj_vjp(const mpi_plan* plan, const void* x, const void* y, void* g_r, void* g_v, void* work,
                        size_t work_bytes, hipStream_t stream) {
-    int rc = check_call(plan, x, y, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    if (!g_r || !g_v || misaligned(g_r, plan->L.elem) || misaligned(g_v, plan->L.elem)) return MPI_ERR_ARG;
-    if (!plan->L.deriv) return MPI_ERR_UNSUPPORTED;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    char* w = static_cast<char*>(work);
-    return plan->dtype == MPI_F64
-               ? traj_vjp_impl<double>(plan, static_cast<const double*>(x), static_cast<const double*>(y),
-                                       static_cast<double*>(g_r), static_cast<double*>(g_v), w, stream)
-               : traj_vjp_impl<float>(plan, static_cast<const float*>(x), static_cast<const float*>(y),
-                                      static_cast<float*>(g_r), static_cast<float*>(g_v), w, stream);
+    return guarded([&]() -> int {
+        int rc = check_call(plan, x, y, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (!g_r || !g_v || misaligned(g_r, plan->L.elem) || misaligned(g_v, plan->L.elem)) return MPI_ERR_ARG;
+        if (!plan->L.deriv) return MPI_ERR_UNSUPPORTED;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        char* w = static_cast<char*>(work);
+        return plan->dtype == MPI_F64
+                   ? traj_vjp_impl<double>(plan, static_cast<const double*>(x), static_cast<const double*>(y),
+                                           static_cast<double*>(g_r), static_cast<double*>(g_v), w, stream)
+                   : traj_vjp_impl<float>(plan, static_cast<const float*>(x), static_cast<const float*>(y),
+                                          static_cast<float*>(g_r), static_cast<float*>(g_v), w, stream);
+    });
 }
 
 int mpi_batch_adjoint_step(const mpi_plan* plan, const void* s, const void* c_in, void* c_out, const double* taus,
                            void* work, size_t work_bytes, hipStream_t stream) {
-    int rc = check_call(plan, s, c_in, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    if (!c_out || misaligned(c_out, plan->L.elem) || !taus) return MPI_ERR_ARG;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    char* w = static_cast<char*>(work);
-    HIP_TRY(hipMemcpyAsync(w + plan->L.w_taus, taus, sizeof(double) * plan->count, hipMemcpyHostToDevice, stream));
-    return plan->dtype == MPI_F64
-               ? adjoint_impl<double, false, 1>(plan, static_cast<const double*>(s), static_cast<double*>(c_out),
-                                                static_cast<const double*>(c_in), w, stream)
-               : adjoint_impl<float, false, 1>(plan, static_cast<const float*>(s), static_cast<float*>(c_out),
-                                               static_cast<const float*>(c_in), w, stream);
+    return guarded([&]() -> int {
+        int rc = check_call(plan, s, c_in, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (!c_out || misaligned(c_out, plan->L.elem) || !taus) return MPI_ERR_ARG;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        char* w = static_cast<char*>(work);
+        HIP_TRY(hipMemcpyAsync(w + plan->L.w_taus, taus, sizeof(double) * plan->count, hipMemcpyHostToDevice, stream));
+        return plan->dtype == MPI_F64
+                   ? adjoint_impl<double, false, 1>(plan, static_cast<const double*>(s), static_cast<double*>(c_out),
+                                                    static_cast<const double*>(c_in), w, stream)
+                   : adjoint_impl<float, false, 1>(plan, static_cast<const float*>(s), static_cast<float*>(c_out),
+                                                   static_cast<const float*>(c_in), w, stream);
+    });
 }
 
 int mpi_batch_denoise(const mpi_plan* plan, const void* u, void* c, double sigma_px, int radius, void* work,
                       size_t work_bytes, hipStream_t stream) {
-    int rc = check_call(plan, u, c, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    if (!(sigma_px > 0.0) || radius < 0 || radius > kDnMaxR || u == c) return MPI_ERR_ARG;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    mpi_plan* pl = const_cast<mpi_plan*>(plan);
-    char* w = static_cast<char*>(work);
-    double sum = 0.0;
-    for (int k = -radius; k <= radius; ++k) {
-        pl->wts[k + radius] = std::exp(-0.5 * k * k / (sigma_px * sigma_px));
-        sum += pl->wts[k + radius];
-    }
-    for (int k = 0; k <= 2 * radius; ++k) pl->wts[k] /= sum;
-    HIP_TRY(hipMemcpyAsync(w + pl->L.w_wts, pl->wts, sizeof(double) * (2 * radius + 1), hipMemcpyHostToDevice,
-                           stream));
-    const dim3 grid(pl->max_dntiles, pl->max_dntiles, pl->count);
-    if (plan->dtype == MPI_F64)
-        k_denoise<double><<<grid, 256, 0, stream>>>(pl->dprob, w, static_cast<const double*>(u),
-                                                    static_cast<double*>(c),
-                                                    reinterpret_cast<const double*>(w + pl->L.w_wts), radius);
-    else
-        k_denoise<float><<<grid, 256, 0, stream>>>(pl->dprob, w, static_cast<const float*>(u),
-                                                   static_cast<float*>(c),
-                                                   reinterpret_cast<const double*>(w + pl->L.w_wts), radius);
-    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    return guarded([&]() -> int {
+        int rc = check_call(plan, u, c, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (!(sigma_px > 0.0) || radius < 0 || radius > kDnMaxR || u == c) return MPI_ERR_ARG;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        mpi_plan* pl = const_cast<mpi_plan*>(plan);
+        char* w = static_cast<char*>(work);
+        double sum = 0.0;
+        for (int k = -radius; k <= radius; ++k) {
+            pl->wts[k + radius] = std::exp(-0.5 * k * k / (sigma_px * sigma_px));
+            sum += pl->wts[k + radius];
+        }
+        for (int k = 0; k <= 2 * radius; ++k) pl->wts[k] /= sum;
+        HIP_TRY(hipMemcpyAsync(w + pl->L.w_wts, pl->wts, sizeof(double) * (2 * radius + 1), hipMemcpyHostToDevice,
+                               stream));
+        const dim3 grid(pl->max_dntiles, pl->max_dntiles, pl->count);
+        if (plan->dtype == MPI_F64)
+            k_denoise<double><<<grid, 256, 0, stream>>>(pl->dprob, w, static_cast<const double*>(u),
+                                                        static_cast<double*>(c),
+                                                        reinterpret_cast<const double*>(w + pl->L.w_wts), radius);
+        else
+            k_denoise<float><<<grid, 256, 0, stream>>>(pl->dprob, w, static_cast<const float*>(u),
+                                                       static_cast<float*>(c),
+                                                       reinterpret_cast<const double*>(w + pl->L.w_wts), radius);
+        return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    });
 }
 
 int mpi_batch_dot(const mpi_plan* plan, const void* a, const void* b, int space, int comp, double* out, void* work,
                   size_t work_bytes, hipStream_t stream) {
-    int rc = check_call(plan, a, b, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    if (!out || (space != 0 && space != 1) || comp < 0 || comp > 2) return MPI_ERR_ARG;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    if (plan->dtype == MPI_F64)
-        launch_dot<double>(plan, static_cast<const double*>(a), static_cast<const double*>(b), space, comp, out, 0,
-                           static_cast<char*>(work), stream);
-    else
-        launch_dot<float>(plan, static_cast<const float*>(a), static_cast<const float*>(b), space, comp, out, 0,
-                          static_cast<char*>(work), stream);
-    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    return guarded([&]() -> int {
+        int rc = check_call(plan, a, b, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (!out || (space != 0 && space != 1) || comp < 0 || comp > 2) return MPI_ERR_ARG;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        if (plan->dtype == MPI_F64)
+            launch_dot<double>(plan, static_cast<const double*>(a), static_cast<const double*>(b), space, comp, out, 0,
+                               static_cast<char*>(work), stream);
+        else
+            launch_dot<float>(plan, static_cast<const float*>(a), static_cast<const float*>(b), space, comp, out, 0,
+                              static_cast<char*>(work), stream);
+        return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    });
 }
 
 int mpi_reduce_lissajous(const mpi_plan* plan, const void* g_r, const void* g_v, const void* rho, const void* nu,
                          double* g_ax, double* g_ay, void* work, size_t work_bytes, hipStream_t stream) {
-    int rc = check_call(plan, g_r, g_v, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    if (!rho || !nu || !g_ax || !g_ay || g_ax == g_ay) return MPI_ERR_ARG;
-    const size_t el = plan->L.elem;
-    if (misaligned(rho, el) || misaligned(nu, el) || misaligned(g_ax, 8) || misaligned(g_ay, 8)) return MPI_ERR_ARG;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    double* part = reinterpret_cast<double*>(static_cast<char*>(work) + plan->L.w_dot);
-    const dim3 grid(kDotParts, plan->count);
-    if (plan->dtype == MPI_F64)
-        k_amp_part<double><<<grid, 256, 0, stream>>>(plan->dprob, static_cast<const double*>(g_r),
-                                                     static_cast<const double*>(g_v), static_cast<const double*>(rho),
-                                                     static_cast<const double*>(nu), part);
-    else
-        k_amp_part<float><<<grid, 256, 0, stream>>>(plan->dprob, static_cast<const float*>(g_r),
-                                                    static_cast<const float*>(g_v), static_cast<const float*>(rho),
-                                                    static_cast<const float*>(nu), part);
-    k_amp_final<<<plan->count, kDotParts, 0, stream>>>(part, g_ax, g_ay);
-    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    return guarded([&]() -> int {
+        int rc = check_call(plan, g_r, g_v, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (!rho || !nu || !g_ax || !g_ay || g_ax == g_ay) return MPI_ERR_ARG;
+        const size_t el = plan->L.elem;
+        if (misaligned(rho, el) || misaligned(nu, el) || misaligned(g_ax, 8) || misaligned(g_ay, 8)) return MPI_ERR_ARG;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        double* part = reinterpret_cast<double*>(static_cast<char*>(work) + plan->L.w_dot);
+        const dim3 grid(kDotParts, plan->count);
+        if (plan->dtype == MPI_F64)
+            k_amp_part<double><<<grid, 256, 0, stream>>>(plan->dprob, static_cast<const double*>(g_r),
+                                                         static_cast<const double*>(g_v), static_cast<const double*>(rho),
+                                                         static_cast<const double*>(nu), part);
+        else
+            k_amp_part<float><<<grid, 256, 0, stream>>>(plan->dprob, static_cast<const float*>(g_r),
+                                                        static_cast<const float*>(g_v), static_cast<const float*>(rho),
+                                                        static_cast<const float*>(nu), part);
+        k_amp_final<<<plan->count, kDotParts, 0, stream>>>(part, g_ax, g_ay);
+        return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    });
 }
 
 int mpi_scale_trajectory(const void* rho, const void* nu, int64_t n_samples, double ax, double ay, int32_t dtype,
                          void* r, void* v, hipStream_t stream) {
-    if (!rho || !nu || !r || !v || n_samples < 1 || n_samples >= kMaxSamples) return MPI_ERR_ARG;
-    if (!std::isfinite(ax) || !std::isfinite(ay)) return MPI_ERR_ARG;
-    if (dtype != MPI_F32 && dtype != MPI_F64) return MPI_ERR_DTYPE;
-    const size_t el = dtype == MPI_F64 ? 8 : 4;
-    if (misaligned(rho, el) || misaligned(nu, el) || misaligned(r, el) || misaligned(v, el)) return MPI_ERR_ARG;
-    if (r == v || r == rho || r == nu || v == rho || v == nu) return MPI_ERR_ARG;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    const int nblk = blocks(n_samples, 256);
-    if (dtype == MPI_F64)
-        k_scale_traj<double><<<nblk, 256, 0, stream>>>(static_cast<const double*>(rho), static_cast<const double*>(nu),
-                                                        n_samples, ax, ay, static_cast<double*>(r),
-                                                        static_cast<double*>(v));
-    else
-        k_scale_traj<float><<<nblk, 256, 0, stream>>>(static_cast<const float*>(rho), static_cast<const float*>(nu),
-                                                       n_samples, ax, ay, static_cast<float*>(r), static_cast<float*>(v));
-    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    return guarded([&]() -> int {
+        if (!rho || !nu || !r || !v || n_samples < 1 || n_samples >= kMaxSamples) return MPI_ERR_ARG;
+        if (!std::isfinite(ax) || !std::isfinite(ay)) return MPI_ERR_ARG;
+        if (dtype != MPI_F32 && dtype != MPI_F64) return MPI_ERR_DTYPE;
+        const size_t el = dtype == MPI_F64 ? 8 : 4;
+        if (misaligned(rho, el) || misaligned(nu, el) || misaligned(r, el) || misaligned(v, el)) return MPI_ERR_ARG;
+        if (r == v || r == rho || r == nu || v == rho || v == nu) return MPI_ERR_ARG;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        const int nblk = blocks(n_samples, 256);
+        if (dtype == MPI_F64)
+            k_scale_traj<double><<<nblk, 256, 0, stream>>>(static_cast<const double*>(rho), static_cast<const double*>(nu),
+                                                            n_samples, ax, ay, static_cast<double*>(r),
+                                                            static_cast<double*>(v));
+        else
+            k_scale_traj<float><<<nblk, 256, 0, stream>>>(static_cast<const float*>(rho), static_cast<const float*>(nu),
+                                                           n_samples, ax, ay, static_cast<float*>(r), static_cast<float*>(v));
+        return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    });
 }
 
 int mpi_batch_unrolled_vjp_bytes(const mpi_plan* plan, int32_t every, size_t* vjp_bytes) {
-    if (!plan || every < 1 || !vjp_bytes) return MPI_ERR_ARG;
-    *vjp_bytes = vjp_layout(plan, every).bytes;
-    return MPI_OK;
+    return guarded([&]() -> int {
+        if (!plan || every < 1 || !vjp_bytes) return MPI_ERR_ARG;
+        *vjp_bytes = vjp_layout(plan, every).bytes;
+        return MPI_OK;
+    });
 }
 
 int mpi_batch_unrolled_vjp(const mpi_plan* plan, const void* s, const void* checkpoints, int32_t n_iter,
                            int32_t every, double denoise_sigma_px, int32_t denoise_radius, const double* taus,
                            void* gbar, double* g_h, void* g_r, void* g_v, void* work, size_t work_bytes,
                            void* vjp_work, size_t vjp_bytes, hipStream_t stream) {
-    int rc = check_call(plan, s, gbar, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    if (!plan->L.deriv) return MPI_ERR_UNSUPPORTED;
-    if (!checkpoints || !g_h || !g_r || !g_v || !vjp_work || !taus || n_iter < 1 || every < 1) return MPI_ERR_ARG;
-    if (denoise_sigma_px > 0.0 && (denoise_radius < 0 || denoise_radius > kDnMaxR)) return MPI_ERR_ARG;
-    const size_t el = plan->L.elem;
-    if (misaligned(checkpoints, el) || misaligned(g_r, el) || misaligned(g_v, el) || misaligned(g_h, 8) ||
-        misaligned(vjp_work, kAlign))
-        return MPI_ERR_ARG;
-    if (vjp_bytes < vjp_layout(plan, every).bytes) return MPI_ERR_WORKSPACE;
-    for (int b = 0; b < plan->count; ++b)
-        if (!std::isfinite(taus[b])) return MPI_ERR_ARG;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    mpi_plan* pl = const_cast<mpi_plan*>(plan);
-    char* w = static_cast<char*>(work);
-    char* vj = static_cast<char*>(vjp_work);
-    const double sigma = denoise_sigma_px > 0.0 ? denoise_sigma_px : 0.0;
-    if (plan->dtype == MPI_F64)
-        return unrolled_vjp_impl<double>(pl, static_cast<const double*>(s), static_cast<const double*>(checkpoints),
-                                         n_iter, every, sigma, denoise_radius, taus, static_cast<double*>(gbar), g_h,
-                                         static_cast<double*>(g_r), static_cast<double*>(g_v), w, vj, stream);
-    return unrolled_vjp_impl<float>(pl, static_cast<const float*>(s), static_cast<const float*>(checkpoints), n_iter,
-                                    every, sigma, denoise_radius, taus, static_cast<float*>(gbar), g_h,
-                                    static_cast<float*>(g_r), static_cast<float*>(g_v), w, vj, stream);
+    return guarded([&]() -> int {
+        int rc = check_call(plan, s, gbar, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (!plan->L.deriv) return MPI_ERR_UNSUPPORTED;
+        if (!checkpoints || !g_h || !g_r || !g_v || !vjp_work || !taus || n_iter < 1 || every < 1) return MPI_ERR_ARG;
+        if (denoise_sigma_px > 0.0 && (denoise_radius < 0 || denoise_radius > kDnMaxR)) return MPI_ERR_ARG;
+        const size_t el = plan->L.elem;
+        if (misaligned(checkpoints, el) || misaligned(g_r, el) || misaligned(g_v, el) || misaligned(g_h, 8) ||
+            misaligned(vjp_work, kAlign))
+            return MPI_ERR_ARG;
+        if (vjp_bytes < vjp_layout(plan, every).bytes) return MPI_ERR_WORKSPACE;
+        for (int b = 0; b < plan->count; ++b)
+            if (!std::isfinite(taus[b])) return MPI_ERR_ARG;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        mpi_plan* pl = const_cast<mpi_plan*>(plan);
+        char* w = static_cast<char*>(work);
+        char* vj = static_cast<char*>(vjp_work);
+        const double sigma = denoise_sigma_px > 0.0 ? denoise_sigma_px : 0.0;
+        if (plan->dtype == MPI_F64)
+            return unrolled_vjp_impl<double>(pl, static_cast<const double*>(s), static_cast<const double*>(checkpoints),
+                                             n_iter, every, sigma, denoise_radius, taus, static_cast<double*>(gbar), g_h,
+                                             static_cast<double*>(g_r), static_cast<double*>(g_v), w, vj, stream);
+        return unrolled_vjp_impl<float>(pl, static_cast<const float*>(s), static_cast<const float*>(checkpoints), n_iter,
+                                        every, sigma, denoise_radius, taus, static_cast<float*>(gbar), g_h,
+                                        static_cast<float*>(g_r), static_cast<float*>(g_v), w, vj, stream);
+    });
 }
 
 int mpi_batch_deconv_bytes(const mpi_plan* plan, size_t* bytes) {
-    if (!plan || !bytes) return MPI_ERR_ARG;
-    *bytes = deconv_layout(plan).bytes;
-    return MPI_OK;
+    return guarded([&]() -> int {
+        if (!plan || !bytes) return MPI_ERR_ARG;
+        *bytes = deconv_layout(plan).bytes;
+        return MPI_OK;
+    });
 }
 
 int mpi_batch_trace_conv(const mpi_plan* plan, const void* x, void* y, void* work, size_t work_bytes,
                          hipStream_t stream) {
-    int rc = check_call(plan, x, y, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    if (x == y) return MPI_ERR_ARG;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    char* w = static_cast<char*>(work);
-    if (plan->dtype == MPI_F64)
-        trace_conv_impl<double>(plan, static_cast<const double*>(x), static_cast<double*>(y), w, stream, nullptr);
-    else
-        trace_conv_impl<float>(plan, static_cast<const float*>(x), static_cast<float*>(y), w, stream, nullptr);
-    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    return guarded([&]() -> int {
+        int rc = check_call(plan, x, y, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (x == y) return MPI_ERR_ARG;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        char* w = static_cast<char*>(work);
+        if (plan->dtype == MPI_F64)
+            trace_conv_impl<double>(plan, static_cast<const double*>(x), static_cast<double*>(y), w, stream, nullptr);
+        else
+            trace_conv_impl<float>(plan, static_cast<const float*>(x), static_cast<float*>(y), w, stream, nullptr);
+        return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    });
 }
 
 int mpi_batch_cg(const mpi_plan* plan, const void* rhs, void* x, const double* nus, double tol, int32_t max_iter,
                  int32_t* iters, void* work, size_t work_bytes, void* dwork, size_t dbytes, hipStream_t stream) {
-    int rc = check_deconv(plan, rhs, x, work, work_bytes, dwork, dbytes);
-    if (rc != MPI_OK) return rc;
-    if (!nus || rhs == x || !(tol >= 0.0) || max_iter < 0) return MPI_ERR_ARG;
-    for (int b = 0; b < plan->count; ++b)
-        if (!(nus[b] >= 0.0) || !std::isfinite(nus[b])) return MPI_ERR_ARG;
-    const DeconvLayout L = deconv_layout(plan);
-    char* w = static_cast<char*>(work);
-    char* dw = static_cast<char*>(dwork);
-    HIP_TRY(hipMemcpyAsync(dw + L.nu, nus, sizeof(double) * plan->count, hipMemcpyHostToDevice, stream));
-    mpi_plan* pl = const_cast<mpi_plan*>(plan);
-    return plan->dtype == MPI_F64
-               ? cg_impl<double>(pl, static_cast<const double*>(rhs), nullptr, static_cast<double*>(x), tol,
-                                 max_iter, w, dw, L, stream, iters)
-               : cg_impl<float>(pl, static_cast<const float*>(rhs), nullptr, static_cast<float*>(x), tol, max_iter, w,
-                                dw, L, stream, iters);
+    return guarded([&]() -> int {
+        int rc = check_deconv(plan, rhs, x, work, work_bytes, dwork, dbytes);
+        if (rc != MPI_OK) return rc;
+        if (!nus || rhs == x || !(tol >= 0.0) || max_iter < 0) return MPI_ERR_ARG;
+        for (int b = 0; b < plan->count; ++b)
+            if (!(nus[b] >= 0.0) || !std::isfinite(nus[b])) return MPI_ERR_ARG;
+        const DeconvLayout L = deconv_layout(plan);
+        char* w = static_cast<char*>(work);
+        char* dw = static_cast<char*>(dwork);
+        HIP_TRY(hipMemcpyAsync(dw + L.nu, nus, sizeof(double) * plan->count, hipMemcpyHostToDevice, stream));
+        mpi_plan* pl = const_cast<mpi_plan*>(plan);
+        return plan->dtype == MPI_F64
+                   ? cg_impl<double>(pl, static_cast<const double*>(rhs), nullptr, static_cast<double*>(x), tol,
+                                     max_iter, w, dw, L, stream, iters)
+                   : cg_impl<float>(pl, static_cast<const float*>(rhs), nullptr, static_cast<float*>(x), tol, max_iter, w,
+                                    dw, L, stream, iters);
+    });
 }
 
 int mpi_batch_trim_sigma(const mpi_plan* plan, void* x, double pct, double* q, double* sigma, void* work,
                          size_t work_bytes, void* dwork, size_t dbytes, hipStream_t stream) {
-    int rc = check_deconv(plan, x, x, work, work_bytes, dwork, dbytes);
-    if (rc != MPI_OK) return rc;
-    if (!(pct <= 100.0) || std::isnan(pct)) return MPI_ERR_ARG;
-    const DeconvLayout L = deconv_layout(plan);
-    std::vector<double> var(plan->count);
-    char* dw = static_cast<char*>(dwork);
-    rc = plan->dtype == MPI_F64
-             ? trim_and_variance<double>(plan, static_cast<double*>(x), pct, dw, L, stream, var.data(), q)
-             : trim_and_variance<float>(plan, static_cast<float*>(x), pct, dw, L, stream, var.data(), q);
-    if (rc != MPI_OK) return rc;
-    if (sigma)
-        for (int b = 0; b < plan->count; ++b) sigma[b] = std::sqrt(var[b]);
-    return MPI_OK;
+    return guarded([&]() -> int {
+        int rc = check_deconv(plan, x, x, work, work_bytes, dwork, dbytes);
+        if (rc != MPI_OK) return rc;
+        if (!(pct <= 100.0) || std::isnan(pct)) return MPI_ERR_ARG;
+        const DeconvLayout L = deconv_layout(plan);
+        std::vector<double> var(plan->count);
+        char* dw = static_cast<char*>(dwork);
+        rc = plan->dtype == MPI_F64
+                 ? trim_and_variance<double>(plan, static_cast<double*>(x), pct, dw, L, stream, var.data(), q)
+                 : trim_and_variance<float>(plan, static_cast<float*>(x), pct, dw, L, stream, var.data(), q);
+        if (rc != MPI_OK) return rc;
+        if (sigma)
+            for (int b = 0; b < plan->count; ++b) sigma[b] = std::sqrt(var[b]);
+        return MPI_OK;
+    });
 }
 
 int mpi_batch_pnp(const mpi_plan* plan, const void* u, void* rho, const mpi_pnp_params* params, int32_t* cg_iters,
                   double* sigmas, double* nus, void* work, size_t work_bytes, void* dwork, size_t dbytes,
                   hipStream_t stream) {
-    int rc = check_deconv(plan, u, rho, work, work_bytes, dwork, dbytes);
-    if (rc != MPI_OK) return rc;
-    if (!params || u == rho || params->n_it < 0 || params->cg_max_iter < 0 || !(params->nu0 > 0.0) ||
-        !std::isfinite(params->nu0) || !(params->cg_tol >= 0.0) || !(params->clip_percentile <= 100.0))
-        return MPI_ERR_ARG;
-    if (params->denoise_sigma_px > 0.0 && (params->denoise_radius < 0 || params->denoise_radius > kDnMaxR))
-        return MPI_ERR_ARG;
-    mpi_plan* pl = const_cast<mpi_plan*>(plan);
-    char* w = static_cast<char*>(work);
-    char* dw = static_cast<char*>(dwork);
-    return plan->dtype == MPI_F64
-               ? pnp_impl<double>(pl, static_cast<const double*>(u), static_cast<double*>(rho), params, cg_iters,
-                                  sigmas, nus, w, dw, stream)
-               : pnp_impl<float>(pl, static_cast<const float*>(u), static_cast<float*>(rho), params, cg_iters, sigmas,
-                                 nus, w, dw, stream);
+    return guarded([&]() -> int {
+        int rc = check_deconv(plan, u, rho, work, work_bytes, dwork, dbytes);
+        if (rc != MPI_OK) return rc;
+        if (!params || u == rho || params->n_it < 0 || params->cg_max_iter < 0 || !(params->nu0 > 0.0) ||
+            !std::isfinite(params->nu0) || !(params->cg_tol >= 0.0) || !(params->clip_percentile <= 100.0))
+            return MPI_ERR_ARG;
+        if (params->denoise_sigma_px > 0.0 && (params->denoise_radius < 0 || params->denoise_radius > kDnMaxR))
+            return MPI_ERR_ARG;
+        mpi_plan* pl = const_cast<mpi_plan*>(plan);
+        char* w = static_cast<char*>(work);
+        char* dw = static_cast<char*>(dwork);
+        return plan->dtype == MPI_F64
+                   ? pnp_impl<double>(pl, static_cast<const double*>(u), static_cast<double*>(rho), params, cg_iters,
+                                      sigmas, nus, w, dw, stream)
+                   : pnp_impl<float>(pl, static_cast<const float*>(u), static_cast<float*>(rho), params, cg_iters, sigmas,
+                                     nus, w, dw, stream);
+    });
 }
 
 int mpi_batch_core_bytes(const mpi_plan* plan, size_t* bytes) {
-    if (!plan || !bytes) return MPI_ERR_ARG;
-    *bytes = core_layout(plan).bytes;
-    return MPI_OK;
+    return guarded([&]() -> int {
+        if (!plan || !bytes) return MPI_ERR_ARG;
+        *bytes = core_layout(plan).bytes;
+        return MPI_OK;
+    });
 }
 
 int mpi_batch_core_stage(const mpi_plan* plan, const void* s, void* field, double gamma, double tol, int32_t max_iter,
                          int32_t* iters, void* work, size_t work_bytes, void* cwork, size_t cbytes,
                          hipStream_t stream) {
-    int rc = check_call(plan, s, field, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    if (!cwork || misaligned(cwork, kAlign) || !(gamma >= 0.0) || !std::isfinite(gamma) || !(tol >= 0.0) ||
-        max_iter < 0)
-        return MPI_ERR_ARG;
-    if (cbytes < core_layout(plan).bytes) return MPI_ERR_WORKSPACE;
-    if (core_scatter_smem(plan) > kSmemLimit || core_dir_smem(plan) > kSmemLimit) return MPI_ERR_UNSUPPORTED;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    mpi_plan* pl = const_cast<mpi_plan*>(plan);
-    char* cw = static_cast<char*>(cwork);
-    return plan->dtype == MPI_F64
-               ? core_impl<double>(pl, static_cast<const double*>(s), static_cast<double*>(field), gamma, tol,
-                                   max_iter, cw, stream, iters)
-               : core_impl<float>(pl, static_cast<const float*>(s), static_cast<float*>(field), gamma, tol, max_iter,
-                                  cw, stream, iters);
+    return guarded([&]() -> int {
+        int rc = check_call(plan, s, field, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (!cwork || misaligned(cwork, kAlign) || !(gamma >= 0.0) || !std::isfinite(gamma) || !(tol >= 0.0) ||
+            max_iter < 0)
+            return MPI_ERR_ARG;
+        if (cbytes < core_layout(plan).bytes) return MPI_ERR_WORKSPACE;
+        if (core_scatter_smem(plan) > kSmemLimit || core_dir_smem(plan) > kSmemLimit) return MPI_ERR_UNSUPPORTED;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        mpi_plan* pl = const_cast<mpi_plan*>(plan);
+        char* cw = static_cast<char*>(cwork);
+        return plan->dtype == MPI_F64
+                   ? core_impl<double>(pl, static_cast<const double*>(s), static_cast<double*>(field), gamma, tol,
+                                       max_iter, cw, stream, iters)
+                   : core_impl<float>(pl, static_cast<const float*>(s), static_cast<float*>(field), gamma, tol, max_iter,
+                                      cw, stream, iters);
+    });
 }
 
 int mpi_velocity_forward_difference(const void* r, void* v, int64_t n_samples, double dt, int32_t dtype,
                                     hipStream_t stream) {
-    if (!r || !v || r == v || n_samples < 2 || !(dt > 0.0) || !std::isfinite(dt)) return MPI_ERR_ARG;
-    if (dtype != MPI_F32 && dtype != MPI_F64) return MPI_ERR_DTYPE;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    if (dtype == MPI_F64)
-        k_forward_difference<double><<<blocks(n_samples, 256), 256, 0, stream>>>(
-            static_cast<const double*>(r), static_cast<double*>(v), n_samples, dt);
-    else
-        k_forward_difference<float><<<blocks(n_samples, 256), 256, 0, stream>>>(
-            static_cast<const float*>(r), static_cast<float*>(v), n_samples, dt);
-    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    return guarded([&]() -> int {
+        if (!r || !v || r == v || n_samples < 2 || !(dt > 0.0) || !std::isfinite(dt)) return MPI_ERR_ARG;
+        if (dtype != MPI_F32 && dtype != MPI_F64) return MPI_ERR_DTYPE;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        if (dtype == MPI_F64)
+            k_forward_difference<double><<<blocks(n_samples, 256), 256, 0, stream>>>(
+                static_cast<const double*>(r), static_cast<double*>(v), n_samples, dt);
+        else
+            k_forward_difference<float><<<blocks(n_samples, 256), 256, 0, stream>>>(
+                static_cast<const float*>(r), static_cast<float*>(v), n_samples, dt);
+        return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    });
 }
 
 int mpi_batch_field_trace(const mpi_plan* plan, const void* field, void* u, hipStream_t stream) {
-    if (!plan || !field || !u || field == u) return MPI_ERR_ARG;
-    const size_t el = plan->L.elem;
-    if (misaligned(field, el) || misaligned(u, el)) return MPI_ERR_ARG;
-    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-    const dim3 grid(blocks(int64_t(plan->max_n) * plan->max_n, 256), plan->count);
-    if (plan->dtype == MPI_F64)
-        k_field_trace<double><<<grid, 256, 0, stream>>>(plan->dprob, static_cast<const double*>(field),
-                                                        static_cast<double*>(u));
-    else
-        k_field_trace<float><<<grid, 256, 0, stream>>>(plan->dprob, static_cast<const float*>(field),
-                                                       static_cast<float*>(u));
-    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    return guarded([&]() -> int {
+        if (!plan || !field || !u || field == u) return MPI_ERR_ARG;
+        const size_t el = plan->L.elem;
+        if (misaligned(field, el) || misaligned(u, el)) return MPI_ERR_ARG;
+        if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+        const dim3 grid(blocks(int64_t(plan->max_n) * plan->max_n, 256), plan->count);
+        if (plan->dtype == MPI_F64)
+            k_field_trace<double><<<grid, 256, 0, stream>>>(plan->dprob, static_cast<const double*>(field),
+                                                            static_cast<double*>(u));
+        else
+            k_field_trace<float><<<grid, 256, 0, stream>>>(plan->dprob, static_cast<const float*>(field),
+                                                           static_cast<float*>(u));
+        return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    });
 }
 
 int mpi_stage_count(const mpi_plan* plan) {
-    if (!plan) return MPI_ERR_ARG;
-    return kFwdStages + kAdjStages;
+    return guarded([&]() -> int {
+        if (!plan) return MPI_ERR_ARG;
+        return kFwdStages + kAdjStages;
+    });
 }
 
 const char* mpi_stage_name(const mpi_plan* plan, int stage) {
@@ -2168,46 +2257,77 @@ const char* mpi_stage_name(const mpi_plan* plan, int stage) {
 
 int mpi_stage_launch(const mpi_plan* plan, int stage, int reps, void* c, void* s, void* work, size_t work_bytes,
                      hipStream_t stream) {
-    int rc = check_call(plan, c, s, work, work_bytes);
-    if (rc != MPI_OK) return rc;
-    if (stage < 0 || stage >= kFwdStages + kAdjStages || reps < 0) return MPI_ERR_ARG;
-    char* w = static_cast<char*>(work);
-    for (int r = 0; r < reps; ++r) {
-        if (plan->dtype == MPI_F64) {
-            if (stage < kFwdStages)
-                fwd_stage<double, 0>(plan, stage, static_cast<const double*>(c),
-                                     GatherIO<double>{static_cast<double*>(s)}, w, stream);
-            else
-                adj_stage<double, false, 0>(plan, stage - kFwdStages, static_cast<const double*>(s),
-                                            static_cast<double*>(c), nullptr, w, stream);
-        } else {
-            if (stage < kFwdStages)
-                fwd_stage<float, 0>(plan, stage, static_cast<const float*>(c),
-                                    GatherIO<float>{static_cast<float*>(s)}, w, stream);
-            else
-                adj_stage<float, false, 0>(plan, stage - kFwdStages, static_cast<const float*>(s),
-                                           static_cast<float*>(c), nullptr, w, stream);
+    return guarded([&]() -> int {
+        int rc = check_call(plan, c, s, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (stage < 0 || stage >= kFwdStages + kAdjStages || reps < 0) return MPI_ERR_ARG;
+        char* w = static_cast<char*>(work);
+        for (int r = 0; r < reps; ++r) {
+            if (plan->dtype == MPI_F64) {
+                if (stage < kFwdStages)
+                    fwd_stage<double, 0>(plan, stage, static_cast<const double*>(c),
+                                         GatherIO<double>{static_cast<double*>(s)}, w, stream);
+                else
+                    adj_stage<double, false, 0>(plan, stage - kFwdStages, static_cast<const double*>(s),
+                                                static_cast<double*>(c), nullptr, w, stream);
+            } else {
+                if (stage < kFwdStages)
+                    fwd_stage<float, 0>(plan, stage, static_cast<const float*>(c),
+                                        GatherIO<float>{static_cast<float*>(s)}, w, stream);
+                else
+                    adj_stage<float, false, 0>(plan, stage - kFwdStages, static_cast<const float*>(s),
+                                               static_cast<float*>(c), nullptr, w, stream);
+            }
         }
-    }
-    return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+        return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
+    });
+}
+
+int mpi_checks_enabled(void) {
+#ifdef MPIK_CHECK
+    return 1;
+#else
+    return 0;
+#endif
+}
+
+int mpi_plan_check(const mpi_plan* plan, int32_t* word, hipStream_t stream) {
+    return guarded([&]() -> int {
+        if (!plan || !word) return MPI_ERR_ARG;
+        alloc_point();
+        std::vector<int32_t> errs(4 * size_t(plan->count), 0);
+        for (int b = 0; b < plan->count; ++b)
+            HIP_TRY(hipMemcpyAsync(&errs[4 * b], plan->plan + plan->L.probs[b].o_err, 16, hipMemcpyDeviceToHost,
+                                   stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        int32_t w = 0;
+        for (int b = 0; b < plan->count; ++b) w |= errs[4 * b + 1];
+        *word = w;
+        return MPI_OK;
+    });
+}
+
+int mpi_debug_fail_alloc(int32_t k) {
+    if (k < 0) return MPI_ERR_ARG;
+    g_fail_at.store(0, std::memory_order_relaxed);
+    g_points_seen.store(0, std::memory_order_relaxed);
+    g_fail_at.store(k, std::memory_order_relaxed);
+    return MPI_OK;
 }
 
 int mpi_plan_destroy(mpi_plan* plan) {
-    if (!plan) return MPI_ERR_ARG;
-    if (plan->gexec) {
-        (void)hipDeviceSynchronize();
-        (void)hipGraphExecDestroy(plan->gexec);
-        (void)hipGraphDestroy(plan->graph);
-    }
-    for (mpi_plan::GraphCache* gc : {&plan->cg_gc, &plan->core_gc, &plan->iter_gc})
-        if (gc->exec) {
-            (void)hipDeviceSynchronize();
-            (void)hipGraphExecDestroy(gc->exec);
-            (void)hipGraphDestroy(gc->graph);
-        }
-    release_streams(plan);
-    delete plan;
-    return MPI_OK;
+    return guarded([&]() -> int {
+        if (!plan) return MPI_ERR_ARG;
+        for (mpi_plan::GraphCache* gc : {&plan->one_gc, &plan->iter_gc, &plan->cg_gc, &plan->core_gc})
+            if (gc->exec) {
+                (void)hipDeviceSynchronize();
+                (void)hipGraphExecDestroy(gc->exec);
+                (void)hipGraphDestroy(gc->graph);
+            }
+        release_streams(plan);
+        delete plan;
+        return MPI_OK;
+    });
 }
 
 }  // extern "C"

@@ -41,6 +41,17 @@ template <typename T, int U> struct GatherRecs {
     vec4<T> e[U];
     int2 id[U];
     vec2<T> y[U];
+#ifdef MPIK_CHECK
+    bool valid[U];       // the record's base cell and time index passed the checks
+#endif
+    __device__ __forceinline__ bool usable(int u) const {
+#ifdef MPIK_CHECK
+        return valid[u];
+#else
+        (void)u;
+        return true;
+#endif
+    }
 };
 
 // chx (x receive channel alone): the y components of the signals read are
@@ -49,13 +60,16 @@ template <typename T, int MODE, int U>
 __device__ __forceinline__ void gather_fetch(GatherRecs<T, U>& r, int base, int p1, int nthreads,
                                              const vec4<T>* __restrict__ samp, const int2* __restrict__ sidx,
                                              const vec2<T>* __restrict__ ysort, const T* __restrict__ in0,
-                                             bool chx) {
+                                             bool chx, const Chk& ck) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int p = base + u * nthreads;
         if (p < p1) {
             r.e[u] = samp[p];
             r.id[u] = sidx[p];
+#ifdef MPIK_CHECK
+            r.valid[u] = ck.cell(r.id[u].x) && ck.time(r.id[u].y);
+#endif
             if (MODE == 1 || MODE == 5) r.y[u] = ysort[p];
             if (MODE == 6) {
                 r.y[u].x = in0[2 * p];
@@ -67,7 +81,7 @@ __device__ __forceinline__ void gather_fetch(GatherRecs<T, U>& r, int base, int 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int p = base + u * nthreads;
-            if (p < p1) {
+            if (p < p1 && r.usable(u)) {
                 r.y[u].x = in0[2 * r.id[u].y];
                 r.y[u].y = in0[2 * r.id[u].y + 1];
             }
@@ -93,6 +107,7 @@ __device__ __forceinline__ void gather_apply(const GatherRecs<T, U>& r, int base
     for (int u = 0; u < U; ++u) {
         const int p = base + u * nthreads;
         if (p >= p1) break;
+        if (!r.usable(u)) continue;
         const int i0 = r.id[u].x & 0xffff;
         const T fx = r.e[u].x, fy = r.e[u].y, gx = T(1) - fx, gy = T(1) - fy;
         vec2<T> sl;                       // weight slopes (read here: kept out of the prefetched records)
@@ -183,7 +198,8 @@ __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int
                                             T* __restrict__ out0, const T* __restrict__ in0, T* __restrict__ out1,
                                             T* __restrict__ out2, T* __restrict__ f, int64_t fstride,
                                             const vec2<T>* __restrict__ dw, bool chx, int tid, int nthreads,
-                                            const GatherRecs<T, U>* first = nullptr, double* sq = nullptr) {
+                                            const Chk& ck, const GatherRecs<T, U>* first = nullptr,
+                                            double* sq = nullptr) {
     int base = p0 + tid;
     if (first) {
         if (base < p1) gather_apply<T, MODE, U>(*first, base, p1, nthreads, g0, g1, N, out_sorted, out0, out1, out2, f,
@@ -192,7 +208,7 @@ __device__ __forceinline__ void gather_band(const T* g0, const T* g1, int N, int
     }
     for (; base < p1; base += U * nthreads) {
         GatherRecs<T, U> r;
-        gather_fetch<T, MODE, U>(r, base, p1, nthreads, samp, sidx, ysort, in0, chx);
+        gather_fetch<T, MODE, U>(r, base, p1, nthreads, samp, sidx, ysort, in0, chx, ck);
         gather_apply<T, MODE, U>(r, base, p1, nthreads, g0, g1, N, out_sorted, out0, out1, out2, f, fstride, dw, chx,
                                  sq);
     }
@@ -246,12 +262,18 @@ template <typename T, bool SORTED, int NT, int U = 4>
 __device__ __forceinline__ void scatter_row(T* g, ScatterLds<T> sm, int N, int j,
                                             const int* __restrict__ binstart, const vec4<T>* __restrict__ samp,
                                             const int2* __restrict__ sidx, const vec2<T>* __restrict__ ys,
-                                            const T* __restrict__ s_time, int tid, bool chx) {
+                                            const T* __restrict__ s_time, int tid, bool chx, const Chk& ck) {
     const int nb = N - 1;
     const int rlo = max(j - 1, 0), rhi = min(j, nb - 1);       // base-cell rows that reach row j
     const int nkeys = 2 * nb;
     for (int i = tid; i < nkeys * 6; i += NT) sm.K[i] = T(0);
+#ifdef MPIK_CHECK
+    int P0 = binstart[rlo * nb], P1 = binstart[(rhi + 1) * nb];
+    ck.range(P0, P1);
+#else
+    (void)ck;
     const int P0 = binstart[rlo * nb], P1 = binstart[(rhi + 1) * nb];
+#endif
     const int E = (P1 - P0 + NT - 1) / NT;
     const int a = min(P0 + tid * E, P1), b = min(a + E, P1);
     int fk = -1, lk = -1;
@@ -263,18 +285,28 @@ __device__ __forceinline__ void scatter_row(T* g, ScatterLds<T> sm, int N, int j
         vec4<T> e[U];
         int2 id[U];
         vec2<T> y[U];
+#ifdef MPIK_CHECK
+        bool use[U];
+#endif
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (base + u < b) {
                 e[u] = samp[base + u];
                 id[u] = sidx[base + u];
                 if (SORTED) y[u] = ys[base + u];
+#ifdef MPIK_CHECK
+                use[u] = ck.cell_near(id[u].x, j) && (SORTED || ck.time(id[u].y));
+#endif
             }
         }
         if (!SORTED) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
+#ifdef MPIK_CHECK
+                if (base + u < b && use[u]) {
+#else
                 if (base + u < b) {
+#endif
                     const int k = id[u].y;
                     y[u].x = s_time[2 * k];
                     y[u].y = s_time[2 * k + 1];
@@ -288,6 +320,9 @@ __device__ __forceinline__ void scatter_row(T* g, ScatterLds<T> sm, int N, int j
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (base + u >= b) break;
+#ifdef MPIK_CHECK
+            if (!use[u]) continue;
+#endif
             const int i0 = id[u].x & 0xffff, j0 = id[u].x >> 16;
             const int key = (j0 - (j - 1)) * nb + i0;      // 0 .. nb-1: row j-1, nb .. 2nb-1: row j
             if (key != lk) {

@@ -12,10 +12,17 @@ import os
 
 import torch
 
-_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmpik.so")
+_PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+# MPIK_LIBRARY selects another build of the library (a file name in this
+# package, e.g. libmpik_check.so, or an absolute path); default libmpik.so.
+_LIB_PATH = os.path.join(_PKG_DIR, os.environ.get("MPIK_LIBRARY") or "libmpik.so")
+CHECK_LIBRARY = os.path.join(_PKG_DIR, "libmpik_check.so")
+# (class, check word) of every plan of the bounds-checked build that closed
+# with a check failed
+CHECK_FAILURES: list[tuple[str, int]] = []
 
 MPI_OK, MPI_ERR_ARG, MPI_ERR_DOMAIN, MPI_ERR_WORKSPACE = 0, -1, -2, -3
-MPI_ERR_DTYPE, MPI_ERR_HIP, MPI_ERR_UNSUPPORTED = -4, -5, -6
+MPI_ERR_DTYPE, MPI_ERR_HIP, MPI_ERR_UNSUPPORTED, MPI_ERR_ALLOC = -4, -5, -6, -7
 MPI_F32, MPI_F64 = 0, 1
 CONV_MODES = {"auto": 0, "direct": 1, "fft": 2}
 INTERPS = {"bilinear": 0, "cosine": 1}
@@ -30,6 +37,7 @@ EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "
            "mpi_batch_deconv_bytes", "mpi_batch_trace_conv", "mpi_batch_cg", "mpi_batch_trim_sigma", "mpi_batch_pnp",
            "mpi_batch_core_bytes", "mpi_batch_core_stage", "mpi_batch_field_trace", "mpi_velocity_forward_difference",
            "mpi_scale_trajectory", "mpi_reduce_lissajous",
+           "mpi_checks_enabled", "mpi_plan_check", "mpi_debug_fail_alloc",
            "mpi_plan_destroy", "mpi_status_str", "mpi_abi_version")
 MPI_BUILD_TUNE, MPI_BUILD_COL_SPLIT, MPI_BUILD_COL_WAVE, MPI_BUILD_DERIV = 1, 2, 4, 8
 NOALLOC_SCRATCH_BYTES = 64 << 20     # MPI_NOALLOC_SCRATCH_BYTES: the allocation-free pair's work memory
@@ -60,84 +68,111 @@ class PnpParams(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
-_lib = None
+_libs: dict[str, ctypes.CDLL] = {}
+_current = [_LIB_PATH]
 
 
 def lib() -> ctypes.CDLL:
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            raise RuntimeError(f"{_LIB_PATH} is missing: build it with `python -m paper_2505_22797_amd.build`")
-        L = ctypes.CDLL(_LIB_PATH)
-        vp, sz = ctypes.c_void_p, ctypes.c_size_t
-        L.mpi_plan_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(sz), ctypes.POINTER(sz)]
-        L.mpi_kernel_build.argtypes = [ctypes.POINTER(Problem), vp, sz, vp, ctypes.POINTER(vp)]
-        L.mpi_forward.argtypes = [vp, vp, vp, vp, sz, vp]
-        L.mpi_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
-        L.mpi_iterate.argtypes = [vp, vp, vp, ctypes.POINTER(IterParams), vp, sz, vp]
-        L.mpi_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                    ctypes.POINTER(ctypes.c_int32)]
-        i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
-        L.mpi_batch_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz),
-                                      ctypes.POINTER(sz)]
-        L.mpi_batch_build.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, vp, sz, vp, sz, ctypes.c_int, vp,
-                                      ctypes.POINTER(vp)]
-        L.mpi_batch_count.argtypes = [vp]
-        L.mpi_batch_offsets.argtypes = [vp, i64p, i64p]
-        L.mpi_batch_info.argtypes = [vp, ctypes.c_int, i32p, i32p, i32p, i32p]
-        L.mpi_batch_forward.argtypes = [vp, vp, vp, vp, sz, vp]
-        L.mpi_batch_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
-        L.mpi_batch_pair.argtypes = [vp, vp, vp, vp, vp, sz, vp]
-        L.mpi_batch_pair_noalloc.argtypes = [vp, vp, vp, vp, vp]
-        L.mpi_batch_iterate.argtypes = [vp, vp, vp, ctypes.POINTER(IterParams), ctypes.POINTER(ctypes.c_double),
-                                        vp, sz, vp]
-        L.mpi_batch_forward_dh.argtypes = [vp, vp, vp, vp, sz, vp]
-        L.mpi_batch_residual.argtypes = [vp, vp, vp, vp, vp, sz, vp]
-        L.mpi_batch_traj_vjp.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
-        L.mpi_batch_adjoint_step.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
-        L.mpi_batch_denoise.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, vp, sz, vp]
-        L.mpi_batch_dot.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, sz, vp]
-        L.mpi_batch_sample_order.argtypes = [vp, ctypes.c_int, vp, vp, vp]
-        L.mpi_batch_unrolled_vjp_bytes.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(sz)]
-        L.mpi_batch_unrolled_vjp.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
-                                             ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp, vp, sz,
-                                             vp, sz, vp]
-        dp = ctypes.POINTER(ctypes.c_double)
-        L.mpi_batch_deconv_bytes.argtypes = [vp, ctypes.POINTER(sz)]
-        L.mpi_batch_trace_conv.argtypes = [vp, vp, vp, vp, sz, vp]
-        L.mpi_batch_cg.argtypes = [vp, vp, vp, dp, ctypes.c_double, ctypes.c_int32, i32p, vp, sz, vp, sz, vp]
-        L.mpi_batch_trim_sigma.argtypes = [vp, vp, ctypes.c_double, dp, dp, vp, sz, vp, sz, vp]
-        L.mpi_batch_pnp.argtypes = [vp, vp, vp, ctypes.POINTER(PnpParams), i32p, dp, dp, vp, sz, vp, sz, vp]
-        L.mpi_batch_core_bytes.argtypes = [vp, ctypes.POINTER(sz)]
-        L.mpi_batch_core_stage.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, i32p, vp, sz,
-                                           vp, sz, vp]
-        L.mpi_batch_field_trace.argtypes = [vp, vp, vp, vp]
-        L.mpi_velocity_forward_difference.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, vp]
-        L.mpi_scale_trajectory.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
-                                           vp, vp, vp]
-        L.mpi_reduce_lissajous.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
-        L.mpi_stage_count.argtypes = [vp]
-        L.mpi_stage_name.argtypes = [vp, ctypes.c_int]
-        L.mpi_stage_name.restype = ctypes.c_char_p
-        L.mpi_stage_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, sz, vp]
-        L.mpi_plan_destroy.argtypes = [vp]
-        L.mpi_status_str.argtypes = [ctypes.c_int]
-        L.mpi_status_str.restype = ctypes.c_char_p
-        L.mpi_abi_version.argtypes = []
-        for name in ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
-                     "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
-                     "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_pair",
-                     "mpi_batch_pair_noalloc", "mpi_batch_iterate", "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
-                     "mpi_batch_dot", "mpi_batch_unrolled_vjp_bytes", "mpi_batch_unrolled_vjp",
-                     "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_launch",
-                     "mpi_batch_deconv_bytes", "mpi_batch_trace_conv", "mpi_batch_cg", "mpi_batch_trim_sigma",
-                     "mpi_batch_pnp", "mpi_batch_core_bytes", "mpi_batch_core_stage", "mpi_batch_field_trace",
-                     "mpi_velocity_forward_difference", "mpi_scale_trajectory", "mpi_reduce_lissajous",
-                     "mpi_plan_destroy",
-                     "mpi_abi_version"):
-            getattr(L, name).restype = ctypes.c_int
-        _lib = L
-    return _lib
+    """The library calls go to: libmpik.so unless MPIK_LIBRARY or
+    use_library chose another build.  Plans keep the library they were built
+    with."""
+    path = _current[-1]
+    if path not in _libs:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_2505_22797_amd.build`")
+        _libs[path] = _load(path)
+    return _libs[path]
+
+
+class use_library:
+    """Context manager: plans built inside use the library at `path` (e.g.
+    CHECK_LIBRARY, the bounds-checked build) for their whole life."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        _current.append(self.path)
+        return lib()
+
+    def __exit__(self, *exc):
+        _current.pop()
+        return False
+
+
+def _load(path: str) -> ctypes.CDLL:
+    L = ctypes.CDLL(path)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    L.mpi_plan_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    L.mpi_kernel_build.argtypes = [ctypes.POINTER(Problem), vp, sz, vp, ctypes.POINTER(vp)]
+    L.mpi_forward.argtypes = [vp, vp, vp, vp, sz, vp]
+    L.mpi_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
+    L.mpi_iterate.argtypes = [vp, vp, vp, ctypes.POINTER(IterParams), vp, sz, vp]
+    L.mpi_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_int32)]
+    i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+    L.mpi_batch_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz),
+                                  ctypes.POINTER(sz)]
+    L.mpi_batch_build.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, vp, sz, vp, sz, ctypes.c_int, vp,
+                                  ctypes.POINTER(vp)]
+    L.mpi_batch_count.argtypes = [vp]
+    L.mpi_batch_offsets.argtypes = [vp, i64p, i64p]
+    L.mpi_batch_info.argtypes = [vp, ctypes.c_int, i32p, i32p, i32p, i32p]
+    L.mpi_batch_forward.argtypes = [vp, vp, vp, vp, sz, vp]
+    L.mpi_batch_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
+    L.mpi_batch_pair.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    L.mpi_batch_pair_noalloc.argtypes = [vp, vp, vp, vp, vp]
+    L.mpi_batch_iterate.argtypes = [vp, vp, vp, ctypes.POINTER(IterParams), ctypes.POINTER(ctypes.c_double),
+                                    vp, sz, vp]
+    L.mpi_batch_forward_dh.argtypes = [vp, vp, vp, vp, sz, vp]
+    L.mpi_batch_residual.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    L.mpi_batch_traj_vjp.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    L.mpi_batch_adjoint_step.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+    L.mpi_batch_denoise.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, vp, sz, vp]
+    L.mpi_batch_dot.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, sz, vp]
+    L.mpi_batch_sample_order.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    L.mpi_batch_unrolled_vjp_bytes.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(sz)]
+    L.mpi_batch_unrolled_vjp.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp, vp, sz,
+                                         vp, sz, vp]
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.mpi_batch_deconv_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.mpi_batch_trace_conv.argtypes = [vp, vp, vp, vp, sz, vp]
+    L.mpi_batch_cg.argtypes = [vp, vp, vp, dp, ctypes.c_double, ctypes.c_int32, i32p, vp, sz, vp, sz, vp]
+    L.mpi_batch_trim_sigma.argtypes = [vp, vp, ctypes.c_double, dp, dp, vp, sz, vp, sz, vp]
+    L.mpi_batch_pnp.argtypes = [vp, vp, vp, ctypes.POINTER(PnpParams), i32p, dp, dp, vp, sz, vp, sz, vp]
+    L.mpi_batch_core_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.mpi_batch_core_stage.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, i32p, vp, sz,
+                                       vp, sz, vp]
+    L.mpi_batch_field_trace.argtypes = [vp, vp, vp, vp]
+    L.mpi_velocity_forward_difference.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, vp]
+    L.mpi_scale_trajectory.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                       vp, vp, vp]
+    L.mpi_reduce_lissajous.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.mpi_stage_count.argtypes = [vp]
+    L.mpi_stage_name.argtypes = [vp, ctypes.c_int]
+    L.mpi_stage_name.restype = ctypes.c_char_p
+    L.mpi_stage_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, sz, vp]
+    L.mpi_plan_destroy.argtypes = [vp]
+    L.mpi_status_str.argtypes = [ctypes.c_int]
+    L.mpi_status_str.restype = ctypes.c_char_p
+    L.mpi_abi_version.argtypes = []
+    L.mpi_checks_enabled.argtypes = []
+    L.mpi_plan_check.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
+    L.mpi_debug_fail_alloc.argtypes = [ctypes.c_int32]
+    for name in ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
+                 "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
+                 "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_pair",
+                 "mpi_batch_pair_noalloc", "mpi_batch_iterate", "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
+                 "mpi_batch_dot", "mpi_batch_unrolled_vjp_bytes", "mpi_batch_unrolled_vjp",
+                 "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_launch",
+                 "mpi_batch_deconv_bytes", "mpi_batch_trace_conv", "mpi_batch_cg", "mpi_batch_trim_sigma",
+                 "mpi_batch_pnp", "mpi_batch_core_bytes", "mpi_batch_core_stage", "mpi_batch_field_trace",
+                 "mpi_velocity_forward_difference", "mpi_scale_trajectory", "mpi_reduce_lissajous",
+                 "mpi_checks_enabled", "mpi_plan_check", "mpi_debug_fail_alloc", "mpi_plan_destroy",
+                 "mpi_abi_version"):
+        getattr(L, name).restype = ctypes.c_int
+    return L
 
 
 def status_str(status: int) -> str:
@@ -192,6 +227,7 @@ class Plan:
     def __init__(self, n: int, h: float, radius: int, r: torch.Tensor, v: torch.Tensor,
                  conv_mode: str = "auto", stream=None, interp: str = "bilinear", channels: str = "xy",
                  grad=(1.0, 1.0)):
+        self._L = lib()
         if not (r.is_cuda and v.is_cuda):
             raise ValueError("r and v must be device tensors")
         if r.dtype != v.dtype or r.shape != v.shape or r.ndim != 2 or r.shape[1] != 2:
@@ -206,11 +242,11 @@ class Plan:
         self.plan_mem = torch.empty(pb, dtype=torch.uint8, device=r.device)
         self.work = torch.empty(wb, dtype=torch.uint8, device=r.device)
         handle = ctypes.c_void_p()
-        _check(lib().mpi_kernel_build(ctypes.byref(prob), self.plan_mem.data_ptr(), pb, _stream(stream),
+        _check(self._L.mpi_kernel_build(ctypes.byref(prob), self.plan_mem.data_ptr(), pb, _stream(stream),
                                       ctypes.byref(handle)), "mpi_kernel_build")
         self._h = handle
         rad, m, mode = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().mpi_plan_info(self._h, ctypes.byref(rad), ctypes.byref(m), ctypes.byref(mode)), "mpi_plan_info")
+        _check(self._L.mpi_plan_info(self._h, ctypes.byref(rad), ctypes.byref(m), ctypes.byref(mode)), "mpi_plan_info")
         self.radius, self.fft_size = rad.value, m.value
         self.conv_mode = "fft" if mode.value == 2 else "direct"
 
@@ -224,7 +260,7 @@ class Plan:
         if s is None:
             s = torch.empty((self.n_samples, 2), dtype=self.dtype, device=self.device)
         self._vec(s, (self.n_samples, 2), "s")
-        _check(lib().mpi_forward(self._h, c.data_ptr(), s.data_ptr(), self.work.data_ptr(), self.work.numel(),
+        _check(self._L.mpi_forward(self._h, c.data_ptr(), s.data_ptr(), self.work.data_ptr(), self.work.numel(),
                                  _stream(stream)), "mpi_forward")
         return s
 
@@ -233,7 +269,7 @@ class Plan:
         if c is None:
             c = torch.empty((self.n, self.n), dtype=self.dtype, device=self.device)
         self._vec(c, (self.n, self.n), "c")
-        _check(lib().mpi_adjoint(self._h, s.data_ptr(), c.data_ptr(), self.work.data_ptr(), self.work.numel(),
+        _check(self._L.mpi_adjoint(self._h, s.data_ptr(), c.data_ptr(), self.work.data_ptr(), self.work.numel(),
                                  _stream(stream)), "mpi_adjoint")
         return c
 
@@ -246,7 +282,7 @@ class Plan:
             g = torch.empty((self.n, self.n), dtype=self.dtype, device=self.device)
         self._vec(s, (self.n_samples, 2), "s")
         self._vec(g, (self.n, self.n), "g")
-        _check(lib().mpi_batch_pair(self._h, c.data_ptr(), s.data_ptr(), g.data_ptr(), self.work.data_ptr(),
+        _check(self._L.mpi_batch_pair(self._h, c.data_ptr(), s.data_ptr(), g.data_ptr(), self.work.data_ptr(),
                                     self.work.numel(), _stream(stream)), "mpi_batch_pair")
         return s, g
 
@@ -257,95 +293,44 @@ class Plan:
         self._vec(s, (self.n_samples, 2), "s")
         self._vec(c, (self.n, self.n), "c")
         ip = IterParams(int(n_iter), float(tau), float(denoise_sigma_px), int(denoise_radius), int(bool(use_graph)))
-        _check(lib().mpi_iterate(self._h, s.data_ptr(), c.data_ptr(), ctypes.byref(ip), self.work.data_ptr(),
+        _check(self._L.mpi_iterate(self._h, s.data_ptr(), c.data_ptr(), ctypes.byref(ip), self.work.data_ptr(),
                                  self.work.numel(), _stream(stream)), "mpi_iterate")
         return c
 
     def stages(self) -> list[str]:
-        n = lib().mpi_stage_count(self._h)
-        return [lib().mpi_stage_name(self._h, k).decode() for k in range(n)]
+        n = self._L.mpi_stage_count(self._h)
+        return [self._L.mpi_stage_name(self._h, k).decode() for k in range(n)]
 
     def launch_stage(self, stage: int, reps: int, c: torch.Tensor, s: torch.Tensor, stream=None):
         """Enqueue `reps` launches of one kernel of the forward/transpose sequence."""
         self._vec(c, (self.n, self.n), "c")
         self._vec(s, (self.n_samples, 2), "s")
-        _check(lib().mpi_stage_launch(self._h, int(stage), int(reps), c.data_ptr(), s.data_ptr(),
+        _check(self._L.mpi_stage_launch(self._h, int(stage), int(reps), c.data_ptr(), s.data_ptr(),
                                       self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_stage_launch")
-
-    # ---- derivative building blocks
-    def forward_dh(self, x_all, s_all=None, stream=None):
-        self._flat(x_all, self.c_offsets[-1], "x_all")
-        if s_all is None:
-            s_all = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
-        self._flat(s_all, self.s_offsets[-1], "s_all")
-        _check(lib().mpi_batch_forward_dh(self._h, x_all.data_ptr(), s_all.data_ptr(), self.work.data_ptr(),
-                                          self.work.numel(), _stream(stream)), "mpi_batch_forward_dh")
-        return s_all
-
-    def residual(self, c_all, y_all, out=None, stream=None):
-        """A c - y, time order."""
-        self._flat(c_all, self.c_offsets[-1], "c_all")
-        self._flat(y_all, self.s_offsets[-1], "y_all")
-        if out is None:
-            out = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
-        _check(lib().mpi_batch_residual(self._h, c_all.data_ptr(), y_all.data_ptr(), out.data_ptr(),
-                                        self.work.data_ptr(), self.work.numel(), _stream(stream)),
-               "mpi_batch_residual")
-        return out
-
-    def traj_vjp(self, x_all, y_all, stream=None):
-        self._flat(x_all, self.c_offsets[-1], "x_all")
-        self._flat(y_all, self.s_offsets[-1], "y_all")
-        g_r = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
-        g_v = torch.empty_like(g_r)
-        _check(lib().mpi_batch_traj_vjp(self._h, x_all.data_ptr(), y_all.data_ptr(), g_r.data_ptr(), g_v.data_ptr(),
-                                        self.work.data_ptr(), self.work.numel(), _stream(stream)),
-               "mpi_batch_traj_vjp")
-        return g_r, g_v
-
-    def adjoint_step(self, s_all, c_in, taus, c_out=None, stream=None):
-        self._flat(s_all, self.s_offsets[-1], "s_all")
-        self._flat(c_in, self.c_offsets[-1], "c_in")
-        if c_out is None:
-            c_out = torch.empty_like(c_in)
-        tarr = (ctypes.c_double * self.count)(*[float(t) for t in taus])
-        _check(lib().mpi_batch_adjoint_step(self._h, s_all.data_ptr(), c_in.data_ptr(), c_out.data_ptr(), tarr,
-                                            self.work.data_ptr(), self.work.numel(), _stream(stream)),
-               "mpi_batch_adjoint_step")
-        return c_out
-
-    def denoise(self, u_all, sigma_px=0.5, radius=2, c_out=None, stream=None):
-        self._flat(u_all, self.c_offsets[-1], "u_all")
-        if c_out is None:
-            c_out = torch.empty_like(u_all)
-        _check(lib().mpi_batch_denoise(self._h, u_all.data_ptr(), c_out.data_ptr(), float(sigma_px), int(radius),
-                                       self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_batch_denoise")
-        return c_out
-
-    def dot(self, a, b, space="signal", comp="both", out=None, stream=None):
-        """Per-problem float64 dot products (device tensor of `count`)."""
-        n = self.s_offsets[-1] if space == "signal" else self.c_offsets[-1]
-        self._flat(a, n, "a")
-        self._flat(b, n, "b")
-        if out is None:
-            out = torch.empty(self.count, dtype=torch.float64, device=self.device)
-        _check(lib().mpi_batch_dot(self._h, a.data_ptr(), b.data_ptr(), 0 if space == "signal" else 1,
-                                   {"x": 0, "y": 1, "both": 2}[comp], out.data_ptr(), self.work.data_ptr(),
-                                   self.work.numel(), _stream(stream)), "mpi_batch_dot")
-        return out
 
     def sample_order(self, stream=None):
         """(time index, base cell i0 | j0 << 16) of the samples in the order
         the plan holds them (int32 device tensors)."""
         order = torch.empty(self.n_samples, dtype=torch.int32, device=self.device)
         cell = torch.empty_like(order)
-        _check(lib().mpi_batch_sample_order(self._h, 0, order.data_ptr(), cell.data_ptr(), _stream(stream)),
+        _check(self._L.mpi_batch_sample_order(self._h, 0, order.data_ptr(), cell.data_ptr(), _stream(stream)),
                "mpi_batch_sample_order")
         return order, cell
 
+    def check_word(self, stream=None) -> int:
+        """OR of the problems' bounds-check words (nonzero only in the
+        bounds-checked build, when a kernel met an index out of range)."""
+        w = ctypes.c_int32()
+        _check(self._L.mpi_plan_check(self._h, ctypes.byref(w), _stream(stream)), "mpi_plan_check")
+        return w.value
+
     def close(self):
         if getattr(self, "_h", None):
-            lib().mpi_plan_destroy(self._h)
+            if self._L.mpi_checks_enabled():
+                w = ctypes.c_int32()
+                if self._L.mpi_plan_check(self._h, ctypes.byref(w), None) == MPI_OK and w.value:
+                    CHECK_FAILURES.append((type(self).__name__, w.value))
+            self._L.mpi_plan_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -368,6 +353,7 @@ class Batch:
         deriv: also build the dK/dh tables (for forward_dh) and the weight slopes.
         interp: "bilinear" or "cosine", for specs that do not name one.
         channels ("xy" or "x") and grad (the selection-field gradient) apply to every problem."""
+        self._L = lib()
         keep = []
         arr = (Problem * len(specs))()
         for i, sp in enumerate(specs):
@@ -389,35 +375,35 @@ class Batch:
         flags = (MPI_BUILD_TUNE if tune else 0) | (MPI_BUILD_DERIV if deriv else 0) | {
             None: 0, "split": MPI_BUILD_COL_SPLIT, "wave": MPI_BUILD_COL_WAVE}[columns]
         pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
-        _check(lib().mpi_batch_bytes(arr, self.count, flags, ctypes.byref(pb), ctypes.byref(wb)), "mpi_batch_bytes")
+        _check(self._L.mpi_batch_bytes(arr, self.count, flags, ctypes.byref(pb), ctypes.byref(wb)), "mpi_batch_bytes")
         self.plan_mem = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
         self.work = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
         handle = ctypes.c_void_p()
-        _check(lib().mpi_batch_build(arr, self.count, self.plan_mem.data_ptr(), pb.value, self.work.data_ptr(),
+        _check(self._L.mpi_batch_build(arr, self.count, self.plan_mem.data_ptr(), pb.value, self.work.data_ptr(),
                                      wb.value, flags, _stream(stream), ctypes.byref(handle)), "mpi_batch_build")
         self._h = handle
         co = (ctypes.c_int64 * (self.count + 1))()
         so = (ctypes.c_int64 * (self.count + 1))()
-        _check(lib().mpi_batch_offsets(self._h, co, so), "mpi_batch_offsets")
+        _check(self._L.mpi_batch_offsets(self._h, co, so), "mpi_batch_offsets")
         self.c_offsets = list(co)
         self.s_offsets = list(so)
         self.info = []
         for b in range(self.count):
             rad, m, mode, sl = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-            _check(lib().mpi_batch_info(self._h, b, ctypes.byref(rad), ctypes.byref(m), ctypes.byref(mode),
+            _check(self._L.mpi_batch_info(self._h, b, ctypes.byref(rad), ctypes.byref(m), ctypes.byref(mode),
                                         ctypes.byref(sl)), "mpi_batch_info")
             self.info.append(dict(radius=rad.value, fft_size=m.value,
                                   conv_mode="fft" if mode.value == 2 else "direct", slices=sl.value))
 
     def stages(self) -> list[str]:
-        n = lib().mpi_stage_count(self._h)
-        return [lib().mpi_stage_name(self._h, k).decode() for k in range(n)]
+        n = self._L.mpi_stage_count(self._h)
+        return [self._L.mpi_stage_name(self._h, k).decode() for k in range(n)]
 
     def launch_stage(self, stage: int, reps: int, c_all: torch.Tensor, s_all: torch.Tensor, stream=None):
         """Enqueue `reps` launches of one kernel of the forward/transpose sequence."""
         self._flat(c_all, self.c_offsets[-1], "c_all")
         self._flat(s_all, self.s_offsets[-1], "s_all")
-        _check(lib().mpi_stage_launch(self._h, int(stage), int(reps), c_all.data_ptr(), s_all.data_ptr(),
+        _check(self._L.mpi_stage_launch(self._h, int(stage), int(reps), c_all.data_ptr(), s_all.data_ptr(),
                                       self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_stage_launch")
 
     def c_views(self, c_all):
@@ -436,7 +422,7 @@ class Batch:
         if s_all is None:
             s_all = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
         self._flat(s_all, self.s_offsets[-1], "s_all")
-        _check(lib().mpi_batch_forward(self._h, c_all.data_ptr(), s_all.data_ptr(), self.work.data_ptr(),
+        _check(self._L.mpi_batch_forward(self._h, c_all.data_ptr(), s_all.data_ptr(), self.work.data_ptr(),
                                        self.work.numel(), _stream(stream)), "mpi_batch_forward")
         return s_all
 
@@ -445,7 +431,7 @@ class Batch:
         if c_all is None:
             c_all = torch.empty(self.c_offsets[-1], dtype=self.dtype, device=self.device)
         self._flat(c_all, self.c_offsets[-1], "c_all")
-        _check(lib().mpi_batch_adjoint(self._h, s_all.data_ptr(), c_all.data_ptr(), self.work.data_ptr(),
+        _check(self._L.mpi_batch_adjoint(self._h, s_all.data_ptr(), c_all.data_ptr(), self.work.data_ptr(),
                                        self.work.numel(), _stream(stream)), "mpi_batch_adjoint")
         return c_all
 
@@ -458,7 +444,7 @@ class Batch:
             g_all = torch.empty(self.c_offsets[-1], dtype=self.dtype, device=self.device)
         self._flat(s_all, self.s_offsets[-1], "s_all")
         self._flat(g_all, self.c_offsets[-1], "g_all")
-        _check(lib().mpi_batch_pair(self._h, c_all.data_ptr(), s_all.data_ptr(), g_all.data_ptr(),
+        _check(self._L.mpi_batch_pair(self._h, c_all.data_ptr(), s_all.data_ptr(), g_all.data_ptr(),
                                     self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_batch_pair")
         return s_all, g_all
 
@@ -469,7 +455,7 @@ class Batch:
         self._flat(c_all, self.c_offsets[-1], "c_all")
         self._flat(s_all, self.s_offsets[-1], "s_all")
         self._flat(g_all, self.c_offsets[-1], "g_all")
-        _check(lib().mpi_batch_pair_noalloc(self._h, c_all.data_ptr(), s_all.data_ptr(), g_all.data_ptr(),
+        _check(self._L.mpi_batch_pair_noalloc(self._h, c_all.data_ptr(), s_all.data_ptr(), g_all.data_ptr(),
                                             _stream(stream)), "mpi_batch_pair_noalloc")
         return s_all, g_all
 
@@ -479,7 +465,7 @@ class Batch:
         self._flat(c_all, self.c_offsets[-1], "c_all")
         tarr = (ctypes.c_double * self.count)(*[float(t) for t in taus])
         ip = IterParams(int(n_iter), 0.0, float(denoise_sigma_px), int(denoise_radius), int(bool(use_graph)))
-        _check(lib().mpi_batch_iterate(self._h, s_all.data_ptr(), c_all.data_ptr(), ctypes.byref(ip), tarr,
+        _check(self._L.mpi_batch_iterate(self._h, s_all.data_ptr(), c_all.data_ptr(), ctypes.byref(ip), tarr,
                                        self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_batch_iterate")
         return c_all
 
@@ -489,7 +475,7 @@ class Batch:
         if s_all is None:
             s_all = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
         self._flat(s_all, self.s_offsets[-1], "s_all")
-        _check(lib().mpi_batch_forward_dh(self._h, x_all.data_ptr(), s_all.data_ptr(), self.work.data_ptr(),
+        _check(self._L.mpi_batch_forward_dh(self._h, x_all.data_ptr(), s_all.data_ptr(), self.work.data_ptr(),
                                           self.work.numel(), _stream(stream)), "mpi_batch_forward_dh")
         return s_all
 
@@ -499,7 +485,7 @@ class Batch:
         self._flat(y_all, self.s_offsets[-1], "y_all")
         if out is None:
             out = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
-        _check(lib().mpi_batch_residual(self._h, c_all.data_ptr(), y_all.data_ptr(), out.data_ptr(),
+        _check(self._L.mpi_batch_residual(self._h, c_all.data_ptr(), y_all.data_ptr(), out.data_ptr(),
                                         self.work.data_ptr(), self.work.numel(), _stream(stream)),
                "mpi_batch_residual")
         return out
@@ -509,7 +495,7 @@ class Batch:
         self._flat(y_all, self.s_offsets[-1], "y_all")
         g_r = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
         g_v = torch.empty_like(g_r)
-        _check(lib().mpi_batch_traj_vjp(self._h, x_all.data_ptr(), y_all.data_ptr(), g_r.data_ptr(), g_v.data_ptr(),
+        _check(self._L.mpi_batch_traj_vjp(self._h, x_all.data_ptr(), y_all.data_ptr(), g_r.data_ptr(), g_v.data_ptr(),
                                         self.work.data_ptr(), self.work.numel(), _stream(stream)),
                "mpi_batch_traj_vjp")
         return g_r, g_v
@@ -520,7 +506,7 @@ class Batch:
         if c_out is None:
             c_out = torch.empty_like(c_in)
         tarr = (ctypes.c_double * self.count)(*[float(t) for t in taus])
-        _check(lib().mpi_batch_adjoint_step(self._h, s_all.data_ptr(), c_in.data_ptr(), c_out.data_ptr(), tarr,
+        _check(self._L.mpi_batch_adjoint_step(self._h, s_all.data_ptr(), c_in.data_ptr(), c_out.data_ptr(), tarr,
                                             self.work.data_ptr(), self.work.numel(), _stream(stream)),
                "mpi_batch_adjoint_step")
         return c_out
@@ -529,7 +515,7 @@ class Batch:
         self._flat(u_all, self.c_offsets[-1], "u_all")
         if c_out is None:
             c_out = torch.empty_like(u_all)
-        _check(lib().mpi_batch_denoise(self._h, u_all.data_ptr(), c_out.data_ptr(), float(sigma_px), int(radius),
+        _check(self._L.mpi_batch_denoise(self._h, u_all.data_ptr(), c_out.data_ptr(), float(sigma_px), int(radius),
                                        self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_batch_denoise")
         return c_out
 
@@ -540,7 +526,7 @@ class Batch:
         self._flat(b, n, "b")
         if out is None:
             out = torch.empty(self.count, dtype=torch.float64, device=self.device)
-        _check(lib().mpi_batch_dot(self._h, a.data_ptr(), b.data_ptr(), 0 if space == "signal" else 1,
+        _check(self._L.mpi_batch_dot(self._h, a.data_ptr(), b.data_ptr(), 0 if space == "signal" else 1,
                                    {"x": 0, "y": 1, "both": 2}[comp], out.data_ptr(), self.work.data_ptr(),
                                    self.work.numel(), _stream(stream)), "mpi_batch_dot")
         return out
@@ -556,7 +542,7 @@ class Batch:
         nseg = (int(n_iter) + int(every) - 1) // int(every)
         self._flat(checkpoints, nseg * self.c_offsets[-1], "checkpoints")
         vb = ctypes.c_size_t()
-        _check(lib().mpi_batch_unrolled_vjp_bytes(self._h, int(every), ctypes.byref(vb)),
+        _check(self._L.mpi_batch_unrolled_vjp_bytes(self._h, int(every), ctypes.byref(vb)),
                "mpi_batch_unrolled_vjp_bytes")
         if getattr(self, "_vjp_work", None) is None or self._vjp_work.numel() < vb.value:
             self._vjp_work = torch.empty(vb.value, dtype=torch.uint8, device=self.device)
@@ -564,7 +550,7 @@ class Batch:
         g_r = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
         g_v = torch.empty_like(g_r)
         tarr = (ctypes.c_double * self.count)(*[float(t) for t in taus])
-        _check(lib().mpi_batch_unrolled_vjp(self._h, s_all.data_ptr(), checkpoints.data_ptr(), int(n_iter),
+        _check(self._L.mpi_batch_unrolled_vjp(self._h, s_all.data_ptr(), checkpoints.data_ptr(), int(n_iter),
                                             int(every), float(denoise_sigma_px), int(denoise_radius), tarr,
                                             gbar.data_ptr(), g_h.data_ptr(), g_r.data_ptr(), g_v.data_ptr(),
                                             self.work.data_ptr(), self.work.numel(), self._vjp_work.data_ptr(),
@@ -575,7 +561,7 @@ class Batch:
     def _deconv_work(self):
         if getattr(self, "_dwork", None) is None:
             nb = ctypes.c_size_t()
-            _check(lib().mpi_batch_deconv_bytes(self._h, ctypes.byref(nb)), "mpi_batch_deconv_bytes")
+            _check(self._L.mpi_batch_deconv_bytes(self._h, ctypes.byref(nb)), "mpi_batch_deconv_bytes")
             self._dwork = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
         return self._dwork
 
@@ -584,7 +570,7 @@ class Batch:
         self._flat(x_all, self.c_offsets[-1], "x_all")
         if out is None:
             out = torch.empty_like(x_all)
-        _check(lib().mpi_batch_trace_conv(self._h, x_all.data_ptr(), out.data_ptr(), self.work.data_ptr(),
+        _check(self._L.mpi_batch_trace_conv(self._h, x_all.data_ptr(), out.data_ptr(), self.work.data_ptr(),
                                           self.work.numel(), _stream(stream)), "mpi_batch_trace_conv")
         return out
 
@@ -596,7 +582,7 @@ class Batch:
         dw = self._deconv_work()
         nu = (ctypes.c_double * self.count)(*[float(v) for v in nus])
         it = (ctypes.c_int32 * self.count)()
-        _check(lib().mpi_batch_cg(self._h, rhs_all.data_ptr(), x_out.data_ptr(), nu, float(tol), int(max_iter), it,
+        _check(self._L.mpi_batch_cg(self._h, rhs_all.data_ptr(), x_out.data_ptr(), nu, float(tol), int(max_iter), it,
                                   self.work.data_ptr(), self.work.numel(), dw.data_ptr(), dw.numel(), _stream(stream)),
                "mpi_batch_cg")
         return x_out, list(it)
@@ -608,7 +594,7 @@ class Batch:
         dw = self._deconv_work()
         q = (ctypes.c_double * self.count)()
         sg = (ctypes.c_double * self.count)()
-        _check(lib().mpi_batch_trim_sigma(self._h, x_all.data_ptr(), float(pct), q, sg, self.work.data_ptr(),
+        _check(self._L.mpi_batch_trim_sigma(self._h, x_all.data_ptr(), float(pct), q, sg, self.work.data_ptr(),
                                           self.work.numel(), dw.data_ptr(), dw.numel(), _stream(stream)),
                "mpi_batch_trim_sigma")
         return list(q), list(sg)
@@ -625,7 +611,7 @@ class Batch:
                         float(0.0 if sigma_px is None else sigma_px), int(radius), 0)
         m = (n_it + 1) * self.count
         it, sg, nu = (ctypes.c_int32 * m)(), (ctypes.c_double * m)(), (ctypes.c_double * m)()
-        _check(lib().mpi_batch_pnp(self._h, u_all.data_ptr(), rho_out.data_ptr(), ctypes.byref(prm), it, sg, nu,
+        _check(self._L.mpi_batch_pnp(self._h, u_all.data_ptr(), rho_out.data_ptr(), ctypes.byref(prm), it, sg, nu,
                                    self.work.data_ptr(), self.work.numel(), dw.data_ptr(), dw.numel(),
                                    _stream(stream)), "mpi_batch_pnp")
         B = self.count
@@ -649,10 +635,10 @@ class Batch:
         self._flat(field_out, 3 * self.c_offsets[-1], "field_out")
         if getattr(self, "_cwork", None) is None:
             nb = ctypes.c_size_t()
-            _check(lib().mpi_batch_core_bytes(self._h, ctypes.byref(nb)), "mpi_batch_core_bytes")
+            _check(self._L.mpi_batch_core_bytes(self._h, ctypes.byref(nb)), "mpi_batch_core_bytes")
             self._cwork = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
         it = (ctypes.c_int32 * self.count)()
-        _check(lib().mpi_batch_core_stage(self._h, s_all.data_ptr(), field_out.data_ptr(), float(gamma), float(tol),
+        _check(self._L.mpi_batch_core_stage(self._h, s_all.data_ptr(), field_out.data_ptr(), float(gamma), float(tol),
                                           int(max_iter), it, self.work.data_ptr(), self.work.numel(),
                                           self._cwork.data_ptr(), self._cwork.numel(), _stream(stream)),
                "mpi_batch_core_stage")
@@ -663,7 +649,7 @@ class Batch:
         self._flat(field_all, 3 * self.c_offsets[-1], "field_all")
         if u_out is None:
             u_out = torch.empty(self.c_offsets[-1], dtype=self.dtype, device=self.device)
-        _check(lib().mpi_batch_field_trace(self._h, field_all.data_ptr(), u_out.data_ptr(), _stream(stream)),
+        _check(self._L.mpi_batch_field_trace(self._h, field_all.data_ptr(), u_out.data_ptr(), _stream(stream)),
                "mpi_batch_field_trace")
         return u_out
 
@@ -676,7 +662,7 @@ class Batch:
             self._flat(t, n, name)
         gax = torch.empty(self.count, dtype=torch.float64, device=self.device)
         gay = torch.empty(self.count, dtype=torch.float64, device=self.device)
-        _check(lib().mpi_reduce_lissajous(self._h, g_r.data_ptr(), g_v.data_ptr(), rho_all.data_ptr(),
+        _check(self._L.mpi_reduce_lissajous(self._h, g_r.data_ptr(), g_v.data_ptr(), rho_all.data_ptr(),
                                           nu_all.data_ptr(), gax.data_ptr(), gay.data_ptr(), self.work.data_ptr(),
                                           self.work.numel(), _stream(stream)), "mpi_reduce_lissajous")
         return gax, gay
@@ -686,13 +672,24 @@ class Batch:
         order the plan holds them (int32 device tensors)."""
         order = torch.empty(self.ts[b], dtype=torch.int32, device=self.device)
         cell = torch.empty_like(order)
-        _check(lib().mpi_batch_sample_order(self._h, int(b), order.data_ptr(), cell.data_ptr(), _stream(stream)),
+        _check(self._L.mpi_batch_sample_order(self._h, int(b), order.data_ptr(), cell.data_ptr(), _stream(stream)),
                "mpi_batch_sample_order")
         return order, cell
 
+    def check_word(self, stream=None) -> int:
+        """OR of the problems' bounds-check words (nonzero only in the
+        bounds-checked build, when a kernel met an index out of range)."""
+        w = ctypes.c_int32()
+        _check(self._L.mpi_plan_check(self._h, ctypes.byref(w), _stream(stream)), "mpi_plan_check")
+        return w.value
+
     def close(self):
         if getattr(self, "_h", None):
-            lib().mpi_plan_destroy(self._h)
+            if self._L.mpi_checks_enabled():
+                w = ctypes.c_int32()
+                if self._L.mpi_plan_check(self._h, ctypes.byref(w), None) == MPI_OK and w.value:
+                    CHECK_FAILURES.append((type(self).__name__, w.value))
+            self._L.mpi_plan_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -21,3 +21,20 @@ def gpu():
         pytest.fail("GPU test selected but no GPU is visible")
     from paper_2505_22797_amd import mpik
     return mpik
+
+
+@pytest.fixture(autouse=True)
+def bounds_checks_clean(request):
+    """With the bounds-checked build loaded (MPIK_LIBRARY=libmpik_check.so),
+    every plan a GPU test closes must report a zero check word."""
+    yield
+    if "gpu" not in request.keywords:
+        return
+    mpik = sys.modules.get("paper_2505_22797_amd.mpik")
+    if mpik is None:
+        return
+    import gc
+    gc.collect()
+    failures = list(mpik.CHECK_FAILURES)
+    mpik.CHECK_FAILURES.clear()
+    assert not failures, f"bounds checks failed in the kernels: {failures}"

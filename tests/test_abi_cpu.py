@@ -40,11 +40,11 @@ def test_library_exports_every_declared_symbol(mpik):
 def test_abi_version_and_status_strings(mpik):
     assert mpik.lib().mpi_abi_version() == 2
     seen = set()
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         s = mpik.status_str(code)
         assert s and s != "unknown status"
         seen.add(s)
-    assert len(seen) == 7
+    assert len(seen) == 8
     assert mpik.status_str(-99) == "unknown status"
 
 
@@ -159,3 +159,53 @@ def test_size_limits(mpik):
     assert code(n=513, radius=7, conv_mode="fft") == -6           # the FFT path stops at 512^2
     assert code(n=400, radius=112, conv_mode="fft", dtype=1) == 0  # M = 512, float64
     assert code(n=400, radius=113, conv_mode="fft", dtype=1) == -6
+
+
+def test_injected_allocation_failure_in_the_sizing(mpik):
+    """The test hook fails the k-th host allocation of the plan sizing: every
+    k up to the number of allocations there makes the call return
+    MPI_ERR_ALLOC, and the next one lets it through with the sizes of an
+    unhooked call.  A build fails the same way at the sizing and at the plan
+    object, before any device call."""
+    L = mpik.lib()
+    probs = (mpik.Problem * 3)(*[_prob(mpik, n=n) for n in (32, 64, 128)])
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.mpi_batch_bytes(probs, 3, 0, ctypes.byref(pb), ctypes.byref(wb)) == 0
+    ref = (pb.value, wb.value)
+    try:
+        k = 1
+        while True:
+            assert L.mpi_debug_fail_alloc(k) == 0
+            pb.value = wb.value = 0
+            rc = L.mpi_batch_bytes(probs, 3, 0, ctypes.byref(pb), ctypes.byref(wb))
+            if rc == 0:
+                break
+            assert rc == mpik.MPI_ERR_ALLOC, (k, rc)
+            k += 1
+            assert k < 64
+        assert k > 1, "the sizing reached no allocation point"
+        assert (pb.value, wb.value) == ref
+        sizing_points = k - 1
+        # the build: the sizing's points, then the plan object, all before any device call
+        p = _prob(mpik)
+        p.r, p.v = 256, 512
+        out = ctypes.c_void_p()
+        for k in (1, sizing_points, sizing_points + 1):
+            assert L.mpi_debug_fail_alloc(k) == 0
+            assert L.mpi_kernel_build(ctypes.byref(p), 4096, 1 << 30, None, ctypes.byref(out)) == mpik.MPI_ERR_ALLOC
+            assert out.value is None
+    finally:
+        L.mpi_debug_fail_alloc(0)
+    assert L.mpi_debug_fail_alloc(-1) == mpik.MPI_ERR_ARG
+    assert L.mpi_batch_bytes(probs, 3, 0, ctypes.byref(pb), ctypes.byref(wb)) == 0
+
+
+def test_bounds_checks_only_in_the_checked_build(mpik):
+    """libmpik_check.so is the build with kernel bounds checks; the others
+    compile them away."""
+    checked = os.path.basename(mpik._LIB_PATH) == "libmpik_check.so"
+    assert mpik.lib().mpi_checks_enabled() == int(checked)
+    assert mpik.lib().mpi_plan_check(None, None, None) == mpik.MPI_ERR_ARG
+    if not checked and os.path.exists(mpik.CHECK_LIBRARY):
+        with mpik.use_library(mpik.CHECK_LIBRARY) as L:
+            assert L.mpi_checks_enabled() == 1

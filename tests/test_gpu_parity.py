@@ -162,8 +162,8 @@ def test_workspace_too_small(gpu):
     small = torch.empty(256, dtype=torch.uint8, device="cuda")
     c = cs.t(cs.c)
     s = torch.empty((cs.plan.n_samples, 2), dtype=torch.float64, device="cuda")
-    rc = mpik.lib().mpi_forward(cs.plan._h, c.data_ptr(), s.data_ptr(), small.data_ptr(), 256,
-                                torch.cuda.current_stream().cuda_stream)
+    rc = cs.plan._L.mpi_forward(cs.plan._h, c.data_ptr(), s.data_ptr(), small.data_ptr(), 256,
+                                 torch.cuda.current_stream().cuda_stream)
     assert rc == mpik.MPI_ERR_WORKSPACE
 
 
