@@ -29,18 +29,17 @@ __host__ __device__ constexpr int direct_row_len(int R) {
     return ((kTile + 2 * R + 12) + 3) / 4 * 4;
 }
 
-template <typename T, int CIN>
+// One channel's input tile with its R-halo (zero outside the grid).
+template <typename T>
 __device__ __forceinline__ void load_tile(T* tile, const T* __restrict__ in, int N, int R, int y0, int x0,
                                           int row_len, int tid, int nt) {
     const int rows = kTile + 2 * R;
-    const int total = CIN * rows * row_len;
+    const int total = rows * row_len;
     for (int idx = tid; idx < total; idx += nt) {
-        const int ch = idx / (rows * row_len);
-        const int rem = idx % (rows * row_len);
-        const int ly = rem / row_len, lx = rem % row_len;
+        const int ly = idx / row_len, lx = idx % row_len;
         const int gy = y0 - R + ly, gx = x0 - R + lx;
         T v = T(0);
-        if (lx < kTile + 2 * R && gy >= 0 && gy < N && gx >= 0 && gx < N) v = in[int64_t(ch) * N * N + int64_t(gy) * N + gx];
+        if (lx < kTile + 2 * R && gy >= 0 && gy < N && gx >= 0 && gx < N) v = in[int64_t(gy) * N + gx];
         tile[idx] = v;
     }
 }
@@ -69,11 +68,8 @@ __global__ void __launch_bounds__(64 * S) k_conv_direct(const Prob* __restrict__
     else out = out_is_caller ? out + p.o_c : reinterpret_cast<T*>(reinterpret_cast<char*>(out) + p.w_g);
     if (c_in) c_in += p.o_c;
     const int row_len = direct_row_len(R);
-    const int rows = kTile + 2 * R;
     T* tile = reinterpret_cast<T*>(smem);
     const int tid = threadIdx.x;
-    load_tile<T, CIN>(tile, in, N, R, ty0, tx0, row_len, tid, 64 * S);
-    __syncthreads();
     const int wave = uniform(tid / kWave), lane = tid % kWave;
     const int ly = lane / 4, sx = (lane % 4) * kStrip;
     const T* taps = at<T>(plan, dh ? p.o_taps_dh : p.o_taps);   // dK/dh for the h-derivative
@@ -83,11 +79,15 @@ __global__ void __launch_bounds__(64 * S) k_conv_direct(const Prob* __restrict__
     for (int o = 0; o < COUT; ++o)
 #pragma unroll
         for (int w = 0; w < kStrip; ++w) acc[o][w] = T(0);
-    for (int dy = -R + wave; dy <= R; dy += S) {
-        const int trow = (dy + R) * tw;
-#pragma unroll
-        for (int ci = 0; ci < CIN; ++ci) {
-            const T* row = tile + (ci * rows + ly - dy + R) * row_len + sx;
+    // the input channels one after another through one LDS tile (a third of
+    // the LDS of all three at once: four work-groups per CU instead of one)
+    for (int ci = 0; ci < CIN; ++ci) {
+        if (ci > 0) __syncthreads();              // every wave is done with the previous channel
+        load_tile<T>(tile, in + int64_t(ci) * N * N, N, R, ty0, tx0, row_len, tid, 64 * S);
+        __syncthreads();
+        for (int dy = -R + wave; dy <= R; dy += S) {
+            const int trow = (dy + R) * tw;
+            const T* row = tile + (ly - dy + R) * row_len + sx;
             T x[8];
 #pragma unroll
             for (int u = 0; u < 4; ++u) x[u] = row[u];

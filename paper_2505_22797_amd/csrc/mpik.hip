@@ -86,8 +86,10 @@ int pow2_at_least(int x) {
 }
 int blocks(int64_t n, int b) { return int((n + b - 1) / b); }
 
-size_t direct_smem(int R, int cin, int cout, int slices, int elem) {
-    const size_t tile = size_t(cin) * (kTile + 2 * R) * direct_row_len(R);
+// LDS of the direct convolution: one channel's input tile (the input channels
+// pass through it one after another), reused for the reduction over waves.
+size_t direct_smem(int R, int cout, int slices, int elem) {
+    const size_t tile = size_t(kTile + 2 * R) * direct_row_len(R);
     const size_t red = size_t(slices) * kWave * cout * kStrip;
     return std::max(tile, red) * elem;
 }
@@ -163,8 +165,8 @@ int validate(const mpi_problem* d, Shape& sh) {
     const int maxM = sh.elem == 8 ? 512 : 1024;
     sh.fft_ok = sh.M <= maxM && sh.n <= 512 && smem_for_dt(sh.elem, sh.M, sh.n, 3) <= kSmemLimit &&
                 smem_for_dt(sh.elem, sh.M, sh.n, 1) <= kSmemLimit && smem_for_dt(sh.elem, sh.M, sh.n, 2) <= kSmemLimit;
-    sh.direct_ok = direct_smem(sh.R, 3, 1, 16, sh.elem) <= kSmemLimit &&
-                   direct_smem(sh.R, 1, 3, 16, sh.elem) <= kSmemLimit && scatter_rows_smem(sh.n, sh.elem) <= kSmemLimit;
+    sh.direct_ok = direct_smem(sh.R, 1, 16, sh.elem) <= kSmemLimit &&
+                   direct_smem(sh.R, 3, 16, sh.elem) <= kSmemLimit && scatter_rows_smem(sh.n, sh.elem) <= kSmemLimit;
     if (d->conv_mode == MPI_CONV_FFT && !sh.fft_ok) return MPI_ERR_UNSUPPORTED;
     if (d->conv_mode == MPI_CONV_DIRECT && !sh.direct_ok) return MPI_ERR_UNSUPPORTED;
     if (!sh.fft_ok && !sh.direct_ok) return MPI_ERR_UNSUPPORTED;
@@ -439,8 +441,8 @@ void finalize_extents(mpi_plan* pl) {
         } else {
             pl->any_direct = true;
             pl->max_tiles = std::max(pl->max_tiles, (p.n + kTile - 1) / kTile);
-            pl->smem_dfwd = std::max(pl->smem_dfwd, direct_smem(p.radius, 1, 3, p.slices, e));
-            pl->smem_dadj = std::max(pl->smem_dadj, direct_smem(p.radius, 3, 1, p.slices, e));
+            pl->smem_dfwd = std::max(pl->smem_dfwd, direct_smem(p.radius, 3, p.slices, e));
+            pl->smem_dadj = std::max(pl->smem_dadj, direct_smem(p.radius, 1, p.slices, e));
             pl->smem_dgather = std::max(pl->smem_dgather, size_t(6) * p.n * e);
             pl->smem_dscatter = std::max(pl->smem_dscatter, scatter_rows_smem(p.n, e));
             for (int i = 0; i < 3; ++i)
