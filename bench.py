@@ -177,6 +177,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--graph-pairs", type=int, default=10)
+    ap.add_argument("--ranges", type=int, default=0,
+                    help="problem ranges of the headline batch (0: timed by mpi_batch_schedule)")
     ap.add_argument("--stage-reps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -248,6 +250,8 @@ def main() -> int:
     c_all = c1.reshape(-1).repeat(B).contiguous()
     s_all = torch.empty(batch.s_offsets[-1], dtype=torch.float32, device=dev)
     g_all = torch.empty(batch.c_offsets[-1], dtype=torch.float32, device=dev)
+    ranges_default = batch.schedule()
+    ranges = batch.schedule(args.ranges, c_all, s_all, g_all)
 
     def pairB():
         batch.pair(c_all, s_all, g_all)
@@ -263,7 +267,8 @@ def main() -> int:
     msB_sep, _, runs_sep = graph_time(pairB_separate, steps, group_for(steps), args.warmup, runs=args.runs)
     stB = stage_times(batch, g_all, s_all, max(3, args.stage_reps // 4))
     pairs_per_s = B * 1e3 / msB
-    print(f"bench: batch {B}: {msB * 1e3:.1f} us/step, {pairs_per_s:.0f} pairs/s", file=sys.stderr, flush=True)
+    print(f"bench: batch {B} ({ranges} ranges): {msB * 1e3:.1f} us/step, {pairs_per_s:.0f} pairs/s", file=sys.stderr,
+          flush=True)
 
     batch_fft = batch.info[0]["fft_size"]
     fft_stages = [k for k in stB if k in STAGE_NAMES]
@@ -289,7 +294,9 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "headline_256: N=256, T=53856 Lissajous 17:16, R=255 (FFT, M=512)",
                    "problems_per_step": B, "grid": n, "samples": t, "radius": plan.radius,
-                   "fft_size": plan.fft_size, "conv_path": plan.conv_mode},
+                   "fft_size": plan.fft_size, "conv_path": plan.conv_mode,
+                   "problem_ranges": ranges, "ranges_by": "timed" if args.ranges == 0 else "given",
+                   "ranges_default": ranges_default},
         "timing": {"runs": len(runs), "steps_per_run": steps, "statistic": "median",
                    "ms_per_step_runs": [round(x, 5) for x in runs],
                    "spread": round((max(runs) - min(runs)) / msB, 4),

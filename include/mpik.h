@@ -28,7 +28,8 @@
  * the plan memory and the work memory.  The library never allocates device
  * memory.  An mpi_plan is a small host object owned by the library
  * (mpi_plan_destroy frees it); it refers into the caller's plan memory, which
- * must outlive it.  A plan is immutable after the build.  Calls on different
+ * must outlive it.  A plan's results are fixed at the build; only its launch
+ * schedule may change later (mpi_batch_schedule), which never changes them.  Calls on different
  * streams may run concurrently if each passes its own work buffer.  A batch
  * whose problems use several FFT sizes (or both paths) runs each group on a
  * side stream of the plan, forked from and joined back to the caller's
@@ -206,6 +207,27 @@ int mpi_batch_adjoint(const mpi_plan* plan, const void* s_all, void* c_all,
  * Enqueued on `stream`. */
 int mpi_batch_pair(const mpi_plan* plan, const void* c_all, void* s_all, void* g_all,
                    void* work, size_t work_bytes, hipStream_t stream);
+/* Launch schedule of a batch: each FFT-size group of the batch is split into
+ * `ranges` contiguous problem ranges, each range on its own side stream, so
+ * that the stages of different ranges overlap (the direct-path problems stay
+ * on the caller's stream).  The build picks the count from the batch size
+ * (one size group: 4 ranges below 48 problems, 2 from 48 on; two groups: 2
+ * each; fewer than 16 problems: 1).  Results never depend on it: every problem
+ * runs the same kernels in any split.
+ *   ranges < 0: only report the count in use; c, s, g and work may be NULL.
+ *   ranges > 0: use that count (1 .. min(count, 8 / size groups), else
+ *               MPI_ERR_ARG); c, s, g and work may be NULL.
+ *   ranges = 0: time the batched pair (mpi_batch_pair on c, s, g and work, as
+ *               that call checks them, replayed from a captured graph) with
+ *               1, 2, 4 and 8 ranges and keep the fastest (the count in
+ *               use stays unless another is faster by more than 3 %).  The
+ *               buffers' contents are overwritten.
+ * The count in use is written to *chosen (may be NULL).  Changing it drops the
+ * plan's cached iteration graphs (recorded again on their next use) and
+ * synchronises `stream`; no other call may use the plan meanwhile. */
+int mpi_batch_schedule(mpi_plan* plan, int32_t ranges, const void* c_all, void* s_all, void* g_all,
+                       void* work, size_t work_bytes, hipStream_t stream, int32_t* chosen);
+
 /* Allocation-free pair, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): mpi_batch_pair with the work memory taken from a fixed array

@@ -1029,10 +1029,21 @@ void release_streams(mpi_plan* pl) {
 // (measured at 16, 32 and 64 headline problems: four ranges are best at 16
 // and 32, two at 64, and ranges queued one after another on a shared stream
 // lose the overlap); two size groups: two ranges each.
-int create_streams(mpi_plan* pl) {
+int default_ranges(const mpi_plan* pl) {
     const int groups = __builtin_popcount(pl->fft_m_mask);
-    pl->chunks = (pl->count >= 16 && groups == 1) ? (pl->count >= 48 ? 2 : 4)
-                                                   : (pl->count >= 16 && groups == 2) ? 2 : 1;
+    return (pl->count >= 16 && groups == 1) ? (pl->count >= 48 ? 2 : 4) : (pl->count >= 16 && groups == 2) ? 2 : 1;
+}
+
+// Largest range count a plan can take: every range holds a problem, and the
+// side streams of all size groups fit the plan's kMaxSide.
+int max_ranges(const mpi_plan* pl) {
+    const int groups = __builtin_popcount(pl->fft_m_mask);
+    return groups ? std::max(1, std::min(pl->count, kMaxSide / groups)) : 1;
+}
+
+int create_streams(mpi_plan* pl, int ranges) {
+    const int groups = __builtin_popcount(pl->fft_m_mask);
+    pl->chunks = ranges;
     if (groups * pl->chunks + (pl->any_direct ? 1 : 0) <= 1) {
         pl->chunks = 1;
         return MPI_OK;
@@ -1084,7 +1095,7 @@ int build_common(const mpi_problem* probs, int count, void* plan_mem, size_t pla
     finalize_extents(pl);
     rc = pl->dtype == MPI_F64 ? build_batch<double>(probs, pl, work, work_bytes, flags, stream)
                               : build_batch<float>(probs, pl, work, work_bytes, flags, stream);
-    if (rc == MPI_OK) rc = create_streams(pl);
+    if (rc == MPI_OK) rc = create_streams(pl, default_ranges(pl));
     if (rc != MPI_OK) return rc;      // the owner releases the plan
     // the allocation-free pair's work memory on this GPU; a failure here only
     // disables that entry point (it returns the status)
@@ -1092,6 +1103,97 @@ int build_common(const mpi_problem* probs, int count, void* plan_mem, size_t pla
     pl->noalloc_rc = scratch_address(pl->device, &pl->noalloc_work);
     *out = owner.release();
     return MPI_OK;
+}
+
+// Drops every cached graph of the plan (they are recorded again on their
+// next use); the caller's stream is synchronised first.
+void drop_graphs(mpi_plan* pl, hipStream_t st) {
+    (void)hipStreamSynchronize(st);
+    for (mpi_plan::GraphCache* gc : {&pl->one_gc, &pl->iter_gc, &pl->cg_gc, &pl->core_gc}) {
+        if (gc->exec) {
+            (void)hipGraphExecDestroy(gc->exec);
+            (void)hipGraphDestroy(gc->graph);
+        }
+        gc->exec = nullptr;
+        gc->graph = nullptr;
+        gc->key.clear();
+    }
+}
+
+// Re-splits the plan's size groups into `ranges` problem ranges, with side
+// streams to match.  Results do not depend on it: every problem runs the
+// same kernels in any split.
+int set_ranges(mpi_plan* pl, int ranges, hipStream_t st) {
+    if (ranges == pl->chunks) return MPI_OK;
+    HIP_TRY(hipStreamSynchronize(st));
+    drop_graphs(pl, st);
+    release_streams(pl);
+    return create_streams(pl, ranges);
+}
+
+// Mean time of one batched pair on the caller's buffers, as the pair runs
+// when replayed from a graph (the way iterations and timed loops run it):
+// eight pairs captured into one graph, replayed once to warm up, then the
+// best of three runs of four replays.
+template <typename T>
+float time_batch_pair(const mpi_plan* pl, const T* c, T* s, T* g, char* work, hipStream_t st) {
+    constexpr int kPairs = 8, kReplays = 4;
+    hipStream_t cap;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return -1.f;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        int rc = MPI_OK;
+        for (int i = 0; i < kPairs && rc == MPI_OK; ++i) rc = pair_impl<T>(pl, c, s, g, work, cap);
+        ok = hipStreamEndCapture(cap, &graph) == hipSuccess && rc == MPI_OK && graph;
+    }
+    ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    (void)hipStreamDestroy(cap);
+    hipEvent_t a = nullptr, b = nullptr;
+    ok = ok && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+    float best = -1.f;
+    if (ok && hipGraphLaunch(exec, st) == hipSuccess) {
+        for (int run = 0; run < 3; ++run) {
+            (void)hipEventRecord(a, st);
+            for (int i = 0; i < kReplays; ++i) (void)hipGraphLaunch(exec, st);
+            (void)hipEventRecord(b, st);
+            float ms = -1.f;
+            if (hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess && ms > 0.f)
+                best = best < 0.f ? ms : std::min(best, ms);
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    return best > 0.f ? best / (kPairs * kReplays) : -1.f;
+}
+
+// Range counts 1, 2, 4, 8 (up to max_ranges) timed on the caller's
+// buffers.  The build's count stays unless another is faster by more than
+// kRangeMargin (run-to-run noise of the timing is about 1 %).
+constexpr float kRangeMargin = 0.03f;
+
+template <typename T>
+int tune_ranges(mpi_plan* pl, const T* c, T* s, T* g, char* work, hipStream_t st) {
+    const int start = pl->chunks;
+    float t_start = -1.f, best = 1e30f;
+    int best_r = start;
+    for (int r = 1; r <= max_ranges(pl); r *= 2) {
+        const int rc = set_ranges(pl, r, st);
+        if (rc != MPI_OK) return rc;
+        const float ms = time_batch_pair<T>(pl, c, s, g, work, st);
+        if (ms < 0.f) return MPI_ERR_HIP;
+        if (r == start) t_start = ms;
+        if (ms < best) {
+            best = ms;
+            best_r = r;
+        }
+    }
+    if (t_start > 0.f && best > t_start * (1.f - kRangeMargin)) best_r = start;
+    return set_ranges(pl, best_r, st);
 }
 
 // Per-problem steps and the normalised Gaussian weights of the denoiser
@@ -1824,6 +1926,35 @@ int mpi_batch_pair(const mpi_plan* plan, const void* c, void* s, void* g, void* 
                                        static_cast<double*>(g), w, stream)
                    : pair_impl<float>(plan, static_cast<const float*>(c), static_cast<float*>(s), static_cast<float*>(g),
                                       w, stream);
+    });
+}
+
+int mpi_batch_schedule(mpi_plan* plan, int32_t ranges, const void* c, void* s, void* g, void* work,
+                       size_t work_bytes, hipStream_t stream, int32_t* chosen) {
+    return guarded([&]() -> int {
+        if (!plan) return MPI_ERR_ARG;
+        if (ranges < 0) {
+            // report only
+        } else if (ranges > 0) {
+            if (ranges > max_ranges(plan)) return MPI_ERR_ARG;
+            const int rc = set_ranges(plan, ranges, stream);
+            if (rc != MPI_OK) return rc;
+        } else {
+            int rc = check_call(plan, c, s, work, work_bytes);
+            if (rc != MPI_OK) return rc;
+            if (!g || misaligned(g, plan->L.elem) || misaligned(s, 2 * plan->L.elem)) return MPI_ERR_ARG;
+            if (g == c || g == s) return MPI_ERR_ARG;
+            if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+            char* w = static_cast<char*>(work);
+            rc = plan->dtype == MPI_F64
+                     ? tune_ranges<double>(plan, static_cast<const double*>(c), static_cast<double*>(s),
+                                           static_cast<double*>(g), w, stream)
+                     : tune_ranges<float>(plan, static_cast<const float*>(c), static_cast<float*>(s),
+                                          static_cast<float*>(g), w, stream);
+            if (rc != MPI_OK) return rc;
+        }
+        if (chosen) *chosen = plan->chunks;
+        return MPI_OK;
     });
 }
 

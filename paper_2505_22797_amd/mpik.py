@@ -30,7 +30,8 @@ CHANNELS = {"xy": 0, "x": 1}
 
 EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
            "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
-           "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_pair", "mpi_batch_pair_noalloc", "mpi_batch_iterate",
+           "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_pair", "mpi_batch_schedule",
+           "mpi_batch_pair_noalloc", "mpi_batch_iterate",
            "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
            "mpi_batch_dot", "mpi_batch_unrolled_vjp_bytes", "mpi_batch_unrolled_vjp",
            "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
@@ -122,6 +123,7 @@ def _load(path: str) -> ctypes.CDLL:
     L.mpi_batch_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
     L.mpi_batch_pair.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     L.mpi_batch_pair_noalloc.argtypes = [vp, vp, vp, vp, vp]
+    L.mpi_batch_schedule.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_int32)]
     L.mpi_batch_iterate.argtypes = [vp, vp, vp, ctypes.POINTER(IterParams), ctypes.POINTER(ctypes.c_double),
                                     vp, sz, vp]
     L.mpi_batch_forward_dh.argtypes = [vp, vp, vp, vp, sz, vp]
@@ -163,7 +165,7 @@ def _load(path: str) -> ctypes.CDLL:
     for name in ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "mpi_iterate",
                  "mpi_plan_info", "mpi_batch_bytes", "mpi_batch_build", "mpi_batch_count", "mpi_batch_offsets",
                  "mpi_batch_info", "mpi_batch_forward", "mpi_batch_adjoint", "mpi_batch_pair",
-                 "mpi_batch_pair_noalloc", "mpi_batch_iterate", "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
+                 "mpi_batch_pair_noalloc", "mpi_batch_schedule", "mpi_batch_iterate", "mpi_batch_forward_dh", "mpi_batch_residual", "mpi_batch_traj_vjp", "mpi_batch_adjoint_step", "mpi_batch_denoise",
                  "mpi_batch_dot", "mpi_batch_unrolled_vjp_bytes", "mpi_batch_unrolled_vjp",
                  "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_launch",
                  "mpi_batch_deconv_bytes", "mpi_batch_trace_conv", "mpi_batch_cg", "mpi_batch_trim_sigma",
@@ -447,6 +449,28 @@ class Batch:
         _check(self._L.mpi_batch_pair(self._h, c_all.data_ptr(), s_all.data_ptr(), g_all.data_ptr(),
                                     self.work.data_ptr(), self.work.numel(), _stream(stream)), "mpi_batch_pair")
         return s_all, g_all
+
+    def schedule(self, ranges: int = -1, c_all=None, s_all=None, g_all=None, stream=None) -> int:
+        """Problem ranges per FFT-size group: -1 reports the count in use, a
+        positive count sets it, 0 times the pair on the given buffers (or on
+        zero-filled ones) with 1, 2, 4 and 8 ranges and keeps the fastest.
+        Results never depend on it."""
+        chosen = ctypes.c_int32()
+        ptrs = [0, 0, 0]
+        if ranges == 0:
+            if c_all is None:
+                c_all = torch.zeros(self.c_offsets[-1], dtype=self.dtype, device=self.device)
+            if s_all is None:
+                s_all = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
+            if g_all is None:
+                g_all = torch.empty(self.c_offsets[-1], dtype=self.dtype, device=self.device)
+            self._flat(c_all, self.c_offsets[-1], "c_all")
+            self._flat(s_all, self.s_offsets[-1], "s_all")
+            self._flat(g_all, self.c_offsets[-1], "g_all")
+            ptrs = [c_all.data_ptr(), s_all.data_ptr(), g_all.data_ptr()]
+        _check(self._L.mpi_batch_schedule(self._h, int(ranges), *ptrs, self.work.data_ptr(), self.work.numel(),
+                                          _stream(stream), ctypes.byref(chosen)), "mpi_batch_schedule")
+        return chosen.value
 
     def pair_noalloc(self, c_all, s_all, g_all, stream=None):
         """As pair(), through the allocation-free entry (mpi_batch_pair_noalloc):

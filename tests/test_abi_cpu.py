@@ -122,6 +122,7 @@ def test_apply_argument_errors_need_no_gpu(mpik):
     assert L.mpi_adjoint(None, 256, 256, 256, 1 << 20, None) == -1
     assert L.mpi_iterate(None, 256, 256, None, 256, 1 << 20, None) == -1
     assert L.mpi_batch_pair(None, 256, 256, 512, 256, 1 << 20, None) == -1
+    assert L.mpi_batch_schedule(None, 2, None, None, None, None, 0, None, None) == -1
     assert L.mpi_plan_destroy(None) == -1
     assert L.mpi_plan_info(None, None, None, None) == -1
 
