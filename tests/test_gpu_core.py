@@ -25,7 +25,7 @@ import torch
 import oracle as O
 from paper_2505_22797_amd import mpik
 from paper_2505_22797_amd import synth as S
-from gpu_helpers import dev, rel_l2, rounded
+from gpu_helpers import dev, f32_steps_ok, rel_l2, rounded
 
 pytestmark = pytest.mark.gpu
 
@@ -62,18 +62,26 @@ SHAPES = [(16, 400, 15, "fft"), (24, 900, 5, "direct"), (32, 2000, 31, "fft")]
 TOL = {torch.float64: 1e-10, torch.float32: 1e-5}
 
 
+# accuracy against the true field, relative to the oracle's: float64 solves
+# stop at the oracle's step; float32 ones within a few steps of it
+ERR_RATIO = {torch.float64: 1.001, torch.float32: 1.02}
+
+
 def check_solve(it, a, steps, ref_steps, ref, dtype, gamma, tol, interp="cosine"):
     """The stop rule in the true residual, the step count, and the accuracy
-    against the true field within 10 % of the oracle's."""
+    against the true field against the oracle's."""
     b = O.core_rhs(it["s"], it["r"], it["v"], it["n"], interp)
     res = O.core_normal(a, it["r"], it["v"], gamma, interp) - b
     slack = 1e-6 if dtype == torch.float64 else 0.05
+    ratio = rel_l2(a, it["G"]) / rel_l2(ref, it["G"])
+    print(f"core stage {dtype} n={it['n']} gamma={gamma}: steps {steps} oracle {ref_steps}, error ratio {ratio:.5f}, "
+          f"to the oracle's solution {rel_l2(a, ref):.2e}", flush=True)
     assert np.linalg.norm(res) <= tol * (1 + slack) * np.linalg.norm(b), np.linalg.norm(res) / np.linalg.norm(b)
     if dtype == torch.float64:
         assert abs(steps - ref_steps) <= 1, (steps, ref_steps)
     else:
-        assert ref_steps - 1 <= steps <= 2 * ref_steps + 2, (steps, ref_steps)
-    assert rel_l2(a, it["G"]) <= 1.1 * rel_l2(ref, it["G"]), (rel_l2(a, it["G"]), rel_l2(ref, it["G"]))
+        assert f32_steps_ok(steps, ref_steps), (steps, ref_steps)
+    assert ratio <= ERR_RATIO[dtype], ratio
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -88,14 +96,15 @@ def test_core_stage_fixed_steps_match_oracle(dtype):
         assert rel_l2(got[i], ref) <= TOL[dtype], (i, rel_l2(got[i], ref))
 
 
+@pytest.mark.parametrize("gamma", [1e-3, 1e-7])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_core_stage_to_tolerance(dtype):
+def test_core_stage_to_tolerance(dtype, gamma):
     cc = CoreCase(SHAPES, dtype)
-    field, steps = cc.batch.core_stage(cc.s_all(), gamma=1e-3, tol=1e-3, max_iter=10000)
+    field, steps = cc.batch.core_stage(cc.s_all(), gamma=gamma, tol=1e-3, max_iter=10000)
     got = cc.fields(field)
     for i, it in enumerate(cc.items):
-        ref, k = O.core_stage(it["s"], it["r"], it["v"], it["n"], 1e-3, tol=1e-3)
-        check_solve(it, got[i], steps[i], k, ref, dtype, 1e-3, 1e-3)
+        ref, k = O.core_stage(it["s"], it["r"], it["v"], it["n"], gamma, tol=1e-3)
+        check_solve(it, got[i], steps[i], k, ref, dtype, gamma, 1e-3)
 
 
 def test_core_stage_bilinear_plan_and_field_trace():
@@ -158,15 +167,18 @@ def test_core_stage_full_size_meets_the_stop_rule():
     true = np.linalg.norm(O.core_normal(a, it["r"], it["v"], ref["gamma"]) - b) / np.linalg.norm(b)
     assert true <= ref["tol"] * 1.05, (true, steps)
     k = ref["steps"]
-    assert k - 1 <= steps[0] <= 2 * k + 2, (steps, k)
-    assert rel_l2(a, it["G"]) <= 1.1 * ref["field_error"], (rel_l2(a, it["G"]), ref["field_error"])
+    ratio = rel_l2(a, it["G"]) / ref["field_error"]
+    print(f"core stage headline float32: steps {steps[0]} oracle {k}, residual {true:.3e}, error ratio {ratio:.5f}",
+          flush=True)
+    assert f32_steps_ok(steps[0], k), (steps, k)
+    assert ratio <= ERR_RATIO[torch.float32], ratio
 
 
 def test_two_stage_pipeline_reconstructs_like_the_oracle():
     """Signals -> Core Stage field -> trace image -> ZeroShot-PnP, on 48^2
     and 64^2 problems with the full kernel, float64: the library's
     reconstruction is as close to the phantom as the oracle's pipeline (within
-    10 % of its relative error), and the intermediate field solves its
+    1 % of its relative error), and the intermediate field solves its
     equations like the oracle's (stop rule, steps, accuracy)."""
     shapes = [(48, 2400, 47, "fft"), (64, 3400, 63, "fft")]
     cc = CoreCase(shapes, torch.float64, seed=9)
@@ -181,7 +193,8 @@ def test_two_stage_pipeline_reconstructs_like_the_oracle():
         check_solve(it, got_f[i], steps[i], k, a, torch.float64, 1e-3, 1e-3)
         ref, _ = O.zeroshot_pnp(a[0] + a[2], it["h"], it["R"], 9, 1e-5)
         err = lambda x: np.linalg.norm(x - it["c"]) / np.linalg.norm(it["c"])
-        assert err(rho[i]) <= 1.1 * err(ref), (i, err(rho[i]), err(ref))
+        print(f"two-stage n={it['n']}: reconstruction error {err(rho[i]):.5f}, oracle {err(ref):.5f}", flush=True)
+        assert err(rho[i]) <= 1.01 * err(ref), (i, err(rho[i]), err(ref))
 
 
 def test_paper_runtime_workload_21():
@@ -208,7 +221,8 @@ def test_paper_runtime_workload_21():
     ref, _ = O.zeroshot_pnp(a_ref[0] + a_ref[2], h, n - 1, 9, 1e-5)
     err = lambda x: np.linalg.norm(x - c) / np.linalg.norm(c)
     got = rho.double().cpu().numpy().reshape(n, n)
-    assert err(got) <= 1.1 * err(ref), (err(got), err(ref))
+    print(f"runtime workload 21^2: reconstruction error {err(got):.5f}, oracle {err(ref):.5f}", flush=True)
+    assert err(got) <= 1.02 * err(ref), (err(got), err(ref))
 
 
 def test_core_stage_smallest_grids():

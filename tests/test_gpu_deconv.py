@@ -21,7 +21,7 @@ import torch
 import oracle as O
 from paper_2505_22797_amd import mpik
 from paper_2505_22797_amd import synth as S
-from gpu_helpers import dev, rel_l2, rounded
+from gpu_helpers import dev, f32_steps_ok, rel_l2, rounded
 
 pytestmark = pytest.mark.gpu
 
@@ -117,7 +117,7 @@ def test_cg_well_conditioned_matches_oracle(dtype, mode):
 def test_cg_at_paper_weights_meets_the_stop_rule(dtype):
     """nu = 1e-5 and 1e-3, tol 1e-3: the true residual of the library's
     solution (float64, oracle operator) meets the tolerance; the step count is
-    the oracle's (float64, +-1) or not below it (float32)."""
+    the oracle's (float64, +-1) or within a few steps of it (float32)."""
     dc = DeconvCase(SHAPES, dtype, seed=5)
     nus = [1e-5 if i % 2 == 0 else 1e-3 for i in range(len(dc.items))]
     rhs = [rounded(O.trace_conv(it["u"], it["h"], it["R"]), dtype) for it in dc.items]
@@ -130,10 +130,11 @@ def test_cg_at_paper_weights_meets_the_stop_rule(dtype):
         true = np.linalg.norm(A(x[i]) - rhs[i]) / np.linalg.norm(rhs[i])
         assert true <= 1e-3 * (1 + slack), (i, true)
         _, k, _ = O.cg(A, rhs[i], 1e-3, 10000)
+        print(f"cg {dtype} nu={nus[i]}: steps {steps[i]} oracle {k}, residual {true:.3e}", flush=True)
         if dtype == torch.float64:
             assert abs(steps[i] - k) <= 1, (i, steps[i], k)
         else:
-            assert k - 1 <= steps[i] <= 2 * k + 2, (i, steps[i], k)
+            assert f32_steps_ok(steps[i], k), (i, steps[i], k)
 
 
 def test_cg_degenerate_inputs():
@@ -224,11 +225,14 @@ def test_pnp_identity_denoiser_single_pass_meets_the_stop_rule(dtype):
         assert info["sigma"][i][0] == pytest.approx(np.std(rho[i]), rel=1e-6)
 
 
+PNP_RATIO = {torch.float64: 1.001, torch.float32: 1.02}
+
+
 def test_pnp_at_paper_parameters_reconstructs_like_the_oracle():
     """nu0 = 1e-5, tol 1e-3, ten passes, 5% trimming, Gaussian stand-in, on
     64^2 full-kernel problems: float64 step counts within one of the oracle's
     on every pass, and float32 and float64 reconstructions as close to the
-    phantom as the oracle's (within 10% of its relative error)."""
+    phantom as the oracle's (within 0.1 % and 2 % of its relative error)."""
     shapes = [(64, 63, "fft"), (48, 47, "fft")]
     for dtype in (torch.float64, torch.float32):
         dc = DeconvCase(shapes, dtype, seed=13)
@@ -237,7 +241,9 @@ def test_pnp_at_paper_parameters_reconstructs_like_the_oracle():
         for i, it in enumerate(dc.items):
             ref, ri = O.zeroshot_pnp(it["u"], it["h"], it["R"], 9, 1e-5, tol=1e-3, max_iter=10000)
             err = lambda x: np.linalg.norm(x - it["rho"]) / np.linalg.norm(it["rho"])
-            assert err(rho[i]) <= 1.1 * err(ref), (dtype, i, err(rho[i]), err(ref))
+            print(f"pnp {dtype} n={it['n']}: error {err(rho[i]):.5f}, oracle {err(ref):.5f}, steps "
+                  f"{info['cg_steps'][i]} oracle {ri['cg_steps']}", flush=True)
+            assert err(rho[i]) <= PNP_RATIO[dtype] * err(ref), (dtype, i, err(rho[i]), err(ref))
             if dtype == torch.float64:
                 assert all(abs(a - b) <= 1 for a, b in zip(info["cg_steps"][i], ri["cg_steps"])), \
                     (i, info["cg_steps"][i], ri["cg_steps"])

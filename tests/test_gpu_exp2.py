@@ -10,7 +10,7 @@ import torch
 import oracle as O
 from paper_2505_22797_amd import mpik
 from paper_2505_22797_amd import synth as S
-from gpu_helpers import dev, rel_l2, rounded
+from gpu_helpers import dev, f32_steps_ok, rel_l2, rounded
 
 pytestmark = pytest.mark.gpu
 
@@ -103,7 +103,8 @@ def test_x_channel_core_stage(dtype):
         b = O.core_rhs(s_list[i], it["r"], it["v"], it["n"], channels="x")
         res = O.core_normal(got[i], it["r"], it["v"], 1e-3, channels="x") - b
         assert np.linalg.norm(res) <= 1e-3 * (1 + slack) * np.linalg.norm(b), i
-        ok = abs(steps[i] - k) <= 1 if dtype == torch.float64 else k - 1 <= steps[i] <= 2 * k + 2
+        print(f"x-channel core stage {dtype} n={it['n']}: steps {steps[i]} oracle {k}", flush=True)
+        ok = abs(steps[i] - k) <= 1 if dtype == torch.float64 else f32_steps_ok(steps[i], k)
         assert ok, (i, steps[i], k)
         assert not np.any(got[i][2]) and np.array_equal(u[i], got[i][0])
 
@@ -180,4 +181,5 @@ def test_experiment2_pipeline_reconstructs_like_the_oracle():
     ref, _ = O.zeroshot_pnp(a[0], h, R, 9, 4e-2, which="xx", grad=GRAD)
     err = lambda x: np.linalg.norm(x - c) / np.linalg.norm(c)
     got = rho.cpu().numpy().reshape(n, n)
-    assert err(got) <= 1.1 * err(ref), (err(got), err(ref))
+    print(f"x-channel pipeline: error {err(got):.5f}, oracle {err(ref):.5f}", flush=True)
+    assert err(got) <= 1.001 * err(ref), (err(got), err(ref))
