@@ -179,8 +179,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--graph-pairs", type=int, default=10)
-    ap.add_argument("--ranges", type=int, default=0,
-                    help="problem ranges of the headline batch (0: timed by mpi_batch_schedule)")
+    ap.add_argument("--ranges", type=int, default=-1,
+                    help="problem ranges of the headline batch (-1: the build's count)")
     ap.add_argument("--stage-reps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -297,7 +297,7 @@ def main() -> int:
         "config": {"workload": "headline_256: N=256, T=53856 Lissajous 17:16, R=255 (FFT, M=512)",
                    "problems_per_step": B, "grid": n, "samples": t, "radius": plan.radius,
                    "fft_size": plan.fft_size, "conv_path": plan.conv_mode,
-                   "problem_ranges": ranges, "ranges_by": "timed" if args.ranges == 0 else "given",
+                   "problem_ranges": ranges, "ranges_by": "build" if args.ranges < 0 else "given",
                    "ranges_default": ranges_default},
         "timing": {"runs": len(runs), "steps_per_run": steps, "statistic": "median",
                    "ms_per_step_runs": [round(x, 5) for x in runs],

@@ -217,11 +217,10 @@ int mpi_batch_pair(const mpi_plan* plan, const void* c_all, void* s_all, void* g
  *   ranges < 0: only report the count in use; c, s, g and work may be NULL.
  *   ranges > 0: use that count (1 .. min(count, 8 / size groups), else
  *               MPI_ERR_ARG); c, s, g and work may be NULL.
- *   ranges = 0: time the batched pair (mpi_batch_pair on c, s, g and work, as
- *               that call checks them, replayed from a captured graph) with
- *               1, 2, 4 and 8 ranges and keep the fastest (the count in
- *               use stays unless another is faster by more than 3 %).  The
- *               buffers' contents are overwritten.
+ *   ranges = 0: reserved for choosing the count by timing the pair;
+ *               switched off (MPI_ERR_UNSUPPORTED): its graph-captured timing
+ *               runs once ended in a host-side fault whose cause is not
+ *               established.
  * The count in use is written to *chosen (may be NULL).  Changing it drops the
  * plan's cached iteration graphs (recorded again on their next use) and
  * synchronises `stream`; no other call may use the plan meanwhile. */
@@ -295,6 +294,30 @@ int mpi_batch_denoise(const mpi_plan* plan, const void* u_all, void* c_all, doub
                       int radius, void* work, size_t work_bytes, hipStream_t stream);
 int mpi_batch_dot(const mpi_plan* plan, const void* a_all, const void* b_all, int space, int comp,
                   double* out, void* work, size_t work_bytes, hipStream_t stream);
+
+/* Composite vector-Jacobian products of the operator in its parameters
+ * theta = (c or y, h, r_k, v_k), the compositions of the building blocks above
+ * that reverse-mode differentiation of s = A c and c' = A^T y needs; plans built
+ * with MPI_BUILD_DERIV (else MPI_ERR_UNSUPPORTED).  All arrays batched as in
+ * mpi_batch_forward; g_h is a device array of count doubles; g_r and g_v are
+ * signal-shaped, time order.  Every output buffer is distinct from every
+ * input and from each other.
+ *
+ * mpi_vjp_forward: for s = A c and an upstream gradient gs (signal-shaped):
+ *   gc = A^T gs, g_h[b] = <(dA/dh) c, gs>_b, and g_r, g_v the gradients of
+ *   <gs, A c> in every sample's position and velocity (as mpi_batch_traj_vjp
+ *   with x = c, y = gs).
+ * mpi_vjp_adjoint: for c' = A^T y and an upstream gradient gc (concentration-
+ *   shaped), using <gc, A^T y> = <A gc, y>: gy = A gc, g_h[b] =
+ *   <(dA/dh) gc, y>_b, and g_r, g_v as mpi_batch_traj_vjp with x = gc.
+ * Each equals its building-block sequence (mpi_batch_adjoint or _forward,
+ * mpi_batch_forward_dh, mpi_batch_dot, mpi_batch_traj_vjp) bit for bit.  The
+ * amplitude gradients then follow from mpi_reduce_lissajous.  Enqueued on
+ * `stream`. */
+int mpi_vjp_forward(const mpi_plan* plan, const void* c_all, const void* gs_all, void* gc_all, double* g_h,
+                    void* g_r_all, void* g_v_all, void* work, size_t work_bytes, hipStream_t stream);
+int mpi_vjp_adjoint(const mpi_plan* plan, const void* y_all, const void* gc_all, void* gy_all, double* g_h,
+                    void* g_r_all, void* g_v_all, void* work, size_t work_bytes, hipStream_t stream);
 
 /* The amplitudes of a trajectory as parameters (the Lissajous figure of eq.
  * lissajous, r = (a_x rho_x, a_y rho_y) over unit-amplitude shapes rho, and

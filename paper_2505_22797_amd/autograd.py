@@ -75,14 +75,6 @@ def _like(g, ref):
     return g.to(device=ref.device, dtype=ref.dtype)
 
 
-def _param_grads(op, plan, x, y):
-    """Gradients of sum_b <y_b, A_b x_b> with respect to (h, ax, ay)."""
-    gh = plan.dot(plan.forward_dh(x), y)
-    g_r, g_v = plan.traj_vjp(x, y)
-    gax, gay = op.amp_grads(plan, g_r, g_v)
-    return gh, gax, gay
-
-
 class ApplyA(torch.autograd.Function):
     """s_all = A(h, ax, ay) c_all for every problem of the operator."""
 
@@ -99,10 +91,11 @@ class ApplyA(torch.autograd.Function):
         c_all, h, ax, ay = ctx.saved_tensors
         plan = ctx.op.plan(h, ax, ay)
         gs = gs.contiguous()
-        gc = plan.adjoint(gs) if ctx.needs_input_grad[0] else None
         if not any(ctx.needs_input_grad[1:4]):
-            return gc, None, None, None, None
-        gh, gax, gay = _param_grads(ctx.op, plan, c_all, gs)
+            return (plan.adjoint(gs) if ctx.needs_input_grad[0] else None), None, None, None, None
+        gc, gh, g_r, g_v = plan.vjp_forward(c_all, gs)
+        gax, gay = ctx.op.amp_grads(plan, g_r, g_v)
+        gc = gc if ctx.needs_input_grad[0] else None
         return gc, _like(gh, h), _like(gax, ax), _like(gay, ay), None
 
 
@@ -122,10 +115,11 @@ class ApplyAT(torch.autograd.Function):
         y_all, h, ax, ay = ctx.saved_tensors
         plan = ctx.op.plan(h, ax, ay)
         gc = gc.contiguous()
-        gy = plan.forward(gc) if ctx.needs_input_grad[0] else None
         if not any(ctx.needs_input_grad[1:4]):
-            return gy, None, None, None, None
-        gh, gax, gay = _param_grads(ctx.op, plan, gc, y_all)
+            return (plan.forward(gc) if ctx.needs_input_grad[0] else None), None, None, None, None
+        gy, gh, g_r, g_v = plan.vjp_adjoint(y_all, gc)
+        gax, gay = ctx.op.amp_grads(plan, g_r, g_v)
+        gy = gy if ctx.needs_input_grad[0] else None
         return gy, _like(gh, h), _like(gax, ax), _like(gay, ay), None
 
 

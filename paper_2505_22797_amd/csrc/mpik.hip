@@ -810,6 +810,20 @@ int adjoint_impl(const mpi_plan* pl, const T* s, T* c_out, const T* c_in, char* 
     });
 }
 
+// The parameter part of a vector-Jacobian product of the bilinear form
+// <y, A(h, r, v) x>: g_h = <(dA/dh) x, y> per problem (float64), and the
+// per-sample position and velocity gradients.  g_r serves as scratch for
+// (dA/dh) x until the trajectory gradients overwrite it.
+template <typename T>
+int param_vjp_impl(const mpi_plan* pl, const T* x, const T* y, double* g_h, T* g_r, T* g_v, char* work,
+                   hipStream_t st) {
+    int rc = forward_impl<T>(pl, x, g_r, work, st, 1);
+    if (rc != MPI_OK) return rc;
+    launch_dot<T>(pl, g_r, y, 0, 2, g_h, 0, work, st);
+    HIP_TRY(hipGetLastError());
+    return traj_vjp_impl<T>(pl, x, y, g_r, g_v, work, st);
+}
+
 // s = A c, then g = A^T s, per part: a problem range's transpose follows its
 // own forward on its stream, with no join in between.
 template <typename T>
@@ -1129,71 +1143,6 @@ int set_ranges(mpi_plan* pl, int ranges, hipStream_t st) {
     drop_graphs(pl, st);
     release_streams(pl);
     return create_streams(pl, ranges);
-}
-
-// Mean time of one batched pair on the caller's buffers, as the pair runs
-// when replayed from a graph (the way iterations and timed loops run it):
-// eight pairs captured into one graph, replayed once to warm up, then the
-// best of three runs of four replays.
-template <typename T>
-float time_batch_pair(const mpi_plan* pl, const T* c, T* s, T* g, char* work, hipStream_t st) {
-    constexpr int kPairs = 8, kReplays = 4;
-    hipStream_t cap;
-    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return -1.f;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
-    if (ok) {
-        int rc = MPI_OK;
-        for (int i = 0; i < kPairs && rc == MPI_OK; ++i) rc = pair_impl<T>(pl, c, s, g, work, cap);
-        ok = hipStreamEndCapture(cap, &graph) == hipSuccess && rc == MPI_OK && graph;
-    }
-    ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
-    (void)hipStreamDestroy(cap);
-    hipEvent_t a = nullptr, b = nullptr;
-    ok = ok && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
-    float best = -1.f;
-    if (ok && hipGraphLaunch(exec, st) == hipSuccess) {
-        for (int run = 0; run < 3; ++run) {
-            (void)hipEventRecord(a, st);
-            for (int i = 0; i < kReplays; ++i) (void)hipGraphLaunch(exec, st);
-            (void)hipEventRecord(b, st);
-            float ms = -1.f;
-            if (hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess && ms > 0.f)
-                best = best < 0.f ? ms : std::min(best, ms);
-        }
-    }
-    (void)hipStreamSynchronize(st);
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    return best > 0.f ? best / (kPairs * kReplays) : -1.f;
-}
-
-// Range counts 1, 2, 4, 8 (up to max_ranges) timed on the caller's
-// buffers.  The build's count stays unless another is faster by more than
-// kRangeMargin (run-to-run noise of the timing is about 1 %).
-constexpr float kRangeMargin = 0.03f;
-
-template <typename T>
-int tune_ranges(mpi_plan* pl, const T* c, T* s, T* g, char* work, hipStream_t st) {
-    const int start = pl->chunks;
-    float t_start = -1.f, best = 1e30f;
-    int best_r = start;
-    for (int r = 1; r <= max_ranges(pl); r *= 2) {
-        const int rc = set_ranges(pl, r, st);
-        if (rc != MPI_OK) return rc;
-        const float ms = time_batch_pair<T>(pl, c, s, g, work, st);
-        if (ms < 0.f) return MPI_ERR_HIP;
-        if (r == start) t_start = ms;
-        if (ms < best) {
-            best = ms;
-            best_r = r;
-        }
-    }
-    if (t_start > 0.f && best > t_start * (1.f - kRangeMargin)) best_r = start;
-    return set_ranges(pl, best_r, st);
 }
 
 // Per-problem steps and the normalised Gaussian weights of the denoiser
@@ -1803,6 +1752,24 @@ int check_deconv(const mpi_plan* pl, const void* a, const void* b, const void* w
     return MPI_OK;
 }
 
+// Checks shared by the two composite VJP entries: a, b are the operator's
+// input and the upstream gradient, out the input gradient (distinct buffers).
+int check_vjp(const mpi_plan* plan, const void* a, const void* b, const void* out, const double* g_h,
+              const void* g_r, const void* g_v, const void* work, size_t work_bytes) {
+    int rc = check_call(plan, a, b, work, work_bytes);
+    if (rc != MPI_OK) return rc;
+    const size_t el = plan->L.elem;
+    if (!out || !g_h || !g_r || !g_v) return MPI_ERR_ARG;
+    if (misaligned(out, el) || misaligned(g_r, 2 * el) || misaligned(g_v, el) || misaligned(g_h, 8)) return MPI_ERR_ARG;
+    const void* bufs[] = {a, b, out, g_r, g_v};
+    for (int i = 0; i < 5; ++i)
+        for (int j = i + 1; j < 5; ++j)
+            if (bufs[i] == bufs[j]) return MPI_ERR_ARG;
+    if (!plan->L.deriv) return MPI_ERR_UNSUPPORTED;
+    if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
+    return MPI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1940,18 +1907,15 @@ int mpi_batch_schedule(mpi_plan* plan, int32_t ranges, const void* c, void* s, v
             const int rc = set_ranges(plan, ranges, stream);
             if (rc != MPI_OK) return rc;
         } else {
-            int rc = check_call(plan, c, s, work, work_bytes);
-            if (rc != MPI_OK) return rc;
-            if (!g || misaligned(g, plan->L.elem) || misaligned(s, 2 * plan->L.elem)) return MPI_ERR_ARG;
-            if (g == c || g == s) return MPI_ERR_ARG;
-            if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-            char* w = static_cast<char*>(work);
-            rc = plan->dtype == MPI_F64
-                     ? tune_ranges<double>(plan, static_cast<const double*>(c), static_cast<double*>(s),
-                                           static_cast<double*>(g), w, stream)
-                     : tune_ranges<float>(plan, static_cast<const float*>(c), static_cast<float*>(s),
-                                          static_cast<float*>(g), w, stream);
-            if (rc != MPI_OK) return rc;
+            // Timing the candidates is switched off: its graph-captured
+            // timing runs once ended in a host-side fault whose cause is not
+            // established.
+            (void)c;
+            (void)s;
+            (void)g;
+            (void)work;
+            (void)work_bytes;
+            return MPI_ERR_UNSUPPORTED;
         }
         if (chosen) *chosen = plan->chunks;
         return MPI_OK;
@@ -2072,6 +2036,53 @@ int mpi_batch_traj_vjp(const mpi_plan* plan, const void* x, const void* y, void*
                                            static_cast<double*>(g_r), static_cast<double*>(g_v), w, stream)
                    : traj_vjp_impl<float>(plan, static_cast<const float*>(x), static_cast<const float*>(y),
                                           static_cast<float*>(g_r), static_cast<float*>(g_v), w, stream);
+    });
+}
+
+int mpi_vjp_forward(const mpi_plan* plan, const void* c, const void* gs, void* gc, double* g_h, void* g_r,
+                    void* g_v, void* work, size_t work_bytes, hipStream_t stream) {
+    return guarded([&]() -> int {
+        int rc = check_vjp(plan, c, gs, gc, g_h, g_r, g_v, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        char* w = static_cast<char*>(work);
+        if (plan->dtype == MPI_F64) {
+            using T = double;
+            rc = adjoint_impl<T, false, 0>(plan, static_cast<const T*>(gs), static_cast<T*>(gc), nullptr, w, stream);
+            if (rc == MPI_OK)
+                rc = param_vjp_impl<T>(plan, static_cast<const T*>(c), static_cast<const T*>(gs), g_h,
+                                       static_cast<T*>(g_r), static_cast<T*>(g_v), w, stream);
+        } else {
+            using T = float;
+            rc = adjoint_impl<T, false, 0>(plan, static_cast<const T*>(gs), static_cast<T*>(gc), nullptr, w, stream);
+            if (rc == MPI_OK)
+                rc = param_vjp_impl<T>(plan, static_cast<const T*>(c), static_cast<const T*>(gs), g_h,
+                                       static_cast<T*>(g_r), static_cast<T*>(g_v), w, stream);
+        }
+        return rc;
+    });
+}
+
+int mpi_vjp_adjoint(const mpi_plan* plan, const void* y, const void* gc, void* gy, double* g_h, void* g_r,
+                    void* g_v, void* work, size_t work_bytes, hipStream_t stream) {
+    return guarded([&]() -> int {
+        int rc = check_vjp(plan, y, gc, gy, g_h, g_r, g_v, work, work_bytes);
+        if (rc != MPI_OK) return rc;
+        if (misaligned(gy, 2 * plan->L.elem)) return MPI_ERR_ARG;
+        char* w = static_cast<char*>(work);
+        if (plan->dtype == MPI_F64) {
+            using T = double;
+            rc = forward_impl<T>(plan, static_cast<const T*>(gc), static_cast<T*>(gy), w, stream);
+            if (rc == MPI_OK)
+                rc = param_vjp_impl<T>(plan, static_cast<const T*>(gc), static_cast<const T*>(y), g_h,
+                                       static_cast<T*>(g_r), static_cast<T*>(g_v), w, stream);
+        } else {
+            using T = float;
+            rc = forward_impl<T>(plan, static_cast<const T*>(gc), static_cast<T*>(gy), w, stream);
+            if (rc == MPI_OK)
+                rc = param_vjp_impl<T>(plan, static_cast<const T*>(gc), static_cast<const T*>(y), g_h,
+                                       static_cast<T*>(g_r), static_cast<T*>(g_v), w, stream);
+        }
+        return rc;
     });
 }
 

@@ -37,7 +37,7 @@ EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "
            "mpi_batch_sample_order", "mpi_stage_count", "mpi_stage_name", "mpi_stage_launch",
            "mpi_batch_deconv_bytes", "mpi_batch_trace_conv", "mpi_batch_cg", "mpi_batch_trim_sigma", "mpi_batch_pnp",
            "mpi_batch_core_bytes", "mpi_batch_core_stage", "mpi_batch_field_trace", "mpi_velocity_forward_difference",
-           "mpi_scale_trajectory", "mpi_reduce_lissajous",
+           "mpi_scale_trajectory", "mpi_reduce_lissajous", "mpi_vjp_forward", "mpi_vjp_adjoint",
            "mpi_checks_enabled", "mpi_plan_check", "mpi_debug_fail_alloc",
            "mpi_plan_destroy", "mpi_status_str", "mpi_abi_version")
 MPI_BUILD_TUNE, MPI_BUILD_COL_SPLIT, MPI_BUILD_COL_WAVE, MPI_BUILD_DERIV = 1, 2, 4, 8
@@ -151,6 +151,8 @@ def _load(path: str) -> ctypes.CDLL:
     L.mpi_scale_trajectory.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                        vp, vp, vp]
     L.mpi_reduce_lissajous.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.mpi_vjp_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.mpi_vjp_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.mpi_stage_count.argtypes = [vp]
     L.mpi_stage_name.argtypes = [vp, ctypes.c_int]
     L.mpi_stage_name.restype = ctypes.c_char_p
@@ -171,6 +173,7 @@ def _load(path: str) -> ctypes.CDLL:
                  "mpi_batch_deconv_bytes", "mpi_batch_trace_conv", "mpi_batch_cg", "mpi_batch_trim_sigma",
                  "mpi_batch_pnp", "mpi_batch_core_bytes", "mpi_batch_core_stage", "mpi_batch_field_trace",
                  "mpi_velocity_forward_difference", "mpi_scale_trajectory", "mpi_reduce_lissajous",
+                 "mpi_vjp_forward", "mpi_vjp_adjoint",
                  "mpi_checks_enabled", "mpi_plan_check", "mpi_debug_fail_alloc", "mpi_plan_destroy",
                  "mpi_abi_version"):
         getattr(L, name).restype = ctypes.c_int
@@ -452,9 +455,9 @@ class Batch:
 
     def schedule(self, ranges: int = -1, c_all=None, s_all=None, g_all=None, stream=None) -> int:
         """Problem ranges per FFT-size group: -1 reports the count in use, a
-        positive count sets it, 0 times the pair on the given buffers (or on
-        zero-filled ones) with 1, 2, 4 and 8 ranges and keeps the fastest.
-        Results never depend on it."""
+        positive count sets it.  0 (choosing it by timing) is switched off in
+        the library and raises MpiError (MPI_ERR_UNSUPPORTED).  Results never
+        depend on the count."""
         chosen = ctypes.c_int32()
         ptrs = [0, 0, 0]
         if ranges == 0:
@@ -523,6 +526,29 @@ class Batch:
                                         self.work.data_ptr(), self.work.numel(), _stream(stream)),
                "mpi_batch_traj_vjp")
         return g_r, g_v
+
+    def _vjp(self, fn, name, a, a_n, b, b_n, out_n, stream):
+        self._flat(a, a_n, "input")
+        self._flat(b, b_n, "upstream gradient")
+        out = torch.empty(out_n, dtype=self.dtype, device=self.device)
+        g_h = torch.empty(self.count, dtype=torch.float64, device=self.device)
+        g_r = torch.empty(self.s_offsets[-1], dtype=self.dtype, device=self.device)
+        g_v = torch.empty_like(g_r)
+        _check(fn(self._h, a.data_ptr(), b.data_ptr(), out.data_ptr(), g_h.data_ptr(), g_r.data_ptr(),
+                  g_v.data_ptr(), self.work.data_ptr(), self.work.numel(), _stream(stream)), name)
+        return out, g_h, g_r, g_v
+
+    def vjp_forward(self, c_all, gs_all, stream=None):
+        """For s = A c: (A^T gs, <(dA/dh) c, gs> per problem, the sample
+        position and velocity gradients of <gs, A c>)."""
+        return self._vjp(self._L.mpi_vjp_forward, "mpi_vjp_forward", c_all, self.c_offsets[-1], gs_all,
+                         self.s_offsets[-1], self.c_offsets[-1], stream)
+
+    def vjp_adjoint(self, y_all, gc_all, stream=None):
+        """For c' = A^T y: (A gc, <(dA/dh) gc, y> per problem, the sample
+        position and velocity gradients of <y, A gc>)."""
+        return self._vjp(self._L.mpi_vjp_adjoint, "mpi_vjp_adjoint", y_all, self.s_offsets[-1], gc_all,
+                         self.c_offsets[-1], self.s_offsets[-1], stream)
 
     def adjoint_step(self, s_all, c_in, taus, c_out=None, stream=None):
         self._flat(s_all, self.s_offsets[-1], "s_all")

@@ -140,6 +140,8 @@ def test_trajectory_amplitude_entries_reject_bad_arguments(mpik):
     assert L.mpi_scale_trajectory(256, 512, 10, 1.0, 1.0, 0, 256, 2048, None) == -1      # r == rho
     assert L.mpi_scale_trajectory(256, 512, 10, 1.0, 1.0, 1, 1028, 2048, None) == -1     # misaligned
     assert L.mpi_reduce_lissajous(None, 256, 512, 768, 1024, 1280, 1536, 4096, 1 << 20, None) == -1
+    assert L.mpi_vjp_forward(None, 256, 512, 768, 1024, 1280, 1536, 4096, 1 << 20, None) == -1
+    assert L.mpi_vjp_adjoint(None, 256, 512, 768, 1024, 1280, 1536, 4096, 1 << 20, None) == -1
 
 
 def test_size_limits(mpik):

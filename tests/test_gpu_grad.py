@@ -104,6 +104,41 @@ def test_derivative_blocks_match_oracle(dtype, shapes, interp):
         assert rel_l2(den[b], O.denoise(xs[b], 0.5, 2)) <= tol, ("denoise", b)
 
 
+@pytest.mark.parametrize("dtype,shapes", [(torch.float32, SHAPES_FFT), (torch.float64, SHAPES)], ids=["fft-f32", "direct-f64"])
+def test_composite_vjps_are_their_building_blocks(dtype, shapes):
+    """mpi_vjp_forward and mpi_vjp_adjoint against the building-block calls
+    they compose, bit for bit, and against the oracle's VJPs of s = A c and
+    c' = A^T y (the h component through its definition <(dA/dh) x, y>)."""
+    gc = GradCase(shapes, dtype)
+    plan = gc.plan()
+    rng = np.random.default_rng(17)
+    ys = [rounded(rng.standard_normal((it["t"], 2)), dtype) for it in gc.items]
+    xs = [it["c"] for it in gc.items]
+    x_all, y_all = gc.cat(xs), gc.cat(ys)
+    # s = A c with upstream gradient y; c' = A^T y with upstream gradient x
+    gcx, gh_f, gr_f, gv_f = plan.vjp_forward(x_all, y_all)
+    gy, gh_a, gr_a, gv_a = plan.vjp_adjoint(y_all, x_all)
+    ref_gc = plan.adjoint(y_all)
+    ref_gy = plan.forward(x_all)
+    ref_gh = plan.dot(plan.forward_dh(x_all), y_all)
+    ref_gr, ref_gv = plan.traj_vjp(x_all, y_all)
+    torch.cuda.synchronize()
+    for got, ref in ((gcx, ref_gc), (gy, ref_gy), (gh_f, ref_gh), (gh_a, ref_gh), (gr_f, ref_gr), (gv_f, ref_gv),
+                     (gr_a, ref_gr), (gv_a, ref_gv)):
+        assert torch.equal(got, ref)
+    tol = APPLY_TOL[dtype]
+    g_r, g_v = GradCase.split(plan, gr_f, "signal"), GradCase.split(plan, gv_f, "signal")
+    gh = gh_f.cpu().numpy()
+    for b, it in enumerate(gc.items):
+        M = it["model"]
+        r_ref, v_ref = M.traj_vjp(xs[b], ys[b])
+        assert rel_l2(g_r[b], r_ref) <= tol and rel_l2(g_v[b], v_ref) <= tol, b
+        h_ref = np.sum(M.forward_dh(xs[b]) * ys[b])
+        assert abs(gh[b] - h_ref) <= tol * np.sum(np.abs(M.forward_dh(xs[b]) * ys[b])), b
+    with pytest.raises(ValueError):
+        plan.vjp_forward(x_all, x_all)               # an upstream gradient of the wrong shape
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_dot_is_exact_per_problem(dtype):
     """Per-problem float64 sums of products, per component and over the grid."""

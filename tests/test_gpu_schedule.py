@@ -1,7 +1,7 @@
 """The launch schedule of a batch (mpi_batch_schedule): problem ranges per
 FFT-size group on their own side streams.  Every range count gives the pair
-bit for bit, the timed choice is one of the candidates and leaves results
-unchanged, and the cached iteration graphs follow a change of schedule."""
+bit for bit, and the cached iteration graphs follow a change of schedule.
+The timed choice of the count is switched off (its test is skipped)."""
 import pytest
 import torch
 
@@ -39,8 +39,18 @@ def test_every_range_count_gives_the_same_pair(gpu, sizes, default, top):
         r *= 2
     with pytest.raises(mpik.MpiError):
         batch.schedule(top + 1)
+    batch.close()
+
+
+@pytest.mark.skip(reason="choosing the range count by timing is switched off in the library: its graph-captured "
+                         "timing runs once ended in a host-side fault whose cause is not established")
+def test_timed_range_choice_keeps_the_results(gpu):
+    batch, c_all = _batch([64] * 10 + [128] * 10)
+    s_ref, g_ref = batch.pair(c_all)
+    torch.cuda.synchronize()
+    s_ref, g_ref = s_ref.clone(), g_ref.clone()
     chosen = batch.schedule(0, c_all)
-    assert chosen in (1, 2, 4, 8) and chosen <= top and batch.schedule() == chosen
+    assert chosen in (1, 2, 4) and batch.schedule() == chosen
     s, g = batch.pair(c_all)
     torch.cuda.synchronize()
     assert torch.equal(s, s_ref) and torch.equal(g, g_ref)
