@@ -92,3 +92,46 @@ def test_random_shapes_match_oracle(gpu, dtype, seed, channels):
           f"{sorted(set(i['conv_mode'] for i in batch.info))}, worst element-wise forward {worst[0]:.1e}, "
           f"transpose {worst[1]:.1e}", flush=True)
     batch.close()
+
+
+@pytest.mark.parametrize("dtype,seed", [(torch.float32, 303), (torch.float64, 404)])
+def test_random_shapes_vjp_and_iteration(gpu, dtype, seed):
+    """The same kind of draw (both receive channels) through the
+    composite VJP of s = A c (A^T gs, <(dA/dh) c, gs>, the trajectory
+    gradients) and six denoised iterations with tau = 0.9 / lambda_max(A^T A)
+    (the oracle's power estimate), against the oracle."""
+    draws = _draw(seed, 16)
+    for d in draws:
+        d["r"], d["v"] = rounded(d["r"], dtype), rounded(d["v"], dtype)
+        d["c"], d["y"] = rounded(d["c"], dtype), rounded(d["y"], dtype)
+    batch = mpik.Batch([(d["n"], d["h"], d["R"], dev(d["r"], dtype), dev(d["v"], dtype), d["mode"], d["interp"])
+                        for d in draws], dtype=dtype, tune=False, deriv=True)
+    c_all = torch.cat([dev(d["c"], dtype).reshape(-1) for d in draws])
+    y_all = torch.cat([dev(d["y"], dtype).reshape(-1) for d in draws])
+    gc, g_h, g_r, g_v = batch.vjp_forward(c_all, y_all)
+    models = [O.Model(d["n"], d["h"], d["R"], d["r"], d["v"], interp=d["interp"]) for d in draws]
+    taus = [0.9 / max(O.power_lambda_max(M, iters=20), 1e-30) for M in models]
+    x_all = torch.zeros_like(c_all)
+    batch.iterate(y_all, x_all, 6, taus, 0.5, 2)
+    torch.cuda.synchronize()
+    gc_v = [x.double().cpu().numpy() for x in batch.c_views(gc)]
+    gr_v = [x.double().cpu().numpy() for x in batch.s_views(g_r)]
+    gv_v = [x.double().cpu().numpy() for x in batch.s_views(g_v)]
+    x_v = [x.double().cpu().numpy() for x in batch.c_views(x_all)]
+    gh = g_h.cpu().numpy()
+    l2 = TOL[dtype][0]
+    it_tol = 1e-4 if dtype == torch.float32 else 1e-11
+    for b, d in enumerate(draws):
+        M = models[b]
+        case = (b, d["n"], d["R"], d["t"], d["mode"], d["interp"])
+        ref_gc = M.adjoint(d["y"])
+        r_ref, v_ref = M.traj_vjp(d["c"], d["y"])
+        dh = M.forward_dh(d["c"]) * d["y"]
+        for got, ref, what in ((gc_v[b], ref_gc, "A^T gs"), (gr_v[b], r_ref, "g_r"), (gv_v[b], v_ref, "g_v")):
+            if np.any(ref):
+                assert rel_l2(got, ref) <= 10 * l2, (what, case, rel_l2(got, ref))
+        assert abs(gh[b] - dh.sum()) <= 10 * l2 * max(np.abs(dh).sum(), 1e-300), ("g_h", case, gh[b], dh.sum())
+        ref_x = O.iterate(M, d["y"], np.zeros((d["n"], d["n"])), taus[b], 6, sigma_px=0.5, radius=2)
+        if np.any(ref_x):
+            assert rel_l2(x_v[b], ref_x) <= it_tol, ("iterate", case, rel_l2(x_v[b], ref_x))
+    batch.close()
