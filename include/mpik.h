@@ -180,6 +180,13 @@ enum { MPI_BUILD_COL_SPLIT = 2, MPI_BUILD_COL_WAVE = 4 };
  * d w/d f (two values per sample); needed by mpi_batch_forward_dh,
  * mpi_batch_traj_vjp and mpi_batch_unrolled_vjp. */
 enum { MPI_BUILD_DERIV = 8 };
+/* Direct-path problems use this many waves splitting a tile's window rows
+ * (one flag at most, else MPI_ERR_ARG), instead of 8 or the tuner's choice;
+ * the path choice of MPI_BUILD_TUNE is then left to the batch-size rule.
+ * Every count computes the same operator; the waves' partial sums are added
+ * in a fixed order, so results may differ in the last bits between counts.
+ * For tests and tuning studies. */
+enum { MPI_BUILD_SLICES_4 = 16, MPI_BUILD_SLICES_8 = 32, MPI_BUILD_SLICES_16 = 64 };
 
 /* Plan and work bytes of a batch built with `flags` (MPI_BUILD_*). */
 int mpi_batch_bytes(const mpi_problem* probs, int count, int flags, size_t* plan_bytes, size_t* work_bytes);

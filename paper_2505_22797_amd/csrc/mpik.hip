@@ -271,8 +271,18 @@ int default_mode(const Shape& sh, int requested) {
     return sh.fft_ok ? 1 : 0;
 }
 
+// Wave slices that MPI_BUILD_SLICES_* force on the direct path: 0 none, -1 several flags.
+int forced_slices(int flags) {
+    const int f = flags & (MPI_BUILD_SLICES_4 | MPI_BUILD_SLICES_8 | MPI_BUILD_SLICES_16);
+    if (f == 0) return 0;
+    if (f & (f - 1)) return -1;
+    return f == MPI_BUILD_SLICES_4 ? 4 : f == MPI_BUILD_SLICES_8 ? 8 : 16;
+}
+
 int make_batch_layout(const mpi_problem* probs, int count, int flags, BatchLayout& B) {
     if (!probs || count < 1 || count > kMaxBatch) return MPI_ERR_ARG;
+    const int slices = forced_slices(flags);
+    if (slices < 0) return MPI_ERR_ARG;
     B.deriv = (flags & MPI_BUILD_DERIV) != 0;
     alloc_point();
     B.shapes.resize(count);
@@ -294,6 +304,7 @@ int make_batch_layout(const mpi_problem* probs, int count, int flags, BatchLayou
         const Shape& sh = B.shapes[b];
         const bool both = B.requested[b] == MPI_CONV_AUTO && sh.fft_ok && sh.direct_ok;
         layout_problem(sh, default_mode(sh, B.requested[b]), both, B.deriv, poff, woff, B.probs[b]);
+        if (slices) B.probs[b].slices = slices;
         B.probs[b].h = probs[b].h;
         B.probs[b].o_c = co;
         B.probs[b].o_s = so;
@@ -997,7 +1008,7 @@ int build_batch(const mpi_problem* probs, mpi_plan* pl, void* work, size_t work_
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_cache_load();
     for (int b = 0; b < pl->count; ++b) {
-        if (B.requested[b] != MPI_CONV_AUTO) continue;
+        if (B.requested[b] != MPI_CONV_AUTO || forced_slices(flags)) continue;
         const Shape& sh = B.shapes[b];
         if (!(sh.fft_ok && sh.direct_ok)) continue;
         const TuneKey key{sh.elem, sh.n, sh.R, t_bucket(sh.T)};

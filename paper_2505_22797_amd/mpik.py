@@ -41,6 +41,7 @@ EXPORTS = ("mpi_plan_bytes", "mpi_kernel_build", "mpi_forward", "mpi_adjoint", "
            "mpi_checks_enabled", "mpi_plan_check", "mpi_debug_fail_alloc",
            "mpi_plan_destroy", "mpi_status_str", "mpi_abi_version")
 MPI_BUILD_TUNE, MPI_BUILD_COL_SPLIT, MPI_BUILD_COL_WAVE, MPI_BUILD_DERIV = 1, 2, 4, 8
+SLICE_FLAGS = {4: 16, 8: 32, 16: 64}        # MPI_BUILD_SLICES_4 / _8 / _16
 NOALLOC_SCRATCH_BYTES = 64 << 20     # MPI_NOALLOC_SCRATCH_BYTES: the allocation-free pair's work memory
 
 
@@ -352,12 +353,13 @@ class Batch:
 
     def __init__(self, specs, dtype=torch.float32, tune: bool = True, columns: str | None = None,
                  deriv: bool = False, stream=None, interp: str = "bilinear", channels: str = "xy",
-                 grad=(1.0, 1.0)):
+                 grad=(1.0, 1.0), slices: int | None = None):
         """specs: list of (n, h, radius, r, v[, conv_mode[, interp]]) with r, v device (T, 2).
         columns: None (by batch size), "split" or "wave": shape of the column-FFT kernels.
         deriv: also build the dK/dh tables (for forward_dh) and the weight slopes.
         interp: "bilinear" or "cosine", for specs that do not name one.
-        channels ("xy" or "x") and grad (the selection-field gradient) apply to every problem."""
+        channels ("xy" or "x") and grad (the selection-field gradient) apply to every problem.
+        slices (4, 8 or 16): the direct path's wave slices per tile, forced for every problem."""
         self._L = lib()
         keep = []
         arr = (Problem * len(specs))()
@@ -378,7 +380,8 @@ class Batch:
         self.ns = [int(sp[0]) for sp in specs]
         self.ts = [int(sp[3].shape[0]) for sp in specs]
         flags = (MPI_BUILD_TUNE if tune else 0) | (MPI_BUILD_DERIV if deriv else 0) | {
-            None: 0, "split": MPI_BUILD_COL_SPLIT, "wave": MPI_BUILD_COL_WAVE}[columns]
+            None: 0, "split": MPI_BUILD_COL_SPLIT, "wave": MPI_BUILD_COL_WAVE}[columns] | (
+            SLICE_FLAGS[slices] if slices else 0)
         pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
         _check(self._L.mpi_batch_bytes(arr, self.count, flags, ctypes.byref(pb), ctypes.byref(wb)), "mpi_batch_bytes")
         self.plan_mem = torch.empty(pb.value, dtype=torch.uint8, device=self.device)

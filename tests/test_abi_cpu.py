@@ -212,3 +212,13 @@ def test_bounds_checks_only_in_the_checked_build(mpik):
     if not checked and os.path.exists(mpik.CHECK_LIBRARY):
         with mpik.use_library(mpik.CHECK_LIBRARY) as L:
             assert L.mpi_checks_enabled() == 1
+
+
+def test_slice_flags_are_exclusive(mpik):
+    """One MPI_BUILD_SLICES_* flag at most; each alone sizes a plan."""
+    L = mpik.lib()
+    probs = (mpik.Problem * 2)(*[_prob(mpik, n=32, radius=7, conv_mode="direct"), _prob(mpik, n=48, radius=15)])
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    for f in (16, 32, 64):
+        assert L.mpi_batch_bytes(probs, 2, f, ctypes.byref(pb), ctypes.byref(wb)) == 0
+    assert L.mpi_batch_bytes(probs, 2, 16 | 64, ctypes.byref(pb), ctypes.byref(wb)) == mpik.MPI_ERR_ARG

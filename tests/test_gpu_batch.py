@@ -157,6 +157,49 @@ def test_uneven_batch_of_64_with_tuning():
         assert rel_l2(gv[b].double().cpu().numpy(), g_ref) <= 1e-5, (b, batch.info[b])
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_every_direct_slice_count_matches_oracle(dtype):
+    """The autotuner's direct-path candidates, 4, 8 and 16 waves splitting a
+    tile's window rows, each forced on a batch of direct-path problems: the
+    forward, the transpose and three denoised iterations match the oracle,
+    and the counts agree with each other to rounding."""
+    shapes = [(24, 3, 2000), (40, 7, 4000), (33, 15, 3000), (64, 30, 6000)]
+    tol = 1e-5 if dtype == torch.float32 else 1e-12
+    items = []
+    for i, (n, R, t) in enumerate(shapes):
+        tr = S.lissajous(t, ax=0.85, ay=0.8 + 0.01 * i)
+        items.append(dict(n=n, R=R, h=S.h_fwhm2(n), r=rounded(tr.r, dtype), v=rounded(tr.v, dtype),
+                          c=rounded(S.ellipses_and_line(n, 300 + i), dtype)))
+    models = [O.Model(it["n"], it["h"], it["R"], it["r"], it["v"]) for it in items]
+    taus = [0.9 / O.power_lambda_max(M, iters=20) for M in models]
+    outs = {}
+    for sl in (4, 8, 16):
+        batch = mpik.Batch([(it["n"], it["h"], it["R"], dev(it["r"], dtype), dev(it["v"], dtype), "direct")
+                            for it in items], dtype=dtype, tune=False, slices=sl)
+        assert all(i["conv_mode"] == "direct" and i["slices"] == sl for i in batch.info)
+        c_all = torch.cat([dev(it["c"], dtype).reshape(-1) for it in items])
+        s_all = batch.forward(c_all)
+        g_all = batch.adjoint(s_all)
+        x_all = torch.zeros_like(c_all)
+        batch.iterate(s_all, x_all, 3, taus, 0.5, 2)
+        torch.cuda.synchronize()
+        outs[sl] = [[x.double().cpu().numpy() for x in batch.s_views(s_all)],
+                    [x.double().cpu().numpy() for x in batch.c_views(g_all)],
+                    [x.double().cpu().numpy() for x in batch.c_views(x_all)]]
+        batch.close()
+        for b, (it, M) in enumerate(zip(items, models)):
+            s_ref = M.forward(it["c"])
+            s_got = outs[sl][0][b]
+            assert rel_l2(s_got, s_ref) <= tol, (sl, b)
+            assert rel_l2(outs[sl][1][b], M.adjoint(rounded(s_got, dtype))) <= tol, (sl, b)
+            x_ref = O.iterate(M, rounded(s_got, dtype), np.zeros((it["n"], it["n"])), taus[b], 3, sigma_px=0.5,
+                              radius=2)
+            assert rel_l2(outs[sl][2][b], x_ref) <= 10 * tol, (sl, b)
+    for k in range(3):
+        for b in range(len(items)):
+            assert rel_l2(outs[4][k][b], outs[16][k][b]) <= tol, (k, b)
+
+
 @pytest.mark.parametrize("columns", ["split", "wave"])
 def test_uneven_sizes_iterate_matches_oracle(columns):
     """Problems of very different sizes in one batch: every launch is sized
