@@ -76,6 +76,7 @@ constexpr int kMaxBatch = 4096;
 constexpr int kSliceChoices[3] = {4, 8, 16};
 constexpr size_t kSmemLimit = 160 * 1024;
 constexpr int kMaxSide = 8;              // side streams of a plan
+constexpr int kLanes = 4;                // side streams per FFT-size group; more ranges queue on them
 constexpr int kIterBlock = 8;            // iterations per graph launch of a long mpi_iterate
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -767,14 +768,17 @@ int by_parts(const mpi_plan* pl, hipStream_t st, F&& body) {
     std::lock_guard<std::mutex> lk(const_cast<mpi_plan*>(pl)->fork_mu);
     HIP_TRY(hipEventRecord(pl->ev_fork, st));
     int k = 0;
+    const int lanes = std::min(pl->chunks, kLanes);
     for (int li = 0; li < 5; ++li) {
         if (!(pl->fft_m_mask & (1 << li))) continue;
-        for (int ch = 0; ch < pl->chunks; ++ch, ++k) {
+        for (int ch = 0; ch < pl->chunks; ++ch) {
             const int b0 = int(int64_t(ch) * B / pl->chunks), b1 = int(int64_t(ch + 1) * B / pl->chunks);
-            HIP_TRY(hipStreamWaitEvent(pl->side[k], pl->ev_fork, 0));
-            body(pl->side[k], li, b0, b1 - b0);
-            HIP_TRY(hipEventRecord(pl->ev_join[k], pl->side[k]));
+            const int q = k + ch % lanes;
+            if (ch < lanes) HIP_TRY(hipStreamWaitEvent(pl->side[q], pl->ev_fork, 0));
+            body(pl->side[q], li, b0, b1 - b0);
+            if (ch + lanes >= pl->chunks) HIP_TRY(hipEventRecord(pl->ev_join[q], pl->side[q]));
         }
+        k += lanes;
     }
     if (pl->any_direct) body(st, kDirectPart, 0, B);
     for (int i = 0; i < k; ++i) HIP_TRY(hipStreamWaitEvent(st, pl->ev_join[i], 0));
@@ -1074,7 +1078,7 @@ int create_streams(mpi_plan* pl, int ranges) {
         return MPI_OK;
     }
     bool ok = !injected_failure() && hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) == hipSuccess;
-    for (int i = 0; i < groups * pl->chunks && ok; ++i)
+    for (int i = 0; i < groups * std::min(pl->chunks, kLanes) && ok; ++i)
         ok = !injected_failure() && hipStreamCreateWithFlags(&pl->side[i], hipStreamNonBlocking) == hipSuccess &&
              !injected_failure() && hipEventCreateWithFlags(&pl->ev_join[i], hipEventDisableTiming) == hipSuccess;
     if (!ok) {
