@@ -176,18 +176,23 @@ __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirs
 
 // Work-groups are dealt to the 8 XCDs (each with its own L2) round-robin by
 // their linear index.  With grid.x a multiple of 8, block x runs on XCD x % 8;
-// mapping it to unit (x % 8) * ceil(n/8) + x / 8 gives every XCD one
+// mapping it to unit ((x + rot) % 8) * ceil(n/8) + x / 8 gives every XCD one
 // contiguous band of units, so the transposing stores of neighbouring rows or
-// columns fill whole cache lines in one L2.  The map is one-to-one from
-// blocks [0, 8 * ceil(n/8)) onto units; it returns -1 for padding blocks and
-// for blocks beyond that range (a batched launch is sized for its largest
-// problem).
+// columns fill whole cache lines in one L2, and the stages that read the
+// samples of two neighbouring rows find the shared row in the same L2.  rot
+// (the problem's index in the launch, for the sampling stages) turns the
+// bands over the XCDs from problem to problem: a trajectory's dense rows (a
+// Lissajous figure's turning lines hold up to nine times the mean samples)
+// then load every XCD alike over a batch instead of always the same two.
+// The map is one-to-one from blocks [0, 8 * ceil(n/8)) onto units; it returns
+// -1 for padding blocks and for blocks beyond that range (a batched launch is
+// sized for its largest problem).
 constexpr int kXcds = 8;
 __host__ __device__ constexpr int xcd_grid(int n) { return (n + kXcds - 1) / kXcds * kXcds; }
-__device__ __forceinline__ int xcd_unit(int x, int n) {
+__device__ __forceinline__ int xcd_unit(int x, int n, int rot = 0) {
     const int per = (n + kXcds - 1) / kXcds;
     if (x / kXcds >= per) return -1;
-    const int u = (x % kXcds) * per + x / kXcds;
+    const int u = ((x + rot) % kXcds) * per + x / kXcds;
     return u < n ? u : -1;
 }
 

@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(256) k_core_dir_gather(const Prob* __restrict_
     double* red = reinterpret_cast<double*>(smem);                 // reductions, while pd is not live
     const int b = blockIdx.y, cnt = gridDim.y, cur = par * cnt + b, nxt = (1 - par) * cnt + b;
     const Prob& p = P[b];
-    const int N = p.n, j = xcd_unit(blockIdx.x, N), tid = threadIdx.x;
+    const int N = p.n, j = xcd_unit(blockIdx.x, N, b), tid = threadIdx.x;
     if (j < 0) return;
     const bool lead = j == 0 && tid == 0;
     if (s.done[cur]) {
@@ -306,7 +306,7 @@ __global__ void __launch_bounds__(256) k_core_update(const Prob* __restrict__ P,
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.y, cnt = gridDim.y, nxt = (1 - par) * cnt + b;
     const Prob& p = P[b];
-    const int N = p.n, j = xcd_unit(blockIdx.x, N), tid = threadIdx.x;
+    const int N = p.n, j = xcd_unit(blockIdx.x, N, b), tid = threadIdx.x;
     if (j < 0 || s.done[nxt]) return;
     const double d2 = 4.0 / (double(N) * N);                   // delta^2
     const double reg = gamma / d2;                               // gamma delta^2 / delta^4

@@ -401,7 +401,7 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
                                      const char* __restrict__ plan, char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<GatherSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
-    const int N = p.n, nb = p.nb, b = xcd_unit(blockIdx.x, nb);
+    const int N = p.n, nb = p.nb, b = xcd_unit(blockIdx.x, nb, blockIdx.y);
     if (b < 0) return;
     const int* binstart = at<int>(plan, p.o_binstart);
     int p0 = binstart[b * nb], p1 = binstart[(b + 1) * nb];
@@ -477,7 +477,7 @@ template <typename T, int M, bool SORTED>
 __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, const char* __restrict__ plan,
                                      char* __restrict__ work, char* smem) {
     constexpr int H = M / 2 + 1;
-    const int N = p.n, j = xcd_unit(blockIdx.x, N);
+    const int N = p.n, j = xcd_unit(blockIdx.x, N, blockIdx.y);
     if (j < 0) return;
     const bool g_in = scatter_g_in_region<T, M>(N);
     char* shared_area = smem + (g_in ? 0 : lds_align(size_t(3) * N * sizeof(T)));
