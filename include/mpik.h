@@ -29,7 +29,14 @@
  * memory.  An mpi_plan is a small host object owned by the library
  * (mpi_plan_destroy frees it); it refers into the caller's plan memory, which
  * must outlive it.  A plan's results are fixed at the build; only its launch
- * schedule may change later (mpi_batch_schedule), which never changes them.  Calls on different
+ * schedule may change later (mpi_batch_schedule), which never changes them.
+ * The buffers an apply call writes (its outputs and the work memory) must not
+ * share a byte with any other buffer of the call, except where a call says
+ * it works in place (mpi_iterate's c; mpi_batch_adjoint_step with c_out ==
+ * c_in); buffers it only reads may share memory.  The forward, transpose,
+ * pair, iteration, derivative, residual, step and denoiser calls compare the
+ * byte ranges the plan gives each buffer and return MPI_ERR_ARG on an
+ * overlap.  Calls on different
  * streams may run concurrently if each passes its own work buffer.  A batch
  * whose problems use several FFT sizes (or both paths) runs each group on a
  * side stream of the plan, forked from and joined back to the caller's
@@ -38,8 +45,8 @@
  * Errors: every call returns an mpi_status; nothing throws or aborts across
  * the ABI.  Argument errors are found on the host before anything is
  * enqueued.  Every apply call only enqueues work on the given stream and
- * never synchronises; a fault of an earlier kernel surfaces as MPI_ERR_HIP
- * on a later call.  mpi_kernel_build synchronises its stream once, to report
+ * never synchronises (except where its description says so); a fault of an
+ * earlier kernel surfaces as MPI_ERR_HIP on a later call.  mpi_kernel_build synchronises its stream once, to report
  * samples outside the grid (MPI_ERR_DOMAIN).
  */
 #ifndef MPIK_H
@@ -114,6 +121,13 @@ typedef struct {
     int32_t use_graph;         /* 1: capture one iteration as a HIP graph and  */
                                /*    replay it (needs a non-null stream)       */
 } mpi_iter_params;
+/* With use_graph the captured graphs stay in the plan, keyed by the buffers
+ * (s, c, work) and the denoiser.  A call with other buffers or another
+ * denoiser records them again after synchronising its own stream, so such a
+ * call must be on the stream of the plan's previous graph-replayed call, or
+ * come after that call's work has finished; and graph-replayed calls on one
+ * plan come from one host thread at a time (the same holds for the
+ * Deconvolution and Core Stage solvers, which replay cached graphs too). */
 
 typedef struct mpi_plan mpi_plan;
 
@@ -281,7 +295,8 @@ int mpi_batch_iterate(const mpi_plan* plan, const void* s_all, void* c_all,
  *   c_in may equal c_out).  taus is a host array of count values.
  *
  * mpi_batch_denoise: c = D(u), the separable Gaussian of mpi_iter_params
- *   (sigma_px > 0, radius 0..8, weights summing to 1, zero padding); u != c.
+ *   (sigma_px > 0, radius 0..8, weights summing to 1, zero padding); u and c
+ *   must not overlap.
  *   D is symmetric, so it is also its own transpose.
  *
  * mpi_batch_dot: out[b] = sum a_b . b_b in float64 for every problem, with a

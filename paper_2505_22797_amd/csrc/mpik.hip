@@ -354,7 +354,6 @@ struct mpi_plan {
     int dtype = MPI_F32;
     char* plan = nullptr;
     const Prob* dprob = nullptr;
-    double wts[32] = {0};
     // launch extents over the batch
     int max_n = 0, max_rowpairs = 0, max_h = 0, max_nb = 0, max_tiles = 0, max_dntiles = 0;
     int64_t max_t = 0;
@@ -874,6 +873,29 @@ int iteration_impl(const mpi_plan* pl, T* c, bool denoise, int rad, char* work, 
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
+// A buffer of an apply call: its bytes over the batch and whether the call
+// writes it.
+struct Buf {
+    const void* p;
+    size_t bytes;
+    bool written;
+};
+size_t c_bytes(const mpi_plan* pl) { return size_t(pl->L.c_elems) * pl->L.elem; }   // concentration-shaped
+size_t s_bytes(const mpi_plan* pl) { return size_t(pl->L.s_elems) * pl->L.elem; }   // signal-shaped
+Buf work_buf(const mpi_plan* pl, const void* work) { return Buf{work, pl->L.work_bytes, true}; }
+
+// True when no buffer the call writes shares a byte with another of its
+// buffers (buffers it only reads may share memory).
+bool disjoint(std::initializer_list<Buf> bufs) {
+    for (auto i = bufs.begin(); i != bufs.end(); ++i)
+        for (auto j = i + 1; j != bufs.end(); ++j) {
+            if (!i->written && !j->written) continue;
+            const uintptr_t a = reinterpret_cast<uintptr_t>(i->p), b = reinterpret_cast<uintptr_t>(j->p);
+            if (a < b + j->bytes && b < a + i->bytes) return false;
+        }
+    return true;
+}
+
 int check_call(const mpi_plan* pl, const void* a, const void* b, const void* work, size_t work_bytes) {
     if (!pl || !a || !b || !work) return MPI_ERR_ARG;
     if (work_bytes < pl->L.work_bytes) return MPI_ERR_WORKSPACE;
@@ -1160,18 +1182,27 @@ int set_ranges(mpi_plan* pl, int ranges, hipStream_t st) {
     return create_streams(pl, ranges);
 }
 
+// Gaussian weights of the denoiser stand-in (2 radius + 1, normalised to sum
+// 1) into the work buffer.  They are computed in a local array: a copy from
+// pageable host memory has consumed its source when hipMemcpyAsync returns,
+// and host threads that share a plan keep their own weights.
+hipError_t upload_gauss(const mpi_plan* pl, double sigma_px, int radius, char* work, hipStream_t st) {
+    double w[2 * kDnMaxR + 1];
+    double sum = 0.0;
+    for (int k = -radius; k <= radius; ++k) {
+        w[k + radius] = std::exp(-0.5 * k * k / (sigma_px * sigma_px));
+        sum += w[k + radius];
+    }
+    for (int k = 0; k <= 2 * radius; ++k) w[k] /= sum;
+    return hipMemcpyAsync(work + pl->L.w_wts, w, sizeof(double) * (2 * radius + 1), hipMemcpyHostToDevice, st);
+}
+
 // Per-problem steps and the normalised Gaussian weights of the denoiser
 // (sigma > 0) into the work buffer.
 hipError_t upload_iter_consts(mpi_plan* pl, double sigma, int rad, const double* taus, char* work, hipStream_t st) {
     hipError_t e = hipMemcpyAsync(work + pl->L.w_taus, taus, sizeof(double) * pl->count, hipMemcpyHostToDevice, st);
     if (e != hipSuccess || !(sigma > 0.0)) return e;
-    double sum = 0.0;
-    for (int k = -rad; k <= rad; ++k) {
-        pl->wts[k + rad] = std::exp(-0.5 * k * k / (sigma * sigma));
-        sum += pl->wts[k + rad];
-    }
-    for (int k = 0; k <= 2 * rad; ++k) pl->wts[k] /= sum;
-    return hipMemcpyAsync(work + pl->L.w_wts, pl->wts, sizeof(double) * (2 * rad + 1), hipMemcpyHostToDevice, st);
+    return upload_gauss(pl, sigma, rad, work, st);
 }
 
 // ------------------------------------------------------------ unrolled VJP --
@@ -1589,17 +1620,6 @@ int trim_and_variance(const mpi_plan* pl, T* x, double pct, char* dw, const Deco
     return MPI_OK;
 }
 
-// Gaussian weights of the denoiser stand-in into the plan's work buffer.
-hipError_t upload_gauss(mpi_plan* pl, double sigma_px, int radius, char* work, hipStream_t st) {
-    double sum = 0.0;
-    for (int k = -radius; k <= radius; ++k) {
-        pl->wts[k + radius] = std::exp(-0.5 * k * k / (sigma_px * sigma_px));
-        sum += pl->wts[k + radius];
-    }
-    for (int k = 0; k <= 2 * radius; ++k) pl->wts[k] /= sum;
-    return hipMemcpyAsync(work + pl->L.w_wts, pl->wts, sizeof(double) * (2 * radius + 1), hipMemcpyHostToDevice, st);
-}
-
 // The ZeroShot-PnP loop (Algorithm "ZeroShot-PnP"): per pass k = 0..n_it,
 // rho_1 = CG on (C^T C + nu I) rho_1 = C u + nu rho_2, trim, sigma =
 // sqrt(Var rho_1), lambda = nu0 sigma^2 on the first pass, rho_2 = D(rho_1),
@@ -1768,18 +1788,20 @@ int check_deconv(const mpi_plan* pl, const void* a, const void* b, const void* w
 }
 
 // Checks shared by the two composite VJP entries: a, b are the operator's
-// input and the upstream gradient, out the input gradient (distinct buffers).
+// input and the upstream gradient, out the input gradient; a_sig: a is
+// signal-shaped (then b is concentration-shaped, out signal-shaped).  Every
+// output is disjoint from every other buffer.
 int check_vjp(const mpi_plan* plan, const void* a, const void* b, const void* out, const double* g_h,
-              const void* g_r, const void* g_v, const void* work, size_t work_bytes) {
+              const void* g_r, const void* g_v, const void* work, size_t work_bytes, bool a_sig) {
     int rc = check_call(plan, a, b, work, work_bytes);
     if (rc != MPI_OK) return rc;
     const size_t el = plan->L.elem;
     if (!out || !g_h || !g_r || !g_v) return MPI_ERR_ARG;
     if (misaligned(out, el) || misaligned(g_r, 2 * el) || misaligned(g_v, el) || misaligned(g_h, 8)) return MPI_ERR_ARG;
-    const void* bufs[] = {a, b, out, g_r, g_v};
-    for (int i = 0; i < 5; ++i)
-        for (int j = i + 1; j < 5; ++j)
-            if (bufs[i] == bufs[j]) return MPI_ERR_ARG;
+    const size_t C = c_bytes(plan), S = s_bytes(plan);
+    if (!disjoint({{a, a_sig ? S : C, false}, {b, a_sig ? C : S, false}, {out, a_sig ? S : C, true},
+                   {g_h, sizeof(double) * plan->count, true}, {g_r, S, true}, {g_v, S, true}, work_buf(plan, work)}))
+        return MPI_ERR_ARG;
     if (!plan->L.deriv) return MPI_ERR_UNSUPPORTED;
     if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
     return MPI_OK;
@@ -1886,6 +1908,7 @@ int mpi_batch_forward(const mpi_plan* plan, const void* c, void* s, void* work, 
         int rc = check_call(plan, c, s, work, work_bytes);
         if (rc != MPI_OK) return rc;
         if (misaligned(s, 2 * plan->L.elem)) return MPI_ERR_ARG;   // written as (x, y) pairs
+        if (!disjoint({{c, c_bytes(plan), false}, {s, s_bytes(plan), true}, work_buf(plan, work)})) return MPI_ERR_ARG;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         char* w = static_cast<char*>(work);
         return plan->dtype == MPI_F64
@@ -1900,7 +1923,9 @@ int mpi_batch_pair(const mpi_plan* plan, const void* c, void* s, void* g, void* 
         int rc = check_call(plan, c, s, work, work_bytes);
         if (rc != MPI_OK) return rc;
         if (!g || misaligned(g, plan->L.elem) || misaligned(s, 2 * plan->L.elem)) return MPI_ERR_ARG;
-        if (g == c || g == s) return MPI_ERR_ARG;
+        if (!disjoint({{c, c_bytes(plan), false}, {s, s_bytes(plan), true}, {g, c_bytes(plan), true},
+                       work_buf(plan, work)}))
+            return MPI_ERR_ARG;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         char* w = static_cast<char*>(work);
         return plan->dtype == MPI_F64
@@ -1951,6 +1976,7 @@ int mpi_batch_adjoint(const mpi_plan* plan, const void* s, void* c, void* work, 
     return guarded([&]() -> int {
         int rc = check_call(plan, s, c, work, work_bytes);
         if (rc != MPI_OK) return rc;
+        if (!disjoint({{s, s_bytes(plan), false}, {c, c_bytes(plan), true}, work_buf(plan, work)})) return MPI_ERR_ARG;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         char* w = static_cast<char*>(work);
         return plan->dtype == MPI_F64
@@ -1983,6 +2009,7 @@ int mpi_batch_iterate(const mpi_plan* plan, const void* s, void* c, const mpi_it
         rc = check_iter(params);
         if (rc != MPI_OK) return rc;
         if (!taus) return MPI_ERR_ARG;
+        if (!disjoint({{s, s_bytes(plan), false}, {c, c_bytes(plan), true}, work_buf(plan, work)})) return MPI_ERR_ARG;
         for (int b = 0; b < plan->count; ++b)
             if (!std::isfinite(taus[b])) return MPI_ERR_ARG;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
@@ -2012,6 +2039,7 @@ int mpi_batch_forward_dh(const mpi_plan* plan, const void* x, void* s, void* wor
         int rc = check_call(plan, x, s, work, work_bytes);
         if (rc != MPI_OK) return rc;
         if (misaligned(s, 2 * plan->L.elem)) return MPI_ERR_ARG;   // written as (x, y) pairs
+        if (!disjoint({{x, c_bytes(plan), false}, {s, s_bytes(plan), true}, work_buf(plan, work)})) return MPI_ERR_ARG;
         if (!plan->L.deriv) return MPI_ERR_UNSUPPORTED;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         char* w = static_cast<char*>(work);
@@ -2027,6 +2055,9 @@ int mpi_batch_residual(const mpi_plan* plan, const void* c, const void* y, void*
         int rc = check_call(plan, c, y, work, work_bytes);
         if (rc != MPI_OK) return rc;
         if (!out || misaligned(out, 2 * plan->L.elem)) return MPI_ERR_ARG;   // written as (x, y) pairs
+        if (!disjoint({{c, c_bytes(plan), false}, {y, s_bytes(plan), false}, {out, s_bytes(plan), true},
+                       work_buf(plan, work)}))
+            return MPI_ERR_ARG;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         char* w = static_cast<char*>(work);
         return plan->dtype == MPI_F64
@@ -2043,6 +2074,9 @@ int mpi_batch_traj_vjp(const mpi_plan* plan, const void* x, const void* y, void*
         int rc = check_call(plan, x, y, work, work_bytes);
         if (rc != MPI_OK) return rc;
         if (!g_r || !g_v || misaligned(g_r, plan->L.elem) || misaligned(g_v, plan->L.elem)) return MPI_ERR_ARG;
+        if (!disjoint({{x, c_bytes(plan), false}, {y, s_bytes(plan), false}, {g_r, s_bytes(plan), true},
+                       {g_v, s_bytes(plan), true}, work_buf(plan, work)}))
+            return MPI_ERR_ARG;
         if (!plan->L.deriv) return MPI_ERR_UNSUPPORTED;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         char* w = static_cast<char*>(work);
@@ -2057,7 +2091,7 @@ int mpi_batch_traj_vjp(const mpi_plan* plan, const void* x, const void* y, void*
 int mpi_vjp_forward(const mpi_plan* plan, const void* c, const void* gs, void* gc, double* g_h, void* g_r,
                     void* g_v, void* work, size_t work_bytes, hipStream_t stream) {
     return guarded([&]() -> int {
-        int rc = check_vjp(plan, c, gs, gc, g_h, g_r, g_v, work, work_bytes);
+        int rc = check_vjp(plan, c, gs, gc, g_h, g_r, g_v, work, work_bytes, false);
         if (rc != MPI_OK) return rc;
         char* w = static_cast<char*>(work);
         if (plan->dtype == MPI_F64) {
@@ -2080,7 +2114,7 @@ int mpi_vjp_forward(const mpi_plan* plan, const void* c, const void* gs, void* g
 int mpi_vjp_adjoint(const mpi_plan* plan, const void* y, const void* gc, void* gy, double* g_h, void* g_r,
                     void* g_v, void* work, size_t work_bytes, hipStream_t stream) {
     return guarded([&]() -> int {
-        int rc = check_vjp(plan, y, gc, gy, g_h, g_r, g_v, work, work_bytes);
+        int rc = check_vjp(plan, y, gc, gy, g_h, g_r, g_v, work, work_bytes, true);
         if (rc != MPI_OK) return rc;
         if (misaligned(gy, 2 * plan->L.elem)) return MPI_ERR_ARG;
         char* w = static_cast<char*>(work);
@@ -2107,6 +2141,12 @@ int mpi_batch_adjoint_step(const mpi_plan* plan, const void* s, const void* c_in
         int rc = check_call(plan, s, c_in, work, work_bytes);
         if (rc != MPI_OK) return rc;
         if (!c_out || misaligned(c_out, plan->L.elem) || !taus) return MPI_ERR_ARG;
+        // c_out may be c_in itself (each element is read, then written, by one thread), not a shifted copy
+        if (c_out != c_in && !disjoint({{c_in, c_bytes(plan), false}, {c_out, c_bytes(plan), true}}))
+            return MPI_ERR_ARG;
+        if (!disjoint({{s, s_bytes(plan), false}, {c_out, c_bytes(plan), true}, work_buf(plan, work)}) ||
+            !disjoint({{c_in, c_bytes(plan), false}, work_buf(plan, work)}))
+            return MPI_ERR_ARG;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         char* w = static_cast<char*>(work);
         HIP_TRY(hipMemcpyAsync(w + plan->L.w_taus, taus, sizeof(double) * plan->count, hipMemcpyHostToDevice, stream));
@@ -2123,18 +2163,12 @@ int mpi_batch_denoise(const mpi_plan* plan, const void* u, void* c, double sigma
     return guarded([&]() -> int {
         int rc = check_call(plan, u, c, work, work_bytes);
         if (rc != MPI_OK) return rc;
-        if (!(sigma_px > 0.0) || radius < 0 || radius > kDnMaxR || u == c) return MPI_ERR_ARG;
+        if (!(sigma_px > 0.0) || radius < 0 || radius > kDnMaxR) return MPI_ERR_ARG;
+        if (!disjoint({{u, c_bytes(plan), false}, {c, c_bytes(plan), true}, work_buf(plan, work)})) return MPI_ERR_ARG;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
-        mpi_plan* pl = const_cast<mpi_plan*>(plan);
+        const mpi_plan* pl = plan;
         char* w = static_cast<char*>(work);
-        double sum = 0.0;
-        for (int k = -radius; k <= radius; ++k) {
-            pl->wts[k + radius] = std::exp(-0.5 * k * k / (sigma_px * sigma_px));
-            sum += pl->wts[k + radius];
-        }
-        for (int k = 0; k <= 2 * radius; ++k) pl->wts[k] /= sum;
-        HIP_TRY(hipMemcpyAsync(w + pl->L.w_wts, pl->wts, sizeof(double) * (2 * radius + 1), hipMemcpyHostToDevice,
-                               stream));
+        HIP_TRY(upload_gauss(pl, sigma_px, radius, w, stream));
         const dim3 grid(pl->max_dntiles, pl->max_dntiles, pl->count);
         if (plan->dtype == MPI_F64)
             k_denoise<double><<<grid, 256, 0, stream>>>(pl->dprob, w, static_cast<const double*>(u),
