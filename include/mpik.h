@@ -33,10 +33,10 @@
  * The buffers an apply call writes (its outputs and the work memory) must not
  * share a byte with any other buffer of the call, except where a call says
  * it works in place (mpi_iterate's c; mpi_batch_adjoint_step with c_out ==
- * c_in); buffers it only reads may share memory.  The forward, transpose,
- * pair, iteration, derivative, residual, step and denoiser calls compare the
- * byte ranges the plan gives each buffer and return MPI_ERR_ARG on an
- * overlap.  Calls on different
+ * c_in); buffers it only reads may share memory.  Every call except the
+ * per-stage diagnostics (mpi_stage_launch) compares the byte ranges that the
+ * plan or its size arguments give each buffer and returns MPI_ERR_ARG on an
+ * overlap, before anything is enqueued.  Calls on different
  * streams may run concurrently if each passes its own work buffer.  A batch
  * whose problems use several FFT sizes (or both paths) runs each group on a
  * side stream of the plan, forked from and joined back to the caller's

@@ -1891,6 +1891,8 @@ int mpi_batch_sample_order(const mpi_plan* plan, int index, int32_t* order, int3
         if (!plan || index < 0 || index >= plan->count || !order || !cell) return MPI_ERR_ARG;
         if (misaligned(order, 4) || misaligned(cell, 4)) return MPI_ERR_ARG;
         const Prob& p = plan->L.probs[index];
+        if (!disjoint({{order, sizeof(int32_t) * size_t(p.t), true}, {cell, sizeof(int32_t) * size_t(p.t), true}}))
+            return MPI_ERR_ARG;
         k_sample_order<<<blocks(p.t, 256), 256, 0, stream>>>(plan->dprob + index, plan->plan, order, cell);
         return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
     });
@@ -2187,7 +2189,10 @@ int mpi_batch_dot(const mpi_plan* plan, const void* a, const void* b, int space,
     return guarded([&]() -> int {
         int rc = check_call(plan, a, b, work, work_bytes);
         if (rc != MPI_OK) return rc;
-        if (!out || (space != 0 && space != 1) || comp < 0 || comp > 2) return MPI_ERR_ARG;
+        if (!out || misaligned(out, 8) || (space != 0 && space != 1) || comp < 0 || comp > 2) return MPI_ERR_ARG;
+        const size_t n = space == 0 ? s_bytes(plan) : c_bytes(plan);
+        if (!disjoint({{a, n, false}, {b, n, false}, {out, sizeof(double) * plan->count, true}, work_buf(plan, work)}))
+            return MPI_ERR_ARG;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         if (plan->dtype == MPI_F64)
             launch_dot<double>(plan, static_cast<const double*>(a), static_cast<const double*>(b), space, comp, out, 0,
@@ -2204,9 +2209,13 @@ int mpi_reduce_lissajous(const mpi_plan* plan, const void* g_r, const void* g_v,
     return guarded([&]() -> int {
         int rc = check_call(plan, g_r, g_v, work, work_bytes);
         if (rc != MPI_OK) return rc;
-        if (!rho || !nu || !g_ax || !g_ay || g_ax == g_ay) return MPI_ERR_ARG;
+        if (!rho || !nu || !g_ax || !g_ay) return MPI_ERR_ARG;
         const size_t el = plan->L.elem;
         if (misaligned(rho, el) || misaligned(nu, el) || misaligned(g_ax, 8) || misaligned(g_ay, 8)) return MPI_ERR_ARG;
+        const size_t S = s_bytes(plan), G = sizeof(double) * plan->count;
+        if (!disjoint({{g_r, S, false}, {g_v, S, false}, {rho, S, false}, {nu, S, false}, {g_ax, G, true},
+                       {g_ay, G, true}, work_buf(plan, work)}))
+            return MPI_ERR_ARG;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         double* part = reinterpret_cast<double*>(static_cast<char*>(work) + plan->L.w_dot);
         const dim3 grid(kDotParts, plan->count);
@@ -2231,7 +2240,8 @@ int mpi_scale_trajectory(const void* rho, const void* nu, int64_t n_samples, dou
         if (dtype != MPI_F32 && dtype != MPI_F64) return MPI_ERR_DTYPE;
         const size_t el = dtype == MPI_F64 ? 8 : 4;
         if (misaligned(rho, el) || misaligned(nu, el) || misaligned(r, el) || misaligned(v, el)) return MPI_ERR_ARG;
-        if (r == v || r == rho || r == nu || v == rho || v == nu) return MPI_ERR_ARG;
+        const size_t n = size_t(2) * size_t(n_samples) * el;
+        if (!disjoint({{rho, n, false}, {nu, n, false}, {r, n, true}, {v, n, true}})) return MPI_ERR_ARG;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         const int nblk = blocks(n_samples, 256);
         if (dtype == MPI_F64)
@@ -2270,6 +2280,11 @@ int mpi_batch_unrolled_vjp(const mpi_plan* plan, const void* s, const void* chec
         if (vjp_bytes < vjp_layout(plan, every).bytes) return MPI_ERR_WORKSPACE;
         for (int b = 0; b < plan->count; ++b)
             if (!std::isfinite(taus[b])) return MPI_ERR_ARG;
+        const size_t C = c_bytes(plan), S = s_bytes(plan), ncp = size_t((n_iter + every - 1) / every);
+        if (!disjoint({{s, S, false}, {checkpoints, ncp * C, false}, {gbar, C, true},
+                       {g_h, sizeof(double) * plan->count, true}, {g_r, S, true}, {g_v, S, true}, work_buf(plan, work),
+                       {vjp_work, vjp_layout(plan, every).bytes, true}}))
+            return MPI_ERR_ARG;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         mpi_plan* pl = const_cast<mpi_plan*>(plan);
         char* w = static_cast<char*>(work);
@@ -2298,7 +2313,7 @@ int mpi_batch_trace_conv(const mpi_plan* plan, const void* x, void* y, void* wor
     return guarded([&]() -> int {
         int rc = check_call(plan, x, y, work, work_bytes);
         if (rc != MPI_OK) return rc;
-        if (x == y) return MPI_ERR_ARG;
+        if (!disjoint({{x, c_bytes(plan), false}, {y, c_bytes(plan), true}, work_buf(plan, work)})) return MPI_ERR_ARG;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         char* w = static_cast<char*>(work);
         if (plan->dtype == MPI_F64)
@@ -2314,7 +2329,10 @@ int mpi_batch_cg(const mpi_plan* plan, const void* rhs, void* x, const double* n
     return guarded([&]() -> int {
         int rc = check_deconv(plan, rhs, x, work, work_bytes, dwork, dbytes);
         if (rc != MPI_OK) return rc;
-        if (!nus || rhs == x || !(tol >= 0.0) || max_iter < 0) return MPI_ERR_ARG;
+        if (!nus || !(tol >= 0.0) || max_iter < 0) return MPI_ERR_ARG;
+        if (!disjoint({{rhs, c_bytes(plan), false}, {x, c_bytes(plan), true}, work_buf(plan, work),
+                       {dwork, deconv_layout(plan).bytes, true}}))
+            return MPI_ERR_ARG;
         for (int b = 0; b < plan->count; ++b)
             if (!(nus[b] >= 0.0) || !std::isfinite(nus[b])) return MPI_ERR_ARG;
         const DeconvLayout L = deconv_layout(plan);
@@ -2336,6 +2354,7 @@ int mpi_batch_trim_sigma(const mpi_plan* plan, void* x, double pct, double* q, d
         int rc = check_deconv(plan, x, x, work, work_bytes, dwork, dbytes);
         if (rc != MPI_OK) return rc;
         if (!(pct <= 100.0) || std::isnan(pct)) return MPI_ERR_ARG;
+        if (!disjoint({{x, c_bytes(plan), true}, {dwork, deconv_layout(plan).bytes, true}})) return MPI_ERR_ARG;
         const DeconvLayout L = deconv_layout(plan);
         std::vector<double> var(plan->count);
         char* dw = static_cast<char*>(dwork);
@@ -2355,7 +2374,10 @@ int mpi_batch_pnp(const mpi_plan* plan, const void* u, void* rho, const mpi_pnp_
     return guarded([&]() -> int {
         int rc = check_deconv(plan, u, rho, work, work_bytes, dwork, dbytes);
         if (rc != MPI_OK) return rc;
-        if (!params || u == rho || params->n_it < 0 || params->cg_max_iter < 0 || !(params->nu0 > 0.0) ||
+        if (!disjoint({{u, c_bytes(plan), false}, {rho, c_bytes(plan), true}, work_buf(plan, work),
+                       {dwork, deconv_layout(plan).bytes, true}}))
+            return MPI_ERR_ARG;
+        if (!params || params->n_it < 0 || params->cg_max_iter < 0 || !(params->nu0 > 0.0) ||
             !std::isfinite(params->nu0) || !(params->cg_tol >= 0.0) || !(params->clip_percentile <= 100.0))
             return MPI_ERR_ARG;
         if (params->denoise_sigma_px > 0.0 && (params->denoise_radius < 0 || params->denoise_radius > kDnMaxR))
@@ -2389,6 +2411,9 @@ int mpi_batch_core_stage(const mpi_plan* plan, const void* s, void* field, doubl
             max_iter < 0)
             return MPI_ERR_ARG;
         if (cbytes < core_layout(plan).bytes) return MPI_ERR_WORKSPACE;
+        if (!disjoint({{s, s_bytes(plan), false}, {field, 3 * c_bytes(plan), true}, work_buf(plan, work),
+                       {cwork, core_layout(plan).bytes, true}}))
+            return MPI_ERR_ARG;
         if (core_scatter_smem(plan) > kSmemLimit || core_dir_smem(plan) > kSmemLimit) return MPI_ERR_UNSUPPORTED;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         mpi_plan* pl = const_cast<mpi_plan*>(plan);
@@ -2404,8 +2429,10 @@ int mpi_batch_core_stage(const mpi_plan* plan, const void* s, void* field, doubl
 int mpi_velocity_forward_difference(const void* r, void* v, int64_t n_samples, double dt, int32_t dtype,
                                     hipStream_t stream) {
     return guarded([&]() -> int {
-        if (!r || !v || r == v || n_samples < 2 || !(dt > 0.0) || !std::isfinite(dt)) return MPI_ERR_ARG;
+        if (!r || !v || n_samples < 2 || !(dt > 0.0) || !std::isfinite(dt)) return MPI_ERR_ARG;
         if (dtype != MPI_F32 && dtype != MPI_F64) return MPI_ERR_DTYPE;
+        const size_t el = dtype == MPI_F64 ? 8 : 4, n = size_t(2) * size_t(n_samples) * el;
+        if (misaligned(r, el) || misaligned(v, el) || !disjoint({{r, n, false}, {v, n, true}})) return MPI_ERR_ARG;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         if (dtype == MPI_F64)
             k_forward_difference<double><<<blocks(n_samples, 256), 256, 0, stream>>>(
@@ -2419,9 +2446,10 @@ int mpi_velocity_forward_difference(const void* r, void* v, int64_t n_samples, d
 
 int mpi_batch_field_trace(const mpi_plan* plan, const void* field, void* u, hipStream_t stream) {
     return guarded([&]() -> int {
-        if (!plan || !field || !u || field == u) return MPI_ERR_ARG;
+        if (!plan || !field || !u) return MPI_ERR_ARG;
         const size_t el = plan->L.elem;
         if (misaligned(field, el) || misaligned(u, el)) return MPI_ERR_ARG;
+        if (!disjoint({{field, 3 * c_bytes(plan), false}, {u, c_bytes(plan), true}})) return MPI_ERR_ARG;
         if (hipPeekAtLastError() != hipSuccess) return MPI_ERR_HIP;
         const dim3 grid(blocks(int64_t(plan->max_n) * plan->max_n, 256), plan->count);
         if (plan->dtype == MPI_F64)

@@ -2,8 +2,9 @@
 
 * Overlapping buffers: an output (or the work memory) that shares bytes with
   another buffer of the call is rejected on the host with MPI_ERR_ARG before
-  anything is enqueued; inputs may share memory; mpi_batch_adjoint_step
-  accepts c_out == c_in (in place) but not a shifted copy.
+  anything is enqueued (apply, derivative, solver and trajectory calls);
+  inputs may share memory; mpi_batch_adjoint_step accepts c_out == c_in (in
+  place) but not a shifted copy.
 * Graph-replayed iterations from two streams, each call replacing the graphs
   the other stream's previous call left (skipped: see its reason).
 """
@@ -78,6 +79,33 @@ def test_overlapping_buffers_are_rejected(gpu):
     torch.cuda.synchronize()
     assert torch.equal(c_in, c_sep)
     _raises_arg(lambda: batch.adjoint_step(s_ref, big[:C], taus, c_out=big[1:1 + C]))
+    batch.close()
+
+
+def test_overlapping_solver_buffers_are_rejected(gpu):
+    """The same rule for the Deconvolution and Core Stage entry points and the
+    trajectory helpers."""
+    batch = _batch()
+    C, S_ = batch.c_offsets[-1], batch.s_offsets[-1]
+    c = _c_all(batch)
+    big = torch.zeros(8 * C + 2 * S_ + 64, dtype=torch.float32, device="cuda")
+    big[:C] = c
+    # trace convolution and CG: the output over the input
+    ok = batch.trace_conv(c)
+    _raises_arg(lambda: batch.trace_conv(big[:C], out=big[C // 3:C // 3 + C]))
+    _raises_arg(lambda: batch.cg(big[:C], [1e-3] * batch.count, max_iter=4, x_out=big[5:5 + C]))
+    # Core Stage: the three-channel field over the signal; field trace: u over the field
+    s = batch.forward(c)
+    big[:S_] = s
+    _raises_arg(lambda: batch.core_stage(big[:S_], max_iter=4, field_out=big[S_ - 4:S_ - 4 + 3 * C]))
+    field = big[S_ + 16:S_ + 16 + 3 * C]
+    _raises_arg(lambda: batch.field_trace(field, u_out=big[S_ + 16 + 2 * C:S_ + 16 + 3 * C]))
+    # forward-difference velocities: v over r
+    T = batch.ts[0]
+    r = big[:2 * T].view(T, 2)
+    _raises_arg(lambda: mpik.velocity_forward_difference(r, 1e-3, out=big[2:2 + 2 * T].view(T, 2)))
+    torch.cuda.synchronize()
+    assert torch.equal(batch.trace_conv(c), ok)          # the rejected calls changed nothing they read
     batch.close()
 
 
