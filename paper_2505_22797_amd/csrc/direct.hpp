@@ -227,41 +227,87 @@ constexpr int kDnTile = 32;
 constexpr int kDnMaxR = 8;
 
 // u is read from the problem's work buffer, or from the caller's buffer u_in
-// (concentration-shaped) when that is given.
-template <typename T>
+// (concentration-shaped) when that is given.  RAD: the half-width r, fixed
+// per instance so that every loop has a fixed trip count.  256 threads as 32
+// columns x 8 rows: every load, pass and store walks whole tile rows, so
+// consecutive threads touch consecutive addresses and no index needs a
+// division; all of a thread's loads are in flight before its first store to
+// LDS; the weights wait in LDS.  Each output sums its taps in the order
+// k = 0..2r in both passes.
+template <typename T, int RAD>
 __global__ void __launch_bounds__(256) k_denoise(const Prob* __restrict__ P, const char* __restrict__ work,
                                                  const T* __restrict__ u_in, T* __restrict__ c,
-                                                 const double* __restrict__ wts, int rad) {
-    __shared__ T a[(kDnTile + 2 * kDnMaxR) * (kDnTile + 2 * kDnMaxR)];
-    __shared__ T b[(kDnTile + 2 * kDnMaxR) * kDnTile];
+                                                 const double* __restrict__ wts) {
+    constexpr int L = kDnTile + 2 * RAD;           // the halo tile's side
+    constexpr int RY = 256 / kDnTile;              // tile rows per pass of the work-group
+    constexpr int RI = (L + RY - 1) / RY, CJ = (L + kDnTile - 1) / kDnTile;
+    static_assert(256 % kDnTile == 0 && RAD >= 0 && RAD <= kDnMaxR, "the launch is 256 threads, r <= 8");
+    __shared__ T a[L * L];
+    __shared__ T b[kDnTile * L];
+    __shared__ T w[2 * RAD + 1];
     const Prob& p = P[blockIdx.z];
     const int N = p.n;
     const int y0 = blockIdx.y * kDnTile, x0 = blockIdx.x * kDnTile;
     if (y0 >= N || x0 >= N) return;
     const T* up = u_in ? u_in + p.o_c : at<T>(work, p.w_u);
     T* cp = c + p.o_c;
-    const int L = kDnTile + 2 * rad;
-    for (int i = threadIdx.x; i < L * L; i += blockDim.x) {
-        const int ly = i / L, lx = i % L;
-        const int gy = y0 - rad + ly, gx = x0 - rad + lx;
-        a[i] = (gy >= 0 && gy < N && gx >= 0 && gx < N) ? up[int64_t(gy) * N + gx] : T(0);
+    const int tx = threadIdx.x % kDnTile, ty = threadIdx.x / kDnTile;
+    if (int(threadIdx.x) <= 2 * RAD) w[threadIdx.x] = T(wts[threadIdx.x]);
+    T v[RI][CJ];
+#pragma unroll
+    for (int i = 0; i < RI; ++i) {
+        const int ly = ty + i * RY, gy = y0 - RAD + ly;
+#pragma unroll
+        for (int j = 0; j < CJ; ++j) {
+            const int lx = tx + j * kDnTile, gx = x0 - RAD + lx;
+            v[i][j] = (ly < L && lx < L && gy >= 0 && gy < N && gx >= 0 && gx < N) ? up[int64_t(gy) * N + gx] : T(0);
+        }
     }
+#pragma unroll
+    for (int i = 0; i < RI; ++i)
+#pragma unroll
+        for (int j = 0; j < CJ; ++j) {
+            const int ly = ty + i * RY, lx = tx + j * kDnTile;
+            if (ly < L && lx < L) a[ly * L + lx] = v[i][j];
+        }
     __syncthreads();
     // vertical pass (over y) first: b[ly][x] for ly in [0, 32), then horizontal
-    for (int i = threadIdx.x; i < kDnTile * L; i += blockDim.x) {
-        const int ly = i / L, lx = i % L;
-        T s = T(0);
-        for (int k = 0; k <= 2 * rad; ++k) s += T(wts[k]) * a[(ly + k) * L + lx];
-        b[ly * L + lx] = s;
-    }
+#pragma unroll
+    for (int i = 0; i < kDnTile / RY; ++i)
+#pragma unroll
+        for (int j = 0; j < CJ; ++j) {
+            const int ly = ty + i * RY, lx = tx + j * kDnTile;
+            if (lx < L) {
+                T s = T(0);
+#pragma unroll
+                for (int k = 0; k <= 2 * RAD; ++k) s += w[k] * a[(ly + k) * L + lx];
+                b[ly * L + lx] = s;
+            }
+        }
     __syncthreads();
-    for (int i = threadIdx.x; i < kDnTile * kDnTile; i += blockDim.x) {
-        const int ly = i / kDnTile, lx = i % kDnTile;
-        const int gy = y0 + ly, gx = x0 + lx;
-        if (gy >= N || gx >= N) continue;
+    const int gx = x0 + tx;
+#pragma unroll
+    for (int i = 0; i < kDnTile / RY; ++i) {
+        const int ly = ty + i * RY, gy = y0 + ly;
         T s = T(0);
-        for (int k = 0; k <= 2 * rad; ++k) s += T(wts[k]) * b[ly * L + lx + k];
-        cp[int64_t(gy) * N + gx] = s;
+#pragma unroll
+        for (int k = 0; k <= 2 * RAD; ++k) s += w[k] * b[ly * L + tx + k];
+        if (gy < N && gx < N) cp[int64_t(gy) * N + gx] = s;
+    }
+}
+
+// Launches k_denoise with the instance of half-width rad (0..kDnMaxR; the
+// callers check the range).
+template <typename T>
+void launch_denoise(dim3 grid, hipStream_t st, const Prob* P, const char* work, const T* u_in, T* c,
+                    const double* wts, int rad) {
+    switch (rad) {
+#define MPIK_DN_CASE(R) \
+    case R: k_denoise<T, R><<<grid, 256, 0, st>>>(P, work, u_in, c, wts); break;
+        MPIK_DN_CASE(0) MPIK_DN_CASE(1) MPIK_DN_CASE(2) MPIK_DN_CASE(3) MPIK_DN_CASE(4)
+        MPIK_DN_CASE(5) MPIK_DN_CASE(6) MPIK_DN_CASE(7) MPIK_DN_CASE(8)
+#undef MPIK_DN_CASE
+        default: break;
     }
 }
 

@@ -868,8 +868,8 @@ int iteration_impl(const mpi_plan* pl, T* c, bool denoise, int rad, char* work, 
     });
     if (rc != MPI_OK) return rc;
     if (denoise)
-        k_denoise<T><<<dim3(pl->max_dntiles, pl->max_dntiles, pl->count), 256, 0, st>>>(
-            pl->dprob, work, nullptr, c, reinterpret_cast<const double*>(work + pl->L.w_wts), rad);
+        launch_denoise<T>(dim3(pl->max_dntiles, pl->max_dntiles, pl->count), st, pl->dprob, work, nullptr, c,
+                          reinterpret_cast<const double*>(work + pl->L.w_wts), rad);
     return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
 }
 
@@ -1289,7 +1289,7 @@ int unrolled_vjp_impl(mpi_plan* pl, const T* s, const T* ckpt, int K, int E, dou
                 rc = adjoint_impl<T, true, 1>(pl, re, next, ce, work, st, zs + e * V.C);
             } else {
                 rc = adjoint_impl<T, true, 2>(pl, re, nullptr, ce, work, st, zs + e * V.C);
-                if (rc == MPI_OK && next) k_denoise<T><<<dn_grid, 256, 0, st>>>(P, work, nullptr, next, wts, rad);
+                if (rc == MPI_OK && next) launch_denoise<T>(dn_grid, st, P, work, nullptr, next, wts, rad);
             }
             if (rc != MPI_OK) return rc;
         }
@@ -1297,7 +1297,7 @@ int unrolled_vjp_impl(mpi_plan* pl, const T* s, const T* ckpt, int K, int E, dou
             const T* ce = cs + e * V.C;
             T* g_u = gbar;
             if (den) {
-                k_denoise<T><<<dn_grid, 256, 0, st>>>(P, work, gbar, gu, wts, rad);
+                launch_denoise<T>(dn_grid, st, P, work, gbar, gu, wts, rad);
                 g_u = gu;
             }
             launch_dot<T>(pl, g_u, zs + e * V.C, 1, 2, acc_h, 1, work, st);
@@ -1648,8 +1648,8 @@ int pnp_impl(mpi_plan* pl, const T* u, T* rho, const mpi_pnp_params* pp, int32_t
         rc = trim_and_variance<T>(pl, rho1, pp->clip_percentile, dw, L, st, var.data(), nullptr);
         if (rc != MPI_OK) return rc;
         if (den)
-            k_denoise<T><<<dim3(pl->max_dntiles, pl->max_dntiles, B), 256, 0, st>>>(P, work, rho1, rho, wts,
-                                                                                  pp->denoise_radius);
+            launch_denoise<T>(dim3(pl->max_dntiles, pl->max_dntiles, B), st, P, work, rho1, rho, wts,
+                              pp->denoise_radius);
         else
             k_copy<T><<<blocks(C, 256), 256, 0, st>>>(rho1, rho, C);
         HIP_TRY(hipGetLastError());
@@ -2173,13 +2173,11 @@ int mpi_batch_denoise(const mpi_plan* plan, const void* u, void* c, double sigma
         HIP_TRY(upload_gauss(pl, sigma_px, radius, w, stream));
         const dim3 grid(pl->max_dntiles, pl->max_dntiles, pl->count);
         if (plan->dtype == MPI_F64)
-            k_denoise<double><<<grid, 256, 0, stream>>>(pl->dprob, w, static_cast<const double*>(u),
-                                                        static_cast<double*>(c),
-                                                        reinterpret_cast<const double*>(w + pl->L.w_wts), radius);
+            launch_denoise<double>(grid, stream, pl->dprob, w, static_cast<const double*>(u), static_cast<double*>(c),
+                                   reinterpret_cast<const double*>(w + pl->L.w_wts), radius);
         else
-            k_denoise<float><<<grid, 256, 0, stream>>>(pl->dprob, w, static_cast<const float*>(u),
-                                                       static_cast<float*>(c),
-                                                       reinterpret_cast<const double*>(w + pl->L.w_wts), radius);
+            launch_denoise<float>(grid, stream, pl->dprob, w, static_cast<const float*>(u), static_cast<float*>(c),
+                                  reinterpret_cast<const double*>(w + pl->L.w_wts), radius);
         return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
     });
 }
