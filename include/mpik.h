@@ -242,9 +242,14 @@ int mpi_batch_pair(const mpi_plan* plan, const void* c_all, void* s_all, void* g
  *               switched off (MPI_ERR_UNSUPPORTED): its graph-captured timing
  *               runs once ended in a host-side fault whose cause is not
  *               established.
- * The count in use is written to *chosen (may be NULL).  Changing it drops the
- * plan's cached iteration graphs (recorded again on their next use) and
- * synchronises `stream`; no other call may use the plan meanwhile. */
+ * The count in use is written to *chosen (may be NULL).  Changing it
+ * re-creates the plan's side streams and synchronises `stream`; no other call
+ * may use the plan meanwhile.  Only a plan that has not yet recorded a graph
+ * (a graph-replayed iteration, CG or Core Stage call) may change it: after
+ * that, a different count returns MPI_ERR_UNSUPPORTED and the plan keeps its
+ * schedule (a capture after the side streams were re-created ended a process
+ * with a host-side fault whose cause is not established).  Set the schedule
+ * right after the build. */
 int mpi_batch_schedule(mpi_plan* plan, int32_t ranges, const void* c_all, void* s_all, void* g_all,
                        void* work, size_t work_bytes, hipStream_t stream, int32_t* chosen);
 

@@ -384,6 +384,9 @@ struct mpi_plan {
         hipGraph_t graph = nullptr;
         std::vector<double> key;
     } one_gc, iter_gc, cg_gc, core_gc;
+    // set by the first graph capture: from then on the side streams stay as
+    // they are (mpi_batch_schedule no longer re-creates them)
+    bool graphs_recorded = false;
 };
 
 namespace {
@@ -1382,6 +1385,7 @@ int iterate_impl(mpi_plan* pl, const T* s, T* c, const mpi_iter_params* ip, cons
     const double sigma = denoise ? ip->denoise_sigma_px : 0.0;
     alloc_point();
     const std::vector<double> key{key_of(s), key_of(c), key_of(work), sigma, double(rad)};
+    pl->graphs_recorded = true;
     const int rc = cached_graph(pl->one_gc, key, st, [&](hipStream_t cap) -> int {
         return iteration_impl<T>(pl, c, denoise, rad, work, cap);
     });
@@ -1581,6 +1585,7 @@ int cg_impl(mpi_plan* pl, const T* cu, const T* rho2, T* x, double tol, int max_
     if (max_iter > 0) {
         alloc_point();
         const std::vector<double> key{key_of(work), key_of(dw), tol, double(max_iter)};
+        pl->graphs_recorded = true;
         int rc = cached_graph(pl->cg_gc, key, st, [&](hipStream_t cap) -> int {
             for (int i = 0; i < kCgBlock; ++i) cg_step<T>(pl, i & 1, tol, max_iter, work, dw, L, cap);
             return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
@@ -1763,6 +1768,7 @@ int core_impl(mpi_plan* pl, const T* sig, T* field, double gamma, double tol, in
     if (max_iter > 0) {
         alloc_point();
         const std::vector<double> key{key_of(cw), gamma, tol, double(max_iter)};
+        pl->graphs_recorded = true;
         int rc = cached_graph(pl->core_gc, key, st, [&](hipStream_t cap) -> int {
             for (int i = 0; i < kCgBlock; ++i) core_step<T>(pl, i & 1, gamma, tol, max_iter, cw, L, cap);
             return hipGetLastError() == hipSuccess ? MPI_OK : MPI_ERR_HIP;
@@ -1946,6 +1952,11 @@ int mpi_batch_schedule(mpi_plan* plan, int32_t ranges, const void* c, void* s, v
             // report only
         } else if (ranges > 0) {
             if (ranges > max_ranges(plan)) return MPI_ERR_ARG;
+            // Once the plan has recorded graphs its side streams stay: a change
+            // of the range count re-creates them, and a capture after such a
+            // re-creation has ended the process with a host-side fault whose
+            // cause is not established.
+            if (ranges != plan->chunks && plan->graphs_recorded) return MPI_ERR_UNSUPPORTED;
             const int rc = set_ranges(plan, ranges, stream);
             if (rc != MPI_OK) return rc;
         } else {

@@ -1,7 +1,8 @@
 """The launch schedule of a batch (mpi_batch_schedule): problem ranges per
 FFT-size group on their own side streams.  Every range count gives the pair
-bit for bit, and the cached iteration graphs follow a change of schedule.
-The timed choice of the count is switched off (its test is skipped)."""
+bit for bit, and a plan that has recorded graphs keeps its schedule.  The
+timed choice of the count is switched off, and so is a change of count after
+a graph capture (their tests are skipped, with the reasons)."""
 import pytest
 import torch
 
@@ -57,6 +58,10 @@ def test_timed_range_choice_keeps_the_results(gpu):
     batch.close()
 
 
+@pytest.mark.skip(reason="a graph-replayed iteration recorded after a change of schedule (side streams destroyed "
+                         "and re-created after an earlier capture) ended the process with a host segmentation "
+                         "fault; no cause is established, so the library refuses such a change once a plan has "
+                         "recorded graphs (test_schedule_is_kept_once_graphs_are_recorded)")
 def test_iteration_graphs_follow_the_schedule(gpu):
     batch, c_all = _batch([64] * 16)
     s = batch.forward(c_all)
@@ -71,4 +76,29 @@ def test_iteration_graphs_follow_the_schedule(gpu):
         batch.iterate(s, x2, 9, taus, 0.5, 2)         # replays the graphs recorded for r
         torch.cuda.synchronize()
         assert torch.equal(x, x_ref) and torch.equal(x2, x_ref), r
+    batch.close()
+
+
+def test_schedule_is_kept_once_graphs_are_recorded(gpu):
+    """A plan that has recorded graphs keeps its range count: a different
+    count is refused with MPI_ERR_UNSUPPORTED (nothing is re-created), the
+    same count is accepted, and the cached graphs keep replaying the same
+    results."""
+    batch, c_all = _batch([64] * 16)
+    assert batch.schedule() == 4                      # the build's count for 16 problems of one size
+    s = batch.forward(c_all)
+    taus = [1e-4] * 16
+    x_ref = torch.zeros_like(c_all)
+    batch.iterate(s, x_ref, 9, taus, 0.5, 2, use_graph=False)
+    x = torch.zeros_like(c_all)
+    batch.iterate(s, x, 9, taus, 0.5, 2)             # records the graphs
+    for r in (1, 2, 8):
+        with pytest.raises(mpik.MpiError) as ei:
+            batch.schedule(r)
+        assert ei.value.status == mpik.MPI_ERR_UNSUPPORTED
+    assert batch.schedule(4) == 4 and batch.schedule() == 4
+    x2 = torch.zeros_like(c_all)
+    batch.iterate(s, x2, 9, taus, 0.5, 2)            # new buffer: recorded again, same streams
+    torch.cuda.synchronize()
+    assert torch.equal(x, x_ref) and torch.equal(x2, x_ref)
     batch.close()
