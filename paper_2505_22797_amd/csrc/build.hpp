@@ -217,51 +217,55 @@ __global__ void k_bin_prep(const Prob* __restrict__ P, const T* __restrict__ r, 
     atomicAdd(&bincount[j0 * (n - 1) + i0], 1);
 }
 
-// Exclusive scan of `count` ints by one work-group of 1024 threads.  Thread t
-// owns the contiguous range [t c, (t + 1) c), c = ceil(count / 1024): it sums
-// its range (independent loads, many in flight), the work-group scans the
-// per-thread sums (lane shuffles within each wave, then the wave totals), and
-// every thread rewrites its range as the running prefix.  out has count + 1
-// entries, out[count] being the total.  Integer sums: the result does not
-// depend on the grouping.
+// Exclusive scan of `count` ints by one work-group of 1024 threads, in tiles
+// of 4096 entries (four consecutive entries per thread, wave scans through
+// lane shuffles, a running carry between tiles); out has count + 1 entries,
+// out[count] being the total.
 constexpr int kScanThreads = 1024;
-// In place (in == out) is allowed: a thread reads each entry of its range
-// before it writes it, and no thread touches another thread's range.
+// In place (in == out) is allowed: a tile is read completely before it is written.
 __global__ void __launch_bounds__(kScanThreads) k_scan(const int* in, int* out, int64_t count) {
     __shared__ int wsum[kScanThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     constexpr int kWaves = kScanThreads / 64;
-    const int64_t chunk = (count + kScanThreads - 1) / kScanThreads;
-    const int64_t lo = min(int64_t(tid) * chunk, count), hi = min(lo + chunk, count);
-    int sum = 0;
-#pragma unroll 16
-    for (int64_t i = lo; i < hi; ++i) sum += in[i];
-    int x = sum;                                   // inclusive scan of the sums within the wave
+    int carry = 0;
+    for (int64_t base = 0; base < count; base += 4 * kScanThreads) {
+        int v[4];
+        int sum = 0;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) wsum[w] = x;
-    __syncthreads();
-    if (w == 0) {
-        int t = lane < kWaves ? wsum[lane] : 0;
-#pragma unroll
-        for (int off = 1; off < kWaves; off <<= 1) {
-            const int y = __shfl_up(t, off, 64);
-            if (lane >= off) t += y;
+        for (int j = 0; j < 4; ++j) {
+            const int64_t idx = base + 4 * tid + j;
+            v[j] = idx < count ? in[idx] : 0;
+            sum += v[j];
         }
-        if (lane < kWaves) wsum[lane] = t;
+        int x = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        if (w == 0) {
+            int t = lane < kWaves ? wsum[lane] : 0;
+#pragma unroll
+            for (int off = 1; off < kWaves; off <<= 1) {
+                const int y = __shfl_up(t, off, 64);
+                if (lane >= off) t += y;
+            }
+            if (lane < kWaves) wsum[lane] = t;
+        }
+        __syncthreads();
+        int run = carry + (w > 0 ? wsum[w - 1] : 0) + x - sum;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t idx = base + 4 * tid + j;
+            if (idx < count) out[idx] = run;
+            run += v[j];
+        }
+        carry += wsum[kWaves - 1];
+        __syncthreads();    // wsum is rewritten by the next tile
     }
-    __syncthreads();
-    int run = (w > 0 ? wsum[w - 1] : 0) + x - sum;  // exclusive prefix of the thread's range
-#pragma unroll 16
-    for (int64_t i = lo; i < hi; ++i) {
-        const int v = in[i];
-        out[i] = run;
-        run += v;
-    }
-    if (tid == 0) out[count] = wsum[kWaves - 1];
+    if (tid == 0) out[count] = carry;
 }
 
 // Stable sort of the samples by base cell: a least-significant-digit radix
