@@ -253,7 +253,9 @@ __global__ void __launch_bounds__(1024) k_percentile(const Prob* __restrict__ P,
     constexpr int kBits = 8 * int(sizeof(T));
     __shared__ int hist[2][256];
     __shared__ K prefix[2];
-    __shared__ int64_t rank[2];
+    __shared__ int64_t rank[2], rank_next[2];
+    __shared__ int digit[2];
+    __shared__ int wtot[8];
     const Prob& p = P[blockIdx.x];
     const int64_t m = int64_t(p.n) * p.n;
     const T* xp = x + p.o_c;
@@ -271,19 +273,55 @@ __global__ void __launch_bounds__(1024) k_percentile(const Prob* __restrict__ P,
         __syncthreads();
         const K hi_mask = shift + 8 >= kBits ? K(0) : ~K(0) << (shift + 8);
         const K pa = prefix[0] & hi_mask, pb = prefix[1] & hi_mask;
-        for (int64_t e = tid; e < m; e += 1024) {
-            const K k = order_key(xp[e]);
-            const int d = int((k >> shift) & K(255));
-            if ((k & hi_mask) == pa) atomicAdd(&hist[0][d], 1);
-            if ((k & hi_mask) == pb) atomicAdd(&hist[1][d], 1);
+        const bool shared_prefix = pa == pb;     // then one histogram serves both ranks
+        // kLoads values per thread in flight before their histogram updates
+        constexpr int kLoads = 16;
+        for (int64_t e0 = tid; e0 < m; e0 += int64_t(1024) * kLoads) {
+            K kk[kLoads];
+#pragma unroll
+            for (int u = 0; u < kLoads; ++u) {
+                const int64_t e = e0 + int64_t(u) * 1024;
+                kk[u] = e < m ? order_key(xp[e]) : K(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kLoads; ++u) {
+                if (e0 + int64_t(u) * 1024 >= m) break;
+                const K k = kk[u];
+                const int d = int((k >> shift) & K(255));
+                if ((k & hi_mask) == pa) atomicAdd(&hist[0][d], 1);
+                if (!shared_prefix && (k & hi_mask) == pb) atomicAdd(&hist[1][d], 1);
+            }
+        }
+        __syncthreads();
+        // the digit of each rank: threads s 256 + d scan histogram s; the bin
+        // whose range [cum, cum + hist) holds the rank takes it (the last bin
+        // also takes a rank past the total), as a walk from digit 0 would
+        int sc = 0, h = 0;
+        if (tid < 512) {
+            h = hist[shared_prefix ? 0 : tid >> 8][tid & 255];
+            sc = h;                                 // inclusive scan within the wave
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int y = __shfl_up(sc, off, 64);
+                if ((tid & 63) >= off) sc += y;
+            }
+            if ((tid & 63) == 63) wtot[tid >> 6] = sc;
+        }
+        __syncthreads();
+        if (tid < 512) {
+            const int s = tid >> 8, d = tid & 255, wv = tid >> 6;
+            int64_t cum = sc - h;
+            for (int q = s * 4; q < wv; ++q) cum += wtot[q];
+            const int64_t r = rank[s];
+            if (cum <= r && (r < cum + h || d == 255)) {
+                rank_next[s] = r - cum;
+                digit[s] = d;
+            }
         }
         __syncthreads();
         if (tid < 2) {
-            int64_t r = rank[tid], cum = 0;
-            int d = 0;
-            while (d < 255 && cum + hist[tid][d] <= r) cum += hist[tid][d++];
-            rank[tid] = r - cum;
-            prefix[tid] |= K(d) << shift;
+            rank[tid] = rank_next[tid];
+            prefix[tid] |= K(digit[tid]) << shift;
         }
         __syncthreads();
     }
