@@ -202,7 +202,13 @@ enum { MPI_BUILD_DERIV = 8 };
  * For tests and tuning studies. */
 enum { MPI_BUILD_SLICES_4 = 16, MPI_BUILD_SLICES_8 = 32, MPI_BUILD_SLICES_16 = 64 };
 
-/* Plan and work bytes of a batch built with `flags` (MPI_BUILD_*). */
+/* Plan and work bytes of a batch built with `flags` (MPI_BUILD_*).  Problems
+ * that have the same kernel -- equal n, effective radius, h, grad_x, grad_y
+ * and requested conv_mode -- share one copy of the kernel tables (spectra,
+ * twiddles, direct-path taps and their dK_h/dh versions), built once for the
+ * first of them; the plan holds that copy only, and the apply stages of a
+ * batch of such problems read it from cache.  Results are those of separate
+ * copies, bitwise. */
 int mpi_batch_bytes(const mpi_problem* probs, int count, int flags, size_t* plan_bytes, size_t* work_bytes);
 int mpi_batch_build(const mpi_problem* probs, int count, void* plan_mem, size_t plan_bytes,
                     void* work, size_t work_bytes, int flags, hipStream_t stream, mpi_plan** out);

@@ -189,7 +189,11 @@ size_t take(size_t& off, size_t bytes) {
 
 // Lays out one problem's plan buffers from `poff` and its work buffers from
 // `woff` (both advanced).  `both`: room for either convolution path (tuning).
-void layout_problem(const Shape& sh, int mode, bool both, bool deriv, size_t& poff, size_t& woff, Prob& p) {
+// `share`: a problem laid out before with the same kernel (the same tables
+// would be built), whose kernel tables, spectra and twiddles this problem
+// reads instead of its own.
+void layout_problem(const Shape& sh, int mode, bool both, bool deriv, size_t& poff, size_t& woff, Prob& p,
+                    const Prob* share) {
     const int N = sh.n, R = sh.R, nb = N - 1, M = sh.M, H = M / 2 + 1, W = 2 * R + 1, e = sh.elem;
     const int64_t T = sh.T;
     std::memset(&p, 0, sizeof(p));
@@ -208,13 +212,21 @@ void layout_problem(const Shape& sh, int mode, bool both, bool deriv, size_t& po
     p.t = T;
     const bool dir = both ? sh.direct_ok : mode == 0;
     const bool fft = both ? sh.fft_ok : mode == 1;
-    if (dir) p.o_taps = take(poff, size_t(3) * W * p.taps_w * e);
-    if (fft) {
-        p.o_spec = take(poff, size_t(3) * H * H * e);
-        p.o_tw = take(poff, size_t(M) * 2 * e);
+    if (share) {
+        p.o_taps = share->o_taps;
+        p.o_spec = share->o_spec;
+        p.o_tw = share->o_tw;
+        p.o_taps_dh = share->o_taps_dh;
+        p.o_spec_dh = share->o_spec_dh;
+    } else {
+        if (dir) p.o_taps = take(poff, size_t(3) * W * p.taps_w * e);
+        if (fft) {
+            p.o_spec = take(poff, size_t(3) * H * H * e);
+            p.o_tw = take(poff, size_t(M) * 2 * e);
+        }
+        if (deriv && dir) p.o_taps_dh = take(poff, size_t(3) * W * p.taps_w * e);
+        if (deriv && fft) p.o_spec_dh = take(poff, size_t(3) * H * H * e);
     }
-    if (deriv && dir) p.o_taps_dh = take(poff, size_t(3) * W * p.taps_w * e);
-    if (deriv && fft) p.o_spec_dh = take(poff, size_t(3) * H * H * e);
     p.o_samp = take(poff, size_t(T) * 4 * e);
     if (deriv) p.o_dw = take(poff, size_t(T) * 2 * e);
     p.o_sidx = take(poff, size_t(T) * 8);
@@ -257,6 +269,7 @@ struct BatchLayout {
     std::vector<Shape> shapes;
     std::vector<Prob> probs;
     std::vector<int> requested;   // MPI_CONV_* per problem
+    std::vector<int> owner;       // per problem: the problem whose kernel tables it reads (itself, or an earlier one)
     size_t desc_bytes = 0, plan_bytes = 0, work_bytes = 0, scratch_base = 0;
     size_t w_taus = 0, w_wts = 0, w_dot = 0;
     int64_t c_elems = 0, s_elems = 0;
@@ -291,6 +304,8 @@ int make_batch_layout(const mpi_problem* probs, int count, int flags, BatchLayou
     B.probs.resize(count);
     alloc_point();
     B.requested.resize(count);
+    alloc_point();
+    B.owner.resize(count);
     for (int b = 0; b < count; ++b) {
         const int rc = validate(&probs[b], B.shapes[b]);
         if (rc != MPI_OK) return rc;
@@ -304,7 +319,20 @@ int make_batch_layout(const mpi_problem* probs, int count, int flags, BatchLayou
     for (int b = 0; b < count; ++b) {
         const Shape& sh = B.shapes[b];
         const bool both = B.requested[b] == MPI_CONV_AUTO && sh.fft_ok && sh.direct_ok;
-        layout_problem(sh, default_mode(sh, B.requested[b]), both, B.deriv, poff, woff, B.probs[b]);
+        // the tables depend on N, R, h, G and the requested path (which sets
+        // the tables laid out): a batch of problems with one kernel keeps one
+        // copy, which the stages then read from L2 instead of from memory
+        B.owner[b] = b;
+        for (int a = 0; a < b; ++a) {
+            const Shape& sa = B.shapes[a];
+            if (B.owner[a] == a && sa.n == sh.n && sa.R == sh.R && sa.gx == sh.gx && sa.gy == sh.gy &&
+                probs[a].h == probs[b].h && B.requested[a] == B.requested[b]) {
+                B.owner[b] = a;
+                break;
+            }
+        }
+        layout_problem(sh, default_mode(sh, B.requested[b]), both, B.deriv, poff, woff, B.probs[b],
+                       B.owner[b] == b ? nullptr : &B.probs[B.owner[b]]);
         if (slices) B.probs[b].slices = slices;
         B.probs[b].h = probs[b].h;
         B.probs[b].o_c = co;
@@ -537,16 +565,12 @@ hipError_t set_smem_limits(const mpi_plan* pl) {
 }
 
 // ---------------------------------------------------------------- build ---
-// Builds problem b (its descriptor already in device memory): kernel table,
-// spectra and/or direct taps, binning.  Enqueued on st; no synchronisation.
+// The kernel tables of a problem: the float64 table, the direct path's taps,
+// the twiddles and the spectra, and with the derivative flag the same for
+// dK_h/dh.
 template <typename T>
-int build_problem(const mpi_problem* d, const BatchLayout& B, int b, char* plan, hipStream_t st) {
-    const Prob& p = B.probs[b];
-    const Prob* P = reinterpret_cast<const Prob*>(plan) + b;
-    const Scratch sc = scratch_layout(B.shapes[b], B.scratch_base);
-    const int N = p.n, R = p.radius, W = 2 * R + 1, nb = p.nb, M = p.m, H = M / 2 + 1;
-    HIP_TRY(hipMemsetAsync(plan + p.o_err, 0, 16, st));
-    HIP_TRY(hipMemsetAsync(plan + sc.bincount, 0, size_t(nb) * nb * 4, st));
+hipError_t build_tables(const Prob& p, const Prob* P, const Scratch& sc, char* plan, hipStream_t st) {
+    const int R = p.radius, W = 2 * R + 1, M = p.m, H = M / 2 + 1;
     double* series = reinterpret_cast<double*>(plan + sc.series);
     double* tab64 = reinterpret_cast<double*>(plan + sc.tab64);
     k_series<<<1, 1, 0, st>>>(series);
@@ -574,6 +598,15 @@ int build_problem(const mpi_problem* d, const BatchLayout& B, int b, char* plan,
                                                                              reinterpret_cast<T*>(plan + p.o_spec_dh));
         }
     }
+    return hipGetLastError();
+}
+
+// Binning of a problem's samples: base cells, the stable sort by cell and the
+// placed sample records.
+template <typename T>
+int build_binning(const mpi_problem* d, const Prob& p, const Prob* P, const Scratch& sc, char* plan,
+                  hipStream_t st) {
+    const int nb = p.nb;
     int* cell = reinterpret_cast<int*>(plan + sc.cell);
     double* frac = reinterpret_cast<double*>(plan + sc.frac);
     int* bincount = reinterpret_cast<int*>(plan + sc.bincount);
@@ -602,6 +635,21 @@ int build_problem(const mpi_problem* d, const BatchLayout& B, int b, char* plan,
     k_place<T><<<blocks(p.t, 256), 256, 0, st>>>(P, order, cell, frac, static_cast<const T*>(d->v), plan);
     HIP_TRY(hipGetLastError());
     return MPI_OK;
+}
+
+// Builds problem b (its descriptor already in device memory): kernel table,
+// spectra and/or direct taps unless it reads an earlier problem's, binning.
+// Enqueued on st; no synchronisation.
+template <typename T>
+int build_problem(const mpi_problem* d, const BatchLayout& B, int b, char* plan, hipStream_t st) {
+    const Prob& p = B.probs[b];
+    const Prob* P = reinterpret_cast<const Prob*>(plan) + b;
+    const Scratch sc = scratch_layout(B.shapes[b], B.scratch_base);
+    const int nb = p.nb;
+    HIP_TRY(hipMemsetAsync(plan + p.o_err, 0, 16, st));
+    HIP_TRY(hipMemsetAsync(plan + sc.bincount, 0, size_t(nb) * nb * 4, st));
+    if (B.owner[b] == b) HIP_TRY(build_tables<T>(p, P, sc, plan, st));
+    return build_binning<T>(d, p, P, sc, plan, st);
 }
 
 // ---------------------------------------------------------------- apply ---

@@ -3,7 +3,7 @@
 A batch runs the same kernels as single-problem plans, so with the same
 convolution path per problem the results are bitwise identical to the single
 plans; every problem also matches the float64 oracle (1e-5 per apply, 1e-4
-after iterations).
+after iterations).  Problems with one kernel share its tables.
 """
 import numpy as np
 import pytest
@@ -63,6 +63,50 @@ def test_batch_equals_single_plans():
         torch.cuda.synchronize()
         assert torch.equal(batch.s_views(s_all)[b], s1), b
         assert torch.equal(batch.c_views(g_all)[b], g1), b
+
+
+def test_problems_with_one_kernel_share_its_tables():
+    """Problems of a batch with the same N, R, h (and gradient and requested
+    path) read one copy of the kernel tables: the plan is smaller than with
+    distinct kernels by the duplicated spectra, twiddles and taps, and every
+    problem -- those reading an earlier problem's tables included -- is
+    bitwise its single-plan result and matches the oracle."""
+    n, R, h = 64, 63, S.h_fwhm2(64)
+    kinds = [dict(ax=0.85, ay=0.85), dict(ax=0.8, ay=0.85, exc_amp=0.04, exc_cycles=17 * 30),
+             dict(ax=0.85, ay=0.85, t0=0.2, t1=0.75)]
+    specs = []
+    for i, (nn, RR, hh, t, mode, kind) in enumerate([(n, R, h, 5000, "fft", 0), (n, R, h, 7000, "fft", 1),
+                                                      (n, R, 1.2 * h, 6000, "fft", 2), (n, R, h, 3000, "fft", 2),
+                                                      (40, 9, S.h_fwhm2(40), 4000, "direct", 0),
+                                                      (40, 9, S.h_fwhm2(40), 3500, "direct", 1)]):
+        tr = S.lissajous(t, **kinds[kind])
+        specs.append(dict(n=nn, h=hh, R=RR, r=rounded(tr.r, torch.float32), v=rounded(tr.v, torch.float32),
+                          c=rounded(S.ellipses_and_line(nn, 2000 + i), torch.float32), mode=mode))
+    batch = _build(specs, columns="split")
+    distinct = [dict(sp, h=sp["h"] * (1.0 + 1e-3 * b)) for b, sp in enumerate(specs)]
+    batch_d = _build(distinct, columns="split")
+    H, W = 65, 19                       # M = 128 for N = 64, R = 63; direct window 2R + 1
+    saved = batch_d.plan_mem.numel() - batch.plan_mem.numel()
+    assert saved >= 2 * (3 * H * H * 4 + 128 * 8) + 3 * W * 20 * 4, saved
+    c_all = _c_all(batch, specs)
+    s_all = batch.forward(c_all)
+    rng = np.random.default_rng(1)
+    y_all = dev(rounded(rng.standard_normal(batch.s_offsets[-1]), torch.float32), torch.float32)
+    g_all = batch.adjoint(y_all)
+    torch.cuda.synchronize()
+    for b, sp in enumerate(specs):
+        plan = mpik.Plan(sp["n"], sp["h"], sp["R"], dev(sp["r"], torch.float32), dev(sp["v"], torch.float32),
+                         conv_mode=sp["mode"])
+        s1 = plan.forward(dev(sp["c"], torch.float32))
+        g1 = plan.adjoint(batch.s_views(y_all)[b].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(batch.s_views(s_all)[b], s1), b
+        assert torch.equal(batch.c_views(g_all)[b], g1), b
+        M = O.Model(sp["n"], sp["h"], sp["R"], sp["r"], sp["v"])
+        assert rel_l2(batch.s_views(s_all)[b].double().cpu().numpy(), M.forward(sp["c"])) <= 1e-5, b
+    print(f"one kernel per group: plan {saved} bytes smaller than with distinct kernels", flush=True)
+    batch.close()
+    batch_d.close()
 
 
 @pytest.mark.parametrize("columns", ["split", "wave"])
