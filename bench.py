@@ -191,6 +191,8 @@ def main() -> int:
     ap.add_argument("--no-cosine", action="store_true")
     ap.add_argument("--no-deconv", action="store_true")
     ap.add_argument("--no-two-stage", action="store_true")
+    ap.add_argument("--no-kernel-per-problem", action="store_true",
+                    help="skip the headline batch with a distinct kernel per problem")
     ap.add_argument("--two-stage-only", action="store_true",
                     help="only the two-stage reconstruction (for a kernel trace of its kernels)")
     ap.add_argument("--deconv-only", action="store_true",
@@ -272,13 +274,15 @@ def main() -> int:
     # the same batch with a kernel of its own per problem (h differing in the
     # sixth digit), so that no two problems share kernel tables: B copies of
     # the spectra read per stage instead of one
-    batch_d = mpik.Batch([(n, P.h * (1.0 + 1e-6 * b), P.radius, r, v, "fft") for b in range(B)], tune=False)
-    batch_d.schedule(ranges)
-    msB_d, _, runs_d = graph_time(lambda: batch_d.pair(c_all, s_all, g_all), steps, group_for(steps), args.warmup)
-    batch_d.close()
-    del batch_d
-    print(f"bench: batch {B}, a kernel per problem: {msB_d * 1e3:.1f} us/step, {B * 1e3 / msB_d:.0f} pairs/s",
-          file=sys.stderr, flush=True)
+    msB_d = None
+    if not args.no_kernel_per_problem:
+        batch_d = mpik.Batch([(n, P.h * (1.0 + 1e-6 * b), P.radius, r, v, "fft") for b in range(B)], tune=False)
+        batch_d.schedule(ranges)
+        msB_d, _, _ = graph_time(lambda: batch_d.pair(c_all, s_all, g_all), steps, group_for(steps), args.warmup)
+        batch_d.close()
+        del batch_d
+        print(f"bench: batch {B}, a kernel per problem: {msB_d * 1e3:.1f} us/step, {B * 1e3 / msB_d:.0f} pairs/s",
+              file=sys.stderr, flush=True)
     print(f"bench: batch {B} ({ranges} ranges): {msB * 1e3:.1f} us/step, {pairs_per_s:.0f} pairs/s", file=sys.stderr,
           flush=True)
 
@@ -328,11 +332,11 @@ def main() -> int:
                      "compulsory_bytes_per_launch": B * stage_bytes(dom, n, batch_fft, t)},
         "counter_bytes_per_pair": round(counter_pair) if counter_pair else None,
         "counter_over_alg": round(counter_pair / b_alg, 3) if counter_pair else None,
-        "kernel_per_problem": {"value": round(B * 1e3 / msB_d, 1), "unit": "pairs/s", "ms_per_step": round(msB_d, 5),
-                               "hbm_fraction": round(b_alg * B * 1e3 / msB_d / (HBM_PEAK_GBS * 1e9), 5),
-                               "note": "the same pairs with a distinct kernel per problem (h varied in the sixth "
-                                       "digit): one copy of the kernel spectra per problem instead of one shared "
-                                       "copy"},
+        "kernel_per_problem": None if msB_d is None else {
+            "value": round(B * 1e3 / msB_d, 1), "unit": "pairs/s", "ms_per_step": round(msB_d, 5),
+            "hbm_fraction": round(b_alg * B * 1e3 / msB_d / (HBM_PEAK_GBS * 1e9), 5),
+            "note": "the same pairs with a distinct kernel per problem (h varied in the sixth digit): one copy of "
+                    "the kernel spectra per problem instead of one shared copy"},
         "separate_calls": {"value": round(B * 1e3 / msB_sep, 1), "unit": "pairs/s", "ms_per_step": round(msB_sep, 5),
                            "ms_per_step_runs": [round(x, 5) for x in runs_sep],
                            "note": "the same pairs as a forward call then a transpose call (a join of the "
