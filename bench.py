@@ -54,18 +54,21 @@ def src_digest() -> str:
 STAGE_NAMES = ("fwd_rows", "fwd_cols", "fwd_rows_gather", "adj_scatter_row", "adj_cols", "adj_rows")
 
 
-def stage_bytes(name: str, n: int, m: int, t: int, elem: int = 4) -> float:
+def stage_bytes(name: str, n: int, m: int, t: int, elem: int = 4, spectra: float = 1.0) -> float:
     """Compulsory bytes of one launch of a stage for one problem: every input
-    and output of the stage moved once (plan constants included)."""
+    and output of the stage moved once (plan constants included).  spectra:
+    copies of the kernel spectra per problem (1/B for a batch of B problems
+    sharing one kernel, whose plan holds one copy)."""
     hh = m // 2 + 1
     cplx = 2 * elem
     samp = t * (4 * elem + 8)          # (fx, fy, vx, vy) and (base cell, time index)
+    spec = spectra * elem * 3 * hh * hh
     return {
         "fwd_rows": elem * n * n + cplx * hh * n,
-        "fwd_cols": cplx * hh * n + elem * 3 * hh * hh + 3 * cplx * n * hh,
+        "fwd_cols": cplx * hh * n + spec + 3 * cplx * n * hh,
         "fwd_rows_gather": 3 * cplx * n * hh + samp + 2 * elem * t,
         "adj_scatter_row": samp + 2 * elem * t + 3 * cplx * hh * n,
-        "adj_cols": 3 * cplx * hh * n + elem * 3 * hh * hh + cplx * n * hh,
+        "adj_cols": 3 * cplx * hh * n + spec + cplx * n * hh,
         "adj_rows": cplx * n * hh + elem * n * n,
     }[name]
 
@@ -323,13 +326,15 @@ def main() -> int:
         # every FFT-path stage: its share of the pair's algorithmic bytes over its HIP-event duration
         "stage_alg_frac": {k: round(B * alg_stage_bytes(k, n, t) / (stB[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                            for k in fft_stages},
-        # every input and output of the stage moved once (spectra, intermediates, sample records)
-        "stage_compulsory_frac": {k: round(B * stage_bytes(k, n, batch_fft, t) / (stB[k] * 1e-3) / 1e9
+        # every input and output of the stage moved once (intermediates, sample records, and the
+        # batch's one copy of the kernel spectra)
+        "stage_compulsory_frac": {k: round(B * stage_bytes(k, n, batch_fft, t, spectra=1.0 / B)
+                                           / (stB[k] * 1e-3) / 1e9
                                            / HBM_PEAK_GBS, 4) for k in fft_stages},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic[dom],
                      "algorithmic_bytes_per_launch": dom_alg, "launch_ms": round(stB[dom], 5),
-                     "compulsory_bytes_per_launch": B * stage_bytes(dom, n, batch_fft, t)},
+                     "compulsory_bytes_per_launch": B * stage_bytes(dom, n, batch_fft, t, spectra=1.0 / B)},
         "counter_bytes_per_pair": round(counter_pair) if counter_pair else None,
         "counter_over_alg": round(counter_pair / b_alg, 3) if counter_pair else None,
         "kernel_per_problem": None if msB_d is None else {
