@@ -199,10 +199,22 @@ __device__ void fwd_rows_body(const Prob& p, const T* __restrict__ c, const char
     __syncthreads();
     cx<T>* line = sm.line[wave];
     if (active) {
+        if constexpr (M == 512 && sizeof(T) == 4) {
+            // register-resident transform with the twiddles read from the LDS
+            // table (registers for them would cost occupancy); the wave's
+            // line holds the exchange, then the spectrum in natural order
+            static_assert(XbLayout<T>::kSlots <= M, "exchange exceeds the line");
+            Fft512TwLds<T> tl;
+            tl.init(sm.tw, lane);
+            fft512_regs<T, false>(x, line, tl, lane);
 #pragma unroll
-        for (int m = 0; m < PL; ++m) line[lane + m * kWave] = x[m];
-        wave_sync();
-        fft_wave<T, false, M>(line, sm.tw, lane);
+            for (int m = 0; m < PL; ++m) line[lane + m * kWave] = x[m];
+        } else {
+#pragma unroll
+            for (int m = 0; m < PL; ++m) line[lane + m * kWave] = x[m];
+            wave_sync();
+            fft_wave<T, false, M>(line, sm.tw, lane);
+        }
     }
     __syncthreads();
     // the work-group's eight rows go out together: T1[k][row0 .. row0+7], so
