@@ -316,21 +316,16 @@ int make_batch_layout(const mpi_problem* probs, int count, int flags, BatchLayou
     B.desc_bytes = align_up(sizeof(Prob) * count);
     size_t poff = B.desc_bytes, woff = 0;
     int64_t co = 0, so = 0;
+    // the tables depend on N, R, h, G and the requested path (which sets the
+    // tables laid out): a batch of problems with one kernel keeps one copy,
+    // which the stages then read from L2 instead of from memory
+    using KernelKey = std::tuple<int, int, double, double, double, int>;
+    std::map<KernelKey, int> first_of;
+    alloc_point();
     for (int b = 0; b < count; ++b) {
         const Shape& sh = B.shapes[b];
         const bool both = B.requested[b] == MPI_CONV_AUTO && sh.fft_ok && sh.direct_ok;
-        // the tables depend on N, R, h, G and the requested path (which sets
-        // the tables laid out): a batch of problems with one kernel keeps one
-        // copy, which the stages then read from L2 instead of from memory
-        B.owner[b] = b;
-        for (int a = 0; a < b; ++a) {
-            const Shape& sa = B.shapes[a];
-            if (B.owner[a] == a && sa.n == sh.n && sa.R == sh.R && sa.gx == sh.gx && sa.gy == sh.gy &&
-                probs[a].h == probs[b].h && B.requested[a] == B.requested[b]) {
-                B.owner[b] = a;
-                break;
-            }
-        }
+        B.owner[b] = first_of.emplace(KernelKey{sh.n, sh.R, probs[b].h, sh.gx, sh.gy, B.requested[b]}, b).first->second;
         layout_problem(sh, default_mode(sh, B.requested[b]), both, B.deriv, poff, woff, B.probs[b],
                        B.owner[b] == b ? nullptr : &B.probs[B.owner[b]]);
         if (slices) B.probs[b].slices = slices;
