@@ -64,6 +64,33 @@ def test_plan_bytes_valid(mpik):
     assert wf > wd
 
 
+def _batch_bytes(mpik, probs, flags=0):
+    arr = (mpik.Problem * len(probs))(*probs)
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert mpik.lib().mpi_batch_bytes(arr, len(probs), flags, ctypes.byref(pb), ctypes.byref(wb)) == 0
+    return pb.value, wb.value
+
+
+def test_batch_bytes_share_kernel_tables(mpik):
+    """Problems with the same N, R, h, gradient and requested path keep one
+    copy of the kernel tables: the plan shrinks by exactly the duplicated
+    spectra and twiddles (FFT path) or taps (direct path), 256-byte aligned;
+    the work memory, per problem, does not."""
+    al = lambda x: (x + 255) // 256 * 256
+    for kw, table in ((dict(n=64, radius=63, conv_mode="fft"), al(3 * 65 * 65 * 4) + al(128 * 2 * 4)),
+                      (dict(n=40, radius=9, conv_mode="direct"), al(3 * 19 * 20 * 4))):
+        same = [_prob(mpik, n_samples=t, **kw) for t in (1000, 1500, 800)]
+        distinct = [_prob(mpik, n_samples=t, h=h, **kw) for t, h in ((1000, 0.01), (1500, 0.0101), (800, 0.0102))]
+        ps, ws = _batch_bytes(mpik, same)
+        pd, wd = _batch_bytes(mpik, distinct)
+        assert ws == wd and pd - ps == 2 * table, (kw, pd - ps, table)
+        # a problem that asks for another path keeps tables of its own: those of
+        # its single plan, which differ from the shared ones by its plan's size
+        mixed = same[:2] + [_prob(mpik, n_samples=800, **dict(kw, conv_mode="auto"))]
+        own = table + _batch_bytes(mpik, mixed[2:])[0] - _batch_bytes(mpik, same[2:])[0]
+        assert _batch_bytes(mpik, mixed)[0] == ps + own, kw
+
+
 @pytest.mark.parametrize("field,value,code", [
     ("n", 1, -1), ("n", 2000, -1), ("h", 0.0, -1), ("h", float("nan"), -1), ("radius", -1, -1),
     ("n_samples", 0, -1), ("dtype", 7, -4), ("conv_mode", 9, -1), ("interp", 2, -1), ("interp", -1, -1),
