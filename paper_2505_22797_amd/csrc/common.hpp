@@ -31,6 +31,12 @@ template <> struct v2<double> { using type = double2; };
 template <typename T> using vec4 = typename v4<T>::type;
 template <typename T> using vec2 = typename v2<T>::type;
 
+// Row pitch, in complex elements, of the half-spectrum intermediates laid out
+// by grid row ([ch][row][kx], kx < M/2 + 1): M/2 + 1 rounded up to four, so
+// that every row starts on a 32-byte boundary in float32 and a column
+// stage's four-column run of a row never straddles two 32-byte sectors.
+__host__ __device__ constexpr int spec_pitch(int M) { return (M / 2 + 4) / 4 * 4; }
+
 // ---------------------------------------------------------------------------
 // Problem descriptor, resident in plan memory.  Offsets are in bytes from the
 // plan base (o_*) or from the work base (w_*); every buffer is 256-byte aligned.
@@ -66,8 +72,8 @@ struct Prob {
     int64_t o_scratch;   // build-time scratch
     // work memory
     int64_t w_g;       // T [3][N][N]       sampled field G or its transpose image
-    int64_t w_t1;      // cx<T> [3][M/2+1][N]
-    int64_t w_t2;      // cx<T> [3][N][M/2+1]
+    int64_t w_t1;      // cx<T> [M/2+1][N] (forward), [3][N][spec_pitch(M)] (transpose)
+    int64_t w_t2;      // cx<T> [3][N][spec_pitch(M)]
     int64_t w_ysort;   // vec2<T> [T]       measured signal in cell order
     int64_t w_res;     // vec2<T> [T]       residual in cell order
     int64_t w_u;       // T [N][N]          pre-denoise iterate

@@ -19,6 +19,9 @@
 //              channel spectra, one inverse column FFT cropped to N rows
 //   adj_rows : per pair of rows: inverse row FFT -> c, with an optional fused
 //              gradient-step epilogue.
+// Rows of T1[ch][row][.] and T2[ch][row][.] are spec_pitch(M) elements apart
+// (M/2 + 1 rounded up to four), so that the column stages' four-column runs
+// are 32-byte aligned.
 // Every FFT line belongs to one 64-lane wave (in place in LDS, no work-group
 // barrier inside the transform).  The column stages come in two shapes: SPLIT
 // spreads one column over three waves (shortest latency for few problems);
@@ -85,6 +88,7 @@ __host__ __device__ constexpr size_t scatter_row_smem_bytes(int N) {
 template <typename T, int M>
 __device__ __forceinline__ T spec_at(const T* __restrict__ spec, int ch, int kx, int ky) {
     constexpr int H = M / 2 + 1;
+    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
     const bool up = ky > M / 2;
     const int kq = up ? M - ky : ky;
     const T v = spec[(ch * H + kx) * H + kq];
@@ -171,6 +175,7 @@ __device__ void fwd_rows_body(const Prob& p, const T* __restrict__ c, const char
                               char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<RowSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
+    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int unit = xcd_unit(blockIdx.x, (N + 7) / 8);   // four row pairs per work-group
     if (unit < 0) return;
@@ -242,6 +247,7 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
     static_assert(!(SPLIT && TRACE), "the trace convolution runs in the four-column shape");
     auto& sm = *reinterpret_cast<ColSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
+    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const T* spec = at<T>(plan, dh ? p.o_spec_dh : p.o_spec);   // dK/dh for the h-derivative
     cx<T>* t2 = at<cx<T>>(work, p.w_t2);
@@ -279,11 +285,11 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
                 x[m] = cscale(sm.c[ky], spec_at<T, M>(spec, wave, kx, ky));
             }
             fft512_regs<T, true>(x, sm.line[wave], tl, lane);
-            cx<T>* out = t2 + int64_t(wave) * N * H;
+            cx<T>* out = t2 + int64_t(wave) * N * HP;
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
                 const int j = lane + m * kWave;
-                if (j < N) out[int64_t(j) * H + kx] = x[m];
+                if (j < N) out[int64_t(j) * HP + kx] = x[m];
             }
             return;
         }
@@ -305,8 +311,8 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
         for (int ky = lane; ky < M; ky += kWave) line[ky] = cscale(sm.c[ky], spec_at<T, M>(spec, wave, kx, ky));
         wave_sync();
         fft_wave<T, true, M>(line, sm.tw, lane);
-        cx<T>* out = t2 + int64_t(wave) * N * H;
-        for (int j = lane; j < N; j += kWave) out[int64_t(j) * H + kx] = line[j];
+        cx<T>* out = t2 + int64_t(wave) * N * HP;
+        for (int j = lane; j < N; j += kWave) out[int64_t(j) * HP + kx] = line[j];
     } else if constexpr (M == 512) {                // four columns, register-resident transforms
         static_assert(4 * kXbStride<T> * sizeof(cx<T>) <= sizeof(ColSmem<T, M>), "exchange buffers exceed the LDS");
         const int unit = xcd_unit(blockIdx.x, (H + 3) / 4);
@@ -344,10 +350,10 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
                     if (lane + m * kWave < N) xb[wave][lane + m * kWave] = v[m];
             }
             __syncthreads();
-            cx<T>* out = t2 + int64_t(ch) * N * H;
+            cx<T>* out = t2 + int64_t(ch) * N * HP;
             for (int i = tid; i < 4 * N; i += 4 * kWave) {
                 const int j = i >> 2, cc = i & 3;
-                if (kx0 + cc < H) out[int64_t(j) * H + kx0 + cc] = xb[cc][j];
+                if (kx0 + cc < H) out[int64_t(j) * HP + kx0 + cc] = xb[cc][j];
             }
             __syncthreads();
         }
@@ -397,10 +403,10 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
             __syncthreads();
             // the four columns go out together: four consecutive threads write
             // T2[ch][j][kx0 .. kx0+3], one contiguous 32-byte run
-            cx<T>* out = t2 + int64_t(ch) * N * H;
+            cx<T>* out = t2 + int64_t(ch) * N * HP;
             for (int i = tid; i < 4 * N; i += 4 * kWave) {
                 const int j = i >> 2, cc = i & 3;
-                if (kx0 + cc < H) out[int64_t(j) * H + kx0 + cc] = sm.line[cc][j];
+                if (kx0 + cc < H) out[int64_t(j) * HP + kx0 + cc] = sm.line[cc][j];
             }
             __syncthreads();
         }
@@ -413,6 +419,7 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
                                      const char* __restrict__ plan, char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<GatherSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
+    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
     const int N = p.n, nb = p.nb, b = xcd_unit(blockIdx.x, nb, blockIdx.y);
     if (b < 0) return;
     const int* binstart = at<int>(plan, p.o_binstart);
@@ -427,8 +434,8 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
     twr.load(plan, p, tid);
     PairRegs<T, M> pr;
     if (wave < 3) {
-        const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(wave) * N * H;
-        pr.load(t2 + int64_t(b) * H, t2 + int64_t(b + 1) * H, true, lane);
+        const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(wave) * N * HP;
+        pr.load(t2 + int64_t(b) * HP, t2 + int64_t(b + 1) * HP, true, lane);
     }
     const vec4<T>* samp = at<vec4<T>>(plan, p.o_samp);
     const int2* sidx = at<int2>(plan, p.o_sidx);
@@ -489,6 +496,7 @@ template <typename T, int M, bool SORTED>
 __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, const char* __restrict__ plan,
                                      char* __restrict__ work, char* smem) {
     constexpr int H = M / 2 + 1;
+    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
     const int N = p.n, j = xcd_unit(blockIdx.x, N, blockIdx.y);
     if (j < 0) return;
     const bool g_in = scatter_g_in_region<T, M>(N);
@@ -530,7 +538,7 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
 #pragma unroll
             for (int m = 0; m < 5; ++m) {
                 const int k = lane + m * kWave;
-                if (k < H) t1[(int64_t(2) * N + j) * H + k] = x[m];
+                if (k < H) t1[(int64_t(2) * N + j) * HP + k] = x[m];
             }
             return;
         }
@@ -540,8 +548,8 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
         for (int k = lane; k < H; k += kWave) {
             cx<T> A, B;
             split_pair<T, M>(xb, k, A, B);
-            t1[int64_t(j) * H + k] = A;
-            t1[(int64_t(N) + j) * H + k] = B;
+            t1[int64_t(j) * HP + k] = A;
+            t1[(int64_t(N) + j) * HP + k] = B;
         }
         return;
     }
@@ -566,10 +574,10 @@ __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, con
         if (wave == 0) {
             cx<T> A, B;
             split_pair<T, M>(line, k, A, B);
-            t1[int64_t(j) * H + k] = A;
-            t1[(int64_t(N) + j) * H + k] = B;
+            t1[int64_t(j) * HP + k] = A;
+            t1[(int64_t(N) + j) * HP + k] = B;
         } else {
-            t1[(int64_t(2) * N + j) * H + k] = line[k];
+            t1[(int64_t(2) * N + j) * HP + k] = line[k];
         }
     }
 }
@@ -582,6 +590,7 @@ template <typename T, int M, bool SPLIT, bool DUAL = false>
 __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<ColSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
+    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const T* spec = at<T>(plan, p.o_spec);
     cx<T>* t2 = at<cx<T>>(work, p.w_t2);
@@ -592,11 +601,11 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         twr.load(plan, p, tid);
         constexpr int PL = M / kWave;
         cx<T> x[PL];
-        const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(wave) * N * H + kx;    // column kx of T1[ch]
+        const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(wave) * N * HP + kx;    // column kx of T1[ch]
 #pragma unroll
         for (int m = 0; m < PL; ++m) {
             const int i = lane + m * kWave;
-            x[m] = (i < N) ? t1[int64_t(i) * H] : cx<T>{T(0), T(0)};
+            x[m] = (i < N) ? t1[int64_t(i) * HP] : cx<T>{T(0), T(0)};
         }
         twr.store(sm.tw, tid);
         __syncthreads();
@@ -624,7 +633,7 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
                 const int j = lane + m * kWave;
-                if (j < N) t2[int64_t(j) * H + kx] = x[m];
+                if (j < N) t2[int64_t(j) * HP + kx] = x[m];
             }
             return;
         }
@@ -640,7 +649,7 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         __syncthreads();
         if (wave != 0) return;
         fft_wave<T, true, M>(sm.c, sm.tw, lane);
-        for (int j = lane; j < N; j += kWave) t2[int64_t(j) * H + kx] = sm.c[j];
+        for (int j = lane; j < N; j += kWave) t2[int64_t(j) * HP + kx] = sm.c[j];
     } else if constexpr (M == 512) {                // four columns, register-resident transforms
         const int unit = xcd_unit(blockIdx.x, (H + 3) / 4);
         if (unit < 0) return;
@@ -662,11 +671,11 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
         constexpr int PT = (4 * 512 + 4 * kWave - 1) / (4 * kWave);   // elements per thread (N < 512)
         cx<T> rg[PT];
         auto load_channel = [&](int ch) {
-            const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(ch) * N * H + kx0;
+            const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(ch) * N * HP + kx0;
 #pragma unroll
             for (int q = 0; q < PT; ++q) {
                 const int e = tid + q * 4 * kWave, row = e >> 2, col = e & 3;
-                rg[q] = (row < N && kx0 + col < H) ? t1[int64_t(row) * H + col] : cx<T>{T(0), T(0)};
+                rg[q] = (row < N && kx0 + col < H) ? t1[int64_t(row) * HP + col] : cx<T>{T(0), T(0)};
             }
         };
         load_channel(0);
@@ -715,10 +724,10 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
                     if (lane + m * kWave < N) xb[wave][lane + m * kWave] = src[m];
             }
             __syncthreads();
-            cx<T>* out = t2 + int64_t(slot) * N * H;
+            cx<T>* out = t2 + int64_t(slot) * N * HP;
             for (int i = tid; i < 4 * N; i += 4 * kWave) {
                 const int j = i >> 2, cc = i & 3;
-                if (kx0 + cc < H) out[int64_t(j) * H + kx0 + cc] = xb[cc][j];
+                if (kx0 + cc < H) out[int64_t(j) * HP + kx0 + cc] = xb[cc][j];
             }
             __syncthreads();
         };
@@ -742,7 +751,7 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
 #pragma unroll
             for (int m = 0; m < PL; ++m) {
                 const int i = lane + m * kWave;
-                x[m] = (i < N) ? t1[int64_t(i) * H] : cx<T>{T(0), T(0)};
+                x[m] = (i < N) ? t1[int64_t(i) * HP] : cx<T>{T(0), T(0)};
             }
         }
         twr.store(sm.tw, tid);
@@ -752,8 +761,8 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
 #pragma unroll
                 for (int m = 0; m < PL; ++m) line[lane + m * kWave] = x[m];
             } else {
-                const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(ch) * N * H + kx;
-                for (int i = lane; i < M; i += kWave) line[i] = (i < N) ? t1[int64_t(i) * H] : cx<T>{T(0), T(0)};
+                const cx<T>* t1 = at<cx<T>>(work, p.w_t1) + int64_t(ch) * N * HP + kx;
+                for (int i = lane; i < M; i += kWave) line[i] = (i < N) ? t1[int64_t(i) * HP] : cx<T>{T(0), T(0)};
             }
             wave_sync();
             fft_wave<T, false, M>(line, sm.tw, lane);
@@ -781,10 +790,10 @@ __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char
                 fft_wave<T, true, M>(line, sm.tw, lane);
             }
             __syncthreads();
-            cx<T>* out = t2 + int64_t(slot) * N * H;
+            cx<T>* out = t2 + int64_t(slot) * N * HP;
             for (int i = tid; i < 4 * N; i += 4 * kWave) {
                 const int j = i >> 2, cc = i & 3;
-                if (kx0 + cc < H) out[int64_t(j) * H + kx0 + cc] = sm.line[cc][j];
+                if (kx0 + cc < H) out[int64_t(j) * HP + kx0 + cc] = sm.line[cc][j];
             }
             __syncthreads();
         };
@@ -812,6 +821,7 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
                               double* __restrict__ part) {
     auto& sm = *reinterpret_cast<RowSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
+    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int unit = xcd_unit(blockIdx.x, (N + 7) / 8);   // four row pairs per work-group
     if (unit < 0) return;
@@ -850,8 +860,8 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
         Fft512Tw<T> tw;
         tw.load(at<cx<T>>(plan, p.o_tw), lane);
         PairRegs<T, M> pr;
-        const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(slot) * N * H;
-        pr.load(t2 + int64_t(r0) * H, t2 + int64_t(two ? r1 : r0) * H, two, lane);
+        const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(slot) * N * HP;
+        pr.load(t2 + int64_t(r0) * HP, t2 + int64_t(two ? r1 : r0) * HP, two, lane);
         cx<T> x[8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) x[m] = pr.spectrum(m, lane);
@@ -866,8 +876,8 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
         twr.load(plan, p, tid);
         PairRegs<T, M> pr;
         if (active) {
-            const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(slot) * N * H;
-            pr.load(t2 + int64_t(r0) * H, t2 + int64_t(two ? r1 : r0) * H, two, lane);
+            const cx<T>* t2 = at<cx<T>>(work, p.w_t2) + int64_t(slot) * N * HP;
+            pr.load(t2 + int64_t(r0) * HP, t2 + int64_t(two ? r1 : r0) * HP, two, lane);
         }
         twr.store(sm.tw, tid);
         __syncthreads();
@@ -892,6 +902,7 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
 template <typename T, int M>
 __device__ void rows_inv_fwd_body(const Prob& p, const char* __restrict__ plan, char* __restrict__ work, char* smem) {
     constexpr int H = M / 2 + 1;
+    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int unit = xcd_unit(blockIdx.x, (N + 7) / 8);   // four row pairs per work-group
     if (unit < 0) return;
@@ -908,7 +919,7 @@ __device__ void rows_inv_fwd_body(const Prob& p, const char* __restrict__ plan, 
             Fft512Tw<T> tw;
             tw.load(at<cx<T>>(plan, p.o_tw), lane);
             PairRegs<T, M> pr;
-            pr.load(t2 + int64_t(r0) * H, t2 + int64_t(two ? r1 : r0) * H, two, lane);
+            pr.load(t2 + int64_t(r0) * HP, t2 + int64_t(two ? r1 : r0) * HP, two, lane);
             cx<T> x[8];
 #pragma unroll
             for (int m = 0; m < 8; ++m) x[m] = pr.spectrum(m, lane);
@@ -928,7 +939,7 @@ __device__ void rows_inv_fwd_body(const Prob& p, const char* __restrict__ plan, 
         TwiddleRegs<T, M, 4 * kWave> twr;
         twr.load(plan, p, tid);
         PairRegs<T, M> pr;
-        if (active) pr.load(t2 + int64_t(r0) * H, t2 + int64_t(two ? r1 : r0) * H, two, lane);
+        if (active) pr.load(t2 + int64_t(r0) * HP, t2 + int64_t(two ? r1 : r0) * HP, two, lane);
         twr.store(sm.tw, tid);
         __syncthreads();
         if (active) {

@@ -234,8 +234,8 @@ void layout_problem(const Shape& sh, int mode, bool both, bool deriv, size_t& po
     p.o_err = take(poff, 16);
     p.w_g = take(woff, size_t(3) * N * N * e);
     if (fft) {
-        p.w_t1 = take(woff, size_t(3) * H * N * 2 * e);
-        p.w_t2 = take(woff, size_t(3) * N * H * 2 * e);
+        p.w_t1 = take(woff, size_t(3) * spec_pitch(M) * N * 2 * e);
+        p.w_t2 = take(woff, size_t(3) * N * spec_pitch(M) * 2 * e);
     }
     p.w_ysort = take(woff, size_t(T) * 2 * e);
     p.w_res = take(woff, size_t(T) * 2 * e);
