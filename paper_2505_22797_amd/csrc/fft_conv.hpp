@@ -88,7 +88,6 @@ __host__ __device__ constexpr size_t scatter_row_smem_bytes(int N) {
 template <typename T, int M>
 __device__ __forceinline__ T spec_at(const T* __restrict__ spec, int ch, int kx, int ky) {
     constexpr int H = M / 2 + 1;
-    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
     const bool up = ky > M / 2;
     const int kq = up ? M - ky : ky;
     const T v = spec[(ch * H + kx) * H + kq];
@@ -175,7 +174,6 @@ __device__ void fwd_rows_body(const Prob& p, const T* __restrict__ c, const char
                               char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<RowSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
-    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int unit = xcd_unit(blockIdx.x, (N + 7) / 8);   // four row pairs per work-group
     if (unit < 0) return;
@@ -247,7 +245,7 @@ __device__ void fwd_cols_body(const Prob& p, const char* __restrict__ plan, char
     static_assert(!(SPLIT && TRACE), "the trace convolution runs in the four-column shape");
     auto& sm = *reinterpret_cast<ColSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
-    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
+    constexpr int HP = spec_pitch(M);   // row pitch of T1[ch][row] and T2[ch][row]
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const T* spec = at<T>(plan, dh ? p.o_spec_dh : p.o_spec);   // dK/dh for the h-derivative
     cx<T>* t2 = at<cx<T>>(work, p.w_t2);
@@ -419,7 +417,7 @@ __device__ void fwd_rows_gather_body(const Prob& p, T* __restrict__ out0, const 
                                      const char* __restrict__ plan, char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<GatherSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
-    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
+    constexpr int HP = spec_pitch(M);   // row pitch of T1[ch][row] and T2[ch][row]
     const int N = p.n, nb = p.nb, b = xcd_unit(blockIdx.x, nb, blockIdx.y);
     if (b < 0) return;
     const int* binstart = at<int>(plan, p.o_binstart);
@@ -496,7 +494,7 @@ template <typename T, int M, bool SORTED>
 __device__ void adj_scatter_row_body(const Prob& p, const T* __restrict__ s, const char* __restrict__ plan,
                                      char* __restrict__ work, char* smem) {
     constexpr int H = M / 2 + 1;
-    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
+    constexpr int HP = spec_pitch(M);   // row pitch of T1[ch][row] and T2[ch][row]
     const int N = p.n, j = xcd_unit(blockIdx.x, N, blockIdx.y);
     if (j < 0) return;
     const bool g_in = scatter_g_in_region<T, M>(N);
@@ -590,7 +588,7 @@ template <typename T, int M, bool SPLIT, bool DUAL = false>
 __device__ void adj_cols_body(const Prob& p, const char* __restrict__ plan, char* __restrict__ work, char* smem) {
     auto& sm = *reinterpret_cast<ColSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
-    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
+    constexpr int HP = spec_pitch(M);   // row pitch of T1[ch][row] and T2[ch][row]
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const T* spec = at<T>(plan, p.o_spec);
     cx<T>* t2 = at<cx<T>>(work, p.w_t2);
@@ -821,7 +819,7 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
                               double* __restrict__ part) {
     auto& sm = *reinterpret_cast<RowSmem<T, M>*>(smem);
     constexpr int H = M / 2 + 1;
-    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
+    constexpr int HP = spec_pitch(M);   // row pitch of T1[ch][row] and T2[ch][row]
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int unit = xcd_unit(blockIdx.x, (N + 7) / 8);   // four row pairs per work-group
     if (unit < 0) return;
@@ -902,7 +900,7 @@ __device__ void adj_rows_body(const Prob& p, T* c_out, const T* c_in, T tau, int
 template <typename T, int M>
 __device__ void rows_inv_fwd_body(const Prob& p, const char* __restrict__ plan, char* __restrict__ work, char* smem) {
     constexpr int H = M / 2 + 1;
-    [[maybe_unused]] constexpr int HP = spec_pitch(M);   // row pitch of T1/T2 rows
+    constexpr int HP = spec_pitch(M);   // row pitch of T1[ch][row] and T2[ch][row]
     const int N = p.n, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int unit = xcd_unit(blockIdx.x, (N + 7) / 8);   // four row pairs per work-group
     if (unit < 0) return;
